@@ -1,0 +1,199 @@
+/*
+ * bires.h -- exact bivariate resultants, discriminants and univariate gcds on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations are those of Berberich, Emeliyanenko, Kobel and Sagraloff,
+ * "Exact Symbolic-Numeric Computation of Planar Algebraic Curves":
+ *   - res(f, g; y) in Z[x], the determinant of the Sylvester matrix of f and g
+ *     taken as polynomials in y (Section 2, "Resultants" paragraph); res(f, g; x)
+ *     is the same with x and y exchanged;
+ *   - res(f, f_y; y), the resultant the curve analysis projects with
+ *     (Section 3.1, Project);
+ *   - gcd(a, b) in Z[x] (Section 5.1, "Computing gcds in Z[x]").
+ * All results are exact integers.  They are computed by the multi-modular
+ * scheme of Section 5.1 ("Computing resultants in Z[x,y]", steps (a)-(e)):
+ * reduction modulo many 31-bit primes, evaluation at many x, univariate
+ * resultants over F_p, interpolation per prime and Chinese remaindering in
+ * mixed-radix form, every step in HIP kernels.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Integers are little-endian arrays of 32-bit limbs in two's complement.
+ *
+ * A bivariate input is a dense rectangle of coefficients:
+ *     c[((j * (deg_x + 1)) + i) * limbs + k]  = limb k of the coefficient of x^i y^j,
+ *     0 <= j <= deg_y, 0 <= i <= deg_x.
+ * Total-degree supports are zero-padded.  deg_y/deg_x are the extents of the
+ * rectangle, not necessarily the true degrees: all-zero top rows or columns
+ * are allowed and ignored.  The caller owns c.
+ *
+ * A univariate polynomial is c[i * limbs + k] = limb k of the coefficient of x^i.
+ * As an output, `degree` holds on entry the largest degree the buffer has room
+ * for and on return the true degree (-1 for the zero polynomial); `limbs` is
+ * fixed by the caller and every coefficient is written sign-extended to it.
+ * Coefficients above the true degree are written as zero.  Size the buffer with
+ * the matching *_bounds() call, which depends only on the extents and limb
+ * counts of the inputs, never on their values.
+ *
+ * Memory space: `mem` says where every coefficient buffer of the call lives,
+ * BIRES_MEM_HOST (ordinary host memory) or BIRES_MEM_DEVICE (device memory
+ * of the current HIP device).  Descriptor structs are always host memory.
+ *
+ * Streams: `stream` is a hipStream_t (cast to void*); NULL selects the
+ * library's own stream.  Calls are synchronous: they return after the result
+ * is in the output buffer.
+ *
+ * Return values: 0 (BIRES_OK) or a negative BIRES_E* code; bires_strerror()
+ * gives a message.  On error the output buffers are unspecified.
+ * Thread safety: calls may come from several host threads; calls that share a
+ * stream are serialised by the library.
+ */
+#ifndef BIRES_H
+#define BIRES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BIRES_OK 0
+#define BIRES_EINVAL (-1)    /* NULL pointer, negative extent, limbs < 1, bad var/kind/mem */
+#define BIRES_EBUFSIZE (-2)  /* output buffer too small (degree or limbs); needed sizes written back */
+#define BIRES_ENOMEM (-3)    /* device or pinned allocation failed, or HBM budget exceeded */
+#define BIRES_ETOOBIG (-4)   /* beyond compiled limits (prime count, degree) */
+#define BIRES_EDEVICE (-5)   /* HIP runtime error or no usable gfx950 device */
+#define BIRES_ECHECK (-6)    /* internal consistency check failed (bound overflow, check prime) */
+#define BIRES_ENOTFOUND (-7) /* unknown server ticket */
+#define BIRES_ETIMEOUT (-8)  /* server wait timed out (the job keeps running) */
+
+#define BIRES_VAR_X 0
+#define BIRES_VAR_Y 1
+
+#define BIRES_MEM_HOST 0
+#define BIRES_MEM_DEVICE 1
+
+#define BIRES_KIND_RESULTANT 0     /* res(f, g; var) */
+#define BIRES_KIND_DISCRIMINANT 1  /* res(f, df/dvar; var); g ignored */
+
+/* Compiled limits. */
+#define BIRES_MAX_PRIMES 2048      /* 31-bit primes per job: results below ~2^63000 */
+#define BIRES_MAX_YDEG 512         /* degree in the eliminated variable, per input */
+
+typedef struct {
+  int32_t deg_y;        /* rows - 1; -1 for an empty (zero) polynomial */
+  int32_t deg_x;        /* columns - 1 */
+  int32_t limbs;        /* 32-bit limbs per coefficient, >= 1 */
+  const uint32_t *c;    /* see layout above */
+} bires_bipoly;
+
+typedef struct {
+  int32_t degree;       /* output: capacity on entry, true degree on return; input: degree (-1 = zero) */
+  int32_t limbs;        /* limbs per coefficient, >= 1 */
+  uint32_t *c;          /* c[i * limbs + k] */
+} bires_upoly;
+
+/* Library set-up on the current HIP device: builds the prime table (the
+ * largest primes below 2^31), the mixed-radix tables and the library stream.
+ * Called implicitly by every compute call; explicit calls are idempotent. */
+int bires_init(void);
+
+/* Output sizes for res(f, g; var): max_degree bounds deg R by
+ * min(n*dx_f + m*dx_g, n*t_f + m*t_g - m*n) (m, n the degrees in var; dx the
+ * degrees in the other variable; t total degrees; all read from the extents),
+ * a sharpening of the deg R <= m*n of Section 2; max_limbs bounds the
+ * coefficients by the Hadamard bound of the Sylvester matrix with every entry
+ * replaced by its 1-norm and every coefficient by 2^(32*limbs-1).
+ * Host-only: no device work. */
+int bires_resultant_bounds(const bires_bipoly *f, const bires_bipoly *g, int var,
+                           int32_t *max_degree, int32_t *max_limbs);
+
+/* R = res(f, g; var) (Section 2, "Resultants"; Section 5.1 for the method).
+ * f = 0 or g = 0 gives the zero polynomial; deg_var f = deg_var g = 0 gives 1. */
+int bires_resultant(const bires_bipoly *f, const bires_bipoly *g, int var,
+                    bires_upoly *out, int mem, void *stream);
+
+/* Output sizes for res(f, df/dvar; var). */
+int bires_discriminant_bounds(const bires_bipoly *f, int var, int32_t *max_degree, int32_t *max_limbs);
+
+/* R = res(f, df/dvar; var) exactly as Project forms it (Section 3.1): no
+ * division by the leading coefficient, no sign normalisation.  Needs
+ * deg_var f >= 1 (else BIRES_EINVAL). */
+int bires_discriminant(const bires_bipoly *f, int var, bires_upoly *out, int mem, void *stream);
+
+/* Output sizes for gcd(a, b): degree <= min(deg a, deg b); coefficient bits from
+ * the Landau-Mignotte bound 2^d * ||a||_2 of a divisor of degree d. */
+int bires_gcd_bounds(const bires_upoly *a, const bires_upoly *b, int32_t *max_degree, int32_t *max_limbs);
+
+/* h = gcd(a, b) in Z[x] (Section 5.1, "Computing gcds in Z[x]": Brown's
+ * modular method): gcd of the contents times the primitive gcd, positive
+ * leading coefficient; gcd(0, 0) = 0, gcd(a, 0) = +-a.  The modular result is
+ * certified by exact division on the device; a failed certificate adds primes.
+ * Inputs are read-only (bires_upoly.c is not written). */
+int bires_gcd(const bires_upoly *a, const bires_upoly *b, bires_upoly *out, int mem, void *stream);
+
+/* n independent jobs in one batched launch sequence.  kind[i] is a
+ * BIRES_KIND_*; var[i] a BIRES_VAR_*; g[i] is ignored for discriminants.
+ * status[i] receives the per-job code; the return value is BIRES_OK when
+ * every job succeeded, else the first failing job's code.  Results equal those
+ * of the single-job calls bit for bit. */
+int bires_resultant_batch(int n, const bires_bipoly *f, const bires_bipoly *g,
+                          const int32_t *kind, const int32_t *var,
+                          bires_upoly *out, int32_t *status, int mem, void *stream);
+
+/* ---------------- serving: continuous batching of mixed jobs ---------------- */
+
+typedef struct bires_server bires_server;
+
+/* A server owns a scheduler thread and a stream.  Jobs are admitted while at
+ * most max_slots are in flight and their device footprint fits in
+ * hbm_budget_bytes; admitted jobs run together in batched launches, and jobs
+ * arriving while others run join the next launch.  Residues stay in device
+ * memory for a job's whole life. */
+int bires_server_create(size_t hbm_budget_bytes, int max_slots, bires_server **out);
+
+/* Copies the (host-memory) inputs and returns at once with a ticket. */
+int bires_server_submit(bires_server *s, int kind, int var, const bires_bipoly *f,
+                        const bires_bipoly *g, uint64_t *ticket);
+
+/* Blocks until the job is done (timeout_s < 0: no limit), then writes the
+ * result to out (host memory) and the submit-to-completion latency. */
+int bires_server_wait(bires_server *s, uint64_t ticket, bires_upoly *out, double timeout_s,
+                      double *latency_s);
+
+/* Stops the scheduler after the jobs in flight finish and frees everything. */
+int bires_server_destroy(bires_server *s);
+
+/* ---------------- introspection ---------------- */
+
+/* Plan of res(f, g; var) or the discriminant (kind) for host-memory inputs:
+ * number of evaluation points D (= degree bound + 1), number of primes P,
+ * log2 of the coefficient bound.  Host-only. */
+int bires_plan(const bires_bipoly *f, const bires_bipoly *g, int kind, int var,
+               int32_t *points, int32_t *primes, double *log2_bound);
+
+/* The first n primes of the table (descending from 2^31 - 1).  Host-only. */
+int bires_primes(int n, uint32_t *out);
+
+/* Values of the univariate resultants res(f(a, y), g(a, y)) mod p_k with the
+ * formal degrees kept, for a = 0 .. D-1 and the plan's P primes:
+ * values[k * D + a] (host memory, at least P*D words).  A stage-level view of
+ * the pipeline for testing. */
+int bires_debug_values(const bires_bipoly *f, const bires_bipoly *g, int kind, int var,
+                       uint32_t *values, int64_t capacity, int32_t *points, int32_t *primes);
+
+/* Kernel timing: when enabled, the library brackets each launch of the
+ * univariate-resultant kernel with HIP events on its stream and accumulates
+ * the durations.  bires_kernel_time returns (milliseconds, launches) since the
+ * last reset. */
+int bires_set_timing(int enable);
+int bires_kernel_time(double *ms, int64_t *launches);
+
+const char *bires_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BIRES_H */

@@ -1,0 +1,421 @@
+"""Exact bivariate resultants, discriminants and gcds on MI355X (gfx950).
+
+Python binding of the C ABI in include/bires.h: argument marshalling only.
+Every step of the computation runs in the HIP kernels of libbires.so; there is
+no CPU fallback, and a missing library raises at the first call.
+
+Bivariate polynomials are lists of rows, ``F[j][i]`` the coefficient of
+x^i y^j (Python ints of any size); univariate results are lists of ints in
+ascending powers of x, ``[]`` for the zero polynomial.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+VAR_X, VAR_Y = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+KIND_RESULTANT, KIND_DISCRIMINANT = 0, 1
+
+ERRORS = {
+    -1: "EINVAL", -2: "EBUFSIZE", -3: "ENOMEM", -4: "ETOOBIG",
+    -5: "EDEVICE", -6: "ECHECK", -7: "ENOTFOUND", -8: "ETIMEOUT",
+}
+
+
+class BiresError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (what, ERRORS.get(code, "?"), code))
+
+
+class Bipoly(ctypes.Structure):
+    _fields_ = [("deg_y", ctypes.c_int32), ("deg_x", ctypes.c_int32), ("limbs", ctypes.c_int32),
+                ("c", ctypes.c_void_p)]
+
+
+class Upoly(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int32), ("limbs", ctypes.c_int32), ("c", ctypes.c_void_p)]
+
+
+_lib = None
+
+_SIGS = {
+    "bires_init": ([], ctypes.c_int),
+    "bires_resultant_bounds": ([ctypes.POINTER(Bipoly), ctypes.POINTER(Bipoly), ctypes.c_int,
+                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "bires_resultant": ([ctypes.POINTER(Bipoly), ctypes.POINTER(Bipoly), ctypes.c_int, ctypes.POINTER(Upoly),
+                         ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "bires_discriminant_bounds": ([ctypes.POINTER(Bipoly), ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "bires_discriminant": ([ctypes.POINTER(Bipoly), ctypes.c_int, ctypes.POINTER(Upoly), ctypes.c_int,
+                            ctypes.c_void_p], ctypes.c_int),
+    "bires_gcd_bounds": ([ctypes.POINTER(Upoly), ctypes.POINTER(Upoly), ctypes.POINTER(ctypes.c_int32),
+                          ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "bires_gcd": ([ctypes.POINTER(Upoly), ctypes.POINTER(Upoly), ctypes.POINTER(Upoly), ctypes.c_int,
+                   ctypes.c_void_p], ctypes.c_int),
+    "bires_resultant_batch": ([ctypes.c_int, ctypes.POINTER(Bipoly), ctypes.POINTER(Bipoly),
+                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(Upoly), ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
+                               ctypes.c_void_p], ctypes.c_int),
+    "bires_server_create": ([ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "bires_server_submit": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Bipoly),
+                             ctypes.POINTER(Bipoly), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "bires_server_wait": ([ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Upoly), ctypes.c_double,
+                           ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "bires_server_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "bires_plan": ([ctypes.POINTER(Bipoly), ctypes.POINTER(Bipoly), ctypes.c_int, ctypes.c_int,
+                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                    ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "bires_primes": ([ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "bires_debug_values": ([ctypes.POINTER(Bipoly), ctypes.POINTER(Bipoly), ctypes.c_int, ctypes.c_int,
+                            ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                            ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "bires_set_timing": ([ctypes.c_int], ctypes.c_int),
+    "bires_kernel_time": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "bires_strerror": ([ctypes.c_int], ctypes.c_char_p),
+}
+
+
+def lib():
+    """The loaded libbires.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path):
+            raise RuntimeError("libbires.so is not built (run __graft_entry__.build() or "
+                               "python -m paper_1201_1548_amd.build); there is no fallback path")
+        L = ctypes.CDLL(path)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(code, what):
+    if code != 0:
+        raise BiresError(code, what)
+
+
+# ----------------------------------------------------------------------------
+# marshalling of integers <-> two's-complement 32-bit limbs
+
+def limbs_needed(values):
+    bits = 1
+    for v in values:
+        b = (v if v >= 0 else ~v).bit_length() + 1
+        if b > bits:
+            bits = b
+    return (bits + 31) // 32
+
+
+def ints_to_limbs(values, L):
+    """Python ints -> uint32 array [len(values), L] (two's complement)."""
+    out = np.zeros((len(values), L), dtype=np.uint32)
+    mod = 1 << (32 * L)
+    for r, v in enumerate(values):
+        u = v % mod
+        if L == 1:
+            out[r, 0] = u
+        else:
+            out[r] = np.frombuffer(u.to_bytes(4 * L, "little"), dtype="<u4")
+    return out
+
+
+def limbs_to_ints(arr):
+    """uint32 array [n, L] -> Python ints (two's complement)."""
+    n, L = arr.shape
+    half = 1 << (32 * L - 1)
+    full = 1 << (32 * L)
+    res = []
+    raw = np.ascontiguousarray(arr, dtype="<u4")
+    for r in range(n):
+        u = int.from_bytes(raw[r].tobytes(), "little")
+        res.append(u - full if u >= half else u)
+    return res
+
+
+def bipoly_array(F, limbs=None):
+    """Rows F[j][i] -> uint32 array [rows, cols, L] (dense rectangle)."""
+    rows = len(F)
+    cols = max((len(r) for r in F), default=0)
+    flat = [F[j][i] if i < len(F[j]) else 0 for j in range(rows) for i in range(cols)]
+    L = limbs or limbs_needed(flat)
+    arr = ints_to_limbs(flat, L).reshape(rows, cols, L)
+    return arr
+
+
+def _desc(arr, ptr=None):
+    rows, cols, L = arr.shape
+    d = Bipoly()
+    d.deg_y = rows - 1 if rows * cols else -1
+    d.deg_x = cols - 1 if rows * cols else -1
+    d.limbs = L
+    d.c = ptr if ptr is not None else arr.ctypes.data
+    return d
+
+
+class DeviceBipoly:
+    """A bivariate input resident in device memory (a torch uint32-word tensor)."""
+
+    def __init__(self, F, limbs=None, device="cuda"):
+        import torch
+        arr = bipoly_array(F, limbs)
+        self.shape = arr.shape
+        self.tensor = torch.from_numpy(arr.view(np.int32)).to(device)
+
+    def desc(self):
+        rows, cols, L = self.shape
+        d = Bipoly()
+        d.deg_y = rows - 1 if rows * cols else -1
+        d.deg_x = cols - 1 if rows * cols else -1
+        d.limbs = L
+        d.c = self.tensor.data_ptr()
+        return d
+
+
+def _bounds(kind, fd, gd, var):
+    deg = ctypes.c_int32()
+    L = ctypes.c_int32()
+    if kind == KIND_RESULTANT:
+        _check(lib().bires_resultant_bounds(ctypes.byref(fd), ctypes.byref(gd), var, ctypes.byref(deg),
+                                            ctypes.byref(L)), "bires_resultant_bounds")
+    else:
+        _check(lib().bires_discriminant_bounds(ctypes.byref(fd), var, ctypes.byref(deg), ctypes.byref(L)),
+               "bires_discriminant_bounds")
+    return deg.value, L.value
+
+
+def _var(var):
+    if var in ("x", VAR_X):
+        return VAR_X
+    if var in ("y", VAR_Y):
+        return VAR_Y
+    raise ValueError("var must be 'x' or 'y'")
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    return ctypes.c_void_p(stream)
+
+
+def resultant(F, G, var="y", stream=None):
+    """res(f, g; var) as a list of Python ints (host-memory call)."""
+    v = _var(var)
+    fa, ga = bipoly_array(F), bipoly_array(G)
+    fd, gd = _desc(fa), _desc(ga)
+    deg, L = _bounds(KIND_RESULTANT, fd, gd, v)
+    out = np.zeros((deg + 1, L), dtype=np.uint32)
+    od = Upoly(deg, L, out.ctypes.data)
+    _check(lib().bires_resultant(ctypes.byref(fd), ctypes.byref(gd), v, ctypes.byref(od), MEM_HOST,
+                                 _stream(stream)), "bires_resultant")
+    return limbs_to_ints(out[: od.degree + 1])
+
+
+def discriminant(F, var="y", stream=None):
+    """res(f, df/dvar; var) as a list of Python ints (host-memory call)."""
+    v = _var(var)
+    fa = bipoly_array(F)
+    fd = _desc(fa)
+    deg, L = _bounds(KIND_DISCRIMINANT, fd, fd, v)
+    out = np.zeros((deg + 1, L), dtype=np.uint32)
+    od = Upoly(deg, L, out.ctypes.data)
+    _check(lib().bires_discriminant(ctypes.byref(fd), v, ctypes.byref(od), MEM_HOST, _stream(stream)),
+           "bires_discriminant")
+    return limbs_to_ints(out[: od.degree + 1])
+
+
+def _upoly_in(a):
+    a = list(a)
+    while a and a[-1] == 0:
+        a.pop()
+    L = limbs_needed(a) if a else 1
+    arr = ints_to_limbs(a, L) if a else np.zeros((1, 1), dtype=np.uint32)
+    return arr, Upoly(len(a) - 1, L, arr.ctypes.data)
+
+
+def gcd(a, b, stream=None):
+    """gcd(a, b) in Z[x] (host-memory call)."""
+    aa, ad = _upoly_in(a)
+    ba, bd = _upoly_in(b)
+    deg = ctypes.c_int32()
+    L = ctypes.c_int32()
+    _check(lib().bires_gcd_bounds(ctypes.byref(ad), ctypes.byref(bd), ctypes.byref(deg), ctypes.byref(L)),
+           "bires_gcd_bounds")
+    out = np.zeros((max(deg.value, 0) + 1, L.value), dtype=np.uint32)
+    od = Upoly(max(deg.value, 0), L.value, out.ctypes.data)
+    _check(lib().bires_gcd(ctypes.byref(ad), ctypes.byref(bd), ctypes.byref(od), MEM_HOST, _stream(stream)),
+           "bires_gcd")
+    return limbs_to_ints(out[: od.degree + 1])
+
+
+def resultant_batch(jobs, stream=None):
+    """jobs: list of (kind, F, G, var) with kind 'res' or 'disc' (G ignored for 'disc').
+    Returns (results, statuses); one batched launch sequence for all jobs."""
+    n = len(jobs)
+    keep = []
+    fds = (Bipoly * n)()
+    gds = (Bipoly * n)()
+    kinds = (ctypes.c_int32 * n)()
+    vars_ = (ctypes.c_int32 * n)()
+    outs = (Upoly * n)()
+    bufs = []
+    for i, (kind, F, G, var) in enumerate(jobs):
+        k = KIND_DISCRIMINANT if kind == "disc" else KIND_RESULTANT
+        fa = bipoly_array(F)
+        ga = bipoly_array(G) if k == KIND_RESULTANT else fa
+        keep += [fa, ga]
+        fds[i] = _desc(fa)
+        gds[i] = _desc(ga)
+        kinds[i] = k
+        vars_[i] = _var(var)
+        try:
+            deg, L = _bounds(k, fds[i], gds[i], vars_[i])
+        except BiresError:
+            deg, L = 0, 1          # the batch call reports this job's error in status
+        out = np.zeros((deg + 1, L), dtype=np.uint32)
+        bufs.append(out)
+        outs[i] = Upoly(deg, L, out.ctypes.data)
+    status = (ctypes.c_int32 * n)()
+    lib().bires_resultant_batch(n, fds, gds, kinds, vars_, outs, status, MEM_HOST, _stream(stream))
+    res = []
+    for i in range(n):
+        res.append(limbs_to_ints(bufs[i][: outs[i].degree + 1]) if status[i] == 0 else None)
+    return res, list(status)
+
+
+def plan(F, G=None, kind="res", var="y"):
+    """(points D, primes P, log2 of the coefficient bound) of a job; host-only."""
+    k = KIND_DISCRIMINANT if kind == "disc" else KIND_RESULTANT
+    fa = bipoly_array(F)
+    ga = bipoly_array(G) if G is not None else fa
+    fd, gd = _desc(fa), _desc(ga)
+    D = ctypes.c_int32()
+    P = ctypes.c_int32()
+    lb = ctypes.c_double()
+    _check(lib().bires_plan(ctypes.byref(fd), ctypes.byref(gd), k, _var(var), ctypes.byref(D), ctypes.byref(P),
+                            ctypes.byref(lb)), "bires_plan")
+    return D.value, P.value, lb.value
+
+
+def bounds(F, G=None, kind="res", var="y"):
+    """(max degree, max limbs) from the extents of the inputs; host-only."""
+    k = KIND_DISCRIMINANT if kind == "disc" else KIND_RESULTANT
+    fa = bipoly_array(F)
+    ga = bipoly_array(G) if G is not None else fa
+    return _bounds(k, _desc(fa), _desc(ga), _var(var))
+
+
+def primes(n):
+    out = np.zeros(max(n, 1), dtype=np.uint32)
+    _check(lib().bires_primes(n, out.ctypes.data), "bires_primes")
+    return [int(v) for v in out[:n]]
+
+
+def debug_values(F, G=None, kind="res", var="y"):
+    """Stage view: (primes, values[P][D]) of the univariate resultants at a = 0..D-1."""
+    k = KIND_DISCRIMINANT if kind == "disc" else KIND_RESULTANT
+    D, P, _ = plan(F, G, kind, var)
+    fa = bipoly_array(F)
+    ga = bipoly_array(G) if G is not None else fa
+    fd, gd = _desc(fa), _desc(ga)
+    vals = np.zeros(P * D, dtype=np.uint32)
+    Dp = ctypes.c_int32()
+    Pp = ctypes.c_int32()
+    _check(lib().bires_debug_values(ctypes.byref(fd), ctypes.byref(gd), k, _var(var), vals.ctypes.data,
+                                    vals.size, ctypes.byref(Dp), ctypes.byref(Pp)), "bires_debug_values")
+    return primes(Pp.value), vals.reshape(Pp.value, Dp.value)
+
+
+def set_timing(enable):
+    _check(lib().bires_set_timing(1 if enable else 0), "bires_set_timing")
+
+
+def kernel_time():
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().bires_kernel_time(ctypes.byref(ms), ctypes.byref(n)), "bires_kernel_time")
+    return ms.value, n.value
+
+
+# ----------------------------------------------------------------------------
+# device-memory entry points (inputs and outputs are torch tensors in HBM)
+
+def _torch_stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class DeviceBatch:
+    """A prepared batch of jobs whose inputs and outputs live in device memory.
+
+    jobs: list of (kind, F, G, var) like resultant_batch.  The descriptors,
+    input tensors and output tensors are built once; run() issues one
+    bires_resultant_batch call (BIRES_MEM_DEVICE) on the given torch stream."""
+
+    def __init__(self, jobs, device="cuda"):
+        import torch
+        n = len(jobs)
+        self.n = n
+        self.inputs = []
+        self.fds = (Bipoly * n)()
+        self.gds = (Bipoly * n)()
+        self.kinds = (ctypes.c_int32 * n)()
+        self.vars = (ctypes.c_int32 * n)()
+        self.outs = (Upoly * n)()
+        self.status = (ctypes.c_int32 * n)()
+        self.out_tensors = []
+        self.caps = []
+        for i, (kind, F, G, var) in enumerate(jobs):
+            k = KIND_DISCRIMINANT if kind == "disc" else KIND_RESULTANT
+            fdev = DeviceBipoly(F, device=device)
+            gdev = DeviceBipoly(G, device=device) if k == KIND_RESULTANT else fdev
+            self.inputs.append((fdev, gdev))
+            self.fds[i] = fdev.desc()
+            self.gds[i] = gdev.desc()
+            self.kinds[i] = k
+            self.vars[i] = _var(var)
+            deg, L = _bounds(k, self.fds[i], self.gds[i], self.vars[i])
+            t = torch.zeros((deg + 1, L), dtype=torch.int32, device=device)
+            self.out_tensors.append(t)
+            self.caps.append((deg, L))
+
+    def run(self, stream=None):
+        for i, (deg, L) in enumerate(self.caps):
+            self.outs[i] = Upoly(deg, L, self.out_tensors[i].data_ptr())
+        code = lib().bires_resultant_batch(self.n, self.fds, self.gds, self.kinds, self.vars, self.outs,
+                                           self.status, MEM_DEVICE, _torch_stream(stream))
+        _check(code, "bires_resultant_batch")
+        return code
+
+    def run_each(self, stream=None):
+        """The plain path: one single-job call per job (bires_resultant / bires_discriminant)."""
+        s = _torch_stream(stream)
+        for i, (deg, L) in enumerate(self.caps):
+            self.outs[i] = Upoly(deg, L, self.out_tensors[i].data_ptr())
+            if self.kinds[i] == KIND_RESULTANT:
+                code = lib().bires_resultant(ctypes.byref(self.fds[i]), ctypes.byref(self.gds[i]), self.vars[i],
+                                             ctypes.byref(self.outs[i]), MEM_DEVICE, s)
+            else:
+                code = lib().bires_discriminant(ctypes.byref(self.fds[i]), self.vars[i], ctypes.byref(self.outs[i]),
+                                                MEM_DEVICE, s)
+            _check(code, "single-job call")
+
+    def results(self):
+        """Results as lists of Python ints (copies the output tensors to the host)."""
+        res = []
+        for i in range(self.n):
+            deg = self.outs[i].degree
+            arr = self.out_tensors[i][: deg + 1].cpu().numpy().view(np.uint32)
+            res.append(limbs_to_ints(arr) if deg >= 0 else [])
+        return res

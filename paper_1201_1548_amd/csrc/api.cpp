@@ -1,0 +1,189 @@
+// The C ABI of include/bires.h.
+#include <cstring>
+#include <mutex>
+
+#include "../../include/bires.h"
+#include "engine.hpp"
+#include "gcd.hpp"
+#include "tables.hpp"
+
+using namespace bires;
+
+namespace {
+
+// Runs f with the caller's stream, or with the library stream held exclusively.
+template <class F>
+int with_stream(void* stream, F&& f) {
+  int err = BIRES_OK;
+  Context* cx = context(&err);
+  if (!cx) return err;
+  if (stream) return f(cx, (hipStream_t)stream);
+  std::lock_guard<std::mutex> lk(cx->stream_mu);
+  return f(cx, cx->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int bires_init(void) {
+  int err = BIRES_OK;
+  context(&err);
+  return err;
+}
+
+int bires_resultant_bounds(const bires_bipoly* f, const bires_bipoly* g, int var, int32_t* max_degree,
+                           int32_t* max_limbs) {
+  if (!f || !g) return BIRES_EINVAL;
+  JobIn jb;
+  jb.f = *f;
+  jb.g = *g;
+  jb.var = var;
+  jb.kind = BIRES_KIND_RESULTANT;
+  return bounds_job(jb, max_degree, max_limbs);
+}
+
+int bires_discriminant_bounds(const bires_bipoly* f, int var, int32_t* max_degree, int32_t* max_limbs) {
+  if (!f) return BIRES_EINVAL;
+  JobIn jb;
+  jb.f = *f;
+  jb.g = *f;
+  jb.var = var;
+  jb.kind = BIRES_KIND_DISCRIMINANT;
+  return bounds_job(jb, max_degree, max_limbs);
+}
+
+int bires_resultant(const bires_bipoly* f, const bires_bipoly* g, int var, bires_upoly* out, int mem,
+                    void* stream) {
+  if (!f || !g || !out) return BIRES_EINVAL;
+  std::vector<JobIn> jobs(1);
+  jobs[0].f = *f;
+  jobs[0].g = *g;
+  jobs[0].var = var;
+  jobs[0].kind = BIRES_KIND_RESULTANT;
+  jobs[0].out = out;
+  return with_stream(stream, [&](Context* cx, hipStream_t st) { return run_batch(cx, jobs, mem, st, nullptr); });
+}
+
+int bires_discriminant(const bires_bipoly* f, int var, bires_upoly* out, int mem, void* stream) {
+  if (!f || !out) return BIRES_EINVAL;
+  std::vector<JobIn> jobs(1);
+  jobs[0].f = *f;
+  jobs[0].g = *f;
+  jobs[0].var = var;
+  jobs[0].kind = BIRES_KIND_DISCRIMINANT;
+  jobs[0].out = out;
+  return with_stream(stream, [&](Context* cx, hipStream_t st) { return run_batch(cx, jobs, mem, st, nullptr); });
+}
+
+int bires_resultant_batch(int n, const bires_bipoly* f, const bires_bipoly* g, const int32_t* kind,
+                          const int32_t* var, bires_upoly* out, int32_t* status, int mem, void* stream) {
+  if (n < 0 || (n > 0 && (!f || !kind || !var || !out))) return BIRES_EINVAL;
+  if (n == 0) return BIRES_OK;
+  std::vector<JobIn> jobs(n);
+  for (int i = 0; i < n; ++i) {
+    jobs[i].f = f[i];
+    jobs[i].kind = kind[i];
+    if (kind[i] == BIRES_KIND_RESULTANT) {
+      if (!g) return BIRES_EINVAL;
+      jobs[i].g = g[i];
+    } else {
+      jobs[i].g = f[i];
+    }
+    jobs[i].var = var[i];
+    jobs[i].out = &out[i];
+  }
+  return with_stream(stream, [&](Context* cx, hipStream_t st) { return run_batch(cx, jobs, mem, st, status); });
+}
+
+int bires_gcd_bounds(const bires_upoly* a, const bires_upoly* b, int32_t* max_degree, int32_t* max_limbs) {
+  return gcd_bounds(a, b, max_degree, max_limbs);
+}
+
+int bires_gcd(const bires_upoly* a, const bires_upoly* b, bires_upoly* out, int mem, void* stream) {
+  if (!a || !b || !out) return BIRES_EINVAL;
+  return with_stream(stream, [&](Context* cx, hipStream_t st) { return run_gcd(cx, *a, *b, out, mem, st); });
+}
+
+int bires_plan(const bires_bipoly* f, const bires_bipoly* g, int kind, int var, int32_t* points, int32_t* primes,
+               double* log2_bound) {
+  if (!f || (kind == BIRES_KIND_RESULTANT && !g)) return BIRES_EINVAL;
+  JobIn jb;
+  jb.f = *f;
+  jb.g = kind == BIRES_KIND_RESULTANT ? *g : *f;
+  jb.kind = kind;
+  jb.var = var;
+  Plan pl;
+  int e = plan_host_job(jb, pl);
+  if (e) return e;
+  if (points) *points = pl.D;
+  if (primes) *primes = pl.P;
+  if (log2_bound) *log2_bound = pl.log2B;
+  return BIRES_OK;
+}
+
+int bires_primes(int n, uint32_t* out) {
+  if (n < 0 || n > MAX_PRIMES || (n && !out)) return BIRES_EINVAL;
+  const HostTables& t = host_tables();
+  for (int i = 0; i < n; ++i) out[i] = t.primes[i].p;
+  return BIRES_OK;
+}
+
+int bires_debug_values(const bires_bipoly* f, const bires_bipoly* g, int kind, int var, uint32_t* values,
+                       int64_t capacity, int32_t* points, int32_t* primes) {
+  if (!f || !values || (kind == BIRES_KIND_RESULTANT && !g)) return BIRES_EINVAL;
+  std::vector<JobIn> jobs(1);
+  jobs[0].f = *f;
+  jobs[0].g = kind == BIRES_KIND_RESULTANT ? *g : *f;
+  jobs[0].kind = kind;
+  jobs[0].var = var;
+  std::vector<uint32_t> vals;
+  std::vector<int> shape;
+  int e = with_stream(nullptr, [&](Context* cx, hipStream_t st) {
+    return run_batch(cx, jobs, BIRES_MEM_HOST, st, nullptr, &vals, &shape);
+  });
+  if (e) return e;
+  if (points) *points = shape[1];
+  if (primes) *primes = shape[0];
+  if ((int64_t)vals.size() > capacity) return BIRES_EBUFSIZE;
+  std::memcpy(values, vals.data(), vals.size() * 4);
+  return BIRES_OK;
+}
+
+int bires_set_timing(int enable) {
+  int err = BIRES_OK;
+  Context* cx = context(&err);
+  if (!cx) return err;
+  std::lock_guard<std::mutex> lk(cx->timing_mu);
+  cx->timing = enable != 0;
+  cx->kernel_ms = 0.0;
+  cx->kernel_launches = 0;
+  return BIRES_OK;
+}
+
+int bires_kernel_time(double* ms, int64_t* launches) {
+  int err = BIRES_OK;
+  Context* cx = context(&err);
+  if (!cx) return err;
+  std::lock_guard<std::mutex> lk(cx->timing_mu);
+  if (ms) *ms = cx->kernel_ms;
+  if (launches) *launches = cx->kernel_launches;
+  return BIRES_OK;
+}
+
+const char* bires_strerror(int code) {
+  switch (code) {
+    case BIRES_OK: return "success";
+    case BIRES_EINVAL: return "invalid argument";
+    case BIRES_EBUFSIZE: return "output buffer too small";
+    case BIRES_ENOMEM: return "out of device or pinned memory, or over the HBM budget";
+    case BIRES_ETOOBIG: return "input beyond the compiled limits";
+    case BIRES_EDEVICE: return "HIP runtime error or no gfx950 device";
+    case BIRES_ECHECK: return "internal consistency check failed";
+    case BIRES_ENOTFOUND: return "unknown ticket";
+    case BIRES_ETIMEOUT: return "timed out";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,475 @@
+// The batched pipeline: plan every job, lay out one device workspace, launch
+// each kernel once for all jobs, copy the results back.
+#include <algorithm>
+#include <cstring>
+
+#include "engine.hpp"
+#include "kernels.hpp"
+#include "tables.hpp"
+
+namespace bires {
+
+namespace {
+
+struct Shape {
+  int rows = 0, ld = 0, L = 1;
+};
+
+Shape shape_of(const bires_bipoly& p, int var) {
+  Shape s;
+  s.L = p.limbs;
+  if (p.deg_y < 0) return s;
+  s.rows = var == BIRES_VAR_Y ? p.deg_y + 1 : p.deg_x + 1;
+  s.ld = var == BIRES_VAR_Y ? p.deg_x + 1 : p.deg_y + 1;
+  return s;
+}
+
+void pack_rect(const bires_bipoly& p, int var, uint32_t* dst) {
+  const size_t n = (size_t)(p.deg_y + 1) * (p.deg_x + 1) * p.limbs;
+  if (var == BIRES_VAR_Y) {
+    std::memcpy(dst, p.c, n * sizeof(uint32_t));
+    return;
+  }
+  const int rows = p.deg_y + 1, cols = p.deg_x + 1, L = p.limbs;
+  for (int j = 0; j < rows; ++j)
+    for (int i = 0; i < cols; ++i)
+      for (int l = 0; l < L; ++l) dst[((size_t)i * rows + j) * L + l] = p.c[((size_t)j * cols + i) * L + l];
+}
+
+struct Layout {
+  size_t bytes = 0;
+  size_t take(size_t n) {
+    const size_t o = (bytes + 255) & ~(size_t)255;
+    bytes = o + n;
+    return o;
+  }
+};
+
+struct Work {
+  Shape sf, sg;
+  bool disc = false;
+  RowStats stf, stg;
+  Plan pl;
+  int status = BIRES_OK;
+  bool active = false;  // goes through the kernels
+  int Lout = 1, degcap = 0, Tf = 0, Tg = 0, ldg = 0, Lacc = 1;
+  const uint32_t* dev_f = nullptr;
+  const uint32_t* dev_g = nullptr;
+  size_t o_in[2] = {0, 0}, o_scan[2] = {0, 0};
+  size_t o_res_f = 0, o_res_g = 0, o_vals = 0, o_coefs = 0, o_digits = 0, o_neg = 0, o_acc_lo = 0, o_acc_hi = 0;
+  size_t o_out = 0, o_hout = 0, o_rowdeg = 0;
+};
+
+// RAII holder of pool blocks.
+struct Held {
+  Pool* pool;
+  void* p = nullptr;
+  Held(Pool* pl, size_t n) : pool(pl) { p = n ? pl->alloc(n) : nullptr; }
+  ~Held() { pool->release(p); }
+  uint8_t* b() const { return (uint8_t*)p; }
+};
+
+}  // namespace
+
+static int validate(const JobIn& jb, bool need_out) {
+  if (jb.kind != BIRES_KIND_RESULTANT && jb.kind != BIRES_KIND_DISCRIMINANT) return BIRES_EINVAL;
+  if (jb.var != BIRES_VAR_X && jb.var != BIRES_VAR_Y) return BIRES_EINVAL;
+  int e = check_bipoly(&jb.f, 0);
+  if (e) return e;
+  if (jb.kind == BIRES_KIND_RESULTANT && (e = check_bipoly(&jb.g, 0))) return e;
+  if (need_out && (!jb.out || jb.out->limbs < 1 || jb.out->degree < 0 || !jb.out->c)) return BIRES_EINVAL;
+  return BIRES_OK;
+}
+
+#define DEV(x)                        \
+  do {                                \
+    if ((x) != hipSuccess) return BIRES_EDEVICE; \
+  } while (0)
+
+int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t st, int32_t* status,
+              std::vector<uint32_t>* debug_values, std::vector<int>* debug_shape) {
+  if (mem != BIRES_MEM_HOST && mem != BIRES_MEM_DEVICE) return BIRES_EINVAL;
+  const int nj = (int)jobs.size();
+  const bool debug = debug_values != nullptr;
+  std::vector<Work> w(nj);
+  for (int i = 0; i < nj; ++i) {
+    const JobIn& jb = jobs[i];
+    w[i].status = validate(jb, !debug);
+    if (w[i].status) continue;
+    w[i].disc = jb.kind == BIRES_KIND_DISCRIMINANT;
+    w[i].sf = shape_of(jb.f, jb.var);
+    if (!w[i].disc) w[i].sg = shape_of(jb.g, jb.var);
+  }
+  auto nsrc = [&](int i) { return w[i].disc ? 1 : 2; };
+  auto shp = [&](int i, int which) -> const Shape& { return which ? w[i].sg : w[i].sf; };
+
+  // ---------------- inputs on the device, row statistics
+  Layout in;
+  std::vector<ScanTask> tasks;
+  std::vector<int4> smap;
+  for (int i = 0; i < nj; ++i) {
+    if (w[i].status) continue;
+    for (int which = 0; which < nsrc(i); ++which) {
+      const Shape& s = shp(i, which);
+      const size_t bytes = (size_t)s.rows * s.ld * s.L * 4;
+      if (mem == BIRES_MEM_HOST || jobs[i].var == BIRES_VAR_X) w[i].o_in[which] = in.take(bytes);
+      if (mem == BIRES_MEM_DEVICE) {
+        w[i].o_scan[which] = in.take((size_t)s.rows * 12);
+        for (int r0 = 0; r0 < s.rows; r0 += 64) smap.push_back(make_int4((int)tasks.size(), r0, 0, 0));
+        tasks.push_back(ScanTask{});
+      }
+    }
+  }
+  const size_t o_tasks = in.take(sizeof(ScanTask) * tasks.size());
+  const size_t o_smap = in.take(sizeof(int4) * smap.size());
+  Held d_in(&cx->dev, in.bytes), h_in(&cx->host, in.bytes);
+  if (in.bytes && (!d_in.p || !h_in.p)) return BIRES_ENOMEM;
+
+  if (mem == BIRES_MEM_HOST) {
+    for (int i = 0; i < nj; ++i) {
+      if (w[i].status) continue;
+      for (int which = 0; which < nsrc(i); ++which) {
+        const Shape& s = shp(i, which);
+        uint32_t* h = (uint32_t*)(h_in.b() + w[i].o_in[which]);
+        if (s.rows) pack_rect(which ? jobs[i].g : jobs[i].f, jobs[i].var, h);
+        (which ? w[i].stg : w[i].stf) = scan_host(h, s.rows, s.ld, s.L);
+        (which ? w[i].dev_g : w[i].dev_f) = (const uint32_t*)(d_in.b() + w[i].o_in[which]);
+      }
+    }
+    if (in.bytes) DEV(hipMemcpyAsync(d_in.p, h_in.p, in.bytes, hipMemcpyHostToDevice, st));
+  } else if (!tasks.empty()) {
+    int t = 0;
+    for (int i = 0; i < nj; ++i) {
+      if (w[i].status) continue;
+      for (int which = 0; which < nsrc(i); ++which) {
+        const bires_bipoly& p = which ? jobs[i].g : jobs[i].f;
+        const Shape& s = shp(i, which);
+        const uint32_t* src = p.c;
+        if (jobs[i].var == BIRES_VAR_X && s.rows) {
+          uint32_t* dst = (uint32_t*)(d_in.b() + w[i].o_in[which]);
+          launch_transpose(p.c, dst, p.deg_y + 1, p.deg_x + 1, p.limbs, st);
+          src = dst;
+        }
+        (which ? w[i].dev_g : w[i].dev_f) = src;
+        tasks[t++] = ScanTask{src, s.rows, s.ld, s.L, (int32_t*)(d_in.b() + w[i].o_scan[which])};
+      }
+    }
+    std::memcpy(h_in.b() + o_tasks, tasks.data(), sizeof(ScanTask) * tasks.size());
+    std::memcpy(h_in.b() + o_smap, smap.data(), sizeof(int4) * smap.size());
+    DEV(hipMemcpyAsync(d_in.b() + o_tasks, h_in.b() + o_tasks, (o_smap - o_tasks) + sizeof(int4) * smap.size(),
+                       hipMemcpyHostToDevice, st));
+    if (!smap.empty())
+      launch_scan((const ScanTask*)(d_in.b() + o_tasks), (const int4*)(d_in.b() + o_smap), (int)smap.size(), st);
+    for (int i = 0; i < nj; ++i) {
+      if (w[i].status) continue;
+      for (int which = 0; which < nsrc(i); ++which) {
+        const size_t o = w[i].o_scan[which];
+        const int rows = shp(i, which).rows;
+        if (rows) DEV(hipMemcpyAsync(h_in.b() + o, d_in.b() + o, (size_t)rows * 12, hipMemcpyDeviceToHost, st));
+      }
+    }
+    DEV(hipStreamSynchronize(st));
+    for (int i = 0; i < nj; ++i) {
+      if (w[i].status) continue;
+      for (int which = 0; which < nsrc(i); ++which) {
+        const int rows = shp(i, which).rows;
+        const int32_t* v = (const int32_t*)(h_in.b() + w[i].o_scan[which]);
+        RowStats& rs = which ? w[i].stg : w[i].stf;
+        rs.deg.resize(rows);
+        rs.bits.resize(rows);
+        rs.cnt.resize(rows);
+        for (int j = 0; j < rows; ++j) {
+          rs.deg[j] = v[3 * j];
+          rs.bits[j] = v[3 * j + 1];
+          rs.cnt[j] = v[3 * j + 2];
+        }
+      }
+    }
+  }
+
+  // ---------------- plans and output capacities
+  for (int i = 0; i < nj; ++i) {
+    Work& x = w[i];
+    if (x.status) continue;
+    if (x.disc) {
+      int top = -1;
+      for (int j = 0; j < (int)x.stf.cnt.size(); ++j)
+        if (x.stf.cnt[j]) top = j;
+      if (top < 1) {
+        x.status = BIRES_EINVAL;
+        continue;
+      }
+      x.stg = derive_stats(x.stf);
+    }
+    if ((x.status = make_plan(x.stf, x.stg, x.pl))) continue;
+    if (x.pl.kind_special == 0 && (size_t)x.pl.D * 12 > cx->lds_per_block) {
+      x.status = BIRES_ETOOBIG;
+      continue;
+    }
+    const int need_limbs = x.pl.kind_special ? 1 : limbs_for_log2(x.pl.log2B);
+    if (!debug) {
+      bires_upoly* o = jobs[i].out;
+      if (o->degree < x.pl.D - 1 || o->limbs < need_limbs) {
+        o->degree = std::max(o->degree, x.pl.D - 1);
+        o->limbs = std::max(o->limbs, need_limbs);
+        x.status = BIRES_EBUFSIZE;
+        continue;
+      }
+      x.degcap = o->degree;
+      x.Lout = o->limbs;
+    }
+    x.active = x.pl.kind_special == 0;
+    if (x.active) {
+      x.ldg = x.disc ? x.sf.ld : x.sg.ld;
+      x.Tf = (x.pl.m + 1) * x.sf.ld;
+      x.Tg = (x.pl.n + 1) * x.ldg;
+      x.Lacc = std::min(x.Lout, x.pl.P + 1);
+    }
+  }
+
+  // ---------------- workspace: device buffers, then the uploaded metadata block
+  Layout ws;
+  Layout hout;  // host staging of outputs (host memory space only)
+  std::vector<int4> m_red, m_ee, m_ip, m_mrc, m_sum, m_car;
+  int maxP = 1, maxWords = 2, maxD = 1;
+  for (int i = 0; i < nj; ++i) {
+    Work& x = w[i];
+    if (x.status || !x.active) continue;
+    const Plan& p = x.pl;
+    x.o_res_f = ws.take((size_t)p.P * x.Tf * 4);
+    x.o_res_g = ws.take((size_t)p.P * x.Tg * 4);
+    x.o_vals = ws.take((size_t)p.P * p.D * 4);
+    if (!debug) {
+      x.o_coefs = ws.take((size_t)p.P * p.D * 4);
+      x.o_digits = ws.take((size_t)p.P * p.D * 4);
+      x.o_neg = ws.take((size_t)p.D * 4);
+      x.o_acc_lo = ws.take((size_t)p.D * x.Lacc * 8);
+      x.o_acc_hi = ws.take((size_t)p.D * x.Lacc * 4);
+      if (mem == BIRES_MEM_HOST) {
+        x.o_out = ws.take((size_t)(x.degcap + 1) * x.Lout * 4);
+        x.o_hout = hout.take((size_t)(x.degcap + 1) * x.Lout * 4);
+      }
+    }
+    maxP = std::max(maxP, p.P);
+    maxD = std::max(maxD, p.D);
+    maxWords = std::max(maxWords, p.m + p.n + 2);
+    for (int t0 = 0; t0 < x.Tf; t0 += 64) m_red.push_back(make_int4(i, 0, t0, 0));
+    for (int t0 = 0; t0 < x.Tg; t0 += 64) m_red.push_back(make_int4(i, 1, t0, 0));
+    for (int k = 0; k < p.P; ++k)
+      for (int a0 = 0; a0 < p.D; a0 += 64) m_ee.push_back(make_int4(i, k, a0, 0));
+    for (int k = 0; k < p.P; ++k) m_ip.push_back(make_int4(i, k, 0, 0));
+    for (int c = 0; c < p.D; ++c) m_mrc.push_back(make_int4(i, c, 0, 0));
+    for (int t0 = 0; t0 < p.D * x.Lacc; t0 += 256) m_sum.push_back(make_int4(i, 0, t0, 0));
+    for (int c0 = 0; c0 <= x.degcap; c0 += 64) m_car.push_back(make_int4(i, 0, c0, 0));
+  }
+  const size_t meta_begin = ws.take(0);
+  const size_t o_jobs = ws.take(sizeof(JobDev) * (size_t)nj);
+  const size_t o_flags = ws.take(sizeof(int32_t) * 2 * (size_t)nj);
+  for (int i = 0; i < nj; ++i)
+    if (!w[i].status && w[i].active) w[i].o_rowdeg = ws.take((size_t)(w[i].pl.m + w[i].pl.n + 2) * 4);
+  const size_t nmaps = m_red.size() + m_ee.size() + m_ip.size() + m_mrc.size() + m_sum.size() + m_car.size();
+  const size_t o_maps = ws.take(sizeof(int4) * nmaps);
+  const size_t meta_end = ws.bytes;
+  Held d_ws(&cx->dev, ws.bytes), h_meta(&cx->host, meta_end - meta_begin), h_out(&cx->host, hout.bytes);
+  if ((ws.bytes && !d_ws.p) || (meta_end > meta_begin && !h_meta.p) || (hout.bytes && !h_out.p))
+    return BIRES_ENOMEM;
+  uint8_t* const D0 = d_ws.b();
+  uint8_t* const H0 = h_meta.b() - meta_begin;  // H0 + offset addresses the metadata image
+
+  int32_t* h_flags = (int32_t*)(H0 + o_flags);
+  JobDev* h_jobs = (JobDev*)(H0 + o_jobs);
+  for (int i = 0; i < nj; ++i) {
+    h_flags[2 * i] = -1;
+    h_flags[2 * i + 1] = 0;
+    h_jobs[i] = JobDev{};
+    Work& x = w[i];
+    if (x.status || !x.active) continue;
+    const Plan& p = x.pl;
+    JobDev& J = h_jobs[i];
+    J.limbs_f = x.dev_f;
+    J.limbs_g = x.disc ? nullptr : x.dev_g;
+    J.Lf = x.sf.L;
+    J.Lg = x.disc ? x.sf.L : x.sg.L;
+    J.ldf = x.sf.ld;
+    J.ldg = x.ldg;
+    J.m = p.m;
+    J.n = p.n;
+    J.disc = x.disc ? 1 : 0;
+    J.P = p.P;
+    J.D = p.D;
+    J.Tf = x.Tf;
+    J.Tg = x.Tg;
+    int32_t* rd = (int32_t*)(H0 + x.o_rowdeg);
+    for (int j = 0; j <= p.m; ++j) rd[j] = x.stf.deg[j];
+    for (int j = 0; j <= p.n; ++j) rd[p.m + 1 + j] = x.stg.deg[j];
+    J.rowdeg_f = (const int32_t*)(D0 + x.o_rowdeg);
+    J.rowdeg_g = J.rowdeg_f + p.m + 1;
+    J.res_f = (uint32_t*)(D0 + x.o_res_f);
+    J.res_g = (uint32_t*)(D0 + x.o_res_g);
+    J.vals = (uint32_t*)(D0 + x.o_vals);
+    if (!debug) {
+      J.coefs = (uint32_t*)(D0 + x.o_coefs);
+      J.digits = (uint32_t*)(D0 + x.o_digits);
+      J.negflag = (int32_t*)(D0 + x.o_neg);
+      J.acc_lo = (uint64_t*)(D0 + x.o_acc_lo);
+      J.acc_hi = (uint32_t*)(D0 + x.o_acc_hi);
+      J.Lacc = x.Lacc;
+      J.out = mem == BIRES_MEM_HOST ? (uint32_t*)(D0 + x.o_out) : jobs[i].out->c;
+      J.Lcap = x.Lout;
+      J.degcap = x.degcap;
+    }
+    J.deg_out = (int32_t*)(D0 + o_flags) + 2 * i;
+    J.err = (int32_t*)(D0 + o_flags) + 2 * i + 1;
+  }
+  int4* hm = (int4*)(H0 + o_maps);
+  const int4* dm = (const int4*)(D0 + o_maps);
+  size_t mo = 0;
+  auto put = [&](const std::vector<int4>& v) {
+    const int4* d = dm + mo;
+    if (!v.empty()) std::memcpy(hm + mo, v.data(), v.size() * sizeof(int4));
+    mo += v.size();
+    return d;
+  };
+  const int4* d_red = put(m_red);
+  const int4* d_ee = put(m_ee);
+  const int4* d_ip = put(m_ip);
+  const int4* d_mrc = put(m_mrc);
+  const int4* d_sum = put(m_sum);
+  const int4* d_car = put(m_car);
+  if (meta_end > meta_begin)
+    DEV(hipMemcpyAsync(D0 + meta_begin, h_meta.p, meta_end - meta_begin, hipMemcpyHostToDevice, st));
+  const JobDev* d_jobs = (const JobDev*)(D0 + o_jobs);
+
+  // ---------------- kernels
+  const bool timing = cx->timing && !m_ee.empty();
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (timing) {
+    DEV(hipEventCreate(&ev0));
+    DEV(hipEventCreate(&ev1));
+  }
+  if (!m_red.empty()) launch_reduce(d_jobs, d_red, (int)m_red.size(), maxP, cx->tab, st);
+  if (timing) DEV(hipEventRecord(ev0, st));
+  if (!m_ee.empty()) launch_eval_elim(d_jobs, d_ee, (int)m_ee.size(), maxWords, cx->tab, st);
+  if (timing) DEV(hipEventRecord(ev1, st));
+  if (!debug) {
+    if (!m_ip.empty()) launch_interp(d_jobs, d_ip, (int)m_ip.size(), maxD, cx->tab, st);
+    if (!m_mrc.empty()) launch_mrc(d_jobs, d_mrc, (int)m_mrc.size(), maxP, cx->tab, st);
+    if (!m_sum.empty()) launch_limbs_sum(d_jobs, d_sum, (int)m_sum.size(), cx->tab, st);
+    if (!m_car.empty()) launch_limbs_carry(d_jobs, d_car, (int)m_car.size(), st);
+  }
+  DEV(hipGetLastError());
+
+  if (debug) {
+    const Work& x = w[0];
+    if (x.status) return x.status;
+    if (!x.active) return BIRES_EINVAL;
+    debug_values->resize((size_t)x.pl.P * x.pl.D);
+    debug_shape->assign({x.pl.P, x.pl.D});
+    DEV(hipMemcpyAsync(debug_values->data(), D0 + x.o_vals, debug_values->size() * 4, hipMemcpyDeviceToHost, st));
+    DEV(hipStreamSynchronize(st));
+    return BIRES_OK;
+  }
+
+  // ---------------- results
+  // special results of device-memory outputs are written on the stream
+  for (int i = 0; i < nj; ++i) {
+    const Work& x = w[i];
+    if (x.status || x.active || mem != BIRES_MEM_DEVICE) continue;
+    bires_upoly* o = jobs[i].out;
+    DEV(hipMemsetAsync(o->c, 0, (size_t)(x.degcap + 1) * x.Lout * 4, st));
+    if (x.pl.kind_special == 2) {
+      static const uint32_t one = 1u;
+      DEV(hipMemcpyAsync(o->c, &one, 4, hipMemcpyHostToDevice, st));
+    }
+  }
+  if (nj) DEV(hipMemcpyAsync(h_flags, D0 + o_flags, sizeof(int32_t) * 2 * nj, hipMemcpyDeviceToHost, st));
+  for (int i = 0; i < nj; ++i) {
+    const Work& x = w[i];
+    if (x.status || !x.active || mem != BIRES_MEM_HOST) continue;
+    DEV(hipMemcpyAsync(h_out.b() + x.o_hout, D0 + x.o_out, (size_t)(x.degcap + 1) * x.Lout * 4,
+                       hipMemcpyDeviceToHost, st));
+  }
+  DEV(hipStreamSynchronize(st));
+  if (timing) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess) {
+      std::lock_guard<std::mutex> lk(cx->timing_mu);
+      cx->kernel_ms += ms;
+      cx->kernel_launches += 1;
+    }
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+  }
+  int first_err = BIRES_OK;
+  for (int i = 0; i < nj; ++i) {
+    Work& x = w[i];
+    bires_upoly* o = jobs[i].out;
+    if (!x.status) {
+      if (x.active) {
+        if (h_flags[2 * i + 1]) {
+          x.status = BIRES_ECHECK;
+        } else {
+          if (mem == BIRES_MEM_HOST)
+            std::memcpy(o->c, h_out.b() + x.o_hout, (size_t)(x.degcap + 1) * x.Lout * 4);
+          o->degree = h_flags[2 * i];
+        }
+      } else {
+        if (mem == BIRES_MEM_HOST) {
+          std::memset(o->c, 0, (size_t)(x.degcap + 1) * x.Lout * 4);
+          if (x.pl.kind_special == 2) o->c[0] = 1u;
+        }
+        o->degree = x.pl.kind_special == 2 ? 0 : -1;
+      }
+    }
+    if (status) status[i] = x.status;
+    if (x.status && first_err == BIRES_OK) first_err = x.status;
+  }
+  return first_err;
+}
+
+}  // namespace bires
+
+namespace bires {
+
+int plan_host_job(const JobIn& jb, Plan& pl) {
+  int e = validate(jb, false);
+  if (e) return e;
+  const Shape sf = shape_of(jb.f, jb.var);
+  std::vector<uint32_t> buf((size_t)sf.rows * sf.ld * sf.L);
+  if (sf.rows) pack_rect(jb.f, jb.var, buf.data());
+  RowStats stf = scan_host(buf.data(), sf.rows, sf.ld, sf.L), stg;
+  if (jb.kind == BIRES_KIND_DISCRIMINANT) {
+    int top = -1;
+    for (int j = 0; j < sf.rows; ++j)
+      if (stf.cnt[j]) top = j;
+    if (top < 1) return BIRES_EINVAL;
+    stg = derive_stats(stf);
+  } else {
+    const Shape sg = shape_of(jb.g, jb.var);
+    std::vector<uint32_t> bg((size_t)sg.rows * sg.ld * sg.L);
+    if (sg.rows) pack_rect(jb.g, jb.var, bg.data());
+    stg = scan_host(bg.data(), sg.rows, sg.ld, sg.L);
+  }
+  return make_plan(stf, stg, pl);
+}
+
+int bounds_job(const JobIn& jb, int32_t* max_degree, int32_t* max_limbs) {
+  int e = validate(jb, false);
+  if (e) return e;
+  const Shape sf = shape_of(jb.f, jb.var);
+  RowStats stf = worst_stats(sf.rows, sf.ld, sf.L), stg;
+  if (jb.kind == BIRES_KIND_DISCRIMINANT) {
+    if (sf.rows < 2) return BIRES_EINVAL;
+    stg = derive_stats(stf);
+  } else {
+    const Shape sg = shape_of(jb.g, jb.var);
+    stg = worst_stats(sg.rows, sg.ld, sg.L);
+  }
+  Plan pl;
+  if ((e = make_plan(stf, stg, pl))) return e;
+  if (max_degree) *max_degree = pl.D - 1;
+  if (max_limbs) *max_limbs = pl.kind_special ? 1 : limbs_for_log2(pl.log2B);
+  return BIRES_OK;
+}
+
+}  // namespace bires

@@ -1,0 +1,73 @@
+// Host orchestration: device context, memory pools and the batched pipeline.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/bires.h"
+#include "job.hpp"
+#include "plan.hpp"
+
+namespace bires {
+
+// Caching allocator over hipMalloc / hipHostMalloc: blocks are rounded up to a
+// size class and returned to a free list instead of being freed.
+class Pool {
+ public:
+  explicit Pool(bool pinned) : pinned_(pinned) {}
+  void* alloc(size_t bytes);
+  void release(void* p);
+  size_t cached_bytes();
+  void trim();
+
+ private:
+  struct Block {
+    void* p;
+    size_t bytes;
+  };
+  bool pinned_;
+  std::mutex mu_;
+  std::vector<Block> free_;
+  std::vector<Block> used_;
+};
+
+struct Context {
+  int device = -1;
+  hipStream_t stream = nullptr;     // library stream (default priority)
+  std::mutex stream_mu;             // serialises use of the library stream
+  TablesDev tab{};                  // device copies of the host tables
+  Pool dev{false};
+  Pool host{true};
+  size_t lds_per_block = 65536;
+  bool timing = false;
+  std::mutex timing_mu;
+  double kernel_ms = 0.0;
+  int64_t kernel_launches = 0;
+};
+
+// Returns the initialised context or nullptr (err set).
+Context* context(int* err);
+
+// One job of a batch as the caller described it.
+struct JobIn {
+  bires_bipoly f, g;
+  int kind = BIRES_KIND_RESULTANT;
+  int var = BIRES_VAR_Y;
+  bires_upoly* out = nullptr;
+};
+
+// Runs the jobs on `stream` (all buffers in memory space `mem`) and waits.
+// status[i] receives each job's code; the return value is the first error.
+int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t stream, int32_t* status,
+              std::vector<uint32_t>* debug_values = nullptr, std::vector<int>* debug_shape = nullptr);
+
+// Plan of one host-memory job, and output sizes from the extents only (host-only).
+int bounds_job(const JobIn& job, int32_t* max_degree, int32_t* max_limbs);
+int plan_host_job(const JobIn& job, Plan& pl);
+
+// Validates the descriptor of a bivariate input.
+int check_bipoly(const bires_bipoly* p, int allow_null_c);
+
+}  // namespace bires

@@ -1,0 +1,47 @@
+// Device-visible description of one resultant job and of the global tables.
+#pragma once
+#include <stdint.h>
+
+#include "modp.hpp"
+
+namespace bires {
+
+// One res(f, g; y) job after planning.  All pointers are device memory.
+// f and g are dense rectangles of limbs (rows = powers of y); for a
+// discriminant the g residues are formed from f (g_{j,i} = (j+1) f_{j+1,i}).
+struct JobDev {
+  const uint32_t* limbs_f;  // [(m+1) * ldf * Lf]
+  const uint32_t* limbs_g;  // [(n+1) * ldg * Lg]; unused when disc
+  int32_t Lf, Lg;           // limbs per input coefficient
+  int32_t ldf, ldg;         // row stride (coefficients) of the rectangles
+  int32_t m, n;             // degrees in y (top non-zero row of f, g)
+  int32_t disc;             // 1: g = df/dy
+  int32_t P, D;             // primes, evaluation points (= degree bound + 1)
+  int32_t Tf, Tg;           // residues per prime: (m+1)*ldf, (n+1)*ldg
+  const int32_t* rowdeg_f;  // [m+1] degree in x of each row (-1: zero row)
+  const int32_t* rowdeg_g;  // [n+1]
+  uint32_t* res_f;          // [P][Tf] Montgomery residues
+  uint32_t* res_g;          // [P][Tg]
+  uint32_t* vals;           // [P][D] values R(a) mod p_k, a = 0..D-1
+  uint32_t* coefs;          // [P][D] coefficients of R mod p_k
+  uint32_t* digits;         // [D][P] mixed-radix digits
+  int32_t* negflag;         // [D] 1 when the symmetric lift is negative
+  uint64_t* acc_lo;         // [D][Lacc] partial sums for limb assembly
+  uint32_t* acc_hi;         // [D][Lacc]
+  int32_t Lacc;             // min(Lcap, P + 1)
+  uint32_t* out;            // [(degcap+1)][Lcap] result limbs
+  int32_t Lcap, degcap;
+  int32_t* deg_out;         // highest non-zero coefficient index (init -1)
+  int32_t* err;             // set non-zero on a failed internal check
+};
+
+// Tables shared by every job: the prime list and the mixed-radix constants.
+struct TablesDev {
+  const ModP* primes;       // [K]
+  const uint32_t* gm;       // [K][K]: gm[j*K+k] = (prod_{i<j} p_i) R mod p_k, j < k
+  const uint32_t* cm;       // [K]: (prod_{i<k} p_i)^{-1} R mod p_k
+  const uint32_t* pi;       // prod_{i<k} p_i as k+1 limbs at offset k(k+1)/2
+  int32_t K;
+};
+
+}  // namespace bires

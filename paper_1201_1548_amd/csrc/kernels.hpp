@@ -1,0 +1,32 @@
+// Launchers of the HIP kernels in kernels.hip (host-callable, no HIP types
+// beyond hipStream_t and the plain structs of job.hpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "job.hpp"
+
+namespace bires {
+
+// Planning statistics of one limb rectangle: out[3*j + {0,1,2}] =
+// (x-degree of row j or -1, max bit length of |c| in the row, non-zero count).
+struct ScanTask {
+  const uint32_t* limbs;
+  int32_t rows, ld, L;
+  int32_t* out;
+};
+
+void launch_scan(const ScanTask* tasks, const int4* bmap, int nblocks, hipStream_t s);
+void launch_transpose(const uint32_t* src, uint32_t* dst, int rows, int cols, int L, hipStream_t s);
+void launch_reduce(const JobDev* jobs, const int4* bmap, int nblocks, int max_primes, TablesDev tab,
+                   hipStream_t s);
+int eval_elim_block();
+void launch_eval_elim(const JobDev* jobs, const int4* bmap, int nblocks, int max_words, TablesDev tab,
+                      hipStream_t s);
+void launch_interp(const JobDev* jobs, const int4* bmap, int nblocks, int max_points, TablesDev tab,
+                   hipStream_t s);
+void launch_mrc(const JobDev* jobs, const int4* bmap, int nblocks, int max_primes, TablesDev tab,
+                hipStream_t s);
+void launch_limbs_sum(const JobDev* jobs, const int4* bmap, int nblocks, TablesDev tab, hipStream_t s);
+void launch_limbs_carry(const JobDev* jobs, const int4* bmap, int nblocks, hipStream_t s);
+
+}  // namespace bires

@@ -1,0 +1,111 @@
+// Host construction of the prime table and of the mixed-radix constants.
+//
+// Primes: the K largest primes below 2^31, descending (deterministic
+// Miller-Rabin with bases 2, 7, 61, exact for n < 4,759,123,141).  Every job
+// uses a prefix of this table, so the Garner constants and the radix products
+// prod_{i<k} p_i are computed once for all jobs.
+#include "tables.hpp"
+
+#include <cmath>
+#include <mutex>
+
+namespace bires {
+
+static uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((unsigned __int128)a * b % m); }
+
+static uint64_t powmod64(uint64_t a, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  a %= m;
+  while (e) {
+    if (e & 1) r = mulmod64(r, a, m);
+    a = mulmod64(a, a, m);
+    e >>= 1;
+  }
+  return r;
+}
+
+static bool is_prime32(uint32_t n) {
+  if (n < 2) return false;
+  for (uint32_t sp : {2u, 3u, 5u, 7u, 11u, 13u, 61u})
+    if (n % sp == 0) return n == sp;
+  uint32_t d = n - 1;
+  int s = 0;
+  while ((d & 1) == 0) {
+    d >>= 1;
+    ++s;
+  }
+  for (uint64_t a : {2ull, 7ull, 61ull}) {
+    uint64_t x = powmod64(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int r = 1; r < s; ++r) {
+      x = mulmod64(x, x, n);
+      if (x == n - 1) {
+        comp = false;
+        break;
+      }
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+ModP make_modp(uint32_t p) {
+  ModP q;
+  q.p = p;
+  uint32_t inv = p;  // Newton iteration for p^{-1} mod 2^32 (p odd)
+  for (int i = 0; i < 5; ++i) inv *= 2u - p * inv;
+  q.pinv = 0u - inv;
+  q.one = (uint32_t)((((uint64_t)1) << 32) % p);
+  q.r2 = (uint32_t)(((unsigned __int128)1 << 64) % p);
+  return q;
+}
+
+static void build(HostTables& t, int K) {
+  t.K = K;
+  t.primes.clear();
+  for (uint32_t c = 0x7FFFFFFFu; (int)t.primes.size() < K; c -= 2)
+    if (is_prime32(c)) t.primes.push_back(make_modp(c));
+  t.log2p.resize(K);
+  t.cumlog.assign(K + 1, 0.0);
+  for (int k = 0; k < K; ++k) {
+    // a lower bound of log2 p_k (the relative error of log2 is far below 1e-12)
+    t.log2p[k] = std::log2((double)t.primes[k].p) - 1e-12;
+    t.cumlog[k + 1] = t.cumlog[k] + t.log2p[k];
+  }
+  t.gm.assign((size_t)K * K, 0u);
+  t.cm.assign(K, 0u);
+  for (int k = 0; k < K; ++k) {
+    const uint64_t pk = t.primes[k].p;
+    uint64_t prod = 1 % pk;  // prod_{i<j} p_i mod p_k
+    for (int j = 0; j < k; ++j) {
+      t.gm[(size_t)j * K + k] = (uint32_t)((prod << 32) % pk);
+      prod = mulmod64(prod, t.primes[j].p % pk, pk);
+    }
+    const uint64_t inv = powmod64(prod, pk - 2, pk);
+    t.cm[k] = (uint32_t)((inv << 32) % pk);
+  }
+  // prod_{i<k} p_i as k+1 little-endian limbs at offset k(k+1)/2
+  t.pi.assign((size_t)K * (K + 1) / 2 + K + 1, 0u);
+  std::vector<uint32_t> cur(1, 1u);
+  for (int k = 0; k < K; ++k) {
+    uint32_t* dst = &t.pi[(size_t)k * (k + 1) / 2];
+    for (int l = 0; l <= k && l < (int)cur.size(); ++l) dst[l] = cur[l];
+    uint64_t carry = 0;
+    for (auto& w : cur) {
+      uint64_t v = (uint64_t)w * t.primes[k].p + carry;
+      w = (uint32_t)v;
+      carry = v >> 32;
+    }
+    if (carry) cur.push_back((uint32_t)carry);
+  }
+}
+
+const HostTables& host_tables() {
+  static HostTables t;
+  static std::once_flag once;
+  std::call_once(once, [] { build(t, MAX_PRIMES); });
+  return t;
+}
+
+}  // namespace bires

@@ -1,0 +1,26 @@
+// Host-side tables: the primes and the mixed-radix constants (see tables.cpp).
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+#include "modp.hpp"
+
+namespace bires {
+
+constexpr int MAX_PRIMES = 2048;
+
+struct HostTables {
+  int K = 0;
+  std::vector<ModP> primes;     // K primes, descending from 2^31 - 1
+  std::vector<double> log2p;    // lower bounds of log2 p_k
+  std::vector<double> cumlog;   // cumlog[k] = sum_{i<k} log2p[i]
+  std::vector<uint32_t> gm;     // [K][K] Montgomery (prod_{i<j} p_i mod p_k), j < k
+  std::vector<uint32_t> cm;     // [K] Montgomery (prod_{i<k} p_i)^{-1} mod p_k
+  std::vector<uint32_t> pi;     // prod_{i<k} p_i, k+1 limbs at offset k(k+1)/2
+};
+
+ModP make_modp(uint32_t p);
+const HostTables& host_tables();
+
+}  // namespace bires

@@ -1,0 +1,202 @@
+"""Parity of the HIP path (through the C ABI) with the oracle: bit-exact.
+
+Stage parity: the univariate resultants the kernel produces at (prime p, point a)
+equal R(a) mod p of the oracle's R.  End-to-end parity: the reconstructed
+coefficients equal the oracle's (or the stored golden values the oracle wrote).
+Covers several tiles and ragged tails (points not a multiple of 64, residue
+counts not a multiple of the tile), degree drops at a = 0, zero inputs,
+y-free inputs, res_x, the discriminant, batches and device-memory buffers.
+"""
+
+import os
+import random
+
+import pytest
+
+import paper_1201_1548_amd as br
+from oracle import zx
+from oracle.closed_forms import product_discriminant, product_pair
+from oracle.resultant import discriminant_y, resultant_at, resultant_x, resultant_y
+from paper_1201_1548_amd import synth
+from tests.golden.make_golden import input_digest, load
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def test_stage_values_config1():
+    F, G = synth.config1_pair(0)
+    say("stage values config1 instance 0")
+    _, R = load("config1_res_0.txt")
+    ps, vals = br.debug_values(F, G)
+    assert vals.shape == (len(ps), 37)
+    for k, p in enumerate(ps):
+        for a in range(vals.shape[1]):
+            assert int(vals[k, a]) == zx.evaluate(R, a) % p, (k, a)
+
+
+@pytest.mark.parametrize("inst", range(4))
+def test_config1_bit_exact(inst):
+    F, G = synth.config1_pair(inst)
+    say("config1 instance", inst)
+    digest, R = load("config1_res_%d.txt" % inst)
+    assert digest == input_digest(F, G)
+    assert br.resultant(F, G) == R
+
+
+SHAPES = [  # (ydeg f, xdeg f, ydeg g, xdeg g, bits)
+    (1, 3, 1, 2, 16), (3, 1, 2, 4, 40), (4, 4, 3, 5, 31), (2, 6, 5, 2, 70),
+    (5, 3, 5, 3, 12), (6, 2, 1, 7, 100), (1, 0, 4, 3, 20), (7, 3, 6, 2, 33),
+]
+
+
+@pytest.mark.parametrize("i", range(len(SHAPES)))
+def test_random_shapes(i):
+    a, b, c, d, bits = SHAPES[i]
+    F, G = synth.random_rect(100 + i, a, b, c, d, bits)
+    say("random shape", SHAPES[i])
+    assert br.resultant(F, G) == resultant_y(F, G)
+
+
+@pytest.mark.parametrize("i", range(4))
+def test_random_shapes_x(i):
+    a, b, c, d, bits = SHAPES[i]
+    F, G = synth.random_rect(200 + i, a, b, c, d, bits)
+    say("res_x shape", SHAPES[i])
+    assert br.resultant(F, G, var="x") == resultant_x(F, G)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_discriminant_random(seed):
+    F, _ = synth.random_rect(300 + seed, 2 + seed, 3, 1, 1, 24 + 10 * seed)
+    say("discriminant seed", seed)
+    assert br.discriminant(F) == discriminant_y(F)
+
+
+def test_discriminant_closed_form_and_repeated_root():
+    rng = random.Random(5)
+    roots = [[rng.randint(-9, 9) for _ in range(3)] for _ in range(5)]
+    f, R = product_discriminant([3, 0, 1], roots)
+    say("discriminant closed form")
+    assert br.discriminant(f) == R
+    f2, R2 = product_discriminant([1, 1], [[1, 2], [1, 2], [0, 5]])
+    assert R2 == [] and br.discriminant(f2) == []
+
+
+def test_sparse_inputs_with_zero_rows():
+    F, G = synth.random_rect(400, 5, 4, 4, 5, 30, zero_frac=0.6)
+    say("sparse inputs")
+    assert br.resultant(F, G) == resultant_y(F, G)
+
+
+def test_degree_drops_at_zero():
+    # lc_y f = x (vanishes at a = 0), lc_y g = x + 1: formal-degree rule for f
+    F = [[1, 2, 3], [4, 0, 5], [0, 1]]
+    G = [[2, -1], [7, 3, 1], [1, 1]]
+    say("degree drops")
+    assert br.resultant(F, G) == resultant_y(F, G)
+    # both leading coefficients vanish at 0
+    G2 = [[2, -1], [7, 3, 1], [0, 2]]
+    assert br.resultant(F, G2) == resultant_y(F, G2)
+    # lc of g vanishes at 0 only
+    assert br.resultant(G, F) == resultant_y(G, F)
+    # f(0, y) identically zero
+    F0 = [[0, 1], [0, 2], [0, 0, 3]]
+    assert br.resultant(F0, G) == resultant_y(F0, G)
+
+
+def test_edge_conventions():
+    say("edge conventions")
+    G = [[1, 2], [0, 1], [5]]
+    assert br.resultant([[3, -1, 2]], G) == resultant_y([[3, -1, 2]], G)   # m_y = 0
+    assert br.resultant(G, [[3, -1, 2]]) == resultant_y(G, [[3, -1, 2]])   # n_y = 0
+    assert br.resultant([[3, 1]], [[7, 2]]) == [1]                          # empty determinant
+    assert br.resultant([[0, 0]], G) == [] and br.resultant(G, []) == []    # zero input
+    assert br.resultant([[0], [0], [0], [4]], [[1], [1]]) == resultant_y([[0], [0], [0], [4]], [[1], [1]])
+    with pytest.raises(br.BiresError):
+        br.discriminant([[1, 2, 3]])
+
+
+def test_closed_form_product_pair():
+    rng = random.Random(9)
+    A = [rng.randint(-5, 5) for _ in range(3)]
+    B = [1, rng.randint(-5, 5)]
+    a = [[rng.randint(-99, 99) for _ in range(3)] for _ in range(6)]
+    b = [[rng.randint(-99, 99) for _ in range(2)] for _ in range(5)]
+    f, g, R = product_pair(A, a, B, b)
+    say("closed form product pair")
+    assert br.resultant(f, g) == R
+    b[2] = a[4]                          # common root: R = 0
+    f, g, R = product_pair(A, a, B, b)
+    assert R == [] and br.resultant(f, g) == []
+
+
+def test_batch_equals_single_and_oracle():
+    jobs = []
+    for i in range(6):
+        a, b, c, d, bits = SHAPES[i]
+        F, G = synth.random_rect(500 + i, a, b, c, d, bits)
+        jobs.append(("res", F, G, "y"))
+    F, G = synth.config1_pair(1)
+    jobs.append(("res", F, G, "y"))
+    jobs.append(("res", F, G, "x"))
+    jobs.append(("disc", F, None, "y"))
+    jobs.append(("res", [[0]], G, "y"))
+    jobs.append(("res", [[3, 1]], [[7, 2]], "y"))
+    say("batch of", len(jobs))
+    res, st = br.resultant_batch(jobs)
+    assert st == [0] * len(jobs)
+    for (kind, F, G, var), R in zip(jobs, res):
+        if kind == "disc":
+            ref = discriminant_y(F)
+            assert br.discriminant(F) == R
+        else:
+            ref = resultant_y(F, G) if var == "y" else resultant_x(F, G)
+            assert br.resultant(F, G, var) == R
+        assert R == ref
+
+
+def test_batch_reports_per_job_errors():
+    F, G = synth.config1_pair(0)
+    res, st = br.resultant_batch([("res", F, G, "y"), ("disc", [[1, 2]], None, "y"), ("res", G, F, "y")])
+    assert st[0] == 0 and st[2] == 0 and st[1] == -1
+    assert res[0] == resultant_y(F, G) and res[2] == resultant_y(G, F)
+
+
+def test_device_memory_batch():
+    F, G = synth.config1_pair(2)
+    H, K = synth.random_rect(600, 3, 4, 4, 2, 50)
+    jobs = [("res", F, G, "y"), ("res", H, K, "x"), ("disc", H, None, "y"), ("res", [[5]], [[1, 1]], "y")]
+    say("device-memory batch")
+    b = br.DeviceBatch(jobs)
+    b.run()
+    out = b.results()
+    assert out[0] == resultant_y(F, G)
+    assert out[1] == resultant_x(H, K)
+    assert out[2] == discriminant_y(H)
+    assert out[3] == [1]
+    b.run_each()
+    assert b.results() == out
+
+
+def test_config2_spot_values():
+    F, G = synth.config2_pair(0)
+    say("config2 spot values")
+    R = br.resultant(F, G)
+    assert len(R) - 1 <= 400
+    for a in (0, 1, -1, 2, 12345):
+        assert zx.evaluate(R, a) == resultant_at(F, G, a), a
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "config2_res_0.txt")),
+                    reason="config-2 golden file not generated")
+def test_config2_golden_bit_exact():
+    F, G = synth.config2_pair(0)
+    say("config2 golden")
+    digest, R = load("config2_res_0.txt")
+    assert digest == input_digest(F, G)
+    assert br.resultant(F, G) == R
