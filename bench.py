@@ -118,18 +118,21 @@ def main():
               "device; see the sharding notes in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import torch
     import paper_1201_1548_amd as br
     from paper_1201_1548_amd import synth
 
+    n = args.pairs
+    pairs = [synth.config2_pair(s) for s in range(n)]
+    D, P, _ = br.plan(pairs[0][0], pairs[0][1])
+    # the CPU leg runs first, in forked workers, before anything touches the GPU
+    cpu = None if args.no_cpu else cpu_baseline(pairs, D)
+
+    import torch
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    n = args.pairs
-    pairs = [synth.config2_pair(s) for s in range(n)]
     batch = br.DeviceBatch([("res", F, G, "y") for F, G in pairs])
-    D, P, _ = br.plan(pairs[0][0], pairs[0][1])
 
     # correctness gate: batched == plain == stored oracle values
     batch.run()
@@ -166,7 +169,6 @@ def main():
     plain_value = n * args.plain_steps / dtp
 
     # roofline of the dominant kernel (evaluation + univariate resultants)
-    from oracle.resultant import bi_trim  # noqa: F401  (imported only to fail early if absent)
     rowdeg = [20 - j for j in range(21)]
     ops_per_instance = instance_ops(rowdeg, rowdeg)
     ops_launch = ops_per_instance * P * D * n
@@ -183,10 +185,6 @@ def main():
         "kernel_ms": round(avg_ms, 4),
         "ops_per_launch": ops_launch,
     }
-
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(pairs, D)
 
     out = {
         "metric": METRIC,

@@ -90,6 +90,14 @@ def lib():
         if not os.path.exists(path):
             raise RuntimeError("libbires.so is not built (run __graft_entry__.build() or "
                                "python -m paper_1201_1548_amd.build); there is no fallback path")
+        # One HIP runtime per process: torch ships its own libamdhip64 (soname
+        # libamdhip64.so.7).  Loading torch first makes the dynamic loader bind
+        # libbires to that same runtime, so torch's streams and device pointers
+        # are valid in the library.  (Importing torch does not touch the GPU.)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(path)
         for name, (args, res) in _SIGS.items():
             fn = getattr(L, name)
