@@ -132,6 +132,7 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    dev = br.device_info()
     batch = br.DeviceBatch([("res", F, G, "y") for F, G in pairs])
 
     # correctness gate: batched == plain == stored oracle values
@@ -208,6 +209,7 @@ def main():
                   "ms_per_pair": round(dtp / (n * args.plain_steps) * 1e3, 3)},
         "batched_over_plain": round(value / plain_value, 2),
         "bit_exact": {"batched_vs_plain": exact_plain, "pair0_vs_oracle_golden": exact_golden},
+        "device": dev,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

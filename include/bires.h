@@ -190,6 +190,10 @@ int bires_debug_values(const bires_bipoly *f, const bires_bipoly *g, int kind, i
 int bires_set_timing(int enable);
 int bires_kernel_time(double *ms, int64_t *launches);
 
+/* Properties of the current device as the HIP runtime reports them: compute
+ * units, peak engine clock (kHz), LDS bytes per workgroup, HBM bytes. */
+int bires_device_info(int32_t *compute_units, int32_t *clock_khz, int64_t *lds_per_block, int64_t *hbm_bytes);
+
 const char *bires_strerror(int code);
 
 #ifdef __cplusplus

@@ -79,6 +79,8 @@ _SIGS = {
     "bires_set_timing": ([ctypes.c_int], ctypes.c_int),
     "bires_kernel_time": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "bires_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "bires_device_info": ([ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
 }
 
 
@@ -398,9 +400,15 @@ class DeviceBatch:
             self.out_tensors.append(t)
             self.caps.append((deg, L))
 
+    def _reset_outs(self):
+        if not hasattr(self, "_outs_template"):
+            self._outs_template = (Upoly * self.n)()
+            for i, (deg, L) in enumerate(self.caps):
+                self._outs_template[i] = Upoly(deg, L, self.out_tensors[i].data_ptr())
+        ctypes.memmove(self.outs, self._outs_template, ctypes.sizeof(self.outs))
+
     def run(self, stream=None):
-        for i, (deg, L) in enumerate(self.caps):
-            self.outs[i] = Upoly(deg, L, self.out_tensors[i].data_ptr())
+        self._reset_outs()
         code = lib().bires_resultant_batch(self.n, self.fds, self.gds, self.kinds, self.vars, self.outs,
                                            self.status, MEM_DEVICE, _torch_stream(stream))
         _check(code, "bires_resultant_batch")
@@ -409,8 +417,8 @@ class DeviceBatch:
     def run_each(self, stream=None):
         """The plain path: one single-job call per job (bires_resultant / bires_discriminant)."""
         s = _torch_stream(stream)
-        for i, (deg, L) in enumerate(self.caps):
-            self.outs[i] = Upoly(deg, L, self.out_tensors[i].data_ptr())
+        self._reset_outs()
+        for i in range(self.n):
             if self.kinds[i] == KIND_RESULTANT:
                 code = lib().bires_resultant(ctypes.byref(self.fds[i]), ctypes.byref(self.gds[i]), self.vars[i],
                                              ctypes.byref(self.outs[i]), MEM_DEVICE, s)
@@ -427,3 +435,14 @@ class DeviceBatch:
             arr = self.out_tensors[i][: deg + 1].cpu().numpy().view(np.uint32)
             res.append(limbs_to_ints(arr) if deg >= 0 else [])
         return res
+
+
+def device_info():
+    """(compute units, peak clock kHz, LDS bytes per block, HBM bytes) of the current device."""
+    cu = ctypes.c_int32()
+    clk = ctypes.c_int32()
+    lds = ctypes.c_int64()
+    hbm = ctypes.c_int64()
+    _check(lib().bires_device_info(ctypes.byref(cu), ctypes.byref(clk), ctypes.byref(lds), ctypes.byref(hbm)),
+           "bires_device_info")
+    return {"cus": cu.value, "clock_khz": clk.value, "lds_per_block": lds.value, "hbm_bytes": hbm.value}

@@ -171,6 +171,19 @@ int bires_kernel_time(double* ms, int64_t* launches) {
   return BIRES_OK;
 }
 
+int bires_device_info(int32_t* compute_units, int32_t* clock_khz, int64_t* lds_per_block, int64_t* hbm_bytes) {
+  int err = BIRES_OK;
+  Context* cx = context(&err);
+  if (!cx) return err;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, cx->device) != hipSuccess) return BIRES_EDEVICE;
+  if (compute_units) *compute_units = prop.multiProcessorCount;
+  if (clock_khz) *clock_khz = prop.clockRate;
+  if (lds_per_block) *lds_per_block = (int64_t)prop.sharedMemPerBlock;
+  if (hbm_bytes) *hbm_bytes = (int64_t)prop.totalGlobalMem;
+  return BIRES_OK;
+}
+
 const char* bires_strerror(int code) {
   switch (code) {
     case BIRES_OK: return "success";

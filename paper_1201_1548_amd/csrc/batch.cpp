@@ -113,13 +113,23 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
       const Shape& s = shp(i, which);
       const size_t bytes = (size_t)s.rows * s.ld * s.L * 4;
       if (mem == BIRES_MEM_HOST || jobs[i].var == BIRES_VAR_X) w[i].o_in[which] = in.take(bytes);
-      if (mem == BIRES_MEM_DEVICE) {
-        w[i].o_scan[which] = in.take((size_t)s.rows * 12);
+    }
+  }
+  // scan outputs in one contiguous region (one copy back)
+  const size_t scan_begin = in.take(0);
+  if (mem == BIRES_MEM_DEVICE) {
+    for (int i = 0; i < nj; ++i) {
+      if (w[i].status) continue;
+      for (int which = 0; which < nsrc(i); ++which) {
+        const Shape& s = shp(i, which);
+        w[i].o_scan[which] = in.bytes;
+        in.bytes += (size_t)s.rows * 12;
         for (int r0 = 0; r0 < s.rows; r0 += 64) smap.push_back(make_int4((int)tasks.size(), r0, 0, 0));
         tasks.push_back(ScanTask{});
       }
     }
   }
+  const size_t scan_end = in.bytes;
   const size_t o_tasks = in.take(sizeof(ScanTask) * tasks.size());
   const size_t o_smap = in.take(sizeof(int4) * smap.size());
   Held d_in(&cx->dev, in.bytes), h_in(&cx->host, in.bytes);
@@ -160,14 +170,9 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
                        hipMemcpyHostToDevice, st));
     if (!smap.empty())
       launch_scan((const ScanTask*)(d_in.b() + o_tasks), (const int4*)(d_in.b() + o_smap), (int)smap.size(), st);
-    for (int i = 0; i < nj; ++i) {
-      if (w[i].status) continue;
-      for (int which = 0; which < nsrc(i); ++which) {
-        const size_t o = w[i].o_scan[which];
-        const int rows = shp(i, which).rows;
-        if (rows) DEV(hipMemcpyAsync(h_in.b() + o, d_in.b() + o, (size_t)rows * 12, hipMemcpyDeviceToHost, st));
-      }
-    }
+    if (scan_end > scan_begin)
+      DEV(hipMemcpyAsync(h_in.b() + scan_begin, d_in.b() + scan_begin, scan_end - scan_begin, hipMemcpyDeviceToHost,
+                         st));
     DEV(hipStreamSynchronize(st));
     for (int i = 0; i < nj; ++i) {
       if (w[i].status) continue;
@@ -202,7 +207,11 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
       x.stg = derive_stats(x.stf);
     }
     if ((x.status = make_plan(x.stf, x.stg, x.pl))) continue;
-    if (x.pl.kind_special == 0 && (size_t)x.pl.D * 12 > cx->lds_per_block) {
+    if (x.pl.kind_special == 0 &&
+        (x.pl.D > MAX_POINTS || interp_lds_words(x.pl.D) * 4 > cx->lds_per_block ||
+         eval_elim_lds_bytes(x.pl.m + x.pl.n + 2,
+                             (x.pl.m + 1) * x.sf.ld + (x.pl.n + 1) * (x.disc ? x.sf.ld : x.sg.ld)) >
+             cx->lds_per_block)) {
       x.status = BIRES_ETOOBIG;
       continue;
     }
@@ -230,8 +239,11 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   // ---------------- workspace: device buffers, then the uploaded metadata block
   Layout ws;
   Layout hout;  // host staging of outputs (host memory space only)
-  std::vector<int4> m_red, m_ee, m_ip, m_mrc, m_sum, m_car;
-  int maxP = 1, maxWords = 2, maxD = 1;
+  // per-kernel first block of each job (prefix sums of the per-job block counts)
+  enum { K_RED, K_EE, K_IP, K_MRC, K_SUM, K_CAR, NK };
+  std::vector<int> starts[NK];
+  for (auto& v : starts) v.assign(nj + 1, 0);
+  int maxP = 1, maxWords = 2, maxD = 1, maxRes = 1;
   for (int i = 0; i < nj; ++i) {
     Work& x = w[i];
     if (x.status || !x.active) continue;
@@ -253,22 +265,22 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     maxP = std::max(maxP, p.P);
     maxD = std::max(maxD, p.D);
     maxWords = std::max(maxWords, p.m + p.n + 2);
-    for (int t0 = 0; t0 < x.Tf; t0 += 64) m_red.push_back(make_int4(i, 0, t0, 0));
-    for (int t0 = 0; t0 < x.Tg; t0 += 64) m_red.push_back(make_int4(i, 1, t0, 0));
-    for (int k = 0; k < p.P; ++k)
-      for (int a0 = 0; a0 < p.D; a0 += 64) m_ee.push_back(make_int4(i, k, a0, 0));
-    for (int k = 0; k < p.P; ++k) m_ip.push_back(make_int4(i, k, 0, 0));
-    for (int c = 0; c < p.D; ++c) m_mrc.push_back(make_int4(i, c, 0, 0));
-    for (int t0 = 0; t0 < p.D * x.Lacc; t0 += 256) m_sum.push_back(make_int4(i, 0, t0, 0));
-    for (int c0 = 0; c0 <= x.degcap; c0 += 64) m_car.push_back(make_int4(i, 0, c0, 0));
+    maxRes = std::max(maxRes, x.Tf + x.Tg);
+    starts[K_RED][i + 1] = (x.Tf + 63) / 64 + (x.Tg + 63) / 64;
+    starts[K_EE][i + 1] = p.P * ((p.D + 63) / 64);
+    starts[K_IP][i + 1] = p.P;
+    starts[K_MRC][i + 1] = p.D;
+    starts[K_SUM][i + 1] = (p.D * x.Lacc + 255) / 256;
+    starts[K_CAR][i + 1] = debug ? 0 : (x.degcap + 1 + 63) / 64;
   }
+  for (auto& v : starts)
+    for (int i = 0; i < nj; ++i) v[i + 1] += v[i];
   const size_t meta_begin = ws.take(0);
   const size_t o_jobs = ws.take(sizeof(JobDev) * (size_t)nj);
   const size_t o_flags = ws.take(sizeof(int32_t) * 2 * (size_t)nj);
   for (int i = 0; i < nj; ++i)
     if (!w[i].status && w[i].active) w[i].o_rowdeg = ws.take((size_t)(w[i].pl.m + w[i].pl.n + 2) * 4);
-  const size_t nmaps = m_red.size() + m_ee.size() + m_ip.size() + m_mrc.size() + m_sum.size() + m_car.size();
-  const size_t o_maps = ws.take(sizeof(int4) * nmaps);
+  const size_t o_maps = ws.take(sizeof(int) * (size_t)NK * (nj + 1));
   const size_t meta_end = ws.bytes;
   Held d_ws(&cx->dev, ws.bytes), h_meta(&cx->host, meta_end - meta_begin), h_out(&cx->host, hout.bytes);
   if ((ws.bytes && !d_ws.p) || (meta_end > meta_begin && !h_meta.p) || (hout.bytes && !h_out.p))
@@ -321,41 +333,31 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     J.deg_out = (int32_t*)(D0 + o_flags) + 2 * i;
     J.err = (int32_t*)(D0 + o_flags) + 2 * i + 1;
   }
-  int4* hm = (int4*)(H0 + o_maps);
-  const int4* dm = (const int4*)(D0 + o_maps);
-  size_t mo = 0;
-  auto put = [&](const std::vector<int4>& v) {
-    const int4* d = dm + mo;
-    if (!v.empty()) std::memcpy(hm + mo, v.data(), v.size() * sizeof(int4));
-    mo += v.size();
-    return d;
-  };
-  const int4* d_red = put(m_red);
-  const int4* d_ee = put(m_ee);
-  const int4* d_ip = put(m_ip);
-  const int4* d_mrc = put(m_mrc);
-  const int4* d_sum = put(m_sum);
-  const int4* d_car = put(m_car);
+  int* hm = (int*)(H0 + o_maps);
+  const int* dm = (const int*)(D0 + o_maps);
+  for (int kk = 0; kk < NK; ++kk) std::memcpy(hm + (size_t)kk * (nj + 1), starts[kk].data(), sizeof(int) * (nj + 1));
+  auto st_of = [&](int kk) { return dm + (size_t)kk * (nj + 1); };
+  auto nb_of = [&](int kk) { return starts[kk][nj]; };
   if (meta_end > meta_begin)
     DEV(hipMemcpyAsync(D0 + meta_begin, h_meta.p, meta_end - meta_begin, hipMemcpyHostToDevice, st));
   const JobDev* d_jobs = (const JobDev*)(D0 + o_jobs);
 
   // ---------------- kernels
-  const bool timing = cx->timing && !m_ee.empty();
+  const bool timing = cx->timing && nb_of(K_EE) > 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (timing) {
     DEV(hipEventCreate(&ev0));
     DEV(hipEventCreate(&ev1));
   }
-  if (!m_red.empty()) launch_reduce(d_jobs, d_red, (int)m_red.size(), maxP, cx->tab, st);
+  if (nb_of(K_RED)) launch_reduce(d_jobs, st_of(K_RED), nj, nb_of(K_RED), maxP, cx->tab, st);
   if (timing) DEV(hipEventRecord(ev0, st));
-  if (!m_ee.empty()) launch_eval_elim(d_jobs, d_ee, (int)m_ee.size(), maxWords, cx->tab, st);
+  if (nb_of(K_EE)) launch_eval_elim(d_jobs, st_of(K_EE), nj, nb_of(K_EE), maxWords, maxRes, cx->tab, st);
   if (timing) DEV(hipEventRecord(ev1, st));
   if (!debug) {
-    if (!m_ip.empty()) launch_interp(d_jobs, d_ip, (int)m_ip.size(), maxD, cx->tab, st);
-    if (!m_mrc.empty()) launch_mrc(d_jobs, d_mrc, (int)m_mrc.size(), maxP, cx->tab, st);
-    if (!m_sum.empty()) launch_limbs_sum(d_jobs, d_sum, (int)m_sum.size(), cx->tab, st);
-    if (!m_car.empty()) launch_limbs_carry(d_jobs, d_car, (int)m_car.size(), st);
+    if (nb_of(K_IP)) launch_interp(d_jobs, st_of(K_IP), nj, nb_of(K_IP), maxD, cx->tab, st);
+    if (nb_of(K_MRC)) launch_mrc(d_jobs, st_of(K_MRC), nj, nb_of(K_MRC), maxP, cx->tab, st);
+    if (nb_of(K_SUM)) launch_limbs_sum(d_jobs, st_of(K_SUM), nj, nb_of(K_SUM), cx->tab, st);
+    if (nb_of(K_CAR)) launch_limbs_carry(d_jobs, st_of(K_CAR), nj, nb_of(K_CAR), st);
   }
   DEV(hipGetLastError());
 

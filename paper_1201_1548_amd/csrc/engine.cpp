@@ -114,6 +114,13 @@ static int init_context(Context& cx) {
   cx.tab.cm = cm;
   cx.tab.pi = pi;
   cx.tab.K = t.K;
+  uint32_t* invfact = nullptr;
+  HIP_OK(hipMalloc(&invfact, (size_t)t.K * MAX_POINTS * sizeof(uint32_t)));
+  launch_invfact(primes, t.K, invfact, MAX_POINTS, cx.stream);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(cx.stream));
+  cx.tab.invfact = invfact;
+  cx.tab.dmax = MAX_POINTS;
   return BIRES_OK;
 }
 

@@ -41,7 +41,9 @@ struct TablesDev {
   const uint32_t* gm;       // [K][K]: gm[j*K+k] = (prod_{i<j} p_i) R mod p_k, j < k
   const uint32_t* cm;       // [K]: (prod_{i<k} p_i)^{-1} R mod p_k
   const uint32_t* pi;       // prod_{i<k} p_i as k+1 limbs at offset k(k+1)/2
+  const uint32_t* invfact;  // [K][dmax]: Montgomery form of 1/n! mod p_k
   int32_t K;
+  int32_t dmax;
 };
 
 }  // namespace bires

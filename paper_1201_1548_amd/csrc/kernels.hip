@@ -7,18 +7,31 @@
 //   k_reduce      (a) coefficients modulo each prime, Montgomery form
 //   k_eval_elim   (b)+(c) evaluate at x = a and take the univariate resultant
 //                 over F_p, one lane per (prime, point)
-//   k_interp      (d) Newton interpolation per prime, nodes a = 0..D-1
+//   k_interp      (d) interpolation per prime, nodes a = 0..D-1
+//   k_invfact     table of 1/n! mod p (set-up)
 //   k_mrc         (e) mixed-radix (Garner) digits per coefficient
 //   k_limbs_sum / k_limbs_carry   (e) digits -> two's-complement limbs
 //
-// Every kernel is batch-native: a block map (int4 per block) names the job and
-// the slice of it the block works on, so a single job is a batch of one.
+// Every kernel is batch-native: an array of per-job first-block indices maps
+// each block to its job (binary search), so a single job is a batch of one.
 #include <hip/hip_runtime.h>
 
 #include "job.hpp"
 #include "kernels.hpp"
 
 namespace bires {
+
+// Block -> job: starts[0..nj] are the first block of each job (starts[nj] =
+// grid size); returns the largest j with starts[j] <= b (uniform, scalar).
+__device__ __forceinline__ int find_job(const int* __restrict__ starts, int nj, int b) {
+  int lo = 0, hi = nj;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (starts[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
 
 // ---------------------------------------------------------------------------
 // planning statistics: for each row j of a rectangle, the x-degree, the
@@ -69,20 +82,23 @@ __global__ void k_transpose(const uint32_t* src, uint32_t* dst, int rows, int co
 }
 
 // ---------------------------------------------------------------------------
-// (a) reduction modulo the primes.  Block map: x = job, y = 0 (f) / 1 (g),
-// z = first coefficient; blockIdx.y selects a tile of KT primes.  A coefficient
+// (a) reduction modulo the primes.  Each job has ceil(Tf/64) blocks for f
+// then ceil(Tg/64) for g, 64 coefficients each; blockIdx.y selects a tile of
+// KT primes.  A coefficient
 // with limbs w_0..w_{L-1} (two's complement) has value sum w_l 2^{32l} - s 2^{32L};
 // its Montgomery residue is built by Horner over the limbs with one two-product
 // reduction per limb, then the sign term (R^L)_M is subtracted.
 
 constexpr int KT = 16;
 
-__global__ void k_reduce(const JobDev* jobs, const int4* bmap, TablesDev tab) {
-  int4 bm = bmap[blockIdx.x];
-  const JobDev& J = jobs[bm.x];
-  const bool isg = bm.y != 0;
+__global__ void k_reduce(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
+  const int job = find_job(starts, nj, blockIdx.x);
+  const JobDev& J = jobs[job];
+  const int lb = blockIdx.x - starts[job];
+  const int nbf = (J.Tf + 63) / 64;
+  const bool isg = lb >= nbf;
   const int T = isg ? J.Tg : J.Tf;
-  const int t = bm.z + threadIdx.x;
+  const int t = (isg ? lb - nbf : lb) * 64 + threadIdx.x;
   const int k0 = blockIdx.y * KT;
   if (t >= T || k0 >= J.P) return;
   const uint32_t* src;
@@ -131,6 +147,28 @@ __global__ void k_reduce(const JobDev* jobs, const int4* bmap, TablesDev tab) {
 // and res(A, B) = (-1)^{ab} lc(B)^{a-c-kb} res(B, A_k); positive powers go to
 // a numerator, negative ones to a denominator inverted once at the end.
 
+__device__ __forceinline__ int wave_uniform(int x) {
+  // 1 when every active lane holds the same value
+  return __ballot(x != __builtin_amdgcn_readfirstlane(x)) == 0ull;
+}
+
+// The a - b + 1 eliminations of one Euclid step: A <- lc(B) A - A_top y^(a'-b) B
+// for a' = a, a-1, ..., b.  Afterwards A holds lc(B)^(a-b+1) (A mod B) in
+// its coefficients 0..b-1 (an elimination whose top coefficient is already
+// zero only scales A, which keeps that identity).  With wave-uniform a and b
+// every loop bound is a scalar.
+template <int W>
+__device__ __forceinline__ void eliminate(uint32_t* A, const uint32_t* B, int a, int b, uint32_t lb,
+                                          const ModP& q) {
+  for (; a >= b; --a) {
+    const uint32_t nla = mneg(A[a * W], q.p);
+    const int s = a - b;
+    for (int t = 0; t < s; ++t) A[t * W] = mmul(lb, A[t * W], q);
+#pragma unroll 4
+    for (int t = s; t < a; ++t) A[t * W] = mdot2(lb, A[t * W], nla, B[(t - s) * W], q);
+  }
+}
+
 template <int W>
 __device__ uint32_t uni_resultant(uint32_t* A, uint32_t* B, int m, int n, const ModP& q) {
   if (m == 0 && n == 0) return q.one;  // empty determinant
@@ -154,119 +192,249 @@ __device__ uint32_t uni_resultant(uint32_t* A, uint32_t* B, int m, int n, const 
     int t = a; a = b; b = t;
     neg ^= ((a * b) & 1) != 0;
   }
-  for (;;) {
-    if (b == 0) {
-      num = mmul(num, mpow(B[0], (uint32_t)a, q), q);
-      break;
-    }
+  // Step i (B of degree b_i, lc l_i, remainder degree c_i) contributes
+  // l_i^(e_i), e_i = a - c_i - (a - b_i + 1) b_i.  Split e_i = -2(b_i - 1) + d_i:
+  // prod_i l_i^(2(b_i - 1)) = prod_t P_t over t = 1..b_0-1 with P the prefix
+  // products of l_i^2 and t in [max(c_i, 1), b_i - 1] taking P_i, so a generic
+  // step (c_i = b_i - 1, d_i = 0) costs three products and no power.
+  uint32_t pfx = q.one;
+  while (b > 0) {
     const uint32_t lb = B[b * W];
-    const int a0 = a;
-    int kk = 0;
-    while (a >= b) {
-      const uint32_t nla = mneg(A[a * W], q.p);
-      const int s = a - b;
-      for (int t = 0; t < s; ++t) A[t * W] = mmul(lb, A[t * W], q);
-      for (int t = s; t < a; ++t) A[t * W] = mdot2(lb, A[t * W], nla, B[(t - s) * W], q);
-      --a;
-      ++kk;
-      while (a >= 0 && A[a * W] == 0u) --a;
-    }
-    if (a < 0) return 0u;
-    neg ^= ((a0 * b) & 1) != 0;
-    const int e = a0 - a - kk * b;
-    if (e > 0) num = mmul(num, mpow(lb, (uint32_t)e, q), q);
-    else if (e < 0) den = mmul(den, mpow(lb, (uint32_t)(-e), q), q);
+    if (wave_uniform(a) && wave_uniform(b))
+      eliminate<W>(A, B, __builtin_amdgcn_readfirstlane(a), __builtin_amdgcn_readfirstlane(b), lb, q);
+    else
+      eliminate<W>(A, B, a, b, lb, q);
+    int c = b - 1;
+    while (c >= 0 && A[c * W] == 0u) --c;
+    if (c < 0) return 0u;
+    neg ^= ((a * b) & 1) != 0;
+    pfx = mmul(pfx, mmul(lb, lb, q), q);
+    const int x = b - (c > 1 ? c : 1);
+    if (x == 1) den = mmul(den, pfx, q);
+    else if (x > 1) den = mmul(den, mpow(pfx, (uint32_t)x, q), q);
+    const int d = a - c - (a - b + 1) * b + 2 * (b - 1);
+    if (d > 0) num = mmul(num, mpow(lb, (uint32_t)d, q), q);
+    else if (d < 0) den = mmul(den, mpow(lb, (uint32_t)(-d), q), q);
     uint32_t* T = A; A = B; B = T;
-    int t = a; a = b; b = t;
+    a = b;
+    b = c;
   }
+  num = mmul(num, mpow(B[0], (uint32_t)a, q), q);
   uint32_t r = (den == q.one) ? num : mmul(num, minv(den, q), q);
   return neg ? mneg(r, q.p) : r;
 }
 
-// (b)+(c): block map x = job, y = prime index k, z = first point; one lane per
-// point a = z + lane.  The prime is uniform over the block, so its constants
-// and the residue rows are scalar loads.
+// (b)+(c): each job has P * ceil(D/W) blocks, prime-major; one lane per
+// point a.  The block stages the prime's residues and the row
+// degrees in LDS, then each lane evaluates f(a, y), g(a, y) by Horner's rule
+// into its own arrays and runs the elimination.
 template <int W>
-__global__ __launch_bounds__(W) void k_eval_elim(const JobDev* jobs, const int4* bmap, TablesDev tab) {
+__global__ __launch_bounds__(W) void k_eval_elim(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
   extern __shared__ uint32_t lds[];
-  const int4 bm = bmap[blockIdx.x];
-  const JobDev& J = jobs[bm.x];
-  const int k = bm.y;
-  const int pt = bm.z + (int)threadIdx.x;
+  const int job = find_job(starts, nj, blockIdx.x);
+  const JobDev& J = jobs[job];
+  const int lb = blockIdx.x - starts[job];
+  const int nbpp = (J.D + W - 1) / W;
+  const int k = lb / nbpp;
+  const int a0 = (lb - k * nbpp) * W;
+  const int m = J.m, n = J.n;
+  const int Tf = J.Tf, Tg = J.Tg, ldf = J.ldf;
+  const int ldg = J.disc ? J.ldf : J.ldg;
+  uint32_t* R = lds;                                 // residues: f rows, then g rows
+  int32_t* RD = (int32_t*)(lds + Tf + Tg);           // row degrees: f, then g
+  uint32_t* A = lds + Tf + Tg + (m + n + 2) + threadIdx.x;
+  uint32_t* B = A + (m + 1) * W;
+  const uint32_t* rf = J.res_f + (size_t)k * Tf;
+  const uint32_t* rg = J.res_g + (size_t)k * Tg;
+  for (int i = threadIdx.x; i < Tf; i += W) R[i] = rf[i];
+  for (int i = threadIdx.x; i < Tg; i += W) R[Tf + i] = rg[i];
+  for (int i = threadIdx.x; i <= m; i += W) RD[i] = J.rowdeg_f[i];
+  for (int i = threadIdx.x; i <= n; i += W) RD[m + 1 + i] = J.rowdeg_g[i];
+  __syncthreads();
+  const int pt = a0 + (int)threadIdx.x;
   if (pt >= J.D) return;
   const ModP q = tab.primes[k];
-  uint32_t* A = lds + threadIdx.x;
-  uint32_t* B = A + (J.m + 1) * W;
   const uint32_t aM = to_mont((uint32_t)pt, q);
-  const uint32_t* rf = J.res_f + (size_t)k * J.Tf;
-  for (int j = 0; j <= J.m; ++j) {
-    const uint32_t* row = rf + j * J.ldf;
+  for (int j = 0; j <= m; ++j) {
+    const uint32_t* row = R + j * ldf;
+    const int d = __builtin_amdgcn_readfirstlane(RD[j]);
     uint32_t acc = 0;
-    for (int i = J.rowdeg_f[j]; i >= 0; --i) acc = madd(mmul(acc, aM, q), row[i], q.p);
+#pragma unroll 4
+    for (int i = d; i >= 0; --i) acc = madd(mmul(acc, aM, q), row[i], q.p);
     A[j * W] = acc;
   }
-  const uint32_t* rg = J.res_g + (size_t)k * J.Tg;
-  const int ldg = J.disc ? J.ldf : J.ldg;
-  for (int j = 0; j <= J.n; ++j) {
-    const uint32_t* row = rg + j * ldg;
+  for (int j = 0; j <= n; ++j) {
+    const uint32_t* row = R + Tf + j * ldg;
+    const int d = __builtin_amdgcn_readfirstlane(RD[m + 1 + j]);
     uint32_t acc = 0;
-    for (int i = J.rowdeg_g[j]; i >= 0; --i) acc = madd(mmul(acc, aM, q), row[i], q.p);
+#pragma unroll 4
+    for (int i = d; i >= 0; --i) acc = madd(mmul(acc, aM, q), row[i], q.p);
     B[j * W] = acc;
   }
-  const uint32_t r = uni_resultant<W>(A, B, J.m, J.n, q);
+  const uint32_t r = uni_resultant<W>(A, B, m, n, q);
   J.vals[(size_t)k * J.D + pt] = from_mont(r, q);
 }
 
 // ---------------------------------------------------------------------------
-// (d) interpolation per prime.  Nodes a_i = i, so the divided differences are
-// c_j <- (c_j - c_{j-1}) / s at stage s; then the Newton form
-// sum_s c_s prod_{t<s} (x - t) is expanded by Horner from the top:
-// P <- P (x - s) + c_s.  Block map: x = job, y = prime index.
+// (d) interpolation per prime on the nodes a = 0, 1, ..., D-1.
+//
+// Sums of products are accumulated exactly in 96 bits (four products of
+// values below 2^31 fit in 64 bits) and reduced once per output.
 
-__global__ __launch_bounds__(256) void k_interp(const JobDev* jobs, const int4* bmap, TablesDev tab) {
+struct Acc96 {
+  uint64_t lo = 0;
+  uint32_t hi = 0;
+  __device__ void add(uint64_t s) {
+    lo += s;
+    hi += lo < s ? 1u : 0u;
+  }
+};
+
+// The 96-bit sum reduced modulo p (plain result).
+__device__ __forceinline__ uint32_t reduce96(const Acc96& A, const ModP& q, uint32_t r3) {
+  // x = lo_lo + 2^32 lo_hi + 2^64 hi = lo_lo + lo_hi (R)_plain + hi (R^2)_plain;
+  // with Montgomery constants R^2 = (R)_M and R^3 = (R^2)_M one two-product
+  // reduction gives lo_hi R + hi R^2 mod p.
+  const uint32_t l0 = reduce32((uint32_t)A.lo, q.p);
+  const uint32_t l1 = reduce32((uint32_t)(A.lo >> 32), q.p);
+  const uint32_t h = reduce32(A.hi, q.p);
+  return madd(mdot2(l1, q.r2, h, r3, q), l0, q.p);
+}
+
+// Divided differences on equally spaced nodes are scaled forward
+// differences: c_k = sum_{i<=k} v_i (-1)^{k-i} / (i! (k-i)!), a triangular
+// convolution of a_i = v_i / i! with b_j = (-1)^j / j!.  The Newton form
+// P(x) = sum_k c_k prod_{t<k} (x - t) is then expanded by Horner's rule over
+// blocks of KB nodes: P = sum_b N_{b KB}(x) T_b(x) with
+// T_b = sum_{r<KB} c_{b KB + r} prod_{t=b KB}^{b KB + r - 1} (x - t) and
+// N_{(b+1) KB} = N_{b KB} Q_b, Q_b = prod_{t=b KB}^{(b+1) KB - 1} (x - t), so
+// P <- P Q_b + T_b from the top block down; T_b and Q_b are built with KB
+// lane-parallel steps in one wave each.  One block per (job, prime).
+constexpr int KB = 32;
+
+__global__ __launch_bounds__(256) void k_interp(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
   extern __shared__ uint32_t lds[];
-  const int4 bm = bmap[blockIdx.x];
-  const JobDev& J = jobs[bm.x];
-  const int k = bm.y;
+  const int job = find_job(starts, nj, blockIdx.x);
+  const JobDev& J = jobs[job];
+  const int k = blockIdx.x - starts[job];
   const int D = J.D;
   const ModP q = tab.primes[k];
-  uint32_t* c0 = lds;
-  uint32_t* c1 = lds + D;
-  uint32_t* inv = lds + 2 * D;  // Montgomery form of 1/s
+  const uint32_t r3 = mmul(q.r2, q.r2, q);  // (R^2)_M = R^3 mod p
+  const int nb = (D + KB - 1) / KB;
+  uint32_t* A = lds;            // a_i, later P (ping)
+  uint32_t* Bv = lds + D;       // b_j, later P (pong)
+  uint32_t* C = lds + 2 * D;    // Newton coefficients
+  uint32_t* TQ = lds + 3 * D;   // per block: T_b (KB words) then Q_b (KB+1 words)
+  const uint32_t* invf = tab.invfact + (size_t)k * tab.dmax;
   const uint32_t* v = J.vals + (size_t)k * D;
-  for (int j = threadIdx.x; j < D; j += blockDim.x) {
-    c0[j] = v[j];
-    inv[j] = j ? minv(to_mont((uint32_t)j, q), q) : 0u;
+  for (int i = threadIdx.x; i < D; i += blockDim.x) {
+    const uint32_t f = invf[i];  // Montgomery form of 1/i!
+    A[i] = mmul(v[i], f, q);
+    const uint32_t bj = from_mont(f, q);
+    Bv[i] = (i & 1) ? mneg(bj, q.p) : bj;
   }
   __syncthreads();
-  for (int s = 1; s < D; ++s) {
-    const uint32_t is = inv[s];
-    for (int j = threadIdx.x; j < D; j += blockDim.x)
-      c1[j] = j >= s ? mmul(msub(c0[j], c0[j - 1], q.p), is, q) : c0[j];
-    __syncthreads();
-    uint32_t* t = c0; c0 = c1; c1 = t;
-  }
-  // c0 holds the Newton coefficients; expand into c1 (then ping-pong), keeping
-  // the Newton coefficients in inv[] (no longer needed as inverses).
-  for (int j = threadIdx.x; j < D; j += blockDim.x) {
-    inv[j] = c0[j];
-    c1[j] = j == 0 ? c0[D - 1] : 0u;
+  for (int kk = threadIdx.x; kk < D; kk += blockDim.x) {
+    Acc96 acc;
+    int i = 0;
+    for (; i + 4 <= kk + 1; i += 4) {
+      uint64_t s = (uint64_t)A[i] * Bv[kk - i];
+      s += (uint64_t)A[i + 1] * Bv[kk - i - 1];
+      s += (uint64_t)A[i + 2] * Bv[kk - i - 2];
+      s += (uint64_t)A[i + 3] * Bv[kk - i - 3];
+      acc.add(s);
+    }
+    uint64_t s = 0;
+    for (; i <= kk; ++i) s += (uint64_t)A[i] * Bv[kk - i];
+    acc.add(s);
+    C[kk] = reduce96(acc, q, r3);
   }
   __syncthreads();
-  uint32_t* a0 = c1;
-  uint32_t* a1 = c0;
-  for (int s = D - 2; s >= 0; --s) {
-    const uint32_t sM = to_mont((uint32_t)s, q);
-    const uint32_t cs = inv[s];
-    for (int j = threadIdx.x; j < D; j += blockDim.x) {
-      uint32_t x = msub(j ? a0[j - 1] : 0u, mmul(a0[j], sM, q), q.p);
-      a1[j] = j ? x : madd(x, cs, q.p);
+  // T_b and Q_b, one wave per block (lanes hold coefficients 0..KB)
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nwaves = blockDim.x >> 6;
+  for (int b = wave; b < nb; b += nwaves) {
+    const int base = b * KB;
+    const int len = min(KB, D - base);
+    uint32_t T = lane == 0 ? C[base + len - 1] : 0u;
+    for (int r = len - 2; r >= 0; --r) {  // T <- T (x - (base + r)) + c_{base + r}
+      const uint32_t tM = to_mont((uint32_t)(base + r), q);
+      const uint32_t up = __shfl_up(T, 1);
+      uint32_t nt = msub(lane ? up : 0u, mmul(T, tM, q), q.p);
+      if (lane == 0) nt = madd(nt, C[base + r], q.p);
+      T = lane <= KB ? nt : 0u;
+    }
+    uint32_t Q = lane == 0 ? 1u : 0u;
+    for (int r = 0; r < KB; ++r) {        // Q <- Q (x - (base + r))
+      const uint32_t tM = to_mont((uint32_t)(base + r), q);
+      const uint32_t up = __shfl_up(Q, 1);
+      const uint32_t nq = msub(lane ? up : 0u, mmul(Q, tM, q), q.p);
+      Q = lane <= KB ? nq : 0u;
+    }
+    if (lane < KB) TQ[b * (2 * KB + 1) + lane] = T;
+    if (lane <= KB) TQ[b * (2 * KB + 1) + KB + lane] = Q;
+  }
+  __syncthreads();
+  // Horner over blocks: P <- P Q_b + T_b
+  uint32_t* P0 = A;
+  uint32_t* P1 = Bv;
+  int degP = min(KB, D - (nb - 1) * KB) - 1;
+  for (int j = threadIdx.x; j <= degP; j += blockDim.x) P0[j] = TQ[(nb - 1) * (2 * KB + 1) + j];
+  __syncthreads();
+  for (int b = nb - 2; b >= 0; --b) {
+    const uint32_t* T = TQ + b * (2 * KB + 1);
+    const uint32_t* Qb = T + KB;
+    const int degN = degP + KB;
+    for (int j = threadIdx.x; j <= degN; j += blockDim.x) {
+      const int t0 = max(0, j - degP), t1 = min(KB, j);
+      Acc96 acc;
+      int t = t0;
+      for (; t + 4 <= t1 + 1; t += 4) {
+        uint64_t s = (uint64_t)P0[j - t] * Qb[t];
+        s += (uint64_t)P0[j - t - 1] * Qb[t + 1];
+        s += (uint64_t)P0[j - t - 2] * Qb[t + 2];
+        s += (uint64_t)P0[j - t - 3] * Qb[t + 3];
+        acc.add(s);
+      }
+      uint64_t s = j < KB ? (uint64_t)T[j] : 0u;
+      for (; t <= t1; ++t) s += (uint64_t)P0[j - t] * Qb[t];
+      acc.add(s);
+      P1[j] = reduce96(acc, q, r3);
     }
     __syncthreads();
-    uint32_t* t = a0; a0 = a1; a1 = t;
+    uint32_t* tmp = P0; P0 = P1; P1 = tmp;
+    degP = degN;
   }
   uint32_t* out = J.coefs + (size_t)k * D;
-  for (int j = threadIdx.x; j < D; j += blockDim.x) out[j] = a0[j];
+  for (int j = threadIdx.x; j < D; j += blockDim.x) out[j] = P0[j];
+}
+
+size_t interp_lds_words(int D) { return (size_t)3 * D + (size_t)((D + KB - 1) / KB) * (2 * KB + 1); }
+
+// Inverse factorials per prime: invfact[k][n] = Montgomery form of 1/n!.
+// One thread per prime: prefix products, one Fermat inverse, backward products.
+__global__ void k_invfact(const ModP* primes, int K, uint32_t* invfact, int dmax) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const ModP q = primes[k];
+  uint32_t* t = invfact + (size_t)k * dmax;
+  uint32_t f = q.one;  // 0! in Montgomery form
+  t[0] = f;
+  for (int n = 1; n < dmax; ++n) {
+    f = mmul(f, to_mont((uint32_t)n, q), q);
+    t[n] = f;  // n! for now
+  }
+  uint32_t inv = minv(f, q);  // 1/(dmax-1)!
+  for (int n = dmax - 1; n >= 1; --n) {
+    t[n] = inv;
+    inv = mmul(inv, to_mont((uint32_t)n, q), q);  // 1/(n-1)! = n / n!
+  }
+  t[0] = q.one;
+}
+
+void launch_invfact(const ModP* primes, int K, uint32_t* invfact, int dmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_invfact, dim3((K + 63) / 64), dim3(64), 0, s, primes, K, invfact, dmax);
 }
 
 // ---------------------------------------------------------------------------
@@ -278,11 +446,11 @@ __global__ __launch_bounds__(256) void k_interp(const JobDev* jobs, const int4* 
 // when the digit vector exceeds ((p_k - 1)/2)_k lexicographically from the top,
 // because sum_k (p_k - 1)/2 prod_{i<k} p_i = (M - 1)/2.
 
-__global__ __launch_bounds__(64) void k_mrc(const JobDev* jobs, const int4* bmap, TablesDev tab) {
+__global__ __launch_bounds__(64) void k_mrc(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
   extern __shared__ uint32_t lds[];
-  const int4 bm = bmap[blockIdx.x];
-  const JobDev& J = jobs[bm.x];
-  const int c = bm.y;
+  const int job = find_job(starts, nj, blockIdx.x);
+  const JobDev& J = jobs[job];
+  const int c = blockIdx.x - starts[job];
   const int P = J.P;
   const int lane = threadIdx.x;
   uint32_t* x = lds;        // residues, then digits
@@ -327,12 +495,12 @@ __global__ __launch_bounds__(64) void k_mrc(const JobDev* jobs, const int4* bmap
 // (e) limb assembly, pass 1: one thread per (coefficient, limb l) forms the
 // 96-bit column sum S_l = sum_k d_k limb_l(prod_{i<k} p_i), with d_k the digit
 // (non-negative lift) or p_k - 1 - digit (negative lift: then
-// M - v - 1 = sum (p_k - 1 - v_k) prod_{i<k} p_i).  Block map: x = job,
-// z = first flat index c * Lacc + l.
-__global__ void k_limbs_sum(const JobDev* jobs, const int4* bmap, TablesDev tab) {
-  const int4 bm = bmap[blockIdx.x];
-  const JobDev& J = jobs[bm.x];
-  const int idx = bm.z + threadIdx.x;
+// M - v - 1 = sum (p_k - 1 - v_k) prod_{i<k} p_i).  256 flat indices
+// c * Lacc + l per block.
+__global__ void k_limbs_sum(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
+  const int job = find_job(starts, nj, blockIdx.x);
+  const JobDev& J = jobs[job];
+  const int idx = (blockIdx.x - starts[job]) * 256 + threadIdx.x;
   if (idx >= J.D * J.Lacc) return;
   const int c = idx / J.Lacc;
   const int l = idx - c * J.Lacc;
@@ -354,10 +522,10 @@ __global__ void k_limbs_sum(const JobDev* jobs, const int4* bmap, TablesDev tab)
 // (e) limb assembly, pass 2: one thread per output coefficient propagates the
 // carries; a negative lift writes the bitwise complement (two's complement of
 // -(C + 1) is ~C).  Overflow of the caller's limb count sets err.
-__global__ void k_limbs_carry(const JobDev* jobs, const int4* bmap) {
-  const int4 bm = bmap[blockIdx.x];
-  const JobDev& J = jobs[bm.x];
-  const int c = bm.z + threadIdx.x;
+__global__ void k_limbs_carry(const JobDev* jobs, const int* starts, int nj) {
+  const int job = find_job(starts, nj, blockIdx.x);
+  const JobDev& J = jobs[job];
+  const int c = (blockIdx.x - starts[job]) * 64 + threadIdx.x;
   if (c > J.degcap) return;
   uint32_t* o = J.out + (size_t)c * J.Lcap;
   if (c >= J.D) {
@@ -401,38 +569,40 @@ void launch_transpose(const uint32_t* src, uint32_t* dst, int rows, int cols, in
   hipLaunchKernelGGL(k_transpose, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, rows, cols, L);
 }
 
-void launch_reduce(const JobDev* jobs, const int4* bmap, int nblocks, int max_primes, TablesDev tab,
+void launch_reduce(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, TablesDev tab,
                    hipStream_t s) {
   dim3 grid(nblocks, (max_primes + KT - 1) / KT);
-  hipLaunchKernelGGL(k_reduce, grid, dim3(64), 0, s, jobs, bmap, tab);
+  hipLaunchKernelGGL(k_reduce, grid, dim3(64), 0, s, jobs, starts, nj, tab);
 }
 
 int eval_elim_block() { return 64; }
 
-void launch_eval_elim(const JobDev* jobs, const int4* bmap, int nblocks, int max_words, TablesDev tab,
-                      hipStream_t s) {
-  size_t lds = (size_t)max_words * 64 * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_eval_elim<64>, dim3(nblocks), dim3(64), lds, s, jobs, bmap, tab);
+size_t eval_elim_lds_bytes(int words, int res) { return ((size_t)words * 65 + res) * sizeof(uint32_t); }
+
+void launch_eval_elim(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_words, int max_res,
+                      TablesDev tab, hipStream_t s) {
+  hipLaunchKernelGGL(k_eval_elim<64>, dim3(nblocks), dim3(64), eval_elim_lds_bytes(max_words, max_res), s, jobs,
+                     starts, nj, tab);
 }
 
-void launch_interp(const JobDev* jobs, const int4* bmap, int nblocks, int max_points, TablesDev tab,
+void launch_interp(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_points, TablesDev tab,
                    hipStream_t s) {
-  size_t lds = (size_t)3 * max_points * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_interp, dim3(nblocks), dim3(256), lds, s, jobs, bmap, tab);
+  size_t lds = interp_lds_words(max_points) * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_interp, dim3(nblocks), dim3(256), lds, s, jobs, starts, nj, tab);
 }
 
-void launch_mrc(const JobDev* jobs, const int4* bmap, int nblocks, int max_primes, TablesDev tab,
+void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, TablesDev tab,
                 hipStream_t s) {
   size_t lds = (size_t)2 * max_primes * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_mrc, dim3(nblocks), dim3(64), lds, s, jobs, bmap, tab);
+  hipLaunchKernelGGL(k_mrc, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, tab);
 }
 
-void launch_limbs_sum(const JobDev* jobs, const int4* bmap, int nblocks, TablesDev tab, hipStream_t s) {
-  hipLaunchKernelGGL(k_limbs_sum, dim3(nblocks), dim3(256), 0, s, jobs, bmap, tab);
+void launch_limbs_sum(const JobDev* jobs, const int* starts, int nj, int nblocks, TablesDev tab, hipStream_t s) {
+  hipLaunchKernelGGL(k_limbs_sum, dim3(nblocks), dim3(256), 0, s, jobs, starts, nj, tab);
 }
 
-void launch_limbs_carry(const JobDev* jobs, const int4* bmap, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_limbs_carry, dim3(nblocks), dim3(64), 0, s, jobs, bmap);
+void launch_limbs_carry(const JobDev* jobs, const int* starts, int nj, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_limbs_carry, dim3(nblocks), dim3(64), 0, s, jobs, starts, nj);
 }
 
 }  // namespace bires

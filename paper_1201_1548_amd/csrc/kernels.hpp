@@ -17,16 +17,23 @@ struct ScanTask {
 
 void launch_scan(const ScanTask* tasks, const int4* bmap, int nblocks, hipStream_t s);
 void launch_transpose(const uint32_t* src, uint32_t* dst, int rows, int cols, int L, hipStream_t s);
-void launch_reduce(const JobDev* jobs, const int4* bmap, int nblocks, int max_primes, TablesDev tab,
+// Job launchers: starts[0..nj] hold the first block of each job (starts[nj] = nblocks).
+// Blocks per job: reduce ceil(Tf/64)+ceil(Tg/64); eval_elim P*ceil(D/64);
+// interp P; mrc D; limbs_sum ceil(D*Lacc/256); limbs_carry ceil((degcap+1)/64).
+void launch_reduce(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, TablesDev tab,
                    hipStream_t s);
 int eval_elim_block();
-void launch_eval_elim(const JobDev* jobs, const int4* bmap, int nblocks, int max_words, TablesDev tab,
-                      hipStream_t s);
-void launch_interp(const JobDev* jobs, const int4* bmap, int nblocks, int max_points, TablesDev tab,
+// max_words: max over jobs of m+n+2; max_res: max over jobs of Tf+Tg.
+size_t eval_elim_lds_bytes(int words, int res);
+void launch_eval_elim(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_words, int max_res,
+                      TablesDev tab, hipStream_t s);
+void launch_interp(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_points, TablesDev tab,
                    hipStream_t s);
-void launch_mrc(const JobDev* jobs, const int4* bmap, int nblocks, int max_primes, TablesDev tab,
+size_t interp_lds_words(int D);
+void launch_invfact(const ModP* primes, int K, uint32_t* invfact, int dmax, hipStream_t s);
+void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, TablesDev tab,
                 hipStream_t s);
-void launch_limbs_sum(const JobDev* jobs, const int4* bmap, int nblocks, TablesDev tab, hipStream_t s);
-void launch_limbs_carry(const JobDev* jobs, const int4* bmap, int nblocks, hipStream_t s);
+void launch_limbs_sum(const JobDev* jobs, const int* starts, int nj, int nblocks, TablesDev tab, hipStream_t s);
+void launch_limbs_carry(const JobDev* jobs, const int* starts, int nj, int nblocks, hipStream_t s);
 
 }  // namespace bires

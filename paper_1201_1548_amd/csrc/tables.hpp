@@ -9,6 +9,7 @@
 namespace bires {
 
 constexpr int MAX_PRIMES = 2048;
+constexpr int MAX_POINTS = 8192;  // evaluation points (degree bound + 1) per job
 
 struct HostTables {
   int K = 0;
