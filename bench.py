@@ -104,6 +104,177 @@ def _point(pair, a):
     return resultant_at(F, G, a)
 
 
+def _percentile(v, q):
+    v = sorted(v)
+    if not v:
+        return None
+    i = min(len(v) - 1, max(0, int(round(q / 100.0 * (len(v) - 1)))))
+    return v[i]
+
+
+def bench_config4(args):
+    """Config 4: 400 curves (total degree U{4..30}, bits U{8..64}), all pairs in
+    seeded groups of 20 (3800 resultants); one batched call vs one call per pair."""
+    import torch
+    import paper_1201_1548_amd as br
+    from paper_1201_1548_amd import synth
+    from oracle.resultant import resultant_y
+
+    curves, pairs = synth.config4_arrangement(0)
+    jobs = [("res", curves[i], curves[j], "y") for i, j in pairs]
+    torch.cuda.set_device(0)
+    batch = br.DeviceBatch(jobs)
+    batch.run()
+    torch.cuda.synchronize()
+    res = batch.results()
+    for _ in range(args.warmup):
+        batch.run()
+    torch.cuda.synchronize()
+    br.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kms, launches = br.kernel_time()
+    br.set_timing(False)
+    batch.run_each()
+    torch.cuda.synchronize()
+    exact_plain = batch.results() == res
+    t0 = time.perf_counter()
+    batch.run_each()
+    torch.cuda.synchronize()
+    dtp = time.perf_counter() - t0
+    # oracle on the pairs small enough for Bareiss over Z[x] in seconds
+    small = [k for k, (i, j) in enumerate(pairs) if len(curves[i]) + len(curves[j]) <= 14][:12]
+    exact_oracle = all(res[k] == resultant_y(curves[pairs[k][0]], curves[pairs[k][1]]) for k in small)
+    n = len(jobs)
+    return {
+        "metric": "arrangement pair resultants/sec (config 4), batched vs plain",
+        "value": round(n * args.steps / dt, 2), "unit": "resultants/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "config 4: 400 dense curves, total degree U{4..30}, coefficient bits U{8..64}, "
+                               "all pairs within 20 seeded groups of 20 (3800 res_y)", "pairs": n},
+        "plain": {"value": round(n / dtp, 2), "unit": "resultants/s", "ms_per_pair": round(dtp / n * 1e3, 3)},
+        "batched_over_plain": round((n * args.steps / dt) / (n / dtp), 2),
+        "eval_elim_ms_per_step": round(kms / max(launches, 1), 3),
+        "bit_exact": {"batched_vs_plain": exact_plain, "oracle_sample": exact_oracle, "oracle_pairs": len(small)},
+    }
+
+
+def bench_config5(args):
+    """Config 5: Poisson stream of resultant/discriminant requests (total degree
+    log-uniform in [5, 64], bits U{10..128}); the continuous-batching server vs
+    a plain server that runs one library call per request in arrival order."""
+    import threading
+    import paper_1201_1548_amd as br
+    from paper_1201_1548_amd import synth
+
+    nreq = args.requests
+    probe = synth.config5_requests(0, n=min(40, nreq), qps=1.0)
+
+    def plain_call(r):
+        return br.discriminant(r["f"]) if r["kind"] == "disc" else br.resultant(r["f"], r["g"])
+
+    plain_call(probe[0])
+    t0 = time.perf_counter()
+    for r in probe:
+        plain_call(r)
+    service = (time.perf_counter() - t0) / len(probe)
+    qps = args.qps or 0.7 / service
+    reqs = synth.config5_requests(0, n=nreq, qps=qps)
+
+    def run_plain():
+        out, lat = [None] * nreq, [0.0] * nreq
+        start = time.perf_counter()
+        for i, r in enumerate(reqs):
+            now = time.perf_counter() - start
+            if now < r["t"]:
+                time.sleep(r["t"] - now)
+            out[i] = plain_call(r)
+            lat[i] = time.perf_counter() - start - r["t"]
+        return out, lat, time.perf_counter() - start
+
+    def run_server():
+        out, lat = [None] * nreq, [0.0] * nreq
+        with br.Server(hbm_budget_bytes=args.budget_gib << 30, max_slots=args.slots) as srv:
+            tickets = [None] * nreq
+            ready = threading.Semaphore(0)
+            start = time.perf_counter()
+
+            def submitter():
+                for i, r in enumerate(reqs):
+                    now = time.perf_counter() - start
+                    if now < r["t"]:
+                        time.sleep(r["t"] - now)
+                    tickets[i] = srv.submit(r["kind"], r["f"], r["g"])
+                    ready.release()
+
+            th = threading.Thread(target=submitter)
+            th.start()
+            for i in range(nreq):
+                ready.acquire()
+                out[i], lat[i] = srv.wait(tickets[i])
+            th.join()
+            total = time.perf_counter() - start
+        return out, lat, total
+
+    out_s, lat_s, tot_s = run_server()
+    out_p, lat_p, tot_p = run_plain()
+    return {
+        "metric": "serving: resultant/discriminant requests/sec with p50/p99 latency (config 5)",
+        "value": round(nreq / tot_s, 2), "unit": "requests/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(tot_s * 1e3, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "config 5: Poisson arrivals, total degree round(exp(U[ln5, ln64])), "
+                               "coefficient bits U{10..128}, resultant or discriminant 50/50",
+                   "requests": nreq, "qps": round(qps, 2), "hbm_budget_gib": args.budget_gib,
+                   "slots": args.slots},
+        "p50_ms": round(_percentile(lat_s, 50) * 1e3, 2), "p99_ms": round(_percentile(lat_s, 99) * 1e3, 2),
+        "plain": {"value": round(nreq / tot_p, 2), "unit": "requests/s",
+                  "p50_ms": round(_percentile(lat_p, 50) * 1e3, 2),
+                  "p99_ms": round(_percentile(lat_p, 99) * 1e3, 2),
+                  "mean_service_ms": round(service * 1e3, 2)},
+        "bit_exact": {"server_vs_plain": out_s == out_p},
+    }
+
+
+def bench_config3(args):
+    """Config 3: res(f, f_y; y) of a dense total-degree-40 curve (16-bit
+    coefficients) and gcd(R, R'); per-call wall time."""
+    import torch
+    import paper_1201_1548_amd as br
+    from oracle import zx
+    from paper_1201_1548_amd import synth
+
+    torch.cuda.set_device(0)
+    out = {}
+    for name, F in (("dense", synth.config3_dense(0)),
+                    ("g2_hk", synth.config3_singular(0)),
+                    ("g2_hk2", synth.config3_singular(0, square_k=True, dk=10))):
+        br.discriminant(F)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            R = br.discriminant(F)
+        td = (time.perf_counter() - t0) / args.steps
+        dR = zx.derivative(R)
+        t0 = time.perf_counter()
+        h = br.gcd(R, dR)
+        tg = time.perf_counter() - t0
+        out[name] = {"disc_ms": round(td * 1e3, 2), "deg_R": len(R) - 1, "gcd_ms": round(tg * 1e3, 1),
+                     "deg_gcd": len(h) - 1}
+    return {
+        "metric": "curve-analysis resultant res(f, f_y; y) and gcd(R, R') wall time (config 3)",
+        "value": round(1e3 / out["dense"]["disc_ms"], 2), "unit": "discriminants/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": out["dense"]["disc_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "config 3: dense total degree 40, 16-bit coefficients; g^2 + h k with dense "
+                               "degree-20 factors, 8-bit; g^2 + h k^2 (k degree 10)"},
+        "cases": out,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,11 +283,20 @@ def main():
     ap.add_argument("--pairs", type=int, default=256)
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5"])
+    ap.add_argument("--requests", type=int, default=300)
+    ap.add_argument("--qps", type=float, default=0.0)
+    ap.add_argument("--budget-gib", type=int, default=32)
+    ap.add_argument("--slots", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each job runs on one "
               "device; see the sharding notes in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "config2":
+        fn = {"config3": bench_config3, "config4": bench_config4, "config5": bench_config5}[args.workload]
+        print(json.dumps(fn(args)), flush=True)
+        return
 
     import paper_1201_1548_amd as br
     from paper_1201_1548_amd import synth

@@ -446,3 +446,44 @@ def device_info():
     _check(lib().bires_device_info(ctypes.byref(cu), ctypes.byref(clk), ctypes.byref(lds), ctypes.byref(hbm)),
            "bires_device_info")
     return {"cus": cu.value, "clock_khz": clk.value, "lds_per_block": lds.value, "hbm_bytes": hbm.value}
+
+
+class Server:
+    """Continuous-batching server (bires_server_*): submit() returns a ticket
+    at once; wait() returns (result, latency in seconds)."""
+
+    def __init__(self, hbm_budget_bytes=8 << 30, max_slots=512):
+        h = ctypes.c_void_p()
+        _check(lib().bires_server_create(hbm_budget_bytes, max_slots, ctypes.byref(h)), "bires_server_create")
+        self.h = h
+
+    def submit(self, kind, F, G=None, var="y"):
+        k = KIND_DISCRIMINANT if kind == "disc" else KIND_RESULTANT
+        fa = bipoly_array(F)
+        ga = bipoly_array(G) if k == KIND_RESULTANT else fa
+        t = ctypes.c_uint64()
+        _check(lib().bires_server_submit(self.h, k, _var(var), ctypes.byref(_desc(fa)), ctypes.byref(_desc(ga)),
+                                         ctypes.byref(t)), "bires_server_submit")
+        self._caps = getattr(self, "_caps", {})
+        self._caps[t.value] = _bounds(k, _desc(fa), _desc(ga), _var(var))
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0):
+        deg, L = self._caps.pop(ticket)
+        out = np.zeros((deg + 1, L), dtype=np.uint32)
+        od = Upoly(deg, L, out.ctypes.data)
+        lat = ctypes.c_double()
+        _check(lib().bires_server_wait(self.h, ticket, ctypes.byref(od), timeout, ctypes.byref(lat)),
+               "bires_server_wait")
+        return limbs_to_ints(out[: od.degree + 1]), lat.value
+
+    def close(self):
+        if self.h:
+            _check(lib().bires_server_destroy(self.h), "bires_server_destroy")
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -240,10 +240,14 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   Layout ws;
   Layout hout;  // host staging of outputs (host memory space only)
   // per-kernel first block of each job (prefix sums of the per-job block counts)
-  enum { K_RED, K_EE, K_IP, K_MRC, K_SUM, K_CAR, NK };
+  // eval_elim runs one launch per size bucket (LDS per block sized for the
+  // bucket, so small jobs are not held to the occupancy of the largest)
+  enum { K_RED, K_IP, K_MRC, K_SUM, K_CAR, K_EE0, NBUCKET = 5, NK = K_EE0 + NBUCKET };
+  const int bucket_words[NBUCKET] = {24, 40, 64, 96, 1 << 30};
+  int bw[NBUCKET] = {0}, br_[NBUCKET] = {0};
   std::vector<int> starts[NK];
   for (auto& v : starts) v.assign(nj + 1, 0);
-  int maxP = 1, maxWords = 2, maxD = 1, maxRes = 1;
+  int maxP = 1, maxD = 1;
   for (int i = 0; i < nj; ++i) {
     Work& x = w[i];
     if (x.status || !x.active) continue;
@@ -264,15 +268,22 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     }
     maxP = std::max(maxP, p.P);
     maxD = std::max(maxD, p.D);
-    maxWords = std::max(maxWords, p.m + p.n + 2);
-    maxRes = std::max(maxRes, x.Tf + x.Tg);
     starts[K_RED][i + 1] = (x.Tf + 63) / 64 + (x.Tg + 63) / 64;
-    starts[K_EE][i + 1] = p.P * ((p.D + 63) / 64);
+    int bk = 0;
+    while (p.m + p.n + 2 > bucket_words[bk]) ++bk;
+    starts[K_EE0 + bk][i + 1] = p.P * ((p.D + 63) / 64);
+    bw[bk] = std::max(bw[bk], p.m + p.n + 2);
+    br_[bk] = std::max(br_[bk], x.Tf + x.Tg);
     starts[K_IP][i + 1] = p.P;
-    starts[K_MRC][i + 1] = p.D;
+    starts[K_MRC][i + 1] = p.D;  // adjusted below once the largest prime count is known
     starts[K_SUM][i + 1] = (p.D * x.Lacc + 255) / 256;
     starts[K_CAR][i + 1] = debug ? 0 : (x.degcap + 1 + 63) / 64;
   }
+  if (mrc_lane_ok(maxP))
+    for (int i = 0; i < nj; ++i) starts[K_MRC][i + 1] = (starts[K_MRC][i + 1] + 63) / 64;
+  int maxLcap = 1;
+  for (int i = 0; i < nj; ++i)
+    if (!w[i].status && w[i].active) maxLcap = std::max(maxLcap, w[i].Lout);
   for (auto& v : starts)
     for (int i = 0; i < nj; ++i) v[i + 1] += v[i];
   const size_t meta_begin = ws.take(0);
@@ -343,7 +354,9 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   const JobDev* d_jobs = (const JobDev*)(D0 + o_jobs);
 
   // ---------------- kernels
-  const bool timing = cx->timing && nb_of(K_EE) > 0;
+  int nb_ee = 0;
+  for (int bk = 0; bk < NBUCKET; ++bk) nb_ee += nb_of(K_EE0 + bk);
+  const bool timing = cx->timing && nb_ee > 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (timing) {
     DEV(hipEventCreate(&ev0));
@@ -351,13 +364,15 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   }
   if (nb_of(K_RED)) launch_reduce(d_jobs, st_of(K_RED), nj, nb_of(K_RED), maxP, cx->tab, st);
   if (timing) DEV(hipEventRecord(ev0, st));
-  if (nb_of(K_EE)) launch_eval_elim(d_jobs, st_of(K_EE), nj, nb_of(K_EE), maxWords, maxRes, cx->tab, st);
+  for (int bk = 0; bk < NBUCKET; ++bk)
+    if (nb_of(K_EE0 + bk))
+      launch_eval_elim(d_jobs, st_of(K_EE0 + bk), nj, nb_of(K_EE0 + bk), bw[bk], br_[bk], cx->tab, st);
   if (timing) DEV(hipEventRecord(ev1, st));
   if (!debug) {
     if (nb_of(K_IP)) launch_interp(d_jobs, st_of(K_IP), nj, nb_of(K_IP), maxD, cx->tab, st);
     if (nb_of(K_MRC)) launch_mrc(d_jobs, st_of(K_MRC), nj, nb_of(K_MRC), maxP, cx->tab, st);
     if (nb_of(K_SUM)) launch_limbs_sum(d_jobs, st_of(K_SUM), nj, nb_of(K_SUM), cx->tab, st);
-    if (nb_of(K_CAR)) launch_limbs_carry(d_jobs, st_of(K_CAR), nj, nb_of(K_CAR), st);
+    if (nb_of(K_CAR)) launch_limbs_carry(d_jobs, st_of(K_CAR), nj, nb_of(K_CAR), maxLcap, st);
   }
   DEV(hipGetLastError());
 
@@ -471,6 +486,28 @@ int bounds_job(const JobIn& jb, int32_t* max_degree, int32_t* max_limbs) {
   if ((e = make_plan(stf, stg, pl))) return e;
   if (max_degree) *max_degree = pl.D - 1;
   if (max_limbs) *max_limbs = pl.kind_special ? 1 : limbs_for_log2(pl.log2B);
+  return BIRES_OK;
+}
+
+}  // namespace bires
+
+namespace bires {
+
+int job_footprint(const JobIn& jb, int32_t* cap_degree, int32_t* cap_limbs, size_t* bytes) {
+  int e = bounds_job(jb, cap_degree, cap_limbs);
+  if (e) return e;
+  Plan pl;
+  if ((e = plan_host_job(jb, pl))) return e;
+  const Shape sf = shape_of(jb.f, jb.var);
+  const Shape sg = jb.kind == BIRES_KIND_RESULTANT ? shape_of(jb.g, jb.var) : sf;
+  size_t b = (size_t)sf.rows * sf.ld * sf.L * 4 + (size_t)sg.rows * sg.ld * sg.L * 4;
+  if (pl.kind_special == 0) {
+    const size_t P = pl.P, D = pl.D, Lacc = std::min(*cap_limbs, pl.P + 1);
+    b += P * ((size_t)(pl.m + 1) * sf.ld + (size_t)(pl.n + 1) * sg.ld) * 4;  // residues
+    b += 3 * P * D * 4 + D * 4 + D * Lacc * 12;                              // values, coefs, digits, limbs
+  }
+  b += (size_t)(*cap_degree + 1) * (*cap_limbs) * 4;
+  *bytes = b;
   return BIRES_OK;
 }
 

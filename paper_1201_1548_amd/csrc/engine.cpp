@@ -100,11 +100,13 @@ static int init_context(Context& cx) {
   HIP_OK(hipStreamCreateWithFlags(&cx.stream, hipStreamNonBlocking));
   const HostTables& t = host_tables();
   ModP* primes = nullptr;
-  uint32_t *gm = nullptr, *cm = nullptr, *pi = nullptr;
+  uint32_t *gm = nullptr, *cm = nullptr, *pi = nullptr, *pm = nullptr;
   HIP_OK(hipMalloc(&primes, t.primes.size() * sizeof(ModP)));
   HIP_OK(hipMalloc(&gm, t.gm.size() * sizeof(uint32_t)));
   HIP_OK(hipMalloc(&cm, t.cm.size() * sizeof(uint32_t)));
   HIP_OK(hipMalloc(&pi, t.pi.size() * sizeof(uint32_t)));
+  HIP_OK(hipMalloc(&pm, t.pm.size() * sizeof(uint32_t)));
+  HIP_OK(hipMemcpy(pm, t.pm.data(), t.pm.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
   HIP_OK(hipMemcpy(primes, t.primes.data(), t.primes.size() * sizeof(ModP), hipMemcpyHostToDevice));
   HIP_OK(hipMemcpy(gm, t.gm.data(), t.gm.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
   HIP_OK(hipMemcpy(cm, t.cm.data(), t.cm.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
@@ -113,6 +115,7 @@ static int init_context(Context& cx) {
   cx.tab.gm = gm;
   cx.tab.cm = cm;
   cx.tab.pi = pi;
+  cx.tab.pm = pm;
   cx.tab.K = t.K;
   uint32_t* invfact = nullptr;
   HIP_OK(hipMalloc(&invfact, (size_t)t.K * MAX_POINTS * sizeof(uint32_t)));

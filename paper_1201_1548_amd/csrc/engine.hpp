@@ -66,6 +66,8 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
 // Plan of one host-memory job, and output sizes from the extents only (host-only).
 int bounds_job(const JobIn& job, int32_t* max_degree, int32_t* max_limbs);
 int plan_host_job(const JobIn& job, Plan& pl);
+// Output capacity (from the extents) and the device bytes one job holds while it runs.
+int job_footprint(const JobIn& job, int32_t* cap_degree, int32_t* cap_limbs, size_t* bytes);
 
 // Validates the descriptor of a bivariate input.
 int check_bipoly(const bires_bipoly* p, int allow_null_c);

@@ -24,10 +24,10 @@ struct JobDev {
   uint32_t* res_g;          // [P][Tg]
   uint32_t* vals;           // [P][D] values R(a) mod p_k, a = 0..D-1
   uint32_t* coefs;          // [P][D] coefficients of R mod p_k
-  uint32_t* digits;         // [D][P] mixed-radix digits
+  uint32_t* digits;         // [P][D] mixed-radix digits
   int32_t* negflag;         // [D] 1 when the symmetric lift is negative
-  uint64_t* acc_lo;         // [D][Lacc] partial sums for limb assembly
-  uint32_t* acc_hi;         // [D][Lacc]
+  uint64_t* acc_lo;         // [Lacc][D] partial sums for limb assembly
+  uint32_t* acc_hi;         // [Lacc][D]
   int32_t Lacc;             // min(Lcap, P + 1)
   uint32_t* out;            // [(degcap+1)][Lcap] result limbs
   int32_t Lcap, degcap;
@@ -35,11 +35,24 @@ struct JobDev {
   int32_t* err;             // set non-zero on a failed internal check
 };
 
+// One modular gcd over P primes (see k_gcd_p).
+struct GcdDev {
+  const uint32_t* res_a;  // [P][da+1] Montgomery residues of a
+  const uint32_t* res_b;  // [P][db+1]
+  int32_t da, db, P;
+  const uint32_t* sc;     // [P][3] plain: beta, lc(a)/beta, lc(b)/beta mod p_k
+  uint32_t* F;            // [P][dmin+1] beta * monic gcd mod p_k (plain), zero-padded
+  uint32_t* QA;           // [P][da+1] (lc(a)/beta) * a / g mod p_k, zero-padded
+  uint32_t* QB;           // [P][db+1] (lc(b)/beta) * b / g mod p_k
+  int32_t* gdeg;          // [P] degree of the gcd mod p_k; -2: p_k divides lc(a) lc(b); -3: failed check
+};
+
 // Tables shared by every job: the prime list and the mixed-radix constants.
 struct TablesDev {
   const ModP* primes;       // [K]
   const uint32_t* gm;       // [K][K]: gm[j*K+k] = (prod_{i<j} p_i) R mod p_k, j < k
   const uint32_t* cm;       // [K]: (prod_{i<k} p_i)^{-1} R mod p_k
+  const uint32_t* pm;       // [K][K]: pm[k*K+j] = (p_j mod p_k) R mod p_k, j < k
   const uint32_t* pi;       // prod_{i<k} p_i as k+1 limbs at offset k(k+1)/2
   const uint32_t* invfact;  // [K][dmax]: Montgomery form of 1/n! mod p_k
   int32_t K;

@@ -439,27 +439,63 @@ void launch_invfact(const ModP* primes, int K, uint32_t* invfact, int dmax, hipS
 
 // ---------------------------------------------------------------------------
 // (e) mixed-radix conversion (Garner).  With primes p_0 > p_1 > ... the value
-// is sum_j v_j prod_{i<j} p_i, v_j in [0, p_j).  Lane k keeps
-// acc_k = sum_{j<k} v_j prod_{i<j} p_i mod p_k; when j reaches k,
-// v_k = (x_k - acc_k) (prod_{i<k} p_i)^{-1} mod p_k.  One wave per coefficient;
-// lanes cover primes k = lane + 64 t.  The symmetric lift is negative exactly
-// when the digit vector exceeds ((p_k - 1)/2)_k lexicographically from the top,
-// because sum_k (p_k - 1)/2 prod_{i<k} p_i = (M - 1)/2.
+// is sum_j v_j prod_{i<j} p_i, v_j in [0, p_j), and
+// v_k = (x_k - sum_{j<k} v_j prod_{i<j} p_i) (prod_{i<k} p_i)^{-1} mod p_k.
+// The symmetric lift is negative exactly when the digit vector exceeds
+// ((p_k - 1)/2)_k lexicographically from the top, because
+// sum_k (p_k - 1)/2 prod_{i<k} p_i = (M - 1)/2.  Digits are stored [P][D].
 
+__device__ __forceinline__ int lift_negative(const uint32_t* v, int stride, int P, const ModP* primes) {
+  for (int kk = P - 1; kk >= 0; --kk) {
+    const uint32_t h = (primes[kk].p - 1u) >> 1;
+    const uint32_t x = v[kk * stride];
+    if (x != h) return x > h ? 1 : 0;
+  }
+  return 0;
+}
+
+// One lane per coefficient (P <= MRC_LANE_MAXP): the prefix value mod p_k is
+// evaluated by Horner's rule over the earlier digits, t <- t p_j + v_j for
+// j = k-1 .. 0, with the constants p_j mod p_k (uniform, scalar loads).
+constexpr int MRC_LANE_MAXP = 128;
+
+__global__ __launch_bounds__(64) void k_mrc_lane(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
+  extern __shared__ uint32_t lds[];
+  const int job = find_job(starts, nj, blockIdx.x);
+  const JobDev& J = jobs[job];
+  const int c = (blockIdx.x - starts[job]) * 64 + threadIdx.x;
+  const int P = J.P, D = J.D;
+  if (c >= D) return;
+  uint32_t* v = lds + threadIdx.x;  // v[k * 64]
+  for (int k = 0; k < P; ++k) {
+    const ModP qk = tab.primes[k];
+    const uint32_t* pmk = tab.pm + (size_t)k * tab.K;
+    uint32_t t = k ? reduce32(v[(k - 1) * 64], qk.p) : 0u;
+#pragma unroll 4
+    for (int j = k - 2; j >= 0; --j) t = madd(mmul(t, pmk[j], qk), reduce32(v[j * 64], qk.p), qk.p);
+    const uint32_t vk = mmul(msub(J.coefs[(size_t)k * D + c], t, qk.p), tab.cm[k], qk);
+    v[k * 64] = vk;
+    J.digits[(size_t)k * D + c] = vk;
+  }
+  J.negflag[c] = lift_negative(v, 64, P, tab.primes);
+}
+
+// One wave per coefficient, lanes over primes k = lane + 64 t: lane k keeps
+// acc_k = sum_{j<k} v_j prod_{i<j} p_i mod p_k; at step j the owner lane of j
+// finishes v_j and broadcasts it.
 __global__ __launch_bounds__(64) void k_mrc(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
   extern __shared__ uint32_t lds[];
   const int job = find_job(starts, nj, blockIdx.x);
   const JobDev& J = jobs[job];
   const int c = blockIdx.x - starts[job];
-  const int P = J.P;
+  const int P = J.P, D = J.D;
   const int lane = threadIdx.x;
   uint32_t* x = lds;        // residues, then digits
   uint32_t* acc = lds + P;  // running prefix values
   for (int kk = lane; kk < P; kk += 64) {
-    x[kk] = J.coefs[(size_t)kk * J.D + c];
+    x[kk] = J.coefs[(size_t)kk * D + c];
     acc[kk] = 0u;
   }
-  uint32_t* dig = J.digits + (size_t)c * P;
   for (int j = 0; j < P; ++j) {
     const int owner = j & 63;
     uint32_t v = 0;
@@ -467,7 +503,7 @@ __global__ __launch_bounds__(64) void k_mrc(const JobDev* jobs, const int* start
       const ModP qj = tab.primes[j];
       v = mmul(msub(x[j], acc[j], qj.p), tab.cm[j], qj);
       x[j] = v;
-      dig[j] = v;
+      J.digits[(size_t)j * D + c] = v;
     }
     v = __builtin_amdgcn_readlane(v, owner);
     const uint32_t* g = tab.gm + (size_t)j * tab.K;
@@ -479,37 +515,27 @@ __global__ __launch_bounds__(64) void k_mrc(const JobDev* jobs, const int* start
     }
   }
   __syncthreads();
-  if (lane == 0) {
-    int neg = 0;
-    for (int kk = P - 1; kk >= 0; --kk) {
-      const uint32_t h = (tab.primes[kk].p - 1u) >> 1;
-      if (x[kk] != h) {
-        neg = x[kk] > h ? 1 : 0;
-        break;
-      }
-    }
-    J.negflag[c] = neg;
-  }
+  if (lane == 0) J.negflag[c] = lift_negative(x, 1, P, tab.primes);
 }
 
-// (e) limb assembly, pass 1: one thread per (coefficient, limb l) forms the
+// (e) limb assembly, pass 1: one thread per (limb l, coefficient c) forms the
 // 96-bit column sum S_l = sum_k d_k limb_l(prod_{i<k} p_i), with d_k the digit
 // (non-negative lift) or p_k - 1 - digit (negative lift: then
-// M - v - 1 = sum (p_k - 1 - v_k) prod_{i<k} p_i).  256 flat indices
-// c * Lacc + l per block.
+// M - v - 1 = sum (p_k - 1 - v_k) prod_{i<k} p_i).  Flat index l * D + c,
+// 256 per block; sums stored [Lacc][D].
 __global__ void k_limbs_sum(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
   const int job = find_job(starts, nj, blockIdx.x);
   const JobDev& J = jobs[job];
   const int idx = (blockIdx.x - starts[job]) * 256 + threadIdx.x;
-  if (idx >= J.D * J.Lacc) return;
-  const int c = idx / J.Lacc;
-  const int l = idx - c * J.Lacc;
+  const int D = J.D;
+  if (idx >= D * J.Lacc) return;
+  const int l = idx / D;
+  const int c = idx - l * D;
   const int neg = J.negflag[c];
-  const uint32_t* dig = J.digits + (size_t)c * J.P;
   uint64_t lo = 0;
   uint32_t hi = 0;
   for (int k = l; k < J.P; ++k) {
-    uint32_t d = dig[k];
+    uint32_t d = J.digits[(size_t)k * D + c];
     if (neg) d = tab.primes[k].p - 1u - d;
     const uint64_t prod = (uint64_t)d * tab.pi[(size_t)k * (k + 1) / 2 + l];
     lo += prod;
@@ -519,41 +545,178 @@ __global__ void k_limbs_sum(const JobDev* jobs, const int* starts, int nj, Table
   J.acc_hi[idx] = hi;
 }
 
-// (e) limb assembly, pass 2: one thread per output coefficient propagates the
+// (e) limb assembly, pass 2: one lane per output coefficient propagates the
 // carries; a negative lift writes the bitwise complement (two's complement of
-// -(C + 1) is ~C).  Overflow of the caller's limb count sets err.
-__global__ void k_limbs_carry(const JobDev* jobs, const int* starts, int nj) {
+// -(C + 1) is ~C).  The 64 coefficients of a block are staged in LDS and
+// written out contiguously when they fit.  Overflow of the caller's limb count
+// sets err.
+constexpr int CARRY_STAGE_MAXL = 128;
+
+// stage_ld > 0: LDS rows of stage_ld words (>= Lcap + 1 of every job); 0: direct writes.
+__global__ __launch_bounds__(64) void k_limbs_carry(const JobDev* jobs, const int* starts, int nj, int stage_ld) {
+  extern __shared__ uint32_t lds[];
   const int job = find_job(starts, nj, blockIdx.x);
   const JobDev& J = jobs[job];
-  const int c = (blockIdx.x - starts[job]) * 64 + threadIdx.x;
-  if (c > J.degcap) return;
-  uint32_t* o = J.out + (size_t)c * J.Lcap;
-  if (c >= J.D) {
-    for (int l = 0; l < J.Lcap; ++l) o[l] = 0u;
+  const int c0 = (blockIdx.x - starts[job]) * 64;
+  const int c = c0 + threadIdx.x;
+  const int Lc = J.Lcap, D = J.D;
+  const bool staged = stage_ld > 0;
+  const int ld = stage_ld;
+  if (c <= J.degcap) {
+    uint32_t* o = staged ? lds + threadIdx.x * ld : J.out + (size_t)c * Lc;
+    if (c >= D) {
+      for (int l = 0; l < Lc; ++l) o[l] = 0u;
+    } else {
+      const int neg = J.negflag[c];
+      const uint32_t flip = neg ? 0xFFFFFFFFu : 0u;
+      uint64_t carry = 0;  // < 2^50
+      bool nz = neg != 0;
+      uint32_t last = 0;
+      for (int l = 0; l < Lc; ++l) {
+        uint64_t lo = 0;
+        uint32_t hi = 0;
+        if (l < J.Lacc) {
+          lo = J.acc_lo[(size_t)l * D + c];
+          hi = J.acc_hi[(size_t)l * D + c];
+        }
+        const uint64_t s = lo + carry;
+        const uint32_t ovf = s < lo ? 1u : 0u;
+        const uint32_t w = (uint32_t)s;
+        carry = (s >> 32) + ((uint64_t)(hi + ovf) << 32);
+        nz |= w != 0u;
+        last = w ^ flip;
+        o[l] = last;
+      }
+      if (carry != 0u || ((last >> 31) != (flip >> 31))) atomicOr(J.err, 1);
+      if (nz) atomicMax(J.deg_out, c);
+    }
+  }
+  if (staged) {
+    __syncthreads();
+    const int nc = min(64, J.degcap + 1 - c0);
+    uint32_t* dst = J.out + (size_t)c0 * Lc;
+    for (int i = threadIdx.x; i < nc * Lc; i += 64) {
+      const int r = i / Lc;
+      dst[i] = lds[r * ld + (i - r * Lc)];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// (a8) modular gcd per prime (Section 5.1, "Computing gcds in Z[x]", step (b)).
+// One block per prime: Euclid's algorithm over F_p on a, b without inverses
+// (each elimination A <- lc(B) A - lc(A) y^s B changes A only by a unit
+// factor, so the last non-zero remainder is the gcd up to a unit); the result
+// is made monic with one inverse.  Then waves 0 and 1 divide a and b exactly
+// by the monic gcd (synthetic division, sequential over the quotient).
+// Outputs are scaled for the integer reconstruction: beta g, (lc a / beta) a/g,
+// (lc b / beta) b/g, whose images multiply to lc(a) a and lc(b) b.
+
+__global__ __launch_bounds__(256) void k_gcd_p(GcdDev G, TablesDev tab) {
+  extern __shared__ uint32_t lds[];
+  const int k = blockIdx.x;
+  const ModP q = tab.primes[k];
+  const int da = G.da, db = G.db;
+  const int mx = da > db ? da : db;
+  const int mn = da < db ? da : db;
+  uint32_t* A0 = lds;
+  uint32_t* B0 = A0 + da + 1;
+  uint32_t* X = B0 + db + 1;
+  uint32_t* Y = X + mx + 1;
+  uint32_t* Gm = Y + mx + 1;
+  const int tid = threadIdx.x;
+  const uint32_t* ra = G.res_a + (size_t)k * (da + 1);
+  const uint32_t* rb = G.res_b + (size_t)k * (db + 1);
+  for (int i = tid; i <= da; i += blockDim.x) A0[i] = X[i] = ra[i];
+  for (int i = tid; i <= db; i += blockDim.x) B0[i] = Y[i] = rb[i];
+  __syncthreads();
+  if (A0[da] == 0u || B0[db] == 0u) {
+    if (tid == 0) G.gdeg[k] = -2;
     return;
   }
-  const int neg = J.negflag[c];
-  const uint32_t flip = neg ? 0xFFFFFFFFu : 0u;
-  uint64_t carry = 0;  // < 2^50
-  bool nz = neg != 0;
-  uint32_t last = 0;
-  for (int l = 0; l < J.Lcap; ++l) {
-    uint64_t lo = 0;
-    uint32_t hi = 0;
-    if (l < J.Lacc) {
-      lo = J.acc_lo[(size_t)c * J.Lacc + l];
-      hi = J.acc_hi[(size_t)c * J.Lacc + l];
-    }
-    const uint64_t s = lo + carry;
-    const uint32_t ovf = s < lo ? 1u : 0u;
-    const uint32_t w = (uint32_t)s;
-    carry = (s >> 32) + ((uint64_t)(hi + ovf) << 32);
-    nz |= w != 0u;
-    last = w ^ flip;
-    o[l] = last;
+  int a = da, b = db;
+  if (a < b) {
+    uint32_t* T = X; X = Y; Y = T;
+    int t = a; a = b; b = t;
   }
-  if (carry != 0u || ((last >> 31) != (flip >> 31))) atomicOr(J.err, 1);
-  if (nz) atomicMax(J.deg_out, c);
+  int d = 0;
+  for (;;) {
+    if (b == 0) {  // a non-zero constant divides both
+      d = 0;
+      break;
+    }
+    const uint32_t lb = Y[b];
+    for (int aa = a; aa >= b; --aa) {
+      const uint32_t nla = mneg(X[aa], q.p);
+      const int s = aa - b;
+      __syncthreads();  // every thread has read X[aa] before it can be overwritten below
+      for (int t = tid; t < aa; t += blockDim.x)
+        X[t] = t < s ? mmul(lb, X[t], q) : mdot2(lb, X[t], nla, Y[t - s], q);
+      __syncthreads();
+    }
+    int c = b - 1;
+    while (c >= 0 && X[c] == 0u) --c;
+    if (c < 0) {
+      d = b;
+      break;
+    }
+    uint32_t* T = X; X = Y; Y = T;
+    a = b;
+    b = c;
+  }
+  // monic gcd (Montgomery) in Gm; b == 0 means gcd 1
+  const uint32_t inv = d ? minv(Y[d], q) : q.one;
+  for (int i = tid; i <= d; i += blockDim.x) Gm[i] = d ? mmul(Y[i], inv, q) : q.one;
+  __syncthreads();
+  const uint32_t beta = G.sc[3 * k], sa = G.sc[3 * k + 1], sb = G.sc[3 * k + 2];
+  uint32_t* F = G.F + (size_t)k * (mn + 1);
+  for (int i = tid; i <= mn; i += blockDim.x) F[i] = i <= d ? mmul(Gm[i], beta, q) : 0u;
+  // cofactors: wave 0 divides a, wave 1 divides b (in X and Y as work arrays)
+  const int wave = tid >> 6, lane = tid & 63;
+  __shared__ int bad_any;
+  if (tid == 0) bad_any = 0;
+  __syncthreads();
+  if (wave < 2) {
+    const int dn = wave ? db : da;
+    const uint32_t* src = wave ? B0 : A0;
+    uint32_t* W = wave ? Y : X;
+    uint32_t* out = wave ? G.QB + (size_t)k * (db + 1) : G.QA + (size_t)k * (da + 1);
+    const uint32_t scl = wave ? sb : sa;
+    for (int i = lane; i <= dn; i += 64) W[i] = src[i];
+    bool bad = false;
+    for (int kq = dn - d; kq >= 0; --kq) {
+      const uint32_t qc = W[kq + d];
+      for (int i = lane; i < d; i += 64) W[kq + i] = msub(W[kq + i], mmul(qc, Gm[i], q), q.p);
+      if (lane == 0) out[kq] = mmul(qc, scl, q);
+    }
+    for (int i = lane; i < d; i += 64) bad |= W[i] != 0u;
+    for (int i = dn - d + 1 + lane; i <= dn; i += 64) out[i] = 0u;
+    if (__ballot(bad) != 0ull && lane == 0) atomicOr(&bad_any, 1);
+  }
+  __syncthreads();
+  if (tid == 0) G.gdeg[k] = bad_any ? -3 : d;
+}
+
+size_t gcd_lds_bytes(int da, int db) {
+  const int mx = da > db ? da : db, mn = da < db ? da : db;
+  return (size_t)(da + db + 2 + 2 * (mx + 1) + mn + 1) * sizeof(uint32_t);
+}
+
+void launch_gcd_p(const GcdDev& g, TablesDev tab, hipStream_t s) {
+  hipLaunchKernelGGL(k_gcd_p, dim3(g.P), dim3(256), gcd_lds_bytes(g.da, g.db), s, g, tab);
+}
+
+// dst[r][0..n) = src[idx[r]][0..n) (row stride of src: ld words)
+__global__ void k_gather_rows(const uint32_t* src, int ld, const int* idx, int rows, int n, uint32_t* dst) {
+  const int r = blockIdx.y;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows || c >= n) return;
+  dst[(size_t)r * n + c] = src[(size_t)idx[r] * ld + c];
+}
+
+void launch_gather_rows(const uint32_t* src, int ld, const int* idx, int rows, int n, uint32_t* dst, hipStream_t s) {
+  if (rows <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_gather_rows, dim3((n + 255) / 256, rows), dim3(256), 0, s, src, ld, idx, rows, n, dst);
 }
 
 // ---------------------------------------------------------------------------
@@ -591,18 +754,27 @@ void launch_interp(const JobDev* jobs, const int* starts, int nj, int nblocks, i
   hipLaunchKernelGGL(k_interp, dim3(nblocks), dim3(256), lds, s, jobs, starts, nj, tab);
 }
 
+bool mrc_lane_ok(int max_primes) { return max_primes <= MRC_LANE_MAXP; }
+
 void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, TablesDev tab,
                 hipStream_t s) {
-  size_t lds = (size_t)2 * max_primes * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_mrc, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, tab);
+  if (mrc_lane_ok(max_primes)) {
+    hipLaunchKernelGGL(k_mrc_lane, dim3(nblocks), dim3(64), (size_t)max_primes * 64 * sizeof(uint32_t), s, jobs,
+                       starts, nj, tab);
+  } else {
+    hipLaunchKernelGGL(k_mrc, dim3(nblocks), dim3(64), (size_t)2 * max_primes * sizeof(uint32_t), s, jobs, starts,
+                       nj, tab);
+  }
 }
 
 void launch_limbs_sum(const JobDev* jobs, const int* starts, int nj, int nblocks, TablesDev tab, hipStream_t s) {
   hipLaunchKernelGGL(k_limbs_sum, dim3(nblocks), dim3(256), 0, s, jobs, starts, nj, tab);
 }
 
-void launch_limbs_carry(const JobDev* jobs, const int* starts, int nj, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_limbs_carry, dim3(nblocks), dim3(64), 0, s, jobs, starts, nj);
+void launch_limbs_carry(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_lcap, hipStream_t s) {
+  const int stage_ld = max_lcap <= CARRY_STAGE_MAXL ? max_lcap + 1 : 0;
+  const size_t lds = (size_t)64 * stage_ld * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_limbs_carry, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, stage_ld);
 }
 
 }  // namespace bires

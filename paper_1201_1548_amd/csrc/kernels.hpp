@@ -31,9 +31,16 @@ void launch_interp(const JobDev* jobs, const int* starts, int nj, int nblocks, i
                    hipStream_t s);
 size_t interp_lds_words(int D);
 void launch_invfact(const ModP* primes, int K, uint32_t* invfact, int dmax, hipStream_t s);
+// mrc blocks per job: ceil(D/64) when mrc_lane_ok(max_primes) (one lane per
+// coefficient), else D (one wave per coefficient).
+bool mrc_lane_ok(int max_primes);
 void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, TablesDev tab,
                 hipStream_t s);
 void launch_limbs_sum(const JobDev* jobs, const int* starts, int nj, int nblocks, TablesDev tab, hipStream_t s);
-void launch_limbs_carry(const JobDev* jobs, const int* starts, int nj, int nblocks, hipStream_t s);
+size_t gcd_lds_bytes(int da, int db);
+void launch_gcd_p(const GcdDev& g, TablesDev tab, hipStream_t s);
+void launch_gather_rows(const uint32_t* src, int ld, const int* idx, int rows, int n, uint32_t* dst, hipStream_t s);
+// max_lcap: the largest Lcap of the jobs in the launch.
+void launch_limbs_carry(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_lcap, hipStream_t s);
 
 }  // namespace bires

@@ -73,27 +73,35 @@ static void build(HostTables& t, int K) {
     t.log2p[k] = std::log2((double)t.primes[k].p) - 1e-12;
     t.cumlog[k + 1] = t.cumlog[k] + t.log2p[k];
   }
-  t.gm.assign((size_t)K * K, 0u);
-  t.cm.assign(K, 0u);
+  mrc_tables(t.primes, t.gm, t.cm, t.pm, t.pi);
+}
+
+void mrc_tables(const std::vector<ModP>& primes, std::vector<uint32_t>& gm, std::vector<uint32_t>& cm,
+                std::vector<uint32_t>& pm, std::vector<uint32_t>& pi) {
+  const int K = (int)primes.size();
+  gm.assign((size_t)K * K, 0u);
+  cm.assign(K, 0u);
+  pm.assign((size_t)K * K, 0u);
   for (int k = 0; k < K; ++k) {
-    const uint64_t pk = t.primes[k].p;
+    const uint64_t pk = primes[k].p;
+    for (int j = 0; j < k; ++j) pm[(size_t)k * K + j] = (uint32_t)(((uint64_t)(primes[j].p % pk) << 32) % pk);
     uint64_t prod = 1 % pk;  // prod_{i<j} p_i mod p_k
     for (int j = 0; j < k; ++j) {
-      t.gm[(size_t)j * K + k] = (uint32_t)((prod << 32) % pk);
-      prod = mulmod64(prod, t.primes[j].p % pk, pk);
+      gm[(size_t)j * K + k] = (uint32_t)((prod << 32) % pk);
+      prod = mulmod64(prod, primes[j].p % pk, pk);
     }
     const uint64_t inv = powmod64(prod, pk - 2, pk);
-    t.cm[k] = (uint32_t)((inv << 32) % pk);
+    cm[k] = (uint32_t)((inv << 32) % pk);
   }
   // prod_{i<k} p_i as k+1 little-endian limbs at offset k(k+1)/2
-  t.pi.assign((size_t)K * (K + 1) / 2 + K + 1, 0u);
+  pi.assign((size_t)K * (K + 1) / 2 + K + 1, 0u);
   std::vector<uint32_t> cur(1, 1u);
   for (int k = 0; k < K; ++k) {
-    uint32_t* dst = &t.pi[(size_t)k * (k + 1) / 2];
+    uint32_t* dst = &pi[(size_t)k * (k + 1) / 2];
     for (int l = 0; l <= k && l < (int)cur.size(); ++l) dst[l] = cur[l];
     uint64_t carry = 0;
     for (auto& w : cur) {
-      uint64_t v = (uint64_t)w * t.primes[k].p + carry;
+      const uint64_t v = (uint64_t)w * primes[k].p + carry;
       w = (uint32_t)v;
       carry = v >> 32;
     }

@@ -10,6 +10,7 @@ namespace bires {
 
 constexpr int MAX_PRIMES = 2048;
 constexpr int MAX_POINTS = 8192;  // evaluation points (degree bound + 1) per job
+constexpr int MAX_GCD_DEGREE = 8000;
 
 struct HostTables {
   int K = 0;
@@ -18,10 +19,14 @@ struct HostTables {
   std::vector<double> cumlog;   // cumlog[k] = sum_{i<k} log2p[i]
   std::vector<uint32_t> gm;     // [K][K] Montgomery (prod_{i<j} p_i mod p_k), j < k
   std::vector<uint32_t> cm;     // [K] Montgomery (prod_{i<k} p_i)^{-1} mod p_k
+  std::vector<uint32_t> pm;     // [K][K] Montgomery (p_j mod p_k) at [k*K + j], j < k
   std::vector<uint32_t> pi;     // prod_{i<k} p_i, k+1 limbs at offset k(k+1)/2
 };
 
 ModP make_modp(uint32_t p);
+// Mixed-radix tables (layouts as in HostTables) for an arbitrary list of primes.
+void mrc_tables(const std::vector<ModP>& primes, std::vector<uint32_t>& gm, std::vector<uint32_t>& cm,
+                std::vector<uint32_t>& pm, std::vector<uint32_t>& pi);
 const HostTables& host_tables();
 
 }  // namespace bires

@@ -14,7 +14,7 @@ import pytest
 import sympy as sp
 
 from oracle import zx
-from oracle.gcd import gcd_mod_p, gcd_zx
+from oracle.gcd import gcd_mod_p, gcd_q_euclid, gcd_zx, prem
 
 X = sp.symbols("x")
 
@@ -97,3 +97,21 @@ def test_gcd_mod_p_matches_sympy(seed):
     ref = sp.Poly(list(reversed(a)), X, modulus=p).gcd(sp.Poly(list(reversed(b)), X, modulus=p))
     ref = [int(c) % p for c in reversed(ref.all_coeffs())]
     assert gcd_mod_p(a, b, p) == ref
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_primitive_prs_equals_rational_euclid(seed):
+    rng = random.Random(400 + seed)
+    C = rpoly(rng, rng.randint(0, 3), -9, 9)
+    a = zx.mul(rpoly(rng, rng.randint(0, 6), -30, 30), C)
+    b = zx.mul(rpoly(rng, rng.randint(0, 6), -30, 30), C)
+    assert gcd_zx(a, b) == gcd_q_euclid(a, b)
+
+
+def test_pseudo_remainder_definition():
+    rng = random.Random(7)
+    u, v = rpoly(rng, 7, -50, 50), rpoly(rng, 3, -50, 50)
+    r = prem(u, v)
+    # lc(v)^(deg u - deg v + 1) u = q v + r with deg r < deg v, checked over Q
+    q, rq = zx.divmod_q([c * v[-1] ** 5 for c in u], v)
+    assert [int(x) for x in rq] == r and all(x.denominator == 1 for x in q)
