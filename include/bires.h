@@ -183,9 +183,21 @@ int bires_primes(int n, uint32_t *out);
 int bires_debug_values(const bires_bipoly *f, const bires_bipoly *g, int kind, int var,
                        uint32_t *values, int64_t capacity, int32_t *points, int32_t *primes);
 
-/* Kernel timing: when enabled, the library brackets each launch of the
- * univariate-resultant kernel with HIP events on its stream and accumulates
- * the durations.  bires_kernel_time returns (milliseconds, launches) since the
+/* Launch schedule of the batched pipeline.
+ *   BIRES_SCHEDULE_STAGED: one launch per stage (reduce, evaluation +
+ *     elimination per size bucket, interpolation, mixed radix, limbs);
+ *   BIRES_SCHEDULE_FUSED: every stage of every job in one persistent launch
+ *     whose blocks take tasks from a device queue in dependency order;
+ *   BIRES_SCHEDULE_AUTO: the library picks (by batch size).
+ * Results are identical under every schedule.  Process-wide setting. */
+#define BIRES_SCHEDULE_STAGED 0
+#define BIRES_SCHEDULE_FUSED 1
+#define BIRES_SCHEDULE_AUTO 2
+int bires_set_schedule(int schedule);
+
+/* Kernel timing: when enabled, the library brackets the univariate-resultant
+ * launches (staged schedule) or the fused launch with HIP events on its stream
+ * and accumulates the durations.  bires_kernel_time returns (milliseconds, launches) since the
  * last reset. */
 int bires_set_timing(int enable);
 int bires_kernel_time(double *ms, int64_t *launches);

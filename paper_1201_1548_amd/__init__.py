@@ -77,6 +77,7 @@ _SIGS = {
                             ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
                             ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "bires_set_timing": ([ctypes.c_int], ctypes.c_int),
+    "bires_set_schedule": ([ctypes.c_int], ctypes.c_int),
     "bires_kernel_time": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "bires_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "bires_device_info": ([ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -343,6 +344,15 @@ def debug_values(F, G=None, kind="res", var="y"):
     _check(lib().bires_debug_values(ctypes.byref(fd), ctypes.byref(gd), k, _var(var), vals.ctypes.data,
                                     vals.size, ctypes.byref(Dp), ctypes.byref(Pp)), "bires_debug_values")
     return primes(Pp.value), vals.reshape(Pp.value, Dp.value)
+
+
+SCHEDULE_STAGED, SCHEDULE_FUSED, SCHEDULE_AUTO = 0, 1, 2
+
+
+def set_schedule(schedule):
+    """Launch schedule of batched calls: 'staged', 'fused' or 'auto'."""
+    code = {"staged": 0, "fused": 1, "auto": 2}[schedule] if isinstance(schedule, str) else schedule
+    _check(lib().bires_set_schedule(code), "bires_set_schedule")
 
 
 def set_timing(enable):

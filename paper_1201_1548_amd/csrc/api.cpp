@@ -161,6 +161,15 @@ int bires_set_timing(int enable) {
   return BIRES_OK;
 }
 
+int bires_set_schedule(int schedule) {
+  if (schedule < BIRES_SCHEDULE_STAGED || schedule > BIRES_SCHEDULE_AUTO) return BIRES_EINVAL;
+  int err = BIRES_OK;
+  Context* cx = context(&err);
+  if (!cx) return err;
+  cx->schedule = schedule;
+  return BIRES_OK;
+}
+
 int bires_kernel_time(double* ms, int64_t* launches) {
   int err = BIRES_OK;
   Context* cx = context(&err);

@@ -292,6 +292,32 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   for (int i = 0; i < nj; ++i)
     if (!w[i].status && w[i].active) w[i].o_rowdeg = ws.take((size_t)(w[i].pl.m + w[i].pl.n + 2) * 4);
   const size_t o_maps = ws.take(sizeof(int) * (size_t)NK * (nj + 1));
+  // persistent fused launch: per-stage task starts, counter offsets, counters
+  const bool fused = !debug && schedule_for(cx, w.size()) == BIRES_SCHEDULE_FUSED;
+  enum { F_STAGES = 6 };
+  std::vector<int> fst[F_STAGES];
+  std::vector<int> ctr_off(nj + 1, 0);
+  if (fused) {
+    for (auto& v : fst) v.assign(nj + 1, 0);
+    for (int i = 0; i < nj; ++i) {
+      const Work& x = w[i];
+      if (x.status || !x.active) continue;
+      const Plan& p = x.pl;
+      fst[0][i + 1] = (x.Tf + 63) / 64 + (x.Tg + 63) / 64;
+      fst[1][i + 1] = p.P * ((p.D + 63) / 64);
+      fst[2][i + 1] = p.P;
+      fst[3][i + 1] = mrc_lane_ok(maxP) ? (p.D + 63) / 64 : p.D;
+      fst[4][i + 1] = (p.D * x.Lacc + 63) / 64;
+      fst[5][i + 1] = (x.degcap + 1 + 63) / 64;
+      ctr_off[i + 1] = 4 + p.P;
+    }
+    for (auto& v : fst)
+      for (int i = 0; i < nj; ++i) v[i + 1] += v[i];
+    for (int i = 0; i < nj; ++i) ctr_off[i + 1] += ctr_off[i];
+  }
+  const size_t o_fst = ws.take(sizeof(int) * F_STAGES * (nj + 1));
+  const size_t o_ctroff = ws.take(sizeof(int) * (nj + 1));
+  const size_t o_ctr = ws.take(sizeof(int) * ((size_t)ctr_off[nj] + 2));  // counters, head, err
   const size_t meta_end = ws.bytes;
   Held d_ws(&cx->dev, ws.bytes), h_meta(&cx->host, meta_end - meta_begin), h_out(&cx->host, hout.bytes);
   if ((ws.bytes && !d_ws.p) || (meta_end > meta_begin && !h_meta.p) || (hout.bytes && !h_out.p))
@@ -348,6 +374,12 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   const int* dm = (const int*)(D0 + o_maps);
   for (int kk = 0; kk < NK; ++kk) std::memcpy(hm + (size_t)kk * (nj + 1), starts[kk].data(), sizeof(int) * (nj + 1));
   auto st_of = [&](int kk) { return dm + (size_t)kk * (nj + 1); };
+  if (fused) {
+    for (int k = 0; k < F_STAGES; ++k)
+      std::memcpy(H0 + o_fst + sizeof(int) * k * (nj + 1), fst[k].data(), sizeof(int) * (nj + 1));
+    std::memcpy(H0 + o_ctroff, ctr_off.data(), sizeof(int) * (nj + 1));
+    std::memset(H0 + o_ctr, 0, sizeof(int) * ((size_t)ctr_off[nj] + 2));
+  }
   auto nb_of = [&](int kk) { return starts[kk][nj]; };
   if (meta_end > meta_begin)
     DEV(hipMemcpyAsync(D0 + meta_begin, h_meta.p, meta_end - meta_begin, hipMemcpyHostToDevice, st));
@@ -362,13 +394,43 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     DEV(hipEventCreate(&ev0));
     DEV(hipEventCreate(&ev1));
   }
-  if (nb_of(K_RED)) launch_reduce(d_jobs, st_of(K_RED), nj, nb_of(K_RED), maxP, cx->tab, st);
-  if (timing) DEV(hipEventRecord(ev0, st));
-  for (int bk = 0; bk < NBUCKET; ++bk)
+  int* d_ctr = (int*)(D0 + o_ctr);
+  if (fused) {
+    FusedPlan F{};
+    F.jobs = d_jobs;
+    F.nj = nj;
+    int total = 0;
+    for (int k = 0; k < F_STAGES; ++k) {
+      F.st[k] = (const int*)(D0 + o_fst + sizeof(int) * k * (nj + 1));
+      F.base[k] = total;
+      total += fst[k][nj];
+    }
+    F.base[F_STAGES] = total;
+    F.ctr = d_ctr;
+    F.ctr_off = (const int*)(D0 + o_ctroff);
+    F.head = d_ctr + ctr_off[nj];
+    F.err = d_ctr + ctr_off[nj] + 1;
+    F.stage_ld = maxLcap <= 128 ? maxLcap + 1 : 0;
+    F.mrc_lane = mrc_lane_ok(maxP) ? 1 : 0;
+    size_t lds = interp_lds_words(maxD) * 4;
+    for (int i = 0; i < nj; ++i)
+      if (!w[i].status && w[i].active)
+        lds = std::max(lds, eval_elim_lds_bytes(w[i].pl.m + w[i].pl.n + 2, w[i].Tf + w[i].Tg));
+    lds = std::max(lds, (size_t)(F.mrc_lane ? maxP * 64 : 2 * maxP) * 4);
+    lds = std::max(lds, (size_t)64 * F.stage_ld * 4);
+    const int blocks = total ? fused_blocks(lds, total) : 0;
+    if (total && blocks <= 0) return BIRES_EDEVICE;
+    if (timing) DEV(hipEventRecord(ev0, st));
+    if (total) launch_fused(F, lds, blocks, cx->tab, st);
+    if (timing) DEV(hipEventRecord(ev1, st));
+  }
+  if (!fused && nb_of(K_RED)) launch_reduce(d_jobs, st_of(K_RED), nj, nb_of(K_RED), maxP, cx->tab, st);
+  if (!fused && timing) DEV(hipEventRecord(ev0, st));
+  for (int bk = 0; bk < NBUCKET && !fused; ++bk)
     if (nb_of(K_EE0 + bk))
       launch_eval_elim(d_jobs, st_of(K_EE0 + bk), nj, nb_of(K_EE0 + bk), bw[bk], br_[bk], cx->tab, st);
-  if (timing) DEV(hipEventRecord(ev1, st));
-  if (!debug) {
+  if (!fused && timing) DEV(hipEventRecord(ev1, st));
+  if (!debug && !fused) {
     if (nb_of(K_IP)) launch_interp(d_jobs, st_of(K_IP), nj, nb_of(K_IP), maxD, cx->tab, st);
     if (nb_of(K_MRC)) launch_mrc(d_jobs, st_of(K_MRC), nj, nb_of(K_MRC), maxP, cx->tab, st);
     if (nb_of(K_SUM)) launch_limbs_sum(d_jobs, st_of(K_SUM), nj, nb_of(K_SUM), cx->tab, st);
@@ -400,6 +462,8 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     }
   }
   if (nj) DEV(hipMemcpyAsync(h_flags, D0 + o_flags, sizeof(int32_t) * 2 * nj, hipMemcpyDeviceToHost, st));
+  int fused_err = 0;
+  if (fused) DEV(hipMemcpyAsync(&fused_err, d_ctr + ctr_off[nj] + 1, sizeof(int), hipMemcpyDeviceToHost, st));
   for (int i = 0; i < nj; ++i) {
     const Work& x = w[i];
     if (x.status || !x.active || mem != BIRES_MEM_HOST) continue;
@@ -421,6 +485,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   for (int i = 0; i < nj; ++i) {
     Work& x = w[i];
     bires_upoly* o = jobs[i].out;
+    if (!x.status && x.active && fused_err) x.status = BIRES_ECHECK;
     if (!x.status) {
       if (x.active) {
         if (h_flags[2 * i + 1]) {

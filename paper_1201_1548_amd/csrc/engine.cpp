@@ -136,6 +136,11 @@ Context* context(int* err) {
   return status == BIRES_OK ? &cx : nullptr;
 }
 
+int schedule_for(Context* cx, size_t njobs) {
+  if (cx->schedule != BIRES_SCHEDULE_AUTO) return cx->schedule;
+  return njobs >= 2 ? BIRES_SCHEDULE_FUSED : BIRES_SCHEDULE_STAGED;
+}
+
 // ---------------------------------------------------------------------------
 // validation and planning
 

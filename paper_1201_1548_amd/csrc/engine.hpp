@@ -42,10 +42,14 @@ struct Context {
   Pool host{true};
   size_t lds_per_block = 65536;
   bool timing = false;
+  int schedule = BIRES_SCHEDULE_STAGED;  // BIRES_SCHEDULE_*
   std::mutex timing_mu;
   double kernel_ms = 0.0;
   int64_t kernel_launches = 0;
 };
+
+// The schedule a batch of njobs runs with (resolves BIRES_SCHEDULE_AUTO).
+int schedule_for(Context* cx, size_t njobs);
 
 // Returns the initialised context or nullptr (err set).
 Context* context(int* err);

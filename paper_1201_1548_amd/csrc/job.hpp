@@ -47,6 +47,23 @@ struct GcdDev {
   int32_t* gdeg;          // [P] degree of the gcd mod p_k; -2: p_k divides lc(a) lc(b); -3: failed check
 };
 
+// The persistent fused launch: one queue of tasks, stage-major (reduce,
+// eval+elim, interp, mrc, limbs_sum, limbs_carry), jobs in order within a
+// stage.  Per job, ctr holds 4 + P counters at ctr_off[job]: reduce tasks
+// done, eval tasks done per prime (P), interp done, mrc done, limbs_sum done.
+struct FusedPlan {
+  const JobDev* jobs;
+  int32_t nj;
+  const int* st[6];      // per-stage first task of each job (nj + 1 entries each)
+  int32_t base[7];       // first queue index of each stage; base[6] = number of tasks
+  int* head;             // next task to take
+  int* ctr;              // completion counters
+  const int* ctr_off;    // [nj]
+  int* err;              // bit 1: a dependency wait timed out
+  int32_t stage_ld;      // limb-assembly staging row (0: direct writes)
+  int32_t mrc_lane;      // 1: lane-per-coefficient Garner
+};
+
 // Tables shared by every job: the prime list and the mixed-radix constants.
 struct TablesDev {
   const ModP* primes;       // [K]

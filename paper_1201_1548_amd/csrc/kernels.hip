@@ -91,15 +91,12 @@ __global__ void k_transpose(const uint32_t* src, uint32_t* dst, int rows, int co
 
 constexpr int KT = 16;
 
-__global__ void k_reduce(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
-  const int job = find_job(starts, nj, blockIdx.x);
-  const JobDev& J = jobs[job];
-  const int lb = blockIdx.x - starts[job];
+// Local block lb of a job (64 coefficients), primes [k0, k1).
+__device__ void dev_reduce(const JobDev& J, int lb, int k0, int k1, TablesDev tab) {
   const int nbf = (J.Tf + 63) / 64;
   const bool isg = lb >= nbf;
   const int T = isg ? J.Tg : J.Tf;
   const int t = (isg ? lb - nbf : lb) * 64 + threadIdx.x;
-  const int k0 = blockIdx.y * KT;
   if (t >= T || k0 >= J.P) return;
   const uint32_t* src;
   int L;
@@ -118,7 +115,7 @@ __global__ void k_reduce(const JobDev* jobs, const int* starts, int nj, TablesDe
   }
   const bool negv = (src[L - 1] >> 31) != 0u;
   uint32_t* dst = (isg ? J.res_g : J.res_f) + t;
-  const int k1 = min(J.P, k0 + KT);
+  k1 = min(J.P, k1);
   for (int k = k0; k < k1; ++k) {
     const ModP q = tab.primes[k];
     uint32_t x = 0;
@@ -127,6 +124,11 @@ __global__ void k_reduce(const JobDev* jobs, const int* starts, int nj, TablesDe
     if (mult) x = mmul(x, to_mont(mult, q), q);
     dst[(size_t)k * T] = x;
   }
+}
+
+__global__ void k_reduce(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
+  const int job = find_job(starts, nj, blockIdx.x);
+  dev_reduce(jobs[job], blockIdx.x - starts[job], blockIdx.y * KT, blockIdx.y * KT + KT, tab);
 }
 
 // ---------------------------------------------------------------------------
@@ -229,11 +231,7 @@ __device__ uint32_t uni_resultant(uint32_t* A, uint32_t* B, int m, int n, const 
 // degrees in LDS, then each lane evaluates f(a, y), g(a, y) by Horner's rule
 // into its own arrays and runs the elimination.
 template <int W>
-__global__ __launch_bounds__(W) void k_eval_elim(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
-  extern __shared__ uint32_t lds[];
-  const int job = find_job(starts, nj, blockIdx.x);
-  const JobDev& J = jobs[job];
-  const int lb = blockIdx.x - starts[job];
+__device__ void dev_eval_elim(const JobDev& J, int lb, TablesDev tab, uint32_t* lds) {
   const int nbpp = (J.D + W - 1) / W;
   const int k = lb / nbpp;
   const int a0 = (lb - k * nbpp) * W;
@@ -275,6 +273,13 @@ __global__ __launch_bounds__(W) void k_eval_elim(const JobDev* jobs, const int* 
   J.vals[(size_t)k * J.D + pt] = from_mont(r, q);
 }
 
+template <int W>
+__global__ __launch_bounds__(W) void k_eval_elim(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
+  extern __shared__ uint32_t lds[];
+  const int job = find_job(starts, nj, blockIdx.x);
+  dev_eval_elim<W>(jobs[job], blockIdx.x - starts[job], tab, lds);
+}
+
 // ---------------------------------------------------------------------------
 // (d) interpolation per prime on the nodes a = 0, 1, ..., D-1.
 //
@@ -312,11 +317,7 @@ __device__ __forceinline__ uint32_t reduce96(const Acc96& A, const ModP& q, uint
 // lane-parallel steps in one wave each.  One block per (job, prime).
 constexpr int KB = 32;
 
-__global__ __launch_bounds__(256) void k_interp(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
-  extern __shared__ uint32_t lds[];
-  const int job = find_job(starts, nj, blockIdx.x);
-  const JobDev& J = jobs[job];
-  const int k = blockIdx.x - starts[job];
+__device__ void dev_interp(const JobDev& J, int k, TablesDev tab, uint32_t* lds) {
   const int D = J.D;
   const ModP q = tab.primes[k];
   const uint32_t r3 = mmul(q.r2, q.r2, q);  // (R^2)_M = R^3 mod p
@@ -410,6 +411,12 @@ __global__ __launch_bounds__(256) void k_interp(const JobDev* jobs, const int* s
   for (int j = threadIdx.x; j < D; j += blockDim.x) out[j] = P0[j];
 }
 
+__global__ __launch_bounds__(256) void k_interp(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
+  extern __shared__ uint32_t lds[];
+  const int job = find_job(starts, nj, blockIdx.x);
+  dev_interp(jobs[job], blockIdx.x - starts[job], tab, lds);
+}
+
 size_t interp_lds_words(int D) { return (size_t)3 * D + (size_t)((D + KB - 1) / KB) * (2 * KB + 1); }
 
 // Inverse factorials per prime: invfact[k][n] = Montgomery form of 1/n!.
@@ -459,11 +466,8 @@ __device__ __forceinline__ int lift_negative(const uint32_t* v, int stride, int 
 // j = k-1 .. 0, with the constants p_j mod p_k (uniform, scalar loads).
 constexpr int MRC_LANE_MAXP = 128;
 
-__global__ __launch_bounds__(64) void k_mrc_lane(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
-  extern __shared__ uint32_t lds[];
-  const int job = find_job(starts, nj, blockIdx.x);
-  const JobDev& J = jobs[job];
-  const int c = (blockIdx.x - starts[job]) * 64 + threadIdx.x;
+__device__ void dev_mrc_lane(const JobDev& J, int lb, TablesDev tab, uint32_t* lds) {
+  const int c = lb * 64 + threadIdx.x;
   const int P = J.P, D = J.D;
   if (c >= D) return;
   uint32_t* v = lds + threadIdx.x;  // v[k * 64]
@@ -480,14 +484,16 @@ __global__ __launch_bounds__(64) void k_mrc_lane(const JobDev* jobs, const int* 
   J.negflag[c] = lift_negative(v, 64, P, tab.primes);
 }
 
+__global__ __launch_bounds__(64) void k_mrc_lane(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
+  extern __shared__ uint32_t lds[];
+  const int job = find_job(starts, nj, blockIdx.x);
+  dev_mrc_lane(jobs[job], blockIdx.x - starts[job], tab, lds);
+}
+
 // One wave per coefficient, lanes over primes k = lane + 64 t: lane k keeps
 // acc_k = sum_{j<k} v_j prod_{i<j} p_i mod p_k; at step j the owner lane of j
 // finishes v_j and broadcasts it.
-__global__ __launch_bounds__(64) void k_mrc(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
-  extern __shared__ uint32_t lds[];
-  const int job = find_job(starts, nj, blockIdx.x);
-  const JobDev& J = jobs[job];
-  const int c = blockIdx.x - starts[job];
+__device__ void dev_mrc_wave(const JobDev& J, int c, TablesDev tab, uint32_t* lds) {
   const int P = J.P, D = J.D;
   const int lane = threadIdx.x;
   uint32_t* x = lds;        // residues, then digits
@@ -518,15 +524,19 @@ __global__ __launch_bounds__(64) void k_mrc(const JobDev* jobs, const int* start
   if (lane == 0) J.negflag[c] = lift_negative(x, 1, P, tab.primes);
 }
 
+__global__ __launch_bounds__(64) void k_mrc(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
+  extern __shared__ uint32_t lds[];
+  const int job = find_job(starts, nj, blockIdx.x);
+  dev_mrc_wave(jobs[job], blockIdx.x - starts[job], tab, lds);
+}
+
 // (e) limb assembly, pass 1: one thread per (limb l, coefficient c) forms the
 // 96-bit column sum S_l = sum_k d_k limb_l(prod_{i<k} p_i), with d_k the digit
 // (non-negative lift) or p_k - 1 - digit (negative lift: then
 // M - v - 1 = sum (p_k - 1 - v_k) prod_{i<k} p_i).  Flat index l * D + c,
 // 256 per block; sums stored [Lacc][D].
-__global__ void k_limbs_sum(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
-  const int job = find_job(starts, nj, blockIdx.x);
-  const JobDev& J = jobs[job];
-  const int idx = (blockIdx.x - starts[job]) * 256 + threadIdx.x;
+__device__ void dev_limbs_sum(const JobDev& J, int lb, TablesDev tab) {
+  const int idx = lb * (int)blockDim.x + threadIdx.x;
   const int D = J.D;
   if (idx >= D * J.Lacc) return;
   const int l = idx / D;
@@ -545,6 +555,11 @@ __global__ void k_limbs_sum(const JobDev* jobs, const int* starts, int nj, Table
   J.acc_hi[idx] = hi;
 }
 
+__global__ void k_limbs_sum(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
+  const int job = find_job(starts, nj, blockIdx.x);
+  dev_limbs_sum(jobs[job], blockIdx.x - starts[job], tab);
+}
+
 // (e) limb assembly, pass 2: one lane per output coefficient propagates the
 // carries; a negative lift writes the bitwise complement (two's complement of
 // -(C + 1) is ~C).  The 64 coefficients of a block are staged in LDS and
@@ -553,11 +568,8 @@ __global__ void k_limbs_sum(const JobDev* jobs, const int* starts, int nj, Table
 constexpr int CARRY_STAGE_MAXL = 128;
 
 // stage_ld > 0: LDS rows of stage_ld words (>= Lcap + 1 of every job); 0: direct writes.
-__global__ __launch_bounds__(64) void k_limbs_carry(const JobDev* jobs, const int* starts, int nj, int stage_ld) {
-  extern __shared__ uint32_t lds[];
-  const int job = find_job(starts, nj, blockIdx.x);
-  const JobDev& J = jobs[job];
-  const int c0 = (blockIdx.x - starts[job]) * 64;
+__device__ void dev_limbs_carry(const JobDev& J, int lb, int stage_ld, uint32_t* lds) {
+  const int c0 = lb * 64;
   const int c = c0 + threadIdx.x;
   const int Lc = J.Lcap, D = J.D;
   const bool staged = stage_ld > 0;
@@ -600,6 +612,101 @@ __global__ __launch_bounds__(64) void k_limbs_carry(const JobDev* jobs, const in
       dst[i] = lds[r * ld + (i - r * Lc)];
     }
   }
+}
+
+__global__ __launch_bounds__(64) void k_limbs_carry(const JobDev* jobs, const int* starts, int nj, int stage_ld) {
+  extern __shared__ uint32_t lds[];
+  const int job = find_job(starts, nj, blockIdx.x);
+  dev_limbs_carry(jobs[job], blockIdx.x - starts[job], stage_ld, lds);
+}
+
+// ---------------------------------------------------------------------------
+// (a9) every stage of every job in one persistent launch.  Single-wave blocks
+// take queue positions with an atomic counter; a task first waits (lane 0,
+// bounded spin with sleeps) until the counter of the stage it depends on
+// reaches its target, then runs the same device function as the staged
+// kernel, then publishes its completion with an agent-scope release.  All
+// dependencies point to earlier queue positions, which were taken by running
+// blocks that wait only on still earlier ones, so the queue drains; a wait that
+// exceeds its bound sets err and the block moves on, so every wave exits.
+
+enum { FS_RED = 0, FS_EE, FS_IP, FS_MRC, FS_SUM, FS_CAR };
+
+__global__ __launch_bounds__(64) void k_fused(FusedPlan F, TablesDev tab) {
+  extern __shared__ uint32_t lds[];
+  __shared__ int s_task;
+  for (;;) {
+    if (threadIdx.x == 0) s_task = atomicAdd(F.head, 1);
+    __syncthreads();
+    const int t = s_task;
+    __syncthreads();
+    if (t >= F.base[6]) return;
+    int stage = 0;
+    while (t >= F.base[stage + 1]) ++stage;
+    const int local = t - F.base[stage];
+    const int job = find_job(F.st[stage], F.nj, local);
+    const int lb = local - F.st[stage][job];
+    const JobDev& J = F.jobs[job];
+    int* c = F.ctr + F.ctr_off[job];
+    const int P = J.P;
+    const int nbpp = (J.D + 63) / 64;
+    int* dep = nullptr;
+    int target = 0;
+    if (stage == FS_EE) {
+      dep = c;
+      target = F.st[FS_RED][job + 1] - F.st[FS_RED][job];
+    } else if (stage == FS_IP) {
+      dep = c + 1 + lb;
+      target = nbpp;
+    } else if (stage == FS_MRC) {
+      dep = c + 1 + P;
+      target = P;
+    } else if (stage == FS_SUM) {
+      dep = c + 2 + P;
+      target = F.st[FS_MRC][job + 1] - F.st[FS_MRC][job];
+    } else if (stage == FS_CAR) {
+      dep = c + 3 + P;
+      target = F.st[FS_SUM][job + 1] - F.st[FS_SUM][job];
+    }
+    if (dep && threadIdx.x == 0) {
+      int spins = 0;
+      while (__hip_atomic_load(dep, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(8);
+        if (++spins > (1 << 24)) {
+          atomicOr(F.err, 2);
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    if (stage == FS_RED) dev_reduce(J, lb, 0, P, tab);
+    else if (stage == FS_EE) dev_eval_elim<64>(J, lb, tab, lds);
+    else if (stage == FS_IP) dev_interp(J, lb, tab, lds);
+    else if (stage == FS_MRC) {
+      if (F.mrc_lane) dev_mrc_lane(J, lb, tab, lds);
+      else dev_mrc_wave(J, lb, tab, lds);
+    } else if (stage == FS_SUM) dev_limbs_sum(J, lb, tab);
+    else dev_limbs_carry(J, lb, F.stage_ld, lds);
+    __syncthreads();
+    if (threadIdx.x == 0 && stage != FS_CAR) {
+      int* done = stage == FS_RED ? c : stage == FS_EE ? c + 1 + lb / nbpp : c + 1 + P + (stage - FS_IP);
+      __threadfence();
+      __hip_atomic_fetch_add(done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+int fused_blocks(size_t lds_bytes, int tasks) {
+  int dev = 0, per_cu = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused, 64, lds_bytes) != hipSuccess) return 0;
+  const long long n = (long long)per_cu * prop.multiProcessorCount;
+  return (int)(n < tasks ? n : tasks);
+}
+
+void launch_fused(const FusedPlan& F, size_t lds_bytes, int blocks, TablesDev tab, hipStream_t s) {
+  hipLaunchKernelGGL(k_fused, dim3(blocks), dim3(64), lds_bytes, s, F, tab);
 }
 
 // ---------------------------------------------------------------------------

@@ -37,6 +37,10 @@ bool mrc_lane_ok(int max_primes);
 void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, TablesDev tab,
                 hipStream_t s);
 void launch_limbs_sum(const JobDev* jobs, const int* starts, int nj, int nblocks, TablesDev tab, hipStream_t s);
+// Persistent fused launch (see FusedPlan): blocks that fit on the device at
+// once for this LDS size, capped at the task count (0 on a runtime error).
+int fused_blocks(size_t lds_bytes, int tasks);
+void launch_fused(const FusedPlan& F, size_t lds_bytes, int blocks, TablesDev tab, hipStream_t s);
 size_t gcd_lds_bytes(int da, int db);
 void launch_gcd_p(const GcdDev& g, TablesDev tab, hipStream_t s);
 void launch_gather_rows(const uint32_t* src, int ld, const int* idx, int rows, int n, uint32_t* dst, hipStream_t s);

@@ -200,3 +200,42 @@ def test_config2_golden_bit_exact():
     digest, R = load("config2_res_0.txt")
     assert digest == input_digest(F, G)
     assert br.resultant(F, G) == R
+
+
+def _mixed_jobs():
+    jobs = []
+    for i in range(8):
+        a, b, c, d, bits = SHAPES[i]
+        F, G = synth.random_rect(700 + i, a, b, c, d, bits)
+        jobs.append(("res", F, G, "y" if i % 3 else "x"))
+    for i in range(24):
+        F, G = synth.config1_pair(i % 4)
+        jobs.append(("res", F, G, "y"))
+    F, G = synth.config2_pair(3)
+    jobs.append(("res", F, G, "y"))
+    H, _ = synth.random_rect(800, 5, 3, 1, 1, 40)
+    jobs += [("disc", H, None, "y"), ("res", [[0]], G, "y"), ("res", [[3, 1]], [[7, 2]], "y"),
+             ("disc", [[1, 2]], None, "y")]
+    return jobs
+
+
+@pytest.mark.parametrize("schedule", ["fused", "auto"])
+def test_fused_schedule_matches_staged(schedule):
+    jobs = _mixed_jobs()
+    say("schedule", schedule, "jobs", len(jobs))
+    br.set_schedule("staged")
+    ref, st_ref = br.resultant_batch(jobs)
+    try:
+        br.set_schedule(schedule)
+        got, st_got = br.resultant_batch(jobs)
+        b = br.DeviceBatch([j for j in jobs if not (j[0] == "disc" and len(j[1]) < 2)])
+        b.run()
+        dev = b.results()
+    finally:
+        br.set_schedule("staged")
+    assert st_got == st_ref and st_ref[-1] == -1 and st_ref.count(0) == len(jobs) - 1
+    assert got == ref
+    assert dev == [r for r, j in zip(ref, jobs) if not (j[0] == "disc" and len(j[1]) < 2)]
+    for (kind, F, G, var), R in list(zip(jobs, ref))[:12]:
+        if kind == "res":
+            assert R == (resultant_y(F, G) if var == "y" else resultant_x(F, G))
