@@ -124,6 +124,8 @@ def bench_config4(args):
     jobs = [("res", curves[i], curves[j], "y") for i, j in pairs]
     torch.cuda.set_device(0)
     batch = br.DeviceBatch(jobs)
+    br.set_schedule(args.schedule)
+    chosen = batch.autotune(reps=1) if args.schedule == "auto" else args.schedule
     batch.run()
     torch.cuda.synchronize()
     res = batch.results()
@@ -158,7 +160,8 @@ def bench_config4(args):
                                "all pairs within 20 seeded groups of 20 (3800 res_y)", "pairs": n},
         "plain": {"value": round(n / dtp, 2), "unit": "resultants/s", "ms_per_pair": round(dtp / n * 1e3, 3)},
         "batched_over_plain": round((n * args.steps / dt) / (n / dtp), 2),
-        "eval_elim_ms_per_step": round(kms / max(launches, 1), 3),
+        "schedule": chosen,
+        "timed_kernels_ms_per_step": round(kms / max(launches, 1), 3),
         "bit_exact": {"batched_vs_plain": exact_plain, "oracle_sample": exact_oracle, "oracle_pairs": len(small)},
     }
 
@@ -275,6 +278,24 @@ def bench_config3(args):
     }
 
 
+def bench_copy(args):
+    """Calibration for the HBM counters: a plain device copy of a known size
+    (torch's copy kernel), repeated `steps` times."""
+    import torch
+    n = 1 << 28  # 1 GiB of int32
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"metric": "device copy bandwidth (counter calibration)", "value": round(2 * 4 * n * args.steps / dt / 1e9, 1),
+            "unit": "GB/s", "bytes_read_per_copy": 4 * n, "bytes_written_per_copy": 4 * n, "copies": args.steps + 1}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,7 +304,9 @@ def main():
     ap.add_argument("--pairs", type=int, default=256)
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5"])
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain path (profiling runs)")
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5", "copy"])
+    ap.add_argument("--schedule", default="auto", choices=["auto", "staged", "fused"])
     ap.add_argument("--requests", type=int, default=300)
     ap.add_argument("--qps", type=float, default=0.0)
     ap.add_argument("--budget-gib", type=int, default=32)
@@ -294,7 +317,8 @@ def main():
               "device; see the sharding notes in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.workload != "config2":
-        fn = {"config3": bench_config3, "config4": bench_config4, "config5": bench_config5}[args.workload]
+        fn = {"config3": bench_config3, "config4": bench_config4, "config5": bench_config5,
+              "copy": bench_copy}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
 
@@ -314,6 +338,8 @@ def main():
     torch.cuda.set_device(0)
     dev = br.device_info()
     batch = br.DeviceBatch([("res", F, G, "y") for F, G in pairs])
+    br.set_schedule(args.schedule)
+    chosen = batch.autotune(reps=2) if args.schedule == "auto" else args.schedule
 
     # correctness gate: batched == plain == stored oracle values
     batch.run()
@@ -339,15 +365,19 @@ def main():
     value = n * args.steps / dt
 
     # plain path: one call per pair, same pairs, same buffers
-    batch.run_each()
-    torch.cuda.synchronize()
-    exact_plain = batch.results() == res_batch
-    t0 = time.perf_counter()
-    for _ in range(args.plain_steps):
+    exact_plain = None
+    if not args.no_plain:
         batch.run_each()
-    torch.cuda.synchronize()
-    dtp = time.perf_counter() - t0
-    plain_value = n * args.plain_steps / dtp
+        torch.cuda.synchronize()
+        exact_plain = batch.results() == res_batch
+    plain_value = dtp = None
+    if args.plain_steps > 0 and not args.no_plain:
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            batch.run_each()
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t0
+        plain_value = n * args.plain_steps / dtp
 
     # roofline of the dominant kernel (evaluation + univariate resultants)
     rowdeg = [20 - j for j in range(21)]
@@ -385,9 +415,11 @@ def main():
                         "uniform 32-bit signed coefficients, res_y" % n,
             "pairs": n, "tdeg": 20, "coef_bits": 32, "points": D, "primes": P,
         },
-        "plain": {"value": round(plain_value, 2), "unit": "resultants/s",
-                  "ms_per_pair": round(dtp / (n * args.plain_steps) * 1e3, 3)},
-        "batched_over_plain": round(value / plain_value, 2),
+        "plain": None if plain_value is None else {
+            "value": round(plain_value, 2), "unit": "resultants/s",
+            "ms_per_pair": round(dtp / (n * args.plain_steps) * 1e3, 3)},
+        "batched_over_plain": None if plain_value is None else round(value / plain_value, 2),
+        "schedule": chosen,
         "bit_exact": {"batched_vs_plain": exact_plain, "pair0_vs_oracle_golden": exact_golden},
         "device": dev,
         "roofline": roofline,

@@ -188,12 +188,24 @@ int bires_debug_values(const bires_bipoly *f, const bires_bipoly *g, int kind, i
  *     elimination per size bucket, interpolation, mixed radix, limbs);
  *   BIRES_SCHEDULE_FUSED: every stage of every job in one persistent launch
  *     whose blocks take tasks from a device queue in dependency order;
- *   BIRES_SCHEDULE_AUTO: the library picks (by batch size).
+ *   BIRES_SCHEDULE_AUTO (default): the autotuner's choice for the batch's size
+ *     key if it has one, else staged.
  * Results are identical under every schedule.  Process-wide setting. */
 #define BIRES_SCHEDULE_STAGED 0
 #define BIRES_SCHEDULE_FUSED 1
 #define BIRES_SCHEDULE_AUTO 2
 int bires_set_schedule(int schedule);
+
+/* Autotuner: runs the batch (arguments as bires_resultant_batch) under every
+ * schedule, keeps the fastest (best of `reps` timed runs after one warm-up) for
+ * the batch's size key (total (prime, point) instances, largest degree sum in
+ * the eliminated variable, largest prime count, each log2-bucketed), and
+ * returns it in *chosen.  BIRES_SCHEDULE_AUTO then uses the table; when the
+ * environment variable BIRES_AUTOTUNE_CACHE names a file, the table is loaded
+ * from it at set-up and rewritten after every tuning run.  The outputs hold the
+ * batch's results afterwards. */
+int bires_autotune(int n, const bires_bipoly *f, const bires_bipoly *g, const int32_t *kind, const int32_t *var,
+                   bires_upoly *out, int32_t *status, int mem, void *stream, int reps, int32_t *chosen);
 
 /* Kernel timing: when enabled, the library brackets the univariate-resultant
  * launches (staged schedule) or the fused launch with HIP events on its stream

@@ -78,6 +78,10 @@ _SIGS = {
                             ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "bires_set_timing": ([ctypes.c_int], ctypes.c_int),
     "bires_set_schedule": ([ctypes.c_int], ctypes.c_int),
+    "bires_autotune": ([ctypes.c_int, ctypes.POINTER(Bipoly), ctypes.POINTER(Bipoly),
+                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Upoly),
+                        ctypes.POINTER(ctypes.c_int32), ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                        ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "bires_kernel_time": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "bires_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "bires_device_info": ([ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -423,6 +427,15 @@ class DeviceBatch:
                                            self.status, MEM_DEVICE, _torch_stream(stream))
         _check(code, "bires_resultant_batch")
         return code
+
+    def autotune(self, reps=3, stream=None):
+        """Times this batch under each schedule; AUTO then uses the fastest. Returns its name."""
+        self._reset_outs()
+        chosen = ctypes.c_int32()
+        _check(lib().bires_autotune(self.n, self.fds, self.gds, self.kinds, self.vars, self.outs, self.status,
+                                    MEM_DEVICE, _torch_stream(stream), reps, ctypes.byref(chosen)),
+               "bires_autotune")
+        return {0: "staged", 1: "fused"}[chosen.value]
 
     def run_each(self, stream=None):
         """The plain path: one single-job call per job (bires_resultant / bires_discriminant)."""

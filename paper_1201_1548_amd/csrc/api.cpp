@@ -1,4 +1,5 @@
 // The C ABI of include/bires.h.
+#include <chrono>
 #include <cstring>
 #include <mutex>
 
@@ -167,6 +168,40 @@ int bires_set_schedule(int schedule) {
   Context* cx = context(&err);
   if (!cx) return err;
   cx->schedule = schedule;
+  return BIRES_OK;
+}
+
+int bires_autotune(int n, const bires_bipoly* f, const bires_bipoly* g, const int32_t* kind, const int32_t* var,
+                   bires_upoly* out, int32_t* status, int mem, void* stream, int reps, int32_t* chosen) {
+  if (reps < 1) return BIRES_EINVAL;
+  int err = BIRES_OK;
+  Context* cx = context(&err);
+  if (!cx) return err;
+  double best = 1e300;
+  int best_s = BIRES_SCHEDULE_STAGED;
+  std::string key;
+  for (int sched : {BIRES_SCHEDULE_STAGED, BIRES_SCHEDULE_FUSED}) {
+    cx->forced_schedule = sched;
+    int e = bires_resultant_batch(n, f, g, kind, var, out, status, mem, stream);  // warm-up
+    double t = 1e300;
+    for (int r = 0; r < reps && e == BIRES_OK; ++r) {
+      const auto t0 = std::chrono::steady_clock::now();
+      e = bires_resultant_batch(n, f, g, kind, var, out, status, mem, stream);
+      t = std::min(t, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+    }
+    cx->forced_schedule = -1;
+    if (e != BIRES_OK) return e;
+    {
+      std::lock_guard<std::mutex> lk(cx->tune_mu);
+      key = cx->last_key;
+    }
+    if (t < best) {
+      best = t;
+      best_s = sched;
+    }
+  }
+  tune_store(cx, key, best_s);
+  if (chosen) *chosen = best_s;
   return BIRES_OK;
 }
 

@@ -279,7 +279,10 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     starts[K_SUM][i + 1] = (p.D * x.Lacc + 255) / 256;
     starts[K_CAR][i + 1] = debug ? 0 : (x.degcap + 1 + 63) / 64;
   }
-  if (mrc_lane_ok(maxP))
+  long long totalD = 0;
+  for (int i = 0; i < nj; ++i) totalD += starts[K_MRC][i + 1];
+  const bool mrc_lane = mrc_lane_ok(maxP, totalD);
+  if (mrc_lane)
     for (int i = 0; i < nj; ++i) starts[K_MRC][i + 1] = (starts[K_MRC][i + 1] + 63) / 64;
   int maxLcap = 1;
   for (int i = 0; i < nj; ++i)
@@ -293,7 +296,19 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     if (!w[i].status && w[i].active) w[i].o_rowdeg = ws.take((size_t)(w[i].pl.m + w[i].pl.n + 2) * 4);
   const size_t o_maps = ws.take(sizeof(int) * (size_t)NK * (nj + 1));
   // persistent fused launch: per-stage task starts, counter offsets, counters
-  const bool fused = !debug && schedule_for(cx, w.size()) == BIRES_SCHEDULE_FUSED;
+  long long instances = 0;
+  int max_r = 0;
+  for (int i = 0; i < nj; ++i)
+    if (!w[i].status && w[i].active) {
+      instances += (long long)w[i].pl.P * w[i].pl.D;
+      max_r = std::max(max_r, w[i].pl.m + w[i].pl.n);
+    }
+  const std::string key = tune_key(instances, max_r, maxP);
+  {
+    std::lock_guard<std::mutex> lk(cx->tune_mu);
+    cx->last_key = key;
+  }
+  const bool fused = !debug && instances > 0 && schedule_for(cx, key) == BIRES_SCHEDULE_FUSED;
   enum { F_STAGES = 6 };
   std::vector<int> fst[F_STAGES];
   std::vector<int> ctr_off(nj + 1, 0);
@@ -306,7 +321,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
       fst[0][i + 1] = (x.Tf + 63) / 64 + (x.Tg + 63) / 64;
       fst[1][i + 1] = p.P * ((p.D + 63) / 64);
       fst[2][i + 1] = p.P;
-      fst[3][i + 1] = mrc_lane_ok(maxP) ? (p.D + 63) / 64 : p.D;
+      fst[3][i + 1] = mrc_lane ? (p.D + 63) / 64 : p.D;
       fst[4][i + 1] = (p.D * x.Lacc + 63) / 64;
       fst[5][i + 1] = (x.degcap + 1 + 63) / 64;
       ctr_off[i + 1] = 4 + p.P;
@@ -411,7 +426,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     F.head = d_ctr + ctr_off[nj];
     F.err = d_ctr + ctr_off[nj] + 1;
     F.stage_ld = maxLcap <= 128 ? maxLcap + 1 : 0;
-    F.mrc_lane = mrc_lane_ok(maxP) ? 1 : 0;
+    F.mrc_lane = mrc_lane ? 1 : 0;
     size_t lds = interp_lds_words(maxD) * 4;
     for (int i = 0; i < nj; ++i)
       if (!w[i].status && w[i].active)
@@ -432,7 +447,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   if (!fused && timing) DEV(hipEventRecord(ev1, st));
   if (!debug && !fused) {
     if (nb_of(K_IP)) launch_interp(d_jobs, st_of(K_IP), nj, nb_of(K_IP), maxD, cx->tab, st);
-    if (nb_of(K_MRC)) launch_mrc(d_jobs, st_of(K_MRC), nj, nb_of(K_MRC), maxP, cx->tab, st);
+    if (nb_of(K_MRC)) launch_mrc(d_jobs, st_of(K_MRC), nj, nb_of(K_MRC), maxP, mrc_lane, cx->tab, st);
     if (nb_of(K_SUM)) launch_limbs_sum(d_jobs, st_of(K_SUM), nj, nb_of(K_SUM), cx->tab, st);
     if (nb_of(K_CAR)) launch_limbs_carry(d_jobs, st_of(K_CAR), nj, nb_of(K_CAR), maxLcap, st);
   }

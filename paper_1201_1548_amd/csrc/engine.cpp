@@ -2,7 +2,9 @@
 #include "engine.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <string>
 
 #include "kernels.hpp"
@@ -124,6 +126,7 @@ static int init_context(Context& cx) {
   HIP_OK(hipStreamSynchronize(cx.stream));
   cx.tab.invfact = invfact;
   cx.tab.dmax = MAX_POINTS;
+  tune_load(&cx);
   return BIRES_OK;
 }
 
@@ -136,9 +139,48 @@ Context* context(int* err) {
   return status == BIRES_OK ? &cx : nullptr;
 }
 
-int schedule_for(Context* cx, size_t njobs) {
+static int log2_bucket(long long v) {
+  int b = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+std::string tune_key(long long instances, int max_r, int max_p) {
+  return "gfx950/i" + std::to_string(log2_bucket(instances)) + "/r" + std::to_string(log2_bucket(max_r)) + "/p" +
+         std::to_string(log2_bucket(max_p));
+}
+
+int schedule_for(Context* cx, const std::string& key) {
+  if (cx->forced_schedule >= 0) return cx->forced_schedule;
   if (cx->schedule != BIRES_SCHEDULE_AUTO) return cx->schedule;
-  return njobs >= 2 ? BIRES_SCHEDULE_FUSED : BIRES_SCHEDULE_STAGED;
+  {
+    std::lock_guard<std::mutex> lk(cx->tune_mu);
+    auto it = cx->tuned.find(key);
+    if (it != cx->tuned.end()) return it->second;
+  }
+  return BIRES_SCHEDULE_STAGED;  // faster in every measured untuned case
+}
+
+void tune_load(Context* cx) {
+  const char* path = std::getenv("BIRES_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  cx->tune_path = path;
+  std::ifstream in(path);
+  std::string key;
+  int sched;
+  while (in >> key >> sched)
+    if (sched == BIRES_SCHEDULE_STAGED || sched == BIRES_SCHEDULE_FUSED) cx->tuned[key] = sched;
+}
+
+void tune_store(Context* cx, const std::string& key, int schedule) {
+  std::lock_guard<std::mutex> lk(cx->tune_mu);
+  cx->tuned[key] = schedule;
+  if (cx->tune_path.empty()) return;
+  std::ofstream out(cx->tune_path, std::ios::trunc);
+  for (auto& kv : cx->tuned) out << kv.first << " " << kv.second << "\n";
 }
 
 // ---------------------------------------------------------------------------

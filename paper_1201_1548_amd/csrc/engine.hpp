@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "../../include/bires.h"
@@ -42,14 +44,25 @@ struct Context {
   Pool host{true};
   size_t lds_per_block = 65536;
   bool timing = false;
-  int schedule = BIRES_SCHEDULE_STAGED;  // BIRES_SCHEDULE_*
+  int schedule = BIRES_SCHEDULE_AUTO;    // BIRES_SCHEDULE_*
+  int forced_schedule = -1;              // set by the autotuner while it measures
+  std::mutex tune_mu;
+  std::map<std::string, int> tuned;      // batch key -> schedule
+  std::string tune_path;                 // BIRES_AUTOTUNE_CACHE
+  std::string last_key;                  // key of the last batch planned
   std::mutex timing_mu;
   double kernel_ms = 0.0;
   int64_t kernel_launches = 0;
 };
 
-// The schedule a batch of njobs runs with (resolves BIRES_SCHEDULE_AUTO).
-int schedule_for(Context* cx, size_t njobs);
+// Autotuning key of a planned batch: log2-buckets of the total (prime, point)
+// instances, of the largest m + n and of the largest prime count.
+std::string tune_key(long long instances, int max_r, int max_p);
+// The schedule a batch with this key runs with (resolves BIRES_SCHEDULE_AUTO:
+// the autotuner's choice for the key, else staged below 64k instances).
+int schedule_for(Context* cx, const std::string& key);
+void tune_load(Context* cx);
+void tune_store(Context* cx, const std::string& key, int schedule);
 
 // Returns the initialised context or nullptr (err set).
 Context* context(int* err);

@@ -861,11 +861,15 @@ void launch_interp(const JobDev* jobs, const int* starts, int nj, int nblocks, i
   hipLaunchKernelGGL(k_interp, dim3(nblocks), dim3(256), lds, s, jobs, starts, nj, tab);
 }
 
-bool mrc_lane_ok(int max_primes) { return max_primes <= MRC_LANE_MAXP; }
+bool mrc_lane_ok(int max_primes, long long total_coefficients) {
+  // one lane per coefficient needs enough coefficients to fill the device;
+  // otherwise one wave per coefficient has the shorter critical path
+  return max_primes <= MRC_LANE_MAXP && total_coefficients >= 16384;
+}
 
-void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, TablesDev tab,
+void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, bool lane, TablesDev tab,
                 hipStream_t s) {
-  if (mrc_lane_ok(max_primes)) {
+  if (lane) {
     hipLaunchKernelGGL(k_mrc_lane, dim3(nblocks), dim3(64), (size_t)max_primes * 64 * sizeof(uint32_t), s, jobs,
                        starts, nj, tab);
   } else {

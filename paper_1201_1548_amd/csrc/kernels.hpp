@@ -31,10 +31,10 @@ void launch_interp(const JobDev* jobs, const int* starts, int nj, int nblocks, i
                    hipStream_t s);
 size_t interp_lds_words(int D);
 void launch_invfact(const ModP* primes, int K, uint32_t* invfact, int dmax, hipStream_t s);
-// mrc blocks per job: ceil(D/64) when mrc_lane_ok(max_primes) (one lane per
-// coefficient), else D (one wave per coefficient).
-bool mrc_lane_ok(int max_primes);
-void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, TablesDev tab,
+// mrc blocks per job: ceil(D/64) with lane = true (one lane per coefficient,
+// allowed when mrc_lane_ok), else D (one wave per coefficient).
+bool mrc_lane_ok(int max_primes, long long total_coefficients);
+void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, bool lane, TablesDev tab,
                 hipStream_t s);
 void launch_limbs_sum(const JobDev* jobs, const int* starts, int nj, int nblocks, TablesDev tab, hipStream_t s);
 // Persistent fused launch (see FusedPlan): blocks that fit on the device at

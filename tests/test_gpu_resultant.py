@@ -239,3 +239,16 @@ def test_fused_schedule_matches_staged(schedule):
     for (kind, F, G, var), R in list(zip(jobs, ref))[:12]:
         if kind == "res":
             assert R == (resultant_y(F, G) if var == "y" else resultant_x(F, G))
+
+
+def test_autotune_keeps_results():
+    jobs = [("res",) + synth.config1_pair(i % 4) + ("y",) for i in range(16)]
+    say("autotune")
+    b = br.DeviceBatch(jobs)
+    choice = b.autotune(reps=1)
+    assert choice in ("staged", "fused")
+    out = b.results()
+    assert out == [resultant_y(F, G) for _, F, G, _ in jobs]
+    br.set_schedule("auto")
+    b.run()
+    assert b.results() == out
