@@ -32,6 +32,37 @@ OPS_MULMOD, OPS_DOT2, OPS_ADDMOD = 5, 6, 2
 INT32_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 
 
+TRAFFIC_SOURCES = ("kernels.hip", "kernels.hpp", "job.hpp", "modp.hpp")
+
+
+def kernel_source_digest():
+    """sha256 over the device sources of the library (fixed order)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1201_1548_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload`, from the committed
+    rocprofv3 counter summary profiles/traffic_<kernel>_<workload>.md, or None
+    when that summary is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.md" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.startswith(("source_sha256", "hbm_bytes_per_launch")):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source_sha256") != kernel_source_digest() or "hbm_bytes_per_launch" not in fields:
+        return None
+    return int(fields["hbm_bytes_per_launch"])
+
+
 def _pow_cost(e):
     return (e.bit_length() + bin(e).count("1")) if e > 0 else 0
 
@@ -361,6 +392,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kms, launches = br.kernel_time()
+    host_us, host_calls = br.host_time()
     br.set_timing(False)
     value = n * args.steps / dt
 
@@ -391,7 +423,8 @@ def main():
         "peak": round(INT32_PEAK_TOPS, 1),
         "unit": "T int32-op/s",
         "frac": round(achieved / INT32_PEAK_TOPS, 4),
-        "traffic": None,
+        "traffic": stored_traffic("k_eval_elim", "config2_batch%d" % n),
+        "traffic_unit": "bytes per launch",
         "kernel": "k_eval_elim",
         "kernel_ms": round(avg_ms, 4),
         "ops_per_launch": ops_launch,
@@ -422,6 +455,7 @@ def main():
         "schedule": chosen,
         "bit_exact": {"batched_vs_plain": exact_plain, "pair0_vs_oracle_golden": exact_golden},
         "device": dev,
+        "host_us_per_step": {k: round(v / max(host_calls, 1), 1) for k, v in host_us.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -214,6 +214,17 @@ int bires_autotune(int n, const bires_bipoly *f, const bires_bipoly *g, const in
 int bires_set_timing(int enable);
 int bires_kernel_time(double *ms, int64_t *launches);
 
+/* Host time of batched calls while timing is enabled, accumulated per phase in
+ * microseconds since the last reset (bires_set_timing):
+ *   us[0] inputs staged and the row-statistics scan submitted,
+ *   us[1] waiting for the statistics (device-memory inputs),
+ *   us[2] planning, workspace layout and job descriptors,
+ *   us[3] metadata upload and kernel launches,
+ *   us[4] waiting for the device, statuses and host outputs.
+ * us must hold BIRES_HOST_PHASES doubles; *calls = batched calls timed. */
+#define BIRES_HOST_PHASES 5
+int bires_host_time(double *us, int64_t *calls);
+
 /* Properties of the current device as the HIP runtime reports them: compute
  * units, peak engine clock (kHz), LDS bytes per workgroup, HBM bytes. */
 int bires_device_info(int32_t *compute_units, int32_t *clock_khz, int64_t *lds_per_block, int64_t *hbm_bytes);

@@ -83,6 +83,7 @@ _SIGS = {
                         ctypes.POINTER(ctypes.c_int32), ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                         ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "bires_kernel_time": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "bires_host_time": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "bires_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "bires_device_info": ([ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
@@ -368,6 +369,18 @@ def kernel_time():
     n = ctypes.c_int64()
     _check(lib().bires_kernel_time(ctypes.byref(ms), ctypes.byref(n)), "bires_kernel_time")
     return ms.value, n.value
+
+
+HOST_PHASES = ("stage_and_scan", "scan_wait", "plan", "upload_and_launch", "device_wait_and_results")
+
+
+def host_time():
+    """Host microseconds per phase of the batched calls timed since the last
+    set_timing (dict keyed by HOST_PHASES) and the number of calls."""
+    us = (ctypes.c_double * len(HOST_PHASES))()
+    n = ctypes.c_int64()
+    _check(lib().bires_host_time(us, ctypes.byref(n)), "bires_host_time")
+    return dict(zip(HOST_PHASES, list(us))), n.value
 
 
 # ----------------------------------------------------------------------------

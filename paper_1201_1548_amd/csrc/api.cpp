@@ -159,6 +159,8 @@ int bires_set_timing(int enable) {
   cx->timing = enable != 0;
   cx->kernel_ms = 0.0;
   cx->kernel_launches = 0;
+  for (double& u : cx->host_us) u = 0.0;
+  cx->host_calls = 0;
   return BIRES_OK;
 }
 
@@ -212,6 +214,17 @@ int bires_kernel_time(double* ms, int64_t* launches) {
   std::lock_guard<std::mutex> lk(cx->timing_mu);
   if (ms) *ms = cx->kernel_ms;
   if (launches) *launches = cx->kernel_launches;
+  return BIRES_OK;
+}
+
+int bires_host_time(double* us, int64_t* calls) {
+  int err = BIRES_OK;
+  Context* cx = context(&err);
+  if (!cx) return err;
+  std::lock_guard<std::mutex> lk(cx->timing_mu);
+  if (us)
+    for (int k = 0; k < BIRES_HOST_PHASES; ++k) us[k] = cx->host_us[k];
+  if (calls) *calls = cx->host_calls;
   return BIRES_OK;
 }
 

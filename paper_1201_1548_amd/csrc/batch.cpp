@@ -1,6 +1,7 @@
 // The batched pipeline: plan every job, lay out one device workspace, launch
 // each kernel once for all jobs, copy the results back.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 
 #include "engine.hpp"
@@ -86,9 +87,34 @@ static int validate(const JobIn& jb, bool need_out) {
     if ((x) != hipSuccess) return BIRES_EDEVICE; \
   } while (0)
 
+namespace {
+// Host time per phase of a batched call (microseconds), accumulated into the
+// context when timing is enabled.
+struct HostClock {
+  using C = std::chrono::steady_clock;
+  bool on;
+  C::time_point last;
+  double us[BIRES_HOST_PHASES] = {0};
+  explicit HostClock(bool enable) : on(enable), last(C::now()) {}
+  void mark(int phase) {
+    if (!on) return;
+    const C::time_point t = C::now();
+    us[phase] += std::chrono::duration<double, std::micro>(t - last).count();
+    last = t;
+  }
+  void commit(Context* cx) {
+    if (!on) return;
+    std::lock_guard<std::mutex> lk(cx->timing_mu);
+    for (int k = 0; k < BIRES_HOST_PHASES; ++k) cx->host_us[k] += us[k];
+    cx->host_calls += 1;
+  }
+};
+}  // namespace
+
 int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t st, int32_t* status,
               std::vector<uint32_t>* debug_values, std::vector<int>* debug_shape) {
   if (mem != BIRES_MEM_HOST && mem != BIRES_MEM_DEVICE) return BIRES_EINVAL;
+  HostClock hc(cx->timing && debug_values == nullptr);
   const int nj = (int)jobs.size();
   const bool debug = debug_values != nullptr;
   std::vector<Work> w(nj);
@@ -173,21 +199,16 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     if (scan_end > scan_begin)
       DEV(hipMemcpyAsync(h_in.b() + scan_begin, d_in.b() + scan_begin, scan_end - scan_begin, hipMemcpyDeviceToHost,
                          st));
+    hc.mark(0);
     DEV(hipStreamSynchronize(st));
+    hc.mark(1);
     for (int i = 0; i < nj; ++i) {
       if (w[i].status) continue;
       for (int which = 0; which < nsrc(i); ++which) {
         const int rows = shp(i, which).rows;
         const int32_t* v = (const int32_t*)(h_in.b() + w[i].o_scan[which]);
         RowStats& rs = which ? w[i].stg : w[i].stf;
-        rs.deg.resize(rows);
-        rs.bits.resize(rows);
-        rs.cnt.resize(rows);
-        for (int j = 0; j < rows; ++j) {
-          rs.deg[j] = v[3 * j];
-          rs.bits[j] = v[3 * j + 1];
-          rs.cnt[j] = v[3 * j + 2];
-        }
+        rs.v.assign(v, v + 3 * (size_t)rows);
       }
     }
   }
@@ -198,8 +219,8 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     if (x.status) continue;
     if (x.disc) {
       int top = -1;
-      for (int j = 0; j < (int)x.stf.cnt.size(); ++j)
-        if (x.stf.cnt[j]) top = j;
+      for (int j = 0; j < x.stf.rows(); ++j)
+        if (x.stf.cnt(j)) top = j;
       if (top < 1) {
         x.status = BIRES_EINVAL;
         continue;
@@ -209,8 +230,8 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     if ((x.status = make_plan(x.stf, x.stg, x.pl))) continue;
     if (x.pl.kind_special == 0 &&
         (x.pl.D > MAX_POINTS || interp_lds_words(x.pl.D) * 4 > cx->lds_per_block ||
-         eval_elim_lds_bytes(x.pl.m + x.pl.n + 2,
-                             (x.pl.m + 1) * x.sf.ld + (x.pl.n + 1) * (x.disc ? x.sf.ld : x.sg.ld)) >
+         eval_elim_lds_bytes(x.pl.m + x.pl.n + 2, (x.pl.m + 1) * pad4(x.sf.ld) +
+                                                      (x.pl.n + 1) * pad4(x.disc ? x.sf.ld : x.sg.ld)) >
              cx->lds_per_block)) {
       x.status = BIRES_ETOOBIG;
       continue;
@@ -230,8 +251,8 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     x.active = x.pl.kind_special == 0;
     if (x.active) {
       x.ldg = x.disc ? x.sf.ld : x.sg.ld;
-      x.Tf = (x.pl.m + 1) * x.sf.ld;
-      x.Tg = (x.pl.n + 1) * x.ldg;
+      x.Tf = (x.pl.m + 1) * pad4(x.sf.ld);
+      x.Tg = (x.pl.n + 1) * pad4(x.ldg);
       x.Lacc = std::min(x.Lout, x.pl.P + 1);
     }
   }
@@ -289,12 +310,6 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     if (!w[i].status && w[i].active) maxLcap = std::max(maxLcap, w[i].Lout);
   for (auto& v : starts)
     for (int i = 0; i < nj; ++i) v[i + 1] += v[i];
-  const size_t meta_begin = ws.take(0);
-  const size_t o_jobs = ws.take(sizeof(JobDev) * (size_t)nj);
-  const size_t o_flags = ws.take(sizeof(int32_t) * 2 * (size_t)nj);
-  for (int i = 0; i < nj; ++i)
-    if (!w[i].status && w[i].active) w[i].o_rowdeg = ws.take((size_t)(w[i].pl.m + w[i].pl.n + 2) * 4);
-  const size_t o_maps = ws.take(sizeof(int) * (size_t)NK * (nj + 1));
   // persistent fused launch: per-stage task starts, counter offsets, counters
   long long instances = 0;
   int max_r = 0;
@@ -309,6 +324,47 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     cx->last_key = key;
   }
   const bool fused = !debug && instances > 0 && schedule_for(cx, key) == BIRES_SCHEDULE_FUSED;
+  // staged schedule: explicit CRT straight to limbs when the prime counts allow
+  std::vector<std::pair<const uint32_t*, int>> crt(nj, {nullptr, 0});
+  bool use_crt = !debug && !fused && crt_ok(maxP);
+  int maxLM = 1;
+  for (int i = 0; i < nj && use_crt; ++i) {
+    if (w[i].status || !w[i].active) continue;
+    int LM = 0;
+    const uint32_t* d = crt_device(cx, w[i].pl.P, &LM);
+    if (!d) use_crt = false;
+    crt[i] = {d, LM};
+    maxLM = std::max(maxLM, LM);
+  }
+  if (use_crt && crt_lds_bytes(maxP, maxLM, maxLcap) > cx->lds_per_block) use_crt = false;
+  // staged schedule: interpolation on the matrix cores when at least 32 jobs
+  // share D and P (all active jobs of the batch)
+  std::vector<int> group;
+  int gD = 0, gP = 0;
+  for (int i = 0; i < nj && !debug && !fused; ++i) {
+    if (w[i].status || !w[i].active) continue;
+    if (group.empty()) {
+      gD = w[i].pl.D;
+      gP = w[i].pl.P;
+    } else if (w[i].pl.D != gD || w[i].pl.P != gP) {
+      group.clear();
+      break;
+    }
+    group.push_back(i);
+  }
+  const int8_t* vinv = nullptr;
+  if ((int)group.size() >= 32 && gD <= 4096) vinv = vinv_device(cx, gD, gP, st);
+  if (!vinv) group.clear();
+  const int gDp = (gD + 31) & ~31, gNp = ((int)group.size() + 31) & ~31;
+  const size_t o_yp = group.empty() ? 0 : ws.take((size_t)4 * gNp * gDp * gP);
+  // metadata uploaded with one copy: descriptors, flags, row degrees, block maps
+  const size_t meta_begin = ws.take(0);
+  const size_t o_jobs = ws.take(sizeof(JobDev) * (size_t)nj);
+  const size_t o_flags = ws.take(sizeof(int32_t) * 2 * (size_t)nj);
+  for (int i = 0; i < nj; ++i)
+    if (!w[i].status && w[i].active) w[i].o_rowdeg = ws.take((size_t)(w[i].pl.m + w[i].pl.n + 2) * 4);
+  const size_t o_maps = ws.take(sizeof(int) * (size_t)NK * (nj + 1));
+  const size_t o_gj = ws.take(sizeof(int) * group.size());
   enum { F_STAGES = 6 };
   std::vector<int> fst[F_STAGES];
   std::vector<int> ctr_off(nj + 1, 0);
@@ -361,11 +417,13 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     J.disc = x.disc ? 1 : 0;
     J.P = p.P;
     J.D = p.D;
+    J.lpf = pad4(x.sf.ld);
+    J.lpg = pad4(x.ldg);
     J.Tf = x.Tf;
     J.Tg = x.Tg;
     int32_t* rd = (int32_t*)(H0 + x.o_rowdeg);
-    for (int j = 0; j <= p.m; ++j) rd[j] = x.stf.deg[j];
-    for (int j = 0; j <= p.n; ++j) rd[p.m + 1 + j] = x.stg.deg[j];
+    for (int j = 0; j <= p.m; ++j) rd[j] = x.stf.deg(j);
+    for (int j = 0; j <= p.n; ++j) rd[p.m + 1 + j] = x.stg.deg(j);
     J.rowdeg_f = (const int32_t*)(D0 + x.o_rowdeg);
     J.rowdeg_g = J.rowdeg_f + p.m + 1;
     J.res_f = (uint32_t*)(D0 + x.o_res_f);
@@ -382,6 +440,8 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
       J.Lcap = x.Lout;
       J.degcap = x.degcap;
     }
+    J.crt = crt[i].first;
+    J.crt_LM = crt[i].second;
     J.deg_out = (int32_t*)(D0 + o_flags) + 2 * i;
     J.err = (int32_t*)(D0 + o_flags) + 2 * i + 1;
   }
@@ -389,6 +449,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   const int* dm = (const int*)(D0 + o_maps);
   for (int kk = 0; kk < NK; ++kk) std::memcpy(hm + (size_t)kk * (nj + 1), starts[kk].data(), sizeof(int) * (nj + 1));
   auto st_of = [&](int kk) { return dm + (size_t)kk * (nj + 1); };
+  if (!group.empty()) std::memcpy(H0 + o_gj, group.data(), sizeof(int) * group.size());
   if (fused) {
     for (int k = 0; k < F_STAGES; ++k)
       std::memcpy(H0 + o_fst + sizeof(int) * k * (nj + 1), fst[k].data(), sizeof(int) * (nj + 1));
@@ -396,6 +457,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     std::memset(H0 + o_ctr, 0, sizeof(int) * ((size_t)ctr_off[nj] + 2));
   }
   auto nb_of = [&](int kk) { return starts[kk][nj]; };
+  hc.mark(2);
   if (meta_end > meta_begin)
     DEV(hipMemcpyAsync(D0 + meta_begin, h_meta.p, meta_end - meta_begin, hipMemcpyHostToDevice, st));
   const JobDev* d_jobs = (const JobDev*)(D0 + o_jobs);
@@ -446,10 +508,19 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
       launch_eval_elim(d_jobs, st_of(K_EE0 + bk), nj, nb_of(K_EE0 + bk), bw[bk], br_[bk], cx->tab, st);
   if (!fused && timing) DEV(hipEventRecord(ev1, st));
   if (!debug && !fused) {
-    if (nb_of(K_IP)) launch_interp(d_jobs, st_of(K_IP), nj, nb_of(K_IP), maxD, cx->tab, st);
-    if (nb_of(K_MRC)) launch_mrc(d_jobs, st_of(K_MRC), nj, nb_of(K_MRC), maxP, mrc_lane, cx->tab, st);
-    if (nb_of(K_SUM)) launch_limbs_sum(d_jobs, st_of(K_SUM), nj, nb_of(K_SUM), cx->tab, st);
-    if (nb_of(K_CAR)) launch_limbs_carry(d_jobs, st_of(K_CAR), nj, nb_of(K_CAR), maxLcap, st);
+    if (!group.empty())
+      launch_interp_mfma(d_jobs, (const int*)(D0 + o_gj), (int)group.size(), gD, gP, vinv, (int8_t*)(D0 + o_yp),
+                         cx->tab, st);
+    else if (nb_of(K_IP))
+      launch_interp(d_jobs, st_of(K_IP), nj, nb_of(K_IP), maxD, cx->tab, st);
+    if (use_crt) {
+      // residues to limbs in one pass over the output capacity
+      if (nb_of(K_CAR)) launch_crt(d_jobs, st_of(K_CAR), nj, nb_of(K_CAR), maxP, maxLM, maxLcap, cx->tab, st);
+    } else {
+      if (nb_of(K_MRC)) launch_mrc(d_jobs, st_of(K_MRC), nj, nb_of(K_MRC), maxP, mrc_lane, cx->tab, st);
+      if (nb_of(K_SUM)) launch_limbs_sum(d_jobs, st_of(K_SUM), nj, nb_of(K_SUM), cx->tab, st);
+      if (nb_of(K_CAR)) launch_limbs_carry(d_jobs, st_of(K_CAR), nj, nb_of(K_CAR), maxLcap, st);
+    }
   }
   DEV(hipGetLastError());
 
@@ -476,6 +547,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
       DEV(hipMemcpyAsync(o->c, &one, 4, hipMemcpyHostToDevice, st));
     }
   }
+  hc.mark(3);
   if (nj) DEV(hipMemcpyAsync(h_flags, D0 + o_flags, sizeof(int32_t) * 2 * nj, hipMemcpyDeviceToHost, st));
   int fused_err = 0;
   if (fused) DEV(hipMemcpyAsync(&fused_err, d_ctr + ctr_off[nj] + 1, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -521,6 +593,8 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     if (status) status[i] = x.status;
     if (x.status && first_err == BIRES_OK) first_err = x.status;
   }
+  hc.mark(4);
+  hc.commit(cx);
   return first_err;
 }
 
@@ -538,7 +612,7 @@ int plan_host_job(const JobIn& jb, Plan& pl) {
   if (jb.kind == BIRES_KIND_DISCRIMINANT) {
     int top = -1;
     for (int j = 0; j < sf.rows; ++j)
-      if (stf.cnt[j]) top = j;
+      if (stf.cnt(j)) top = j;
     if (top < 1) return BIRES_EINVAL;
     stg = derive_stats(stf);
   } else {

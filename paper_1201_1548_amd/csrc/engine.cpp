@@ -126,8 +126,58 @@ static int init_context(Context& cx) {
   HIP_OK(hipStreamSynchronize(cx.stream));
   cx.tab.invfact = invfact;
   cx.tab.dmax = MAX_POINTS;
+  std::vector<double> invp(t.K);
+  for (int k = 0; k < t.K; ++k) invp[k] = 1.0 / (double)t.primes[k].p;
+  double* d_invp = nullptr;
+  HIP_OK(hipMalloc(&d_invp, invp.size() * sizeof(double)));
+  HIP_OK(hipMemcpy(d_invp, invp.data(), invp.size() * sizeof(double), hipMemcpyHostToDevice));
+  cx.tab.inv_p = d_invp;
   tune_load(&cx);
   return BIRES_OK;
+}
+
+const uint32_t* crt_device(Context* cx, int P, int* LM) {
+  std::lock_guard<std::mutex> lk(cx->crt_mu);
+  auto it = cx->crt.find(P);
+  if (it == cx->crt.end()) {
+    const CrtHost h = crt_tables(P);
+    uint32_t* d = nullptr;
+    if (hipMalloc(&d, h.buf.size() * sizeof(uint32_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    if (hipMemcpy(d, h.buf.data(), h.buf.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(d);
+      return nullptr;
+    }
+    it = cx->crt.emplace(P, std::make_pair((const uint32_t*)d, h.LM)).first;
+  }
+  *LM = it->second.second;
+  return it->second.first;
+}
+
+const int8_t* vinv_device(Context* cx, int D, int P, hipStream_t st) {
+  constexpr size_t kLimit = (size_t)2 << 30;  // bytes of cached tables
+  std::lock_guard<std::mutex> lk(cx->vinv_mu);
+  auto it = cx->vinv.find({D, P});
+  if (it != cx->vinv.end()) return it->second;
+  const int Dp = (D + 31) & ~31;
+  const size_t bytes = vinv_bytes(Dp, P);
+  if (cx->vinv_total + bytes > kLimit) return nullptr;
+  int8_t* d = nullptr;
+  if (hipMalloc(&d, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  launch_vinv(D, Dp, P, cx->tab, d, st);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+    (void)hipFree(d);
+    return nullptr;
+  }
+  cx->vinv_total += bytes;
+  cx->vinv.emplace(std::make_pair(D, P), d);
+  return d;
 }
 
 Context* context(int* err) {

@@ -53,7 +53,22 @@ struct Context {
   std::mutex timing_mu;
   double kernel_ms = 0.0;
   int64_t kernel_launches = 0;
+  double host_us[BIRES_HOST_PHASES] = {0};
+  int64_t host_calls = 0;
+  std::mutex crt_mu;
+  std::map<int, std::pair<const uint32_t*, int>> crt;  // P -> (device CrtHost buffer, LM)
+  std::mutex vinv_mu;
+  std::map<std::pair<int, int>, const int8_t*> vinv;   // (D, P) -> inverse Vandermonde digit planes
+  size_t vinv_total = 0;
 };
+
+// Inverse Vandermonde digit planes for nodes 0..D-1 and the first P primes,
+// built on first use (on stream st, which is then synchronised) and kept;
+// nullptr when it would exceed the cache limit or allocation fails.
+const int8_t* vinv_device(Context* cx, int D, int P, hipStream_t st);
+
+// Device copy of crt_tables(P), built on first use and kept (nullptr on failure).
+const uint32_t* crt_device(Context* cx, int P, int* LM);
 
 // Autotuning key of a planned batch: log2-buckets of the total (prime, point)
 // instances, of the largest m + n and of the largest prime count.

@@ -193,6 +193,8 @@ int modular_phase(Context* cx, const Poly& A, const Poly& B, const BigInt& beta,
   J.ldf = da + 1;
   J.ldg = db + 1;
   J.P = P;
+  J.lpf = da + 1;
+  J.lpg = db + 1;
   J.Tf = da + 1;
   J.Tg = db + 1;
   J.res_f = dev.as<uint32_t>(o_ra);

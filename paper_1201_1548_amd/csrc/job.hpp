@@ -17,7 +17,8 @@ struct JobDev {
   int32_t m, n;             // degrees in y (top non-zero row of f, g)
   int32_t disc;             // 1: g = df/dy
   int32_t P, D;             // primes, evaluation points (= degree bound + 1)
-  int32_t Tf, Tg;           // residues per prime: (m+1)*ldf, (n+1)*ldg
+  int32_t lpf, lpg;         // row stride of the residue rows (ldf, ldg rounded up to 4)
+  int32_t Tf, Tg;           // residues per prime: (m+1)*lpf, (n+1)*lpg; padding is zero
   const int32_t* rowdeg_f;  // [m+1] degree in x of each row (-1: zero row)
   const int32_t* rowdeg_g;  // [n+1]
   uint32_t* res_f;          // [P][Tf] Montgomery residues
@@ -31,6 +32,8 @@ struct JobDev {
   int32_t Lacc;             // min(Lcap, P + 1)
   uint32_t* out;            // [(degcap+1)][Lcap] result limbs
   int32_t Lcap, degcap;
+  const uint32_t* crt;      // explicit CRT constants of the job's prime count (CrtHost layout)
+  int32_t crt_LM;           // limbs of M = prod_{k<P} p_k
   int32_t* deg_out;         // highest non-zero coefficient index (init -1)
   int32_t* err;             // set non-zero on a failed internal check
 };
@@ -72,6 +75,7 @@ struct TablesDev {
   const uint32_t* pm;       // [K][K]: pm[k*K+j] = (p_j mod p_k) R mod p_k, j < k
   const uint32_t* pi;       // prod_{i<k} p_i as k+1 limbs at offset k(k+1)/2
   const uint32_t* invfact;  // [K][dmax]: Montgomery form of 1/n! mod p_k
+  const double* inv_p;      // [K]: 1 / p_k rounded to nearest
   int32_t K;
   int32_t dmax;
 };

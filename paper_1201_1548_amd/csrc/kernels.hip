@@ -16,6 +16,8 @@
 // each block to its job (binary search), so a single job is a batch of one.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "job.hpp"
 #include "kernels.hpp"
 
@@ -98,24 +100,31 @@ __device__ void dev_reduce(const JobDev& J, int lb, int k0, int k1, TablesDev ta
   const int T = isg ? J.Tg : J.Tf;
   const int t = (isg ? lb - nbf : lb) * 64 + threadIdx.x;
   if (t >= T || k0 >= J.P) return;
+  // residue t is coefficient (j, i) of its rectangle; i >= ld is row padding
+  const int lp = isg ? J.lpg : J.lpf;
+  const int ld = isg ? J.ldg : J.ldf;
+  const int j = t / lp, i = t - j * lp;
+  uint32_t* dst = (isg ? J.res_g : J.res_f) + t;
+  k1 = min(J.P, k1);
+  if (i >= ld) {
+    for (int k = k0; k < k1; ++k) dst[(size_t)k * T] = 0u;
+    return;
+  }
   const uint32_t* src;
   int L;
   uint32_t mult = 0;  // 0: none; else the derivative factor j+1
   if (!isg) {
-    src = J.limbs_f + (size_t)t * J.Lf;
+    src = J.limbs_f + ((size_t)j * J.ldf + i) * J.Lf;
     L = J.Lf;
   } else if (J.disc) {
-    int j = t / J.ldf;
-    src = J.limbs_f + (size_t)(t + J.ldf) * J.Lf;  // coefficient (j+1, i) of f
+    src = J.limbs_f + ((size_t)(j + 1) * J.ldf + i) * J.Lf;  // coefficient (j+1, i) of f
     L = J.Lf;
     mult = (uint32_t)(j + 1);
   } else {
-    src = J.limbs_g + (size_t)t * J.Lg;
+    src = J.limbs_g + ((size_t)j * J.ldg + i) * J.Lg;
     L = J.Lg;
   }
   const bool negv = (src[L - 1] >> 31) != 0u;
-  uint32_t* dst = (isg ? J.res_g : J.res_f) + t;
-  k1 = min(J.P, k1);
   for (int k = k0; k < k1; ++k) {
     const ModP q = tab.primes[k];
     uint32_t x = 0;
@@ -158,16 +167,53 @@ __device__ __forceinline__ int wave_uniform(int x) {
 // for a' = a, a-1, ..., b.  Afterwards A holds lc(B)^(a-b+1) (A mod B) in
 // its coefficients 0..b-1 (an elimination whose top coefficient is already
 // zero only scales A, which keeps that identity).  With wave-uniform a and b
-// every loop bound is a scalar.
+// every loop bound is a scalar.  A and B are disjoint.
+//
+// The usual step has a = b + 1: its two eliminations run as one pass.  The
+// second one's multiplier is the first one's new top coefficient
+// lc(B) A_{a-1} - A_a B_{b-1}, computed first; then each coefficient takes
+// A_t <- lc(B) (lc(B) A_t - A_a B_{t-1}) - A'_{a-1} B_t, so every A_t and B_t
+// is read once.
 template <int W>
-__device__ __forceinline__ void eliminate(uint32_t* A, const uint32_t* B, int a, int b, uint32_t lb,
-                                          const ModP& q) {
+__device__ __forceinline__ void eliminate(uint32_t* __restrict__ A, const uint32_t* __restrict__ B, int a, int b,
+                                          uint32_t lb, const ModP& q) {
+  if (a == b + 1) {
+    const uint32_t n1 = mneg(A[a * W], q.p);
+    const uint32_t n2 = mneg(mdot2(lb, A[(a - 1) * W], n1, B[(b - 1) * W], q), q.p);
+    uint32_t bp = B[0];
+    A[0] = mdot2(lb, mmul(lb, A[0], q), n2, bp, q);
+    int t = 1;
+    for (; t + 4 <= b; t += 4) {
+      const uint32_t x0 = A[t * W], x1 = A[(t + 1) * W], x2 = A[(t + 2) * W], x3 = A[(t + 3) * W];
+      const uint32_t y0 = B[t * W], y1 = B[(t + 1) * W], y2 = B[(t + 2) * W], y3 = B[(t + 3) * W];
+      A[t * W] = mdot2(lb, mdot2(lb, x0, n1, bp, q), n2, y0, q);
+      A[(t + 1) * W] = mdot2(lb, mdot2(lb, x1, n1, y0, q), n2, y1, q);
+      A[(t + 2) * W] = mdot2(lb, mdot2(lb, x2, n1, y1, q), n2, y2, q);
+      A[(t + 3) * W] = mdot2(lb, mdot2(lb, x3, n1, y2, q), n2, y3, q);
+      bp = y3;
+    }
+    for (; t < b; ++t) {
+      const uint32_t y = B[t * W];
+      A[t * W] = mdot2(lb, mdot2(lb, A[t * W], n1, bp, q), n2, y, q);
+      bp = y;
+    }
+    return;
+  }
   for (; a >= b; --a) {
     const uint32_t nla = mneg(A[a * W], q.p);
     const int s = a - b;
     for (int t = 0; t < s; ++t) A[t * W] = mmul(lb, A[t * W], q);
-#pragma unroll 4
-    for (int t = s; t < a; ++t) A[t * W] = mdot2(lb, A[t * W], nla, B[(t - s) * W], q);
+    int t = s;
+    for (; t + 4 <= a; t += 4) {
+      const uint32_t x0 = A[t * W], x1 = A[(t + 1) * W], x2 = A[(t + 2) * W], x3 = A[(t + 3) * W];
+      const uint32_t y0 = B[(t - s) * W], y1 = B[(t - s + 1) * W], y2 = B[(t - s + 2) * W],
+                     y3 = B[(t - s + 3) * W];
+      A[t * W] = mdot2(lb, x0, nla, y0, q);
+      A[(t + 1) * W] = mdot2(lb, x1, nla, y1, q);
+      A[(t + 2) * W] = mdot2(lb, x2, nla, y2, q);
+      A[(t + 3) * W] = mdot2(lb, x3, nla, y3, q);
+    }
+    for (; t < a; ++t) A[t * W] = mdot2(lb, A[t * W], nla, B[(t - s) * W], q);
   }
 }
 
@@ -226,66 +272,8 @@ __device__ uint32_t uni_resultant(uint32_t* A, uint32_t* B, int m, int n, const 
   return neg ? mneg(r, q.p) : r;
 }
 
-// (b)+(c): each job has P * ceil(D/W) blocks, prime-major; one lane per
-// point a.  The block stages the prime's residues and the row
-// degrees in LDS, then each lane evaluates f(a, y), g(a, y) by Horner's rule
-// into its own arrays and runs the elimination.
-template <int W>
-__device__ void dev_eval_elim(const JobDev& J, int lb, TablesDev tab, uint32_t* lds) {
-  const int nbpp = (J.D + W - 1) / W;
-  const int k = lb / nbpp;
-  const int a0 = (lb - k * nbpp) * W;
-  const int m = J.m, n = J.n;
-  const int Tf = J.Tf, Tg = J.Tg, ldf = J.ldf;
-  const int ldg = J.disc ? J.ldf : J.ldg;
-  uint32_t* R = lds;                                 // residues: f rows, then g rows
-  int32_t* RD = (int32_t*)(lds + Tf + Tg);           // row degrees: f, then g
-  uint32_t* A = lds + Tf + Tg + (m + n + 2) + threadIdx.x;
-  uint32_t* B = A + (m + 1) * W;
-  const uint32_t* rf = J.res_f + (size_t)k * Tf;
-  const uint32_t* rg = J.res_g + (size_t)k * Tg;
-  for (int i = threadIdx.x; i < Tf; i += W) R[i] = rf[i];
-  for (int i = threadIdx.x; i < Tg; i += W) R[Tf + i] = rg[i];
-  for (int i = threadIdx.x; i <= m; i += W) RD[i] = J.rowdeg_f[i];
-  for (int i = threadIdx.x; i <= n; i += W) RD[m + 1 + i] = J.rowdeg_g[i];
-  __syncthreads();
-  const int pt = a0 + (int)threadIdx.x;
-  if (pt >= J.D) return;
-  const ModP q = tab.primes[k];
-  const uint32_t aM = to_mont((uint32_t)pt, q);
-  for (int j = 0; j <= m; ++j) {
-    const uint32_t* row = R + j * ldf;
-    const int d = __builtin_amdgcn_readfirstlane(RD[j]);
-    uint32_t acc = 0;
-#pragma unroll 4
-    for (int i = d; i >= 0; --i) acc = madd(mmul(acc, aM, q), row[i], q.p);
-    A[j * W] = acc;
-  }
-  for (int j = 0; j <= n; ++j) {
-    const uint32_t* row = R + Tf + j * ldg;
-    const int d = __builtin_amdgcn_readfirstlane(RD[m + 1 + j]);
-    uint32_t acc = 0;
-#pragma unroll 4
-    for (int i = d; i >= 0; --i) acc = madd(mmul(acc, aM, q), row[i], q.p);
-    B[j * W] = acc;
-  }
-  const uint32_t r = uni_resultant<W>(A, B, m, n, q);
-  J.vals[(size_t)k * J.D + pt] = from_mont(r, q);
-}
-
-template <int W>
-__global__ __launch_bounds__(W) void k_eval_elim(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
-  extern __shared__ uint32_t lds[];
-  const int job = find_job(starts, nj, blockIdx.x);
-  dev_eval_elim<W>(jobs[job], blockIdx.x - starts[job], tab, lds);
-}
-
-// ---------------------------------------------------------------------------
-// (d) interpolation per prime on the nodes a = 0, 1, ..., D-1.
-//
-// Sums of products are accumulated exactly in 96 bits (four products of
-// values below 2^31 fit in 64 bits) and reduced once per output.
-
+// Exact sums of products of residues: 96 bits, four products of values below
+// 2^31 per 64-bit partial sum.
 struct Acc96 {
   uint64_t lo = 0;
   uint32_t hi = 0;
@@ -294,6 +282,118 @@ struct Acc96 {
     hi += lo < s ? 1u : 0u;
   }
 };
+
+// (b) evaluation at x = a.  With Montgomery residues c_M of a row and the
+// Montgomery powers (a^i)_M, S = sum_i c_M (a^i)_M is f_j(a) R^2 mod p; S is
+// summed exactly and one reduction turns it into f_j(a) R.  The powers live
+// in registers, so a coefficient costs one 32x32->64 multiply-add instead of
+// the three of a Montgomery Horner step, and the products do not form a
+// dependency chain.  Rows longer than EV_PW coefficients are cut into chunks
+// of EV_PW, combined by Horner's rule in a^EV_PW.
+constexpr int EV_PW = 24;
+
+// S R^{-1} mod p for S = hi 2^64 + lo with hi < 2^32 - 4 (here hi <= 5):
+// REDC(lo_lo + hi R^2) = lo_lo R^{-1} + hi R, and lo_hi R R^{-1} = lo_hi.
+// The REDC argument is below p 2^32, so its result is below 2p.
+__device__ __forceinline__ uint32_t fold96(const Acc96& S, const ModP& q) {
+  const uint64_t t = (uint64_t)S.hi * q.r2 + (uint32_t)S.lo;
+  return madd(redc(t, q.p, q.pinv), reduce32((uint32_t)(S.lo >> 32), q.p), q.p);
+}
+
+// Value of the row c[0..d] (zero-padded to a multiple of 4, 16-byte aligned)
+// at the point whose powers are pw; apw = (a^EV_PW)_M.  d is wave-uniform.
+__device__ __forceinline__ uint32_t eval_row(const uint32_t* c, int d, const uint32_t (&pw)[EV_PW], uint32_t apw,
+                                             const ModP& q) {
+  if (d < 0) return 0u;
+  const int top = d / EV_PW;
+  uint32_t acc = 0u;
+  for (int ch = top; ch >= 0; --ch) {
+    const uint4* cc = (const uint4*)(c + ch * EV_PW);
+    const int ng = (min(EV_PW, d + 1 - ch * EV_PW) + 3) >> 2;
+    Acc96 S;
+#pragma unroll
+    for (int g = 0; g < EV_PW / 4; ++g) {
+      if (g < ng) {
+        const uint4 v = cc[g];
+        uint64_t t = (uint64_t)v.x * pw[4 * g];
+        t += (uint64_t)v.y * pw[4 * g + 1];
+        t += (uint64_t)v.z * pw[4 * g + 2];
+        t += (uint64_t)v.w * pw[4 * g + 3];
+        S.add(t);
+      }
+    }
+    const uint32_t r = fold96(S, q);
+    acc = ch == top ? r : madd(mmul(acc, apw, q), r, q.p);
+  }
+  return acc;
+}
+
+// (b)+(c): each job has P * ceil(D/W) blocks, prime-major; one lane per
+// point a.  The block stages the prime's residues (rows at the padded
+// strides lpf, lpg) and the row degrees in LDS; each lane evaluates f(a, y),
+// g(a, y) into its own arrays and runs the elimination.  lds must be 16-byte
+// aligned.
+template <int W>
+__device__ __forceinline__ void dev_eval_elim(const JobDev& J, int lb, TablesDev tab, uint32_t* lds) {
+  const int nbpp = (J.D + W - 1) / W;
+  const int k = lb / nbpp;
+  const int a0 = (lb - k * nbpp) * W;
+  const int m = J.m, n = J.n;
+  const int Tf = J.Tf, Tg = J.Tg, lpf = J.lpf, lpg = J.lpg;
+  uint32_t* R = lds;                                 // residues: f rows, then g rows
+  int32_t* RD = (int32_t*)(lds + Tf + Tg);           // row degrees: f, then g
+  uint32_t* A = lds + Tf + Tg + (m + n + 2) + threadIdx.x;
+  uint32_t* B = A + (m + 1) * W;
+  const uint4* rf = (const uint4*)(J.res_f + (size_t)k * Tf);
+  const uint4* rg = (const uint4*)(J.res_g + (size_t)k * Tg);
+  uint4* R4 = (uint4*)R;
+  for (int i = threadIdx.x; i < Tf / 4; i += W) R4[i] = rf[i];
+  for (int i = threadIdx.x; i < Tg / 4; i += W) R4[Tf / 4 + i] = rg[i];
+  for (int i = threadIdx.x; i <= m; i += W) RD[i] = J.rowdeg_f[i];
+  for (int i = threadIdx.x; i <= n; i += W) RD[m + 1 + i] = J.rowdeg_g[i];
+  __syncthreads();
+  const int pt = a0 + (int)threadIdx.x;
+  if (pt >= J.D) return;
+  const ModP q = tab.primes[k];
+  const uint32_t aM = to_mont((uint32_t)pt, q);
+  const int dmax = max(J.ldf, J.disc ? J.ldf : J.ldg) - 1;
+  uint32_t pw[EV_PW];
+  pw[0] = q.one;
+#pragma unroll
+  for (int i = 1; i < EV_PW; ++i) pw[i] = i <= dmax ? mmul(pw[i - 1], aM, q) : 0u;
+  const uint32_t apw = dmax >= EV_PW ? mmul(pw[EV_PW - 1], aM, q) : 0u;
+  for (int j = 0; j <= m; ++j)
+    A[j * W] = eval_row(R + j * lpf, __builtin_amdgcn_readfirstlane(RD[j]), pw, apw, q);
+  for (int j = 0; j <= n; ++j)
+    B[j * W] = eval_row(R + Tf + j * lpg, __builtin_amdgcn_readfirstlane(RD[m + 1 + j]), pw, apw, q);
+  const uint32_t r = uni_resultant<W>(A, B, m, n, q);
+  J.vals[(size_t)k * J.D + pt] = from_mont(r, q);
+}
+
+// Workgroups are dispatched to the 8 XCDs round-robin in blockIdx order, and
+// each XCD has its own L2.  This bijection of [0, nb) gives XCD x the
+// contiguous logical range [x q + min(x, r), ...) of q + (x < r) blocks
+// (q = nb / 8, r = nb % 8), so the blocks of one (job, prime), which share
+// that prime's residues, run on one XCD and share its L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+template <int W>
+__global__ __launch_bounds__(W) void k_eval_elim(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int job = find_job(starts, nj, b);
+  dev_eval_elim<W>(jobs[job], b - starts[job], tab, lds);
+}
+
+// ---------------------------------------------------------------------------
+// (d) interpolation per prime on the nodes a = 0, 1, ..., D-1.
+//
+// Sums of products are accumulated exactly in 96 bits (four products of
+// values below 2^31 fit in 64 bits) and reduced once per output.
+
 
 // The 96-bit sum reduced modulo p (plain result).
 __device__ __forceinline__ uint32_t reduce96(const Acc96& A, const ModP& q, uint32_t r3) {
@@ -412,12 +512,168 @@ __device__ void dev_interp(const JobDev& J, int k, TablesDev tab, uint32_t* lds)
 }
 
 __global__ __launch_bounds__(256) void k_interp(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   const int job = find_job(starts, nj, blockIdx.x);
   dev_interp(jobs[job], blockIdx.x - starts[job], tab, lds);
 }
 
 size_t interp_lds_words(int D) { return (size_t)3 * D + (size_t)((D + KB - 1) / KB) * (2 * KB + 1); }
+
+// (d) interpolation of a batch whose jobs share D and P, on the int8 matrix
+// cores.  With nodes 0..D-1 the coefficients are C = V^{-1} Y (one column of
+// Y per job, V the Vandermonde matrix), a dense product per prime.
+//
+// V^{-1} mod p is built once per (D, P) by synthetic division: column a holds
+// the coefficients of N(x) / (x - a) times 1 / N'(a), N = prod_b (x - b),
+// N'(a) = (-1)^(D-1-a) a! (D-1-a)!.  Every residue is stored as four balanced
+// base-256 digits of its symmetric representative (int8; |x| < 2^30, so the
+// top digit lies in [-64, 64]); then C = sum_{s,t} 256^(s+t) A_s Y_t, and the
+// 16 int8 products v_mfma_i32_32x32x32_i8 are summed into 7 int32
+// accumulators by weight u = s + t (|G_u| <= 4 Dp 2^14 < 2^31 for Dp < 2^15).
+// The epilogue reduces sum_u G_u 256^u mod p.  Matrices are stored per prime
+// and digit plane, row-major with the contraction index contiguous and padded
+// to Dp (a multiple of 32) with zeros, so a lane's 16 operand bytes are one
+// aligned 16-byte load.
+
+typedef int im_v4i __attribute__((ext_vector_type(4)));
+typedef int im_v16i __attribute__((ext_vector_type(16)));
+
+// The four balanced base-256 digits of the symmetric representative of x mod p,
+// packed little-endian into one word.
+__device__ __forceinline__ uint32_t digits4(uint32_t x, uint32_t p) {
+  int32_t v = x > (p >> 1) ? (int32_t)(x - p) : (int32_t)x;
+  uint32_t out = 0;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int32_t r = ((v + 128) & 255) - 128;
+    out |= (uint32_t)(r & 255) << (8 * s);
+    v = (v - r) >> 8;
+  }
+  return out | ((uint32_t)(v & 255) << 24);
+}
+
+__device__ __forceinline__ void put_digits(int8_t* base, size_t plane, size_t off, uint32_t d) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) base[s * plane + off] = (int8_t)(d >> (8 * s));
+}
+
+// V^{-1} mod p_k for k = blockIdx.x: Ap[k][s][i][a] (s: digit, i: coefficient,
+// a: node), Dp x Dp per plane, zero outside [0, D)^2.  LDS: 2 (D + 1) words.
+__global__ __launch_bounds__(256) void k_vinv(int D, int Dp, TablesDev tab, int8_t* Ap) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const int k = blockIdx.x;
+  const ModP q = tab.primes[k];
+  uint32_t* cur = lds;
+  uint32_t* nxt = lds + D + 1;
+  for (int j = threadIdx.x; j <= D; j += blockDim.x) cur[j] = j == 0 ? q.one : 0u;
+  __syncthreads();
+  for (int b = 0; b < D; ++b) {  // cur has degree b: cur <- cur (x - b)
+    const uint32_t bM = to_mont((uint32_t)b, q);
+    for (int j = threadIdx.x; j <= b + 1; j += blockDim.x) {
+      const uint32_t lo = j ? cur[j - 1] : 0u;
+      const uint32_t hi = j <= b ? mmul(bM, cur[j], q) : 0u;
+      nxt[j] = msub(lo, hi, q.p);
+    }
+    __syncthreads();
+    uint32_t* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  const size_t plane = (size_t)Dp * Dp;
+  int8_t* base = Ap + (size_t)k * 4 * plane;
+  const uint32_t* invf = tab.invfact + (size_t)k * tab.dmax;
+  for (int a = threadIdx.x; a < Dp; a += blockDim.x) {
+    if (a >= D) {
+      for (int i = 0; i < Dp; ++i) put_digits(base, plane, (size_t)i * Dp + a, 0u);
+      continue;
+    }
+    uint32_t w = mmul(invf[a], invf[D - 1 - a], q);
+    if ((D - 1 - a) & 1) w = mneg(w, q.p);
+    const uint32_t aM = to_mont((uint32_t)a, q);
+    uint32_t qj = cur[D];  // q_{D-1} = leading coefficient of N
+    for (int j = D - 1; j >= 0; --j) {
+      put_digits(base, plane, (size_t)j * Dp + a, digits4(from_mont(mmul(w, qj, q), q), q.p));
+      if (j) qj = madd(cur[j], mmul(aM, qj, q), q.p);  // q_{j-1} = n_j + a q_j
+    }
+    for (int i = D; i < Dp; ++i) put_digits(base, plane, (size_t)i * Dp + a, 0u);
+  }
+}
+
+// Digit planes of the values: Yp[k][t][n][a] for the group's jobs gj[0..N),
+// zero for n >= N or a >= D.  Grid (Np, P), 256 threads over a.
+__global__ __launch_bounds__(256) void k_yplanes(const JobDev* jobs, const int* gj, int N, int Np, int D, int Dp,
+                                                 TablesDev tab, int8_t* Yp) {
+  const int n = blockIdx.x, k = blockIdx.y;
+  const uint32_t p = tab.primes[k].p;
+  const size_t plane = (size_t)Np * Dp;
+  int8_t* base = Yp + (size_t)k * 4 * plane + (size_t)n * Dp;
+  const uint32_t* v = n < N ? jobs[gj[n]].vals + (size_t)k * D : nullptr;
+  for (int a = threadIdx.x; a < Dp; a += blockDim.x) put_digits(base, plane, a, v && a < D ? digits4(v[a], p) : 0u);
+}
+
+// One wave per 32 x 32 tile of C for prime k: grid (Dp/32, Np/32, P).
+// Accumulator register r of lane l holds row 8 (r/4) + 4 (l/32) + r%4 and
+// column l%32 of the tile; operand lanes hold row (A) or column (Y) l%32 and
+// contraction indices 16 (l/32) + 0..15 of the 32-wide step.
+__global__ __launch_bounds__(64) void k_interp_mfma(const JobDev* jobs, const int* gj, int N, int Np, int D, int Dp,
+                                                    const int8_t* Ap, const int8_t* Yp, TablesDev tab) {
+  const int l = threadIdx.x, r32 = l & 31, g = l >> 5;
+  const int i0 = blockIdx.x * 32, n0 = blockIdx.y * 32, k = blockIdx.z;
+  const size_t pa = (size_t)Dp * Dp, py = (size_t)Np * Dp;
+  const int8_t* A = Ap + (size_t)k * 4 * pa + (size_t)(i0 + r32) * Dp + 16 * g;
+  const int8_t* Y = Yp + (size_t)k * 4 * py + (size_t)(n0 + r32) * Dp + 16 * g;
+  im_v16i G0 = {0}, G1 = {0}, G2 = {0}, G3 = {0}, G4 = {0}, G5 = {0}, G6 = {0};
+  for (int a0 = 0; a0 < Dp; a0 += 32) {
+    const im_v4i a_0 = *(const im_v4i*)(A + a0), a_1 = *(const im_v4i*)(A + pa + a0);
+    const im_v4i a_2 = *(const im_v4i*)(A + 2 * pa + a0), a_3 = *(const im_v4i*)(A + 3 * pa + a0);
+    const im_v4i y_0 = *(const im_v4i*)(Y + a0), y_1 = *(const im_v4i*)(Y + py + a0);
+    const im_v4i y_2 = *(const im_v4i*)(Y + 2 * py + a0), y_3 = *(const im_v4i*)(Y + 3 * py + a0);
+    G0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_0, y_0, G0, 0, 0, 0);
+    G1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_0, y_1, G1, 0, 0, 0);
+    G1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_1, y_0, G1, 0, 0, 0);
+    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_0, y_2, G2, 0, 0, 0);
+    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_1, y_1, G2, 0, 0, 0);
+    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_2, y_0, G2, 0, 0, 0);
+    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_0, y_3, G3, 0, 0, 0);
+    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_1, y_2, G3, 0, 0, 0);
+    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_2, y_1, G3, 0, 0, 0);
+    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_3, y_0, G3, 0, 0, 0);
+    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_1, y_3, G4, 0, 0, 0);
+    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_2, y_2, G4, 0, 0, 0);
+    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_3, y_1, G4, 0, 0, 0);
+    G5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_2, y_3, G5, 0, 0, 0);
+    G5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_3, y_2, G5, 0, 0, 0);
+    G6 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_3, y_3, G6, 0, 0, 0);
+  }
+  const int n = n0 + r32;
+  if (n >= N) return;
+  const JobDev& J = jobs[gj[n]];
+  if (k >= J.P) return;
+  const ModP q = tab.primes[k];
+  uint32_t w[7];  // Montgomery forms of 256^u
+  w[0] = q.one;
+  const uint32_t m256 = to_mont(256u, q);
+#pragma unroll
+  for (int u = 1; u < 7; ++u) w[u] = mmul(w[u - 1], m256, q);
+  uint32_t* out = J.coefs + (size_t)k * D;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = i0 + 8 * (r >> 2) + 4 * g + (r & 3);
+    const int32_t gv[7] = {G0[r], G1[r], G2[r], G3[r], G4[r], G5[r], G6[r]};
+    Acc96 S;
+    uint64_t t = 0;
+#pragma unroll
+    for (int u = 0; u < 7; ++u) {
+      const uint32_t res = gv[u] < 0 ? (uint32_t)(gv[u] + (int32_t)q.p) : (uint32_t)gv[u];
+      t += (uint64_t)res * w[u];
+      if (u == 3 || u == 6) {
+        S.add(t);
+        t = 0;
+      }
+    }
+    if (i < D) out[i] = fold96(S, q);
+  }
+}
 
 // Inverse factorials per prime: invfact[k][n] = Montgomery form of 1/n!.
 // One thread per prime: prefix products, one Fermat inverse, backward products.
@@ -485,7 +741,7 @@ __device__ void dev_mrc_lane(const JobDev& J, int lb, TablesDev tab, uint32_t* l
 }
 
 __global__ __launch_bounds__(64) void k_mrc_lane(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   const int job = find_job(starts, nj, blockIdx.x);
   dev_mrc_lane(jobs[job], blockIdx.x - starts[job], tab, lds);
 }
@@ -525,7 +781,7 @@ __device__ void dev_mrc_wave(const JobDev& J, int c, TablesDev tab, uint32_t* ld
 }
 
 __global__ __launch_bounds__(64) void k_mrc(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   const int job = find_job(starts, nj, blockIdx.x);
   dev_mrc_wave(jobs[job], blockIdx.x - starts[job], tab, lds);
 }
@@ -615,9 +871,116 @@ __device__ void dev_limbs_carry(const JobDev& J, int lb, int stage_ld, uint32_t*
 }
 
 __global__ __launch_bounds__(64) void k_limbs_carry(const JobDev* jobs, const int* starts, int nj, int stage_ld) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   const int job = find_job(starts, nj, blockIdx.x);
   dev_limbs_carry(jobs[job], blockIdx.x - starts[job], stage_ld, lds);
+}
+
+// (e) explicit CRT, one block of 256 threads per 64 output coefficients.
+// With M = prod_{k<P} p_k, M_k = M / p_k and w_k = M_k^{-1} mod p_k, the
+// integer X = sum_k y_k M_k, y_k = x_k w_k mod p_k, is congruent to the
+// coefficient modulo every p_k, and X / M = sum_k y_k / p_k.  The planner
+// takes M > 2^1.001 B (B the coefficient bound), so the coefficient is
+// X - t M with t the integer nearest to sum_k y_k / p_k; fp64 gives that sum
+// within P 2^-52, far inside the margin of more than 3e-4 to a half-integer.
+// Limb l of X - t M is the signed column sum
+// S_l = sum_k y_k limb_l(M_k) - t limb_l(M) plus the carry out of limb l-1.
+// The columns are independent, so all four waves form them (limbs l = wave,
+// wave + 4, ...); one lane per coefficient then propagates the carries.
+// Nothing is serial in the prime index, unlike Garner's digits.
+constexpr int CRT_MAXP = 128;
+
+__device__ void dev_crt(const JobDev& J, int lb, int stage_ld, TablesDev tab, uint32_t* lds) {
+  const int P = J.P, D = J.D, Lc = J.Lcap, LM = J.crt_LM;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c0 = lb * 64, c = c0 + lane;
+  const uint32_t* w = J.crt;
+  const uint32_t* Mk = J.crt + P;
+  const uint32_t* M = Mk + (size_t)P * LM;
+  const int ny = max(P, stage_ld);
+  uint32_t* Y = lds;                               // [P][64] y_k; then the output staging rows
+  int32_t* Tq = (int32_t*)(lds + ny * 64);         // [64] nearest integers t
+  uint32_t* S0 = lds + ny * 64 + 64;               // [LM][64] column sums: bits 0-31,
+  uint32_t* S1 = S0 + LM * 64;                     //   32-63,
+  int32_t* S2 = (int32_t*)(S1 + LM * 64);          //   64-95 (signed)
+  for (int k = wave; k < P; k += 4)
+    Y[k * 64 + lane] = c < D ? mmul(J.coefs[(size_t)k * D + c], w[k], tab.primes[k]) : 0u;
+  __syncthreads();
+  if (wave == 0) {
+    double f = 0.0;
+    for (int k = 0; k < P; ++k) f = fma((double)Y[k * 64 + lane], tab.inv_p[k], f);
+    Tq[lane] = (int32_t)(f + 0.5);
+  }
+  __syncthreads();
+  const uint64_t t = (uint64_t)Tq[lane];
+  for (int l = wave; l < LM; l += 4) {
+    uint64_t lo = 0;
+    uint32_t hi = 0;
+    const uint32_t* col = Mk + l;
+    for (int k = 0; k < P; ++k) {
+      const uint64_t pr = (uint64_t)Y[k * 64 + lane] * col[(size_t)k * LM];
+      lo += pr;
+      hi += lo < pr ? 1u : 0u;
+    }
+    const uint64_t sub = t * M[l];
+    hi -= lo < sub ? 1u : 0u;
+    lo -= sub;
+    S0[l * 64 + lane] = (uint32_t)lo;
+    S1[l * 64 + lane] = (uint32_t)(lo >> 32);
+    S2[l * 64 + lane] = (int32_t)hi;
+  }
+  __syncthreads();
+  const bool staged = stage_ld > 0;
+  if (wave == 0 && c <= J.degcap) {
+    uint32_t* o = staged ? Y + lane * stage_ld : J.out + (size_t)c * Lc;
+    if (c >= D) {
+      for (int l = 0; l < Lc; ++l) o[l] = 0u;
+    } else {
+      // v = S_l + carry as (hi:lo) 96-bit two's complement; carry = v >> 32 (arithmetic)
+      int64_t carry = 0;
+      bool nz = false, bad = false;
+      uint32_t last = 0;
+      const int Lrun = max(Lc, LM);
+      for (int l = 0; l < Lrun; ++l) {
+        uint64_t lo = 0;
+        int32_t hi = 0;
+        if (l < LM) {
+          lo = (uint64_t)S0[l * 64 + lane] | ((uint64_t)S1[l * 64 + lane] << 32);
+          hi = S2[l * 64 + lane];
+        }
+        const uint64_t add = (uint64_t)carry;
+        const uint64_t lo2 = lo + add;
+        hi += (carry < 0 ? -1 : 0) + (lo2 < lo ? 1 : 0);
+        const uint32_t limb = (uint32_t)lo2;
+        carry = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (lo2 >> 32));
+        if (l < Lc) {
+          o[l] = limb;
+          nz |= limb != 0u;
+          last = limb;
+        } else if (limb != ((int32_t)last < 0 ? 0xFFFFFFFFu : 0u)) {
+          bad = true;
+        }
+      }
+      if (bad || carry != ((int32_t)last < 0 ? -1 : 0)) atomicOr(J.err, 1);
+      if (nz) atomicMax(J.deg_out, c);
+    }
+  }
+  if (staged) {
+    __syncthreads();
+    const int nc = min(64, J.degcap + 1 - c0);
+    uint32_t* dst = J.out + (size_t)c0 * Lc;
+    for (int i = threadIdx.x; i < nc * Lc; i += blockDim.x) {
+      const int r = i / Lc;
+      dst[i] = Y[r * stage_ld + (i - r * Lc)];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_crt(const JobDev* jobs, const int* starts, int nj, int stage_ld,
+                                             TablesDev tab) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const int job = find_job(starts, nj, blockIdx.x);
+  dev_crt(jobs[job], blockIdx.x - starts[job], stage_ld, tab, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -633,7 +996,7 @@ __global__ __launch_bounds__(64) void k_limbs_carry(const JobDev* jobs, const in
 enum { FS_RED = 0, FS_EE, FS_IP, FS_MRC, FS_SUM, FS_CAR };
 
 __global__ __launch_bounds__(64) void k_fused(FusedPlan F, TablesDev tab) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ int s_task;
   for (;;) {
     if (threadIdx.x == 0) s_task = atomicAdd(F.head, 1);
@@ -720,7 +1083,7 @@ void launch_fused(const FusedPlan& F, size_t lds_bytes, int blocks, TablesDev ta
 // (lc b / beta) b/g, whose images multiply to lc(a) a and lc(b) b.
 
 __global__ __launch_bounds__(256) void k_gcd_p(GcdDev G, TablesDev tab) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   const int k = blockIdx.x;
   const ModP q = tab.primes[k];
   const int da = G.da, db = G.db;
@@ -861,6 +1224,19 @@ void launch_interp(const JobDev* jobs, const int* starts, int nj, int nblocks, i
   hipLaunchKernelGGL(k_interp, dim3(nblocks), dim3(256), lds, s, jobs, starts, nj, tab);
 }
 
+size_t vinv_bytes(int Dp, int P) { return (size_t)4 * Dp * Dp * P; }
+
+void launch_vinv(int D, int Dp, int P, TablesDev tab, int8_t* Ap, hipStream_t s) {
+  hipLaunchKernelGGL(k_vinv, dim3(P), dim3(256), (size_t)2 * (D + 1) * sizeof(uint32_t), s, D, Dp, tab, Ap);
+}
+
+void launch_interp_mfma(const JobDev* jobs, const int* gj, int N, int D, int P, const int8_t* Ap, int8_t* Yp,
+                        TablesDev tab, hipStream_t s) {
+  const int Dp = (D + 31) & ~31, Np = (N + 31) & ~31;
+  hipLaunchKernelGGL(k_yplanes, dim3(Np, P), dim3(256), 0, s, jobs, gj, N, Np, D, Dp, tab, Yp);
+  hipLaunchKernelGGL(k_interp_mfma, dim3(Dp / 32, Np / 32, P), dim3(64), 0, s, jobs, gj, N, Np, D, Dp, Ap, Yp, tab);
+}
+
 bool mrc_lane_ok(int max_primes, long long total_coefficients) {
   // one lane per coefficient needs enough coefficients to fill the device;
   // otherwise one wave per coefficient has the shorter critical path
@@ -876,6 +1252,20 @@ void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int 
     hipLaunchKernelGGL(k_mrc, dim3(nblocks), dim3(64), (size_t)2 * max_primes * sizeof(uint32_t), s, jobs, starts,
                        nj, tab);
   }
+}
+
+bool crt_ok(int max_primes) { return max_primes <= CRT_MAXP; }
+
+size_t crt_lds_bytes(int max_primes, int max_lm, int max_lcap) {
+  const int stage_ld = max_lcap <= CARRY_STAGE_MAXL ? max_lcap + 1 : 0;
+  return ((size_t)64 * std::max(max_primes, stage_ld) + 64 + (size_t)3 * 64 * max_lm) * sizeof(uint32_t);
+}
+
+void launch_crt(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, int max_lm, int max_lcap,
+                TablesDev tab, hipStream_t s) {
+  const int stage_ld = max_lcap <= CARRY_STAGE_MAXL ? max_lcap + 1 : 0;
+  hipLaunchKernelGGL(k_crt, dim3(nblocks), dim3(256), crt_lds_bytes(max_primes, max_lm, max_lcap), s, jobs, starts,
+                     nj, stage_ld, tab);
 }
 
 void launch_limbs_sum(const JobDev* jobs, const int* starts, int nj, int nblocks, TablesDev tab, hipStream_t s) {

@@ -23,19 +23,37 @@ void launch_transpose(const uint32_t* src, uint32_t* dst, int rows, int cols, in
 void launch_reduce(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, TablesDev tab,
                    hipStream_t s);
 int eval_elim_block();
-// max_words: max over jobs of m+n+2; max_res: max over jobs of Tf+Tg.
+// Residue rows are stored at a stride rounded up to a multiple of 4 words so
+// the evaluation reads them as aligned 16-byte groups.
+inline int pad4(int ld) { return (ld + 3) & ~3; }
+// max_words: max over jobs of m+n+2; max_res: max over jobs of Tf+Tg (padded).
 size_t eval_elim_lds_bytes(int words, int res);
 void launch_eval_elim(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_words, int max_res,
                       TablesDev tab, hipStream_t s);
 void launch_interp(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_points, TablesDev tab,
                    hipStream_t s);
 size_t interp_lds_words(int D);
+// Interpolation of N jobs sharing D and P (job indices gj[0..N)) as int8
+// matrix-core products with V^{-1}: Ap = vinv_bytes(Dp, P) bytes built by
+// launch_vinv (Dp = D rounded up to 32); Yp = 4 Np Dp P bytes of workspace
+// (Np = N rounded up to 32).  Writes the jobs' coefs.
+size_t vinv_bytes(int Dp, int P);
+void launch_vinv(int D, int Dp, int P, TablesDev tab, int8_t* Ap, hipStream_t s);
+void launch_interp_mfma(const JobDev* jobs, const int* gj, int N, int D, int P, const int8_t* Ap, int8_t* Yp,
+                        TablesDev tab, hipStream_t s);
 void launch_invfact(const ModP* primes, int K, uint32_t* invfact, int dmax, hipStream_t s);
 // mrc blocks per job: ceil(D/64) with lane = true (one lane per coefficient,
 // allowed when mrc_lane_ok), else D (one wave per coefficient).
 bool mrc_lane_ok(int max_primes, long long total_coefficients);
 void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, bool lane, TablesDev tab,
                 hipStream_t s);
+// Explicit CRT straight to limbs (dev_crt): blocks of 256 threads, 64 output
+// coefficients each, ceil((degcap+1)/64) per job; needs crt_ok(max primes),
+// the jobs' crt tables and crt_lds_bytes within the LDS per block.
+bool crt_ok(int max_primes);
+size_t crt_lds_bytes(int max_primes, int max_lm, int max_lcap);
+void launch_crt(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, int max_lm, int max_lcap,
+                TablesDev tab, hipStream_t s);
 void launch_limbs_sum(const JobDev* jobs, const int* starts, int nj, int nblocks, TablesDev tab, hipStream_t s);
 // Persistent fused launch (see FusedPlan): blocks that fit on the device at
 // once for this LDS size, capped at the task count (0 on a runtime error).

@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "../../include/bires.h"
 #include "tables.hpp"
@@ -37,62 +38,69 @@ static int bitlen_abs(const uint32_t* c, int L, bool* nonzero) {
 
 RowStats scan_host(const uint32_t* limbs, int rows, int ld, int L) {
   RowStats s;
-  s.deg.assign(rows, -1);
-  s.bits.assign(rows, 0);
-  s.cnt.assign(rows, 0);
+  s.resize(rows);
   for (int j = 0; j < rows; ++j) {
+    int deg = -1, bits = 0, cnt = 0;
     for (int i = 0; i < ld; ++i) {
       bool nz;
       const int b = bitlen_abs(limbs + ((size_t)j * ld + i) * L, L, &nz);
       if (nz) {
-        s.deg[j] = i;
-        s.cnt[j]++;
-        s.bits[j] = std::max(s.bits[j], b);
+        deg = i;
+        cnt++;
+        bits = std::max(bits, b);
       }
     }
+    s.set(j, deg, bits, cnt);
   }
   return s;
 }
 
 RowStats derive_stats(const RowStats& f) {
   RowStats g;
-  const int rows = (int)f.deg.size() - 1;
+  const int rows = f.rows() - 1;
   if (rows <= 0) return g;
-  g.deg.resize(rows);
-  g.bits.resize(rows);
-  g.cnt.resize(rows);
+  g.resize(rows);
   for (int j = 0; j < rows; ++j) {
-    g.deg[j] = f.deg[j + 1];
-    g.cnt[j] = f.cnt[j + 1];
     const int lj = 32 - __builtin_clz((uint32_t)(j + 1));  // (j+1) < 2^lj
-    g.bits[j] = f.cnt[j + 1] ? f.bits[j + 1] + lj : 0;
+    g.set(j, f.deg(j + 1), f.cnt(j + 1) ? f.bits(j + 1) + lj : 0, f.cnt(j + 1));
   }
   return g;
 }
 
 RowStats worst_stats(int rows, int ld, int L) {
   RowStats s;
-  s.deg.assign(rows, ld - 1);
-  s.bits.assign(rows, 32 * L);
-  s.cnt.assign(rows, ld);
+  s.resize(rows);
+  for (int j = 0; j < rows; ++j) s.set(j, ld - 1, 32 * L, ld);
   return s;
 }
 
 static int top_row(const RowStats& s) {
-  for (int j = (int)s.deg.size() - 1; j >= 0; --j)
-    if (s.cnt[j] > 0) return j;
+  for (int j = s.rows() - 1; j >= 0; --j)
+    if (s.cnt(j) > 0) return j;
   return -1;
 }
 
-// log2 (sum_j N_j^2) with N_j <= cnt_j 2^bits_j, rows 0..top.
+// 2^e for e <= 0 as a double (0 below the normal range).
+static double pow2_nonpos(int e) {
+  if (e < -1022) return 0.0;
+  const uint64_t rep = (uint64_t)(e + 1023) << 52;
+  double d;
+  std::memcpy(&d, &rep, sizeof d);
+  return d;
+}
+
+// log2 (sum_j N_j^2) with N_j <= cnt_j 2^bits_j, rows 0..top: the terms
+// cnt_j^2 4^(bits_j - bmax) are exact in double (cnt_j^2 < 2^53, power-of-two
+// scaling; a term below 2^-1022 of the largest one is dropped, far inside the
+// margin of hadamard_log2), so one log2 per call remains.
 static double log2_sum_sq(const RowStats& s, int top) {
-  double emax = -1e300;
+  int bmax = 0;
   for (int j = 0; j <= top; ++j)
-    if (s.cnt[j]) emax = std::max(emax, std::log2((double)s.cnt[j]) + s.bits[j]);
+    if (s.cnt(j)) bmax = std::max(bmax, (int)s.bits(j));
   double acc = 0.0;
   for (int j = 0; j <= top; ++j)
-    if (s.cnt[j]) acc += std::exp2(2.0 * (std::log2((double)s.cnt[j]) + s.bits[j] - emax));
-  return 2.0 * emax + std::log2(acc);
+    if (s.cnt(j)) acc += (double)s.cnt(j) * (double)s.cnt(j) * pow2_nonpos(2 * (s.bits(j) - bmax));
+  return 2.0 * bmax + std::log2(acc);
 }
 
 double hadamard_log2(const RowStats& f, int m, const RowStats& g, int n) {
@@ -119,12 +127,12 @@ int make_plan(const RowStats& f, const RowStats& g, Plan& pl) {
   }
   if (pl.m > BIRES_MAX_YDEG || pl.n > BIRES_MAX_YDEG) return BIRES_ETOOBIG;
   for (int j = 0; j <= pl.m; ++j) {
-    pl.dxf = std::max(pl.dxf, f.deg[j]);
-    if (f.deg[j] >= 0) pl.tf = std::max(pl.tf, f.deg[j] + j);
+    pl.dxf = std::max(pl.dxf, f.deg(j));
+    if (f.deg(j) >= 0) pl.tf = std::max(pl.tf, f.deg(j) + j);
   }
   for (int j = 0; j <= pl.n; ++j) {
-    pl.dxg = std::max(pl.dxg, g.deg[j]);
-    if (g.deg[j] >= 0) pl.tg = std::max(pl.tg, g.deg[j] + j);
+    pl.dxg = std::max(pl.dxg, g.deg(j));
+    if (g.deg(j) >= 0) pl.tg = std::max(pl.tg, g.deg(j) + j);
   }
   const long long b1 = (long long)pl.n * pl.dxf + (long long)pl.m * pl.dxg;
   const long long b2 = (long long)pl.n * pl.tf + (long long)pl.m * pl.tg - (long long)pl.m * pl.n;
@@ -133,7 +141,9 @@ int make_plan(const RowStats& f, const RowStats& g, Plan& pl) {
   pl.D = (int)bound + 1;
   pl.log2B = hadamard_log2(f, pl.m, g, pl.n);
   const HostTables& t = host_tables();
-  const double need = pl.log2B + 1.0;  // M > 2B
+  // M > 2^1.001 B: the symmetric residue then sits at least 3e-4 M away from
+  // +-M/2, which the explicit CRT's fp64 rounding relies on
+  const double need = pl.log2B + 1.001;
   int P = 1;
   while (P <= t.K && t.cumlog[P] <= need) ++P;
   if (P > t.K) return BIRES_ETOOBIG;

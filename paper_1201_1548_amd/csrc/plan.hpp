@@ -1,6 +1,7 @@
 // Job planning on the host: true degrees, degree bound (number of evaluation
 // points) and Hadamard coefficient bound (number of primes).
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 #include <vector>
@@ -9,9 +10,19 @@ namespace bires {
 
 // Per-row statistics of a bivariate input (rows = powers of the eliminated
 // variable): x-degree (-1 for a zero row), bit length bound of |c| (|c| < 2^bits)
-// and non-zero count.
+// and non-zero count, interleaved per row as the device scan writes them.
 struct RowStats {
-  std::vector<int32_t> deg, bits, cnt;
+  std::vector<int32_t> v;  // [rows][3]: deg, bits, cnt
+  int rows() const { return (int)(v.size() / 3); }
+  int32_t deg(int j) const { return v[3 * j]; }
+  int32_t bits(int j) const { return v[3 * j + 1]; }
+  int32_t cnt(int j) const { return v[3 * j + 2]; }
+  void resize(int rows) { v.assign((size_t)3 * rows, 0); }
+  void set(int j, int32_t d, int32_t b, int32_t c) {
+    v[3 * j] = d;
+    v[3 * j + 1] = b;
+    v[3 * j + 2] = c;
+  }
 };
 
 struct Plan {

@@ -109,6 +109,34 @@ void mrc_tables(const std::vector<ModP>& primes, std::vector<uint32_t>& gm, std:
   }
 }
 
+CrtHost crt_tables(int P) {
+  const HostTables& t = host_tables();
+  CrtHost c;
+  c.P = P;
+  std::vector<uint32_t> M(&t.pi[(size_t)P * (P + 1) / 2], &t.pi[(size_t)P * (P + 1) / 2] + P + 1);
+  while (M.size() > 1 && M.back() == 0u) M.pop_back();
+  const int LM = (int)M.size();
+  c.LM = LM;
+  c.buf.assign((size_t)P + (size_t)P * LM + LM, 0u);
+  for (int k = 0; k < P; ++k) {
+    const ModP& q = t.primes[k];
+    // M / p_k by schoolbook division with a one-limb divisor (exact)
+    uint32_t* row = &c.buf[(size_t)P + (size_t)k * LM];
+    uint64_t rem = 0;
+    for (int l = LM - 1; l >= 0; --l) {
+      const uint64_t cur = (rem << 32) | M[l];
+      row[l] = (uint32_t)(cur / q.p);
+      rem = cur % q.p;
+    }
+    // (M / p_k) mod p_k by Horner over its limbs
+    uint64_t r = 0;
+    for (int l = LM - 1; l >= 0; --l) r = ((r << 32) | row[l]) % q.p;
+    c.buf[k] = minv(to_mont((uint32_t)r, q), q);
+  }
+  for (int l = 0; l < LM; ++l) c.buf[(size_t)P + (size_t)P * LM + l] = M[l];
+  return c;
+}
+
 const HostTables& host_tables() {
   static HostTables t;
   static std::once_flag once;

@@ -29,4 +29,14 @@ void mrc_tables(const std::vector<ModP>& primes, std::vector<uint32_t>& gm, std:
                 std::vector<uint32_t>& pm, std::vector<uint32_t>& pi);
 const HostTables& host_tables();
 
+// Explicit CRT constants for the first P primes of the table, M = prod_{k<P} p_k:
+// one buffer [w (P words) | M_k rows (P x LM words) | M (LM words)] with
+// w[k] the Montgomery form of ((M / p_k) mod p_k)^{-1} mod p_k and the rows
+// the little-endian limbs of M / p_k, zero-padded to LM = limbs of M.
+struct CrtHost {
+  int P = 0, LM = 0;
+  std::vector<uint32_t> buf;
+};
+CrtHost crt_tables(int P);
+
 }  // namespace bires

@@ -252,3 +252,38 @@ def test_autotune_keeps_results():
     br.set_schedule("auto")
     b.run()
     assert b.results() == out
+
+
+def test_large_batch_lane_garner_path():
+    # >= 16384 output coefficients in one batch selects the lane-per-coefficient
+    # Garner + limb kernel; single calls take the wave-per-coefficient kernels
+    jobs = [("res",) + synth.config2_pair(i) + ("y",) for i in range(40)]
+    jobs += [("res",) + synth.config1_pair(i % 4) + ("y",) for i in range(10)]
+    say("large batch", len(jobs))
+    res, st = br.resultant_batch(jobs)
+    assert st == [0] * len(jobs)
+    _, R0 = load("config2_res_0.txt")
+    assert res[0] == R0
+    for i in range(10):
+        assert res[40 + i] == load("config1_res_%d.txt" % (i % 4))[1]
+    for i in (1, 17, 39):
+        assert res[i] == br.resultant(*synth.config2_pair(i))
+        for a in (3, -7):
+            assert zx.evaluate(res[i], a) == resultant_at(*synth.config2_pair(i), a)
+
+
+def test_shared_shape_batch_matrix_core_interpolation():
+    # >= 32 jobs with the same point and prime counts interpolate as int8
+    # matrix-core products with the inverse Vandermonde matrix; single calls
+    # use the per-job interpolation kernel
+    pairs = [synth.config2_pair(i) for i in range(36)]
+    D, P, _ = br.plan(*pairs[0])
+    assert all(br.plan(F, G)[:2] == (D, P) for F, G in pairs)
+    say("shared-shape batch", len(pairs), D, P)
+    res, st = br.resultant_batch([("res", F, G, "y") for F, G in pairs])
+    assert st == [0] * len(pairs)
+    assert res[0] == load("config2_res_0.txt")[1]
+    for i, (F, G) in enumerate(pairs):
+        assert res[i] == br.resultant(F, G), i
+    for i in (5, 35):
+        assert zx.evaluate(res[i], 11) == resultant_at(*pairs[i], 11)

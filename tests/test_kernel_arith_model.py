@@ -1,0 +1,376 @@
+"""CPU model of the evaluation/elimination arithmetic of the HIP kernel.
+
+The univariate-resultant kernel computes, per (prime p, point a):
+
+* f_j(a) in Montgomery form as an exact 96-bit sum S = sum_i c_i,M (a^i)_M,
+  reduced by one REDC of (S mod 2^32) + (S >> 64) R^2 plus the middle word;
+  rows longer than 24 coefficients in chunks of 24 combined by Horner's rule;
+* the determinant of the Sylvester matrix (Section 2) over F_p by Euclid's
+  algorithm without inverses: a - b + 1 eliminations per step (two of them
+  fused into one pass when a = b + 1), formal-degree rules for vanishing
+  leading coefficients, and the exponent of lc(B) split into prefix products.
+
+This module restates that arithmetic in Python integers with the same word
+bounds (asserted) and checks it against the oracle's determinant of the
+Sylvester matrix mod p.  It pins the algebra of the kernel design; the GPU
+parity tests pin the kernel itself.
+"""
+
+import random
+
+import pytest
+
+from oracle.resultant import det_mod, sylvester
+
+R = 1 << 32
+PRIMES = [2147483647, 2147483629, 2147483587, 1073741827, 1073741831]
+
+
+def redc(t, p):
+    pinv = (-pow(p, -1, R)) % R
+    assert 0 <= t < p * R
+    m = (t % R) * pinv % R
+    u = t + m * p
+    assert u < 1 << 64
+    r = u >> 32
+    assert r < 2 * p
+    return r - p if r >= p else r
+
+
+def mont(x, p):
+    return x * R % p
+
+
+def mmul(a, b, p):
+    return redc(a * b, p)
+
+
+def mdot2(a, b, c, d, p):
+    return redc(a * b + c * d, p)
+
+
+def mneg(x, p):
+    return (p - x) % p
+
+
+def reduce32(x, p):
+    assert 0 <= x < R
+    x = min(x, (x - 2 * p) % R)
+    return min(x, (x - p) % R)
+
+
+def fold96(S, p):
+    lo_lo, lo_hi, hi = S & (R - 1), (S >> 32) & (R - 1), S >> 64
+    assert hi < R - 4
+    x = redc(lo_lo + hi * (R * R % p), p)
+    return (x + reduce32(lo_hi, p)) % p
+
+
+PW = 24
+
+
+def eval_row(row, d, a, p):
+    """Montgomery value of sum_i c_i a^i from Montgomery residues `row`
+    (zero-padded to a multiple of 4), as the kernel computes it."""
+    aM = mont(a, p)
+    pw = [mont(1, p)]
+    for _ in range(1, PW):
+        pw.append(mmul(pw[-1], aM, p))
+    apw = mmul(pw[-1], aM, p)
+    if d < 0:
+        return 0
+    top = d // PW
+    acc = 0
+    for ch in range(top, -1, -1):
+        ng = (min(PW, d + 1 - ch * PW) + 3) // 4
+        S = 0
+        for g in range(ng):
+            t = sum(row[ch * PW + 4 * g + u] * pw[4 * g + u] for u in range(4))
+            assert t < 1 << 64
+            S += t
+        r = fold96(S, p)
+        acc = r if ch == top else (mmul(acc, apw, p) + r) % p
+    return acc
+
+
+def eliminate(A, B, a, b, lb, p, fused):
+    if fused and a == b + 1:
+        n1 = mneg(A[a], p)
+        n2 = mneg(mdot2(lb, A[a - 1], n1, B[b - 1], p), p)
+        bp = B[0]
+        A[0] = mdot2(lb, mmul(lb, A[0], p), n2, bp, p)
+        for t in range(1, b):
+            y = B[t]
+            A[t] = mdot2(lb, mdot2(lb, A[t], n1, bp, p), n2, y, p)
+            bp = y
+        return
+    while a >= b:
+        nla = mneg(A[a], p)
+        s = a - b
+        for t in range(s):
+            A[t] = mmul(lb, A[t], p)
+        for t in range(s, a):
+            A[t] = mdot2(lb, A[t], nla, B[t - s], p)
+        a -= 1
+
+
+def mpow(x, e, p):
+    r = mont(1, p)
+    for _ in range(e):
+        r = mmul(r, x, p)
+    return r
+
+
+def minv(x, p):
+    return mpow(x, p - 2, p) if p < 100 else mont(pow(x * pow(R, -1, p) % p, p - 2, p), p)
+
+
+def uni_resultant(A, B, m, n, p, fused=True):
+    """Montgomery form of det Sylvester(A, B) with formal degrees m, n."""
+    A, B = list(A), list(B)
+    one = mont(1, p)
+    if m == 0 and n == 0:
+        return one
+    a = m
+    while a >= 0 and A[a] == 0:
+        a -= 1
+    b = n
+    while b >= 0 and B[b] == 0:
+        b -= 1
+    if a < 0:
+        return mpow(B[0], m, p) if n == 0 else 0
+    if b < 0:
+        return mpow(A[0], n, p) if m == 0 else 0
+    if a < m and b < n:
+        return 0
+    num, den, neg = one, one, False
+    if a < m:
+        num, neg = mpow(B[n], m - a, p), (n * (m - a)) & 1 == 1
+    elif b < n:
+        num = mpow(A[m], n - b, p)
+    if a < b:
+        A, B, a, b = B, A, b, a
+        neg ^= (a * b) & 1 == 1
+    pfx = one
+    while b > 0:
+        lb = B[b]
+        eliminate(A, B, a, b, lb, p, fused)
+        c = b - 1
+        while c >= 0 and A[c] == 0:
+            c -= 1
+        if c < 0:
+            return 0
+        neg ^= (a * b) & 1 == 1
+        pfx = mmul(pfx, mmul(lb, lb, p), p)
+        x = b - max(c, 1)
+        if x >= 1:
+            den = mmul(den, mpow(pfx, x, p), p)
+        d = a - c - (a - b + 1) * b + 2 * (b - 1)
+        if d > 0:
+            num = mmul(num, mpow(lb, d, p), p)
+        elif d < 0:
+            den = mmul(den, mpow(lb, -d, p), p)
+        A, B, a, b = B, A, b, c
+    num = mmul(num, mpow(B[0], a, p), p)
+    r = mmul(num, minv(den, p), p)
+    return mneg(r, p) if neg else r
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_power_dot_evaluation(seed):
+    rng = random.Random(seed)
+    for _ in range(150):
+        p = rng.choice(PRIMES)
+        a = rng.randrange(0, 8192)
+        d = rng.randrange(-1, 80)
+        c = [rng.randrange(p) if rng.random() > 0.3 else rng.choice([0, p - 1]) for _ in range(d + 1)]
+        row = [mont(x, p) for x in c] + [0] * (4 * rng.randrange(1, 3) - (d + 1) % 4)
+        ref = sum(ci * pow(a, i, p) for i, ci in enumerate(c)) % p
+        assert eval_row(row, d, a, p) == mont(ref, p)
+
+
+def test_fold_bound_at_extremes():
+    for p in PRIMES:
+        top = (p - 1) * (p - 1)
+        S = 24 * top                         # the largest chunk sum
+        assert fold96(S, p) == S * pow(R, -1, p) % p
+        assert fold96(0, p) == 0
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_euclid_matches_sylvester_determinant(fused):
+    rng = random.Random(11 + fused)
+    for _ in range(1500):
+        p = rng.choice(PRIMES)
+        m, n = rng.randint(0, 7), rng.randint(0, 7)
+        f = [rng.randrange(p) if rng.random() > 0.3 else rng.choice([0, 1, p - 1]) for _ in range(m + 1)]
+        g = [rng.randrange(p) if rng.random() > 0.3 else rng.choice([0, 1, p - 1]) for _ in range(n + 1)]
+        if rng.random() < 0.2:
+            f[-1] = 0
+        if rng.random() < 0.2:
+            g[-1] = 0
+        ref = det_mod(sylvester(f, g), p) if m + n else 1
+        got = uni_resultant([mont(x, p) for x in f], [mont(x, p) for x in g], m, n, p, fused)
+        assert got == mont(ref, p), (f, g)
+
+
+def test_model_catches_a_planted_mistake():
+    # a wrong sign of the second multiplier of the fused step must be caught
+    rng = random.Random(5)
+    p = PRIMES[0]
+    bad = 0
+    for _ in range(200):
+        m = n = 4
+        f = [rng.randrange(p) for _ in range(m + 1)]
+        g = [rng.randrange(p) for _ in range(n + 1)]
+        A, B = [mont(x, p) for x in f], [mont(x, p) for x in g]
+        ref = mont(det_mod(sylvester(f, g), p), p)
+        saved = globals()["mneg"]
+        try:
+            calls = {"k": 0}
+
+            def flipped(x, q):
+                calls["k"] += 1
+                return x if calls["k"] % 2 == 0 else saved(x, q)
+
+            globals()["mneg"] = flipped
+            got = uni_resultant(A, B, m, n, p, True)
+        finally:
+            globals()["mneg"] = saved
+        bad += got != ref
+    assert bad > 150
+
+
+def xcd_block(b, nb):
+    q, r, x = nb >> 3, nb & 7, b & 7
+    return x * q + min(x, r) + (b >> 3)
+
+
+@pytest.mark.parametrize("nb", [1, 7, 8, 9, 63, 64, 65, 1000, 4096 * 49 + 5])
+def test_xcd_block_map_is_a_bijection_with_contiguous_xcd_ranges(nb):
+    logical = [xcd_block(b, nb) for b in range(nb)]
+    assert sorted(logical) == list(range(nb))
+    for x in range(8):
+        mine = sorted(logical[b] for b in range(x, nb, 8))
+        assert mine == list(range(mine[0], mine[0] + len(mine))) if mine else True
+
+
+def _primes_desc(n):
+    import sympy
+    out, c = [], (1 << 31) - 1
+    while len(out) < n:
+        if sympy.isprime(c):
+            out.append(c)
+        c -= 2
+    return out
+
+
+def crt_model(residues, primes):
+    """The explicit CRT of the limb kernel: y_k = x_k w_k mod p_k,
+    t = nearest integer to sum y_k / p_k (fp64), R = sum y_k M_k - t M,
+    assembled from signed 32-bit column sums with carries."""
+    import math
+    P = len(primes)
+    M = math.prod(primes)
+    LM = (M.bit_length() + 31) // 32
+    Mk = [M // p for p in primes]
+    y = [x * pow(mk % p, -1, p) % p for x, mk, p in zip(residues, Mk, primes)]
+    f = 0.0
+    for yk, p in zip(y, primes):
+        f = math.fma(float(yk), 1.0 / p, f) if hasattr(math, "fma") else f + float(yk) * (1.0 / p)
+    t = int(f + 0.5)
+    limbs, carry = [], 0
+    for l in range(LM):
+        col = sum(yk * ((mk >> (32 * l)) & 0xFFFFFFFF) for yk, mk in zip(y, Mk))
+        col -= t * ((M >> (32 * l)) & 0xFFFFFFFF)
+        assert -(1 << 95) <= col < 1 << 95
+        v = col + carry
+        limbs.append(v & 0xFFFFFFFF)
+        carry = v >> 32
+    assert carry in (0, -1)
+    val = sum(w << (32 * i) for i, w in enumerate(limbs))
+    return val - (1 << (32 * LM)) if carry == -1 else val
+
+
+def test_explicit_crt_at_the_margin():
+    import math
+    primes = _primes_desc(60)
+    rng = random.Random(21)
+    for P in (1, 2, 3, 7, 49, 60):
+        ps = primes[:P]
+        M = math.prod(ps)
+        # the largest bound the planner admits for this P: M > 2^1.001 B
+        from fractions import Fraction
+        B = int(Fraction(M) * Fraction(2.0 ** -1.001)) - 1
+        for R in [0, 1, -1, B, -B, B - 1, -B + 1] + [rng.randint(-B, B) for _ in range(40)]:
+            assert crt_model([R % p for p in ps], ps) == R, (P, R)
+
+
+# ---------------------------------------------------------------------------
+# interpolation as a matrix product: coefficients = V^{-1} values, with V the
+# Vandermonde matrix of the nodes 0..D-1, and V^{-1} by synthetic division:
+# column a holds the coefficients of N(x) / ((x - a) N'(a)), N = prod (x - b).
+# Products of residues are formed from balanced base-256 digits (int8) with
+# 32-bit sums grouped by digit weight, as the int8 matrix-core kernel does.
+
+def vinv_columns(D, p):
+    N = [1]
+    for b in range(D):                      # N <- N (x - b)
+        N = [((N[j - 1] if j else 0) - b * (N[j] if j < len(N) else 0)) % p for j in range(len(N) + 1)]
+    cols = []
+    for a in range(D):
+        q = [0] * D
+        q[D - 1] = N[D]
+        for j in range(D - 1, 0, -1):
+            q[j - 1] = (N[j] + a * q[j]) % p
+        fa = 1
+        for b in range(D):
+            if b != a:
+                fa = fa * (a - b) % p
+        w = pow(fa, p - 2, p)
+        cols.append([w * qi % p for qi in q])
+    return cols                              # cols[a][i] = V^{-1}[i][a]
+
+
+def balanced_digits(x, p):
+    v = x - p if x > p // 2 else x
+    d = []
+    for _ in range(3):
+        r = ((v + 128) & 255) - 128
+        d.append(r)
+        v = (v - r) >> 8
+    assert -128 <= v <= 127
+    d.append(v)
+    return d
+
+
+def test_vinv_by_synthetic_division_inverts_vandermonde():
+    p = PRIMES[1]
+    for D in (1, 2, 5, 13):
+        cols = vinv_columns(D, p)
+        for i in range(D):
+            for c in range(D):
+                # (V^{-1} V)[i][c] = sum_a V^{-1}[i][a] a^c
+                s = sum(cols[a][i] * pow(a, c, p) for a in range(D)) % p
+                assert s == (1 if i == c else 0)
+
+
+def test_digit_grouped_products_reconstruct_the_residue():
+    rng = random.Random(8)
+    for p in PRIMES:
+        w = [pow(256, u, p) for u in range(7)]
+        for _ in range(30):
+            K = rng.randrange(1, 70)
+            A = [rng.randrange(p) for _ in range(K)]
+            B = [rng.randrange(p) for _ in range(K)]
+            dA = [balanced_digits(x, p) for x in A]
+            dB = [balanced_digits(x, p) for x in B]
+            for x, d in zip(A, dA):
+                assert sum(di << (8 * s) for s, di in enumerate(d)) % p == x
+            G = [0] * 7
+            for s in range(4):
+                for t in range(4):
+                    G[s + t] += sum(da[s] * db[t] for da, db in zip(dA, dB))
+            assert all(abs(g) < 1 << 31 for g in G)
+            got = sum((g % p) * wu for g, wu in zip(G, w)) % p
+            assert got == sum(a * b for a, b in zip(A, B)) % p
