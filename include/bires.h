@@ -12,7 +12,7 @@
  *   - gcd(a, b) in Z[x] (Section 5.1, "Computing gcds in Z[x]").
  * All results are exact integers.  They are computed by the multi-modular
  * scheme of Section 5.1 ("Computing resultants in Z[x,y]", steps (a)-(e)):
- * reduction modulo many 31-bit primes, evaluation at many x, univariate
+ * reduction modulo many word-size primes, evaluation at many x, univariate
  * resultants over F_p, interpolation per prime and Chinese remaindering in
  * mixed-radix form, every step in HIP kernels.
  *
@@ -78,7 +78,7 @@ extern "C" {
 #define BIRES_KIND_DISCRIMINANT 1  /* res(f, df/dvar; var); g ignored */
 
 /* Compiled limits. */
-#define BIRES_MAX_PRIMES 2048      /* 31-bit primes per job: results below ~2^63000 */
+#define BIRES_MAX_PRIMES 2048      /* primes per job (each above 2^30): results below ~2^62000 */
 #define BIRES_MAX_YDEG 512         /* degree in the eliminated variable, per input */
 
 typedef struct {
@@ -95,7 +95,7 @@ typedef struct {
 } bires_upoly;
 
 /* Library set-up on the current HIP device: builds the prime table (the
- * largest primes below 2^31), the mixed-radix tables and the library stream.
+ * largest primes below 2^32/3), the mixed-radix tables and the library stream.
  * Called implicitly by every compute call; explicit calls are idempotent. */
 int bires_init(void);
 
@@ -173,7 +173,8 @@ int bires_server_destroy(bires_server *s);
 int bires_plan(const bires_bipoly *f, const bires_bipoly *g, int kind, int var,
                int32_t *points, int32_t *primes, double *log2_bound);
 
-/* The first n primes of the table (descending from 2^31 - 1).  Host-only. */
+/* The first n primes of the table (the largest primes below 2^32/3,
+ * descending).  Host-only. */
 int bires_primes(int n, uint32_t *out);
 
 /* Values of the univariate resultants res(f(a, y), g(a, y)) mod p_k with the
@@ -216,13 +217,14 @@ int bires_kernel_time(double *ms, int64_t *launches);
 
 /* Host time of batched calls while timing is enabled, accumulated per phase in
  * microseconds since the last reset (bires_set_timing):
- *   us[0] inputs staged and the row-statistics scan submitted,
- *   us[1] waiting for the statistics (device-memory inputs),
- *   us[2] planning, workspace layout and job descriptors,
- *   us[3] metadata upload and kernel launches,
- *   us[4] waiting for the device, statuses and host outputs.
+ *   us[0] validation, input layout and staging buffers,
+ *   us[1] inputs copied and the row-statistics scan submitted,
+ *   us[2] waiting for the statistics (device-memory inputs),
+ *   us[3] planning, workspace layout and job descriptors,
+ *   us[4] metadata upload and kernel launches,
+ *   us[5] waiting for the device, statuses and host outputs.
  * us must hold BIRES_HOST_PHASES doubles; *calls = batched calls timed. */
-#define BIRES_HOST_PHASES 5
+#define BIRES_HOST_PHASES 6
 int bires_host_time(double *us, int64_t *calls);
 
 /* Properties of the current device as the HIP runtime reports them: compute

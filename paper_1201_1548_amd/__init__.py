@@ -371,7 +371,7 @@ def kernel_time():
     return ms.value, n.value
 
 
-HOST_PHASES = ("stage_and_scan", "scan_wait", "plan", "upload_and_launch", "device_wait_and_results")
+HOST_PHASES = ("setup", "scan_submit", "scan_wait", "plan", "upload_and_launch", "device_wait_and_results")
 
 
 def host_time():

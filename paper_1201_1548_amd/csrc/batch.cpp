@@ -141,8 +141,8 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
       if (mem == BIRES_MEM_HOST || jobs[i].var == BIRES_VAR_X) w[i].o_in[which] = in.take(bytes);
     }
   }
-  // scan outputs in one contiguous region (one copy back)
-  const size_t scan_begin = in.take(0);
+  // scan outputs: read by the host from the pinned staging block
+  (void)in.take(0);
   if (mem == BIRES_MEM_DEVICE) {
     for (int i = 0; i < nj; ++i) {
       if (w[i].status) continue;
@@ -155,7 +155,6 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
       }
     }
   }
-  const size_t scan_end = in.bytes;
   const size_t o_tasks = in.take(sizeof(ScanTask) * tasks.size());
   const size_t o_smap = in.take(sizeof(int4) * smap.size());
   Held d_in(&cx->dev, in.bytes), h_in(&cx->host, in.bytes);
@@ -172,8 +171,14 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
         (which ? w[i].dev_g : w[i].dev_f) = (const uint32_t*)(d_in.b() + w[i].o_in[which]);
       }
     }
+    hc.mark(0);
     if (in.bytes) DEV(hipMemcpyAsync(d_in.p, h_in.p, in.bytes, hipMemcpyHostToDevice, st));
+    hc.mark(1);
   } else if (!tasks.empty()) {
+    // The scan reads its task list from and writes its statistics to the
+    // pinned staging block through its device mapping: no copies to wait on.
+    uint8_t* hmap = nullptr;
+    DEV(hipHostGetDevicePointer((void**)&hmap, h_in.p, 0));
     int t = 0;
     for (int i = 0; i < nj; ++i) {
       if (w[i].status) continue;
@@ -187,21 +192,17 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
           src = dst;
         }
         (which ? w[i].dev_g : w[i].dev_f) = src;
-        tasks[t++] = ScanTask{src, s.rows, s.ld, s.L, (int32_t*)(d_in.b() + w[i].o_scan[which])};
+        tasks[t++] = ScanTask{src, s.rows, s.ld, s.L, (int32_t*)(hmap + w[i].o_scan[which])};
       }
     }
     std::memcpy(h_in.b() + o_tasks, tasks.data(), sizeof(ScanTask) * tasks.size());
     std::memcpy(h_in.b() + o_smap, smap.data(), sizeof(int4) * smap.size());
-    DEV(hipMemcpyAsync(d_in.b() + o_tasks, h_in.b() + o_tasks, (o_smap - o_tasks) + sizeof(int4) * smap.size(),
-                       hipMemcpyHostToDevice, st));
-    if (!smap.empty())
-      launch_scan((const ScanTask*)(d_in.b() + o_tasks), (const int4*)(d_in.b() + o_smap), (int)smap.size(), st);
-    if (scan_end > scan_begin)
-      DEV(hipMemcpyAsync(h_in.b() + scan_begin, d_in.b() + scan_begin, scan_end - scan_begin, hipMemcpyDeviceToHost,
-                         st));
     hc.mark(0);
-    DEV(hipStreamSynchronize(st));
+    if (!smap.empty())
+      launch_scan((const ScanTask*)(hmap + o_tasks), (const int4*)(hmap + o_smap), (int)smap.size(), st);
     hc.mark(1);
+    DEV(hipStreamSynchronize(st));
+    hc.mark(2);
     for (int i = 0; i < nj; ++i) {
       if (w[i].status) continue;
       for (int which = 0; which < nsrc(i); ++which) {
@@ -457,7 +458,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     std::memset(H0 + o_ctr, 0, sizeof(int) * ((size_t)ctr_off[nj] + 2));
   }
   auto nb_of = [&](int kk) { return starts[kk][nj]; };
-  hc.mark(2);
+  hc.mark(3);
   if (meta_end > meta_begin)
     DEV(hipMemcpyAsync(D0 + meta_begin, h_meta.p, meta_end - meta_begin, hipMemcpyHostToDevice, st));
   const JobDev* d_jobs = (const JobDev*)(D0 + o_jobs);
@@ -547,7 +548,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
       DEV(hipMemcpyAsync(o->c, &one, 4, hipMemcpyHostToDevice, st));
     }
   }
-  hc.mark(3);
+  hc.mark(4);
   if (nj) DEV(hipMemcpyAsync(h_flags, D0 + o_flags, sizeof(int32_t) * 2 * nj, hipMemcpyDeviceToHost, st));
   int fused_err = 0;
   if (fused) DEV(hipMemcpyAsync(&fused_err, d_ctr + ctr_off[nj] + 1, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -593,7 +594,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     if (status) status[i] = x.status;
     if (x.status && first_err == BIRES_OK) first_err = x.status;
   }
-  hc.mark(4);
+  hc.mark(5);
   hc.commit(cx);
   return first_err;
 }

@@ -172,29 +172,34 @@ __device__ __forceinline__ int wave_uniform(int x) {
 // The usual step has a = b + 1: its two eliminations run as one pass.  The
 // second one's multiplier is the first one's new top coefficient
 // lc(B) A_{a-1} - A_a B_{b-1}, computed first; then each coefficient takes
-// A_t <- lc(B) (lc(B) A_t - A_a B_{t-1}) - A'_{a-1} B_t, so every A_t and B_t
-// is read once.
+// A_t <- lc(B) (lc(B) A_t - A_a B_{t-1}) - A'_{a-1} B_t
+//      = lc(B)^2 A_t - lc(B) A_a B_{t-1} - A'_{a-1} B_t,
+// a three-product sum with one reduction (3p < 2^32), and every A_t and B_t
+// is read once.  In Montgomery form the two step constants are
+// l2 = lc(B)^2 R^{-1} and l1 = -lc(B) A_a R^{-1}, so that
+// redc(l2 A_t + l1 B_{t-1} + n2 B_t) equals the two nested reductions.
 template <int W>
 __device__ __forceinline__ void eliminate(uint32_t* __restrict__ A, const uint32_t* __restrict__ B, int a, int b,
                                           uint32_t lb, const ModP& q) {
   if (a == b + 1) {
     const uint32_t n1 = mneg(A[a * W], q.p);
     const uint32_t n2 = mneg(mdot2(lb, A[(a - 1) * W], n1, B[(b - 1) * W], q), q.p);
+    const uint32_t l2 = mmul(lb, lb, q), l1 = mmul(lb, n1, q);
     uint32_t bp = B[0];
-    A[0] = mdot2(lb, mmul(lb, A[0], q), n2, bp, q);
+    A[0] = mdot2(l2, A[0], n2, bp, q);
     int t = 1;
     for (; t + 4 <= b; t += 4) {
       const uint32_t x0 = A[t * W], x1 = A[(t + 1) * W], x2 = A[(t + 2) * W], x3 = A[(t + 3) * W];
       const uint32_t y0 = B[t * W], y1 = B[(t + 1) * W], y2 = B[(t + 2) * W], y3 = B[(t + 3) * W];
-      A[t * W] = mdot2(lb, mdot2(lb, x0, n1, bp, q), n2, y0, q);
-      A[(t + 1) * W] = mdot2(lb, mdot2(lb, x1, n1, y0, q), n2, y1, q);
-      A[(t + 2) * W] = mdot2(lb, mdot2(lb, x2, n1, y1, q), n2, y2, q);
-      A[(t + 3) * W] = mdot2(lb, mdot2(lb, x3, n1, y2, q), n2, y3, q);
+      A[t * W] = mdot3(l2, x0, l1, bp, n2, y0, q);
+      A[(t + 1) * W] = mdot3(l2, x1, l1, y0, n2, y1, q);
+      A[(t + 2) * W] = mdot3(l2, x2, l1, y1, n2, y2, q);
+      A[(t + 3) * W] = mdot3(l2, x3, l1, y2, n2, y3, q);
       bp = y3;
     }
     for (; t < b; ++t) {
       const uint32_t y = B[t * W];
-      A[t * W] = mdot2(lb, mdot2(lb, A[t * W], n1, bp, q), n2, y, q);
+      A[t * W] = mdot3(l2, A[t * W], l1, bp, n2, y, q);
       bp = y;
     }
     return;
@@ -246,9 +251,43 @@ __device__ uint32_t uni_resultant(uint32_t* A, uint32_t* B, int m, int n, const 
   // products of l_i^2 and t in [max(c_i, 1), b_i - 1] taking P_i, so a generic
   // step (c_i = b_i - 1, d_i = 0) costs three products and no power.
   uint32_t pfx = q.one;
+  // Fast path: while every lane has the same (a, b) and every remainder has
+  // degree exactly b - 1, a and b stay scalar and a step's bookkeeping is
+  // x = 1 (or 0 at b = 1) and d = (1 - b)(a - b - 1), both uniform.  The
+  // first step whose remainder is shorter on some lane finishes in the
+  // general loop below without eliminating again.
+  bool eliminated = false;
+  uint32_t lb_done = 0;
+  if (wave_uniform(a) && wave_uniform(b)) {
+    int as = __builtin_amdgcn_readfirstlane(a), bs = __builtin_amdgcn_readfirstlane(b);
+    while (bs > 0) {
+      const uint32_t lb = B[bs * W];
+      eliminate<W>(A, B, as, bs, lb, q);
+      if (__ballot(A[(bs - 1) * W] == 0u) != 0ull) {
+        eliminated = true;
+        lb_done = lb;
+        break;
+      }
+      neg ^= ((as * bs) & 1) != 0;
+      pfx = mmul(pfx, mmul(lb, lb, q), q);
+      if (bs > 1) den = mmul(den, pfx, q);
+      const int d = (1 - bs) * (as - bs - 1);
+      if (d > 0) num = mmul(num, mpow(lb, (uint32_t)d, q), q);
+      else if (d < 0) den = mmul(den, mpow(lb, (uint32_t)(-d), q), q);
+      uint32_t* T = A;
+      A = B;
+      B = T;
+      as = bs;
+      bs = bs - 1;
+    }
+    a = as;
+    b = bs;
+  }
   while (b > 0) {
-    const uint32_t lb = B[b * W];
-    if (wave_uniform(a) && wave_uniform(b))
+    const uint32_t lb = eliminated ? lb_done : B[b * W];
+    if (eliminated)
+      eliminated = false;
+    else if (wave_uniform(a) && wave_uniform(b))
       eliminate<W>(A, B, __builtin_amdgcn_readfirstlane(a), __builtin_amdgcn_readfirstlane(b), lb, q);
     else
       eliminate<W>(A, B, a, b, lb, q);
@@ -531,9 +570,10 @@ size_t interp_lds_words(int D) { return (size_t)3 * D + (size_t)((D + KB - 1) / 
 // 16 int8 products v_mfma_i32_32x32x32_i8 are summed into 7 int32
 // accumulators by weight u = s + t (|G_u| <= 4 Dp 2^14 < 2^31 for Dp < 2^15).
 // The epilogue reduces sum_u G_u 256^u mod p.  Matrices are stored per prime
-// and digit plane, row-major with the contraction index contiguous and padded
-// to Dp (a multiple of 32) with zeros, so a lane's 16 operand bytes are one
-// aligned 16-byte load.
+// and digit plane in operand order, padded with zeros to multiples of 32: for
+// row tile rt (32 rows) and contraction step ks (32 indices) one 1 KiB block
+// holds lane L = r + 32 g's 16 bytes (row 32 rt + r, indices 32 ks + 16 g +
+// 0..15), so each operand load of a wave reads 1 KiB contiguously.
 
 typedef int im_v4i __attribute__((ext_vector_type(4)));
 typedef int im_v16i __attribute__((ext_vector_type(16)));
@@ -555,6 +595,13 @@ __device__ __forceinline__ uint32_t digits4(uint32_t x, uint32_t p) {
 __device__ __forceinline__ void put_digits(int8_t* base, size_t plane, size_t off, uint32_t d) {
 #pragma unroll
   for (int s = 0; s < 4; ++s) base[s * plane + off] = (int8_t)(d >> (8 * s));
+}
+
+// Byte offset of element (row, idx) of a plane with Kp = padded contraction
+// length, in the operand-order layout described above.
+__device__ __forceinline__ size_t im_off(int row, int idx, int Kp) {
+  const int rt = row >> 5, r = row & 31, ks = idx >> 5, g = (idx >> 4) & 1, b = idx & 15;
+  return ((((size_t)rt * (Kp >> 5) + ks) * 64) + r + 32 * g) * 16 + b;
 }
 
 // V^{-1} mod p_k for k = blockIdx.x: Ap[k][s][i][a] (s: digit, i: coefficient,
@@ -584,7 +631,7 @@ __global__ __launch_bounds__(256) void k_vinv(int D, int Dp, TablesDev tab, int8
   const uint32_t* invf = tab.invfact + (size_t)k * tab.dmax;
   for (int a = threadIdx.x; a < Dp; a += blockDim.x) {
     if (a >= D) {
-      for (int i = 0; i < Dp; ++i) put_digits(base, plane, (size_t)i * Dp + a, 0u);
+      for (int i = 0; i < Dp; ++i) put_digits(base, plane, im_off(i, a, Dp), 0u);
       continue;
     }
     uint32_t w = mmul(invf[a], invf[D - 1 - a], q);
@@ -592,10 +639,10 @@ __global__ __launch_bounds__(256) void k_vinv(int D, int Dp, TablesDev tab, int8
     const uint32_t aM = to_mont((uint32_t)a, q);
     uint32_t qj = cur[D];  // q_{D-1} = leading coefficient of N
     for (int j = D - 1; j >= 0; --j) {
-      put_digits(base, plane, (size_t)j * Dp + a, digits4(from_mont(mmul(w, qj, q), q), q.p));
+      put_digits(base, plane, im_off(j, a, Dp), digits4(from_mont(mmul(w, qj, q), q), q.p));
       if (j) qj = madd(cur[j], mmul(aM, qj, q), q.p);  // q_{j-1} = n_j + a q_j
     }
-    for (int i = D; i < Dp; ++i) put_digits(base, plane, (size_t)i * Dp + a, 0u);
+    for (int i = D; i < Dp; ++i) put_digits(base, plane, im_off(i, a, Dp), 0u);
   }
 }
 
@@ -606,59 +653,75 @@ __global__ __launch_bounds__(256) void k_yplanes(const JobDev* jobs, const int* 
   const int n = blockIdx.x, k = blockIdx.y;
   const uint32_t p = tab.primes[k].p;
   const size_t plane = (size_t)Np * Dp;
-  int8_t* base = Yp + (size_t)k * 4 * plane + (size_t)n * Dp;
+  int8_t* base = Yp + (size_t)k * 4 * plane;
   const uint32_t* v = n < N ? jobs[gj[n]].vals + (size_t)k * D : nullptr;
-  for (int a = threadIdx.x; a < Dp; a += blockDim.x) put_digits(base, plane, a, v && a < D ? digits4(v[a], p) : 0u);
+  for (int a = threadIdx.x; a < Dp; a += blockDim.x)
+    put_digits(base, plane, im_off(n, a, Dp), v && a < D ? digits4(v[a], p) : 0u);
 }
 
 // One wave per 32 x 32 tile of C for prime k: grid (Dp/32, Np/32, P).
 // Accumulator register r of lane l holds row 8 (r/4) + 4 (l/32) + r%4 and
 // column l%32 of the tile; operand lanes hold row (A) or column (Y) l%32 and
-// contraction indices 16 (l/32) + 0..15 of the 32-wide step.
+// contraction indices 16 (l/32) + 0..15 of the 32-wide step.  The operands of
+// step a0 + 32 are loaded before the products of step a0 are issued.  The
+// reduced tile is transposed through LDS so that each job's 32 coefficients
+// are written as one contiguous segment.
+struct ImOps {
+  im_v4i a0, a1, a2, a3, y0, y1, y2, y3;
+};
+
+__device__ __forceinline__ ImOps im_load(const int8_t* A, const int8_t* Y, size_t pa, size_t py, int a0) {
+  ImOps o;
+  o.a0 = *(const im_v4i*)(A + a0);
+  o.a1 = *(const im_v4i*)(A + pa + a0);
+  o.a2 = *(const im_v4i*)(A + 2 * pa + a0);
+  o.a3 = *(const im_v4i*)(A + 3 * pa + a0);
+  o.y0 = *(const im_v4i*)(Y + a0);
+  o.y1 = *(const im_v4i*)(Y + py + a0);
+  o.y2 = *(const im_v4i*)(Y + 2 * py + a0);
+  o.y3 = *(const im_v4i*)(Y + 3 * py + a0);
+  return o;
+}
+
 __global__ __launch_bounds__(64) void k_interp_mfma(const JobDev* jobs, const int* gj, int N, int Np, int D, int Dp,
                                                     const int8_t* Ap, const int8_t* Yp, TablesDev tab) {
+  __shared__ uint32_t tile[32][33];
   const int l = threadIdx.x, r32 = l & 31, g = l >> 5;
   const int i0 = blockIdx.x * 32, n0 = blockIdx.y * 32, k = blockIdx.z;
   const size_t pa = (size_t)Dp * Dp, py = (size_t)Np * Dp;
-  const int8_t* A = Ap + (size_t)k * 4 * pa + (size_t)(i0 + r32) * Dp + 16 * g;
-  const int8_t* Y = Yp + (size_t)k * 4 * py + (size_t)(n0 + r32) * Dp + 16 * g;
+  // operand-order blocks: 1 KiB per (row tile, step); a lane reads bytes 16 l..16 l + 15
+  const int8_t* A = Ap + (size_t)k * 4 * pa + (size_t)blockIdx.x * Dp * 32 + 16 * l;
+  const int8_t* Y = Yp + (size_t)k * 4 * py + (size_t)blockIdx.y * Dp * 32 + 16 * l;
   im_v16i G0 = {0}, G1 = {0}, G2 = {0}, G3 = {0}, G4 = {0}, G5 = {0}, G6 = {0};
+  ImOps cur = im_load(A, Y, pa, py, 0);
   for (int a0 = 0; a0 < Dp; a0 += 32) {
-    const im_v4i a_0 = *(const im_v4i*)(A + a0), a_1 = *(const im_v4i*)(A + pa + a0);
-    const im_v4i a_2 = *(const im_v4i*)(A + 2 * pa + a0), a_3 = *(const im_v4i*)(A + 3 * pa + a0);
-    const im_v4i y_0 = *(const im_v4i*)(Y + a0), y_1 = *(const im_v4i*)(Y + py + a0);
-    const im_v4i y_2 = *(const im_v4i*)(Y + 2 * py + a0), y_3 = *(const im_v4i*)(Y + 3 * py + a0);
-    G0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_0, y_0, G0, 0, 0, 0);
-    G1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_0, y_1, G1, 0, 0, 0);
-    G1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_1, y_0, G1, 0, 0, 0);
-    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_0, y_2, G2, 0, 0, 0);
-    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_1, y_1, G2, 0, 0, 0);
-    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_2, y_0, G2, 0, 0, 0);
-    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_0, y_3, G3, 0, 0, 0);
-    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_1, y_2, G3, 0, 0, 0);
-    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_2, y_1, G3, 0, 0, 0);
-    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_3, y_0, G3, 0, 0, 0);
-    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_1, y_3, G4, 0, 0, 0);
-    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_2, y_2, G4, 0, 0, 0);
-    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_3, y_1, G4, 0, 0, 0);
-    G5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_2, y_3, G5, 0, 0, 0);
-    G5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_3, y_2, G5, 0, 0, 0);
-    G6 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_3, y_3, G6, 0, 0, 0);
+    const ImOps o = cur;
+    if (a0 + 32 < Dp) cur = im_load(A, Y, pa, py, (a0 + 32) * 32);
+    G0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a0, o.y0, G0, 0, 0, 0);
+    G1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a0, o.y1, G1, 0, 0, 0);
+    G1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a1, o.y0, G1, 0, 0, 0);
+    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a0, o.y2, G2, 0, 0, 0);
+    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a1, o.y1, G2, 0, 0, 0);
+    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a2, o.y0, G2, 0, 0, 0);
+    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a0, o.y3, G3, 0, 0, 0);
+    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a1, o.y2, G3, 0, 0, 0);
+    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a2, o.y1, G3, 0, 0, 0);
+    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a3, o.y0, G3, 0, 0, 0);
+    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a1, o.y3, G4, 0, 0, 0);
+    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a2, o.y2, G4, 0, 0, 0);
+    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a3, o.y1, G4, 0, 0, 0);
+    G5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a2, o.y3, G5, 0, 0, 0);
+    G5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a3, o.y2, G5, 0, 0, 0);
+    G6 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a3, o.y3, G6, 0, 0, 0);
   }
-  const int n = n0 + r32;
-  if (n >= N) return;
-  const JobDev& J = jobs[gj[n]];
-  if (k >= J.P) return;
   const ModP q = tab.primes[k];
   uint32_t w[7];  // Montgomery forms of 256^u
   w[0] = q.one;
   const uint32_t m256 = to_mont(256u, q);
 #pragma unroll
   for (int u = 1; u < 7; ++u) w[u] = mmul(w[u - 1], m256, q);
-  uint32_t* out = J.coefs + (size_t)k * D;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const int i = i0 + 8 * (r >> 2) + 4 * g + (r & 3);
     const int32_t gv[7] = {G0[r], G1[r], G2[r], G3[r], G4[r], G5[r], G6[r]};
     Acc96 S;
     uint64_t t = 0;
@@ -671,7 +734,17 @@ __global__ __launch_bounds__(64) void k_interp_mfma(const JobDev* jobs, const in
         t = 0;
       }
     }
-    if (i < D) out[i] = fold96(S, q);
+    tile[r32][8 * (r >> 2) + 4 * g + (r & 3)] = fold96(S, q);  // [column][row]
+  }
+  __syncthreads();
+  // lanes 0-31 write column n0 + 2c, lanes 32-63 column n0 + 2c + 1: 32 rows each
+  for (int c = 0; c < 16; ++c) {
+    const int col = 2 * c + g, n = n0 + col;
+    const int i = i0 + r32;
+    if (n < N && i < D) {
+      const JobDev& J = jobs[gj[n]];
+      if (k < J.P) J.coefs[(size_t)k * D + i] = tile[col][r32];
+    }
   }
 }
 
@@ -889,22 +962,46 @@ __global__ __launch_bounds__(64) void k_limbs_carry(const JobDev* jobs, const in
 // wave + 4, ...); one lane per coefficient then propagates the carries.
 // Nothing is serial in the prime index, unlike Garner's digits.
 constexpr int CRT_MAXP = 128;
+constexpr int CRT_R = 16;  // limb columns per wave and pass (registers)
 
-__device__ void dev_crt(const JobDev& J, int lb, int stage_ld, TablesDev tab, uint32_t* lds) {
+// LDS layout (words): Y [P][64] (later the output staging rows), Tq [64],
+// Mk [P][LMp], w [P], M [LMp], limbs [LMp][64], carries [4 * npass][64][2];
+// LMp = LM rounded up to 4 * CRT_R.
+__device__ __forceinline__ void dev_crt(const JobDev& J, int lb, int stage_ld, TablesDev tab, uint32_t* lds) {
   const int P = J.P, D = J.D, Lc = J.Lcap, LM = J.crt_LM;
+  const int LMp = (LM + 4 * CRT_R - 1) / (4 * CRT_R) * (4 * CRT_R);
+  const int npass = LMp / (4 * CRT_R);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c0 = lb * 64, c = c0 + lane;
-  const uint32_t* w = J.crt;
-  const uint32_t* Mk = J.crt + P;
-  const uint32_t* M = Mk + (size_t)P * LM;
+  if (c0 >= D) {
+    // beyond the degree bound: zero coefficients up to the output capacity
+    const int nc = min(64, J.degcap + 1 - c0);
+    uint32_t* dst = J.out + (size_t)c0 * Lc;
+    for (int i = threadIdx.x; i < nc * Lc; i += blockDim.x) dst[i] = 0u;
+    return;
+  }
   const int ny = max(P, stage_ld);
-  uint32_t* Y = lds;                               // [P][64] y_k; then the output staging rows
-  int32_t* Tq = (int32_t*)(lds + ny * 64);         // [64] nearest integers t
-  uint32_t* S0 = lds + ny * 64 + 64;               // [LM][64] column sums: bits 0-31,
-  uint32_t* S1 = S0 + LM * 64;                     //   32-63,
-  int32_t* S2 = (int32_t*)(S1 + LM * 64);          //   64-95 (signed)
+  uint32_t* Y = lds;
+  int32_t* Tq = (int32_t*)(lds + ny * 64);
+  uint32_t* Mk = lds + ny * 64 + 64;
+  uint32_t* wv = Mk + P * LMp;
+  uint32_t* Ms = wv + P;
+  uint32_t* Lb = Ms + LMp;                              // [LMp][64] limbs of each wave's range
+  const int co_off = (int)(Lb - lds) + LMp * 64;
+  int64_t* Co = (int64_t*)(lds + co_off + (co_off & 1));  // [4 npass][64] carries out of a range (8-byte aligned)
+  // stage the CRT constants
+  const uint32_t* gw = J.crt;
+  const uint32_t* gMk = J.crt + P;
+  const uint32_t* gM = gMk + (size_t)P * LM;
+  for (int i = threadIdx.x; i < P * LMp; i += blockDim.x) {
+    const int k = i / LMp, l = i - k * LMp;
+    Mk[i] = l < LM ? gMk[(size_t)k * LM + l] : 0u;
+  }
+  for (int i = threadIdx.x; i < P; i += blockDim.x) wv[i] = gw[i];
+  for (int i = threadIdx.x; i < LMp; i += blockDim.x) Ms[i] = i < LM ? gM[i] : 0u;
+  __syncthreads();
   for (int k = wave; k < P; k += 4)
-    Y[k * 64 + lane] = c < D ? mmul(J.coefs[(size_t)k * D + c], w[k], tab.primes[k]) : 0u;
+    Y[k * 64 + lane] = c < D ? mmul(J.coefs[(size_t)k * D + c], wv[k], tab.primes[k]) : 0u;
   __syncthreads();
   if (wave == 0) {
     double f = 0.0;
@@ -912,22 +1009,48 @@ __device__ void dev_crt(const JobDev& J, int lb, int stage_ld, TablesDev tab, ui
     Tq[lane] = (int32_t)(f + 0.5);
   }
   __syncthreads();
+  // column sums of the wave's CRT_R limbs per pass, prime-outer; then the
+  // range is normalised to 32-bit limbs plus a signed carry out
   const uint64_t t = (uint64_t)Tq[lane];
-  for (int l = wave; l < LM; l += 4) {
-    uint64_t lo = 0;
-    uint32_t hi = 0;
-    const uint32_t* col = Mk + l;
-    for (int k = 0; k < P; ++k) {
-      const uint64_t pr = (uint64_t)Y[k * 64 + lane] * col[(size_t)k * LM];
-      lo += pr;
-      hi += lo < pr ? 1u : 0u;
+  for (int pass = 0; pass < npass; ++pass) {
+    const int l0 = (pass * 4 + wave) * CRT_R;
+    uint64_t lo[CRT_R];
+    uint32_t hi[CRT_R];
+#pragma unroll
+    for (int j = 0; j < CRT_R; ++j) {
+      lo[j] = 0;
+      hi[j] = 0;
     }
-    const uint64_t sub = t * M[l];
-    hi -= lo < sub ? 1u : 0u;
-    lo -= sub;
-    S0[l * 64 + lane] = (uint32_t)lo;
-    S1[l * 64 + lane] = (uint32_t)(lo >> 32);
-    S2[l * 64 + lane] = (int32_t)hi;
+    // a range past the last limb is all padding (zero columns); the padded
+    // columns of a partial range are zero in LDS and cost no branches
+    const bool live = __builtin_amdgcn_readfirstlane(l0) < __builtin_amdgcn_readfirstlane(LM);
+#pragma unroll 2
+    for (int k = 0; k < P && live; ++k) {
+      const uint64_t y = Y[k * 64 + lane];
+      const uint4* mk = (const uint4*)(Mk + k * LMp + l0);
+      const uint4 m0 = mk[0], m1 = mk[1], m2 = mk[2], m3 = mk[3];
+      const uint32_t mm[CRT_R] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w,
+                                  m2.x, m2.y, m2.z, m2.w, m3.x, m3.y, m3.z, m3.w};
+#pragma unroll
+      for (int j = 0; j < CRT_R; ++j) {
+        const uint64_t pr = y * mm[j];
+        lo[j] += pr;
+        hi[j] += lo[j] < pr ? 1u : 0u;
+      }
+    }
+    int64_t carry = 0;
+#pragma unroll
+    for (int j = 0; j < CRT_R; ++j) {
+      const uint64_t sub = t * Ms[l0 + j];
+      uint32_t h = hi[j] - (lo[j] < sub ? 1u : 0u);
+      uint64_t v = lo[j] - sub;
+      // v + carry as 96-bit two's complement (h:v)
+      const uint64_t v2 = v + (uint64_t)carry;
+      h += (carry < 0 ? 0xFFFFFFFFu : 0u) + (v2 < v ? 1u : 0u);
+      Lb[(l0 + j) * 64 + lane] = (uint32_t)v2;
+      carry = (int64_t)(((uint64_t)h << 32) | (v2 >> 32));
+    }
+    Co[(pass * 4 + wave) * 64 + lane] = carry;
   }
   __syncthreads();
   const bool staged = stage_ld > 0;
@@ -936,23 +1059,18 @@ __device__ void dev_crt(const JobDev& J, int lb, int stage_ld, TablesDev tab, ui
     if (c >= D) {
       for (int l = 0; l < Lc; ++l) o[l] = 0u;
     } else {
-      // v = S_l + carry as (hi:lo) 96-bit two's complement; carry = v >> 32 (arithmetic)
+      // limbs of the ranges plus the carries out of the ranges below them
       int64_t carry = 0;
       bool nz = false, bad = false;
       uint32_t last = 0;
       const int Lrun = max(Lc, LM);
       for (int l = 0; l < Lrun; ++l) {
-        uint64_t lo = 0;
-        int32_t hi = 0;
-        if (l < LM) {
-          lo = (uint64_t)S0[l * 64 + lane] | ((uint64_t)S1[l * 64 + lane] << 32);
-          hi = S2[l * 64 + lane];
-        }
-        const uint64_t add = (uint64_t)carry;
-        const uint64_t lo2 = lo + add;
-        hi += (carry < 0 ? -1 : 0) + (lo2 < lo ? 1 : 0);
-        const uint32_t limb = (uint32_t)lo2;
-        carry = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (lo2 >> 32));
+        uint64_t v = (uint64_t)(l < LMp ? Lb[l * 64 + lane] : 0u);
+        int64_t acc = carry + (int64_t)v;
+        if (l > 0 && l < LMp && l % CRT_R == 0) acc += Co[(l / CRT_R - 1) * 64 + lane];
+        if (l == LMp && LMp > 0) acc += Co[(LMp / CRT_R - 1) * 64 + lane];
+        const uint32_t limb = (uint32_t)acc;
+        carry = acc >> 32;
         if (l < Lc) {
           o[l] = limb;
           nz |= limb != 0u;
@@ -960,6 +1078,18 @@ __device__ void dev_crt(const JobDev& J, int lb, int stage_ld, TablesDev tab, ui
         } else if (limb != ((int32_t)last < 0 ? 0xFFFFFFFFu : 0u)) {
           bad = true;
         }
+      }
+      if (Lrun < LMp + 1) {
+        // carries beyond the last processed limb must be pure sign
+        int64_t rest = carry;
+        for (int l = Lrun; l <= LMp; ++l) {
+          int64_t acc = rest + (int64_t)(l < LMp ? Lb[l * 64 + lane] : 0u);
+          if (l > 0 && l < LMp && l % CRT_R == 0) acc += Co[(l / CRT_R - 1) * 64 + lane];
+          if (l == LMp) acc += Co[(LMp / CRT_R - 1) * 64 + lane];
+          if ((uint32_t)acc != ((int32_t)last < 0 ? 0xFFFFFFFFu : 0u)) bad = true;
+          rest = acc >> 32;
+        }
+        carry = rest;
       }
       if (bad || carry != ((int32_t)last < 0 ? -1 : 0)) atomicOr(J.err, 1);
       if (nz) atomicMax(J.deg_out, c);
@@ -1258,7 +1388,10 @@ bool crt_ok(int max_primes) { return max_primes <= CRT_MAXP; }
 
 size_t crt_lds_bytes(int max_primes, int max_lm, int max_lcap) {
   const int stage_ld = max_lcap <= CARRY_STAGE_MAXL ? max_lcap + 1 : 0;
-  return ((size_t)64 * std::max(max_primes, stage_ld) + 64 + (size_t)3 * 64 * max_lm) * sizeof(uint32_t);
+  const size_t LMp = (size_t)(max_lm + 4 * CRT_R - 1) / (4 * CRT_R) * (4 * CRT_R);
+  const size_t words = (size_t)64 * std::max(max_primes, stage_ld) + 64 + (size_t)max_primes * LMp + max_primes +
+                       LMp + LMp * 64 + 1 + (LMp / CRT_R) * 64 * 2;
+  return words * sizeof(uint32_t);
 }
 
 void launch_crt(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, int max_lm, int max_lcap,

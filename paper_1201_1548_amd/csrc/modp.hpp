@@ -1,12 +1,13 @@
-// Arithmetic modulo 31-bit primes (2^30 < p < 2^31), for host and gfx950 device code.
+// Arithmetic modulo the table primes 2^30 < p < 2^32 / 3, for host and gfx950
+// device code.
 //
 // Montgomery representation with R = 2^32 (Montgomery, "Modular multiplication
 // without trial division", Math. Comp. 44, 1985): x is held as xR mod p.
-// redc(t) = t R^{-1} mod p for any t < 2 p^2, so one reduction serves a single
-// product or a sum of two products (t = ab + cd < 2p^2).  The bound keeps
-// t + m p below 2^64 (2p^2 < 2^63, m p < 2^63) and the result below 2p, which
-// one conditional subtraction fixes; min(r, r - p) is that subtraction in
-// unsigned arithmetic (r - p wraps above r exactly when r < p).
+// redc(t) = t R^{-1} mod p for any t < p 2^32: t + m p < p 2^33 < 2^64 and the
+// result is below 2p, which one conditional subtraction fixes; min(r, r - p)
+// is that subtraction in unsigned arithmetic (r - p wraps above r exactly when
+// r < p).  Since 3p < 2^32, one reduction serves a single product or a sum of
+// two or three products of residues (t < 3p^2 < p 2^32).
 #pragma once
 #include <stdint.h>
 
@@ -42,6 +43,11 @@ BIRES_HD uint32_t mdot2(uint32_t a, uint32_t b, uint32_t c, uint32_t d, const Mo
   return redc((uint64_t)a * b + (uint64_t)c * d, q.p, q.pinv);
 }
 
+// (a b + c d + e f) R^{-1} mod p with a single reduction (residues below p).
+BIRES_HD uint32_t mdot3(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t e, uint32_t f, const ModP& q) {
+  return redc((uint64_t)a * b + (uint64_t)c * d + (uint64_t)e * f, q.p, q.pinv);
+}
+
 BIRES_HD uint32_t madd(uint32_t a, uint32_t b, uint32_t p) {
   uint32_t s = a + b;
   return umin32(s, s - p);
@@ -54,7 +60,7 @@ BIRES_HD uint32_t msub(uint32_t a, uint32_t b, uint32_t p) {
 
 BIRES_HD uint32_t mneg(uint32_t a, uint32_t p) { return a ? p - a : 0u; }
 
-BIRES_HD uint32_t to_mont(uint32_t a, const ModP& q) { return mmul(a, q.r2, q); }   // needs a < 2^31 (a*r2 < 2p^2)
+BIRES_HD uint32_t to_mont(uint32_t a, const ModP& q) { return mmul(a, q.r2, q); }   // any 32-bit a (a r2 < p 2^32)
 BIRES_HD uint32_t from_mont(uint32_t a, const ModP& q) { return redc((uint64_t)a, q.p, q.pinv); }
 
 // x mod p for any 32-bit x (x < 4p because p > 2^30).

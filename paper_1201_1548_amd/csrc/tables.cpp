@@ -1,9 +1,11 @@
 // Host construction of the prime table and of the mixed-radix constants.
 //
-// Primes: the K largest primes below 2^31, descending (deterministic
-// Miller-Rabin with bases 2, 7, 61, exact for n < 4,759,123,141).  Every job
-// uses a prefix of this table, so the Garner constants and the radix products
-// prod_{i<k} p_i are computed once for all jobs.
+// Primes: the K largest primes below 2^32 / 3, descending (deterministic
+// Miller-Rabin with bases 2, 7, 61, exact for n < 4,759,123,141).  3p < 2^32
+// lets one Montgomery reduction absorb a sum of three products, and p > 2^30
+// keeps every 32-bit word below 4p.  Every job uses a prefix of this table, so
+// the Garner constants and the radix products prod_{i<k} p_i are computed
+// once for all jobs.
 #include "tables.hpp"
 
 #include <cmath>
@@ -64,7 +66,7 @@ ModP make_modp(uint32_t p) {
 static void build(HostTables& t, int K) {
   t.K = K;
   t.primes.clear();
-  for (uint32_t c = 0x7FFFFFFFu; (int)t.primes.size() < K; c -= 2)
+  for (uint32_t c = PRIME_CEIL; (int)t.primes.size() < K; c -= 2)
     if (is_prime32(c)) t.primes.push_back(make_modp(c));
   t.log2p.resize(K);
   t.cumlog.assign(K + 1, 0.0);

@@ -9,12 +9,13 @@
 namespace bires {
 
 constexpr int MAX_PRIMES = 2048;
+constexpr uint32_t PRIME_CEIL = 1431655765u;  // floor((2^32 - 1) / 3), odd; the table descends from here
 constexpr int MAX_POINTS = 8192;  // evaluation points (degree bound + 1) per job
 constexpr int MAX_GCD_DEGREE = 8000;
 
 struct HostTables {
   int K = 0;
-  std::vector<ModP> primes;     // K primes, descending from 2^31 - 1
+  std::vector<ModP> primes;     // K primes, descending from below PRIME_CEIL
   std::vector<double> log2p;    // lower bounds of log2 p_k
   std::vector<double> cumlog;   // cumlog[k] = sum_{i<k} log2p[i]
   std::vector<uint32_t> gm;     // [K][K] Montgomery (prod_{i<j} p_i mod p_k), j < k

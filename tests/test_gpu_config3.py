@@ -21,7 +21,7 @@ from oracle.resultant import bi_diff_y, discriminant_y, resultant_at_mod
 from paper_1201_1548_amd import synth
 
 pytestmark = pytest.mark.gpu
-Q = (1 << 61) - 1   # Mersenne prime, not in the 31-bit table
+Q = (1 << 61) - 1   # Mersenne prime, not in the prime table
 
 
 def say(*a):

@@ -5,6 +5,8 @@ the oracle (degree bound, Hadamard coefficient bound, prime table)."""
 import os
 import re
 
+import math
+
 import pytest
 import sympy as sp
 
@@ -32,8 +34,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_prime_table():
     ps = br.primes(300)
-    assert ps[0] == 2**31 - 1
-    assert all(2**30 < p < 2**31 for p in ps)
+    ceil = (2**32 - 1) // 3                        # 3p < 2^32: three-product reductions
+    assert not any(sp.isprime(c) for c in range(ps[0] + 1, ceil + 1))
+    assert all(2**30 < p and 3 * p < 2**32 for p in ps)
     assert all(a > b for a, b in zip(ps, ps[1:]))
     assert all(sp.isprime(p) for p in ps)
     # no prime skipped between consecutive table entries
@@ -58,7 +61,7 @@ def _check_plan(F, G, R, kind="res", var="y"):
     M = 1
     for p in ps:
         M *= p
-    assert M.bit_length() - 1 >= log2B + 1           # M > 2B
+    assert math.log2(M) > log2B + 1.001              # M > 2^1.001 B (margin of the explicit CRT)
     deg, L = br.bounds(F, G, kind, var)
     assert deg >= D - 1
     assert L >= (max((abs(c) for c in R), default=0).bit_length() + 1 + 31) // 32

@@ -23,7 +23,8 @@ import pytest
 from oracle.resultant import det_mod, sylvester
 
 R = 1 << 32
-PRIMES = [2147483647, 2147483629, 2147483587, 1073741827, 1073741831]
+CEIL = (R - 1) // 3          # the table's primes lie in (2^30, 2^32 / 3)
+PRIMES = [1431655751, 1431655747, 1431655739, 1073741827, 1073741831]
 
 
 def redc(t, p):
@@ -47,6 +48,10 @@ def mmul(a, b, p):
 
 def mdot2(a, b, c, d, p):
     return redc(a * b + c * d, p)
+
+
+def mdot3(a, b, c, d, e, f, p):
+    return redc(a * b + c * d + e * f, p)
 
 
 def mneg(x, p):
@@ -97,11 +102,12 @@ def eliminate(A, B, a, b, lb, p, fused):
     if fused and a == b + 1:
         n1 = mneg(A[a], p)
         n2 = mneg(mdot2(lb, A[a - 1], n1, B[b - 1], p), p)
+        l2, l1 = mmul(lb, lb, p), mmul(lb, n1, p)
         bp = B[0]
-        A[0] = mdot2(lb, mmul(lb, A[0], p), n2, bp, p)
+        A[0] = mdot2(l2, A[0], n2, bp, p)
         for t in range(1, b):
             y = B[t]
-            A[t] = mdot2(lb, mdot2(lb, A[t], n1, bp, p), n2, y, p)
+            A[t] = mdot3(l2, A[t], l1, bp, n2, y, p)
             bp = y
         return
     while a >= b:
@@ -152,9 +158,32 @@ def uni_resultant(A, B, m, n, p, fused=True):
         A, B, a, b = B, A, b, a
         neg ^= (a * b) & 1 == 1
     pfx = one
-    while b > 0:
+    # fast path of the kernel (one lane here): while each remainder has degree
+    # exactly b - 1, the step's exponent bookkeeping is x = [b > 1] and
+    # d = (1 - b)(a - b - 1)
+    eliminated, lb_done = False, 0
+    while fused and b > 0:
         lb = B[b]
         eliminate(A, B, a, b, lb, p, fused)
+        if A[b - 1] == 0:
+            eliminated, lb_done = True, lb
+            break
+        neg ^= (a * b) & 1 == 1
+        pfx = mmul(pfx, mmul(lb, lb, p), p)
+        if b > 1:
+            den = mmul(den, pfx, p)
+        d = (1 - b) * (a - b - 1)
+        if d > 0:
+            num = mmul(num, mpow(lb, d, p), p)
+        elif d < 0:
+            den = mmul(den, mpow(lb, -d, p), p)
+        A, B, a, b = B, A, b, b - 1
+    while b > 0:
+        lb = lb_done if eliminated else B[b]
+        if eliminated:
+            eliminated = False
+        else:
+            eliminate(A, B, a, b, lb, p, fused)
         c = b - 1
         while c >= 0 and A[c] == 0:
             c -= 1
@@ -215,7 +244,7 @@ def test_euclid_matches_sylvester_determinant(fused):
 
 
 def test_model_catches_a_planted_mistake():
-    # a wrong sign of the second multiplier of the fused step must be caught
+    # a wrong sign of a multiplier of the fused step must be caught
     rng = random.Random(5)
     p = PRIMES[0]
     bad = 0
@@ -257,7 +286,7 @@ def test_xcd_block_map_is_a_bijection_with_contiguous_xcd_ranges(nb):
 
 def _primes_desc(n):
     import sympy
-    out, c = [], (1 << 31) - 1
+    out, c = [], CEIL
     while len(out) < n:
         if sympy.isprime(c):
             out.append(c)
@@ -374,3 +403,58 @@ def test_digit_grouped_products_reconstruct_the_residue():
             assert all(abs(g) < 1 << 31 for g in G)
             got = sum((g % p) * wu for g, wu in zip(G, w)) % p
             assert got == sum(a * b for a, b in zip(A, B)) % p
+
+
+def crt_model_ranges(residues, primes, R=16, Lc=None):
+    """The limb kernel's staging of the explicit CRT: limb columns in ranges
+    of R, each range normalised to 32-bit limbs plus a signed carry out with
+    its own carry chain, then one pass adding each range's carry at the next
+    range's first limb; returns the two's-complement value of Lc limbs."""
+    import math
+    P = len(primes)
+    M = math.prod(primes)
+    LM = (M.bit_length() + 31) // 32
+    LMp = -(-LM // (4 * R)) * (4 * R)
+    Mk = [M // p for p in primes]
+    y = [x * pow(mk % p, -1, p) % p for x, mk, p in zip(residues, Mk, primes)]
+    f = 0.0
+    for yk, p in zip(y, primes):
+        f = math.fma(float(yk), 1.0 / p, f) if hasattr(math, "fma") else f + float(yk) * (1.0 / p)
+    t = int(f + 0.5)
+    limb = lambda v, l: (v >> (32 * l)) & 0xFFFFFFFF
+    Lb, Co = [0] * LMp, []
+    for r in range(LMp // R):
+        carry = 0
+        for j in range(R):
+            l = r * R + j
+            v = sum(yk * limb(mk, l) for yk, mk in zip(y, Mk)) - t * limb(M, l) + carry
+            Lb[l] = v & 0xFFFFFFFF
+            carry = v >> 32
+        assert abs(carry) < 1 << 63
+        Co.append(carry)
+    Lc = Lc or LM
+    out, carry = [], 0
+    for l in range(max(Lc, LMp + 1)):
+        acc = carry + (Lb[l] if l < LMp else 0)
+        if 0 < l <= LMp and l % R == 0:
+            acc += Co[l // R - 1]
+        out.append(acc & 0xFFFFFFFF)
+        carry = acc >> 32
+    assert carry in (0, -1)
+    val = sum(w << (32 * i) for i, w in enumerate(out[:Lc]))
+    sign = out[Lc - 1] >> 31
+    assert all(w == (0xFFFFFFFF if sign else 0) for w in out[Lc:])
+    return val - (1 << (32 * Lc)) if sign else val
+
+
+def test_explicit_crt_with_range_carries():
+    import math
+    from fractions import Fraction
+    primes = _primes_desc(70)
+    rng = random.Random(23)
+    for P in (1, 2, 17, 50, 70):
+        ps = primes[:P]
+        M = math.prod(ps)
+        B = int(Fraction(M) * Fraction(2.0 ** -1.001)) - 1
+        for R in [0, 1, -1, B, -B] + [rng.randint(-B, B) for _ in range(20)]:
+            assert crt_model_ranges([R % p for p in ps], ps) == R, (P, R)
