@@ -149,7 +149,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
       for (int which = 0; which < nsrc(i); ++which) {
         const Shape& s = shp(i, which);
         w[i].o_scan[which] = in.bytes;
-        in.bytes += (size_t)s.rows * 12;
+        in.bytes += (size_t)s.rows * ROWSTAT_WORDS * 4;
         for (int r0 = 0; r0 < s.rows; r0 += 64) smap.push_back(make_int4((int)tasks.size(), r0, 0, 0));
         tasks.push_back(ScanTask{});
       }
@@ -209,7 +209,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
         const int rows = shp(i, which).rows;
         const int32_t* v = (const int32_t*)(h_in.b() + w[i].o_scan[which]);
         RowStats& rs = which ? w[i].stg : w[i].stf;
-        rs.v.assign(v, v + 3 * (size_t)rows);
+        rs.v.assign(v, v + ROWSTAT_WORDS * (size_t)rows);
       }
     }
   }

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "job.hpp"
 #include "kernels.hpp"
@@ -35,9 +36,30 @@ __device__ __forceinline__ int find_job(const int* __restrict__ starts, int nj, 
   return lo;
 }
 
+// Global-memory view of a pointer the host guarantees to be device memory:
+// loads through it compile to global (not flat) loads, which do not share
+// the LDS wait counter.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
 // ---------------------------------------------------------------------------
 // planning statistics: for each row j of a rectangle, the x-degree, the
-// largest bit length of |c| and the number of non-zero coefficients.
+// largest bit length of |c|, the number of non-zero coefficients and an upper
+// bound of log2 of the row's 1-norm sum_i |c_ji| in 1/1024 bits (rounded up).
+// |c| is bounded by its top 64 magnitude bits plus one unit of the next limb
+// (double, raised by 2^-52), the sum by ld 2^-53 relative rounding (raised by
+// 2^-40), the logarithm by 10^-6.
+
+__device__ __forceinline__ double mag_upper(const uint32_t* c, int L) {
+  const uint32_t inv = (c[L - 1] >> 31) ? 0xFFFFFFFFu : 0u;  // |c| <= (c xor sign) + 1
+  int t = L - 1;
+  while (t > 0 && (c[t] ^ inv) == 0u) --t;
+  const uint64_t top = t ? (((uint64_t)(c[t] ^ inv) << 32) | (c[t - 1] ^ inv)) : (uint64_t)(c[0] ^ inv);
+  const double v = ((double)top + 1.0) * (1.0 + 0x1p-52);
+  return t ? ldexp(v, 32 * (t - 1)) : v;
+}
 
 __global__ void k_scan(const ScanTask* tasks, const int4* bmap) {
   int4 bm = bmap[blockIdx.x];
@@ -45,6 +67,7 @@ __global__ void k_scan(const ScanTask* tasks, const int4* bmap) {
   int j = bm.y + threadIdx.x;
   if (j >= T.rows) return;
   int deg = -1, bits = 0, cnt = 0;
+  double norm = 0.0;
   for (int i = 0; i < T.ld; ++i) {
     const uint32_t* c = T.limbs + ((size_t)j * T.ld + i) * T.L;
     uint32_t top = c[T.L - 1];
@@ -62,11 +85,13 @@ __global__ void k_scan(const ScanTask* tasks, const int4* bmap) {
       ++cnt;
       b += inv ? 1 : 0;
       bits = b > bits ? b : bits;
+      norm += mag_upper(c, T.L);
     }
   }
-  T.out[3 * j + 0] = deg;
-  T.out[3 * j + 1] = bits;
-  T.out[3 * j + 2] = cnt;
+  T.out[4 * j + 0] = deg;
+  T.out[4 * j + 1] = bits;
+  T.out[4 * j + 2] = cnt;
+  T.out[4 * j + 3] = cnt ? (int32_t)ceil((log2(norm * (1.0 + 0x1p-40)) + 1e-6) * 1024.0) : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -339,21 +364,30 @@ __device__ __forceinline__ uint32_t fold96(const Acc96& S, const ModP& q) {
   return madd(redc(t, q.p, q.pinv), reduce32((uint32_t)(S.lo >> 32), q.p), q.p);
 }
 
+// Read-only data with wave-uniform addresses, read through the scalar cache.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(4))) const uint32_t cu32;
+typedef __attribute__((address_space(4))) const u32x4 cu4;
+typedef __attribute__((address_space(4))) const int32_t ci32;
+
 // Value of the row c[0..d] (zero-padded to a multiple of 4, 16-byte aligned)
 // at the point whose powers are pw; apw = (a^EV_PW)_M.  d is wave-uniform.
-__device__ __forceinline__ uint32_t eval_row(const uint32_t* c, int d, const uint32_t (&pw)[EV_PW], uint32_t apw,
-                                             const ModP& q) {
+// With C = cu32 the coefficients come in by scalar loads and feed the
+// products as scalar operands (the data must not change during the launch);
+// with C = const uint32_t they are ordinary loads.
+template <class C, class C4>
+__device__ __forceinline__ uint32_t eval_row(C* c, int d, const uint32_t (&pw)[EV_PW], uint32_t apw, const ModP& q) {
   if (d < 0) return 0u;
   const int top = d / EV_PW;
   uint32_t acc = 0u;
   for (int ch = top; ch >= 0; --ch) {
-    const uint4* cc = (const uint4*)(c + ch * EV_PW);
+    C4* cc = (C4*)(c + ch * EV_PW);
     const int ng = (min(EV_PW, d + 1 - ch * EV_PW) + 3) >> 2;
     Acc96 S;
 #pragma unroll
     for (int g = 0; g < EV_PW / 4; ++g) {
       if (g < ng) {
-        const uint4 v = cc[g];
+        const u32x4 v = cc[g];
         uint64_t t = (uint64_t)v.x * pw[4 * g];
         t += (uint64_t)v.y * pw[4 * g + 1];
         t += (uint64_t)v.z * pw[4 * g + 2];
@@ -368,29 +402,28 @@ __device__ __forceinline__ uint32_t eval_row(const uint32_t* c, int d, const uin
 }
 
 // (b)+(c): each job has P * ceil(D/W) blocks, prime-major; one lane per
-// point a.  The block stages the prime's residues (rows at the padded
-// strides lpf, lpg) and the row degrees in LDS; each lane evaluates f(a, y),
-// g(a, y) into its own arrays and runs the elimination.  lds must be 16-byte
-// aligned.
-template <int W>
+// point a.  The prime's residues (rows at the padded strides lpf, lpg) and
+// the row degrees are read with wave-uniform addresses; LDS holds only each
+// lane's coefficient arrays, so more blocks fit on a CU.  SC: through the
+// scalar cache, which is valid when the residues were written by an earlier
+// launch (the staged schedule); the persistent fused launch, which writes
+// them itself, uses ordinary loads.
+template <int W, bool SC>
 __device__ __forceinline__ void dev_eval_elim(const JobDev& J, int lb, TablesDev tab, uint32_t* lds) {
+  typedef typename std::conditional<SC, cu32, const uint32_t>::type RW;
+  typedef typename std::conditional<SC, cu4, const u32x4>::type RW4;
+  typedef typename std::conditional<SC, ci32, const int32_t>::type RI;
   const int nbpp = (J.D + W - 1) / W;
   const int k = lb / nbpp;
   const int a0 = (lb - k * nbpp) * W;
   const int m = J.m, n = J.n;
   const int Tf = J.Tf, Tg = J.Tg, lpf = J.lpf, lpg = J.lpg;
-  uint32_t* R = lds;                                 // residues: f rows, then g rows
-  int32_t* RD = (int32_t*)(lds + Tf + Tg);           // row degrees: f, then g
-  uint32_t* A = lds + Tf + Tg + (m + n + 2) + threadIdx.x;
+  RW* Rf = (RW*)(J.res_f + (size_t)k * Tf);
+  RW* Rg = (RW*)(J.res_g + (size_t)k * Tg);
+  RI* RDf = (RI*)J.rowdeg_f;
+  RI* RDg = (RI*)J.rowdeg_g;
+  uint32_t* A = lds + threadIdx.x;
   uint32_t* B = A + (m + 1) * W;
-  const uint4* rf = (const uint4*)(J.res_f + (size_t)k * Tf);
-  const uint4* rg = (const uint4*)(J.res_g + (size_t)k * Tg);
-  uint4* R4 = (uint4*)R;
-  for (int i = threadIdx.x; i < Tf / 4; i += W) R4[i] = rf[i];
-  for (int i = threadIdx.x; i < Tg / 4; i += W) R4[Tf / 4 + i] = rg[i];
-  for (int i = threadIdx.x; i <= m; i += W) RD[i] = J.rowdeg_f[i];
-  for (int i = threadIdx.x; i <= n; i += W) RD[m + 1 + i] = J.rowdeg_g[i];
-  __syncthreads();
   const int pt = a0 + (int)threadIdx.x;
   if (pt >= J.D) return;
   const ModP q = tab.primes[k];
@@ -402,9 +435,9 @@ __device__ __forceinline__ void dev_eval_elim(const JobDev& J, int lb, TablesDev
   for (int i = 1; i < EV_PW; ++i) pw[i] = i <= dmax ? mmul(pw[i - 1], aM, q) : 0u;
   const uint32_t apw = dmax >= EV_PW ? mmul(pw[EV_PW - 1], aM, q) : 0u;
   for (int j = 0; j <= m; ++j)
-    A[j * W] = eval_row(R + j * lpf, __builtin_amdgcn_readfirstlane(RD[j]), pw, apw, q);
+    A[j * W] = eval_row<RW, RW4>(Rf + j * lpf, __builtin_amdgcn_readfirstlane(RDf[j]), pw, apw, q);
   for (int j = 0; j <= n; ++j)
-    B[j * W] = eval_row(R + Tf + j * lpg, __builtin_amdgcn_readfirstlane(RD[m + 1 + j]), pw, apw, q);
+    B[j * W] = eval_row<RW, RW4>(Rg + j * lpg, __builtin_amdgcn_readfirstlane(RDg[j]), pw, apw, q);
   const uint32_t r = uni_resultant<W>(A, B, m, n, q);
   J.vals[(size_t)k * J.D + pt] = from_mont(r, q);
 }
@@ -424,7 +457,7 @@ __global__ __launch_bounds__(W) void k_eval_elim(const JobDev* jobs, const int* 
   extern __shared__ __align__(16) uint32_t lds[];
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int job = find_job(starts, nj, b);
-  dev_eval_elim<W>(jobs[job], b - starts[job], tab, lds);
+  dev_eval_elim<W, true>(jobs[job], b - starts[job], tab, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -646,20 +679,34 @@ __global__ __launch_bounds__(256) void k_vinv(int D, int Dp, TablesDev tab, int8
   }
 }
 
-// Digit planes of the values: Yp[k][t][n][a] for the group's jobs gj[0..N),
-// zero for n >= N or a >= D.  Grid (Np, P), 256 threads over a.
+// Digit planes of the values for the group's jobs gj[0..N), zero for n >= N
+// or a >= D.  One thread per 16 consecutive nodes of one job: 16 values in,
+// one aligned 16-byte chunk out per plane.  Grid (ceil(Np Dp / 16 / 256), P).
 __global__ __launch_bounds__(256) void k_yplanes(const JobDev* jobs, const int* gj, int N, int Np, int D, int Dp,
                                                  TablesDev tab, int8_t* Yp) {
-  const int n = blockIdx.x, k = blockIdx.y;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x, k = blockIdx.y;
+  const int per = Dp >> 4;
+  if (idx >= Np * per) return;
+  const int n = idx / per, a0 = (idx - n * per) * 16;
   const uint32_t p = tab.primes[k].p;
   const size_t plane = (size_t)Np * Dp;
-  int8_t* base = Yp + (size_t)k * 4 * plane;
+  int8_t* base = Yp + (size_t)k * 4 * plane + im_off(n, a0, Dp);
   const uint32_t* v = n < N ? jobs[gj[n]].vals + (size_t)k * D : nullptr;
-  for (int a = threadIdx.x; a < Dp; a += blockDim.x)
-    put_digits(base, plane, im_off(n, a, Dp), v && a < D ? digits4(v[a], p) : 0u);
+  uint32_t d[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) d[u] = v && a0 + u < D ? digits4(v[a0 + u], p) : 0u;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    uint32_t w[4];
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4)
+      w[q4] = ((d[4 * q4] >> (8 * s)) & 255u) | (((d[4 * q4 + 1] >> (8 * s)) & 255u) << 8) |
+              (((d[4 * q4 + 2] >> (8 * s)) & 255u) << 16) | (((d[4 * q4 + 3] >> (8 * s)) & 255u) << 24);
+    *(uint4*)(base + s * plane) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
 }
 
-// One wave per 32 x 32 tile of C for prime k: grid (Dp/32, Np/32, P).
+// One wave per 32 x 32 tile of C for one prime: (Dp/32) (Np/32) P blocks.
 // Accumulator register r of lane l holds row 8 (r/4) + 4 (l/32) + r%4 and
 // column l%32 of the tile; operand lanes hold row (A) or column (Y) l%32 and
 // contraction indices 16 (l/32) + 0..15 of the 32-wide step.  The operands of
@@ -687,11 +734,17 @@ __global__ __launch_bounds__(64) void k_interp_mfma(const JobDev* jobs, const in
                                                     const int8_t* Ap, const int8_t* Yp, TablesDev tab) {
   __shared__ uint32_t tile[32][33];
   const int l = threadIdx.x, r32 = l & 31, g = l >> 5;
-  const int i0 = blockIdx.x * 32, n0 = blockIdx.y * 32, k = blockIdx.z;
+  // one-dimensional grid in XCD order: the tiles of one prime, which share
+  // its operand planes, run on one XCD and share its L2
+  const int nit = Dp >> 5, nnt = Np >> 5;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int k = lb / (nit * nnt), rem = lb - k * nit * nnt;
+  const int it = rem % nit, nt = rem / nit;
+  const int i0 = it * 32, n0 = nt * 32;
   const size_t pa = (size_t)Dp * Dp, py = (size_t)Np * Dp;
   // operand-order blocks: 1 KiB per (row tile, step); a lane reads bytes 16 l..16 l + 15
-  const int8_t* A = Ap + (size_t)k * 4 * pa + (size_t)blockIdx.x * Dp * 32 + 16 * l;
-  const int8_t* Y = Yp + (size_t)k * 4 * py + (size_t)blockIdx.y * Dp * 32 + 16 * l;
+  const int8_t* A = Ap + (size_t)k * 4 * pa + (size_t)it * Dp * 32 + 16 * l;
+  const int8_t* Y = Yp + (size_t)k * 4 * py + (size_t)nt * Dp * 32 + 16 * l;
   im_v16i G0 = {0}, G1 = {0}, G2 = {0}, G3 = {0}, G4 = {0}, G5 = {0}, G6 = {0};
   ImOps cur = im_load(A, Y, pa, py, 0);
   for (int a0 = 0; a0 < Dp; a0 += 32) {
@@ -903,6 +956,7 @@ __device__ void dev_limbs_carry(const JobDev& J, int lb, int stage_ld, uint32_t*
   const int Lc = J.Lcap, D = J.D;
   const bool staged = stage_ld > 0;
   const int ld = stage_ld;
+  bool nz = false;
   if (c <= J.degcap) {
     uint32_t* o = staged ? lds + threadIdx.x * ld : J.out + (size_t)c * Lc;
     if (c >= D) {
@@ -911,7 +965,7 @@ __device__ void dev_limbs_carry(const JobDev& J, int lb, int stage_ld, uint32_t*
       const int neg = J.negflag[c];
       const uint32_t flip = neg ? 0xFFFFFFFFu : 0u;
       uint64_t carry = 0;  // < 2^50
-      bool nz = neg != 0;
+      nz = neg != 0;
       uint32_t last = 0;
       for (int l = 0; l < Lc; ++l) {
         uint64_t lo = 0;
@@ -929,8 +983,12 @@ __device__ void dev_limbs_carry(const JobDev& J, int lb, int stage_ld, uint32_t*
         o[l] = last;
       }
       if (carry != 0u || ((last >> 31) != (flip >> 31))) atomicOr(J.err, 1);
-      if (nz) atomicMax(J.deg_out, c);
     }
+  }
+  {
+    // one atomic per wave: the highest non-zero coefficient of the 64
+    const uint64_t any = __ballot(nz);
+    if (any && threadIdx.x == 0) atomicMax(J.deg_out, c0 + 63 - __clzll((long long)any));
   }
   if (staged) {
     __syncthreads();
@@ -971,7 +1029,7 @@ __device__ __forceinline__ void dev_crt(const JobDev& J, int lb, int stage_ld, T
   const int P = J.P, D = J.D, Lc = J.Lcap, LM = J.crt_LM;
   const int LMp = (LM + 4 * CRT_R - 1) / (4 * CRT_R) * (4 * CRT_R);
   const int npass = LMp / (4 * CRT_R);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c0 = lb * 64, c = c0 + lane;
   if (c0 >= D) {
     // beyond the degree bound: zero coefficients up to the output capacity
@@ -1000,13 +1058,35 @@ __device__ __forceinline__ void dev_crt(const JobDev& J, int lb, int stage_ld, T
   for (int i = threadIdx.x; i < P; i += blockDim.x) wv[i] = gw[i];
   for (int i = threadIdx.x; i < LMp; i += blockDim.x) Ms[i] = i < LM ? gM[i] : 0u;
   __syncthreads();
-  for (int k = wave; k < P; k += 4)
-    Y[k * 64 + lane] = c < D ? mmul(J.coefs[(size_t)k * D + c], wv[k], tab.primes[k]) : 0u;
-  __syncthreads();
-  if (wave == 0) {
+  // y_k for primes k = wave + 4 u, eight loads in flight per batch; each wave
+  // also sums its share of y_k / p_k
+  {
+    const __attribute__((address_space(1))) uint32_t* co = gmem(J.coefs) + (c < D ? c : 0);
     double f = 0.0;
-    for (int k = 0; k < P; ++k) f = fma((double)Y[k * 64 + lane], tab.inv_p[k], f);
-    Tq[lane] = (int32_t)(f + 0.5);
+    for (int k0 = wave; k0 < P; k0 += 32) {
+      uint32_t x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + 4 * u;
+        x[u] = (k < P && c < D) ? co[(size_t)k * D] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + 4 * u;
+        if (k < P) {
+          const uint32_t y = mmul(x[u], wv[k], tab.primes[k]);
+          Y[k * 64 + lane] = y;
+          f = fma((double)y, tab.inv_p[k], f);
+        }
+      }
+    }
+    double* part = (double*)(lds + co_off + (co_off & 1)) + 0;  // reuses the carry area (free until the sums)
+    part[wave * 64 + lane] = f;
+    __syncthreads();
+    if (wave == 0) {
+      const double ft = ((part[lane] + part[64 + lane]) + part[128 + lane]) + part[192 + lane];
+      Tq[lane] = (int32_t)(ft + 0.5);
+    }
   }
   __syncthreads();
   // column sums of the wave's CRT_R limbs per pass, prime-outer; then the
@@ -1054,6 +1134,7 @@ __device__ __forceinline__ void dev_crt(const JobDev& J, int lb, int stage_ld, T
   }
   __syncthreads();
   const bool staged = stage_ld > 0;
+  bool nz = false;
   if (wave == 0 && c <= J.degcap) {
     uint32_t* o = staged ? Y + lane * stage_ld : J.out + (size_t)c * Lc;
     if (c >= D) {
@@ -1061,7 +1142,7 @@ __device__ __forceinline__ void dev_crt(const JobDev& J, int lb, int stage_ld, T
     } else {
       // limbs of the ranges plus the carries out of the ranges below them
       int64_t carry = 0;
-      bool nz = false, bad = false;
+      bool bad = false;
       uint32_t last = 0;
       const int Lrun = max(Lc, LM);
       for (int l = 0; l < Lrun; ++l) {
@@ -1092,8 +1173,12 @@ __device__ __forceinline__ void dev_crt(const JobDev& J, int lb, int stage_ld, T
         carry = rest;
       }
       if (bad || carry != ((int32_t)last < 0 ? -1 : 0)) atomicOr(J.err, 1);
-      if (nz) atomicMax(J.deg_out, c);
     }
+  }
+  if (wave == 0) {
+    // one atomic per wave: the highest non-zero coefficient of the 64
+    const uint64_t any = __ballot(nz);
+    if (any && lane == 0) atomicMax(J.deg_out, c0 + 63 - __clzll((long long)any));
   }
   if (staged) {
     __syncthreads();
@@ -1173,7 +1258,7 @@ __global__ __launch_bounds__(64) void k_fused(FusedPlan F, TablesDev tab) {
     }
     __syncthreads();
     if (stage == FS_RED) dev_reduce(J, lb, 0, P, tab);
-    else if (stage == FS_EE) dev_eval_elim<64>(J, lb, tab, lds);
+    else if (stage == FS_EE) dev_eval_elim<64, false>(J, lb, tab, lds);
     else if (stage == FS_IP) dev_interp(J, lb, tab, lds);
     else if (stage == FS_MRC) {
       if (F.mrc_lane) dev_mrc_lane(J, lb, tab, lds);
@@ -1340,7 +1425,10 @@ void launch_reduce(const JobDev* jobs, const int* starts, int nj, int nblocks, i
 
 int eval_elim_block() { return 64; }
 
-size_t eval_elim_lds_bytes(int words, int res) { return ((size_t)words * 65 + res) * sizeof(uint32_t); }
+size_t eval_elim_lds_bytes(int words, int res) {
+  (void)res;  // residues are read through the scalar cache
+  return (size_t)words * 64 * sizeof(uint32_t);
+}
 
 void launch_eval_elim(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_words, int max_res,
                       TablesDev tab, hipStream_t s) {
@@ -1363,8 +1451,10 @@ void launch_vinv(int D, int Dp, int P, TablesDev tab, int8_t* Ap, hipStream_t s)
 void launch_interp_mfma(const JobDev* jobs, const int* gj, int N, int D, int P, const int8_t* Ap, int8_t* Yp,
                         TablesDev tab, hipStream_t s) {
   const int Dp = (D + 31) & ~31, Np = (N + 31) & ~31;
-  hipLaunchKernelGGL(k_yplanes, dim3(Np, P), dim3(256), 0, s, jobs, gj, N, Np, D, Dp, tab, Yp);
-  hipLaunchKernelGGL(k_interp_mfma, dim3(Dp / 32, Np / 32, P), dim3(64), 0, s, jobs, gj, N, Np, D, Dp, Ap, Yp, tab);
+  const int chunks = Np * (Dp / 16);
+  hipLaunchKernelGGL(k_yplanes, dim3((chunks + 255) / 256, P), dim3(256), 0, s, jobs, gj, N, Np, D, Dp, tab, Yp);
+  hipLaunchKernelGGL(k_interp_mfma, dim3((Dp / 32) * (Np / 32) * P), dim3(64), 0, s, jobs, gj, N, Np, D, Dp, Ap, Yp,
+                     tab);
 }
 
 bool mrc_lane_ok(int max_primes, long long total_coefficients) {

@@ -10,13 +10,15 @@
 // 1-norm N_j of f_j, so Hadamard's inequality bounds |R(x)| by
 // (sum N_j^2)^{n/2} (sum N'_j^2)^{m/2}, and by Cauchy's estimate on the unit
 // circle every coefficient of R is bounded by the same number B.  Reconstruction
-// modulo M = prod p_k is exact once M > 2B (symmetric residues).  N_j is
-// bounded by cnt_j 2^{bits_j}; all sums are done in log2 with a margin.
+// modulo M = prod p_k is exact once M > 2B (symmetric residues).  N_j comes
+// from the row scan as an upper bound of log2 N_j in 1/1024 bits; all sums are
+// done in log2 with a margin.
 #include "plan.hpp"
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/bires.h"
 #include "tables.hpp"
@@ -36,21 +38,38 @@ static int bitlen_abs(const uint32_t* c, int L, bool* nonzero) {
   return nz ? b + (inv ? 1 : 0) : 0;
 }
 
+int32_t log2_fx_up(double x) { return (int32_t)std::ceil((std::log2(x) + 1e-6) * 1024.0); }
+
+// Upper bound of |c| as a double: the top 64 magnitude bits plus one unit of
+// the next limb, raised by 2^-52 against the rounding of the conversion.
+static double mag_upper(const uint32_t* c, int L) {
+  const uint32_t inv = (c[L - 1] >> 31) ? 0xFFFFFFFFu : 0u;
+  int t = L - 1;
+  while (t > 0 && (c[t] ^ inv) == 0u) --t;
+  const uint64_t top = t ? (((uint64_t)(c[t] ^ inv) << 32) | (c[t - 1] ^ inv)) : (uint64_t)(c[0] ^ inv);
+  const double v = ((double)top + 1.0) * (1.0 + 0x1p-52);
+  return t ? std::ldexp(v, 32 * (t - 1)) : v;
+}
+
 RowStats scan_host(const uint32_t* limbs, int rows, int ld, int L) {
   RowStats s;
   s.resize(rows);
   for (int j = 0; j < rows; ++j) {
     int deg = -1, bits = 0, cnt = 0;
+    double norm = 0.0;
     for (int i = 0; i < ld; ++i) {
       bool nz;
-      const int b = bitlen_abs(limbs + ((size_t)j * ld + i) * L, L, &nz);
+      const uint32_t* c = limbs + ((size_t)j * ld + i) * L;
+      const int b = bitlen_abs(c, L, &nz);
       if (nz) {
         deg = i;
         cnt++;
         bits = std::max(bits, b);
+        norm += mag_upper(c, L);
       }
     }
-    s.set(j, deg, bits, cnt);
+    // the sum's rounding (at most ld 2^-53 relative) is covered by 2^-40
+    s.set(j, deg, bits, cnt, cnt ? log2_fx_up(norm * (1.0 + 0x1p-40)) : 0);
   }
   return s;
 }
@@ -62,7 +81,9 @@ RowStats derive_stats(const RowStats& f) {
   g.resize(rows);
   for (int j = 0; j < rows; ++j) {
     const int lj = 32 - __builtin_clz((uint32_t)(j + 1));  // (j+1) < 2^lj
-    g.set(j, f.deg(j + 1), f.cnt(j + 1) ? f.bits(j + 1) + lj : 0, f.cnt(j + 1));
+    // row j of the derivative is (j+1) times row j+1: its 1-norm scales by j+1
+    g.set(j, f.deg(j + 1), f.cnt(j + 1) ? f.bits(j + 1) + lj : 0, f.cnt(j + 1),
+          f.cnt(j + 1) ? f.norm(j + 1) + log2_fx_up((double)(j + 1)) : 0);
   }
   return g;
 }
@@ -70,7 +91,7 @@ RowStats derive_stats(const RowStats& f) {
 RowStats worst_stats(int rows, int ld, int L) {
   RowStats s;
   s.resize(rows);
-  for (int j = 0; j < rows; ++j) s.set(j, ld - 1, 32 * L, ld);
+  for (int j = 0; j < rows; ++j) s.set(j, ld - 1, 32 * L, ld, log2_fx_up((double)ld) + 1024 * 32 * L);
   return s;
 }
 
@@ -89,18 +110,37 @@ static double pow2_nonpos(int e) {
   return d;
 }
 
-// log2 (sum_j N_j^2) with N_j <= cnt_j 2^bits_j, rows 0..top: the terms
-// cnt_j^2 4^(bits_j - bmax) are exact in double (cnt_j^2 < 2^53, power-of-two
-// scaling; a term below 2^-1022 of the largest one is dropped, far inside the
-// margin of hadamard_log2), so one log2 per call remains.
+// 2^(r / 1024) for r = 0..1023.
+static const double* frac_pow2() {
+  static double t[1024];
+  static std::once_flag once;
+  std::call_once(once, [] {
+    for (int r = 0; r < 1024; ++r) t[r] = std::exp2(r / 1024.0);
+  });
+  return t;
+}
+
+// log2 (sum_j N_j^2) with log2 N_j <= norm_j / 1024, rows 0..top: each term
+// 2^((2 norm_j - 2 emax) / 1024) is a power of two times a table entry (a term
+// below 2^-1022 of the largest one is dropped, far inside the margin of
+// hadamard_log2), so one log2 per call remains.
 static double log2_sum_sq(const RowStats& s, int top) {
-  int bmax = 0;
+  const double* fr = frac_pow2();
+  bool any = false;
+  int emax = 0;
   for (int j = 0; j <= top; ++j)
-    if (s.cnt(j)) bmax = std::max(bmax, (int)s.bits(j));
+    if (s.cnt(j)) {
+      emax = any ? std::max(emax, (int)s.norm(j)) : (int)s.norm(j);
+      any = true;
+    }
   double acc = 0.0;
   for (int j = 0; j <= top; ++j)
-    if (s.cnt(j)) acc += (double)s.cnt(j) * (double)s.cnt(j) * pow2_nonpos(2 * (s.bits(j) - bmax));
-  return 2.0 * bmax + std::log2(acc);
+    if (s.cnt(j)) {
+      const int e = 2 * (s.norm(j) - emax);  // <= 0, in 1/1024 bits
+      const int q = e >= 0 ? 0 : -((-e + 1023) / 1024);
+      acc += pow2_nonpos(q) * fr[e - 1024 * q];
+    }
+  return 2.0 * emax / 1024.0 + std::log2(acc);
 }
 
 double hadamard_log2(const RowStats& f, int m, const RowStats& g, int n) {

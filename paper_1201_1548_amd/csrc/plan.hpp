@@ -9,21 +9,27 @@
 namespace bires {
 
 // Per-row statistics of a bivariate input (rows = powers of the eliminated
-// variable): x-degree (-1 for a zero row), bit length bound of |c| (|c| < 2^bits)
-// and non-zero count, interleaved per row as the device scan writes them.
+// variable): x-degree (-1 for a zero row), bit length bound of |c| (|c| < 2^bits),
+// non-zero count and an upper bound of log2 of the row's 1-norm in 1/1024
+// bits, interleaved per row as the device scan writes them.
+constexpr int ROWSTAT_WORDS = 4;
 struct RowStats {
-  std::vector<int32_t> v;  // [rows][3]: deg, bits, cnt
-  int rows() const { return (int)(v.size() / 3); }
-  int32_t deg(int j) const { return v[3 * j]; }
-  int32_t bits(int j) const { return v[3 * j + 1]; }
-  int32_t cnt(int j) const { return v[3 * j + 2]; }
-  void resize(int rows) { v.assign((size_t)3 * rows, 0); }
-  void set(int j, int32_t d, int32_t b, int32_t c) {
-    v[3 * j] = d;
-    v[3 * j + 1] = b;
-    v[3 * j + 2] = c;
+  std::vector<int32_t> v;  // [rows][4]: deg, bits, cnt, norm
+  int rows() const { return (int)(v.size() / ROWSTAT_WORDS); }
+  int32_t deg(int j) const { return v[ROWSTAT_WORDS * j]; }
+  int32_t bits(int j) const { return v[ROWSTAT_WORDS * j + 1]; }
+  int32_t cnt(int j) const { return v[ROWSTAT_WORDS * j + 2]; }
+  int32_t norm(int j) const { return v[ROWSTAT_WORDS * j + 3]; }  // ceil(1024 log2 sum |c|)
+  void resize(int rows) { v.assign((size_t)ROWSTAT_WORDS * rows, 0); }
+  void set(int j, int32_t d, int32_t b, int32_t c, int32_t n) {
+    v[ROWSTAT_WORDS * j] = d;
+    v[ROWSTAT_WORDS * j + 1] = b;
+    v[ROWSTAT_WORDS * j + 2] = c;
+    v[ROWSTAT_WORDS * j + 3] = n;
   }
 };
+// ceil(1024 log2 x) + margin for x > 0, the fixed-point logarithm of RowStats.
+int32_t log2_fx_up(double x);
 
 struct Plan {
   int m = -1, n = -1;       // degrees in y of f and g (-1: zero polynomial)
