@@ -336,6 +336,7 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain path (profiling runs)")
+    ap.add_argument("--no-graphs", action="store_true", help="skip the graph-replay leg")
     ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5", "copy"])
     ap.add_argument("--schedule", default="auto", choices=["auto", "staged", "fused"])
     ap.add_argument("--requests", type=int, default=300)
@@ -395,6 +396,25 @@ def main():
     host_us, host_calls = br.host_time()
     br.set_timing(False)
     value = n * args.steps / dt
+
+    # the same steps replayed from a captured HIP graph (checked bit-exact)
+    graph = None
+    if not args.no_graphs:
+        br.set_graphs(True)
+        try:
+            batch.run()
+            torch.cuda.synchronize()
+            graph_exact = batch.results() == res_batch
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                batch.run()
+            torch.cuda.synchronize()
+            dtg = time.perf_counter() - t0
+            caps, reps = br.graph_stats()
+        finally:
+            br.set_graphs(False)
+        graph = {"value": round(n * args.steps / dtg, 2), "ms_per_step": round(dtg / args.steps * 1e3, 3),
+                 "bit_exact": graph_exact, "captures": caps, "replays": reps}
 
     # plain path: one call per pair, same pairs, same buffers
     exact_plain = None
@@ -456,6 +476,7 @@ def main():
         "bit_exact": {"batched_vs_plain": exact_plain, "pair0_vs_oracle_golden": exact_golden},
         "device": dev,
         "host_us_per_step": {k: round(v / max(host_calls, 1), 1) for k, v in host_us.items()},
+        "graph_replay": graph,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -197,6 +197,18 @@ int bires_debug_values(const bires_bipoly *f, const bires_bipoly *g, int kind, i
 #define BIRES_SCHEDULE_AUTO 2
 int bires_set_schedule(int schedule);
 
+/* Graph replay: when enabled, batched calls issue their device sequence
+ * (metadata upload, the stage kernels of the chosen schedule, status and
+ * host-output copies) as a captured HIP graph, one per distinct set of launch
+ * arguments (workspace addresses, sizes, grids), replayed by later calls with
+ * the same arguments; at most 32 graphs are kept.  Zero fills of special
+ * results are issued outside the graph.  Results are identical to eager issue;
+ * kernel timing (bires_set_timing) does not cover graph replays.  Disabling
+ * waits for the device and destroys the cached graphs.  Process-wide. */
+int bires_set_graphs(int enable);
+/* Graphs captured and cached graphs replayed since the library was set up. */
+int bires_graph_stats(int64_t *captures, int64_t *replays);
+
 /* Autotuner: runs the batch (arguments as bires_resultant_batch) under every
  * schedule, keeps the fastest (best of `reps` timed runs after one warm-up) for
  * the batch's size key (total (prime, point) instances, largest degree sum in

@@ -78,6 +78,8 @@ _SIGS = {
                             ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "bires_set_timing": ([ctypes.c_int], ctypes.c_int),
     "bires_set_schedule": ([ctypes.c_int], ctypes.c_int),
+    "bires_set_graphs": ([ctypes.c_int], ctypes.c_int),
+    "bires_graph_stats": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "bires_autotune": ([ctypes.c_int, ctypes.POINTER(Bipoly), ctypes.POINTER(Bipoly),
                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Upoly),
                         ctypes.POINTER(ctypes.c_int32), ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
@@ -358,6 +360,19 @@ def set_schedule(schedule):
     """Launch schedule of batched calls: 'staged', 'fused' or 'auto'."""
     code = {"staged": 0, "fused": 1, "auto": 2}[schedule] if isinstance(schedule, str) else schedule
     _check(lib().bires_set_schedule(code), "bires_set_schedule")
+
+
+def set_graphs(enable):
+    """Replay each batched call's device sequence as a captured HIP graph."""
+    _check(lib().bires_set_graphs(1 if enable else 0), "bires_set_graphs")
+
+
+def graph_stats():
+    """(graphs captured, cached graphs replayed) since the library was set up."""
+    c = ctypes.c_int64()
+    r = ctypes.c_int64()
+    _check(lib().bires_graph_stats(ctypes.byref(c), ctypes.byref(r)), "bires_graph_stats")
+    return c.value, r.value
 
 
 def set_timing(enable):

@@ -164,6 +164,31 @@ int bires_set_timing(int enable) {
   return BIRES_OK;
 }
 
+int bires_set_graphs(int enable) {
+  int err = BIRES_OK;
+  Context* cx = context(&err);
+  if (!cx) return err;
+  std::lock_guard<std::mutex> lk(cx->graph_mu);
+  cx->graphs = enable != 0;
+  if (!cx->graphs && !cx->graph_cache.empty()) {
+    if (hipDeviceSynchronize() != hipSuccess) return BIRES_EDEVICE;
+    for (auto& kv : cx->graph_cache) (void)hipGraphExecDestroy(kv.second);
+    cx->graph_cache.clear();
+    cx->graph_order.clear();
+  }
+  return BIRES_OK;
+}
+
+int bires_graph_stats(int64_t* captures, int64_t* replays) {
+  int err = BIRES_OK;
+  Context* cx = context(&err);
+  if (!cx) return err;
+  std::lock_guard<std::mutex> lk(cx->graph_mu);
+  if (captures) *captures = cx->graph_captures;
+  if (replays) *replays = cx->graph_replays;
+  return BIRES_OK;
+}
+
 int bires_set_schedule(int schedule) {
   if (schedule < BIRES_SCHEDULE_STAGED || schedule > BIRES_SCHEDULE_AUTO) return BIRES_EINVAL;
   int err = BIRES_OK;

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <type_traits>
 
 #include "engine.hpp"
 #include "kernels.hpp"
@@ -88,6 +89,30 @@ static int validate(const JobIn& jb, bool need_out) {
   } while (0)
 
 namespace {
+// FNV-1a hash of the arguments of a device call sequence.
+struct SeqHash {
+  uint64_t h = 1469598103934665603ull;
+  void bytes(const void* p, size_t n) {
+    const unsigned char* c = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  }
+  template <class T>
+  void one(const T& v) {
+    static_assert(std::is_arithmetic<T>::value || std::is_pointer<T>::value || std::is_enum<T>::value,
+                  "hash scalars and pointers only");
+    bytes(&v, sizeof v);
+  }
+  void one(const FusedPlan& F) {
+    one(F.jobs), one(F.nj), one(F.head), one(F.ctr), one(F.ctr_off), one(F.err), one(F.stage_ld), one(F.mrc_lane);
+    for (int k = 0; k < 6; ++k) one(F.st[k]);
+    for (int k = 0; k < 7; ++k) one(F.base[k]);
+  }
+  template <class... A>
+  void add(const A&... a) {
+    (one(a), ...);
+  }
+};
+
 // Host time per phase of a batched call (microseconds), accumulated into the
 // context when timing is enabled.
 struct HostClock {
@@ -329,13 +354,17 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   std::vector<std::pair<const uint32_t*, int>> crt(nj, {nullptr, 0});
   bool use_crt = !debug && !fused && crt_ok(maxP);
   int maxLM = 1;
+  int lastP = -1, lastLM = 0;
+  const uint32_t* lastd = nullptr;
   for (int i = 0; i < nj && use_crt; ++i) {
     if (w[i].status || !w[i].active) continue;
-    int LM = 0;
-    const uint32_t* d = crt_device(cx, w[i].pl.P, &LM);
-    if (!d) use_crt = false;
-    crt[i] = {d, LM};
-    maxLM = std::max(maxLM, LM);
+    if (w[i].pl.P != lastP) {  // consecutive jobs mostly share P
+      lastP = w[i].pl.P;
+      lastd = crt_device(cx, lastP, &lastLM);
+    }
+    if (!lastd) use_crt = false;
+    crt[i] = {lastd, lastLM};
+    maxLM = std::max(maxLM, lastLM);
   }
   if (use_crt && crt_lds_bytes(maxP, maxLM, maxLcap) > cx->lds_per_block) use_crt = false;
   // staged schedule: interpolation on the matrix cores when at least 32 jobs
@@ -361,7 +390,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   // metadata uploaded with one copy: descriptors, flags, row degrees, block maps
   const size_t meta_begin = ws.take(0);
   const size_t o_jobs = ws.take(sizeof(JobDev) * (size_t)nj);
-  const size_t o_flags = ws.take(sizeof(int32_t) * 2 * (size_t)nj);
+  const size_t o_flags = ws.take(sizeof(int32_t) * (2 * (size_t)nj + 1));  // [deg_out, err] per job, fused error
   for (int i = 0; i < nj; ++i)
     if (!w[i].status && w[i].active) w[i].o_rowdeg = ws.take((size_t)(w[i].pl.m + w[i].pl.n + 2) * 4);
   const size_t o_maps = ws.take(sizeof(int) * (size_t)NK * (nj + 1));
@@ -402,6 +431,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   for (int i = 0; i < nj; ++i) {
     h_flags[2 * i] = -1;
     h_flags[2 * i + 1] = 0;
+    if (i == nj - 1) h_flags[2 * nj] = 0;
     h_jobs[i] = JobDev{};
     Work& x = w[i];
     if (x.status || !x.active) continue;
@@ -459,22 +489,31 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   }
   auto nb_of = [&](int kk) { return starts[kk][nj]; };
   hc.mark(3);
-  if (meta_end > meta_begin)
-    DEV(hipMemcpyAsync(D0 + meta_begin, h_meta.p, meta_end - meta_begin, hipMemcpyHostToDevice, st));
+  // special results of device-memory outputs are written on the stream
+  // (outside any captured graph: memset nodes are not used in graphs)
+  for (int i = 0; i < nj && !debug; ++i) {
+    const Work& x = w[i];
+    if (x.status || x.active || mem != BIRES_MEM_DEVICE) continue;
+    bires_upoly* o = jobs[i].out;
+    DEV(hipMemsetAsync(o->c, 0, (size_t)(x.degcap + 1) * x.Lout * 4, st));
+    if (x.pl.kind_special == 2) {
+      static const uint32_t one = 1u;
+      DEV(hipMemcpyAsync(o->c, &one, 4, hipMemcpyHostToDevice, st));
+    }
+  }
   const JobDev* d_jobs = (const JobDev*)(D0 + o_jobs);
-
-  // ---------------- kernels
   int nb_ee = 0;
   for (int bk = 0; bk < NBUCKET; ++bk) nb_ee += nb_of(K_EE0 + bk);
-  const bool timing = cx->timing && nb_ee > 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  if (timing) {
-    DEV(hipEventCreate(&ev0));
-    DEV(hipEventCreate(&ev1));
-  }
   int* d_ctr = (int*)(D0 + o_ctr);
+
+  // The device sequence of the call: metadata upload, kernels, result copies.
+  // seq(run, sig) hashes every argument of every call into sig and, with
+  // run, issues the calls; a graph captured from one issue is valid for any
+  // later call with the same hash.
+  FusedPlan F{};
+  size_t f_lds = 0;
+  int f_blocks = 0;
   if (fused) {
-    FusedPlan F{};
     F.jobs = d_jobs;
     F.nj = nj;
     int total = 0;
@@ -490,40 +529,108 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     F.err = d_ctr + ctr_off[nj] + 1;
     F.stage_ld = maxLcap <= 128 ? maxLcap + 1 : 0;
     F.mrc_lane = mrc_lane ? 1 : 0;
-    size_t lds = interp_lds_words(maxD) * 4;
+    f_lds = interp_lds_words(maxD) * 4;
     for (int i = 0; i < nj; ++i)
       if (!w[i].status && w[i].active)
-        lds = std::max(lds, eval_elim_lds_bytes(w[i].pl.m + w[i].pl.n + 2, w[i].Tf + w[i].Tg));
-    lds = std::max(lds, (size_t)(F.mrc_lane ? maxP * 64 : 2 * maxP) * 4);
-    lds = std::max(lds, (size_t)64 * F.stage_ld * 4);
-    const int blocks = total ? fused_blocks(lds, total) : 0;
-    if (total && blocks <= 0) return BIRES_EDEVICE;
-    if (timing) DEV(hipEventRecord(ev0, st));
-    if (total) launch_fused(F, lds, blocks, cx->tab, st);
-    if (timing) DEV(hipEventRecord(ev1, st));
+        f_lds = std::max(f_lds, eval_elim_lds_bytes(w[i].pl.m + w[i].pl.n + 2, w[i].Tf + w[i].Tg));
+    f_lds = std::max(f_lds, (size_t)(F.mrc_lane ? maxP * 64 : 2 * maxP) * 4);
+    f_lds = std::max(f_lds, (size_t)64 * F.stage_ld * 4);
+    f_blocks = total ? fused_blocks(f_lds, total) : 0;
+    if (total && f_blocks <= 0) return BIRES_EDEVICE;
   }
-  if (!fused && nb_of(K_RED)) launch_reduce(d_jobs, st_of(K_RED), nj, nb_of(K_RED), maxP, cx->tab, st);
-  if (!fused && timing) DEV(hipEventRecord(ev0, st));
-  for (int bk = 0; bk < NBUCKET && !fused; ++bk)
-    if (nb_of(K_EE0 + bk))
-      launch_eval_elim(d_jobs, st_of(K_EE0 + bk), nj, nb_of(K_EE0 + bk), bw[bk], br_[bk], cx->tab, st);
-  if (!fused && timing) DEV(hipEventRecord(ev1, st));
-  if (!debug && !fused) {
-    if (!group.empty())
-      launch_interp_mfma(d_jobs, (const int*)(D0 + o_gj), (int)group.size(), gD, gP, vinv, (int8_t*)(D0 + o_yp),
-                         cx->tab, st);
-    else if (nb_of(K_IP))
-      launch_interp(d_jobs, st_of(K_IP), nj, nb_of(K_IP), maxD, cx->tab, st);
-    if (use_crt) {
-      // residues to limbs in one pass over the output capacity
-      if (nb_of(K_CAR)) launch_crt(d_jobs, st_of(K_CAR), nj, nb_of(K_CAR), maxP, maxLM, maxLcap, cx->tab, st);
+  const bool use_graph = cx->graphs && !debug;
+  const bool timing = cx->timing && nb_ee > 0 && !use_graph;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (timing) {
+    DEV(hipEventCreate(&ev0));
+    DEV(hipEventCreate(&ev1));
+  }
+  auto seq = [&](bool run, SeqHash& sg) -> int {
+    sg.add(st, D0, meta_begin, meta_end, (const void*)h_meta.p);
+    if (run && meta_end > meta_begin)
+      DEV(hipMemcpyAsync(D0 + meta_begin, h_meta.p, meta_end - meta_begin, hipMemcpyHostToDevice, st));
+    if (fused) {
+      sg.add(F, f_lds, f_blocks);
+      if (run && timing) DEV(hipEventRecord(ev0, st));
+      if (run && F.base[F_STAGES]) launch_fused(F, f_lds, f_blocks, cx->tab, st);
+      if (run && timing) DEV(hipEventRecord(ev1, st));
     } else {
-      if (nb_of(K_MRC)) launch_mrc(d_jobs, st_of(K_MRC), nj, nb_of(K_MRC), maxP, mrc_lane, cx->tab, st);
-      if (nb_of(K_SUM)) launch_limbs_sum(d_jobs, st_of(K_SUM), nj, nb_of(K_SUM), cx->tab, st);
-      if (nb_of(K_CAR)) launch_limbs_carry(d_jobs, st_of(K_CAR), nj, nb_of(K_CAR), maxLcap, st);
+      sg.add(nb_of(K_RED), maxP);
+      if (run && nb_of(K_RED)) launch_reduce(d_jobs, st_of(K_RED), nj, nb_of(K_RED), maxP, cx->tab, st);
+      if (run && timing) DEV(hipEventRecord(ev0, st));
+      for (int bk = 0; bk < NBUCKET; ++bk) {
+        sg.add(nb_of(K_EE0 + bk), bw[bk], br_[bk]);
+        if (run && nb_of(K_EE0 + bk))
+          launch_eval_elim(d_jobs, st_of(K_EE0 + bk), nj, nb_of(K_EE0 + bk), bw[bk], br_[bk], cx->tab, st);
+      }
+      if (run && timing) DEV(hipEventRecord(ev1, st));
+      if (!debug) {
+        sg.add((int)group.size(), gD, gP, (const void*)vinv, o_yp, o_gj, nb_of(K_IP), maxD, use_crt, nb_of(K_CAR),
+               maxLM, maxLcap, nb_of(K_MRC), mrc_lane, nb_of(K_SUM));
+        if (run) {
+          if (!group.empty())
+            launch_interp_mfma(d_jobs, (const int*)(D0 + o_gj), (int)group.size(), gD, gP, vinv,
+                               (int8_t*)(D0 + o_yp), cx->tab, st);
+          else if (nb_of(K_IP))
+            launch_interp(d_jobs, st_of(K_IP), nj, nb_of(K_IP), maxD, cx->tab, st);
+          if (use_crt) {
+            // residues to limbs in one pass over the output capacity
+            if (nb_of(K_CAR)) launch_crt(d_jobs, st_of(K_CAR), nj, nb_of(K_CAR), maxP, maxLM, maxLcap, cx->tab, st);
+          } else {
+            if (nb_of(K_MRC)) launch_mrc(d_jobs, st_of(K_MRC), nj, nb_of(K_MRC), maxP, mrc_lane, cx->tab, st);
+            if (nb_of(K_SUM)) launch_limbs_sum(d_jobs, st_of(K_SUM), nj, nb_of(K_SUM), cx->tab, st);
+            if (nb_of(K_CAR)) launch_limbs_carry(d_jobs, st_of(K_CAR), nj, nb_of(K_CAR), maxLcap, st);
+          }
+        }
+      }
     }
+    if (run) DEV(hipGetLastError());
+    if (debug) return BIRES_OK;
+    sg.add(nj, o_flags, (const void*)h_flags);
+    if (run && nj) DEV(hipMemcpyAsync(h_flags, D0 + o_flags, sizeof(int32_t) * 2 * nj, hipMemcpyDeviceToHost, st));
+    if (fused) {
+      sg.add(ctr_off[nj]);
+      if (run)
+        DEV(hipMemcpyAsync(h_flags + 2 * nj, d_ctr + ctr_off[nj] + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    }
+    for (int i = 0; i < nj; ++i) {
+      const Work& x = w[i];
+      if (x.status || !x.active || mem != BIRES_MEM_HOST) continue;
+      sg.add(i, (const void*)h_out.b(), x.o_hout, x.o_out, x.degcap, x.Lout);
+      if (run)
+        DEV(hipMemcpyAsync(h_out.b() + x.o_hout, D0 + x.o_out, (size_t)(x.degcap + 1) * x.Lout * 4,
+                           hipMemcpyDeviceToHost, st));
+    }
+    return BIRES_OK;
+  };
+  if (use_graph) {
+    SeqHash sig;
+    (void)seq(false, sig);
+    bool launched = graph_launch(cx, sig.h, st);
+    if (!launched) {
+      // capture one issue of the sequence, then launch it as a graph
+      SeqHash again;
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        const int e = seq(true, again);
+        hipGraph_t g = nullptr;
+        hipGraphExec_t exec = nullptr;
+        const bool ended = hipStreamEndCapture(st, &g) == hipSuccess;
+        if (e == BIRES_OK && ended && g && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess)
+          launched = graph_store_launch(cx, sig.h, exec, st);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+      }
+    }
+    if (!launched) {  // capture unavailable: issue the calls directly
+      SeqHash unused;
+      const int e = seq(true, unused);
+      if (e) return e;
+    }
+  } else {
+    SeqHash unused;
+    const int e = seq(true, unused);
+    if (e) return e;
   }
-  DEV(hipGetLastError());
 
   if (debug) {
     const Work& x = w[0];
@@ -535,29 +642,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     DEV(hipStreamSynchronize(st));
     return BIRES_OK;
   }
-
-  // ---------------- results
-  // special results of device-memory outputs are written on the stream
-  for (int i = 0; i < nj; ++i) {
-    const Work& x = w[i];
-    if (x.status || x.active || mem != BIRES_MEM_DEVICE) continue;
-    bires_upoly* o = jobs[i].out;
-    DEV(hipMemsetAsync(o->c, 0, (size_t)(x.degcap + 1) * x.Lout * 4, st));
-    if (x.pl.kind_special == 2) {
-      static const uint32_t one = 1u;
-      DEV(hipMemcpyAsync(o->c, &one, 4, hipMemcpyHostToDevice, st));
-    }
-  }
   hc.mark(4);
-  if (nj) DEV(hipMemcpyAsync(h_flags, D0 + o_flags, sizeof(int32_t) * 2 * nj, hipMemcpyDeviceToHost, st));
-  int fused_err = 0;
-  if (fused) DEV(hipMemcpyAsync(&fused_err, d_ctr + ctr_off[nj] + 1, sizeof(int), hipMemcpyDeviceToHost, st));
-  for (int i = 0; i < nj; ++i) {
-    const Work& x = w[i];
-    if (x.status || !x.active || mem != BIRES_MEM_HOST) continue;
-    DEV(hipMemcpyAsync(h_out.b() + x.o_hout, D0 + x.o_out, (size_t)(x.degcap + 1) * x.Lout * 4,
-                       hipMemcpyDeviceToHost, st));
-  }
   DEV(hipStreamSynchronize(st));
   if (timing) {
     float ms = 0.f;
@@ -569,6 +654,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
   }
+  const int fused_err = fused ? h_flags[2 * nj] : 0;
   int first_err = BIRES_OK;
   for (int i = 0; i < nj; ++i) {
     Work& x = w[i];

@@ -157,6 +157,37 @@ const uint32_t* crt_device(Context* cx, int P, int* LM) {
   return it->second.first;
 }
 
+bool graph_launch(Context* cx, uint64_t key, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(cx->graph_mu);
+  auto it = cx->graph_cache.find(key);
+  if (it == cx->graph_cache.end()) return false;
+  if (hipGraphLaunch(it->second, st) != hipSuccess) return false;
+  cx->graph_replays++;
+  return true;
+}
+
+bool graph_store_launch(Context* cx, uint64_t key, hipGraphExec_t exec, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(cx->graph_mu);
+  auto it = cx->graph_cache.find(key);
+  if (it != cx->graph_cache.end()) {  // another thread stored the same sequence
+    (void)hipGraphExecDestroy(exec);
+    exec = it->second;
+  } else {
+    if (cx->graph_order.size() >= 32) {
+      // rare: wait for every launch before destroying the oldest executable
+      (void)hipDeviceSynchronize();
+      const uint64_t old = cx->graph_order.front();
+      cx->graph_order.erase(cx->graph_order.begin());
+      (void)hipGraphExecDestroy(cx->graph_cache[old]);
+      cx->graph_cache.erase(old);
+    }
+    cx->graph_cache[key] = exec;
+    cx->graph_order.push_back(key);
+    cx->graph_captures++;
+  }
+  return hipGraphLaunch(exec, st) == hipSuccess;
+}
+
 const int8_t* vinv_device(Context* cx, int D, int P, hipStream_t st) {
   constexpr size_t kLimit = (size_t)2 << 30;  // bytes of cached tables
   std::lock_guard<std::mutex> lk(cx->vinv_mu);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -57,10 +58,22 @@ struct Context {
   int64_t host_calls = 0;
   std::mutex crt_mu;
   std::map<int, std::pair<const uint32_t*, int>> crt;  // P -> (device CrtHost buffer, LM)
+  std::atomic<bool> graphs{false};                       // replay device sequences as captured graphs
+  std::mutex graph_mu;
+  std::map<uint64_t, hipGraphExec_t> graph_cache;       // sequence hash -> instantiated graph
+  std::vector<uint64_t> graph_order;                    // insertion order (oldest first)
+  int64_t graph_captures = 0, graph_replays = 0;        // under graph_mu
   std::mutex vinv_mu;
   std::map<std::pair<int, int>, const int8_t*> vinv;   // (D, P) -> inverse Vandermonde digit planes
   size_t vinv_total = 0;
 };
+
+// Captured device sequences keyed by the hash of their call arguments:
+// graph_launch launches a cached one (false if absent or the launch failed);
+// graph_store_launch caches a new executable (at most 32, the oldest is
+// destroyed after a device synchronisation) and launches it.
+bool graph_launch(Context* cx, uint64_t key, hipStream_t st);
+bool graph_store_launch(Context* cx, uint64_t key, hipGraphExec_t exec, hipStream_t st);
 
 // Inverse Vandermonde digit planes for nodes 0..D-1 and the first P primes,
 // built on first use (on stream st, which is then synchronised) and kept;

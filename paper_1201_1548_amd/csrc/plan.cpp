@@ -184,9 +184,10 @@ int make_plan(const RowStats& f, const RowStats& g, Plan& pl) {
   // M > 2^1.001 B: the symmetric residue then sits at least 3e-4 M away from
   // +-M/2, which the explicit CRT's fp64 rounding relies on
   const double need = pl.log2B + 1.001;
-  int P = 1;
-  while (P <= t.K && t.cumlog[P] <= need) ++P;
-  if (P > t.K) return BIRES_ETOOBIG;
+  // smallest P with cumlog[P] > need (cumlog increases)
+  const auto it = std::upper_bound(t.cumlog.begin() + 1, t.cumlog.end(), need);
+  if (it == t.cumlog.end()) return BIRES_ETOOBIG;
+  const int P = (int)(it - t.cumlog.begin());
   pl.P = P;
   return BIRES_OK;
 }

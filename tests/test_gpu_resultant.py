@@ -287,3 +287,43 @@ def test_shared_shape_batch_matrix_core_interpolation():
         assert res[i] == br.resultant(F, G), i
     for i in (5, 35):
         assert zx.evaluate(res[i], 11) == resultant_at(*pairs[i], 11)
+
+
+@pytest.mark.parametrize("schedule", ["staged", "fused"])
+def test_graph_replay_matches_eager(schedule):
+    # batched calls replayed from captured HIP graphs: every replay, with eager
+    # work and synchronisations between replays and another batch's graph in
+    # between, equals the eagerly issued result
+    import torch
+    jobs = [j for j in _mixed_jobs() if not (j[0] == "disc" and len(j[1]) < 2)]
+    say("graph replay", schedule, len(jobs))
+    br.set_schedule(schedule)
+    try:
+        b = br.DeviceBatch(jobs)
+        b.run()
+        eager = b.results()
+        other = br.DeviceBatch([("res",) + synth.config1_pair(i % 4) + ("y",) for i in range(6)])
+        other.run()
+        eager_other = other.results()
+        host_ref = br.resultant_batch(jobs)
+        br.set_graphs(True)
+        c0, r0 = br.graph_stats()
+        for rep in range(4):
+            for t in b.out_tensors:
+                t.fill_(-1)
+            torch.cuda.synchronize()
+            b.run()
+            assert b.results() == eager, rep
+            if rep == 1:
+                for t in other.out_tensors:
+                    t.zero_()
+                other.run()
+                assert other.results() == eager_other
+            assert br.resultant_batch(jobs) == host_ref, rep
+        c1, r1 = br.graph_stats()
+        say("graphs captured", c1 - c0, "replayed", r1 - r0)
+        assert r1 - r0 >= 4 and c1 - c0 >= 2
+    finally:
+        br.set_graphs(False)
+        br.set_schedule("staged")
+    assert eager[:len(jobs)] == host_ref[0]
