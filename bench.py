@@ -337,6 +337,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain path (profiling runs)")
     ap.add_argument("--no-graphs", action="store_true", help="skip the graph-replay leg")
+    ap.add_argument("--eval-kernel", default="auto", choices=["auto", "lds"],
+                    help="evaluation + elimination kernel of the staged schedule")
     ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5", "copy"])
     ap.add_argument("--schedule", default="auto", choices=["auto", "staged", "fused"])
     ap.add_argument("--requests", type=int, default=300)
@@ -370,6 +372,7 @@ def main():
     torch.cuda.set_device(0)
     dev = br.device_info()
     batch = br.DeviceBatch([("res", F, G, "y") for F, G in pairs])
+    br.set_eval_kernel(args.eval_kernel)
     br.set_schedule(args.schedule)
     chosen = batch.autotune(reps=2) if args.schedule == "auto" else args.schedule
 

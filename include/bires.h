@@ -197,6 +197,17 @@ int bires_debug_values(const bires_bipoly *f, const bires_bipoly *g, int kind, i
 #define BIRES_SCHEDULE_AUTO 2
 int bires_set_schedule(int schedule);
 
+/* Evaluation + elimination kernel of the staged schedule.
+ *   BIRES_EVAL_AUTO (default): jobs with 1 <= min(m, n) and max(m, n) < 32
+ *     (m, n: degrees in the eliminated variable) keep f's coefficient array in
+ *     registers; blocks that meet a vanishing leading coefficient or a
+ *     degree drop are recomputed by the general kernel; other jobs use it;
+ *   BIRES_EVAL_LDS: every job uses the general kernel (both arrays in LDS).
+ * Results are identical.  Process-wide setting. */
+#define BIRES_EVAL_AUTO 0
+#define BIRES_EVAL_LDS 1
+int bires_set_eval_kernel(int kernel);
+
 /* Graph replay: when enabled, batched calls issue their device sequence
  * (metadata upload, the stage kernels of the chosen schedule, status and
  * host-output copies) as a captured HIP graph, one per distinct set of launch

@@ -79,6 +79,7 @@ _SIGS = {
     "bires_set_timing": ([ctypes.c_int], ctypes.c_int),
     "bires_set_schedule": ([ctypes.c_int], ctypes.c_int),
     "bires_set_graphs": ([ctypes.c_int], ctypes.c_int),
+    "bires_set_eval_kernel": ([ctypes.c_int], ctypes.c_int),
     "bires_graph_stats": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "bires_autotune": ([ctypes.c_int, ctypes.POINTER(Bipoly), ctypes.POINTER(Bipoly),
                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Upoly),
@@ -360,6 +361,12 @@ def set_schedule(schedule):
     """Launch schedule of batched calls: 'staged', 'fused' or 'auto'."""
     code = {"staged": 0, "fused": 1, "auto": 2}[schedule] if isinstance(schedule, str) else schedule
     _check(lib().bires_set_schedule(code), "bires_set_schedule")
+
+
+def set_eval_kernel(kernel):
+    """Evaluation + elimination kernel of the staged schedule: 'auto' (f's
+    array in registers where the degrees allow) or 'lds'."""
+    _check(lib().bires_set_eval_kernel({"auto": 0, "lds": 1}[kernel]), "bires_set_eval_kernel")
 
 
 def set_graphs(enable):

@@ -179,6 +179,15 @@ int bires_set_graphs(int enable) {
   return BIRES_OK;
 }
 
+int bires_set_eval_kernel(int kernel) {
+  if (kernel != BIRES_EVAL_AUTO && kernel != BIRES_EVAL_LDS) return BIRES_EINVAL;
+  int err = BIRES_OK;
+  Context* cx = context(&err);
+  if (!cx) return err;
+  cx->eval_rg = kernel == BIRES_EVAL_AUTO;
+  return BIRES_OK;
+}
+
 int bires_graph_stats(int64_t* captures, int64_t* replays) {
   int err = BIRES_OK;
   Context* cx = context(&err);

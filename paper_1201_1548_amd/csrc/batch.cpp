@@ -289,9 +289,13 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   // per-kernel first block of each job (prefix sums of the per-job block counts)
   // eval_elim runs one launch per size bucket (LDS per block sized for the
   // bucket, so small jobs are not held to the occupancy of the largest)
-  enum { K_RED, K_IP, K_MRC, K_SUM, K_CAR, K_EE0, NBUCKET = 5, NK = K_EE0 + NBUCKET };
+  // jobs whose f array fits in registers (eval_elim_rg_capacity 24 or 32) run
+  // in two more launches
+  enum { K_RED, K_IP, K_MRC, K_SUM, K_CAR, K_EE0, NBUCKET = 5, K_RG0 = K_EE0 + NBUCKET, NRG = 2, NK = K_RG0 + NRG };
   const int bucket_words[NBUCKET] = {24, 40, 64, 96, 1 << 30};
+  const int rg_cap[NRG] = {24, 32};
   int bw[NBUCKET] = {0}, br_[NBUCKET] = {0};
+  int rdeg[NRG] = {0}, rw[NRG] = {0};
   std::vector<int> starts[NK];
   for (auto& v : starts) v.assign(nj + 1, 0);
   int maxP = 1, maxD = 1;
@@ -316,11 +320,19 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     maxP = std::max(maxP, p.P);
     maxD = std::max(maxD, p.D);
     starts[K_RED][i + 1] = (x.Tf + 63) / 64 + (x.Tg + 63) / 64;
-    int bk = 0;
-    while (p.m + p.n + 2 > bucket_words[bk]) ++bk;
-    starts[K_EE0 + bk][i + 1] = p.P * ((p.D + 63) / 64);
-    bw[bk] = std::max(bw[bk], p.m + p.n + 2);
-    br_[bk] = std::max(br_[bk], x.Tf + x.Tg);
+    const int rc = cx->eval_rg ? eval_elim_rg_capacity(p.m, p.n) : 0;
+    if (rc) {
+      const int r = rc == rg_cap[0] ? 0 : 1;
+      starts[K_RG0 + r][i + 1] = p.P * ((p.D + 63) / 64);
+      rdeg[r] = std::max(rdeg[r], std::max(p.m, p.n));
+      rw[r] = std::max(rw[r], p.m + p.n + 2);
+    } else {
+      int bk = 0;
+      while (p.m + p.n + 2 > bucket_words[bk]) ++bk;
+      starts[K_EE0 + bk][i + 1] = p.P * ((p.D + 63) / 64);
+      bw[bk] = std::max(bw[bk], p.m + p.n + 2);
+      br_[bk] = std::max(br_[bk], x.Tf + x.Tg);
+    }
     starts[K_IP][i + 1] = p.P;
     starts[K_MRC][i + 1] = p.D;  // adjusted below once the largest prime count is known
     starts[K_SUM][i + 1] = (p.D * x.Lacc + 255) / 256;
@@ -387,10 +399,13 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   if (!vinv) group.clear();
   const int gDp = (gD + 31) & ~31, gNp = ((int)group.size() + 31) & ~31;
   const size_t o_yp = group.empty() ? 0 : ws.take((size_t)4 * gNp * gDp * gP);
+  size_t o_fbq[NRG];  // queues of blocks recomputed by the LDS kernel
+  for (int r = 0; r < NRG; ++r) o_fbq[r] = ws.take(sizeof(int) * (size_t)starts[K_RG0 + r][nj]);
   // metadata uploaded with one copy: descriptors, flags, row degrees, block maps
   const size_t meta_begin = ws.take(0);
   const size_t o_jobs = ws.take(sizeof(JobDev) * (size_t)nj);
   const size_t o_flags = ws.take(sizeof(int32_t) * (2 * (size_t)nj + 1));  // [deg_out, err] per job, fused error
+  const size_t o_fbc = ws.take(sizeof(int) * NRG);                         // queue lengths, uploaded as zero
   for (int i = 0; i < nj; ++i)
     if (!w[i].status && w[i].active) w[i].o_rowdeg = ws.take((size_t)(w[i].pl.m + w[i].pl.n + 2) * 4);
   const size_t o_maps = ws.take(sizeof(int) * (size_t)NK * (nj + 1));
@@ -427,6 +442,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   uint8_t* const H0 = h_meta.b() - meta_begin;  // H0 + offset addresses the metadata image
 
   int32_t* h_flags = (int32_t*)(H0 + o_flags);
+  std::memset(H0 + o_fbc, 0, sizeof(int) * NRG);
   JobDev* h_jobs = (JobDev*)(H0 + o_jobs);
   for (int i = 0; i < nj; ++i) {
     h_flags[2 * i] = -1;
@@ -503,7 +519,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   }
   const JobDev* d_jobs = (const JobDev*)(D0 + o_jobs);
   int nb_ee = 0;
-  for (int bk = 0; bk < NBUCKET; ++bk) nb_ee += nb_of(K_EE0 + bk);
+  for (int bk = 0; bk < NBUCKET + NRG; ++bk) nb_ee += nb_of(K_EE0 + bk);
   int* d_ctr = (int*)(D0 + o_ctr);
 
   // The device sequence of the call: metadata upload, kernels, result copies.
@@ -562,6 +578,12 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
         sg.add(nb_of(K_EE0 + bk), bw[bk], br_[bk]);
         if (run && nb_of(K_EE0 + bk))
           launch_eval_elim(d_jobs, st_of(K_EE0 + bk), nj, nb_of(K_EE0 + bk), bw[bk], br_[bk], cx->tab, st);
+      }
+      for (int r = 0; r < NRG; ++r) {
+        sg.add(nb_of(K_RG0 + r), rdeg[r], rw[r], o_fbc, o_fbq[r]);
+        if (run && nb_of(K_RG0 + r))
+          launch_eval_elim_rg(rg_cap[r], d_jobs, st_of(K_RG0 + r), nj, nb_of(K_RG0 + r), rdeg[r], rw[r],
+                              (int*)(D0 + o_fbc) + r, (int*)(D0 + o_fbq[r]), cx->tab, st);
       }
       if (run && timing) DEV(hipEventRecord(ev1, st));
       if (!debug) {

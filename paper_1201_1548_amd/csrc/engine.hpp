@@ -58,6 +58,7 @@ struct Context {
   int64_t host_calls = 0;
   std::mutex crt_mu;
   std::map<int, std::pair<const uint32_t*, int>> crt;  // P -> (device CrtHost buffer, LM)
+  std::atomic<bool> eval_rg{true};                       // register-array evaluation kernel where it applies
   std::atomic<bool> graphs{false};                       // replay device sequences as captured graphs
   std::mutex graph_mu;
   std::map<uint64_t, hipGraphExec_t> graph_cache;       // sequence hash -> instantiated graph

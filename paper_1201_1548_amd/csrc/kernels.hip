@@ -371,21 +371,22 @@ typedef __attribute__((address_space(4))) const u32x4 cu4;
 typedef __attribute__((address_space(4))) const int32_t ci32;
 
 // Value of the row c[0..d] (zero-padded to a multiple of 4, 16-byte aligned)
-// at the point whose powers are pw; apw = (a^EV_PW)_M.  d is wave-uniform.
-// With C = cu32 the coefficients come in by scalar loads and feed the
-// products as scalar operands (the data must not change during the launch);
-// with C = const uint32_t they are ordinary loads.
-template <class C, class C4>
-__device__ __forceinline__ uint32_t eval_row(C* c, int d, const uint32_t (&pw)[EV_PW], uint32_t apw, const ModP& q) {
+// at the point whose powers are pw (NPW of them, a multiple of 4); apw =
+// (a^NPW)_M.  d is wave-uniform.  With C = cu32 the coefficients come in by
+// scalar loads and feed the products as scalar operands (the data must not
+// change during the launch); with C = const uint32_t they are ordinary loads.
+template <class C, class C4, int NPW>
+__device__ __forceinline__ uint32_t eval_row(C* c, int d, const uint32_t (&pw)[NPW], uint32_t apw, const ModP& q) {
+  static_assert(NPW % 4 == 0, "powers come in groups of four");
   if (d < 0) return 0u;
-  const int top = d / EV_PW;
+  const int top = d / NPW;
   uint32_t acc = 0u;
   for (int ch = top; ch >= 0; --ch) {
-    C4* cc = (C4*)(c + ch * EV_PW);
-    const int ng = (min(EV_PW, d + 1 - ch * EV_PW) + 3) >> 2;
+    C4* cc = (C4*)(c + ch * NPW);
+    const int ng = (min(NPW, d + 1 - ch * NPW) + 3) >> 2;
     Acc96 S;
 #pragma unroll
-    for (int g = 0; g < EV_PW / 4; ++g) {
+    for (int g = 0; g < NPW / 4; ++g) {
       if (g < ng) {
         const u32x4 v = cc[g];
         uint64_t t = (uint64_t)v.x * pw[4 * g];
@@ -458,6 +459,220 @@ __global__ __launch_bounds__(W) void k_eval_elim(const JobDev* jobs, const int* 
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int job = find_job(starts, nj, b);
   dev_eval_elim<W, true>(jobs[job], b - starts[job], tab, lds);
+}
+
+// ---------------------------------------------------------------------------
+// (b)+(c) with one coefficient array in registers.
+//
+// The Euclid arrays above take (m + n + 2) words of LDS per lane, and that
+// LDS, not the register file, limits the blocks resident on a CU.  Here the
+// arrays are stored top-aligned: index k holds the coefficient of y^(deg - k),
+// so the leading coefficient is always at index 0 and an elimination
+//   A <- lc(B) A - lc(A) y^(a'-b) B
+// becomes A[j] <- lc(B) A[j+1] - A[0] B[j+1] (j < b), lc(B) A[j+1] (b <= j < a')
+// whatever the degree gap, and the fused double step of a normal remainder
+// sequence (a = b + 1) becomes
+//   A[k] <- l2 A[k+2] + l1 B[k+2] + n2 B[k+1]   (k < b - 1; the last one has
+//   no B[k+2] term),
+// with the constants of eliminate().  Both read index j+1 or k+2 before
+// writing index j or k, so they run in place in ascending order.  Every index
+// is a compile-time constant once the loops over the capacity C are unrolled
+// (the degrees are wave-uniform, so the guards are scalar branches), which
+// lets f's array X live in registers; g's array L stays in LDS at stride 64.
+// The two roles alternate every Euclid step.
+//
+// A wave runs only the uniform normal case: non-zero leading coefficients at
+// its points, then remainders of degree exactly b - 1.  At the first
+// exception (probability about one in 2^25 per step and point for
+// generic inputs) the block gives up, appends its index to a queue, and a
+// second launch recomputes the queued blocks with dev_eval_elim.
+
+#define RG_A(k) (AREG ? X[k] : L[(k) * 64])
+#define RG_B(k) (AREG ? L[(k) * 64] : X[k])
+#define RG_SET_A(k, v)          \
+  do {                          \
+    const uint32_t v_ = (v);    \
+    if (AREG)                   \
+      X[k] = v_;                \
+    else                        \
+      L[(k) * 64] = v_;         \
+  } while (0)
+
+// One elimination of A (degree ap) by B (degree bs, leading coefficient lb).
+template <int C, bool AREG>
+__device__ __forceinline__ void rg_elim(uint32_t (&X)[C], uint32_t* __restrict__ L, int bs, int ap, uint32_t lb,
+                                        const ModP& q) {
+  const uint32_t nla = mneg(RG_A(0), q.p);
+#pragma unroll
+  for (int j0 = 0; j0 < C - 1; j0 += 4) {
+    if (j0 + 4 < C && j0 + 4 <= bs) {
+      uint32_t x[4], y[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        x[i] = RG_A(j0 + 1 + i);
+        y[i] = RG_B(j0 + 1 + i);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) RG_SET_A(j0 + i, mdot2(lb, x[i], nla, y[i], q));
+    } else if (j0 < ap) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = j0 + i;
+        if (j < C - 1) {
+          if (j < bs)
+            RG_SET_A(j, mdot2(lb, RG_A(j + 1), nla, RG_B(j + 1), q));
+          else if (j < ap)
+            RG_SET_A(j, mmul(lb, RG_A(j + 1), q));
+        }
+      }
+    }
+  }
+}
+
+// The two eliminations of a normal step (A of degree bs + 1) as one pass.
+template <int C, bool AREG>
+__device__ __forceinline__ void rg_fused(uint32_t (&X)[C], uint32_t* __restrict__ L, int bs, uint32_t lb,
+                                         const ModP& q) {
+  const uint32_t n1 = mneg(RG_A(0), q.p);
+  const uint32_t n2 = mneg(mdot2(lb, RG_A(1), n1, RG_B(1), q), q.p);
+  const uint32_t l2 = mmul(lb, lb, q), l1 = mmul(lb, n1, q);
+#pragma unroll
+  for (int k0 = 0; k0 < C - 2; k0 += 4) {
+    if (k0 + 5 < C && k0 + 4 < bs) {
+      uint32_t x[4], y[5];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[i] = RG_A(k0 + 2 + i);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) y[i] = RG_B(k0 + 1 + i);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) RG_SET_A(k0 + i, mdot3(l2, x[i], l1, y[i + 1], n2, y[i], q));
+    } else if (k0 < bs) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = k0 + i;
+        if (k < C - 2) {
+          if (k < bs - 1)
+            RG_SET_A(k, mdot3(l2, RG_A(k + 2), l1, RG_B(k + 2), n2, RG_B(k + 1), q));
+          else if (k == bs - 1)
+            RG_SET_A(k, mdot2(l2, RG_A(k + 2), n2, RG_B(k + 1), q));
+        }
+      }
+    }
+  }
+}
+
+// The eliminations of one Euclid step of the uniform case; returns lc(B) and
+// leaves in *short_rem whether some lane's remainder has degree below b - 1.
+template <int C, bool AREG>
+__device__ __forceinline__ uint32_t rg_step(uint32_t (&X)[C], uint32_t* __restrict__ L, int as, int bs,
+                                            bool* short_rem, const ModP& q) {
+  const uint32_t lb = RG_B(0);
+  if (as == bs + 1)
+    rg_fused<C, AREG>(X, L, bs, lb, q);
+  else
+    for (int ap = as; ap >= bs; --ap) rg_elim<C, AREG>(X, L, bs, ap, lb, q);
+  *short_rem = __ballot(RG_A(0) == 0u) != 0ull;
+  return lb;
+}
+
+#undef RG_A
+#undef RG_B
+#undef RG_SET_A
+
+// Powers held in registers by the register-array kernel (fewer than EV_PW, to
+// leave room for X; longer rows take one more Horner chunk).
+constexpr int RG_PW = 16;
+
+// Returns false (on every active lane) when the block must be recomputed by
+// dev_eval_elim.  Needs 1 <= m, n and max(m, n) < C; LDS: (max(m, n) + 1)
+// words per lane.
+template <int C>
+__device__ __forceinline__ bool dev_eval_elim_rg(const JobDev& J, int lb, TablesDev tab, uint32_t* lds) {
+  const int nbpp = (J.D + 63) / 64;
+  const int k = lb / nbpp;
+  const int a0 = (lb - k * nbpp) * 64;
+  const int m = J.m, n = J.n;
+  const int lpf = J.lpf, lpg = J.lpg;
+  cu32* Rf = (cu32*)(J.res_f + (size_t)k * J.Tf);
+  cu32* Rg = (cu32*)(J.res_g + (size_t)k * J.Tg);
+  ci32* RDf = (ci32*)J.rowdeg_f;
+  ci32* RDg = (ci32*)J.rowdeg_g;
+  uint32_t* L = lds + threadIdx.x;
+  const int pt = a0 + (int)threadIdx.x;
+  if (pt >= J.D) return true;
+  const ModP q = tab.primes[k];
+  const uint32_t aM = to_mont((uint32_t)pt, q);
+  const int dmax = max(J.ldf, J.disc ? J.ldf : J.ldg) - 1;
+  uint32_t pw[RG_PW];
+  pw[0] = q.one;
+#pragma unroll
+  for (int i = 1; i < RG_PW; ++i) pw[i] = i <= dmax ? mmul(pw[i - 1], aM, q) : 0u;
+  const uint32_t apw = dmax >= RG_PW ? mmul(pw[RG_PW - 1], aM, q) : 0u;
+  // f's values go through L (a loop with runtime trip counts cannot fill a
+  // register array), then g's take their place
+  for (int t = 0; t <= m; ++t)
+    L[t * 64] = eval_row<cu32, cu4>(Rf + (m - t) * lpf, __builtin_amdgcn_readfirstlane(RDf[m - t]), pw, apw, q);
+  uint32_t X[C];
+#pragma unroll
+  for (int t = 0; t < C; ++t) X[t] = t <= m ? L[t * 64] : 0u;
+  for (int t = 0; t <= n; ++t)
+    L[t * 64] = eval_row<cu32, cu4>(Rg + (n - t) * lpg, __builtin_amdgcn_readfirstlane(RDg[n - t]), pw, apw, q);
+  if (__ballot(X[0] == 0u || L[0] == 0u) != 0ull) return false;
+  uint32_t num = q.one, den = q.one, pfx = q.one;
+  bool neg = false, areg = true;
+  int as = m, bs = n;
+  if (m < n) {
+    areg = false;
+    as = n;
+    bs = m;
+    neg = ((m * n) & 1) != 0;
+  }
+  while (bs > 0) {
+    bool short_rem;
+    const uint32_t lb = areg ? rg_step<C, true>(X, L, as, bs, &short_rem, q)
+                             : rg_step<C, false>(X, L, as, bs, &short_rem, q);
+    if (short_rem) return false;
+    // bookkeeping of uni_resultant's fast path (remainder degree bs - 1)
+    neg ^= ((as * bs) & 1) != 0;
+    pfx = mmul(pfx, mmul(lb, lb, q), q);
+    if (bs > 1) den = mmul(den, pfx, q);
+    const int d = (1 - bs) * (as - bs - 1);
+    if (d > 0)
+      num = mmul(num, mpow(lb, (uint32_t)d, q), q);
+    else if (d < 0)
+      den = mmul(den, mpow(lb, (uint32_t)(-d), q), q);
+    areg = !areg;
+    as = bs;
+    bs -= 1;
+  }
+  // the constant remainder is in the array that does not hold A
+  num = mmul(num, mpow(areg ? L[0] : X[0], (uint32_t)as, q), q);
+  uint32_t r = den == q.one ? num : mmul(num, minv(den, q), q);
+  if (neg) r = mneg(r, q.p);
+  J.vals[(size_t)k * J.D + pt] = from_mont(r, q);
+  return true;
+}
+
+template <int C>
+__global__ __launch_bounds__(64) void k_eval_elim_rg(
+    const JobDev* jobs, const int* starts, int nj, TablesDev tab, int* fb_count, int* fb_queue) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int job = find_job(starts, nj, b);
+  const bool ok = dev_eval_elim_rg<C>(jobs[job], b - starts[job], tab, lds);
+  if (__ballot(!ok) != 0ull && threadIdx.x == 0) fb_queue[atomicAdd(fb_count, 1)] = b;
+}
+
+// The queued blocks of k_eval_elim_rg, recomputed with the general kernel.
+__global__ __launch_bounds__(64) void k_eval_elim_fb(const JobDev* jobs, const int* starts, int nj, TablesDev tab,
+                                                     const int* fb_count, const int* fb_queue) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const int cnt = *fb_count;
+  for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
+    const int b = fb_queue[i];
+    const int job = find_job(starts, nj, b);
+    dev_eval_elim<64, true>(jobs[job], b - starts[job], tab, lds);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1434,6 +1649,23 @@ void launch_eval_elim(const JobDev* jobs, const int* starts, int nj, int nblocks
                       TablesDev tab, hipStream_t s) {
   hipLaunchKernelGGL(k_eval_elim<64>, dim3(nblocks), dim3(64), eval_elim_lds_bytes(max_words, max_res), s, jobs,
                      starts, nj, tab);
+}
+
+int eval_elim_rg_capacity(int m, int n) {
+  if (m < 1 || n < 1) return 0;
+  const int d = std::max(m, n);
+  return d < 24 ? 24 : d < 32 ? 32 : 0;
+}
+
+void launch_eval_elim_rg(int C, const JobDev* jobs, const int* starts, int nj, int nblocks, int max_deg,
+                         int max_words, int* fb_count, int* fb_queue, TablesDev tab, hipStream_t s) {
+  const size_t lds = (size_t)(max_deg + 1) * 64 * sizeof(uint32_t);
+  if (C == 24)
+    hipLaunchKernelGGL(k_eval_elim_rg<24>, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, tab, fb_count, fb_queue);
+  else
+    hipLaunchKernelGGL(k_eval_elim_rg<32>, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, tab, fb_count, fb_queue);
+  hipLaunchKernelGGL(k_eval_elim_fb, dim3(std::min(nblocks, 1024)), dim3(64), eval_elim_lds_bytes(max_words, 0), s,
+                     jobs, starts, nj, tab, fb_count, fb_queue);
 }
 
 void launch_interp(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_points, TablesDev tab,

@@ -327,3 +327,31 @@ def test_graph_replay_matches_eager(schedule):
         br.set_graphs(False)
         br.set_schedule("staged")
     assert eager[:len(jobs)] == host_ref[0]
+
+
+def test_register_and_lds_evaluation_kernels_agree():
+    # the register-array kernel (with its fallback queue) and the general LDS
+    # kernel give the same results on generic jobs and on jobs whose leading
+    # coefficients vanish at some points or whose remainder sequences are not
+    # normal (every block of those falls back)
+    jobs = [j for j in _mixed_jobs() if not (j[0] == "disc" and len(j[1]) < 2)]
+    jobs += [("res",) + synth.config2_pair(i) + ("y",) for i in range(3)]
+    # lc_y(f) = x - 5 vanishes at a = 5; in the second pair lc_y(g) = x^2
+    # vanishes at a = 0 and the first remainder's y-coefficient
+    # x^3 - 3x - 2 = (x + 1)^2 (x - 2) at a = 2
+    jobs += [("res", [[2], [3, 7], [-5, 1]], [[1, 1, 4], [0, 2]], "y"),
+             ("res", [[7, 0, 1], [0, 1], [1]], [[1], [2, 3], [0, 0, 1]], "y")]
+    say("register vs lds kernels", len(jobs))
+    try:
+        br.set_eval_kernel("lds")
+        ref, st_ref = br.resultant_batch(jobs)
+        br.set_eval_kernel("auto")
+        got, st_got = br.resultant_batch(jobs)
+        single = [br.resultant(F, G, var) if k == "res" else None for k, F, G, var in jobs[-5:]]
+    finally:
+        br.set_eval_kernel("auto")
+    assert st_got == st_ref
+    assert got == ref
+    assert got[-5:-2] == single[:3]
+    for (kind, F, G, var), R in list(zip(jobs, got))[-2:]:
+        assert R == resultant_y(F, G)
