@@ -654,13 +654,29 @@ __device__ __forceinline__ bool dev_eval_elim_rg(const JobDev& J, int lb, Tables
 }
 
 template <int C>
-__global__ __launch_bounds__(64) void k_eval_elim_rg(
-    const JobDev* jobs, const int* starts, int nj, TablesDev tab, int* fb_count, int* fb_queue) {
-  extern __shared__ __align__(16) uint32_t lds[];
+__device__ __forceinline__ void eval_elim_rg_block(const JobDev* jobs, const int* starts, int nj, TablesDev tab,
+                                                   int* fb_count, int* fb_queue, uint32_t* lds) {
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int job = find_job(starts, nj, b);
   const bool ok = dev_eval_elim_rg<C>(jobs[job], b - starts[job], tab, lds);
   if (__ballot(!ok) != 0ull && threadIdx.x == 0) fb_queue[atomicAdd(fb_count, 1)] = b;
+}
+
+// C = 24 is held to RG24_WAVES waves per SIMD (its few spills sit outside
+// the Euclid loop); C = 32 takes the registers it needs.
+#ifndef RG24_WAVES
+#define RG24_WAVES 6
+#endif
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RG24_WAVES, 8))) void k_eval_elim_rg24(
+    const JobDev* jobs, const int* starts, int nj, TablesDev tab, int* fb_count, int* fb_queue) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  eval_elim_rg_block<24>(jobs, starts, nj, tab, fb_count, fb_queue, lds);
+}
+
+__global__ __launch_bounds__(64) void k_eval_elim_rg32(const JobDev* jobs, const int* starts, int nj, TablesDev tab,
+                                                       int* fb_count, int* fb_queue) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  eval_elim_rg_block<32>(jobs, starts, nj, tab, fb_count, fb_queue, lds);
 }
 
 // The queued blocks of k_eval_elim_rg, recomputed with the general kernel.
@@ -1661,9 +1677,9 @@ void launch_eval_elim_rg(int C, const JobDev* jobs, const int* starts, int nj, i
                          int max_words, int* fb_count, int* fb_queue, TablesDev tab, hipStream_t s) {
   const size_t lds = (size_t)(max_deg + 1) * 64 * sizeof(uint32_t);
   if (C == 24)
-    hipLaunchKernelGGL(k_eval_elim_rg<24>, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, tab, fb_count, fb_queue);
+    hipLaunchKernelGGL(k_eval_elim_rg24, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, tab, fb_count, fb_queue);
   else
-    hipLaunchKernelGGL(k_eval_elim_rg<32>, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, tab, fb_count, fb_queue);
+    hipLaunchKernelGGL(k_eval_elim_rg32, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, tab, fb_count, fb_queue);
   hipLaunchKernelGGL(k_eval_elim_fb, dim3(std::min(nblocks, 1024)), dim3(64), eval_elim_lds_bytes(max_words, 0), s,
                      jobs, starts, nj, tab, fb_count, fb_queue);
 }
