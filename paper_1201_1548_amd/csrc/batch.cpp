@@ -305,6 +305,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     const Plan& p = x.pl;
     x.o_res_f = ws.take((size_t)p.P * x.Tf * 4);
     x.o_res_g = ws.take((size_t)p.P * x.Tg * 4);
+    (void)ws.take(128);  // whole-chunk loads of the evaluation may read past the last row
     x.o_vals = ws.take((size_t)p.P * p.D * 4);
     if (!debug) {
       x.o_coefs = ws.take((size_t)p.P * p.D * 4);

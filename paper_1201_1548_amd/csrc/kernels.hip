@@ -336,8 +336,8 @@ __device__ uint32_t uni_resultant(uint32_t* A, uint32_t* B, int m, int n, const 
   return neg ? mneg(r, q.p) : r;
 }
 
-// Exact sums of products of residues: 96 bits, four products of values below
-// 2^31 per 64-bit partial sum.
+// Exact sums of products of residues in 96 bits: 64-bit partial sums (up to
+// eight products of residues, below 8 p^2 < 2^64) added with a carry word.
 struct Acc96 {
   uint64_t lo = 0;
   uint32_t hi = 0;
@@ -356,7 +356,7 @@ struct Acc96 {
 // of EV_PW, combined by Horner's rule in a^EV_PW.
 constexpr int EV_PW = 24;
 
-// S R^{-1} mod p for S = hi 2^64 + lo with hi < 2^32 - 4 (here hi <= 5):
+// S R^{-1} mod p for S = hi 2^64 + lo with hi < 2^32 - 4 (here hi <= 2):
 // REDC(lo_lo + hi R^2) = lo_lo R^{-1} + hi R, and lo_hi R R^{-1} = lo_hi.
 // The REDC argument is below p 2^32, so its result is below 2p.
 __device__ __forceinline__ uint32_t fold96(const Acc96& S, const ModP& q) {
@@ -371,28 +371,42 @@ typedef __attribute__((address_space(4))) const u32x4 cu4;
 typedef __attribute__((address_space(4))) const int32_t ci32;
 
 // Value of the row c[0..d] (zero-padded to a multiple of 4, 16-byte aligned)
-// at the point whose powers are pw (NPW of them, a multiple of 4); apw =
+// at the point whose powers are pw (NPW of them, a multiple of 8); apw =
 // (a^NPW)_M.  d is wave-uniform.  With C = cu32 the coefficients come in by
 // scalar loads and feed the products as scalar operands (the data must not
 // change during the launch); with C = const uint32_t they are ordinary loads.
+// A chunk's NPW words are loaded at once, which can read up to NPW - 4 words
+// past the end of a short row: the residue buffers are followed by at least
+// that much workspace.  Eight products of residues stay below 8 p^2 < 2^64
+// (p < 2^32 / 3), so each 64-bit partial sum takes eight.
 template <class C, class C4, int NPW>
 __device__ __forceinline__ uint32_t eval_row(C* c, int d, const uint32_t (&pw)[NPW], uint32_t apw, const ModP& q) {
-  static_assert(NPW % 4 == 0, "powers come in groups of four");
+  static_assert(NPW % 8 == 0, "powers come in groups of eight");
   if (d < 0) return 0u;
   const int top = d / NPW;
   uint32_t acc = 0u;
   for (int ch = top; ch >= 0; --ch) {
     C4* cc = (C4*)(c + ch * NPW);
     const int ng = (min(NPW, d + 1 - ch * NPW) + 3) >> 2;
+    u32x4 v[NPW / 4];
+#pragma unroll
+    for (int g = 0; g < NPW / 4; ++g) v[g] = cc[g];
     Acc96 S;
 #pragma unroll
-    for (int g = 0; g < NPW / 4; ++g) {
-      if (g < ng) {
-        const u32x4 v = cc[g];
-        uint64_t t = (uint64_t)v.x * pw[4 * g];
-        t += (uint64_t)v.y * pw[4 * g + 1];
-        t += (uint64_t)v.z * pw[4 * g + 2];
-        t += (uint64_t)v.w * pw[4 * g + 3];
+    for (int h = 0; h < NPW / 8; ++h) {
+      if (2 * h < ng) {
+        const u32x4 x = v[2 * h];
+        uint64_t t = (uint64_t)x.x * pw[8 * h];
+        t += (uint64_t)x.y * pw[8 * h + 1];
+        t += (uint64_t)x.z * pw[8 * h + 2];
+        t += (uint64_t)x.w * pw[8 * h + 3];
+        if (2 * h + 1 < ng) {
+          const u32x4 y = v[2 * h + 1];
+          t += (uint64_t)y.x * pw[8 * h + 4];
+          t += (uint64_t)y.y * pw[8 * h + 5];
+          t += (uint64_t)y.z * pw[8 * h + 6];
+          t += (uint64_t)y.w * pw[8 * h + 7];
+        }
         S.add(t);
       }
     }
