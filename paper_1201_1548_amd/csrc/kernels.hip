@@ -589,9 +589,57 @@ __device__ __forceinline__ uint32_t rg_step(uint32_t (&X)[C], uint32_t* __restri
   return lb;
 }
 
+// The fused step of a normal sequence with the degree bs = B known at
+// compile time: straight-line code, no guards.  Returns l2 = lc(B)^2 R^{-1}
+// and whether every lane's remainder keeps degree B - 1.
+struct RgStep {
+  uint32_t l2;
+  bool ok;
+};
+
+template <int C, int B, bool AREG>
+__device__ __forceinline__ RgStep rg_fstep(uint32_t (&X)[C], uint32_t* __restrict__ L, const ModP& q) {
+  static_assert(B >= 1 && B + 1 < C, "A of degree B + 1 must fit");
+  // keep the scheduler from hoisting later steps' loads (register pressure)
+  __builtin_amdgcn_sched_barrier(0);
+  const uint32_t lb = RG_B(0);
+  const uint32_t n1 = mneg(RG_A(0), q.p);
+  const uint32_t n2 = mneg(mdot2(lb, RG_A(1), n1, RG_B(1), q), q.p);
+  const uint32_t l2 = mmul(lb, lb, q), l1 = mmul(lb, n1, q);
+#pragma unroll
+  for (int k = 0; k < B - 1; ++k) RG_SET_A(k, mdot3(l2, RG_A(k + 2), l1, RG_B(k + 2), n2, RG_B(k + 1), q));
+  RG_SET_A(B - 1, mdot2(l2, RG_A(B + 1), n2, RG_B(B), q));
+  return RgStep{l2, __ballot(RG_A(0) == 0u) == 0ull};
+}
+
 #undef RG_A
 #undef RG_B
 #undef RG_SET_A
+
+// One step of the unrolled chain of normal steps from the current degree bs
+// down to 1: step BV runs when bs >= BV.  (A switch into a fall-through
+// sequence would be shorter to issue but makes every case a merge point of
+// the register array, which the register allocator answers with copies.)
+// In the chain of parity EVEN, A is the register array at even BV.  A step
+// of a normal sequence (a = b + 1) has bookkeeping d = 0 and an even a b.
+#define RG_CHAIN_STEP(BV, EVEN)                                                  \
+  if constexpr (BV + 1 < C) {                                                    \
+    if (bs >= BV) {                                                              \
+      const RgStep o_ = rg_fstep<C, BV, ((((BV) & 1) == 0) == (EVEN))>(X, L, q); \
+      if (!o_.ok) return false;                                                  \
+      pfx = mmul(pfx, o_.l2, q);                                                 \
+      if (BV > 1) den = mmul(den, pfx, q);                                       \
+    }                                                                            \
+  }
+#define RG_CHAIN(EVEN)                                                                                         \
+  RG_CHAIN_STEP(30, EVEN) RG_CHAIN_STEP(29, EVEN) RG_CHAIN_STEP(28, EVEN) RG_CHAIN_STEP(27, EVEN)              \
+  RG_CHAIN_STEP(26, EVEN) RG_CHAIN_STEP(25, EVEN) RG_CHAIN_STEP(24, EVEN) RG_CHAIN_STEP(23, EVEN)              \
+  RG_CHAIN_STEP(22, EVEN) RG_CHAIN_STEP(21, EVEN) RG_CHAIN_STEP(20, EVEN) RG_CHAIN_STEP(19, EVEN)              \
+  RG_CHAIN_STEP(18, EVEN) RG_CHAIN_STEP(17, EVEN) RG_CHAIN_STEP(16, EVEN) RG_CHAIN_STEP(15, EVEN)              \
+  RG_CHAIN_STEP(14, EVEN) RG_CHAIN_STEP(13, EVEN) RG_CHAIN_STEP(12, EVEN) RG_CHAIN_STEP(11, EVEN)              \
+  RG_CHAIN_STEP(10, EVEN) RG_CHAIN_STEP(9, EVEN) RG_CHAIN_STEP(8, EVEN) RG_CHAIN_STEP(7, EVEN)                 \
+  RG_CHAIN_STEP(6, EVEN) RG_CHAIN_STEP(5, EVEN) RG_CHAIN_STEP(4, EVEN) RG_CHAIN_STEP(3, EVEN)                  \
+  RG_CHAIN_STEP(2, EVEN) RG_CHAIN_STEP(1, EVEN)
 
 // Powers held in registers by the register-array kernel (fewer than EV_PW, to
 // leave room for X; longer rows take one more Horner chunk).
@@ -641,7 +689,8 @@ __device__ __forceinline__ bool dev_eval_elim_rg(const JobDev& J, int lb, Tables
     bs = m;
     neg = ((m * n) & 1) != 0;
   }
-  while (bs > 0) {
+  if (as != bs + 1) {
+    // the first step of a pair with a != b + 1 (only the first can be)
     bool short_rem;
     const uint32_t lb = areg ? rg_step<C, true>(X, L, as, bs, &short_rem, q)
                              : rg_step<C, false>(X, L, as, bs, &short_rem, q);
@@ -659,8 +708,18 @@ __device__ __forceinline__ bool dev_eval_elim_rg(const JobDev& J, int lb, Tables
     as = bs;
     bs -= 1;
   }
-  // the constant remainder is in the array that does not hold A
-  num = mmul(num, mpow(areg ? L[0] : X[0], (uint32_t)as, q), q);
+  uint32_t last;
+  if (bs == 0) {
+    // the constant remainder is in the array that does not hold A
+    last = mpow(areg ? L[0] : X[0], (uint32_t)as, q);
+  } else if (areg == ((bs & 1) == 0)) {
+    RG_CHAIN(true)
+    last = L[0];  // the last step (B = 1, odd) eliminated into L
+  } else {
+    RG_CHAIN(false)
+    last = X[0];
+  }
+  num = mmul(num, last, q);
   uint32_t r = den == q.one ? num : mmul(num, minv(den, q), q);
   if (neg) r = mneg(r, q.p);
   J.vals[(size_t)k * J.D + pt] = from_mont(r, q);
