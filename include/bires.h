@@ -142,6 +142,26 @@ int bires_resultant_batch(int n, const bires_bipoly *f, const bires_bipoly *g,
                           const int32_t *kind, const int32_t *var,
                           bires_upoly *out, int32_t *status, int mem, void *stream);
 
+/* Asynchronous form of bires_resultant_batch (same arguments, plus *ticket).
+ * The batch is queued to one of two library worker threads, each with its own
+ * stream, and the call returns at once.  The batch starts on the device after
+ * the work queued on `stream` before the call (an event recorded there), so
+ * inputs produced on that stream are complete; with stream = NULL it starts
+ * at once (the caller guarantees complete inputs; an event on the legacy
+ * default stream would also wait for the batches in flight, so pass a
+ * non-blocking stream to order after).  The descriptor, status and
+ * output arrays and the input and output buffers must stay valid, and the
+ * inputs unchanged, until bires_batch_wait returns for the ticket.  With two
+ * batches in flight, one batch's row scan and planning overlap the other's
+ * kernels.  Batches in flight must not share output buffers. */
+int bires_resultant_batch_async(int n, const bires_bipoly *f, const bires_bipoly *g, const int32_t *kind,
+                                const int32_t *var, bires_upoly *out, int32_t *status, int mem, void *stream,
+                                uint64_t *ticket);
+/* Blocks until the batch of `ticket` has finished (its outputs are then
+ * complete for every stream) and returns what bires_resultant_batch would
+ * have; BIRES_EINVAL for an unknown or already collected ticket. */
+int bires_batch_wait(uint64_t ticket);
+
 /* ---------------- serving: continuous batching of mixed jobs ---------------- */
 
 typedef struct bires_server bires_server;
@@ -207,6 +227,19 @@ int bires_set_schedule(int schedule);
 #define BIRES_EVAL_AUTO 0
 #define BIRES_EVAL_LDS 1
 int bires_set_eval_kernel(int kernel);
+
+/* Plan reuse for batched calls with device-memory inputs (default on): when
+ * a call has the same descriptors as the previous one (input and output
+ * pointers, extents, capacities, kinds, variables) and the last planned calls
+ * saw the same row statistics, it keeps their plans and does not wait for its
+ * own row scan before launching; a device kernel then compares the scan's
+ * output with the statistics those plans came from, word for word, and on any
+ * difference the call is rerun with fresh plans before it returns.  Equal
+ * statistics give equal plans, so results never depend on the setting.
+ * bires_plan_cache_stats: calls that reused plans, and reuses undone by a
+ * mismatch, since set-up.  Process-wide. */
+int bires_set_plan_cache(int enable);
+int bires_plan_cache_stats(int64_t *hits, int64_t *misses);
 
 /* Graph replay: when enabled, batched calls issue their device sequence
  * (metadata upload, the stage kernels of the chosen schedule, status and

@@ -63,6 +63,11 @@ _SIGS = {
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(Upoly), ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
                                ctypes.c_void_p], ctypes.c_int),
+    "bires_resultant_batch_async": ([ctypes.c_int, ctypes.POINTER(Bipoly), ctypes.POINTER(Bipoly),
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(Upoly), ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
+                                     ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "bires_batch_wait": ([ctypes.c_uint64], ctypes.c_int),
     "bires_server_create": ([ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "bires_server_submit": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Bipoly),
                              ctypes.POINTER(Bipoly), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -80,6 +85,8 @@ _SIGS = {
     "bires_set_schedule": ([ctypes.c_int], ctypes.c_int),
     "bires_set_graphs": ([ctypes.c_int], ctypes.c_int),
     "bires_set_eval_kernel": ([ctypes.c_int], ctypes.c_int),
+    "bires_set_plan_cache": ([ctypes.c_int], ctypes.c_int),
+    "bires_plan_cache_stats": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "bires_graph_stats": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "bires_autotune": ([ctypes.c_int, ctypes.POINTER(Bipoly), ctypes.POINTER(Bipoly),
                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Upoly),
@@ -369,6 +376,19 @@ def set_eval_kernel(kernel):
     _check(lib().bires_set_eval_kernel({"auto": 0, "lds": 1}[kernel]), "bires_set_eval_kernel")
 
 
+def set_plan_cache(enable):
+    """Reuse of the previous batched call's plans (checked on the device)."""
+    _check(lib().bires_set_plan_cache(1 if enable else 0), "bires_set_plan_cache")
+
+
+def plan_cache_stats():
+    """(calls that reused plans, reuses undone by a statistics mismatch)."""
+    h = ctypes.c_int64()
+    m = ctypes.c_int64()
+    _check(lib().bires_plan_cache_stats(ctypes.byref(h), ctypes.byref(m)), "bires_plan_cache_stats")
+    return h.value, m.value
+
+
 def set_graphs(enable):
     """Replay each batched call's device sequence as a captured HIP graph."""
     _check(lib().bires_set_graphs(1 if enable else 0), "bires_set_graphs")
@@ -461,6 +481,32 @@ class DeviceBatch:
         code = lib().bires_resultant_batch(self.n, self.fds, self.gds, self.kinds, self.vars, self.outs,
                                            self.status, MEM_DEVICE, _torch_stream(stream))
         _check(code, "bires_resultant_batch")
+        return code
+
+    def run_async(self, stream=None):
+        """Queues the batch (bires_resultant_batch_async) and returns at once;
+        wait() collects it.  With stream (a torch stream) the batch starts
+        after the work queued there; without one the inputs must be complete.
+        One call per DeviceBatch may be in flight: its descriptors and output
+        tensors belong to that call until wait()."""
+        if getattr(self, "_ticket", None) is not None:
+            raise RuntimeError("a call of this batch is still in flight")
+        self._reset_outs()
+        t = ctypes.c_uint64()
+        _check(lib().bires_resultant_batch_async(self.n, self.fds, self.gds, self.kinds, self.vars, self.outs,
+                                                 self.status, MEM_DEVICE,
+                                                 None if stream is None else _torch_stream(stream), ctypes.byref(t)),
+               "bires_resultant_batch_async")
+        self._ticket = t.value
+        return t.value
+
+    def wait(self):
+        """Blocks until the call queued by run_async has finished."""
+        t, self._ticket = getattr(self, "_ticket", None), None
+        if t is None:
+            raise RuntimeError("no call of this batch in flight")
+        code = lib().bires_batch_wait(t)
+        _check(code, "bires_batch_wait")
         return code
 
     def autotune(self, reps=3, stream=None):

@@ -2,8 +2,11 @@
 #include <chrono>
 #include <cstring>
 #include <mutex>
+#include <utility>
+#include <vector>
 
 #include "../../include/bires.h"
+#include "async.hpp"
 #include "engine.hpp"
 #include "gcd.hpp"
 #include "tables.hpp"
@@ -21,6 +24,27 @@ int with_stream(void* stream, F&& f) {
   if (stream) return f(cx, (hipStream_t)stream);
   std::lock_guard<std::mutex> lk(cx->stream_mu);
   return f(cx, cx->stream);
+}
+
+// Job list of a batched call (validation of the array arguments only).
+int batch_jobs(int n, const bires_bipoly* f, const bires_bipoly* g, const int32_t* kind, const int32_t* var,
+               bires_upoly* out, std::vector<JobIn>* jobs) {
+  if (n < 0 || (n > 0 && (!f || !kind || !var || !out))) return BIRES_EINVAL;
+  jobs->assign(n, JobIn{});
+  for (int i = 0; i < n; ++i) {
+    JobIn& jb = (*jobs)[i];
+    jb.f = f[i];
+    jb.kind = kind[i];
+    if (kind[i] == BIRES_KIND_RESULTANT) {
+      if (!g) return BIRES_EINVAL;
+      jb.g = g[i];
+    } else {
+      jb.g = f[i];
+    }
+    jb.var = var[i];
+    jb.out = &out[i];
+  }
+  return BIRES_OK;
 }
 
 }  // namespace
@@ -79,22 +103,30 @@ int bires_discriminant(const bires_bipoly* f, int var, bires_upoly* out, int mem
 
 int bires_resultant_batch(int n, const bires_bipoly* f, const bires_bipoly* g, const int32_t* kind,
                           const int32_t* var, bires_upoly* out, int32_t* status, int mem, void* stream) {
-  if (n < 0 || (n > 0 && (!f || !kind || !var || !out))) return BIRES_EINVAL;
-  if (n == 0) return BIRES_OK;
-  std::vector<JobIn> jobs(n);
-  for (int i = 0; i < n; ++i) {
-    jobs[i].f = f[i];
-    jobs[i].kind = kind[i];
-    if (kind[i] == BIRES_KIND_RESULTANT) {
-      if (!g) return BIRES_EINVAL;
-      jobs[i].g = g[i];
-    } else {
-      jobs[i].g = f[i];
-    }
-    jobs[i].var = var[i];
-    jobs[i].out = &out[i];
-  }
+  std::vector<JobIn> jobs;
+  const int e = batch_jobs(n, f, g, kind, var, out, &jobs);
+  if (e || n == 0) return e;
   return with_stream(stream, [&](Context* cx, hipStream_t st) { return run_batch(cx, jobs, mem, st, status); });
+}
+
+int bires_resultant_batch_async(int n, const bires_bipoly* f, const bires_bipoly* g, const int32_t* kind,
+                                const int32_t* var, bires_upoly* out, int32_t* status, int mem, void* stream,
+                                uint64_t* ticket) {
+  if (!ticket) return BIRES_EINVAL;
+  std::vector<JobIn> jobs;
+  const int e = batch_jobs(n, f, g, kind, var, out, &jobs);
+  if (e) return e;
+  int err = BIRES_OK;
+  Context* cx = context(&err);
+  if (!cx) return err;
+  return async_submit(cx, std::move(jobs), mem, status, (hipStream_t)stream, ticket);
+}
+
+int bires_batch_wait(uint64_t ticket) {
+  int err = BIRES_OK;
+  Context* cx = context(&err);
+  if (!cx) return err;
+  return async_wait(cx, ticket);
 }
 
 int bires_gcd_bounds(const bires_upoly* a, const bires_upoly* b, int32_t* max_degree, int32_t* max_limbs) {
@@ -185,6 +217,27 @@ int bires_set_eval_kernel(int kernel) {
   Context* cx = context(&err);
   if (!cx) return err;
   cx->eval_rg = kernel == BIRES_EVAL_AUTO;
+  return BIRES_OK;
+}
+
+int bires_set_plan_cache(int enable) {
+  int err = BIRES_OK;
+  Context* cx = context(&err);
+  if (!cx) return err;
+  cx->plan_cache = enable != 0;
+  std::lock_guard<std::mutex> lk(cx->spec.mu);
+  cx->spec.valid = false;
+  cx->spec.conf = 0;
+  return BIRES_OK;
+}
+
+int bires_plan_cache_stats(int64_t* hits, int64_t* misses) {
+  int err = BIRES_OK;
+  Context* cx = context(&err);
+  if (!cx) return err;
+  std::lock_guard<std::mutex> lk(cx->spec.mu);
+  if (hits) *hits = cx->spec.hits;
+  if (misses) *misses = cx->spec.misses;
   return BIRES_OK;
 }
 

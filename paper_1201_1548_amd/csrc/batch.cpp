@@ -73,6 +73,26 @@ struct Held {
 
 }  // namespace
 
+static SpecKey key_of(const JobIn& jb) {
+  SpecKey k;
+  std::memset(&k, 0, sizeof k);
+  k.fc = jb.f.c;
+  k.gc = jb.g.c;
+  k.oc = jb.out ? jb.out->c : nullptr;
+  k.f[0] = jb.f.deg_x, k.f[1] = jb.f.deg_y, k.f[2] = jb.f.limbs;
+  k.g[0] = jb.g.deg_x, k.g[1] = jb.g.deg_y, k.g[2] = jb.g.limbs;
+  k.kind = jb.kind;
+  k.var = jb.var;
+  k.odeg = jb.out ? jb.out->degree : 0;
+  k.olimbs = jb.out ? jb.out->limbs : 0;
+  return k;
+}
+
+static bool same_key(const SpecKey& a, const JobIn& jb) {
+  const SpecKey b = key_of(jb);
+  return std::memcmp(&a, &b, sizeof a) == 0;
+}
+
 static int validate(const JobIn& jb, bool need_out) {
   if (jb.kind != BIRES_KIND_RESULTANT && jb.kind != BIRES_KIND_DISCRIMINANT) return BIRES_EINVAL;
   if (jb.var != BIRES_VAR_X && jb.var != BIRES_VAR_Y) return BIRES_EINVAL;
@@ -167,7 +187,8 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     }
   }
   // scan outputs: read by the host from the pinned staging block
-  (void)in.take(0);
+  const size_t o_scan0 = in.take(0);
+  size_t o_scan_end = o_scan0;
   if (mem == BIRES_MEM_DEVICE) {
     for (int i = 0; i < nj; ++i) {
       if (w[i].status) continue;
@@ -180,10 +201,24 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
       }
     }
   }
+  o_scan_end = in.bytes;
   const size_t o_tasks = in.take(sizeof(ScanTask) * tasks.size());
   const size_t o_smap = in.take(sizeof(int4) * smap.size());
+  const size_t scan_words = (o_scan_end - o_scan0) / 4;
   Held d_in(&cx->dev, in.bytes), h_in(&cx->host, in.bytes);
   if (in.bytes && (!d_in.p || !h_in.p)) return BIRES_ENOMEM;
+  // Plans reused from the previous call when it had the same descriptors and
+  // the statistics have repeated; the scan still runs and a device check of
+  // its output against the statistics of those plans decides, at the end,
+  // whether the call stands or is rerun with fresh plans.
+  SpecCache& sc = cx->spec;
+  std::unique_lock<std::mutex> spec_lk(sc.mu, std::defer_lock);
+  const bool spec_ok = cx->plan_cache && mem == BIRES_MEM_DEVICE && !debug && scan_words > 0 && spec_lk.try_lock();
+  bool spec = false;
+  if (spec_ok && sc.valid && sc.conf >= 1 && sc.image.size() == scan_words && sc.keys.size() == (size_t)nj) {
+    spec = true;
+    for (int i = 0; i < nj && spec; ++i) spec = same_key(sc.keys[i], jobs[i]);
+  }
 
   if (mem == BIRES_MEM_HOST) {
     for (int i = 0; i < nj; ++i) {
@@ -226,21 +261,42 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     if (!smap.empty())
       launch_scan((const ScanTask*)(hmap + o_tasks), (const int4*)(hmap + o_smap), (int)smap.size(), st);
     hc.mark(1);
-    DEV(hipStreamSynchronize(st));
-    hc.mark(2);
-    for (int i = 0; i < nj; ++i) {
-      if (w[i].status) continue;
-      for (int which = 0; which < nsrc(i); ++which) {
-        const int rows = shp(i, which).rows;
-        const int32_t* v = (const int32_t*)(h_in.b() + w[i].o_scan[which]);
-        RowStats& rs = which ? w[i].stg : w[i].stf;
-        rs.v.assign(v, v + ROWSTAT_WORDS * (size_t)rows);
+    if (!spec) {
+      DEV(hipStreamSynchronize(st));
+      hc.mark(2);
+      for (int i = 0; i < nj; ++i) {
+        if (w[i].status) continue;
+        for (int which = 0; which < nsrc(i); ++which) {
+          const int rows = shp(i, which).rows;
+          const int32_t* v = (const int32_t*)(h_in.b() + w[i].o_scan[which]);
+          RowStats& rs = which ? w[i].stg : w[i].stf;
+          rs.v.assign(v, v + ROWSTAT_WORDS * (size_t)rows);
+        }
       }
     }
   }
 
   // ---------------- plans and output capacities
-  for (int i = 0; i < nj; ++i) {
+  std::vector<int32_t> rowdeg;  // per active job: the m + 1 row degrees of f, then the n + 1 of g
+  std::vector<int> rd_off(nj, 0);
+  if (spec) {
+    rowdeg = sc.rowdeg;
+    for (int i = 0; i < nj; ++i) {
+      Work& x = w[i];
+      const SpecJob& c = sc.plans[i];
+      x.status = c.status;
+      x.active = c.active;
+      x.pl = c.pl;
+      x.Lout = c.Lout;
+      x.degcap = c.degcap;
+      x.Tf = c.Tf;
+      x.Tg = c.Tg;
+      x.ldg = c.ldg;
+      x.Lacc = c.Lacc;
+      rd_off[i] = c.rd_off;
+    }
+  }
+  for (int i = 0; i < nj && !spec; ++i) {
     Work& x = w[i];
     if (x.status) continue;
     if (x.disc) {
@@ -280,6 +336,9 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
       x.Tf = (x.pl.m + 1) * pad4(x.sf.ld);
       x.Tg = (x.pl.n + 1) * pad4(x.ldg);
       x.Lacc = std::min(x.Lout, x.pl.P + 1);
+      rd_off[i] = (int)rowdeg.size();
+      for (int j = 0; j <= x.pl.m; ++j) rowdeg.push_back(x.stf.deg(j));
+      for (int j = 0; j <= x.pl.n; ++j) rowdeg.push_back(x.stg.deg(j));
     }
   }
 
@@ -405,7 +464,8 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   // metadata uploaded with one copy: descriptors, flags, row degrees, block maps
   const size_t meta_begin = ws.take(0);
   const size_t o_jobs = ws.take(sizeof(JobDev) * (size_t)nj);
-  const size_t o_flags = ws.take(sizeof(int32_t) * (2 * (size_t)nj + 1));  // [deg_out, err] per job, fused error
+  // [deg_out, err] per job, fused error, statistics mismatch of reused plans
+  const size_t o_flags = ws.take(sizeof(int32_t) * (2 * (size_t)nj + 2));
   const size_t o_fbc = ws.take(sizeof(int) * NRG);                         // queue lengths, uploaded as zero
   for (int i = 0; i < nj; ++i)
     if (!w[i].status && w[i].active) w[i].o_rowdeg = ws.take((size_t)(w[i].pl.m + w[i].pl.n + 2) * 4);
@@ -448,7 +508,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   for (int i = 0; i < nj; ++i) {
     h_flags[2 * i] = -1;
     h_flags[2 * i + 1] = 0;
-    if (i == nj - 1) h_flags[2 * nj] = 0;
+    if (i == nj - 1) h_flags[2 * nj] = h_flags[2 * nj + 1] = 0;
     h_jobs[i] = JobDev{};
     Work& x = w[i];
     if (x.status || !x.active) continue;
@@ -470,8 +530,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     J.Tf = x.Tf;
     J.Tg = x.Tg;
     int32_t* rd = (int32_t*)(H0 + x.o_rowdeg);
-    for (int j = 0; j <= p.m; ++j) rd[j] = x.stf.deg(j);
-    for (int j = 0; j <= p.n; ++j) rd[p.m + 1 + j] = x.stg.deg(j);
+    std::memcpy(rd, rowdeg.data() + rd_off[i], sizeof(int32_t) * (size_t)(p.m + p.n + 2));
     J.rowdeg_f = (const int32_t*)(D0 + x.o_rowdeg);
     J.rowdeg_g = J.rowdeg_f + p.m + 1;
     J.res_f = (uint32_t*)(D0 + x.o_res_f);
@@ -562,10 +621,21 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     DEV(hipEventCreate(&ev0));
     DEV(hipEventCreate(&ev1));
   }
+  const int32_t* spec_got = nullptr;
+  if (spec) {
+    uint8_t* hmap = nullptr;
+    DEV(hipHostGetDevicePointer((void**)&hmap, h_in.p, 0));
+    spec_got = (const int32_t*)(hmap + o_scan0);
+  }
   auto seq = [&](bool run, SeqHash& sg) -> int {
     sg.add(st, D0, meta_begin, meta_end, (const void*)h_meta.p);
     if (run && meta_end > meta_begin)
       DEV(hipMemcpyAsync(D0 + meta_begin, h_meta.p, meta_end - meta_begin, hipMemcpyHostToDevice, st));
+    if (spec) {
+      sg.add((const void*)spec_got, (const void*)sc.d_image, scan_words);
+      if (run)
+        launch_stats_check(spec_got, sc.d_image, (long long)scan_words, (int*)(D0 + o_flags) + 2 * nj + 1, st);
+    }
     if (fused) {
       sg.add(F, f_lds, f_blocks);
       if (run && timing) DEV(hipEventRecord(ev0, st));
@@ -610,7 +680,8 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     if (run) DEV(hipGetLastError());
     if (debug) return BIRES_OK;
     sg.add(nj, o_flags, (const void*)h_flags);
-    if (run && nj) DEV(hipMemcpyAsync(h_flags, D0 + o_flags, sizeof(int32_t) * 2 * nj, hipMemcpyDeviceToHost, st));
+    if (run && nj)
+      DEV(hipMemcpyAsync(h_flags, D0 + o_flags, sizeof(int32_t) * (2 * nj + 2), hipMemcpyDeviceToHost, st));
     if (fused) {
       sg.add(ctr_off[nj]);
       if (run)
@@ -676,6 +747,53 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     }
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
+  }
+  if (spec) {
+    if (h_flags[2 * nj + 1]) {
+      // the statistics changed: drop the cache and rerun with fresh plans
+      sc.valid = false;
+      sc.conf = 0;
+      sc.misses++;
+      spec_lk.unlock();
+      return run_batch(cx, jobs, mem, st, status);
+    }
+    sc.hits++;
+  } else if (spec_ok) {
+    int bad = 0;
+    for (int i = 0; i < nj; ++i) bad |= w[i].status;
+    const int32_t* img = (const int32_t*)(h_in.b() + o_scan0);
+    bool same = sc.valid && sc.image.size() == scan_words && sc.keys.size() == (size_t)nj &&
+                std::memcmp(sc.image.data(), img, scan_words * 4) == 0;
+    for (int i = 0; i < nj && same; ++i) same = same_key(sc.keys[i], jobs[i]);
+    if (bad) {
+      sc.valid = false;  // output-size errors rewrite descriptors: plan those calls afresh
+      sc.conf = 0;
+    } else {
+      sc.conf = same ? sc.conf + 1 : 0;
+      if (!same) {
+        sc.keys.resize(nj);
+        for (int i = 0; i < nj; ++i) sc.keys[i] = key_of(jobs[i]);
+        sc.image.assign(img, img + scan_words);
+        sc.plans.resize(nj);
+        for (int i = 0; i < nj; ++i) {
+          const Work& x = w[i];
+          sc.plans[i] = SpecJob{x.status, x.active, x.pl, x.Lout, x.degcap, x.Tf, x.Tg, x.ldg, x.Lacc, rd_off[i]};
+        }
+        sc.rowdeg = rowdeg;
+        bool up = true;
+        if (sc.d_cap < scan_words) {
+          if (sc.d_image) (void)hipFree(sc.d_image);
+          sc.d_image = nullptr;
+          sc.d_cap = 0;
+          up = hipMalloc((void**)&sc.d_image, scan_words * 4) == hipSuccess;
+          if (up) sc.d_cap = scan_words;
+        }
+        up = up && hipMemcpy(sc.d_image, img, scan_words * 4, hipMemcpyHostToDevice) == hipSuccess;
+        if (!up) (void)hipGetLastError();
+        sc.valid = up;
+        if (!up) sc.conf = 0;
+      }
+    }
   }
   const int fused_err = fused ? h_flags[2 * nj] : 0;
   int first_err = BIRES_OK;

@@ -36,6 +36,36 @@ class Pool {
   std::vector<Block> used_;
 };
 
+// Plans of the last batched call with device-memory inputs, reused by the
+// next call with the same descriptors while the row statistics repeat; the
+// reusing call checks the fresh statistics against `image` on the device and
+// is rerun with fresh plans when they differ.
+struct SpecJob {
+  int status = 0;
+  bool active = false;
+  Plan pl;
+  int Lout = 1, degcap = 0, Tf = 0, Tg = 0, ldg = 0, Lacc = 1;
+  int rd_off = 0;  // into rowdeg: m + 1 + n + 1 row degrees when active
+};
+struct SpecKey {  // the fields of a JobIn that planning reads
+  const void* fc;
+  const void* gc;
+  const void* oc;
+  int32_t f[3], g[3], kind, var, odeg, olimbs;
+};
+struct SpecCache {
+  std::mutex mu;
+  bool valid = false;
+  int conf = 0;  // consecutive planned calls whose statistics equalled the previous ones
+  std::vector<SpecKey> keys;
+  std::vector<int32_t> image;  // the scan's output words
+  int32_t* d_image = nullptr;  // device copy of image
+  size_t d_cap = 0;
+  std::vector<SpecJob> plans;
+  std::vector<int32_t> rowdeg;
+  int64_t hits = 0, misses = 0;
+};
+
 struct Context {
   int device = -1;
   hipStream_t stream = nullptr;     // library stream (default priority)
@@ -60,6 +90,8 @@ struct Context {
   std::map<int, std::pair<const uint32_t*, int>> crt;  // P -> (device CrtHost buffer, LM)
   std::atomic<bool> eval_rg{true};                       // register-array evaluation kernel where it applies
   std::atomic<bool> graphs{false};                       // replay device sequences as captured graphs
+  std::atomic<bool> plan_cache{true};                    // speculative reuse of the last call's plans
+  SpecCache spec;
   std::mutex graph_mu;
   std::map<uint64_t, hipGraphExec_t> graph_cache;       // sequence hash -> instantiated graph
   std::vector<uint64_t> graph_order;                    // insertion order (oldest first)

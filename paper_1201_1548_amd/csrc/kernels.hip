@@ -1711,6 +1711,21 @@ void launch_gather_rows(const uint32_t* src, int ld, const int* idx, int rows, i
 // ---------------------------------------------------------------------------
 // launchers
 
+// Word-by-word comparison of the row statistics a call's scan produced with
+// the ones its reused plans were made from; any difference sets *flag.
+__global__ __launch_bounds__(256) void k_stats_check(const int32_t* got, const int32_t* want, long long n,
+                                                     int* flag) {
+  bool diff = false;
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    diff |= got[i] != want[i];
+  if (__ballot(diff) != 0ull && (threadIdx.x & 63) == 0) *flag = 1;
+}
+
+void launch_stats_check(const int32_t* got, const int32_t* want, long long n, int* flag, hipStream_t s) {
+  const long long blocks = std::min<long long>((n + 255) / 256, 1024);
+  if (blocks > 0) hipLaunchKernelGGL(k_stats_check, dim3((unsigned)blocks), dim3(256), 0, s, got, want, n, flag);
+}
+
 void launch_scan(const ScanTask* tasks, const int4* bmap, int nblocks, hipStream_t s) {
   hipLaunchKernelGGL(k_scan, dim3(nblocks), dim3(64), 0, s, tasks, bmap);
 }

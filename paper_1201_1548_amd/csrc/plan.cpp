@@ -110,37 +110,37 @@ static double pow2_nonpos(int e) {
   return d;
 }
 
-// 2^(r / 1024) for r = 0..1023.
-static const double* frac_pow2() {
-  static double t[1024];
-  static std::once_flag once;
-  std::call_once(once, [] {
-    for (int r = 0; r < 1024; ++r) t[r] = std::exp2(r / 1024.0);
-  });
-  return t;
+// 2^(-r / 1024) for r = 0..1023 (a function-local static: after the first
+// call, a guard check instead of std::call_once's per-call cost).
+struct FracPow2 {
+  double t[1024];
+  FracPow2() {
+    for (int r = 0; r < 1024; ++r) t[r] = std::exp2(-r / 1024.0);
+  }
+};
+static const double* frac_pow2_neg() {
+  static const FracPow2 f;
+  return f.t;
 }
 
-// log2 (sum_j N_j^2) with log2 N_j <= norm_j / 1024, rows 0..top: each term
-// 2^((2 norm_j - 2 emax) / 1024) is a power of two times a table entry (a term
-// below 2^-1022 of the largest one is dropped, far inside the margin of
-// hadamard_log2), so one log2 per call remains.
+// log2 (sum_j N_j^2) with log2 N_j <= norm_j / 1024, rows 0..top: with
+// d_j = 2 (emax - norm_j) >= 0 (1/1024 bits) each term is 2^(-d_j / 1024) =
+// 2^(-(d_j >> 10)) 2^(-(d_j & 1023) / 1024), a power of two times a table
+// entry (a term below 2^-1022 of the largest one is dropped, far inside the
+// margin of hadamard_log2), so one log2 per call remains.
 static double log2_sum_sq(const RowStats& s, int top) {
-  const double* fr = frac_pow2();
-  bool any = false;
-  int emax = 0;
+  const double* fr = frac_pow2_neg();
+  int emax = INT32_MIN;
+  for (int j = 0; j <= top; ++j)
+    if (s.cnt(j)) emax = std::max(emax, (int)s.norm(j));
+  if (emax == INT32_MIN) return -INFINITY;
+  double acc[2] = {0.0, 0.0};
   for (int j = 0; j <= top; ++j)
     if (s.cnt(j)) {
-      emax = any ? std::max(emax, (int)s.norm(j)) : (int)s.norm(j);
-      any = true;
+      const int d = 2 * (emax - s.norm(j));
+      acc[j & 1] += pow2_nonpos(-(d >> 10)) * fr[d & 1023];
     }
-  double acc = 0.0;
-  for (int j = 0; j <= top; ++j)
-    if (s.cnt(j)) {
-      const int e = 2 * (s.norm(j) - emax);  // <= 0, in 1/1024 bits
-      const int q = e >= 0 ? 0 : -((-e + 1023) / 1024);
-      acc += pow2_nonpos(q) * fr[e - 1024 * q];
-    }
-  return 2.0 * emax / 1024.0 + std::log2(acc);
+  return 2.0 * emax / 1024.0 + std::log2(acc[0] + acc[1]);
 }
 
 double hadamard_log2(const RowStats& f, int m, const RowStats& g, int n) {

@@ -139,10 +139,14 @@ CrtHost crt_tables(int P) {
   return c;
 }
 
+static HostTables built() {
+  HostTables t;
+  build(t, MAX_PRIMES);
+  return t;
+}
+
 const HostTables& host_tables() {
-  static HostTables t;
-  static std::once_flag once;
-  std::call_once(once, [] { build(t, MAX_PRIMES); });
+  static const HostTables t = built();  // thread-safe one-time initialisation
   return t;
 }
 

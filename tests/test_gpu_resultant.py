@@ -355,3 +355,91 @@ def test_register_and_lds_evaluation_kernels_agree():
     assert got[-5:-2] == single[:3]
     for (kind, F, G, var), R in list(zip(jobs, got))[-2:]:
         assert R == resultant_y(F, G)
+
+
+def test_async_batches_overlap_and_match():
+    # two device batches alternately in flight through the library workers;
+    # every result equals the synchronous call's, also with the caller's
+    # stream still busy writing the inputs when the batch is queued
+    import torch
+    jobs_a = [j for j in _mixed_jobs() if not (j[0] == "disc" and len(j[1]) < 2)]
+    jobs_b = [("res",) + synth.config1_pair(i % 4) + ("y",) for i in range(20)]
+    say("async batches", len(jobs_a), len(jobs_b))
+    a, b = br.DeviceBatch(jobs_a), br.DeviceBatch(jobs_b)
+    a.run()
+    ref_a = a.results()
+    b.run()
+    ref_b = b.results()
+    for rep in range(3):
+        for t in a.out_tensors + b.out_tensors:
+            t.fill_(7)
+        torch.cuda.synchronize()  # no stream given: the buffers must be settled
+        a.run_async()
+        b.run_async()
+        a.wait()
+        b.wait()
+        assert a.results() == ref_a, rep
+        assert b.results() == ref_b, rep
+    # inputs rewritten on a side stream right before the submission: the
+    # batch must see the new values (zeroed f rows give the zero resultant)
+    s = torch.cuda.Stream()
+    f0 = a.inputs[0][0]
+    saved = f0.tensor.clone()
+    with torch.cuda.stream(s):
+        torch.cuda._sleep(2000000)
+        f0.tensor.zero_()
+        a.run_async(stream=s)
+    a.wait()
+    got = a.results()
+    assert got[0] == []
+    assert got[1:] == ref_a[1:]
+    f0.tensor.copy_(saved)
+    torch.cuda.synchronize()
+    bad = br.lib().bires_batch_wait(123456789)
+    assert bad != 0
+
+
+def test_plan_reuse_is_checked_on_the_device():
+    # repeated device batches reuse the previous plans; a changed input whose
+    # row statistics stay the same keeps them (and its new results), one whose
+    # statistics change is caught by the device check and rerun
+    import torch
+    pairs = [synth.config1_pair(i % 4) for i in range(12)] + [synth.config2_pair(5)]
+    jobs = [("res", F, G, "y") for F, G in pairs]
+    say("plan reuse", len(jobs))
+    br.set_plan_cache(True)
+    b = br.DeviceBatch(jobs)
+    ref = [load("config1_res_%d.txt" % (i % 4))[1] for i in range(12)] + [br.resultant(*pairs[-1])]
+    h0, m0 = br.plan_cache_stats()
+    for _ in range(4):
+        b.run()
+        assert b.results() == ref
+    h1, m1 = br.plan_cache_stats()
+    assert h1 - h0 >= 2 and m1 == m0
+    # negate f's coefficient of x^1 y^0 in job 0: same magnitudes, same statistics
+    F0 = [list(r) for r in pairs[0][0]]
+    t = b.inputs[0][0].tensor
+    assert b.inputs[0][0].shape[2] == 1  # one 32-bit limb per coefficient
+    F0[0][1] = -F0[0][1]
+    t.view(-1)[1] = -int(t.view(-1)[1].item())
+    torch.cuda.synchronize()
+    b.run()
+    got = b.results()
+    assert got[0] == resultant_y(F0, pairs[0][1])
+    assert got[1:] == ref[1:]
+    h2, m2 = br.plan_cache_stats()
+    assert h2 == h1 + 1 and m2 == m1
+    # a coefficient far larger than before: new statistics, caught and rerun
+    F0[0][1] = 1 << 29
+    t.view(-1)[1] = 1 << 29
+    torch.cuda.synchronize()
+    b.run()
+    got = b.results()
+    assert got[0] == resultant_y(F0, pairs[0][1])
+    assert got[1:] == ref[1:]
+    h3, m3 = br.plan_cache_stats()
+    assert m3 == m2 + 1
+    br.set_plan_cache(False)
+    b.run()
+    assert b.results()[0] == got[0]
+    br.set_plan_cache(True)
