@@ -1324,7 +1324,7 @@ __global__ __launch_bounds__(64) void k_limbs_carry(const JobDev* jobs, const in
 // wave + 4, ...); one lane per coefficient then propagates the carries.
 // Nothing is serial in the prime index, unlike Garner's digits.
 constexpr int CRT_MAXP = 128;
-constexpr int CRT_R = 16;  // limb columns per wave and pass (registers)
+constexpr int CRT_R = 12;  // limb columns per wave and pass (registers)
 
 // LDS layout (words): Y [P][64] (later the output staging rows), Tq [64],
 // Mk [P][LMp], w [P], M [LMp], limbs [LMp][64], carries [4 * npass][64][2];
@@ -1394,40 +1394,44 @@ __device__ __forceinline__ void dev_crt(const JobDev& J, int lb, int stage_ld, T
   }
   __syncthreads();
   // column sums of the wave's CRT_R limbs per pass, prime-outer; then the
-  // range is normalised to 32-bit limbs plus a signed carry out
+  // range is normalised to 32-bit limbs plus a signed carry out.  y_k is
+  // split into 16-bit halves: each half times a limb is below 2^48, so P <=
+  // 128 of them sum in 64 bits with no carry word, one multiply-add each.
   const uint64_t t = (uint64_t)Tq[lane];
   for (int pass = 0; pass < npass; ++pass) {
     const int l0 = (pass * 4 + wave) * CRT_R;
-    uint64_t lo[CRT_R];
-    uint32_t hi[CRT_R];
+    uint64_t alo[CRT_R], ahi[CRT_R];
 #pragma unroll
     for (int j = 0; j < CRT_R; ++j) {
-      lo[j] = 0;
-      hi[j] = 0;
+      alo[j] = 0;
+      ahi[j] = 0;
     }
     // a range past the last limb is all padding (zero columns); the padded
     // columns of a partial range are zero in LDS and cost no branches
     const bool live = __builtin_amdgcn_readfirstlane(l0) < __builtin_amdgcn_readfirstlane(LM);
 #pragma unroll 2
     for (int k = 0; k < P && live; ++k) {
-      const uint64_t y = Y[k * 64 + lane];
+      const uint32_t y = Y[k * 64 + lane];
+      const uint64_t ylo = y & 0xFFFFu, yhi = y >> 16;
       const uint4* mk = (const uint4*)(Mk + k * LMp + l0);
-      const uint4 m0 = mk[0], m1 = mk[1], m2 = mk[2], m3 = mk[3];
-      const uint32_t mm[CRT_R] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w,
-                                  m2.x, m2.y, m2.z, m2.w, m3.x, m3.y, m3.z, m3.w};
+      const uint4 m0 = mk[0], m1 = mk[1], m2 = mk[2];
+      const uint32_t mm[CRT_R] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w, m2.x, m2.y, m2.z, m2.w};
 #pragma unroll
       for (int j = 0; j < CRT_R; ++j) {
-        const uint64_t pr = y * mm[j];
-        lo[j] += pr;
-        hi[j] += lo[j] < pr ? 1u : 0u;
+        alo[j] += ylo * mm[j];
+        ahi[j] += yhi * mm[j];
       }
     }
     int64_t carry = 0;
 #pragma unroll
     for (int j = 0; j < CRT_R; ++j) {
+      // the column sum ahi 2^16 + alo as 96 bits (h : lo); ahi < 2^54
+      const uint64_t sh = ahi[j] << 16;
+      const uint64_t lo = sh + alo[j];
+      const uint32_t hi = (uint32_t)(ahi[j] >> 48) + (lo < sh ? 1u : 0u);
       const uint64_t sub = t * Ms[l0 + j];
-      uint32_t h = hi[j] - (lo[j] < sub ? 1u : 0u);
-      uint64_t v = lo[j] - sub;
+      uint32_t h = hi - (lo < sub ? 1u : 0u);
+      uint64_t v = lo - sub;
       // v + carry as 96-bit two's complement (h:v)
       const uint64_t v2 = v + (uint64_t)carry;
       h += (carry < 0 ? 0xFFFFFFFFu : 0u) + (v2 < v ? 1u : 0u);

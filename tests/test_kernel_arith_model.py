@@ -405,7 +405,7 @@ def test_digit_grouped_products_reconstruct_the_residue():
             assert got == sum(a * b for a, b in zip(A, B)) % p
 
 
-def crt_model_ranges(residues, primes, R=16, Lc=None):
+def crt_model_ranges(residues, primes, R=12, Lc=None):
     """The limb kernel's staging of the explicit CRT: limb columns in ranges
     of R, each range normalised to 32-bit limbs plus a signed carry out with
     its own carry chain, then one pass adding each range's carry at the next
@@ -427,7 +427,11 @@ def crt_model_ranges(residues, primes, R=16, Lc=None):
         carry = 0
         for j in range(R):
             l = r * R + j
-            v = sum(yk * limb(mk, l) for yk, mk in zip(y, Mk)) - t * limb(M, l) + carry
+            # y_k in 16-bit halves, each half's column sum in 64 bits
+            alo = sum((yk & 0xFFFF) * limb(mk, l) for yk, mk in zip(y, Mk))
+            ahi = sum((yk >> 16) * limb(mk, l) for yk, mk in zip(y, Mk))
+            assert alo < 1 << 64 and ahi < 1 << 54
+            v = (ahi << 16) + alo - t * limb(M, l) + carry
             Lb[l] = v & 0xFFFFFFFF
             carry = v >> 32
         assert abs(carry) < 1 << 63
@@ -457,4 +461,5 @@ def test_explicit_crt_with_range_carries():
         M = math.prod(ps)
         B = int(Fraction(M) * Fraction(2.0 ** -1.001)) - 1
         for R in [0, 1, -1, B, -B] + [rng.randint(-B, B) for _ in range(20)]:
-            assert crt_model_ranges([R % p for p in ps], ps) == R, (P, R)
+            for width in (12, 16):
+                assert crt_model_ranges([R % p for p in ps], ps, R=width) == R, (P, R, width)
