@@ -309,6 +309,18 @@ def bench_config3(args):
     }
 
 
+def bench_rates(args):
+    """VALU issue cost per wave64 instruction (the library's probe kernels),
+    the figures behind the roofline's instruction model."""
+    import torch
+    import paper_1201_1548_amd as br
+    torch.cuda.set_device(0)
+    r = br.issue_rates()
+    return {"metric": "VALU issue cycles per wave64 instruction per SIMD", "value": r["v_mad_u64_u32"],
+            "unit": "cycles (v_mad_u64_u32)", "rates": {k: round(v, 3) for k, v in r.items()},
+            "device": br.device_info()}
+
+
 def bench_copy(args):
     """Calibration for the HBM counters: a plain device copy of a known size
     (torch's copy kernel), repeated `steps` times."""
@@ -341,7 +353,7 @@ def main():
                     help="also time the steps with two batches in flight (async submit)")
     ap.add_argument("--eval-kernel", default="auto", choices=["auto", "lds"],
                     help="evaluation + elimination kernel of the staged schedule")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5", "copy"])
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5", "copy", "rates"])
     ap.add_argument("--schedule", default="auto", choices=["auto", "staged", "fused"])
     ap.add_argument("--requests", type=int, default=300)
     ap.add_argument("--qps", type=float, default=0.0)
@@ -354,7 +366,7 @@ def main():
         sys.exit(2)
     if args.workload != "config2":
         fn = {"config3": bench_config3, "config4": bench_config4, "config5": bench_config5,
-              "copy": bench_copy}[args.workload]
+              "copy": bench_copy, "rates": bench_rates}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
 
@@ -478,9 +490,9 @@ def main():
         "peak": round(INT32_PEAK_TOPS, 1),
         "unit": "T int32-op/s",
         "frac": round(achieved / INT32_PEAK_TOPS, 4),
-        "traffic": stored_traffic("k_eval_elim", "config2_batch%d" % n),
+        "traffic": stored_traffic("k_eval_elim_rg24", "config2_batch%d" % n),
         "traffic_unit": "bytes per launch",
-        "kernel": "k_eval_elim",
+        "kernel": "k_eval_elim_rg24 (+ k_eval_elim_fb)",
         "kernel_ms": round(avg_ms, 4),
         "ops_per_launch": ops_launch,
     }

@@ -86,6 +86,7 @@ _SIGS = {
     "bires_set_graphs": ([ctypes.c_int], ctypes.c_int),
     "bires_set_eval_kernel": ([ctypes.c_int], ctypes.c_int),
     "bires_set_plan_cache": ([ctypes.c_int], ctypes.c_int),
+    "bires_issue_rates": ([ctypes.POINTER(ctypes.c_double), ctypes.c_int], ctypes.c_int),
     "bires_plan_cache_stats": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "bires_graph_stats": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "bires_autotune": ([ctypes.c_int, ctypes.POINTER(Bipoly), ctypes.POINTER(Bipoly),
@@ -374,6 +375,16 @@ def set_eval_kernel(kernel):
     """Evaluation + elimination kernel of the staged schedule: 'auto' (f's
     array in registers where the degrees allow) or 'lds'."""
     _check(lib().bires_set_eval_kernel({"auto": 0, "lds": 1}[kernel]), "bires_set_eval_kernel")
+
+
+ISSUE_RATE_INSTRUCTIONS = ("v_add_u32", "v_min_u32", "v_mul_lo_u32", "v_mad_u64_u32", "v_fma_f64")
+
+
+def issue_rates():
+    """SIMD cycles per wave64 instruction of single VALU instructions (dict)."""
+    c = (ctypes.c_double * len(ISSUE_RATE_INSTRUCTIONS))()
+    _check(lib().bires_issue_rates(c, len(c)), "bires_issue_rates")
+    return dict(zip(ISSUE_RATE_INSTRUCTIONS, list(c)))
 
 
 def set_plan_cache(enable):

@@ -1,4 +1,5 @@
 // The C ABI of include/bires.h.
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <mutex>
@@ -9,6 +10,7 @@
 #include "async.hpp"
 #include "engine.hpp"
 #include "gcd.hpp"
+#include "kernels.hpp"
 #include "tables.hpp"
 
 using namespace bires;
@@ -218,6 +220,42 @@ int bires_set_eval_kernel(int kernel) {
   if (!cx) return err;
   cx->eval_rg = kernel == BIRES_EVAL_AUTO;
   return BIRES_OK;
+}
+
+int bires_issue_rates(double* cycles, int n) {
+  if (!cycles || n < 1) return BIRES_EINVAL;
+  int err = BIRES_OK;
+  Context* cx = context(&err);
+  if (!cx) return err;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, cx->device) != hipSuccess) return BIRES_EDEVICE;
+  const int blocks = prop.multiProcessorCount * 16, iters = 2048;
+  uint32_t* out = nullptr;
+  if (hipMalloc((void**)&out, (size_t)blocks * 256 * 4) != hipSuccess) return BIRES_ENOMEM;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = BIRES_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = BIRES_EDEVICE;
+  const double simds = 4.0 * prop.multiProcessorCount, hz = prop.clockRate * 1e3;
+  const double waves = (double)blocks * 256 / 64, instr = waves * iters * 16;
+  std::lock_guard<std::mutex> lk(cx->stream_mu);
+  for (int k = 0; k < n && k < 5 && rc == BIRES_OK; ++k) {
+    float best = 1e30f;
+    for (int rep = 0; rep < 3 && rc == BIRES_OK; ++rep) {
+      float ms = 0.f;
+      if (hipEventRecord(e0, cx->stream) != hipSuccess) rc = BIRES_EDEVICE;
+      launch_issue_rate(k, out, blocks, iters, cx->stream);
+      if (hipEventRecord(e1, cx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess || hipGetLastError() != hipSuccess)
+        rc = BIRES_EDEVICE;
+      best = std::min(best, ms);
+    }
+    cycles[k] = simds * hz * best * 1e-3 / instr;  // SIMD-cycles per wave instruction
+  }
+  for (int k = 5; k < n; ++k) cycles[k] = 0.0;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  return rc;
 }
 
 int bires_set_plan_cache(int enable) {

@@ -1715,6 +1715,52 @@ void launch_gather_rows(const uint32_t* src, int ld, const int* idx, int rows, i
 // ---------------------------------------------------------------------------
 // launchers
 
+// Issue-rate probe for the roofline: every lane runs 16 independent chains
+// of one VALU instruction (inline assembly, so the compiler can neither fold
+// nor reorder them); the host divides the SIMD-cycles of the launch by the
+// wave instructions issued.  Writes one word per thread.
+template <int K>
+__global__ __launch_bounds__(256) void k_issue_rate(uint32_t* out, uint32_t s, int iters) {
+  uint32_t a[16];
+  uint64_t w[16];
+  double f[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    a[c] = threadIdx.x + c;
+    w[c] = threadIdx.x * 3u + c;
+    f[c] = threadIdx.x + c * 0.5;
+  }
+  const uint32_t b = s ^ threadIdx.x;
+  const double fb = 0.999 + threadIdx.x * 1e-9;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      if constexpr (K == 0) asm volatile("v_add_u32 %0, %0, %1" : "+v"(a[c]) : "v"(b));
+      if constexpr (K == 1) asm volatile("v_min_u32 %0, %0, %1" : "+v"(a[c]) : "v"(b));
+      if constexpr (K == 2) asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(a[c]) : "v"(b));
+      if constexpr (K == 3) {
+        uint64_t cy;
+        asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(w[c]), "=s"(cy) : "v"(a[c]), "v"(b));
+      }
+      if constexpr (K == 4) asm volatile("v_fma_f64 %0, %0, %1, 1.0" : "+v"(f[c]) : "v"(fb));
+    }
+  }
+  uint32_t r = 0;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) r += a[c] + (uint32_t)w[c] + (uint32_t)f[c];
+  out[blockIdx.x * 256 + threadIdx.x] = r;
+}
+
+void launch_issue_rate(int kind, uint32_t* out, int blocks, int iters, hipStream_t s) {
+  switch (kind) {
+    case 0: hipLaunchKernelGGL(k_issue_rate<0>, dim3(blocks), dim3(256), 0, s, out, 7u, iters); break;
+    case 1: hipLaunchKernelGGL(k_issue_rate<1>, dim3(blocks), dim3(256), 0, s, out, 7u, iters); break;
+    case 2: hipLaunchKernelGGL(k_issue_rate<2>, dim3(blocks), dim3(256), 0, s, out, 7u, iters); break;
+    case 3: hipLaunchKernelGGL(k_issue_rate<3>, dim3(blocks), dim3(256), 0, s, out, 7u, iters); break;
+    default: hipLaunchKernelGGL(k_issue_rate<4>, dim3(blocks), dim3(256), 0, s, out, 7u, iters); break;
+  }
+}
+
 // Word-by-word comparison of the row statistics a call's scan produced with
 // the ones its reused plans were made from; any difference sets *flag.
 __global__ __launch_bounds__(256) void k_stats_check(const int32_t* got, const int32_t* want, long long n,
@@ -1772,7 +1818,7 @@ void launch_eval_elim_rg(int C, const JobDev* jobs, const int* starts, int nj, i
     hipLaunchKernelGGL(k_eval_elim_rg24, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, tab, fb_count, fb_queue);
   else
     hipLaunchKernelGGL(k_eval_elim_rg32, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, tab, fb_count, fb_queue);
-  hipLaunchKernelGGL(k_eval_elim_fb, dim3(std::min(nblocks, 1024)), dim3(64), eval_elim_lds_bytes(max_words, 0), s,
+  hipLaunchKernelGGL(k_eval_elim_fb, dim3(std::min(nblocks, 256)), dim3(64), eval_elim_lds_bytes(max_words, 0), s,
                      jobs, starts, nj, tab, fb_count, fb_queue);
 }
 

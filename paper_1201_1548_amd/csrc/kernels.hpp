@@ -16,6 +16,10 @@ struct ScanTask {
 };
 
 void launch_scan(const ScanTask* tasks, const int4* bmap, int nblocks, hipStream_t s);
+// Issue-rate probe: kind 0..4 = v_add_u32, v_min_u32, v_mul_lo_u32,
+// v_mad_u64_u32, v_fma_f64; 16 chains per lane, `iters` rounds; out holds
+// blocks * 256 words.
+void launch_issue_rate(int kind, uint32_t* out, int blocks, int iters, hipStream_t s);
 // Sets *flag (not cleared here) when got[0..n) and want[0..n) differ.
 void launch_stats_check(const int32_t* got, const int32_t* want, long long n, int* flag, hipStream_t s);
 void launch_transpose(const uint32_t* src, uint32_t* dst, int rows, int cols, int L, hipStream_t s);
