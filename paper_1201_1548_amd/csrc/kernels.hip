@@ -391,21 +391,31 @@ __device__ __forceinline__ uint32_t eval_row(C* c, int d, const uint32_t (&pw)[N
     u32x4 v[NPW / 4];
 #pragma unroll
     for (int g = 0; g < NPW / 4; ++g) v[g] = cc[g];
+    // The powers pass through an empty asm here so that their widening to
+    // 64 bits stays at the products (where it is free in v_mad_u64_u32)
+    // instead of being hoisted out of the row loop as zero-extended register
+    // pairs, which doubled their register count.
+    uint32_t pq[NPW];
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+      pq[i] = pw[i];
+      asm volatile("" : "+v"(pq[i]));
+    }
     Acc96 S;
 #pragma unroll
     for (int h = 0; h < NPW / 8; ++h) {
       if (2 * h < ng) {
         const u32x4 x = v[2 * h];
-        uint64_t t = (uint64_t)x.x * pw[8 * h];
-        t += (uint64_t)x.y * pw[8 * h + 1];
-        t += (uint64_t)x.z * pw[8 * h + 2];
-        t += (uint64_t)x.w * pw[8 * h + 3];
+        uint64_t t = (uint64_t)x.x * pq[8 * h];
+        t += (uint64_t)x.y * pq[8 * h + 1];
+        t += (uint64_t)x.z * pq[8 * h + 2];
+        t += (uint64_t)x.w * pq[8 * h + 3];
         if (2 * h + 1 < ng) {
           const u32x4 y = v[2 * h + 1];
-          t += (uint64_t)y.x * pw[8 * h + 4];
-          t += (uint64_t)y.y * pw[8 * h + 5];
-          t += (uint64_t)y.z * pw[8 * h + 6];
-          t += (uint64_t)y.w * pw[8 * h + 7];
+          t += (uint64_t)y.x * pq[8 * h + 4];
+          t += (uint64_t)y.y * pq[8 * h + 5];
+          t += (uint64_t)y.z * pq[8 * h + 6];
+          t += (uint64_t)y.w * pq[8 * h + 7];
         }
         S.add(t);
       }
