@@ -1649,13 +1649,26 @@ __global__ __launch_bounds__(256) void k_gcd_p(GcdDev G, TablesDev tab) {
       break;
     }
     const uint32_t lb = Y[b];
-    for (int aa = a; aa >= b; --aa) {
-      const uint32_t nla = mneg(X[aa], q.p);
-      const int s = aa - b;
-      __syncthreads();  // every thread has read X[aa] before it can be overwritten below
-      for (int t = tid; t < aa; t += blockDim.x)
-        X[t] = t < s ? mmul(lb, X[t], q) : mdot2(lb, X[t], nla, Y[t - s], q);
+    if (a == b + 1) {
+      // the usual step: both eliminations in one pass, as in eliminate()
+      // (X_t <- lb^2 X_t - lb X_a Y_{t-1} - X'_{a-1} Y_t with X'_{a-1} the
+      // first elimination's new top coefficient)
+      const uint32_t nla = mneg(X[a], q.p);
+      const uint32_t n2 = mneg(mdot2(lb, X[a - 1], nla, Y[b - 1], q), q.p);
+      const uint32_t l2 = mmul(lb, lb, q), l1 = mmul(lb, nla, q);
+      __syncthreads();  // every thread has read X[a], X[a-1] before they can be overwritten below
+      for (int t = tid; t < b; t += blockDim.x)
+        X[t] = t ? mdot3(l2, X[t], l1, Y[t - 1], n2, Y[t], q) : mdot2(l2, X[0], n2, Y[0], q);
       __syncthreads();
+    } else {
+      for (int aa = a; aa >= b; --aa) {
+        const uint32_t nla = mneg(X[aa], q.p);
+        const int s = aa - b;
+        __syncthreads();  // every thread has read X[aa] before it can be overwritten below
+        for (int t = tid; t < aa; t += blockDim.x)
+          X[t] = t < s ? mmul(lb, X[t], q) : mdot2(lb, X[t], nla, Y[t - s], q);
+        __syncthreads();
+      }
     }
     int c = b - 1;
     while (c >= 0 && X[c] == 0u) --c;
