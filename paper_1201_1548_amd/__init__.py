@@ -145,28 +145,20 @@ def limbs_needed(values):
 
 def ints_to_limbs(values, L):
     """Python ints -> uint32 array [len(values), L] (two's complement)."""
-    out = np.zeros((len(values), L), dtype=np.uint32)
-    mod = 1 << (32 * L)
-    for r, v in enumerate(values):
-        u = v % mod
-        if L == 1:
-            out[r, 0] = u
-        else:
-            out[r] = np.frombuffer(u.to_bytes(4 * L, "little"), dtype="<u4")
-    return out
+    n = len(values)
+    if L == 1:
+        return np.array([v & 0xFFFFFFFF for v in values], dtype=np.uint32).reshape(n, 1)
+    nb = 4 * L
+    buf = b"".join(v.to_bytes(nb, "little", signed=True) for v in values)
+    return np.frombuffer(buf, dtype="<u4").reshape(n, L).copy()
 
 
 def limbs_to_ints(arr):
     """uint32 array [n, L] -> Python ints (two's complement)."""
     n, L = arr.shape
-    half = 1 << (32 * L - 1)
-    full = 1 << (32 * L)
-    res = []
-    raw = np.ascontiguousarray(arr, dtype="<u4")
-    for r in range(n):
-        u = int.from_bytes(raw[r].tobytes(), "little")
-        res.append(u - full if u >= half else u)
-    return res
+    raw = np.ascontiguousarray(arr, dtype="<u4").tobytes()
+    nb = 4 * L
+    return [int.from_bytes(raw[r * nb:(r + 1) * nb], "little", signed=True) for r in range(n)]
 
 
 def bipoly_array(F, limbs=None):
