@@ -457,6 +457,14 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   const int8_t* vinv = nullptr;
   if ((int)group.size() >= 32 && gD <= 4096) vinv = vinv_device(cx, gD, gP, st);
   if (!vinv) group.clear();
+  // the per-(job, prime) interpolation kernel reads its block tables
+  const uint32_t *itW = nullptr, *itQ = nullptr;
+  int itNB = 0;
+  if (group.empty() && !fused && !debug &&
+      !interp_tables_device(cx, interp_table_blocks(maxD), maxP, st, &itW, &itQ, &itNB)) {
+    itW = itQ = nullptr;
+    itNB = 0;
+  }
   const int gDp = (gD + 31) & ~31, gNp = ((int)group.size() + 31) & ~31;
   const size_t o_yp = group.empty() ? 0 : ws.take((size_t)4 * gNp * gDp * gP);
   size_t o_fbq[NRG];  // queues of blocks recomputed by the LDS kernel
@@ -658,6 +666,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
       }
       if (run && timing) DEV(hipEventRecord(ev1, st));
       if (!debug) {
+        sg.add((const void*)itW, (const void*)itQ, itNB);
         sg.add((int)group.size(), gD, gP, (const void*)vinv, o_yp, o_gj, nb_of(K_IP), maxD, use_crt, nb_of(K_CAR),
                maxLM, maxLcap, nb_of(K_MRC), mrc_lane, nb_of(K_SUM));
         if (run) {
@@ -665,7 +674,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
             launch_interp_mfma(d_jobs, (const int*)(D0 + o_gj), (int)group.size(), gD, gP, vinv,
                                (int8_t*)(D0 + o_yp), cx->tab, st);
           else if (nb_of(K_IP))
-            launch_interp(d_jobs, st_of(K_IP), nj, nb_of(K_IP), maxD, cx->tab, st);
+            launch_interp(d_jobs, st_of(K_IP), nj, nb_of(K_IP), maxD, cx->tab, itW, itQ, itNB, st);
           if (use_crt) {
             // residues to limbs in one pass over the output capacity
             if (nb_of(K_CAR)) launch_crt(d_jobs, st_of(K_CAR), nj, nb_of(K_CAR), maxP, maxLM, maxLcap, cx->tab, st);

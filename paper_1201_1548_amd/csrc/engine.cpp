@@ -188,6 +188,36 @@ bool graph_store_launch(Context* cx, uint64_t key, hipGraphExec_t exec, hipStrea
   return hipGraphLaunch(exec, st) == hipSuccess;
 }
 
+bool interp_tables_device(Context* cx, int blocks, int primes, hipStream_t st, const uint32_t** W,
+                          const uint32_t** Q, int* nb) {
+  std::lock_guard<std::mutex> lk(cx->itab_mu);
+  if (!cx->itab || cx->itab_nb < blocks || cx->itab_P < primes) {
+    const int nbn = std::max(blocks, cx->itab_nb), Pn = std::max(primes, cx->itab_P);
+    size_t qoff = 0;
+    const size_t words = interp_table_words(nbn, Pn, &qoff);
+    if (words * sizeof(uint32_t) > ((size_t)512 << 20)) return false;
+    uint32_t* d = nullptr;
+    if (hipMalloc((void**)&d, words * sizeof(uint32_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    launch_interp_tables(nbn, Pn, cx->tab, d, d + qoff, st);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+      (void)hipFree(d);
+      return false;
+    }
+    if (cx->itab) cx->itab_retired.push_back(cx->itab);
+    cx->itab = d;
+    cx->itab_nb = nbn;
+    cx->itab_P = Pn;
+    cx->itab_qoff = qoff;
+  }
+  *W = cx->itab;
+  *Q = cx->itab + cx->itab_qoff;
+  *nb = cx->itab_nb;
+  return true;
+}
+
 const int8_t* vinv_device(Context* cx, int D, int P, hipStream_t st) {
   constexpr size_t kLimit = (size_t)2 << 30;  // bytes of cached tables
   std::lock_guard<std::mutex> lk(cx->vinv_mu);

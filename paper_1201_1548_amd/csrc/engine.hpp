@@ -96,6 +96,11 @@ struct Context {
   std::map<uint64_t, hipGraphExec_t> graph_cache;       // sequence hash -> instantiated graph
   std::vector<uint64_t> graph_order;                    // insertion order (oldest first)
   int64_t graph_captures = 0, graph_replays = 0;        // under graph_mu
+  std::mutex itab_mu;                                   // interpolation block tables (interp_tables_device)
+  uint32_t* itab = nullptr;
+  int itab_nb = 0, itab_P = 0;
+  size_t itab_qoff = 0;
+  std::vector<uint32_t*> itab_retired;                  // outgrown tables (kernels in flight may still read them)
   std::mutex vinv_mu;
   std::map<std::pair<int, int>, const int8_t*> vinv;   // (D, P) -> inverse Vandermonde digit planes
   size_t vinv_total = 0;
@@ -112,6 +117,12 @@ bool graph_store_launch(Context* cx, uint64_t key, hipGraphExec_t exec, hipStrea
 // built on first use (on stream st, which is then synchronised) and kept;
 // nullptr when it would exceed the cache limit or allocation fails.
 const int8_t* vinv_device(Context* cx, int D, int P, hipStream_t st);
+// Newton-to-monomial block tables for at least `blocks` blocks and `primes`
+// primes, built on `st` and cached (grown when a call needs more); false when
+// they would exceed 512 MiB or the build failed (the kernel then computes the
+// blocks itself).  *nb receives the table's block count (its stride).
+bool interp_tables_device(Context* cx, int blocks, int primes, hipStream_t st, const uint32_t** W,
+                          const uint32_t** Q, int* nb);
 
 // Device copy of crt_tables(P), built on first use and kept (nullptr on failure).
 const uint32_t* crt_device(Context* cx, int P, int* LM);

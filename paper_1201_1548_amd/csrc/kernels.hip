@@ -803,7 +803,18 @@ __device__ __forceinline__ uint32_t reduce96(const Acc96& A, const ModP& q, uint
 // lane-parallel steps in one wave each.  One block per (job, prime).
 constexpr int KB = 32;
 
-__device__ void dev_interp(const JobDev& J, int k, TablesDev tab, uint32_t* lds) {
+// Per-prime block tables of the Newton-to-monomial step (k_interp_tables):
+// W[k][b][j][r] = [x^j] prod_{t<r} (x - 32 b - t) and Q[k][b][j] = [x^j]
+// prod_{t<32} (x - 32 b - t), plain residues, for blocks b < nb and primes
+// k < P.  With them T_b[j] = sum_{r>=j} W[k][b][j][r] c_{32 b + r} is a set of
+// independent dot products instead of a 32-step recurrence per block.
+struct InterpTab {
+  const uint32_t* W = nullptr;
+  const uint32_t* Q = nullptr;
+  int nb = 0;
+};
+
+__device__ void dev_interp(const JobDev& J, int k, TablesDev tab, uint32_t* lds, InterpTab it = InterpTab{}) {
   const int D = J.D;
   const ModP q = tab.primes[k];
   const uint32_t r3 = mmul(q.r2, q.r2, q);  // (R^2)_M = R^3 mod p
@@ -837,11 +848,41 @@ __device__ void dev_interp(const JobDev& J, int k, TablesDev tab, uint32_t* lds)
     C[kk] = reduce96(acc, q, r3);
   }
   __syncthreads();
-  // T_b and Q_b, one wave per block (lanes hold coefficients 0..KB)
+  // T_b and Q_b: from the tables when the caller has them, else one wave per
+  // block (lanes hold coefficients 0..KB)
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
-  for (int b = wave; b < nb; b += nwaves) {
+  if (it.W && nb <= it.nb) {
+    const uint32_t* W = it.W + (size_t)k * it.nb * KB * KB;
+    const uint32_t* Qt = it.Q + (size_t)k * it.nb * (KB + 1);
+    for (int o = threadIdx.x; o < nb * KB; o += blockDim.x) {
+      const int b = o / KB, j = o - b * KB, base = b * KB, len = min(KB, D - base);
+      uint32_t T = 0u;
+      if (j < len) {
+        const uint32_t* w = W + ((size_t)b * KB + j) * KB;
+        Acc96 acc;
+        int r = j;
+        for (; r + 4 <= len; r += 4) {
+          uint64_t sm = (uint64_t)w[r] * C[base + r];
+          sm += (uint64_t)w[r + 1] * C[base + r + 1];
+          sm += (uint64_t)w[r + 2] * C[base + r + 2];
+          sm += (uint64_t)w[r + 3] * C[base + r + 3];
+          acc.add(sm);
+        }
+        uint64_t sm = 0;
+        for (; r < len; ++r) sm += (uint64_t)w[r] * C[base + r];
+        acc.add(sm);
+        T = reduce96(acc, q, r3);
+      }
+      TQ[b * (2 * KB + 1) + j] = T;
+    }
+    for (int o = threadIdx.x; o < nb * (KB + 1); o += blockDim.x) {
+      const int b = o / (KB + 1), j = o - b * (KB + 1);
+      TQ[b * (2 * KB + 1) + KB + j] = Qt[(size_t)b * (KB + 1) + j];
+    }
+  }
+  for (int b = wave; b < nb && !(it.W && nb <= it.nb); b += nwaves) {
     const int base = b * KB;
     const int len = min(KB, D - base);
     uint32_t T = lane == 0 ? C[base + len - 1] : 0u;
@@ -897,10 +938,29 @@ __device__ void dev_interp(const JobDev& J, int k, TablesDev tab, uint32_t* lds)
   for (int j = threadIdx.x; j < D; j += blockDim.x) out[j] = P0[j];
 }
 
-__global__ __launch_bounds__(256) void k_interp(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
+__global__ __launch_bounds__(256) void k_interp(const JobDev* jobs, const int* starts, int nj, TablesDev tab,
+                                                InterpTab it) {
   extern __shared__ __align__(16) uint32_t lds[];
   const int job = find_job(starts, nj, blockIdx.x);
-  dev_interp(jobs[job], blockIdx.x - starts[job], tab, lds);
+  dev_interp(jobs[job], blockIdx.x - starts[job], tab, lds, it);
+}
+
+// The tables of InterpTab for blocks b < nb (grid x) and primes k < P (grid
+// y): one wave holds N_{b,r} (coefficients 0..32 on lanes 0..32) and steps
+// r = 0..31, N <- N (x - (32 b + r)).
+__global__ __launch_bounds__(64) void k_interp_tables(int nb, TablesDev tab, uint32_t* W, uint32_t* Q) {
+  const int b = blockIdx.x, k = blockIdx.y, lane = threadIdx.x;
+  const ModP q = tab.primes[k];
+  uint32_t* w = W + ((size_t)k * nb + b) * KB * KB;
+  uint32_t N = lane == 0 ? q.one : 0u;
+  for (int r = 0; r < KB; ++r) {
+    if (lane < KB) w[lane * KB + r] = from_mont(N, q);
+    const uint32_t tM = to_mont((uint32_t)(b * KB + r), q);
+    const uint32_t up = __shfl_up(N, 1);
+    const uint32_t nn = msub(lane ? up : 0u, mmul(N, tM, q), q.p);
+    N = lane <= KB ? nn : 0u;
+  }
+  if (lane <= KB) Q[((size_t)k * nb + b) * (KB + 1) + lane] = from_mont(N, q);
 }
 
 size_t interp_lds_words(int D) { return (size_t)3 * D + (size_t)((D + KB - 1) / KB) * (2 * KB + 1); }
@@ -1846,9 +1906,24 @@ void launch_eval_elim_rg(int C, const JobDev* jobs, const int* starts, int nj, i
 }
 
 void launch_interp(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_points, TablesDev tab,
-                   hipStream_t s) {
+                   const uint32_t* W, const uint32_t* Q, int tab_blocks, hipStream_t s) {
   size_t lds = interp_lds_words(max_points) * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_interp, dim3(nblocks), dim3(256), lds, s, jobs, starts, nj, tab);
+  InterpTab it;
+  it.W = W;
+  it.Q = Q;
+  it.nb = tab_blocks;
+  hipLaunchKernelGGL(k_interp, dim3(nblocks), dim3(256), lds, s, jobs, starts, nj, tab, it);
+}
+
+int interp_table_blocks(int max_points) { return (max_points + KB - 1) / KB; }
+
+size_t interp_table_words(int blocks, int primes, size_t* q_offset) {
+  *q_offset = (size_t)primes * blocks * KB * KB;
+  return *q_offset + (size_t)primes * blocks * (KB + 1);
+}
+
+void launch_interp_tables(int blocks, int primes, TablesDev tab, uint32_t* W, uint32_t* Q, hipStream_t s) {
+  hipLaunchKernelGGL(k_interp_tables, dim3(blocks, primes), dim3(64), 0, s, blocks, tab, W, Q);
 }
 
 size_t vinv_bytes(int Dp, int P) { return (size_t)4 * Dp * Dp * P; }

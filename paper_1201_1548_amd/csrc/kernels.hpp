@@ -47,8 +47,16 @@ void launch_eval_elim(const JobDev* jobs, const int* starts, int nj, int nblocks
 int eval_elim_rg_capacity(int m, int n);
 void launch_eval_elim_rg(int C, const JobDev* jobs, const int* starts, int nj, int nblocks, int max_deg,
                          int max_words, int* fb_count, int* fb_queue, TablesDev tab, hipStream_t s);
+// Interpolation of one (job, prime) per block.  W, Q: the block tables of
+// launch_interp_tables for tab_blocks blocks (null: computed in the kernel).
 void launch_interp(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_points, TablesDev tab,
-                   hipStream_t s);
+                   const uint32_t* W, const uint32_t* Q, int tab_blocks, hipStream_t s);
+// Newton-to-monomial block tables for `blocks` 32-node blocks (enough for
+// max_points nodes: interp_table_blocks) and the first `primes` primes:
+// interp_table_words words, W at 0 and Q at *q_offset.
+int interp_table_blocks(int max_points);
+size_t interp_table_words(int blocks, int primes, size_t* q_offset);
+void launch_interp_tables(int blocks, int primes, TablesDev tab, uint32_t* W, uint32_t* Q, hipStream_t s);
 size_t interp_lds_words(int D);
 // Interpolation of N jobs sharing D and P (job indices gj[0..N)) as int8
 // matrix-core products with V^{-1}: Ap = vinv_bytes(Dp, P) bytes built by

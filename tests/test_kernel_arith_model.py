@@ -463,3 +463,52 @@ def test_explicit_crt_with_range_carries():
         for R in [0, 1, -1, B, -B] + [rng.randint(-B, B) for _ in range(20)]:
             for width in (12, 16):
                 assert crt_model_ranges([R % p for p in ps], ps, R=width) == R, (P, R, width)
+
+
+def test_newton_block_tables_expand_the_newton_form():
+    # The interpolation kernel's block tables: W_b[j][r] = [x^j] prod_{t<r}
+    # (x - 32 b - t) and Q_b = prod_{t<32} (x - 32 b - t).  With T_b[j] =
+    # sum_{r>=j} W_b[j][r] c_{32 b + r}, Horner over blocks (P <- P Q_b + T_b
+    # from the top block down) must give the monomial coefficients of the
+    # Newton form sum_k c_k prod_{t<k} (x - t) on the nodes 0, 1, 2, ...
+    p = PRIMES[3]
+    KB = 32
+    rng = random.Random(77)
+
+    def mul_lin(poly, t):  # poly * (x - t)
+        out = [0] * (len(poly) + 1)
+        for j, a in enumerate(poly):
+            out[j + 1] = (out[j + 1] + a) % p
+            out[j] = (out[j] - t * a) % p
+        return out
+
+    for D in (1, 5, 32, 33, 70, 97):
+        c = [rng.randrange(p) for _ in range(D)]
+        # direct Newton expansion
+        ref, basis = [0] * D, [1]
+        for k in range(D):
+            for j, a in enumerate(basis):
+                ref[j] = (ref[j] + c[k] * a) % p
+            basis = mul_lin(basis, k)
+        nb = -(-D // KB)
+        T, Q = [], []
+        for b in range(nb):
+            N, W = [1], [[0] * KB for _ in range(KB)]
+            for r in range(KB):
+                for j, a in enumerate(N):
+                    if j < KB:
+                        W[j][r] = a
+                N = mul_lin(N, KB * b + r)
+            Q.append(N)
+            length = min(KB, D - KB * b)
+            T.append([sum(W[j][r] * c[KB * b + r] for r in range(j, length)) % p if j < length else 0
+                      for j in range(KB)])
+        P = T[nb - 1][:]
+        for b in range(nb - 2, -1, -1):
+            prod = [0] * (len(P) + KB)
+            for i, a in enumerate(P):
+                for t, qv in enumerate(Q[b]):
+                    prod[i + t] = (prod[i + t] + a * qv) % p
+            P = [(prod[j] + (T[b][j] if j < KB else 0)) % p for j in range(len(prod))]
+        P = (P + [0] * D)[:D]
+        assert P == ref, D
