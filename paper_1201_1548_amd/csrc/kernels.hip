@@ -745,8 +745,8 @@ __device__ __forceinline__ void eval_elim_rg_block(const JobDev* jobs, const int
   if (__ballot(!ok) != 0ull && threadIdx.x == 0) fb_queue[atomicAdd(fb_count, 1)] = b;
 }
 
-// C = 24 is held to RG24_WAVES waves per SIMD (its few spills sit outside
-// the Euclid loop); C = 32 takes the registers it needs.
+// C = 24 is held to RG24_WAVES waves per SIMD (76 VGPRs, no spills); C = 32
+// runs at RG32_WAVES (102 VGPRs; at 5 waves it spills inside the chain).
 #ifndef RG24_WAVES
 #define RG24_WAVES 6
 #endif
@@ -756,8 +756,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RG24_WAVES, 
   eval_elim_rg_block<24>(jobs, starts, nj, tab, fb_count, fb_queue, lds);
 }
 
-__global__ __launch_bounds__(64) void k_eval_elim_rg32(const JobDev* jobs, const int* starts, int nj, TablesDev tab,
-                                                       int* fb_count, int* fb_queue) {
+#ifndef RG32_WAVES
+#define RG32_WAVES 4
+#endif
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RG32_WAVES, 8))) void k_eval_elim_rg32(
+    const JobDev* jobs, const int* starts, int nj, TablesDev tab, int* fb_count, int* fb_queue) {
   extern __shared__ __align__(16) uint32_t lds[];
   eval_elim_rg_block<32>(jobs, starts, nj, tab, fb_count, fb_queue, lds);
 }
