@@ -336,6 +336,21 @@ __device__ uint32_t uni_resultant(uint32_t* A, uint32_t* B, int m, int n, const 
   return neg ? mneg(r, q.p) : r;
 }
 
+// a b + c with 32-bit a, b (one v_mad_u64_u32).  Inline assembly keeps a as a
+// single 32-bit register where the compiler would keep a zero-extended pair.
+// SB: b is wave-uniform and held in a scalar register (the residues read
+// through the scalar cache).
+template <bool SB = false>
+__device__ __forceinline__ uint64_t mad_u64_u32(uint32_t a, uint32_t b, uint64_t c) {
+  uint64_t d;
+  uint64_t carry;
+  if constexpr (SB)
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(d), "=s"(carry) : "v"(a), "s"(b), "v"(c));
+  else
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(d), "=s"(carry) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
 // Exact sums of products of residues in 96 bits: 64-bit partial sums (up to
 // eight products of residues, below 8 p^2 < 2^64) added with a carry word.
 struct Acc96 {
@@ -391,31 +406,26 @@ __device__ __forceinline__ uint32_t eval_row(C* c, int d, const uint32_t (&pw)[N
     u32x4 v[NPW / 4];
 #pragma unroll
     for (int g = 0; g < NPW / 4; ++g) v[g] = cc[g];
-    // The powers pass through an empty asm here so that their widening to
-    // 64 bits stays at the products (where it is free in v_mad_u64_u32)
-    // instead of being hoisted out of the row loop as zero-extended register
-    // pairs, which doubled their register count.
-    uint32_t pq[NPW];
-#pragma unroll
-    for (int i = 0; i < NPW; ++i) {
-      pq[i] = pw[i];
-      asm volatile("" : "+v"(pq[i]));
-    }
+    // The products are v_mad_u64_u32 with the 32-bit power as an operand.
+    // Written in C, (uint64_t) pw[i] * c lets the compiler hoist the
+    // zero-extended powers out of the row loop as 64-bit register pairs,
+    // which doubles their register count.
     Acc96 S;
 #pragma unroll
     for (int h = 0; h < NPW / 8; ++h) {
       if (2 * h < ng) {
+        constexpr bool SB = std::is_same<C, cu32>::value;
         const u32x4 x = v[2 * h];
-        uint64_t t = (uint64_t)x.x * pq[8 * h];
-        t += (uint64_t)x.y * pq[8 * h + 1];
-        t += (uint64_t)x.z * pq[8 * h + 2];
-        t += (uint64_t)x.w * pq[8 * h + 3];
+        uint64_t t = (uint64_t)x.x * pw[8 * h];
+        t = mad_u64_u32<SB>(pw[8 * h + 1], x.y, t);
+        t = mad_u64_u32<SB>(pw[8 * h + 2], x.z, t);
+        t = mad_u64_u32<SB>(pw[8 * h + 3], x.w, t);
         if (2 * h + 1 < ng) {
           const u32x4 y = v[2 * h + 1];
-          t += (uint64_t)y.x * pq[8 * h + 4];
-          t += (uint64_t)y.y * pq[8 * h + 5];
-          t += (uint64_t)y.z * pq[8 * h + 6];
-          t += (uint64_t)y.w * pq[8 * h + 7];
+          t = mad_u64_u32<SB>(pw[8 * h + 4], y.x, t);
+          t = mad_u64_u32<SB>(pw[8 * h + 5], y.y, t);
+          t = mad_u64_u32<SB>(pw[8 * h + 6], y.z, t);
+          t = mad_u64_u32<SB>(pw[8 * h + 7], y.w, t);
         }
         S.add(t);
       }
