@@ -443,3 +443,26 @@ def test_plan_reuse_is_checked_on_the_device():
     b.run()
     assert b.results()[0] == got[0]
     br.set_plan_cache(True)
+
+
+@pytest.mark.parametrize("mn", [(23, 9), (9, 23), (24, 4), (31, 31), (31, 2), (32, 6), (5, 0), (0, 7), (1, 1)])
+def test_evaluation_kernel_capacity_boundaries(mn):
+    # jobs on both sides of each routing boundary (capacity 24, capacity 32,
+    # LDS kernel, min(m, n) = 0): register and LDS kernels, batched and single
+    # calls agree, and the result matches the oracle's determinant at nodes
+    m, n = mn
+    F, G = synth.random_rect(900 + 37 * m + n, m, 2, n, 1, 20)
+    jobs = [("res", F, G, "y")] * 2 + [("res",) + synth.config1_pair(1) + ("y",)]
+    say("capacity boundary", m, n)
+    try:
+        br.set_eval_kernel("lds")
+        ref, st_ref = br.resultant_batch(jobs)
+        br.set_eval_kernel("auto")
+        got, st_got = br.resultant_batch(jobs)
+    finally:
+        br.set_eval_kernel("auto")
+    assert st_got == st_ref == [0, 0, 0]
+    assert got == ref
+    assert got[0] == got[1] == br.resultant(F, G)
+    for a in (0, 1, -3, 7):
+        assert zx.evaluate(got[0], a) == resultant_at(F, G, a), a
