@@ -143,17 +143,16 @@ int bires_resultant_batch(int n, const bires_bipoly *f, const bires_bipoly *g,
                           bires_upoly *out, int32_t *status, int mem, void *stream);
 
 /* Asynchronous form of bires_resultant_batch (same arguments, plus *ticket).
- * The batch is queued to one of two library worker threads, each with its own
- * stream, and the call returns at once.  The batch starts on the device after
- * the work queued on `stream` before the call (an event recorded there), so
- * inputs produced on that stream are complete; with stream = NULL it starts
- * at once (the caller guarantees complete inputs; an event on the legacy
- * default stream would also wait for the batches in flight, so pass a
- * non-blocking stream to order after).  The descriptor, status and
- * output arrays and the input and output buffers must stay valid, and the
- * inputs unchanged, until bires_batch_wait returns for the ticket.  With two
- * batches in flight, one batch's row scan and planning overlap the other's
- * kernels.  Batches in flight must not share output buffers. */
+ * The calling thread plans the batch and queues its device work on `stream`
+ * (the library stream when NULL), after the work queued there before, and
+ * returns without waiting for the device; with device-memory inputs whose
+ * plans are reused (bires_set_plan_cache) nothing on the host waits at all.
+ * An error found before any device work was queued is returned here and no
+ * ticket is issued.  The descriptor, status and output arrays and the input
+ * and output buffers must stay valid, and the inputs unchanged, until
+ * bires_batch_wait returns for the ticket.  While one batch runs on the
+ * device, the caller can plan and queue the next, so the device runs them
+ * back to back.  Batches in flight must not share output buffers. */
 int bires_resultant_batch_async(int n, const bires_bipoly *f, const bires_bipoly *g, const int32_t *kind,
                                 const int32_t *var, bires_upoly *out, int32_t *status, int mem, void *stream,
                                 uint64_t *ticket);
@@ -229,9 +228,10 @@ int bires_set_schedule(int schedule);
 int bires_set_eval_kernel(int kernel);
 
 /* Plan reuse for batched calls with device-memory inputs (default on): when
- * a call has the same descriptors as the previous one (input and output
- * pointers, extents, capacities, kinds, variables) and the last planned calls
- * saw the same row statistics, it keeps their plans and does not wait for its
+ * every job of a call is valid and has the same extents, output capacities,
+ * kind and variable as in the previous call (buffer addresses may differ),
+ * and the last planned calls saw the same row statistics, it keeps their
+ * plans and does not wait for its
  * own row scan before launching; a device kernel then compares the scan's
  * output with the statistics those plans came from, word for word, and on any
  * difference the call is rerun with fresh plans before it returns.  Equal

@@ -487,9 +487,11 @@ class DeviceBatch:
         return code
 
     def run_async(self, stream=None):
-        """Queues the batch (bires_resultant_batch_async) and returns at once;
-        wait() collects it.  With stream (a torch stream) the batch starts
-        after the work queued there; without one the inputs must be complete.
+        """Plans the batch and queues its device work (bires_resultant_batch_async),
+        returning without waiting for the device; wait() collects it.  With
+        stream (a torch stream) the work is queued there, after what is queued
+        before; without one it goes to the library stream and the inputs must
+        be complete.
         One call per DeviceBatch may be in flight: its descriptors and output
         tensors belong to that call until wait()."""
         if getattr(self, "_ticket", None) is not None:

@@ -62,12 +62,20 @@ struct Work {
   size_t o_out = 0, o_hout = 0, o_rowdeg = 0;
 };
 
-// RAII holder of pool blocks.
+// Holder of one pool block (given back when the holder goes).
 struct Held {
-  Pool* pool;
+  Pool* pool = nullptr;
   void* p = nullptr;
-  Held(Pool* pl, size_t n) : pool(pl) { p = n ? pl->alloc(n) : nullptr; }
-  ~Held() { pool->release(p); }
+  Held() = default;
+  Held(const Held&) = delete;
+  Held& operator=(const Held&) = delete;
+  void take(Pool* pl, size_t n) {
+    pool = pl;
+    p = n ? pl->alloc(n) : nullptr;
+  }
+  ~Held() {
+    if (pool) pool->release(p);
+  }
   uint8_t* b() const { return (uint8_t*)p; }
 };
 
@@ -76,9 +84,6 @@ struct Held {
 static SpecKey key_of(const JobIn& jb) {
   SpecKey k;
   std::memset(&k, 0, sizeof k);
-  k.fc = jb.f.c;
-  k.gc = jb.g.c;
-  k.oc = jb.out ? jb.out->c : nullptr;
   k.f[0] = jb.f.deg_x, k.f[1] = jb.f.deg_y, k.f[2] = jb.f.limbs;
   k.g[0] = jb.g.deg_x, k.g[1] = jb.g.deg_y, k.g[2] = jb.g.limbs;
   k.kind = jb.kind;
@@ -147,6 +152,9 @@ struct HostClock {
     us[phase] += std::chrono::duration<double, std::micro>(t - last).count();
     last = t;
   }
+  void resume() {  // not counting the time since the last mark
+    if (on) last = C::now();
+  }
   void commit(Context* cx) {
     if (!on) return;
     std::lock_guard<std::mutex> lk(cx->timing_mu);
@@ -154,15 +162,79 @@ struct HostClock {
     cx->host_calls += 1;
   }
 };
+
+hipEvent_t take_event(Context* cx) {
+  {
+    std::lock_guard<std::mutex> lk(cx->ev_mu);
+    if (!cx->ev_free.empty()) {
+      hipEvent_t e = cx->ev_free.back();
+      cx->ev_free.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  return e;
+}
+
+void give_event(Context* cx, hipEvent_t e) {
+  if (!e) return;
+  std::lock_guard<std::mutex> lk(cx->ev_mu);
+  cx->ev_free.push_back(e);
+}
 }  // namespace
 
-int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t st, int32_t* status,
-              std::vector<uint32_t>* debug_values, std::vector<int>* debug_shape) {
+// State of a launched call until run_batch_finish: the jobs, the per-job
+// work, the pool blocks the device work reads and writes, and the event that
+// marks its end.
+struct PendingBatch {
+  Context* cx = nullptr;
+  std::vector<JobIn> jobs;
+  int mem = BIRES_MEM_DEVICE;
+  hipStream_t st = nullptr;
+  int32_t* status = nullptr;
+  bool lock_stream = false;  // a rerun takes cx->stream_mu (calls on the library stream)
+  bool in_flight = true;     // device work may still use the blocks
+  HostClock hc;
+  int nj = 0;
+  std::vector<Work> w;
+  std::vector<int32_t> rowdeg;  // per active job: the m + 1 row degrees of f, then the n + 1 of g
+  std::vector<int> rd_off;
+  bool spec = false, spec_ok = false, fused = false, timing = false;
+  std::shared_ptr<DevImage> image;  // statistics the reused plans were made from
+  size_t o_scan0 = 0, scan_words = 0;
+  int32_t* h_flags = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, done = nullptr;
+  Held d_in, h_in, d_ws, h_meta, h_out;
+  explicit PendingBatch(bool clock) : hc(clock) {}
+};
+
+void PendingDeleter::operator()(PendingBatch* p) const {
+  if (!p) return;
+  if (p->in_flight && p->st) (void)hipStreamSynchronize(p->st);  // an error after queued work
+  if (p->ev0) (void)hipEventDestroy(p->ev0);
+  if (p->ev1) (void)hipEventDestroy(p->ev1);
+  give_event(p->cx, p->done);
+  delete p;
+}
+
+namespace {
+
+int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStream_t st, int32_t* status,
+                std::vector<uint32_t>* debug_values, std::vector<int>* debug_shape, PendingPtr* pending) {
   if (mem != BIRES_MEM_HOST && mem != BIRES_MEM_DEVICE) return BIRES_EINVAL;
-  HostClock hc(cx->timing && debug_values == nullptr);
-  const int nj = (int)jobs.size();
+  PendingPtr P(new PendingBatch(cx->timing && debug_values == nullptr));
+  P->cx = cx;
+  P->jobs = jobs_in;
+  P->mem = mem;
+  P->st = st;
+  P->status = status;
+  const std::vector<JobIn>& jobs = P->jobs;
+  HostClock& hc = P->hc;
+  const int nj = P->nj = (int)jobs.size();
   const bool debug = debug_values != nullptr;
-  std::vector<Work> w(nj);
+  std::vector<Work>& w = P->w;
+  w.resize(nj);
   for (int i = 0; i < nj; ++i) {
     const JobIn& jb = jobs[i];
     w[i].status = validate(jb, !debug);
@@ -205,19 +277,36 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   const size_t o_tasks = in.take(sizeof(ScanTask) * tasks.size());
   const size_t o_smap = in.take(sizeof(int4) * smap.size());
   const size_t scan_words = (o_scan_end - o_scan0) / 4;
-  Held d_in(&cx->dev, in.bytes), h_in(&cx->host, in.bytes);
+  P->o_scan0 = o_scan0;
+  P->scan_words = scan_words;
+  Held& d_in = P->d_in;
+  Held& h_in = P->h_in;
+  d_in.take(&cx->dev, in.bytes);
+  h_in.take(&cx->host, in.bytes);
   if (in.bytes && (!d_in.p || !h_in.p)) return BIRES_ENOMEM;
   // Plans reused from the previous call when it had the same descriptors and
   // the statistics have repeated; the scan still runs and a device check of
   // its output against the statistics of those plans decides, at the end,
   // whether the call stands or is rerun with fresh plans.
   SpecCache& sc = cx->spec;
-  std::unique_lock<std::mutex> spec_lk(sc.mu, std::defer_lock);
-  const bool spec_ok = cx->plan_cache && mem == BIRES_MEM_DEVICE && !debug && scan_words > 0 && spec_lk.try_lock();
-  bool spec = false;
-  if (spec_ok && sc.valid && sc.conf >= 1 && sc.image.size() == scan_words && sc.keys.size() == (size_t)nj) {
-    spec = true;
-    for (int i = 0; i < nj && spec; ++i) spec = same_key(sc.keys[i], jobs[i]);
+  const bool spec_ok = P->spec_ok = cx->plan_cache && mem == BIRES_MEM_DEVICE && !debug && scan_words > 0;
+  bool& spec = P->spec;
+  std::vector<int32_t>& rowdeg = P->rowdeg;
+  std::vector<int>& rd_off = P->rd_off;
+  rd_off.assign(nj, 0);
+  std::vector<SpecJob> reused;
+  if (spec_ok) {
+    std::lock_guard<std::mutex> lk(sc.mu);
+    if (sc.valid && sc.conf >= 1 && sc.dimg && sc.image.size() == scan_words && sc.keys.size() == (size_t)nj) {
+      spec = true;
+      // cached plans come from calls where every job was valid
+      for (int i = 0; i < nj && spec; ++i) spec = w[i].status == BIRES_OK && same_key(sc.keys[i], jobs[i]);
+    }
+    if (spec) {
+      reused = sc.plans;
+      rowdeg = sc.rowdeg;
+      P->image = sc.dimg;
+    }
   }
 
   if (mem == BIRES_MEM_HOST) {
@@ -277,13 +366,10 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   }
 
   // ---------------- plans and output capacities
-  std::vector<int32_t> rowdeg;  // per active job: the m + 1 row degrees of f, then the n + 1 of g
-  std::vector<int> rd_off(nj, 0);
   if (spec) {
-    rowdeg = sc.rowdeg;
     for (int i = 0; i < nj; ++i) {
       Work& x = w[i];
-      const SpecJob& c = sc.plans[i];
+      const SpecJob& c = reused[i];
       x.status = c.status;
       x.active = c.active;
       x.pl = c.pl;
@@ -421,7 +507,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     std::lock_guard<std::mutex> lk(cx->tune_mu);
     cx->last_key = key;
   }
-  const bool fused = !debug && instances > 0 && schedule_for(cx, key) == BIRES_SCHEDULE_FUSED;
+  const bool fused = P->fused = !debug && instances > 0 && schedule_for(cx, key) == BIRES_SCHEDULE_FUSED;
   // staged schedule: explicit CRT straight to limbs when the prime counts allow
   std::vector<std::pair<const uint32_t*, int>> crt(nj, {nullptr, 0});
   bool use_crt = !debug && !fused && crt_ok(maxP);
@@ -504,13 +590,18 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   const size_t o_ctroff = ws.take(sizeof(int) * (nj + 1));
   const size_t o_ctr = ws.take(sizeof(int) * ((size_t)ctr_off[nj] + 2));  // counters, head, err
   const size_t meta_end = ws.bytes;
-  Held d_ws(&cx->dev, ws.bytes), h_meta(&cx->host, meta_end - meta_begin), h_out(&cx->host, hout.bytes);
+  Held& d_ws = P->d_ws;
+  Held& h_meta = P->h_meta;
+  Held& h_out = P->h_out;
+  d_ws.take(&cx->dev, ws.bytes);
+  h_meta.take(&cx->host, meta_end - meta_begin);
+  h_out.take(&cx->host, hout.bytes);
   if ((ws.bytes && !d_ws.p) || (meta_end > meta_begin && !h_meta.p) || (hout.bytes && !h_out.p))
     return BIRES_ENOMEM;
   uint8_t* const D0 = d_ws.b();
   uint8_t* const H0 = h_meta.b() - meta_begin;  // H0 + offset addresses the metadata image
 
-  int32_t* h_flags = (int32_t*)(H0 + o_flags);
+  int32_t* h_flags = P->h_flags = (int32_t*)(H0 + o_flags);
   std::memset(H0 + o_fbc, 0, sizeof(int) * NRG);
   JobDev* h_jobs = (JobDev*)(H0 + o_jobs);
   for (int i = 0; i < nj; ++i) {
@@ -623,12 +714,13 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     if (total && f_blocks <= 0) return BIRES_EDEVICE;
   }
   const bool use_graph = cx->graphs && !debug;
-  const bool timing = cx->timing && nb_ee > 0 && !use_graph;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  const bool timing = P->timing = cx->timing && nb_ee > 0 && !use_graph;
   if (timing) {
-    DEV(hipEventCreate(&ev0));
-    DEV(hipEventCreate(&ev1));
+    DEV(hipEventCreate(&P->ev0));
+    DEV(hipEventCreate(&P->ev1));
   }
+  const hipEvent_t ev0 = P->ev0, ev1 = P->ev1;
+  const int32_t* const d_image = spec ? P->image->d : nullptr;
   const int32_t* spec_got = nullptr;
   if (spec) {
     uint8_t* hmap = nullptr;
@@ -640,9 +732,9 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     if (run && meta_end > meta_begin)
       DEV(hipMemcpyAsync(D0 + meta_begin, h_meta.p, meta_end - meta_begin, hipMemcpyHostToDevice, st));
     if (spec) {
-      sg.add((const void*)spec_got, (const void*)sc.d_image, scan_words);
+      sg.add((const void*)spec_got, (const void*)d_image, scan_words);
       if (run)
-        launch_stats_check(spec_got, sc.d_image, (long long)scan_words, (int*)(D0 + o_flags) + 2 * nj + 1, st);
+        launch_stats_check(spec_got, d_image, (long long)scan_words, (int*)(D0 + o_flags) + 2 * nj + 1, st);
     }
     if (fused) {
       sg.add(F, f_lds, f_blocks);
@@ -743,34 +835,76 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
     debug_shape->assign({x.pl.P, x.pl.D});
     DEV(hipMemcpyAsync(debug_values->data(), D0 + x.o_vals, debug_values->size() * 4, hipMemcpyDeviceToHost, st));
     DEV(hipStreamSynchronize(st));
+    P->in_flight = false;
     return BIRES_OK;
   }
+  P->done = take_event(cx);
+  if (!P->done) return BIRES_EDEVICE;
+  DEV(hipEventRecord(P->done, st));
   hc.mark(4);
-  DEV(hipStreamSynchronize(st));
-  if (timing) {
+  *pending = std::move(P);
+  return BIRES_OK;
+}
+
+}  // namespace
+
+int run_batch_launch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t st, int32_t* status,
+                     PendingPtr* pending) {
+  pending->reset();
+  return launch_impl(cx, jobs, mem, st, status, nullptr, nullptr, pending);
+}
+
+void set_pending_stream_lock(PendingBatch* pending) {
+  if (pending) pending->lock_stream = true;
+}
+
+int run_batch_finish(PendingPtr P) {
+  if (!P) return BIRES_EINVAL;
+  Context* cx = P->cx;
+  const std::vector<JobIn>& jobs = P->jobs;
+  const int mem = P->mem;
+  const int nj = P->nj;
+  std::vector<Work>& w = P->w;
+  HostClock& hc = P->hc;
+  const int32_t* h_flags = P->h_flags;
+  const size_t scan_words = P->scan_words;
+  SpecCache& sc = cx->spec;
+  hc.resume();
+  DEV(hipEventSynchronize(P->done));
+  P->in_flight = false;
+  if (P->timing) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess) {
+    if (hipEventElapsedTime(&ms, P->ev0, P->ev1) == hipSuccess) {
       std::lock_guard<std::mutex> lk(cx->timing_mu);
       cx->kernel_ms += ms;
       cx->kernel_launches += 1;
     }
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
   }
-  if (spec) {
+  if (P->spec) {
     if (h_flags[2 * nj + 1]) {
       // the statistics changed: drop the cache and rerun with fresh plans
-      sc.valid = false;
-      sc.conf = 0;
-      sc.misses++;
-      spec_lk.unlock();
-      return run_batch(cx, jobs, mem, st, status);
+      {
+        std::lock_guard<std::mutex> lk(sc.mu);
+        sc.valid = false;
+        sc.conf = 0;
+        sc.misses++;
+      }
+      const std::vector<JobIn> again = std::move(P->jobs);
+      hipStream_t st = P->st;
+      int32_t* status = P->status;
+      const bool lock_stream = P->lock_stream;
+      P.reset();
+      if (!lock_stream) return run_batch(cx, again, mem, st, status);
+      std::lock_guard<std::mutex> lk(cx->stream_mu);
+      return run_batch(cx, again, mem, st, status);
     }
+    std::lock_guard<std::mutex> lk(sc.mu);
     sc.hits++;
-  } else if (spec_ok) {
+  } else if (P->spec_ok) {
     int bad = 0;
     for (int i = 0; i < nj; ++i) bad |= w[i].status;
-    const int32_t* img = (const int32_t*)(h_in.b() + o_scan0);
+    const int32_t* img = (const int32_t*)(P->h_in.b() + P->o_scan0);
+    std::lock_guard<std::mutex> lk(sc.mu);
     bool same = sc.valid && sc.image.size() == scan_words && sc.keys.size() == (size_t)nj &&
                 std::memcmp(sc.image.data(), img, scan_words * 4) == 0;
     for (int i = 0; i < nj && same; ++i) same = same_key(sc.keys[i], jobs[i]);
@@ -786,25 +920,23 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
         sc.plans.resize(nj);
         for (int i = 0; i < nj; ++i) {
           const Work& x = w[i];
-          sc.plans[i] = SpecJob{x.status, x.active, x.pl, x.Lout, x.degcap, x.Tf, x.Tg, x.ldg, x.Lacc, rd_off[i]};
+          sc.plans[i] =
+              SpecJob{x.status, x.active, x.pl, x.Lout, x.degcap, x.Tf, x.Tg, x.ldg, x.Lacc, P->rd_off[i]};
         }
-        sc.rowdeg = rowdeg;
-        bool up = true;
-        if (sc.d_cap < scan_words) {
-          if (sc.d_image) (void)hipFree(sc.d_image);
-          sc.d_image = nullptr;
-          sc.d_cap = 0;
-          up = hipMalloc((void**)&sc.d_image, scan_words * 4) == hipSuccess;
-          if (up) sc.d_cap = scan_words;
-        }
-        up = up && hipMemcpy(sc.d_image, img, scan_words * 4, hipMemcpyHostToDevice) == hipSuccess;
+        sc.rowdeg = P->rowdeg;
+        // a fresh device copy: calls in flight keep the one they check against
+        std::shared_ptr<DevImage> di = std::make_shared<DevImage>();
+        bool up = hipMalloc((void**)&di->d, scan_words * 4) == hipSuccess;
+        if (!up) di->d = nullptr;
+        up = up && hipMemcpy(di->d, img, scan_words * 4, hipMemcpyHostToDevice) == hipSuccess;
         if (!up) (void)hipGetLastError();
+        sc.dimg = up ? di : nullptr;
         sc.valid = up;
         if (!up) sc.conf = 0;
       }
     }
   }
-  const int fused_err = fused ? h_flags[2 * nj] : 0;
+  const int fused_err = P->fused ? h_flags[2 * nj] : 0;
   int first_err = BIRES_OK;
   for (int i = 0; i < nj; ++i) {
     Work& x = w[i];
@@ -816,7 +948,7 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
           x.status = BIRES_ECHECK;
         } else {
           if (mem == BIRES_MEM_HOST)
-            std::memcpy(o->c, h_out.b() + x.o_hout, (size_t)(x.degcap + 1) * x.Lout * 4);
+            std::memcpy(o->c, P->h_out.b() + x.o_hout, (size_t)(x.degcap + 1) * x.Lout * 4);
           o->degree = h_flags[2 * i];
         }
       } else {
@@ -827,12 +959,20 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
         o->degree = x.pl.kind_special == 2 ? 0 : -1;
       }
     }
-    if (status) status[i] = x.status;
+    if (P->status) P->status[i] = x.status;
     if (x.status && first_err == BIRES_OK) first_err = x.status;
   }
   hc.mark(5);
   hc.commit(cx);
   return first_err;
+}
+
+int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t st, int32_t* status,
+              std::vector<uint32_t>* debug_values, std::vector<int>* debug_shape) {
+  PendingPtr p;
+  const int e = launch_impl(cx, jobs, mem, st, status, debug_values, debug_shape, &p);
+  if (e || !p) return e;
+  return run_batch_finish(std::move(p));
 }
 
 }  // namespace bires

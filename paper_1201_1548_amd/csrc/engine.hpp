@@ -5,6 +5,7 @@
 
 #include <atomic>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -37,9 +38,9 @@ class Pool {
 };
 
 // Plans of the last batched call with device-memory inputs, reused by the
-// next call with the same descriptors while the row statistics repeat; the
-// reusing call checks the fresh statistics against `image` on the device and
-// is rerun with fresh plans when they differ.
+// next call with the same extents and capacities while the row statistics
+// repeat; the reusing call checks the fresh statistics against `image` on the
+// device and is rerun with fresh plans when they differ.
 struct SpecJob {
   int status = 0;
   bool active = false;
@@ -47,11 +48,16 @@ struct SpecJob {
   int Lout = 1, degcap = 0, Tf = 0, Tg = 0, ldg = 0, Lacc = 1;
   int rd_off = 0;  // into rowdeg: m + 1 + n + 1 row degrees when active
 };
-struct SpecKey {  // the fields of a JobIn that planning reads
-  const void* fc;
-  const void* gc;
-  const void* oc;
+struct SpecKey {  // the fields of a JobIn that planning reads (not its buffer addresses)
   int32_t f[3], g[3], kind, var, odeg, olimbs;
+};
+// A device copy of a statistics image; calls in flight hold a reference, so
+// a newer image never overwrites one a pending check still reads.
+struct DevImage {
+  int32_t* d = nullptr;
+  ~DevImage() {
+    if (d) (void)hipFree(d);
+  }
 };
 struct SpecCache {
   std::mutex mu;
@@ -59,8 +65,7 @@ struct SpecCache {
   int conf = 0;  // consecutive planned calls whose statistics equalled the previous ones
   std::vector<SpecKey> keys;
   std::vector<int32_t> image;  // the scan's output words
-  int32_t* d_image = nullptr;  // device copy of image
-  size_t d_cap = 0;
+  std::shared_ptr<DevImage> dimg;  // device copy of image
   std::vector<SpecJob> plans;
   std::vector<int32_t> rowdeg;
   int64_t hits = 0, misses = 0;
@@ -101,6 +106,8 @@ struct Context {
   int itab_nb = 0, itab_P = 0;
   size_t itab_qoff = 0;
   std::vector<uint32_t*> itab_retired;                  // outgrown tables (kernels in flight may still read them)
+  std::mutex ev_mu;
+  std::vector<hipEvent_t> ev_free;                      // completion events of batched calls, reused
   std::mutex vinv_mu;
   std::map<std::pair<int, int>, const int8_t*> vinv;   // (D, P) -> inverse Vandermonde digit planes
   size_t vinv_total = 0;
@@ -151,6 +158,22 @@ struct JobIn {
 // status[i] receives each job's code; the return value is the first error.
 int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t stream, int32_t* status,
               std::vector<uint32_t>* debug_values = nullptr, std::vector<int>* debug_shape = nullptr);
+
+// The same in two halves: run_batch_launch issues the device work and returns
+// (its state in *pending, or an error before anything was queued);
+// run_batch_finish waits for that work only (an event, not the stream) and
+// completes the call.  Between the two, the caller's buffers belong to the call.
+struct PendingBatch;
+struct PendingDeleter {
+  void operator()(PendingBatch* p) const;
+};
+using PendingPtr = std::unique_ptr<PendingBatch, PendingDeleter>;
+int run_batch_launch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t stream, int32_t* status,
+                     PendingPtr* pending);
+int run_batch_finish(PendingPtr pending);
+// Marks a launched call as running on the library stream: a rerun inside
+// run_batch_finish then holds cx->stream_mu.
+void set_pending_stream_lock(PendingBatch* pending);
 
 // Plan of one host-memory job, and output sizes from the extents only (host-only).
 int bounds_job(const JobIn& job, int32_t* max_degree, int32_t* max_limbs);

@@ -358,7 +358,7 @@ def test_register_and_lds_evaluation_kernels_agree():
 
 
 def test_async_batches_overlap_and_match():
-    # two device batches alternately in flight through the library workers;
+    # two device batches alternately in flight (planned and queued by the caller);
     # every result equals the synchronous call's, also with the caller's
     # stream still busy writing the inputs when the batch is queued
     import torch
@@ -443,6 +443,52 @@ def test_plan_reuse_is_checked_on_the_device():
     b.run()
     assert b.results()[0] == got[0]
     br.set_plan_cache(True)
+
+
+def test_plan_reuse_with_alternating_batches_in_flight():
+    # two batches of the same shapes in separate buffers, two calls in flight:
+    # both reuse the plans (addresses are not part of the key); a statistics
+    # change in one of them while the other is in flight is caught and rerun
+    import torch
+    pairs = [synth.config1_pair(i % 4) for i in range(12)] + [synth.config2_pair(5)]
+    jobs = [("res", F, G, "y") for F, G in pairs]
+    say("alternating plan reuse", len(jobs))
+    br.set_plan_cache(True)
+    a, b = br.DeviceBatch(jobs), br.DeviceBatch(jobs)
+    ref = [load("config1_res_%d.txt" % (i % 4))[1] for i in range(12)] + [br.resultant(*pairs[-1])]
+    for x in (a, b):
+        x.run()
+        assert x.results() == ref
+    h0, m0 = br.plan_cache_stats()
+    prev = None
+    for k in range(8):
+        x = (a, b)[k % 2]
+        x.run_async()
+        if prev is not None:
+            prev.wait()
+            assert prev.results() == ref, k
+        prev = x
+    prev.wait()
+    assert prev.results() == ref
+    h1, m1 = br.plan_cache_stats()
+    assert h1 - h0 >= 6 and m1 == m0
+    # b's job 0 gets a much larger coefficient while a is in flight
+    F0 = [list(r) for r in pairs[0][0]]
+    F0[0][1] = 1 << 29
+    t = b.inputs[0][0].tensor
+    assert b.inputs[0][0].shape[2] == 1
+    a.run_async()
+    t.view(-1)[1] = 1 << 29
+    torch.cuda.synchronize()
+    b.run_async()
+    a.wait()
+    b.wait()
+    assert a.results() == ref
+    got = b.results()
+    assert got[0] == resultant_y(F0, pairs[0][1])
+    assert got[1:] == ref[1:]
+    h2, m2 = br.plan_cache_stats()
+    assert m2 == m1 + 1
 
 
 @pytest.mark.parametrize("mn", [(23, 9), (9, 23), (24, 4), (31, 31), (31, 2), (32, 6), (5, 0), (0, 7), (1, 1)])
