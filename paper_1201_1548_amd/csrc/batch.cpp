@@ -436,7 +436,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   // bucket, so small jobs are not held to the occupancy of the largest)
   // jobs whose f array fits in registers (eval_elim_rg_capacity 24 or 32) run
   // in two more launches
-  enum { K_RED, K_IP, K_MRC, K_SUM, K_CAR, K_EE0, NBUCKET = 5, K_RG0 = K_EE0 + NBUCKET, NRG = 2, NK = K_RG0 + NRG };
+  enum { K_RED, K_IP, K_MRC, K_SUM, K_CAR, K_CRT, K_EE0, NBUCKET = 5, K_RG0 = K_EE0 + NBUCKET, NRG = 2, NK = K_RG0 + NRG };
   const int bucket_words[NBUCKET] = {24, 40, 64, 96, 1 << 30};
   const int rg_cap[NRG] = {24, 32};
   int bw[NBUCKET] = {0}, br_[NBUCKET] = {0};
@@ -483,6 +483,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     starts[K_MRC][i + 1] = p.D;  // adjusted below once the largest prime count is known
     starts[K_SUM][i + 1] = (p.D * x.Lacc + 255) / 256;
     starts[K_CAR][i + 1] = debug ? 0 : (x.degcap + 1 + 63) / 64;
+    starts[K_CRT][i + 1] = debug ? 0 : (x.degcap + 1 + 31) / 32;
   }
   long long totalD = 0;
   for (int i = 0; i < nj; ++i) totalD += starts[K_MRC][i + 1];
@@ -511,7 +512,6 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   // staged schedule: explicit CRT straight to limbs when the prime counts allow
   std::vector<std::pair<const uint32_t*, int>> crt(nj, {nullptr, 0});
   bool use_crt = !debug && !fused && crt_ok(maxP);
-  int maxLM = 1;
   int lastP = -1, lastLM = 0;
   const uint32_t* lastd = nullptr;
   for (int i = 0; i < nj && use_crt; ++i) {
@@ -522,9 +522,8 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     }
     if (!lastd) use_crt = false;
     crt[i] = {lastd, lastLM};
-    maxLM = std::max(maxLM, lastLM);
   }
-  if (use_crt && crt_lds_bytes(maxP, maxLM, maxLcap) > cx->lds_per_block) use_crt = false;
+  if (use_crt && crt_lds_bytes(maxLcap) > cx->lds_per_block) use_crt = false;
   // staged schedule: interpolation on the matrix cores when at least 32 jobs
   // share D and P (all active jobs of the batch)
   std::vector<int> group;
@@ -760,7 +759,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
       if (!debug) {
         sg.add((const void*)itW, (const void*)itQ, itNB);
         sg.add((int)group.size(), gD, gP, (const void*)vinv, o_yp, o_gj, nb_of(K_IP), maxD, use_crt, nb_of(K_CAR),
-               maxLM, maxLcap, nb_of(K_MRC), mrc_lane, nb_of(K_SUM));
+               nb_of(K_CRT), maxLcap, nb_of(K_MRC), mrc_lane, nb_of(K_SUM));
         if (run) {
           if (!group.empty())
             launch_interp_mfma(d_jobs, (const int*)(D0 + o_gj), (int)group.size(), gD, gP, vinv,
@@ -769,7 +768,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
             launch_interp(d_jobs, st_of(K_IP), nj, nb_of(K_IP), maxD, cx->tab, itW, itQ, itNB, st);
           if (use_crt) {
             // residues to limbs in one pass over the output capacity
-            if (nb_of(K_CAR)) launch_crt(d_jobs, st_of(K_CAR), nj, nb_of(K_CAR), maxP, maxLM, maxLcap, cx->tab, st);
+            if (nb_of(K_CRT)) launch_crt(d_jobs, st_of(K_CRT), nj, nb_of(K_CRT), maxP, maxLcap, cx->tab, st);
           } else {
             if (nb_of(K_MRC)) launch_mrc(d_jobs, st_of(K_MRC), nj, nb_of(K_MRC), maxP, mrc_lane, cx->tab, st);
             if (nb_of(K_SUM)) launch_limbs_sum(d_jobs, st_of(K_SUM), nj, nb_of(K_SUM), cx->tab, st);

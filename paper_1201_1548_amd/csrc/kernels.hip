@@ -998,18 +998,14 @@ size_t interp_lds_words(int D) { return (size_t)3 * D + (size_t)((D + KB - 1) / 
 typedef int im_v4i __attribute__((ext_vector_type(4)));
 typedef int im_v16i __attribute__((ext_vector_type(16)));
 
-// The four balanced base-256 digits of the symmetric representative of x mod p,
-// packed little-endian into one word.
+// The four balanced base-256 digits of the symmetric representative v of
+// x mod p, packed little-endian into one word.  Adding 128 at each of the
+// three low digit positions makes those digits d_s + 128 in [0, 255] (plain
+// base 256), with the top digit (|d_3| <= 64) left in the top byte; flipping
+// bit 7 of the three low bytes subtracts the 128 again in int8 terms.
 __device__ __forceinline__ uint32_t digits4(uint32_t x, uint32_t p) {
-  int32_t v = x > (p >> 1) ? (int32_t)(x - p) : (int32_t)x;
-  uint32_t out = 0;
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    const int32_t r = ((v + 128) & 255) - 128;
-    out |= (uint32_t)(r & 255) << (8 * s);
-    v = (v - r) >> 8;
-  }
-  return out | ((uint32_t)(v & 255) << 24);
+  const uint32_t v = x > (p >> 1) ? x - p : x;
+  return (v + 0x808080u) ^ 0x808080u;
 }
 
 __device__ __forceinline__ void put_digits(int8_t* base, size_t plane, size_t off, uint32_t d) {
@@ -1394,199 +1390,166 @@ __global__ __launch_bounds__(64) void k_limbs_carry(const JobDev* jobs, const in
   dev_limbs_carry(jobs[job], blockIdx.x - starts[job], stage_ld, lds);
 }
 
-// (e) explicit CRT, one block of 256 threads per 64 output coefficients.
-// With M = prod_{k<P} p_k, M_k = M / p_k and w_k = M_k^{-1} mod p_k, the
-// integer X = sum_k y_k M_k, y_k = x_k w_k mod p_k, is congruent to the
-// coefficient modulo every p_k, and X / M = sum_k y_k / p_k.  The planner
-// takes M > 2^1.001 B (B the coefficient bound), so the coefficient is
-// X - t M with t the integer nearest to sum_k y_k / p_k; fp64 gives that sum
-// within P 2^-52, far inside the margin of more than 3e-4 to a half-integer.
-// Limb l of X - t M is the signed column sum
-// S_l = sum_k y_k limb_l(M_k) - t limb_l(M) plus the carry out of limb l-1.
-// The columns are independent, so all four waves form them (limbs l = wave,
-// wave + 4, ...); one lane per coefficient then propagates the carries.
-// Nothing is serial in the prime index, unlike Garner's digits.
+// (e) explicit CRT on the int8 matrix cores.  With M = prod_{k<P} p_k,
+// M_k = M / p_k and w_k = M_k^{-1} mod p_k, let y_k be the symmetric
+// representative of x_k w_k mod p_k (|y_k| < p_k / 2).  Then X = sum_k y_k M_k
+// is congruent to the coefficient modulo every p_k and X / M = sum_k y_k / p_k,
+// so the coefficient is X - t M with t the integer nearest to that sum (the
+// planner takes M > 2^1.001 B, B the coefficient bound, and fp64 gives the sum
+// within P 2^-52 of its value, far inside the margin of more than 3e-4 to a
+// half-integer).
+//
+// X is a contraction: with y_k = sum_s d_ks 256^s and M_k = sum_j e_kj 256^j in
+// balanced base-256 digits (int8), X = sum_c S_c 256^c where
+// S_c = sum_{k,s} d_ks e_k(c - s).  For one coefficient per row that is a
+// product [rows x 4P] x [4P x byte columns] whose right operand depends only on
+// P (crt_tables builds it in operand order); |S_c| < 2^23 for P <= 128.
+// One wave per 32 coefficients of one job: the lanes form the digit words of
+// their rows' y_k straight into the left operand (lane x + 32 g: row x,
+// primes 8 ks + 4 g + 0..3 of step ks, four digits each), then for each tile
+// of 32 byte columns, low to high, v_mfma_i32_32x32x32_i8 over the steps, the
+// tile through LDS, and lanes 0..31 fold its 32 columns into eight 32-bit
+// limbs of X - t M with a signed carry kept in a register.  The limbs are
+// staged in LDS rows of sld words and written as one contiguous range.
 constexpr int CRT_MAXP = 128;
-constexpr int CRT_R = 12;  // limb columns per wave and pass (registers)
 
-// LDS layout (words): Y [P][64] (later the output staging rows), Tq [64],
-// Mk [P][LMp], w [P], M [LMp], limbs [LMp][64], carries [4 * npass][64][2];
-// LMp = LM rounded up to 4 * CRT_R.
-__device__ __forceinline__ void dev_crt(const JobDev& J, int lb, int stage_ld, TablesDev tab, uint32_t* lds) {
+// Every lane runs the same instructions: indices past the job's primes or
+// degree bound are clamped for the loads and their values masked to zero, and
+// all KSMAX steps run (the left operand is zero past the job's KS steps), so
+// the loads of a phase are issued together instead of behind per-lane branches.
+template <int KSMAX>
+__global__ __launch_bounds__(64) void k_crt_mfma(const JobDev* jobs, const int* starts, int nj, int sld,
+                                                 TablesDev tab) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const int job = find_job(starts, nj, blockIdx.x);
+  const JobDev& J = jobs[job];
   const int P = J.P, D = J.D, Lc = J.Lcap, LM = J.crt_LM;
-  const int LMp = (LM + 4 * CRT_R - 1) / (4 * CRT_R) * (4 * CRT_R);
-  const int npass = LMp / (4 * CRT_R);
-  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int c0 = lb * 64, c = c0 + lane;
+  const int KS = (P + 7) >> 3, NCT = (4 * LM + 4 + 31) >> 5;
+  const int l = threadIdx.x, x = l & 31, g = l >> 5;
+  const int c0 = (blockIdx.x - starts[job]) * 32, c = c0 + x;
   if (c0 >= D) {
     // beyond the degree bound: zero coefficients up to the output capacity
-    const int nc = min(64, J.degcap + 1 - c0);
+    const int nr = min(32, J.degcap + 1 - c0);
     uint32_t* dst = J.out + (size_t)c0 * Lc;
-    for (int i = threadIdx.x; i < nc * Lc; i += blockDim.x) dst[i] = 0u;
+    for (int i = l; i < nr * Lc; i += 64) dst[i] = 0u;
     return;
   }
-  const int ny = max(P, stage_ld);
-  uint32_t* Y = lds;
-  int32_t* Tq = (int32_t*)(lds + ny * 64);
-  uint32_t* Mk = lds + ny * 64 + 64;
-  uint32_t* wv = Mk + P * LMp;
-  uint32_t* Ms = wv + P;
-  uint32_t* Lb = Ms + LMp;                              // [LMp][64] limbs of each wave's range
-  const int co_off = (int)(Lb - lds) + LMp * 64;
-  int64_t* Co = (int64_t*)(lds + co_off + (co_off & 1));  // [4 npass][64] carries out of a range (8-byte aligned)
-  // stage the CRT constants
-  const uint32_t* gw = J.crt;
-  const uint32_t* gMk = J.crt + P;
-  const uint32_t* gM = gMk + (size_t)P * LM;
-  for (int i = threadIdx.x; i < P * LMp; i += blockDim.x) {
-    const int k = i / LMp, l = i - k * LMp;
-    Mk[i] = l < LM ? gMk[(size_t)k * LM + l] : 0u;
+  int32_t* T = (int32_t*)lds;   // [32][33]: one accumulator tile, [row][column]
+  uint32_t* O = lds + 32 * 33;  // [32][sld]: limbs of the rows, then the prime constants
+  const uint32_t* wv = J.crt;
+  const uint32_t* Mw = J.crt + P + (size_t)P * LM;
+  const __attribute__((address_space(1))) uint32_t* Bt =
+      gmem(J.crt) + (((size_t)P + (size_t)P * LM + LM + 3) & ~(size_t)3) + 4 * l;
+  const bool row = c < D;
+  const __attribute__((address_space(1))) uint32_t* col = gmem(J.coefs) + min(c, D - 1);
+  // this lane's residues (primes 8 ks + 4 g + j), all issued before the barrier
+  uint32_t xr[KSMAX * 4];
+#pragma unroll
+  for (int u = 0; u < KSMAX * 4; ++u) xr[u] = col[(size_t)min(8 * (u >> 2) + 4 * g + (u & 3), P - 1) * D];
+  // per-prime constants staged in LDS: p, -p^{-1} mod 2^32, w_k, 1 / p_k;
+  // then the words of M, zero from LM up to the last byte column's limb
+  uint32_t* Cp = O + 32 * sld;
+  double* Ci = (double*)(Cp + 3 * CRT_MAXP);
+  uint32_t* Ms = Cp + 5 * CRT_MAXP;
+  for (int k = l; k < P; k += 64) {
+    const ModP q = tab.primes[k];
+    Cp[k] = q.p;
+    Cp[CRT_MAXP + k] = q.pinv;
+    Cp[2 * CRT_MAXP + k] = wv[k];
+    Ci[k] = tab.inv_p[k];
   }
-  for (int i = threadIdx.x; i < P; i += blockDim.x) wv[i] = gw[i];
-  for (int i = threadIdx.x; i < LMp; i += blockDim.x) Ms[i] = i < LM ? gM[i] : 0u;
+  for (int w = l; w < 8 * NCT; w += 64) Ms[w] = w < LM ? Mw[w] : 0u;
   __syncthreads();
-  // y_k for primes k = wave + 4 u, eight loads in flight per batch; each wave
-  // also sums its share of y_k / p_k
-  {
-    const __attribute__((address_space(1))) uint32_t* co = gmem(J.coefs) + (c < D ? c : 0);
-    double f = 0.0;
-    for (int k0 = wave; k0 < P; k0 += 32) {
-      uint32_t x[8];
+  im_v4i A[KSMAX];
+  double f = 0.0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int k = k0 + 4 * u;
-        x[u] = (k < P && c < D) ? co[(size_t)k * D] : 0u;
-      }
+  for (int ks = 0; ks < KSMAX; ++ks) {
+    uint32_t d[4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int k = k0 + 4 * u;
-        if (k < P) {
-          const uint32_t y = mmul(x[u], wv[k], tab.primes[k]);
-          Y[k * 64 + lane] = y;
-          f = fma((double)y, tab.inv_p[k], f);
-        }
-      }
+    for (int j = 0; j < 4; ++j) {
+      const int u = 4 * ks + j, kl = 8 * ks + 4 * g + j, k = min(kl, P - 1);
+      const uint32_t p = Cp[k], pinv = Cp[CRT_MAXP + k];
+      const bool live = row && kl < P;
+      const uint32_t y = redc((uint64_t)xr[u] * Cp[2 * CRT_MAXP + k], p, pinv);
+      const int32_t ys = y > (p >> 1) ? (int32_t)(y - p) : (int32_t)y;
+      f = fma((double)(live ? ys : 0), Ci[k], f);
+      d[j] = digits4(y, p) & (0u - (uint32_t)live);
     }
-    double* part = (double*)(lds + co_off + (co_off & 1)) + 0;  // reuses the carry area (free until the sums)
-    part[wave * 64 + lane] = f;
+    A[ks] = (im_v4i){(int)d[0], (int)d[1], (int)d[2], (int)d[3]};
+  }
+  f += __shfl_xor(f, 32);
+  const int64_t tq = (int64_t)floor(f + 0.5);
+  int64_t carry = 0;
+  uint32_t last = 0;
+  bool bad = false, nz = false;
+  im_v4i B[KSMAX];
+#pragma unroll
+  for (int ks = 0; ks < KSMAX; ++ks)
+    B[ks] = *(const __attribute__((address_space(1))) im_v4i*)(Bt + (size_t)min(ks, KS - 1) * 256);
+  for (int ct = 0; ct < NCT; ++ct) {
+    im_v16i acc = {0};
+#pragma unroll
+    for (int ks = 0; ks < KSMAX; ++ks) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[ks], B[ks], acc, 0, 0, 0);
+    // the next tile's operand blocks and this tile's words of M
+    const __attribute__((address_space(1))) uint32_t* Bn = Bt + (size_t)min(ct + 1, NCT - 1) * KS * 256;
+#pragma unroll
+    for (int ks = 0; ks < KSMAX; ++ks)
+      B[ks] = *(const __attribute__((address_space(1))) im_v4i*)(Bn + (size_t)min(ks, KS - 1) * 256);
+    // accumulator register r of lane l: row 8 (r / 4) + 4 g + r % 4, column x
+#pragma unroll
+    for (int r = 0; r < 16; ++r) T[(8 * (r >> 2) + 4 * g + (r & 3)) * 33 + x] = acc[r];
     __syncthreads();
-    if (wave == 0) {
-      const double ft = ((part[lane] + part[64 + lane]) + part[128 + lane]) + part[192 + lane];
-      Tq[lane] = (int32_t)(ft + 0.5);
-    }
-  }
-  __syncthreads();
-  // column sums of the wave's CRT_R limbs per pass, prime-outer; then the
-  // range is normalised to 32-bit limbs plus a signed carry out.  y_k is
-  // split into 16-bit halves: each half times a limb is below 2^48, so P <=
-  // 128 of them sum in 64 bits with no carry word, one multiply-add each.
-  const uint64_t t = (uint64_t)Tq[lane];
-  for (int pass = 0; pass < npass; ++pass) {
-    const int l0 = (pass * 4 + wave) * CRT_R;
-    uint64_t alo[CRT_R], ahi[CRT_R];
+    if (g == 0) {
+      const int32_t* t = T + x * 33;
 #pragma unroll
-    for (int j = 0; j < CRT_R; ++j) {
-      alo[j] = 0;
-      ahi[j] = 0;
-    }
-    // a range past the last limb is all padding (zero columns); the padded
-    // columns of a partial range are zero in LDS and cost no branches
-    const bool live = __builtin_amdgcn_readfirstlane(l0) < __builtin_amdgcn_readfirstlane(LM);
-#pragma unroll 2
-    for (int k = 0; k < P && live; ++k) {
-      const uint32_t y = Y[k * 64 + lane];
-      const uint64_t ylo = y & 0xFFFFu, yhi = y >> 16;
-      const uint4* mk = (const uint4*)(Mk + k * LMp + l0);
-      const uint4 m0 = mk[0], m1 = mk[1], m2 = mk[2];
-      const uint32_t mm[CRT_R] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w, m2.x, m2.y, m2.z, m2.w};
-#pragma unroll
-      for (int j = 0; j < CRT_R; ++j) {
-        alo[j] += ylo * mm[j];
-        ahi[j] += yhi * mm[j];
-      }
-    }
-    int64_t carry = 0;
-#pragma unroll
-    for (int j = 0; j < CRT_R; ++j) {
-      // the column sum ahi 2^16 + alo as 96 bits (h : lo); ahi < 2^54
-      const uint64_t sh = ahi[j] << 16;
-      const uint64_t lo = sh + alo[j];
-      const uint32_t hi = (uint32_t)(ahi[j] >> 48) + (lo < sh ? 1u : 0u);
-      const uint64_t sub = t * Ms[l0 + j];
-      uint32_t h = hi - (lo < sub ? 1u : 0u);
-      uint64_t v = lo - sub;
-      // v + carry as 96-bit two's complement (h:v)
-      const uint64_t v2 = v + (uint64_t)carry;
-      h += (carry < 0 ? 0xFFFFFFFFu : 0u) + (v2 < v ? 1u : 0u);
-      Lb[(l0 + j) * 64 + lane] = (uint32_t)v2;
-      carry = (int64_t)(((uint64_t)h << 32) | (v2 >> 32));
-    }
-    Co[(pass * 4 + wave) * 64 + lane] = carry;
-  }
-  __syncthreads();
-  const bool staged = stage_ld > 0;
-  bool nz = false;
-  if (wave == 0 && c <= J.degcap) {
-    uint32_t* o = staged ? Y + lane * stage_ld : J.out + (size_t)c * Lc;
-    if (c >= D) {
-      for (int l = 0; l < Lc; ++l) o[l] = 0u;
-    } else {
-      // limbs of the ranges plus the carries out of the ranges below them
-      int64_t carry = 0;
-      bool bad = false;
-      uint32_t last = 0;
-      const int Lrun = max(Lc, LM);
-      for (int l = 0; l < Lrun; ++l) {
-        uint64_t v = (uint64_t)(l < LMp ? Lb[l * 64 + lane] : 0u);
-        int64_t acc = carry + (int64_t)v;
-        if (l > 0 && l < LMp && l % CRT_R == 0) acc += Co[(l / CRT_R - 1) * 64 + lane];
-        if (l == LMp && LMp > 0) acc += Co[(LMp / CRT_R - 1) * 64 + lane];
-        const uint32_t limb = (uint32_t)acc;
-        carry = acc >> 32;
-        if (l < Lc) {
-          o[l] = limb;
+      for (int w = 0; w < 8; ++w) {
+        const int L = 8 * ct + w;
+        // |S_c| <= P (3 * 128 + 64) 128 < 2^23 (the top digit of y_k is at most
+        // 64 in size), so t_0 + 2^8 t_1 and t_2 + 2^8 t_3 fit in 32 bits
+        const int32_t lo = t[4 * w] + (t[4 * w + 1] << 8), hi = t[4 * w + 2] + (t[4 * w + 3] << 8);
+        const int64_t v = carry + (int64_t)lo + ((int64_t)hi << 16) - tq * (int64_t)Ms[L];
+        const uint32_t limb = (uint32_t)v;
+        carry = v >> 32;
+        if (L < Lc) {
+          O[x * sld + L] = limb;
           nz |= limb != 0u;
           last = limb;
         } else if (limb != ((int32_t)last < 0 ? 0xFFFFFFFFu : 0u)) {
           bad = true;
         }
       }
-      if (Lrun < LMp + 1) {
-        // carries beyond the last processed limb must be pure sign
-        int64_t rest = carry;
-        for (int l = Lrun; l <= LMp; ++l) {
-          int64_t acc = rest + (int64_t)(l < LMp ? Lb[l * 64 + lane] : 0u);
-          if (l > 0 && l < LMp && l % CRT_R == 0) acc += Co[(l / CRT_R - 1) * 64 + lane];
-          if (l == LMp) acc += Co[(LMp / CRT_R - 1) * 64 + lane];
-          if ((uint32_t)acc != ((int32_t)last < 0 ? 0xFFFFFFFFu : 0u)) bad = true;
-          rest = acc >> 32;
-        }
-        carry = rest;
-      }
-      if (bad || carry != ((int32_t)last < 0 ? -1 : 0)) atomicOr(J.err, 1);
     }
-  }
-  if (wave == 0) {
-    // one atomic per wave: the highest non-zero coefficient of the 64
-    const uint64_t any = __ballot(nz);
-    if (any && lane == 0) atomicMax(J.deg_out, c0 + 63 - __clzll((long long)any));
-  }
-  if (staged) {
     __syncthreads();
-    const int nc = min(64, J.degcap + 1 - c0);
-    uint32_t* dst = J.out + (size_t)c0 * Lc;
-    for (int i = threadIdx.x; i < nc * Lc; i += blockDim.x) {
-      const int r = i / Lc;
-      dst[i] = Y[r * stage_ld + (i - r * Lc)];
+  }
+  if (g == 0) {
+    // limbs above the last byte column: the carry's extension
+    for (int L = 8 * NCT; L < Lc; ++L) {
+      const uint32_t limb = (uint32_t)carry;
+      carry >>= 32;
+      O[x * sld + L] = limb;
+      nz |= limb != 0u;
+      last = limb;
+    }
+    if (row && (bad || carry != ((int32_t)last < 0 ? -1 : 0))) atomicOr(J.err, 1);
+  }
+  // one atomic per wave: the highest non-zero coefficient of the 32
+  const uint64_t any = __ballot(g == 0 && row && nz);
+  if (any && l == 0) atomicMax(J.deg_out, c0 + 63 - __clzll((long long)any));
+  __syncthreads();
+  // rows c0 .. c0 + nr - 1 are one contiguous range of nr Lc words
+  const int nr = min(32, J.degcap + 1 - c0);
+  uint32_t* dst = J.out + (size_t)c0 * Lc;
+  const int dq = 64 / Lc, dr = 64 - dq * Lc;
+  int r = l / Lc, L = l - r * Lc;
+  for (int i = l; i < nr * Lc; i += 64) {
+    dst[i] = O[r * sld + L];
+    r += dq;
+    L += dr;
+    if (L >= Lc) {
+      L -= Lc;
+      ++r;
     }
   }
-}
-
-__global__ __launch_bounds__(256) void k_crt(const JobDev* jobs, const int* starts, int nj, int stage_ld,
-                                             TablesDev tab) {
-  extern __shared__ __align__(16) uint32_t lds[];
-  const int job = find_job(starts, nj, blockIdx.x);
-  dev_crt(jobs[job], blockIdx.x - starts[job], stage_ld, tab, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1973,19 +1936,37 @@ void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int 
 
 bool crt_ok(int max_primes) { return max_primes <= CRT_MAXP; }
 
-size_t crt_lds_bytes(int max_primes, int max_lm, int max_lcap) {
-  const int stage_ld = max_lcap <= CARRY_STAGE_MAXL ? max_lcap + 1 : 0;
-  const size_t LMp = (size_t)(max_lm + 4 * CRT_R - 1) / (4 * CRT_R) * (4 * CRT_R);
-  const size_t words = (size_t)64 * std::max(max_primes, stage_ld) + 64 + (size_t)max_primes * LMp + max_primes +
-                       LMp + LMp * 64 + 1 + (LMp / CRT_R) * 64 * 2;
-  return words * sizeof(uint32_t);
+int crt_row_stride(int max_lcap) { return max_lcap | 1; }
+
+// words of M for the largest prime count, rounded up to whole column tiles
+static int crt_max_words() { return 8 * ((4 * (CRT_MAXP + 1) + 4 + 31) / 32); }
+
+size_t crt_lds_bytes(int max_lcap) {
+  // accumulator tile, limb rows (an even word count), prime constants
+  const size_t rows = (size_t)32 * crt_row_stride(max_lcap);
+  return (size_t)(32 * 33 + rows + 5 * CRT_MAXP + crt_max_words()) * sizeof(uint32_t);
 }
 
-void launch_crt(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, int max_lm, int max_lcap,
+void launch_crt(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, int max_lcap,
                 TablesDev tab, hipStream_t s) {
-  const int stage_ld = max_lcap <= CARRY_STAGE_MAXL ? max_lcap + 1 : 0;
-  hipLaunchKernelGGL(k_crt, dim3(nblocks), dim3(256), crt_lds_bytes(max_primes, max_lm, max_lcap), s, jobs, starts,
-                     nj, stage_ld, tab);
+  const int sld = crt_row_stride(max_lcap);
+  const size_t lds = crt_lds_bytes(max_lcap);
+  const int ks = (max_primes + 7) / 8;
+#define BIRES_CRT_LAUNCH(K) \
+  hipLaunchKernelGGL(k_crt_mfma<K>, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, sld, tab)
+  if (ks <= 2)
+    BIRES_CRT_LAUNCH(2);
+  else if (ks <= 4)
+    BIRES_CRT_LAUNCH(4);
+  else if (ks <= 6)
+    BIRES_CRT_LAUNCH(6);
+  else if (ks <= 8)
+    BIRES_CRT_LAUNCH(8);
+  else if (ks <= 12)
+    BIRES_CRT_LAUNCH(12);
+  else
+    BIRES_CRT_LAUNCH(16);
+#undef BIRES_CRT_LAUNCH
 }
 
 void launch_limbs_sum(const JobDev* jobs, const int* starts, int nj, int nblocks, TablesDev tab, hipStream_t s) {

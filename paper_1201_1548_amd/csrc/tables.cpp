@@ -111,6 +111,13 @@ void mrc_tables(const std::vector<ModP>& primes, std::vector<uint32_t>& gm, std:
   }
 }
 
+size_t crt_operand_offset(int P, int LM) { return ((size_t)P + (size_t)P * LM + LM + 3) & ~(size_t)3; }
+
+void crt_operand_tiles(int P, int LM, int* nct, int* nks) {
+  *nct = (4 * LM + 4 + 31) / 32;  // byte columns 0..4 LM + 3
+  *nks = (P + 7) / 8;             // 4 P contraction indices, 32 per step
+}
+
 CrtHost crt_tables(int P) {
   const HostTables& t = host_tables();
   CrtHost c;
@@ -119,7 +126,10 @@ CrtHost crt_tables(int P) {
   while (M.size() > 1 && M.back() == 0u) M.pop_back();
   const int LM = (int)M.size();
   c.LM = LM;
-  c.buf.assign((size_t)P + (size_t)P * LM + LM, 0u);
+  int nct = 0, nks = 0;
+  crt_operand_tiles(P, LM, &nct, &nks);
+  const size_t ob = crt_operand_offset(P, LM);
+  c.buf.assign(ob + (size_t)nct * nks * 256, 0u);
   for (int k = 0; k < P; ++k) {
     const ModP& q = t.primes[k];
     // M / p_k by schoolbook division with a one-limb divisor (exact)
@@ -136,6 +146,29 @@ CrtHost crt_tables(int P) {
     c.buf[k] = minv(to_mont((uint32_t)r, q), q);
   }
   for (int l = 0; l < LM; ++l) c.buf[(size_t)P + (size_t)P * LM + l] = M[l];
+  // balanced base-256 digits of each M / p_k: 4 LM bytes plus one top digit
+  const int nd = 4 * LM + 1;
+  std::vector<int8_t> dig((size_t)P * nd);
+  for (int k = 0; k < P; ++k) {
+    const uint32_t* row = &c.buf[(size_t)P + (size_t)k * LM];
+    int carry = 0;
+    for (int j = 0; j < 4 * LM; ++j) {
+      const int v = (int)((row[j >> 2] >> (8 * (j & 3))) & 255u) + carry;
+      carry = v >= 128 ? 1 : 0;
+      dig[(size_t)k * nd + j] = (int8_t)(v - 256 * carry);
+    }
+    dig[(size_t)k * nd + 4 * LM] = (int8_t)carry;
+  }
+  uint8_t* B = (uint8_t*)&c.buf[ob];
+  for (int ct = 0; ct < nct; ++ct)
+    for (int ks = 0; ks < nks; ++ks)
+      for (int L = 0; L < 64; ++L)
+        for (int b = 0; b < 16; ++b) {
+          const int col = 32 * ct + (L & 31), idx = 32 * ks + 16 * (L >> 5) + b;
+          const int k = idx >> 2, s = idx & 3, j = col - s;
+          const int8_t e = (k < P && j >= 0 && j < nd) ? dig[(size_t)k * nd + j] : (int8_t)0;
+          B[(((size_t)ct * nks + ks) * 64 + L) * 16 + b] = (uint8_t)e;
+        }
   return c;
 }
 

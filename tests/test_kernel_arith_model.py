@@ -384,6 +384,18 @@ def test_vinv_by_synthetic_division_inverts_vandermonde():
                 assert s == (1 if i == c else 0)
 
 
+def test_packed_digits_by_offset_and_flip():
+    # the kernels pack the four balanced digits of the symmetric representative
+    # v as ((v + 0x808080) mod 2^32) xor 0x808080, one byte per digit
+    rng = random.Random(5)
+    for p in PRIMES + [3, 257, 65537]:
+        for x in [0, 1, p - 1, p // 2, p // 2 + 1] + [rng.randrange(p) for _ in range(3000)]:
+            v = x - p if x > p // 2 else x
+            w = ((v + 0x808080) & 0xFFFFFFFF) ^ 0x808080
+            got = [((w >> (8 * s)) & 255) - (256 if (w >> (8 * s)) & 128 else 0) for s in range(4)]
+            assert got == balanced_digits(x, p), (x, p)
+
+
 def test_digit_grouped_products_reconstruct_the_residue():
     rng = random.Random(8)
     for p in PRIMES:
@@ -405,64 +417,77 @@ def test_digit_grouped_products_reconstruct_the_residue():
             assert got == sum(a * b for a, b in zip(A, B)) % p
 
 
-def crt_model_ranges(residues, primes, R=12, Lc=None):
-    """The limb kernel's staging of the explicit CRT: limb columns in ranges
-    of R, each range normalised to 32-bit limbs plus a signed carry out with
-    its own carry chain, then one pass adding each range's carry at the next
-    range's first limb; returns the two's-complement value of Lc limbs."""
+def crt_model_mfma(residues, primes, Lc=None):
+    """The matrix-core CRT: y_k as the symmetric representative of x_k w_k
+    mod p_k, t = nearest integer to sum y_k / p_k (fp64), and X = sum_k y_k M_k
+    formed as byte-column sums S_c = sum_{k,s} d_ks e_k(c - s) of balanced
+    base-256 digits (d of y_k, e of M_k; the int8 product), folded into
+    32-bit limbs of X - t M, eight per tile of 32 columns, with one signed
+    carry; returns the two's-complement value of Lc limbs."""
     import math
     P = len(primes)
     M = math.prod(primes)
     LM = (M.bit_length() + 31) // 32
-    LMp = -(-LM // (4 * R)) * (4 * R)
+    NCT = (4 * LM + 4 + 31) // 32
     Mk = [M // p for p in primes]
     y = [x * pow(mk % p, -1, p) % p for x, mk, p in zip(residues, Mk, primes)]
     f = 0.0
     for yk, p in zip(y, primes):
-        f = math.fma(float(yk), 1.0 / p, f) if hasattr(math, "fma") else f + float(yk) * (1.0 / p)
-    t = int(f + 0.5)
-    limb = lambda v, l: (v >> (32 * l)) & 0xFFFFFFFF
-    Lb, Co = [0] * LMp, []
-    for r in range(LMp // R):
-        carry = 0
-        for j in range(R):
-            l = r * R + j
-            # y_k in 16-bit halves, each half's column sum in 64 bits
-            alo = sum((yk & 0xFFFF) * limb(mk, l) for yk, mk in zip(y, Mk))
-            ahi = sum((yk >> 16) * limb(mk, l) for yk, mk in zip(y, Mk))
-            assert alo < 1 << 64 and ahi < 1 << 54
-            v = (ahi << 16) + alo - t * limb(M, l) + carry
-            Lb[l] = v & 0xFFFFFFFF
-            carry = v >> 32
-        assert abs(carry) < 1 << 63
-        Co.append(carry)
+        ys = yk - p if yk > p // 2 else yk
+        f = math.fma(float(ys), 1.0 / p, f) if hasattr(math, "fma") else f + float(ys) * (1.0 / p)
+    t = math.floor(f + 0.5)
+    d = [balanced_digits(yk, p) for yk, p in zip(y, primes)]
+    e = []
+    for mk in Mk:
+        dig, carry = [], 0
+        for j in range(4 * LM):
+            v = ((mk >> (8 * j)) & 255) + carry
+            carry = 1 if v >= 128 else 0
+            dig.append(v - 256 * carry)
+        dig.append(carry)
+        assert sum(di << (8 * j) for j, di in enumerate(dig)) == mk
+        e.append(dig)
+    S = [0] * (32 * NCT)
+    for c in range(32 * NCT):
+        for k in range(P):
+            for s_ in range(4):
+                if 0 <= c - s_ < 4 * LM + 1:
+                    S[c] += d[k][s_] * e[k][c - s_]
+        assert abs(S[c]) <= P * (3 * 128 + 64) * 128 < 1 << 23
+    assert all(abs(dk[3]) <= 64 for dk in d)
     Lc = Lc or LM
-    out, carry = [], 0
-    for l in range(max(Lc, LMp + 1)):
-        acc = carry + (Lb[l] if l < LMp else 0)
-        if 0 < l <= LMp and l % R == 0:
-            acc += Co[l // R - 1]
-        out.append(acc & 0xFFFFFFFF)
-        carry = acc >> 32
-    assert carry in (0, -1)
-    val = sum(w << (32 * i) for i, w in enumerate(out[:Lc]))
-    sign = out[Lc - 1] >> 31
-    assert all(w == (0xFFFFFFFF if sign else 0) for w in out[Lc:])
+    limbs, carry = [], 0
+    for L in range(max(8 * NCT, Lc)):
+        v = carry
+        if L < 8 * NCT:
+            lo, hi = S[4 * L] + (S[4 * L + 1] << 8), S[4 * L + 2] + (S[4 * L + 3] << 8)
+            assert -(1 << 31) <= lo < 1 << 31 and -(1 << 31) <= hi < 1 << 31
+            v += lo + (hi << 16)
+        if L < LM:
+            v -= t * ((M >> (32 * L)) & 0xFFFFFFFF)
+        assert -(1 << 63) <= v < 1 << 63
+        limbs.append(v & 0xFFFFFFFF)
+        carry = v >> 32
+    sign = limbs[Lc - 1] >> 31
+    assert carry == (-1 if sign else 0)
+    assert all(w == (0xFFFFFFFF if sign else 0) for w in limbs[Lc:])
+    val = sum(w << (32 * i) for i, w in enumerate(limbs[:Lc]))
     return val - (1 << (32 * Lc)) if sign else val
 
 
-def test_explicit_crt_with_range_carries():
+def test_explicit_crt_on_digit_columns():
     import math
     from fractions import Fraction
     primes = _primes_desc(70)
     rng = random.Random(23)
-    for P in (1, 2, 17, 50, 70):
+    for P in (1, 2, 7, 17, 48, 70):
         ps = primes[:P]
         M = math.prod(ps)
         B = int(Fraction(M) * Fraction(2.0 ** -1.001)) - 1
-        for R in [0, 1, -1, B, -B] + [rng.randint(-B, B) for _ in range(20)]:
-            for width in (12, 16):
-                assert crt_model_ranges([R % p for p in ps], ps, R=width) == R, (P, R, width)
+        LM = (M.bit_length() + 31) // 32
+        for R in [0, 1, -1, B, -B, B - 1] + [rng.randint(-B, B) for _ in range(12)]:
+            for Lc in (LM, LM + 1, 8 * ((4 * LM + 35) // 32) + 3):
+                assert crt_model_mfma([R % p for p in ps], ps, Lc=Lc) == R, (P, R, Lc)
 
 
 def test_newton_block_tables_expand_the_newton_form():
