@@ -1062,10 +1062,11 @@ __global__ __launch_bounds__(256) void k_vinv(int D, int Dp, TablesDev tab, int8
   }
 }
 
-// Digit planes of the values for the group's jobs gj[0..N), zero for n >= N
-// or a >= D.  One thread per 16 consecutive nodes of one job: 16 values in,
-// one aligned 16-byte chunk out per plane.  Grid (ceil(Np Dp / 16 / 256), P).
-__global__ __launch_bounds__(256) void k_yplanes(const JobDev* jobs, const int* gj, int N, int Np, int D, int Dp,
+// Digit planes of the values of the group's jobs (gva[n] = their vals), zero
+// for n >= N or a >= D.  One thread per 16 consecutive nodes of one job: 16
+// values in (clamped loads, no branches), one aligned 16-byte chunk out per
+// plane.  Grid (ceil(Np Dp / 16 / 256), P).
+__global__ __launch_bounds__(256) void k_yplanes(const uint32_t* const* gva, int N, int Np, int D, int Dp,
                                                  TablesDev tab, int8_t* Yp) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x, k = blockIdx.y;
   const int per = Dp >> 4;
@@ -1074,10 +1075,12 @@ __global__ __launch_bounds__(256) void k_yplanes(const JobDev* jobs, const int* 
   const uint32_t p = tab.primes[k].p;
   const size_t plane = (size_t)Np * Dp;
   int8_t* base = Yp + (size_t)k * 4 * plane + im_off(n, a0, Dp);
-  const uint32_t* v = n < N ? jobs[gj[n]].vals + (size_t)k * D : nullptr;
+  const __attribute__((address_space(1))) uint32_t* v = gmem(gva[min(n, N - 1)]) + (size_t)k * D;
   uint32_t d[16];
 #pragma unroll
-  for (int u = 0; u < 16; ++u) d[u] = v && a0 + u < D ? digits4(v[a0 + u], p) : 0u;
+  for (int u = 0; u < 16; ++u) d[u] = v[min(a0 + u, D - 1)];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) d[u] = digits4(d[u], p) & (n < N && a0 + u < D ? ~0u : 0u);
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     uint32_t w[4];
@@ -1113,9 +1116,10 @@ __device__ __forceinline__ ImOps im_load(const int8_t* A, const int8_t* Y, size_
   return o;
 }
 
-__global__ __launch_bounds__(64) void k_interp_mfma(const JobDev* jobs, const int* gj, int N, int Np, int D, int Dp,
+__global__ __launch_bounds__(64) void k_interp_mfma(uint32_t* const* gco, int N, int Np, int D, int Dp,
                                                     const int8_t* Ap, const int8_t* Yp, TablesDev tab) {
   __shared__ uint32_t tile[32][33];
+  __shared__ uint32_t* colp[32];
   const int l = threadIdx.x, r32 = l & 31, g = l >> 5;
   // one-dimensional grid in XCD order: the tiles of one prime, which share
   // its operand planes, run on one XCD and share its L2
@@ -1128,6 +1132,9 @@ __global__ __launch_bounds__(64) void k_interp_mfma(const JobDev* jobs, const in
   // operand-order blocks: 1 KiB per (row tile, step); a lane reads bytes 16 l..16 l + 15
   const int8_t* A = Ap + (size_t)k * 4 * pa + (size_t)it * Dp * 32 + 16 * l;
   const int8_t* Y = Yp + (size_t)k * 4 * py + (size_t)nt * Dp * 32 + 16 * l;
+  // each column's output row (null past the group), loaded now so that the
+  // latency overlaps the products; every job of the group has P primes
+  uint32_t* const cp = gco[min(n0 + r32, N - 1)];
   im_v16i G0 = {0}, G1 = {0}, G2 = {0}, G3 = {0}, G4 = {0}, G5 = {0}, G6 = {0};
   ImOps cur = im_load(A, Y, pa, py, 0);
   for (int a0 = 0; a0 < Dp; a0 += 32) {
@@ -1172,15 +1179,14 @@ __global__ __launch_bounds__(64) void k_interp_mfma(const JobDev* jobs, const in
     }
     tile[r32][8 * (r >> 2) + 4 * g + (r & 3)] = fold96(S, q);  // [column][row]
   }
+  if (l < 32) colp[l] = n0 + l < N ? cp + (size_t)k * D : nullptr;
   __syncthreads();
   // lanes 0-31 write column n0 + 2c, lanes 32-63 column n0 + 2c + 1: 32 rows each
+  const int i = i0 + r32;
   for (int c = 0; c < 16; ++c) {
-    const int col = 2 * c + g, n = n0 + col;
-    const int i = i0 + r32;
-    if (n < N && i < D) {
-      const JobDev& J = jobs[gj[n]];
-      if (k < J.P) J.coefs[(size_t)k * D + i] = tile[col][r32];
-    }
+    const int col = 2 * c + g;
+    uint32_t* dst = colp[col];
+    if (dst && i < D) dst[i] = tile[col][r32];
   }
 }
 
@@ -1908,13 +1914,12 @@ void launch_vinv(int D, int Dp, int P, TablesDev tab, int8_t* Ap, hipStream_t s)
   hipLaunchKernelGGL(k_vinv, dim3(P), dim3(256), (size_t)2 * (D + 1) * sizeof(uint32_t), s, D, Dp, tab, Ap);
 }
 
-void launch_interp_mfma(const JobDev* jobs, const int* gj, int N, int D, int P, const int8_t* Ap, int8_t* Yp,
-                        TablesDev tab, hipStream_t s) {
+void launch_interp_mfma(const uint32_t* const* gva, uint32_t* const* gco, int N, int D, int P, const int8_t* Ap,
+                        int8_t* Yp, TablesDev tab, hipStream_t s) {
   const int Dp = (D + 31) & ~31, Np = (N + 31) & ~31;
   const int chunks = Np * (Dp / 16);
-  hipLaunchKernelGGL(k_yplanes, dim3((chunks + 255) / 256, P), dim3(256), 0, s, jobs, gj, N, Np, D, Dp, tab, Yp);
-  hipLaunchKernelGGL(k_interp_mfma, dim3((Dp / 32) * (Np / 32) * P), dim3(64), 0, s, jobs, gj, N, Np, D, Dp, Ap, Yp,
-                     tab);
+  hipLaunchKernelGGL(k_yplanes, dim3((chunks + 255) / 256, P), dim3(256), 0, s, gva, N, Np, D, Dp, tab, Yp);
+  hipLaunchKernelGGL(k_interp_mfma, dim3((Dp / 32) * (Np / 32) * P), dim3(64), 0, s, gco, N, Np, D, Dp, Ap, Yp, tab);
 }
 
 bool mrc_lane_ok(int max_primes, long long total_coefficients) {

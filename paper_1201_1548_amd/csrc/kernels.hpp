@@ -58,14 +58,15 @@ int interp_table_blocks(int max_points);
 size_t interp_table_words(int blocks, int primes, size_t* q_offset);
 void launch_interp_tables(int blocks, int primes, TablesDev tab, uint32_t* W, uint32_t* Q, hipStream_t s);
 size_t interp_lds_words(int D);
-// Interpolation of N jobs sharing D and P (job indices gj[0..N)) as int8
-// matrix-core products with V^{-1}: Ap = vinv_bytes(Dp, P) bytes built by
-// launch_vinv (Dp = D rounded up to 32); Yp = 4 Np Dp P bytes of workspace
-// (Np = N rounded up to 32).  Writes the jobs' coefs.
+// Interpolation of N jobs sharing D and P (gva[n] and gco[n] the vals and
+// coefs of job n of the group) as int8 matrix-core products with V^{-1}: Ap =
+// vinv_bytes(Dp, P) bytes built by launch_vinv (Dp = D rounded up to 32);
+// Yp = 4 Np Dp P bytes of workspace (Np = N rounded up to 32).  Writes the
+// jobs' coefs.
 size_t vinv_bytes(int Dp, int P);
 void launch_vinv(int D, int Dp, int P, TablesDev tab, int8_t* Ap, hipStream_t s);
-void launch_interp_mfma(const JobDev* jobs, const int* gj, int N, int D, int P, const int8_t* Ap, int8_t* Yp,
-                        TablesDev tab, hipStream_t s);
+void launch_interp_mfma(const uint32_t* const* gva, uint32_t* const* gco, int N, int D, int P, const int8_t* Ap,
+                        int8_t* Yp, TablesDev tab, hipStream_t s);
 void launch_invfact(const ModP* primes, int K, uint32_t* invfact, int dmax, hipStream_t s);
 // mrc blocks per job: ceil(D/64) with lane = true (one lane per coefficient,
 // allowed when mrc_lane_ok), else D (one wave per coefficient).
