@@ -149,6 +149,28 @@ __device__ void dev_reduce(const JobDev& J, int lb, int k0, int k1, TablesDev ta
     src = J.limbs_g + ((size_t)j * J.ldg + i) * J.Lg;
     L = J.Lg;
   }
+  if (L == 1) {
+    // one limb w (the common case): w R mod p, less R mod p when w is
+    // negative; w is loaded once, ahead of the stores
+    // (the prime constants are loaded eight at a time ahead of their stores)
+    const uint32_t w0 = src[0];
+    const bool neg = (w0 >> 31) != 0u;
+    for (int kb = k0; kb < k1; kb += 8) {
+      ModP qs[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) qs[j] = tab.primes[min(kb + j, k1 - 1)];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (kb + j >= k1) break;
+        const ModP& q = qs[j];
+        uint32_t x = mmul(w0, q.r2, q);
+        if (neg) x = msub(x, q.r2, q.p);
+        if (mult) x = mmul(x, to_mont(mult, q), q);
+        dst[(size_t)(kb + j) * T] = x;
+      }
+    }
+    return;
+  }
   const bool negv = (src[L - 1] >> 31) != 0u;
   for (int k = k0; k < k1; ++k) {
     const ModP q = tab.primes[k];
