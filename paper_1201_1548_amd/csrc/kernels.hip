@@ -68,6 +68,32 @@ __global__ void k_scan(const ScanTask* tasks, const int4* bmap) {
   if (j >= T.rows) return;
   int deg = -1, bits = 0, cnt = 0;
   double norm = 0.0;
+  if (T.L == 1) {
+    // one-limb coefficients: the row's words eight at a time (loads first),
+    // each handled as below, in the same order
+    const uint32_t* rowp = T.limbs + (size_t)j * T.ld;
+    for (int i0 = 0; i0 < T.ld; i0 += 8) {
+      uint32_t w[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) w[u] = rowp[min(i0 + u, T.ld - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (i0 + u >= T.ld || w[u] == 0u) continue;
+        const uint32_t inv = (w[u] >> 31) ? 0xFFFFFFFFu : 0u;
+        const uint32_t x = w[u] ^ inv;
+        const int b = (x ? 32 - __clz(x) : 0) + (inv ? 1 : 0);
+        deg = i0 + u;
+        ++cnt;
+        bits = b > bits ? b : bits;
+        norm += ((double)x + 1.0) * (1.0 + 0x1p-52);
+      }
+    }
+    T.out[4 * j + 0] = deg;
+    T.out[4 * j + 1] = bits;
+    T.out[4 * j + 2] = cnt;
+    T.out[4 * j + 3] = cnt ? (int32_t)ceil((log2(norm * (1.0 + 0x1p-40)) + 1e-6) * 1024.0) : 0;
+    return;
+  }
   for (int i = 0; i < T.ld; ++i) {
     const uint32_t* c = T.limbs + ((size_t)j * T.ld + i) * T.L;
     uint32_t top = c[T.L - 1];
