@@ -1211,21 +1211,18 @@ __global__ __launch_bounds__(64) void k_interp_mfma(uint32_t* const* gco, int N,
   const uint32_t m256 = to_mont(256u, q);
 #pragma unroll
   for (int u = 1; u < 7; ++u) w[u] = mmul(w[u - 1], m256, q);
+  // |G_u| <= 4 Dp 2^14 <= 2^28 and w_u < p < 2^31, so sum_u G_u w_u lies
+  // within 7 * 2^58.5 < 2^62 < p 2^32; adding p 2^32 (a multiple of p) makes
+  // it non-negative and below 2 p 2^32, where one Montgomery reduction
+  // leaves a value below 3p, hence one more conditional subtraction
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int32_t gv[7] = {G0[r], G1[r], G2[r], G3[r], G4[r], G5[r], G6[r]};
-    Acc96 S;
-    uint64_t t = 0;
+    int64_t t = (int64_t)q.p << 32;
 #pragma unroll
-    for (int u = 0; u < 7; ++u) {
-      const uint32_t res = gv[u] < 0 ? (uint32_t)(gv[u] + (int32_t)q.p) : (uint32_t)gv[u];
-      t += (uint64_t)res * w[u];
-      if (u == 3 || u == 6) {
-        S.add(t);
-        t = 0;
-      }
-    }
-    tile[r32][8 * (r >> 2) + 4 * g + (r & 3)] = fold96(S, q);  // [column][row]
+    for (int u = 0; u < 7; ++u) t += (int64_t)gv[u] * (int64_t)(int32_t)w[u];
+    const uint32_t v = redc((uint64_t)t, q.p, q.pinv);
+    tile[r32][8 * (r >> 2) + 4 * g + (r & 3)] = umin32(v, v - q.p);  // [column][row]
   }
   if (l < 32) colp[l] = n0 + l < N ? cp + (size_t)k * D : nullptr;
   __syncthreads();

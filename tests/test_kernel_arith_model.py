@@ -396,6 +396,15 @@ def test_packed_digits_by_offset_and_flip():
             assert got == balanced_digits(x, p), (x, p)
 
 
+def test_digit_group_sums_stay_within_the_epilogue_bound():
+    # seven weight groups of up to four int8 x int8 products per contraction
+    # index, at most 4096 indices (padded D): |G_u| <= 2^28, and the signed sum
+    # against residues below p < 2^32 / 3 stays inside 2^62 < p 2^32
+    bound = 4 * 4096 * 128 * 128
+    assert bound <= 1 << 28
+    assert 7 * bound * ((1 << 32) // 3) < 1 << 62 < PRIMES[-1] * (1 << 32)
+
+
 def test_digit_grouped_products_reconstruct_the_residue():
     rng = random.Random(8)
     for p in PRIMES:
@@ -415,6 +424,22 @@ def test_digit_grouped_products_reconstruct_the_residue():
             assert all(abs(g) < 1 << 31 for g in G)
             got = sum((g % p) * wu for g, wu in zip(G, w)) % p
             assert got == sum(a * b for a, b in zip(A, B)) % p
+            # the kernel's epilogue: signed sum against the Montgomery forms
+            # of 256^u, offset by p 2^32, one reduction, one subtraction
+            R = 1 << 32
+            wm = [(pow(256, u, p) * R) % p for u in range(7)]
+            t = sum(g * wu for g, wu in zip(G, wm))
+            assert abs(t) < 1 << 62
+            t += p * R
+            assert 0 <= t < 2 * p * R
+            pinv = (-pow(p, -1, R)) % R
+            m = ((t % R) * pinv) % R
+            u = t + m * p
+            assert u < 1 << 64 and u % R == 0
+            v = u >> 32
+            v = v - p if v >= p else v
+            v = v - p if v >= p else v
+            assert v == got
 
 
 def crt_model_mfma(residues, primes, Lc=None):
