@@ -711,7 +711,7 @@ __device__ __forceinline__ RgStep rg_fstep(uint32_t (&X)[C], uint32_t* __restric
 
 // Powers held in registers by the register-array kernel (fewer than EV_PW, to
 // leave room for X; longer rows take one more Horner chunk).
-constexpr int RG_PW = 16;
+constexpr int RG_PW = 24;
 
 // Returns false (on every active lane) when the block must be recomputed by
 // dev_eval_elim.  Needs 1 <= m, n and max(m, n) < C; LDS: (max(m, n) + 1)
