@@ -6,9 +6,13 @@
 //   k_transpose   exchange x and y in a limb rectangle (res_x, disc_x)
 //   k_reduce      (a) coefficients modulo each prime, Montgomery form
 //   k_eval_elim   (b)+(c) evaluate at x = a and take the univariate resultant
-//                 over F_p, one lane per (prime, point)
+//                 over F_p, one lane per (prime, point); k_eval_elim_rg24 and
+//                 _rg32 keep f's coefficient array in registers
 //   k_interp      (d) interpolation per prime, nodes a = 0..D-1
+//   k_interp_mfma (d) interpolation of a batch sharing the nodes, int8 matrix
+//                 cores (digit planes by k_yplanes, V^{-1} by k_vinv)
 //   k_invfact     table of 1/n! mod p (set-up)
+//   k_crt_mfma    (e) explicit CRT straight to limbs, int8 matrix cores
 //   k_mrc         (e) mixed-radix (Garner) digits per coefficient
 //   k_limbs_sum / k_limbs_carry   (e) digits -> two's-complement limbs
 //
