@@ -289,6 +289,40 @@ def test_shared_shape_batch_matrix_core_interpolation():
         assert zx.evaluate(res[i], 11) == resultant_at(*pairs[i], 11)
 
 
+def test_config2_full_batch_in_the_bench_configuration():
+    # the timed workload itself: 256 config-2 pairs as device-memory batches
+    # (plan reuse on), synchronous and with two batches in flight; pair 0
+    # equals the stored oracle value, every pair the single call, sampled
+    # pairs the oracle's determinant at nodes, every repeat the first run
+    pairs = [synth.config2_pair(s) for s in range(256)]
+    jobs = [("res", F, G, "y") for F, G in pairs]
+    say("config2 full batch", len(jobs))
+    br.set_plan_cache(True)
+    a, b = br.DeviceBatch(jobs), br.DeviceBatch(jobs)
+    a.run()
+    ref = a.results()
+    assert list(a.status) == [0] * len(jobs)
+    assert ref[0] == load("config2_res_0.txt")[1]
+    for i, (F, G) in enumerate(pairs):
+        assert ref[i] == br.resultant(F, G), i
+    for i in (1, 97, 255):
+        for x in (5, -3):
+            assert zx.evaluate(ref[i], x) == resultant_at(*pairs[i], x), (i, x)
+    for _ in range(3):
+        a.run()
+        assert a.results() == ref
+    prev = None
+    for k in range(6):
+        cur = (a, b)[k % 2]
+        cur.run_async()
+        if prev is not None:
+            prev.wait()
+            assert prev.results() == ref, k
+        prev = cur
+    prev.wait()
+    assert prev.results() == ref
+
+
 @pytest.mark.parametrize("schedule", ["staged", "fused"])
 def test_graph_replay_matches_eager(schedule):
     # batched calls replayed from captured HIP graphs: every replay, with eager
