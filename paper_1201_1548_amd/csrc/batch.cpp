@@ -735,10 +735,18 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     DEV(hipHostGetDevicePointer((void**)&hmap, h_in.p, 0));
     spec_got = (const int32_t*)(hmap + o_scan0);
   }
+  // the metadata block is uploaded by a kernel that reads it through the
+  // pinned block's device mapping (all its regions are whole words)
+  const uint32_t* meta_mapped = nullptr;
+  if (meta_end > meta_begin) {
+    uint8_t* m = nullptr;
+    DEV(hipHostGetDevicePointer((void**)&m, h_meta.p, 0));
+    meta_mapped = (const uint32_t*)m;
+  }
   auto seq = [&](bool run, SeqHash& sg) -> int {
-    sg.add(st, D0, meta_begin, meta_end, (const void*)h_meta.p);
+    sg.add(st, D0, meta_begin, meta_end, (const void*)meta_mapped);
     if (run && meta_end > meta_begin)
-      DEV(hipMemcpyAsync(D0 + meta_begin, h_meta.p, meta_end - meta_begin, hipMemcpyHostToDevice, st));
+      launch_upload(meta_mapped, (uint32_t*)(D0 + meta_begin), (long long)((meta_end - meta_begin) / 4), st);
     if (spec) {
       sg.add((const void*)spec_got, (const void*)d_image, scan_words);
       if (run)

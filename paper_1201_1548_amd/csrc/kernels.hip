@@ -1885,6 +1885,20 @@ __global__ __launch_bounds__(256) void k_stats_check(const int32_t* got, const i
   if (__ballot(diff) != 0ull && (threadIdx.x & 63) == 0) *flag = 1;
 }
 
+// Word copy from pinned host memory, read through its device mapping, to
+// device memory: the call's metadata upload as a kernel on the compute queue
+// (no hand-off to a copy engine between two kernels of the same call).
+__global__ __launch_bounds__(256) void k_upload(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
+                                                long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+void launch_upload(const uint32_t* src_mapped, uint32_t* dst, long long words, hipStream_t s) {
+  const long long blocks = std::min<long long>((words + 255) / 256, 256);
+  if (blocks > 0) hipLaunchKernelGGL(k_upload, dim3((unsigned)blocks), dim3(256), 0, s, src_mapped, dst, words);
+}
+
 void launch_stats_check(const int32_t* got, const int32_t* want, long long n, int* flag, hipStream_t s) {
   const long long blocks = std::min<long long>((n + 255) / 256, 1024);
   if (blocks > 0) hipLaunchKernelGGL(k_stats_check, dim3((unsigned)blocks), dim3(256), 0, s, got, want, n, flag);

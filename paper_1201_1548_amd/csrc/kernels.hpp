@@ -22,6 +22,9 @@ void launch_scan(const ScanTask* tasks, const int4* bmap, int nblocks, hipStream
 void launch_issue_rate(int kind, uint32_t* out, int blocks, int iters, hipStream_t s);
 // Sets *flag (not cleared here) when got[0..n) and want[0..n) differ.
 void launch_stats_check(const int32_t* got, const int32_t* want, long long n, int* flag, hipStream_t s);
+// dst[0..words) = src_mapped[0..words): src_mapped is the device mapping of
+// pinned host memory (hipHostGetDevicePointer).
+void launch_upload(const uint32_t* src_mapped, uint32_t* dst, long long words, hipStream_t s);
 void launch_transpose(const uint32_t* src, uint32_t* dst, int rows, int cols, int L, hipStream_t s);
 // Job launchers: starts[0..nj] hold the first block of each job (starts[nj] = nblocks).
 // Blocks per job: reduce ceil(Tf/64)+ceil(Tg/64); eval_elim P*ceil(D/64);
