@@ -241,13 +241,17 @@ const int8_t* vinv_device(Context* cx, int D, int P, hipStream_t st) {
   return d;
 }
 
+// The context lives until the process ends and is never destroyed: its device
+// buffers (pools, tables, cached graphs, the plan cache's statistics copy) are
+// not freed from a static destructor, which may run after the HIP runtime has
+// shut down.
 Context* context(int* err) {
-  static Context cx;
+  static Context* cx = new Context;
   static std::once_flag once;
   static int status = BIRES_OK;
-  std::call_once(once, [] { status = init_context(cx); });
+  std::call_once(once, [] { status = init_context(*cx); });
   *err = status;
-  return status == BIRES_OK ? &cx : nullptr;
+  return status == BIRES_OK ? cx : nullptr;
 }
 
 static int log2_bucket(long long v) {
