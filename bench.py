@@ -123,7 +123,7 @@ def cpu_baseline(pairs, D, budget_s=15.0):
         "unit": "resultants/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": "%d evaluation points R(a) of config-2 pairs by the oracle's integer Bareiss "
+        "sample": "%d evaluation points R(a) of the dense total-degree-20 pairs by the oracle's integer Bareiss "
                   "determinant of the specialised Sylvester matrix, %d processes; value = points/s / %d "
                   "points per resultant (interpolation not counted)" % (npts, cores, D),
     }
@@ -143,15 +143,15 @@ def _percentile(v, q):
     return v[i]
 
 
-def bench_config4(args):
-    """Config 4: 400 curves (total degree U{4..30}, bits U{8..64}), all pairs in
+def bench_arrangement(args):
+    """Arrangement: 400 curves (total degree U{4..30}, bits U{8..64}), all pairs in
     seeded groups of 20 (3800 resultants); one batched call vs one call per pair."""
     import torch
     import paper_1201_1548_amd as br
     from paper_1201_1548_amd import synth
     from oracle.resultant import resultant_y
 
-    curves, pairs = synth.config4_arrangement(0)
+    curves, pairs = synth.arrangement_batch(0)
     jobs = [("res", curves[i], curves[j], "y") for i, j in pairs]
     torch.cuda.set_device(0)
     batch = br.DeviceBatch(jobs)
@@ -183,11 +183,11 @@ def bench_config4(args):
     exact_oracle = all(res[k] == resultant_y(curves[pairs[k][0]], curves[pairs[k][1]]) for k in small)
     n = len(jobs)
     return {
-        "metric": "arrangement pair resultants/sec (config 4), batched vs plain",
+        "metric": "arrangement pair resultants/sec, batched vs plain",
         "value": round(n * args.steps / dt, 2), "unit": "resultants/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "config 4: 400 dense curves, total degree U{4..30}, coefficient bits U{8..64}, "
+        "config": {"workload": "arrangement: 400 dense curves, total degree U{4..30}, coefficient bits U{8..64}, "
                                "all pairs within 20 seeded groups of 20 (3800 res_y)", "pairs": n},
         "plain": {"value": round(n / dtp, 2), "unit": "resultants/s", "ms_per_pair": round(dtp / n * 1e3, 3)},
         "batched_over_plain": round((n * args.steps / dt) / (n / dtp), 2),
@@ -197,8 +197,8 @@ def bench_config4(args):
     }
 
 
-def bench_config5(args):
-    """Config 5: Poisson stream of resultant/discriminant requests (total degree
+def bench_serving(args):
+    """Serving: Poisson stream of resultant/discriminant requests (total degree
     log-uniform in [5, 64], bits U{10..128}); the continuous-batching server vs
     a plain server that runs one library call per request in arrival order."""
     import threading
@@ -206,7 +206,7 @@ def bench_config5(args):
     from paper_1201_1548_amd import synth
 
     nreq = args.requests
-    probe = synth.config5_requests(0, n=min(40, nreq), qps=1.0)
+    probe = synth.poisson_requests(0, n=min(40, nreq), qps=1.0)
 
     def plain_call(r):
         return br.discriminant(r["f"]) if r["kind"] == "disc" else br.resultant(r["f"], r["g"])
@@ -217,7 +217,7 @@ def bench_config5(args):
         plain_call(r)
     service = (time.perf_counter() - t0) / len(probe)
     qps = args.qps or 0.7 / service
-    reqs = synth.config5_requests(0, n=nreq, qps=qps)
+    reqs = synth.poisson_requests(0, n=nreq, qps=qps)
 
     def run_plain():
         out, lat = [None] * nreq, [0.0] * nreq
@@ -257,11 +257,11 @@ def bench_config5(args):
     out_s, lat_s, tot_s = run_server()
     out_p, lat_p, tot_p = run_plain()
     return {
-        "metric": "serving: resultant/discriminant requests/sec with p50/p99 latency (config 5)",
+        "metric": "serving: resultant/discriminant requests/sec with p50/p99 latency",
         "value": round(nreq / tot_s, 2), "unit": "requests/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": round(tot_s * 1e3, 1), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "config 5: Poisson arrivals, total degree round(exp(U[ln5, ln64])), "
+        "config": {"workload": "serving: Poisson arrivals, total degree round(exp(U[ln5, ln64])), "
                                "coefficient bits U{10..128}, resultant or discriminant 50/50",
                    "requests": nreq, "qps": round(qps, 2), "hbm_budget_gib": args.budget_gib,
                    "slots": args.slots},
@@ -274,8 +274,8 @@ def bench_config5(args):
     }
 
 
-def bench_config3(args):
-    """Config 3: res(f, f_y; y) of a dense total-degree-40 curve (16-bit
+def bench_curve40(args):
+    """Curve analysis: res(f, f_y; y) of a dense total-degree-40 curve (16-bit
     coefficients) and gcd(R, R'); per-call wall time."""
     import torch
     import paper_1201_1548_amd as br
@@ -284,9 +284,9 @@ def bench_config3(args):
 
     torch.cuda.set_device(0)
     out = {}
-    for name, F in (("dense", synth.config3_dense(0)),
-                    ("g2_hk", synth.config3_singular(0)),
-                    ("g2_hk2", synth.config3_singular(0, square_k=True, dk=10))):
+    for name, F in (("dense", synth.curve_deg40(0)),
+                    ("g2_hk", synth.singular_curve_deg40(0)),
+                    ("g2_hk2", synth.singular_curve_deg40(0, square_k=True, dk=10))):
         br.discriminant(F)
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -301,11 +301,11 @@ def bench_config3(args):
         out[name] = {"disc_ms": round(td * 1e3, 2), "deg_R": len(R) - 1, "gcd_ms": round(tg * 1e3, 2),
                      "deg_gcd": len(h) - 1}
     return {
-        "metric": "curve-analysis resultant res(f, f_y; y) and gcd(R, R') wall time (config 3)",
+        "metric": "curve-analysis resultant res(f, f_y; y) and gcd(R, R') wall time (degree-40 curves)",
         "value": round(1e3 / out["dense"]["disc_ms"], 2), "unit": "discriminants/s", "n_gpus": 1,
         "steps": args.steps, "warmup": 1, "ms_per_step": out["dense"]["disc_ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "config 3: dense total degree 40, 16-bit coefficients; g^2 + h k with dense "
+        "config": {"workload": "curve analysis: dense total degree 40, 16-bit coefficients; g^2 + h k with dense "
                                "degree-20 factors, 8-bit; g^2 + h k^2 (k degree 10)"},
         "cases": out,
     }
@@ -355,7 +355,7 @@ def main():
                     help="skip the leg with two batches in flight (the headline is then the synchronous leg)")
     ap.add_argument("--eval-kernel", default="auto", choices=["auto", "lds"],
                     help="evaluation + elimination kernel of the staged schedule")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5", "copy", "rates"])
+    ap.add_argument("--workload", default="deg20", choices=["deg20", "curve40", "arrangement", "serving", "copy", "rates"])
     ap.add_argument("--schedule", default="auto", choices=["auto", "staged", "fused"])
     ap.add_argument("--requests", type=int, default=300)
     ap.add_argument("--qps", type=float, default=0.0)
@@ -363,11 +363,11 @@ def main():
     ap.add_argument("--slots", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (each job runs on one "
-              "device; see the sharding notes in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (each job runs on one "
+              "device; a batch would shard by jobs, a large job by primes). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
-    if args.workload != "config2":
-        fn = {"config3": bench_config3, "config4": bench_config4, "config5": bench_config5,
+    if args.workload != "deg20":
+        fn = {"curve40": bench_curve40, "arrangement": bench_arrangement, "serving": bench_serving,
               "copy": bench_copy, "rates": bench_rates}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
@@ -376,7 +376,7 @@ def main():
     from paper_1201_1548_amd import synth
 
     n = args.pairs
-    pairs = [synth.config2_pair(s) for s in range(n)]
+    pairs = [synth.pair_deg20(s) for s in range(n)]
     D, P, _ = br.plan(pairs[0][0], pairs[0][1])
     # the CPU leg runs first, in forked workers, before anything touches the GPU
     cpu = None if args.no_cpu else cpu_baseline(pairs, D)
@@ -396,11 +396,11 @@ def main():
     batch.run()
     torch.cuda.synchronize()
     res_batch = batch.results()
-    golden = os.path.join(ROOT, "tests", "golden", "config2_res_0.txt")
+    golden = os.path.join(ROOT, "tests", "golden", "deg20_res_0.txt")
     exact_golden = None
     if os.path.exists(golden):
         from tests.golden.make_golden import load
-        exact_golden = load("config2_res_0.txt")[1] == res_batch[0]
+        exact_golden = load("deg20_res_0.txt")[1] == res_batch[0]
 
     for _ in range(args.warmup):
         batch.run()
@@ -497,7 +497,7 @@ def main():
         "peak": round(INT32_PEAK_TOPS, 1),
         "unit": "T int32-op/s",
         "frac": round(achieved / INT32_PEAK_TOPS, 4),
-        "traffic": stored_traffic("k_eval_elim_rg24", "config2_batch%d" % n),
+        "traffic": stored_traffic("k_eval_elim_rg24", "deg20_batch%d" % n),
         "traffic_unit": "bytes per launch",
         "kernel": "k_eval_elim_rg24 (+ k_eval_elim_fb)",
         "kernel_ms": round(avg_ms, 4),
@@ -518,7 +518,7 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {
-            "workload": "config 2 batched: %d pairs of dense total-degree-20 polynomials in Z[x,y], "
+            "workload": "batch of %d pairs of dense total-degree-20 polynomials in Z[x,y], "
                         "uniform 32-bit signed coefficients, res_y" % n,
             "pairs": n, "tdeg": 20, "coef_bits": 32, "points": D, "primes": P,
         },

@@ -90,28 +90,28 @@ def _biadd(F, G):
 
 
 # ----------------------------------------------------------------------------
-# the five workloads (seed = config index * 1000 + instance)
+# the five workloads (seed = workload index * 1000 + instance)
 
-def config1_pair(instance=0):
+def pair_deg6(instance=0):
     """Dense total degree 6, coefficients uniform in [-2^10, 2^10]."""
     rng = rng_for(1000 + instance)
     draw = lambda n: inclusive_range(rng, -(1 << 10), 1 << 10, n)
     return dense_bivariate(rng, 6, draw), dense_bivariate(rng, 6, draw)
 
 
-def config2_pair(instance=0):
+def pair_deg20(instance=0):
     """Dense total degree 20, uniform 32-bit signed coefficients."""
     rng = rng_for(2000 + instance)
     return dense_signed(rng, 20, 32), dense_signed(rng, 20, 32)
 
 
-def config3_dense(instance=0, tdeg=40, bits=16):
+def curve_deg40(instance=0, tdeg=40, bits=16):
     """Curve for res(f, f_y; y): dense total degree 40, 16-bit signed coefficients."""
     rng = rng_for(3000 + instance)
     return dense_signed(rng, tdeg, bits)
 
 
-def config3_singular(instance=0, dg=20, dh=20, dk=20, bits=8, square_k=False):
+def singular_curve_deg40(instance=0, dg=20, dh=20, dk=20, bits=8, square_k=False):
     """f = g^2 + h*k (or g^2 + h*k^2 with square_k) from dense g, h, k."""
     rng = rng_for(3500 + instance)
     g = dense_signed(rng, dg, bits)
@@ -121,7 +121,7 @@ def config3_singular(instance=0, dg=20, dh=20, dk=20, bits=8, square_k=False):
     return _biadd(_bimul(g, g), hk)
 
 
-def config4_arrangement(instance=0, n_curves=400, group=20, deg_range=(4, 30), bits_range=(8, 64)):
+def arrangement_batch(instance=0, n_curves=400, group=20, deg_range=(4, 30), bits_range=(8, 64)):
     """400 curves (total degree U{4..30}, bits U{8..64}); all pairs inside
     seeded groups of 20.  Returns (curves, pairs) with pairs as index tuples."""
     rng = rng_for(4000 + instance)
@@ -138,7 +138,7 @@ def config4_arrangement(instance=0, n_curves=400, group=20, deg_range=(4, 30), b
     return curves, pairs
 
 
-def config5_requests(instance=0, n=2000, qps=100.0, deg_range=(5, 64), bits_range=(10, 128), p_disc=0.5):
+def poisson_requests(instance=0, n=2000, qps=100.0, deg_range=(5, 64), bits_range=(10, 128), p_disc=0.5):
     """Poisson arrivals.  Each request: kind ('res' or 'disc'), shared total
     degree round(exp(U[ln 5, ln 64])), coefficient bits U{10..128}, f and g."""
     rng = rng_for(5000 + instance)

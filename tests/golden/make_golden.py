@@ -1,6 +1,6 @@
 """Write the stored expected resultants under tests/golden/ from the oracle alone.
 
-Usage:  python tests/golden/make_golden.py [config1|config2|all]
+Usage:  python tests/golden/make_golden.py [deg6|deg20|all]
 
 Each file holds res(f, g; y) (the Sylvester determinant of Section 2,
 "Resultants" paragraph) for one seeded synthetic pair, computed by
@@ -68,16 +68,15 @@ def load(name):
 
 
 def main(which):
-    if which in ("config1", "all"):
+    if which in ("deg6", "all"):
         for inst in range(4):
-            F, G = synth.config1_pair(inst)
-            write("config1_res_%d.txt" % inst, F, G,
-                  "config 1: dense total degree 6, coefficients uniform in [-2^10, 2^10], instance %d" % inst)
-    if which in ("config2", "all"):
-        F, G = synth.config2_pair(0)
-        write("config2_res_0.txt", F, G,
-              "config 2: dense total degree 20, uniform 32-bit signed coefficients, instance 0")
+            F, G = synth.pair_deg6(inst)
+            write("deg6_res_%d.txt" % inst, F, G,
+                  "dense total degree 6, coefficients uniform in [-2^10, 2^10], instance %d" % inst)
+    if which in ("deg20", "all"):
+        F, G = synth.pair_deg20(0)
+        write("deg20_res_0.txt", F, G, "dense total degree 20, uniform 32-bit signed coefficients, instance 0")
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "config1")
+    main(sys.argv[1] if len(sys.argv) > 1 else "deg6")

@@ -20,20 +20,20 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 @pytest.mark.parametrize("inst", range(4))
-def test_config1_golden(inst):
-    F, G = synth.config1_pair(inst)
-    digest, R = load("config1_res_%d.txt" % inst)
+def test_deg6_golden(inst):
+    F, G = synth.pair_deg6(inst)
+    digest, R = load("deg6_res_%d.txt" % inst)
     assert digest == input_digest(F, G)
     assert R == resultant_y(F, G)
     for a in (-2, 0, 5):
         assert zx.evaluate(R, a) == resultant_at(F, G, a)
 
 
-@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "config2_res_0.txt")),
-                    reason="config-2 golden file not generated")
-def test_config2_golden_spot_values():
-    F, G = synth.config2_pair(0)
-    digest, R = load("config2_res_0.txt")
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "deg20_res_0.txt")),
+                    reason="degree-20 golden file not generated")
+def test_deg20_golden_spot_values():
+    F, G = synth.pair_deg20(0)
+    digest, R = load("deg20_res_0.txt")
     assert digest == input_digest(F, G)
     assert len(R) - 1 <= 400
     for a in (0, 1, -1, 3):

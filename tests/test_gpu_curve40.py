@@ -1,4 +1,4 @@
-"""Config 3 (curve analysis): R = res(f, f_y; y) for dense total-degree-40
+"""Curve analysis: R = res(f, f_y; y) for dense total-degree-40
 curves with 16-bit coefficients, and gcd(R, R') in Z[x].
 
 At full size the oracle cannot form R by Bareiss in test time, so R is checked
@@ -45,31 +45,31 @@ def check_gcd(R, h):
 
 
 def test_small_curve_full_oracle():
-    F = synth.config3_dense(7, tdeg=7, bits=16)
-    say("config3-shaped small curve")
+    F = synth.curve_deg40(7, tdeg=7, bits=16)
+    say("small curve shaped like the degree-40 ones")
     R = br.discriminant(F)
     assert R == discriminant_y(F)
     dR = zx.derivative(R)
     assert br.gcd(R, dR) == gcd_zx(R, dR)
 
 
-def test_config3_dense_deg40():
-    F = synth.config3_dense(0)
-    say("config3 dense total degree 40: discriminant")
+def test_curve_deg40_dense():
+    F = synth.curve_deg40(0)
+    say("dense total degree 40: discriminant")
     R = br.discriminant(F)
     assert len(R) - 1 <= 40 * 39
     rng = random.Random(3)
     check_R_samples(F, R, [0, 1, -2] + [rng.randint(-10**6, 10**6) for _ in range(3)])
-    say("config3 dense: gcd(R, R')")
+    say("dense total degree 40: gcd(R, R')")
     h = br.gcd(R, zx.derivative(R))
     say("deg gcd =", len(h) - 1)
     check_gcd(R, h)
 
 
 @pytest.mark.parametrize("square_k", [False, True])
-def test_config3_singular_variants(square_k):
-    F = synth.config3_singular(0, square_k=square_k, dk=20 if not square_k else 10)
-    say("config3 g^2 + h k%s" % ("^2" if square_k else ""), "ydeg", len(F) - 1)
+def test_curve_deg40_singular_variants(square_k):
+    F = synth.singular_curve_deg40(0, square_k=square_k, dk=20 if not square_k else 10)
+    say("g^2 + h k%s" % ("^2" if square_k else ""), "ydeg", len(F) - 1)
     R = br.discriminant(F)
     rng = random.Random(4)
     check_R_samples(F, R, [0, 1] + [rng.randint(-10**5, 10**5) for _ in range(2)])

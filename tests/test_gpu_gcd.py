@@ -73,7 +73,7 @@ def test_high_power_common_factor():
 
 def test_discriminant_gcd_with_derivative():
     # f = g^2 + h k^2 is singular where g = k = 0, so R = res(f, f_y; y) has repeated roots
-    f = synth.config3_singular(0, dg=3, dh=2, dk=2, bits=4, square_k=True)
+    f = synth.singular_curve_deg40(0, dg=3, dh=2, dk=2, bits=4, square_k=True)
     say("gcd(R, R') of a singular curve")
     R = br.discriminant(f)
     assert R == discriminant_y(f)

@@ -28,10 +28,10 @@ def say(*a):
     print(*a, flush=True)
 
 
-def test_stage_values_config1():
-    F, G = synth.config1_pair(0)
-    say("stage values config1 instance 0")
-    _, R = load("config1_res_0.txt")
+def test_stage_values_deg6():
+    F, G = synth.pair_deg6(0)
+    say("stage values deg6 instance 0")
+    _, R = load("deg6_res_0.txt")
     ps, vals = br.debug_values(F, G)
     assert vals.shape == (len(ps), 37)
     for k, p in enumerate(ps):
@@ -40,10 +40,10 @@ def test_stage_values_config1():
 
 
 @pytest.mark.parametrize("inst", range(4))
-def test_config1_bit_exact(inst):
-    F, G = synth.config1_pair(inst)
-    say("config1 instance", inst)
-    digest, R = load("config1_res_%d.txt" % inst)
+def test_deg6_bit_exact(inst):
+    F, G = synth.pair_deg6(inst)
+    say("deg6 instance", inst)
+    digest, R = load("deg6_res_%d.txt" % inst)
     assert digest == input_digest(F, G)
     assert br.resultant(F, G) == R
 
@@ -141,7 +141,7 @@ def test_batch_equals_single_and_oracle():
         a, b, c, d, bits = SHAPES[i]
         F, G = synth.random_rect(500 + i, a, b, c, d, bits)
         jobs.append(("res", F, G, "y"))
-    F, G = synth.config1_pair(1)
+    F, G = synth.pair_deg6(1)
     jobs.append(("res", F, G, "y"))
     jobs.append(("res", F, G, "x"))
     jobs.append(("disc", F, None, "y"))
@@ -161,14 +161,14 @@ def test_batch_equals_single_and_oracle():
 
 
 def test_batch_reports_per_job_errors():
-    F, G = synth.config1_pair(0)
+    F, G = synth.pair_deg6(0)
     res, st = br.resultant_batch([("res", F, G, "y"), ("disc", [[1, 2]], None, "y"), ("res", G, F, "y")])
     assert st[0] == 0 and st[2] == 0 and st[1] == -1
     assert res[0] == resultant_y(F, G) and res[2] == resultant_y(G, F)
 
 
 def test_device_memory_batch():
-    F, G = synth.config1_pair(2)
+    F, G = synth.pair_deg6(2)
     H, K = synth.random_rect(600, 3, 4, 4, 2, 50)
     jobs = [("res", F, G, "y"), ("res", H, K, "x"), ("disc", H, None, "y"), ("res", [[5]], [[1, 1]], "y")]
     say("device-memory batch")
@@ -183,21 +183,21 @@ def test_device_memory_batch():
     assert b.results() == out
 
 
-def test_config2_spot_values():
-    F, G = synth.config2_pair(0)
-    say("config2 spot values")
+def test_deg20_spot_values():
+    F, G = synth.pair_deg20(0)
+    say("deg20 spot values")
     R = br.resultant(F, G)
     assert len(R) - 1 <= 400
     for a in (0, 1, -1, 2, 12345):
         assert zx.evaluate(R, a) == resultant_at(F, G, a), a
 
 
-@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "config2_res_0.txt")),
-                    reason="config-2 golden file not generated")
-def test_config2_golden_bit_exact():
-    F, G = synth.config2_pair(0)
-    say("config2 golden")
-    digest, R = load("config2_res_0.txt")
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "deg20_res_0.txt")),
+                    reason="degree-20 golden file not generated")
+def test_deg20_golden_bit_exact():
+    F, G = synth.pair_deg20(0)
+    say("deg20 golden")
+    digest, R = load("deg20_res_0.txt")
     assert digest == input_digest(F, G)
     assert br.resultant(F, G) == R
 
@@ -209,9 +209,9 @@ def _mixed_jobs():
         F, G = synth.random_rect(700 + i, a, b, c, d, bits)
         jobs.append(("res", F, G, "y" if i % 3 else "x"))
     for i in range(24):
-        F, G = synth.config1_pair(i % 4)
+        F, G = synth.pair_deg6(i % 4)
         jobs.append(("res", F, G, "y"))
-    F, G = synth.config2_pair(3)
+    F, G = synth.pair_deg20(3)
     jobs.append(("res", F, G, "y"))
     H, _ = synth.random_rect(800, 5, 3, 1, 1, 40)
     jobs += [("disc", H, None, "y"), ("res", [[0]], G, "y"), ("res", [[3, 1]], [[7, 2]], "y"),
@@ -242,7 +242,7 @@ def test_fused_schedule_matches_staged(schedule):
 
 
 def test_autotune_keeps_results():
-    jobs = [("res",) + synth.config1_pair(i % 4) + ("y",) for i in range(16)]
+    jobs = [("res",) + synth.pair_deg6(i % 4) + ("y",) for i in range(16)]
     say("autotune")
     b = br.DeviceBatch(jobs)
     choice = b.autotune(reps=1)
@@ -257,52 +257,52 @@ def test_autotune_keeps_results():
 def test_large_batch_lane_garner_path():
     # >= 16384 output coefficients in one batch selects the lane-per-coefficient
     # Garner + limb kernel; single calls take the wave-per-coefficient kernels
-    jobs = [("res",) + synth.config2_pair(i) + ("y",) for i in range(40)]
-    jobs += [("res",) + synth.config1_pair(i % 4) + ("y",) for i in range(10)]
+    jobs = [("res",) + synth.pair_deg20(i) + ("y",) for i in range(40)]
+    jobs += [("res",) + synth.pair_deg6(i % 4) + ("y",) for i in range(10)]
     say("large batch", len(jobs))
     res, st = br.resultant_batch(jobs)
     assert st == [0] * len(jobs)
-    _, R0 = load("config2_res_0.txt")
+    _, R0 = load("deg20_res_0.txt")
     assert res[0] == R0
     for i in range(10):
-        assert res[40 + i] == load("config1_res_%d.txt" % (i % 4))[1]
+        assert res[40 + i] == load("deg6_res_%d.txt" % (i % 4))[1]
     for i in (1, 17, 39):
-        assert res[i] == br.resultant(*synth.config2_pair(i))
+        assert res[i] == br.resultant(*synth.pair_deg20(i))
         for a in (3, -7):
-            assert zx.evaluate(res[i], a) == resultant_at(*synth.config2_pair(i), a)
+            assert zx.evaluate(res[i], a) == resultant_at(*synth.pair_deg20(i), a)
 
 
 def test_shared_shape_batch_matrix_core_interpolation():
     # >= 32 jobs with the same point and prime counts interpolate as int8
     # matrix-core products with the inverse Vandermonde matrix; single calls
     # use the per-job interpolation kernel
-    pairs = [synth.config2_pair(i) for i in range(36)]
+    pairs = [synth.pair_deg20(i) for i in range(36)]
     D, P, _ = br.plan(*pairs[0])
     assert all(br.plan(F, G)[:2] == (D, P) for F, G in pairs)
     say("shared-shape batch", len(pairs), D, P)
     res, st = br.resultant_batch([("res", F, G, "y") for F, G in pairs])
     assert st == [0] * len(pairs)
-    assert res[0] == load("config2_res_0.txt")[1]
+    assert res[0] == load("deg20_res_0.txt")[1]
     for i, (F, G) in enumerate(pairs):
         assert res[i] == br.resultant(F, G), i
     for i in (5, 35):
         assert zx.evaluate(res[i], 11) == resultant_at(*pairs[i], 11)
 
 
-def test_config2_full_batch_in_the_bench_configuration():
-    # the timed workload itself: 256 config-2 pairs as device-memory batches
+def test_deg20_full_batch_in_the_bench_configuration():
+    # the timed workload itself: 256 dense total-degree-20 pairs as device-memory batches
     # (plan reuse on), synchronous and with two batches in flight; pair 0
     # equals the stored oracle value, every pair the single call, sampled
     # pairs the oracle's determinant at nodes, every repeat the first run
-    pairs = [synth.config2_pair(s) for s in range(256)]
+    pairs = [synth.pair_deg20(s) for s in range(256)]
     jobs = [("res", F, G, "y") for F, G in pairs]
-    say("config2 full batch", len(jobs))
+    say("deg20 full batch", len(jobs))
     br.set_plan_cache(True)
     a, b = br.DeviceBatch(jobs), br.DeviceBatch(jobs)
     a.run()
     ref = a.results()
     assert list(a.status) == [0] * len(jobs)
-    assert ref[0] == load("config2_res_0.txt")[1]
+    assert ref[0] == load("deg20_res_0.txt")[1]
     for i, (F, G) in enumerate(pairs):
         assert ref[i] == br.resultant(F, G), i
     for i in (1, 97, 255):
@@ -336,7 +336,7 @@ def test_graph_replay_matches_eager(schedule):
         b = br.DeviceBatch(jobs)
         b.run()
         eager = b.results()
-        other = br.DeviceBatch([("res",) + synth.config1_pair(i % 4) + ("y",) for i in range(6)])
+        other = br.DeviceBatch([("res",) + synth.pair_deg6(i % 4) + ("y",) for i in range(6)])
         other.run()
         eager_other = other.results()
         host_ref = br.resultant_batch(jobs)
@@ -369,7 +369,7 @@ def test_register_and_lds_evaluation_kernels_agree():
     # coefficients vanish at some points or whose remainder sequences are not
     # normal (every block of those falls back)
     jobs = [j for j in _mixed_jobs() if not (j[0] == "disc" and len(j[1]) < 2)]
-    jobs += [("res",) + synth.config2_pair(i) + ("y",) for i in range(3)]
+    jobs += [("res",) + synth.pair_deg20(i) + ("y",) for i in range(3)]
     # lc_y(f) = x - 5 vanishes at a = 5; in the second pair lc_y(g) = x^2
     # vanishes at a = 0 and the first remainder's y-coefficient
     # x^3 - 3x - 2 = (x + 1)^2 (x - 2) at a = 2
@@ -397,7 +397,7 @@ def test_async_batches_overlap_and_match():
     # stream still busy writing the inputs when the batch is queued
     import torch
     jobs_a = [j for j in _mixed_jobs() if not (j[0] == "disc" and len(j[1]) < 2)]
-    jobs_b = [("res",) + synth.config1_pair(i % 4) + ("y",) for i in range(20)]
+    jobs_b = [("res",) + synth.pair_deg6(i % 4) + ("y",) for i in range(20)]
     say("async batches", len(jobs_a), len(jobs_b))
     a, b = br.DeviceBatch(jobs_a), br.DeviceBatch(jobs_b)
     a.run()
@@ -438,12 +438,12 @@ def test_plan_reuse_is_checked_on_the_device():
     # row statistics stay the same keeps them (and its new results), one whose
     # statistics change is caught by the device check and rerun
     import torch
-    pairs = [synth.config1_pair(i % 4) for i in range(12)] + [synth.config2_pair(5)]
+    pairs = [synth.pair_deg6(i % 4) for i in range(12)] + [synth.pair_deg20(5)]
     jobs = [("res", F, G, "y") for F, G in pairs]
     say("plan reuse", len(jobs))
     br.set_plan_cache(True)
     b = br.DeviceBatch(jobs)
-    ref = [load("config1_res_%d.txt" % (i % 4))[1] for i in range(12)] + [br.resultant(*pairs[-1])]
+    ref = [load("deg6_res_%d.txt" % (i % 4))[1] for i in range(12)] + [br.resultant(*pairs[-1])]
     h0, m0 = br.plan_cache_stats()
     for _ in range(4):
         b.run()
@@ -484,12 +484,12 @@ def test_plan_reuse_with_alternating_batches_in_flight():
     # both reuse the plans (addresses are not part of the key); a statistics
     # change in one of them while the other is in flight is caught and rerun
     import torch
-    pairs = [synth.config1_pair(i % 4) for i in range(12)] + [synth.config2_pair(5)]
+    pairs = [synth.pair_deg6(i % 4) for i in range(12)] + [synth.pair_deg20(5)]
     jobs = [("res", F, G, "y") for F, G in pairs]
     say("alternating plan reuse", len(jobs))
     br.set_plan_cache(True)
     a, b = br.DeviceBatch(jobs), br.DeviceBatch(jobs)
-    ref = [load("config1_res_%d.txt" % (i % 4))[1] for i in range(12)] + [br.resultant(*pairs[-1])]
+    ref = [load("deg6_res_%d.txt" % (i % 4))[1] for i in range(12)] + [br.resultant(*pairs[-1])]
     for x in (a, b):
         x.run()
         assert x.results() == ref
@@ -532,7 +532,7 @@ def test_evaluation_kernel_capacity_boundaries(mn):
     # calls agree, and the result matches the oracle's determinant at nodes
     m, n = mn
     F, G = synth.random_rect(900 + 37 * m + n, m, 2, n, 1, 20)
-    jobs = [("res", F, G, "y")] * 2 + [("res",) + synth.config1_pair(1) + ("y",)]
+    jobs = [("res", F, G, "y")] * 2 + [("res",) + synth.pair_deg6(1) + ("y",)]
     say("capacity boundary", m, n)
     try:
         br.set_eval_kernel("lds")

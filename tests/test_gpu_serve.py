@@ -68,7 +68,7 @@ def test_concurrent_submitters():
 
 
 def test_budget_admission():
-    F, G = synth.config1_pair(0)
+    F, G = synth.pair_deg6(0)
     say("budget admission")
     # a budget that holds one job at a time still completes every request, in order
     with br.Server(hbm_budget_bytes=3 << 20, max_slots=1) as srv:

@@ -69,8 +69,8 @@ def _check_plan(F, G, R, kind="res", var="y"):
 
 
 @pytest.mark.parametrize("inst", range(3))
-def test_plan_bounds_config1(inst):
-    F, G = synth.config1_pair(inst)
+def test_plan_bounds_deg6(inst):
+    F, G = synth.pair_deg6(inst)
     D, P = _check_plan(F, G, resultant_y(F, G))
     assert D == 37
 
@@ -83,8 +83,8 @@ def test_plan_bounds_random_shapes(seed):
     _check_plan(F, None, discriminant_y(F), kind="disc")
 
 
-def test_plan_config2_prime_count():
-    F, G = synth.config2_pair(0)
+def test_plan_deg20_prime_count():
+    F, G = synth.pair_deg20(0)
     D, P, log2B = br.plan(F, G)
     assert D == 401
     assert 40 <= P <= 60

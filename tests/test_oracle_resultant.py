@@ -62,8 +62,8 @@ def test_matches_sympy_resultant(seed):
 
 
 @pytest.mark.parametrize("seed", range(4))
-def test_matches_sympy_on_config1_shape(seed):
-    F, G = synth.config1_pair(seed)
+def test_matches_sympy_on_deg6_shape(seed):
+    F, G = synth.pair_deg6(seed)
     F = [r[:4] for r in F[:4]]  # tdeg-6 rows cut to a 4x4 block keeps sympy fast
     G = [r[:4] for r in G[:4]]
     assert resultant_y(F, G) == sympy_res_y(F, G)
@@ -212,7 +212,7 @@ def _det_fraction(M):
 
 @pytest.mark.parametrize("seed", range(3))
 def test_evaluation_homomorphism(seed):
-    F, G = synth.config1_pair(seed)
+    F, G = synth.pair_deg6(seed)
     R = resultant_y(F, G)
     for a in (-3, 0, 1, 7, 123456789):
         fa = [zx.evaluate(r, a) for r in F]
@@ -270,8 +270,8 @@ def test_degree_bounds(seed):
     assert zx.deg(R) <= n * tf + m * tg - m * n
 
 
-def test_config1_dense_degree_is_bezout():
-    F, G = synth.config1_pair(0)
+def test_deg6_dense_degree_is_bezout():
+    F, G = synth.pair_deg6(0)
     assert zx.deg(resultant_y(F, G)) == 36
 
 
