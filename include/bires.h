@@ -133,6 +133,22 @@ int bires_gcd_bounds(const bires_upoly *a, const bires_upoly *b, int32_t *max_de
  * Inputs are read-only (bires_upoly.c is not written). */
 int bires_gcd(const bires_upoly *a, const bires_upoly *b, bires_upoly *out, int mem, void *stream);
 
+/* Square-free decomposition of r in Z[x] by Yun's algorithm, each step one
+ * modular gcd with its exact cofactors (the gcd of Section 5.1; the
+ * decomposition is the next step of the curve analysis, whose projection
+ * factors the resultant into square-free parts):
+ *     r = u * a_1 * a_2^2 * ... * a_k^k,
+ * u the signed content of r (degree 0; the zero polynomial when r = 0), each
+ * a_i primitive with positive leading coefficient, square-free and coprime to
+ * the others (a_i = 1 when r has no factor of multiplicity i), a_k of degree
+ * >= 1; k = 0 for constant r.  *count receives k; factors[0..k) receive a_1..a_k
+ * (caller-allocated, at most max_factors; k <= deg r).  BIRES_EBUFSIZE when k
+ * exceeds max_factors or an output is too small: the needed degree and limbs
+ * are written back into that descriptor (sizes of the others are kept), and
+ * the call can be repeated.  mem: where the buffers of r, unit and factors live. */
+int bires_squarefree(const bires_upoly *r, bires_upoly *unit, bires_upoly *factors, int32_t max_factors,
+                     int32_t *count, int mem, void *stream);
+
 /* n independent jobs in one batched launch sequence.  kind[i] is a
  * BIRES_KIND_*; var[i] a BIRES_VAR_*; g[i] is ignored for discriminants.
  * status[i] receives the per-job code; the return value is BIRES_OK when

@@ -26,6 +26,7 @@ ERRORS = {
     -1: "EINVAL", -2: "EBUFSIZE", -3: "ENOMEM", -4: "ETOOBIG",
     -5: "EDEVICE", -6: "ECHECK", -7: "ENOTFOUND", -8: "ETIMEOUT",
 }
+E_BUFSIZE = -2
 
 
 class BiresError(RuntimeError):
@@ -59,6 +60,8 @@ _SIGS = {
                           ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "bires_gcd": ([ctypes.POINTER(Upoly), ctypes.POINTER(Upoly), ctypes.POINTER(Upoly), ctypes.c_int,
                    ctypes.c_void_p], ctypes.c_int),
+    "bires_squarefree": ([ctypes.POINTER(Upoly), ctypes.POINTER(Upoly), ctypes.POINTER(Upoly), ctypes.c_int32,
+                          ctypes.POINTER(ctypes.c_int32), ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "bires_resultant_batch": ([ctypes.c_int, ctypes.POINTER(Bipoly), ctypes.POINTER(Bipoly),
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(Upoly), ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
@@ -274,6 +277,38 @@ def gcd(a, b, stream=None):
     _check(lib().bires_gcd(ctypes.byref(ad), ctypes.byref(bd), ctypes.byref(od), MEM_HOST, _stream(stream)),
            "bires_gcd")
     return limbs_to_ints(out[: od.degree + 1])
+
+
+def squarefree(r, stream=None):
+    """Square-free decomposition (bires_squarefree): returns (u, [a_1, ..., a_k])
+    with r = u * a_1 * a_2^2 * ... * a_k^k (host-memory call; the output sizes
+    are grown and the call repeated when the library reports them too small)."""
+    ra, rd = _upoly_in(r)
+    deg = max(len(r) - 1, 0)
+    cap_deg, cap_L = deg, int(ra.shape[1]) + 2
+    nmax = max(deg, 1)
+    degs, Ls = [cap_deg] * nmax, [cap_L] * nmax
+    udeg, uL = 0, cap_L
+    for _ in range(4):
+        ubuf = np.zeros((udeg + 1, uL), dtype=np.uint32)
+        ud = Upoly(udeg, uL, ubuf.ctypes.data)
+        bufs = [np.zeros((degs[i] + 1, Ls[i]), dtype=np.uint32) for i in range(nmax)]
+        fds = (Upoly * nmax)()
+        for i in range(nmax):
+            fds[i] = Upoly(degs[i], Ls[i], bufs[i].ctypes.data)
+        count = ctypes.c_int32()
+        code = lib().bires_squarefree(ctypes.byref(rd), ctypes.byref(ud), fds, nmax, ctypes.byref(count), MEM_HOST,
+                                      _stream(stream))
+        if code == E_BUFSIZE:
+            udeg, uL = max(udeg, ud.degree), max(uL, ud.limbs)
+            for i in range(nmax):
+                degs[i], Ls[i] = max(degs[i], fds[i].degree), max(Ls[i], fds[i].limbs)
+            continue
+        _check(code, "bires_squarefree")
+        u = limbs_to_ints(ubuf[: ud.degree + 1]) if ud.degree >= 0 else []
+        facs = [limbs_to_ints(bufs[i][: fds[i].degree + 1]) for i in range(count.value)]
+        return (u[0] if u else 0), facs
+    raise BiresError(E_BUFSIZE, "bires_squarefree: output sizes did not settle")
 
 
 def resultant_batch(jobs, stream=None):

@@ -140,6 +140,14 @@ int bires_gcd(const bires_upoly* a, const bires_upoly* b, bires_upoly* out, int 
   return with_stream(stream, [&](Context* cx, hipStream_t st) { return run_gcd(cx, *a, *b, out, mem, st); });
 }
 
+int bires_squarefree(const bires_upoly* r, bires_upoly* unit, bires_upoly* factors, int32_t max_factors,
+                     int32_t* count, int mem, void* stream) {
+  if (!r) return BIRES_EINVAL;
+  return with_stream(stream, [&](Context* cx, hipStream_t st) {
+    return run_squarefree(cx, *r, unit, factors, max_factors, count, mem, st);
+  });
+}
+
 int bires_plan(const bires_bipoly* f, const bires_bipoly* g, int kind, int var, int32_t* points, int32_t* primes,
                double* log2_bound) {
   if (!f || (kind == BIRES_KIND_RESULTANT && !g)) return BIRES_EINVAL;

@@ -66,6 +66,48 @@ BigInt big_abs(const BigInt& a) {
   return r;
 }
 
+// |a| + |b| and |a| - |b| (|a| >= |b|) on magnitudes.
+static std::vector<uint32_t> add_mag(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b) {
+  std::vector<uint32_t> r(std::max(a.size(), b.size()) + 1, 0u);
+  uint64_t carry = 0;
+  for (size_t i = 0; i + 1 < r.size(); ++i) {
+    const uint64_t s = carry + (i < a.size() ? a[i] : 0u) + (i < b.size() ? b[i] : 0u);
+    r[i] = (uint32_t)s;
+    carry = s >> 32;
+  }
+  r.back() = (uint32_t)carry;
+  trim(r);
+  return r;
+}
+
+static std::vector<uint32_t> sub_mag(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b) {
+  std::vector<uint32_t> r(a.size(), 0u);
+  int64_t borrow = 0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    int64_t s = (int64_t)a[i] - (i < b.size() ? (int64_t)b[i] : 0) - borrow;
+    borrow = s < 0 ? 1 : 0;
+    r[i] = (uint32_t)(s + (borrow << 32));
+  }
+  trim(r);
+  return r;
+}
+
+BigInt big_add(const BigInt& a, const BigInt& b) {
+  BigInt r;
+  if (a.neg == b.neg) {
+    r.mag = add_mag(a.mag, b.mag);
+    r.neg = a.neg;
+  } else if (cmp_mag(a.mag, b.mag) >= 0) {
+    r.mag = sub_mag(a.mag, b.mag);
+    r.neg = a.neg;
+  } else {
+    r.mag = sub_mag(b.mag, a.mag);
+    r.neg = b.neg;
+  }
+  if (r.mag.empty()) r.neg = false;
+  return r;
+}
+
 BigInt big_mul(const BigInt& a, const BigInt& b) {
   BigInt r;
   if (a.is_zero() || b.is_zero()) return r;

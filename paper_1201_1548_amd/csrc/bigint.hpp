@@ -22,6 +22,7 @@ struct BigInt {
 void trim(std::vector<uint32_t>& m);
 int cmp_mag(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b);
 BigInt big_abs(const BigInt& a);
+BigInt big_add(const BigInt& a, const BigInt& b);
 BigInt big_mul(const BigInt& a, const BigInt& b);
 // Quotient and remainder of |a| by |b| (b != 0), Knuth's algorithm D.
 void divmod_mag(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b, std::vector<uint32_t>& q,

@@ -331,6 +331,123 @@ int reconstruct(Context* cx, const std::vector<int>& S, const std::vector<const 
 
 }  // namespace
 
+namespace {
+
+// The modular core for A, B of degree >= 1: G = pp(F) with positive leading
+// coefficient and, when CA / CB are given, the exact cofactors A / G and
+// B / G.  From F Qa = lc(A) A (certified over Z): A / pp(F) = cont(F) Qa /
+// lc(A), an exact division per coefficient.
+int gcd_core(Context* cx, const Poly& A, const Poly& B, hipStream_t st, Poly& G, Poly* CA, Poly* CB) {
+  const int da = (int)A.size() - 1, db = (int)B.size() - 1;
+  if (std::max(da, db) > MAX_GCD_DEGREE) return BIRES_ETOOBIG;
+  if (gcd_lds_bytes(da, db) > cx->lds_per_block) return BIRES_ETOOBIG;
+  const BigInt beta = big_gcd(A.back(), B.back());
+  const int ba = max_bits(A), bb = max_bits(B);
+  const HostTables& T = host_tables();
+  int need = std::max(A.back().bits() + ba, B.back().bits() + bb) + beta.bits() + 64;
+  std::vector<Poly> rec;
+  for (int attempt = 0;; ++attempt) {
+    int P = 0;
+    while (P < T.K && T.cumlog[P] < need) ++P;
+    P = std::min(T.K, P + 4);  // spares for primes dividing lc(a) lc(b) or unlucky ones
+    if (attempt > 8 || T.cumlog[P] < need) return BIRES_ETOOBIG;
+    DevBuf ws(&cx->dev, 0);
+    size_t o_F = 0, o_QA = 0, o_QB = 0;
+    std::vector<int32_t> gdeg;
+    int e = modular_phase(cx, A, B, beta, P, st, ws, o_F, o_QA, o_QB, gdeg);
+    if (e) return e;
+    int d = 1 << 30;
+    for (int k = 0; k < P; ++k) {
+      if (gdeg[k] == -3) return BIRES_ECHECK;
+      if (gdeg[k] >= 0) d = std::min(d, (int)gdeg[k]);
+    }
+    if (d == (1 << 30)) {
+      need *= 2;
+      continue;
+    }
+    std::vector<int> S;
+    for (int k = 0; k < P; ++k)
+      if (gdeg[k] == d) S.push_back(k);
+    const int mn = std::min(da, db);
+    rec.clear();
+    e = reconstruct(cx, S, {ws.as<uint32_t>(o_F), ws.as<uint32_t>(o_QA), ws.as<uint32_t>(o_QB)},
+                    {mn + 1, da + 1, db + 1}, {d + 1, da - d + 1, db - d + 1}, st, rec);
+    if (e) return e;
+    double log2M = 0.0;
+    for (int k : S) log2M += T.log2p[k];
+    auto n1 = [](const Poly& v) { return max_bits(v) + std::log2((double)v.size() + 1.0); };
+    const bool ok_a = n1(rec[0]) + n1(rec[1]) < log2M - 2.0 && A.back().bits() + ba < log2M - 2.0;
+    const bool ok_b = n1(rec[0]) + n1(rec[2]) < log2M - 2.0 && B.back().bits() + bb < log2M - 2.0;
+    if (ok_a && ok_b && (int)rec[0].size() == d + 1) break;
+    need = (int)std::ceil(std::max<double>(need, n1(rec[0]) + std::max(n1(rec[1]), n1(rec[2])) + 8.0)) * 2;
+  }
+  const Poly& Fs = rec[0];
+  const BigInt cf = content(Fs);
+  G.assign(Fs.size(), BigInt());
+  for (size_t i = 0; i < Fs.size(); ++i)
+    if (!big_divexact(Fs[i], cf, G[i])) return BIRES_ECHECK;
+  const bool flip = G.back().neg;
+  make_positive(G);
+  for (int w = 0; w < 2; ++w) {
+    Poly* C = w ? CB : CA;
+    if (!C) continue;
+    const Poly& Q = rec[1 + w];
+    const BigInt& lc = w ? B.back() : A.back();
+    C->assign(Q.size(), BigInt());
+    for (size_t i = 0; i < Q.size(); ++i) {
+      if (!big_divexact(big_mul(cf, Q[i]), lc, (*C)[i])) return BIRES_ECHECK;
+      if (flip) (*C)[i].neg = !(*C)[i].neg && !(*C)[i].is_zero();
+    }
+    trim_poly(*C);
+  }
+  return BIRES_OK;
+}
+
+// gcd with exact cofactors for any A, B (G primitive when A or B is
+// primitive): G = 1 when either is a non-zero constant, G = pp(A) when B = 0.
+int gcd_cofactors(Context* cx, const Poly& A, const Poly& B, hipStream_t st, Poly& G, Poly& CA, Poly& CB) {
+  if (B.empty()) {
+    if (A.empty()) return BIRES_EINVAL;
+    const BigInt c = content(A);
+    G.assign(A.size(), BigInt());
+    for (size_t i = 0; i < A.size(); ++i)
+      if (!big_divexact(A[i], c, G[i])) return BIRES_ECHECK;
+    BigInt u = c;
+    if (G.back().neg) u.neg = true;
+    make_positive(G);
+    CA = Poly{u};
+    CB.clear();
+    return BIRES_OK;
+  }
+  if (A.size() == 1 || B.size() == 1) {
+    G = Poly{BigInt::from_u64(1)};
+    CA = A;
+    CB = B;
+    return BIRES_OK;
+  }
+  return gcd_core(cx, A, B, st, G, &CA, &CB);
+}
+
+Poly derivative(const Poly& v) {
+  Poly d;
+  for (size_t i = 1; i < v.size(); ++i) d.push_back(big_mul(v[i], BigInt::from_u64(i)));
+  trim_poly(d);
+  return d;
+}
+
+Poly poly_sub(const Poly& a, const Poly& b) {
+  Poly r(std::max(a.size(), b.size()));
+  for (size_t i = 0; i < r.size(); ++i) {
+    BigInt nb = i < b.size() ? b[i] : BigInt();
+    nb.neg = !nb.neg && !nb.is_zero();
+    r[i] = big_add(i < a.size() ? a[i] : BigInt(), nb);
+  }
+  trim_poly(r);
+  return r;
+}
+
+}  // namespace
+
 int run_gcd(Context* cx, const bires_upoly& a, const bires_upoly& b, bires_upoly* out, int mem, hipStream_t st) {
   if (mem != BIRES_MEM_HOST && mem != BIRES_MEM_DEVICE) return BIRES_EINVAL;
   if (!out || out->degree < 0 || out->limbs < 1 || !out->c) return BIRES_EINVAL;
@@ -346,61 +463,51 @@ int run_gcd(Context* cx, const bires_upoly& a, const bires_upoly& b, bires_upoly
   }
   const BigInt c = big_gcd(content(A), content(B));
   if (A.size() == 1 || B.size() == 1) return write_upoly(Poly{c}, out, mem, st);
-  const int da = (int)A.size() - 1, db = (int)B.size() - 1;
-  if (std::max(da, db) > MAX_GCD_DEGREE) return BIRES_ETOOBIG;
-  if (gcd_lds_bytes(da, db) > cx->lds_per_block) return BIRES_ETOOBIG;
-  const BigInt beta = big_gcd(A.back(), B.back());
-  const int ba = max_bits(A), bb = max_bits(B);
-  const HostTables& T = host_tables();
-  int need = std::max(A.back().bits() + ba, B.back().bits() + bb) + beta.bits() + 64;
-  Poly Fs;
-  for (int attempt = 0;; ++attempt) {
-    int P = 0;
-    while (P < T.K && T.cumlog[P] < need) ++P;
-    P = std::min(T.K, P + 4);  // spares for primes dividing lc(a) lc(b) or unlucky ones
-    if (attempt > 8 || T.cumlog[P] < need) return BIRES_ETOOBIG;
-    DevBuf ws(&cx->dev, 0);
-    size_t o_F = 0, o_QA = 0, o_QB = 0;
-    std::vector<int32_t> gdeg;
-    if ((e = modular_phase(cx, A, B, beta, P, st, ws, o_F, o_QA, o_QB, gdeg))) return e;
-    int d = 1 << 30;
-    for (int k = 0; k < P; ++k) {
-      if (gdeg[k] == -3) return BIRES_ECHECK;
-      if (gdeg[k] >= 0) d = std::min(d, (int)gdeg[k]);
-    }
-    if (d == (1 << 30)) {
-      need *= 2;
-      continue;
-    }
-    std::vector<int> S;
-    for (int k = 0; k < P; ++k)
-      if (gdeg[k] == d) S.push_back(k);
-    const int mn = std::min(da, db);
-    std::vector<Poly> rec;
-    e = reconstruct(cx, S, {ws.as<uint32_t>(o_F), ws.as<uint32_t>(o_QA), ws.as<uint32_t>(o_QB)},
-                    {mn + 1, da + 1, db + 1}, {d + 1, da - d + 1, db - d + 1}, st, rec);
-    if (e) return e;
-    double log2M = 0.0;
-    for (int k : S) log2M += T.log2p[k];
-    auto n1 = [](const Poly& v) { return max_bits(v) + std::log2((double)v.size() + 1.0); };
-    const bool ok_a = n1(rec[0]) + n1(rec[1]) < log2M - 2.0 && A.back().bits() + ba < log2M - 2.0;
-    const bool ok_b = n1(rec[0]) + n1(rec[2]) < log2M - 2.0 && B.back().bits() + bb < log2M - 2.0;
-    if (ok_a && ok_b && (int)rec[0].size() == d + 1) {
-      Fs = rec[0];
-      break;
-    }
-    need = (int)std::ceil(std::max<double>(need, n1(rec[0]) + std::max(n1(rec[1]), n1(rec[2])) + 8.0)) * 2;
-  }
-  // primitive part of F times the gcd of the contents, positive leading coefficient
-  const BigInt cf = content(Fs);
-  Poly G(Fs.size());
-  for (size_t i = 0; i < Fs.size(); ++i) {
-    BigInt qi;
-    if (!big_divexact(Fs[i], cf, qi)) return BIRES_ECHECK;
-    G[i] = big_mul(qi, c);
-  }
-  make_positive(G);
+  Poly G;
+  if ((e = gcd_core(cx, A, B, st, G, nullptr, nullptr))) return e;
+  // primitive gcd times the gcd of the contents
+  for (auto& x : G) x = big_mul(x, c);
   return write_upoly(G, out, mem, st);
+}
+
+int run_squarefree(Context* cx, const bires_upoly& r, bires_upoly* unit, bires_upoly* factors, int32_t max_factors,
+                   int32_t* count, int mem, hipStream_t st) {
+  if (mem != BIRES_MEM_HOST && mem != BIRES_MEM_DEVICE) return BIRES_EINVAL;
+  if (!unit || !count || max_factors < 0 || (max_factors > 0 && !factors)) return BIRES_EINVAL;
+  Poly R;
+  int e = read_upoly(r, mem, st, R);
+  if (e) return e;
+  std::vector<Poly> out;
+  BigInt u;  // signed content
+  if (R.size() >= 2) {
+    u = content(R);
+    if (R.back().neg) u.neg = true;
+    Poly Rp(R.size());
+    for (size_t i = 0; i < R.size(); ++i)
+      if (!big_divexact(R[i], u, Rp[i])) return BIRES_ECHECK;
+    // Yun: b_1 = R / g, d_1 = R' / g - b_1' with g = gcd(R, R'); then
+    // a_i = gcd(b_i, d_i), b_{i+1} = b_i / a_i, d_{i+1} = d_i / a_i - b_{i+1}'
+    Poly g, b, c;
+    if ((e = gcd_cofactors(cx, Rp, derivative(Rp), st, g, b, c))) return e;
+    Poly d = poly_sub(c, derivative(b));
+    while (b.size() >= 2) {
+      Poly a, b2, c2;
+      if ((e = gcd_cofactors(cx, b, d, st, a, b2, c2))) return e;
+      out.push_back(a);
+      b = b2;
+      d = poly_sub(c2, derivative(b));
+    }
+  } else if (R.size() == 1) {
+    u = R[0];
+  }
+  *count = (int32_t)out.size();
+  int first = BIRES_OK;
+  const Poly U = u.is_zero() ? Poly() : Poly{u};
+  if ((e = write_upoly(U, unit, mem, st)) && first == BIRES_OK) first = e;
+  if ((int)out.size() > max_factors) return BIRES_EBUFSIZE;
+  for (size_t i = 0; i < out.size(); ++i)
+    if ((e = write_upoly(out[i], &factors[i], mem, st)) && first == BIRES_OK) first = e;
+  return first;
 }
 
 }  // namespace bires
