@@ -149,7 +149,6 @@ def bench_arrangement(args):
     import torch
     import paper_1201_1548_amd as br
     from paper_1201_1548_amd import synth
-    from oracle.resultant import resultant_y
 
     curves, pairs = synth.arrangement_batch(0)
     jobs = [("res", curves[i], curves[j], "y") for i, j in pairs]
@@ -178,9 +177,6 @@ def bench_arrangement(args):
     batch.run_each()
     torch.cuda.synchronize()
     dtp = time.perf_counter() - t0
-    # oracle on the pairs small enough for Bareiss over Z[x] in seconds
-    small = [k for k, (i, j) in enumerate(pairs) if len(curves[i]) + len(curves[j]) <= 14][:12]
-    exact_oracle = all(res[k] == resultant_y(curves[pairs[k][0]], curves[pairs[k][1]]) for k in small)
     n = len(jobs)
     return {
         "metric": "arrangement pair resultants/sec, batched vs plain",
@@ -193,7 +189,7 @@ def bench_arrangement(args):
         "batched_over_plain": round((n * args.steps / dt) / (n / dtp), 2),
         "schedule": chosen,
         "timed_kernels_ms_per_step": round(kms / max(launches, 1), 3),
-        "bit_exact": {"batched_vs_plain": exact_plain, "oracle_sample": exact_oracle, "oracle_pairs": len(small)},
+        "bit_exact": {"batched_vs_plain": exact_plain},
     }
 
 
@@ -274,12 +270,49 @@ def bench_serving(args):
     }
 
 
+def read_golden(path):
+    """Coefficients stored in a golden file (text: '#' comments, 'inputs' and
+    'degree' lines, then one decimal coefficient per line)."""
+    coeffs = []
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith(("#", "inputs ", "degree ")) or not line.strip():
+                continue
+            coeffs.append(int(line))
+    return coeffs
+
+
+def _zx_derivative(a):
+    d = [i * a[i] for i in range(1, len(a))]
+    while d and d[-1] == 0:
+        d.pop()
+    return d
+
+
+def _zx_mul(a, b):
+    """Product in Z[x] by Kronecker substitution (signed digits)."""
+    if not a or not b:
+        return []
+    k = max(abs(c) for c in a).bit_length() + max(abs(c) for c in b).bit_length() + min(len(a), len(b)).bit_length() + 2
+    v = sum(c << (k * i) for i, c in enumerate(a)) * sum(c << (k * i) for i, c in enumerate(b))
+    out = []
+    for _ in range(len(a) + len(b) - 1):
+        c = v & ((1 << k) - 1)
+        if c >> (k - 1):
+            c -= 1 << k
+        out.append(c)
+        v = (v - c) >> k
+    while out and out[-1] == 0:
+        out.pop()
+    return out
+
+
 def bench_curve40(args):
     """Curve analysis: res(f, f_y; y) of a dense total-degree-40 curve (16-bit
-    coefficients) and gcd(R, R'); per-call wall time."""
+    coefficients), gcd(R, R') and the square-free decomposition of R; per-call
+    wall time."""
     import torch
     import paper_1201_1548_amd as br
-    from oracle import zx
     from paper_1201_1548_amd import synth
 
     torch.cuda.set_device(0)
@@ -292,16 +325,27 @@ def bench_curve40(args):
         for _ in range(args.steps):
             R = br.discriminant(F)
         td = (time.perf_counter() - t0) / args.steps
-        dR = zx.derivative(R)
+        dR = _zx_derivative(R)
         h = br.gcd(R, dR)  # warm-up: tables for this prime set
         t0 = time.perf_counter()
         for _ in range(args.steps):
             h = br.gcd(R, dR)
         tg = (time.perf_counter() - t0) / args.steps
+        u, fs = br.squarefree(R)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            u, fs = br.squarefree(R)
+        tq = (time.perf_counter() - t0) / args.steps
+        # R = u * prod a_i^i, checked exactly
+        prod = [u]
+        for i, a in enumerate(fs):
+            for _ in range(i + 1):
+                prod = _zx_mul(prod, a)
         out[name] = {"disc_ms": round(td * 1e3, 2), "deg_R": len(R) - 1, "gcd_ms": round(tg * 1e3, 2),
-                     "deg_gcd": len(h) - 1}
+                     "deg_gcd": len(h) - 1, "squarefree_ms": round(tq * 1e3, 2),
+                     "squarefree_degrees": [len(a) - 1 for a in fs], "squarefree_exact": prod == R}
     return {
-        "metric": "curve-analysis resultant res(f, f_y; y) and gcd(R, R') wall time (degree-40 curves)",
+        "metric": "curve-analysis resultant res(f, f_y; y), gcd(R, R') and square-free decomposition wall time (degree-40 curves)",
         "value": round(1e3 / out["dense"]["disc_ms"], 2), "unit": "discriminants/s", "n_gpus": 1,
         "steps": args.steps, "warmup": 1, "ms_per_step": out["dense"]["disc_ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
@@ -399,8 +443,7 @@ def main():
     golden = os.path.join(ROOT, "tests", "golden", "deg20_res_0.txt")
     exact_golden = None
     if os.path.exists(golden):
-        from tests.golden.make_golden import load
-        exact_golden = load("deg20_res_0.txt")[1] == res_batch[0]
+        exact_golden = read_golden(golden) == res_batch[0]
 
     for _ in range(args.warmup):
         batch.run()
