@@ -286,7 +286,7 @@ def squarefree(r, stream=None):
     ra, rd = _upoly_in(r)
     deg = max(len(r) - 1, 0)
     cap_deg, cap_L = deg, int(ra.shape[1]) + 2
-    nmax = max(deg, 1)
+    nmax = min(max(deg, 1), 8)  # grown when the library reports more factors
     degs, Ls = [cap_deg] * nmax, [cap_L] * nmax
     udeg, uL = 0, cap_L
     for _ in range(4):
@@ -303,6 +303,10 @@ def squarefree(r, stream=None):
             udeg, uL = max(udeg, ud.degree), max(uL, ud.limbs)
             for i in range(nmax):
                 degs[i], Ls[i] = max(degs[i], fds[i].degree), max(Ls[i], fds[i].limbs)
+            if count.value > nmax:
+                degs += [cap_deg] * (count.value - nmax)
+                Ls += [cap_L] * (count.value - nmax)
+                nmax = count.value
             continue
         _check(code, "bires_squarefree")
         u = limbs_to_ints(ubuf[: ud.degree + 1]) if ud.degree >= 0 else []

@@ -388,15 +388,33 @@ int gcd_core(Context* cx, const Poly& A, const Poly& B, hipStream_t st, Poly& G,
     if (!big_divexact(Fs[i], cf, G[i])) return BIRES_ECHECK;
   const bool flip = G.back().neg;
   make_positive(G);
+  if (G.size() == 1) {  // coprime: the cofactors are A and B
+    if (CA) *CA = A;
+    if (CB) *CB = B;
+    return BIRES_OK;
+  }
   for (int w = 0; w < 2; ++w) {
     Poly* C = w ? CB : CA;
     if (!C) continue;
     const Poly& Q = rec[1 + w];
+    // cont(F) Q / lc with the common factor of cont(F) and lc cancelled
+    // first, so that a unit divisor leaves only products
     const BigInt& lc = w ? B.back() : A.back();
+    const BigInt h = big_gcd(cf, lc);
+    BigInt num, den;
+    if (!big_divexact(cf, h, num) || !big_divexact(lc, h, den)) return BIRES_ECHECK;
+    const bool unit = den.mag.size() == 1 && den.mag[0] == 1u;
+    const bool neg = den.neg != flip;
+    den.neg = false;
     C->assign(Q.size(), BigInt());
     for (size_t i = 0; i < Q.size(); ++i) {
-      if (!big_divexact(big_mul(cf, Q[i]), lc, (*C)[i])) return BIRES_ECHECK;
-      if (flip) (*C)[i].neg = !(*C)[i].neg && !(*C)[i].is_zero();
+      const BigInt t = (num.mag.size() == 1 && num.mag[0] == 1u && !num.neg) ? Q[i] : big_mul(num, Q[i]);
+      if (unit) {
+        (*C)[i] = t;
+      } else if (!big_divexact(t, den, (*C)[i])) {
+        return BIRES_ECHECK;
+      }
+      if (neg) (*C)[i].neg = !(*C)[i].neg && !(*C)[i].is_zero();
     }
     trim_poly(*C);
   }
