@@ -105,7 +105,8 @@ def cpu_baseline(pairs, D, budget_s=15.0):
     import multiprocessing as mp
     from oracle.resultant import resultant_at
 
-    cores = max(1, min(16, os.cpu_count() or 1))
+    affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = max(1, min(16, affinity))
     F, G = pairs[0]
     t0 = time.time()
     resultant_at(F, G, 0)
@@ -122,6 +123,8 @@ def cpu_baseline(pairs, D, budget_s=15.0):
         "value": npts / dt / D,
         "unit": "resultants/s",
         "cores": cores,
+        "host_cpu_count": os.cpu_count(),
+        "host_cpus_allowed": affinity,
         "kind": "oracle",
         "sample": "%d evaluation points R(a) of the dense total-degree-20 pairs by the oracle's integer Bareiss "
                   "determinant of the specialised Sylvester matrix, %d processes; value = points/s / %d "

@@ -193,7 +193,13 @@ int bires_server_submit(bires_server *s, int kind, int var, const bires_bipoly *
                         const bires_bipoly *g, uint64_t *ticket);
 
 /* Blocks until the job is done (timeout_s < 0: no limit), then writes the
- * result to out (host memory) and the submit-to-completion latency. */
+ * result to out (host memory) and the submit-to-completion latency, and
+ * retires the ticket.  When out is too small (degree capacity below the
+ * result's degree, or fewer limbs than its largest coefficient needs) it
+ * returns BIRES_EBUFSIZE with the needed degree and limbs written back into
+ * out and keeps the ticket, so the caller can wait again with a larger
+ * buffer.  A failed job's error code is returned once and retires the ticket;
+ * BIRES_ENOTFOUND for an unknown or retired ticket. */
 int bires_server_wait(bires_server *s, uint64_t ticket, bires_upoly *out, double timeout_s,
                       double *latency_s);
 

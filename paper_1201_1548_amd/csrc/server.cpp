@@ -216,6 +216,21 @@ int bires_server_submit(bires_server* s, int kind, int var, const bires_bipoly* 
   return BIRES_OK;
 }
 
+// Smallest limb count that holds every coefficient of a finished request's
+// result in two's complement.
+static int needed_limbs(const Request* r) {
+  const int Lr = r->out_limbs;
+  int need = 1;
+  for (int i = 0; i <= r->out_degree; ++i) {
+    const uint32_t* c = &r->out[(size_t)i * Lr];
+    const uint32_t ext = (c[Lr - 1] >> 31) ? 0xFFFFFFFFu : 0u;
+    int l = Lr;
+    while (l > 1 && c[l - 1] == ext && (c[l - 2] >> 31) == (ext >> 31)) --l;
+    need = std::max(need, l);
+  }
+  return need;
+}
+
 int bires_server_wait(bires_server* s, uint64_t ticket, bires_upoly* out, double timeout_s, double* latency_s) {
   if (!s || !out) return BIRES_EINVAL;
   std::unique_lock<std::mutex> lk(s->mu);
@@ -227,28 +242,30 @@ int bires_server_wait(bires_server* s, uint64_t ticket, bires_upoly* out, double
   } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] { return r->done; })) {
     return BIRES_ETIMEOUT;
   }
-  s->table.erase(it);
-  lk.unlock();
   int e = r->status;
   if (!e) {
+    // a buffer that is too small keeps the ticket: the needed sizes are
+    // written back and the caller can wait again with a larger one
     const int deg = r->out_degree;
-    if (out->degree < std::max(deg, 0) || out->limbs < 1 || !out->c) {
-      e = out->c ? BIRES_EBUFSIZE : BIRES_EINVAL;
-      out->degree = std::max(deg, 0);
-    } else {
-      // re-encode at the caller's limb count (sign-extend or check the fit)
-      const int Lr = r->out_limbs, Lc = out->limbs;
-      for (int i = 0; i <= out->degree; ++i) {
-        const uint32_t* src = i <= deg ? &r->out[(size_t)i * Lr] : nullptr;
-        const uint32_t ext = src && (src[Lr - 1] >> 31) ? 0xFFFFFFFFu : 0u;
-        for (int l = 0; l < Lc; ++l) out->c[(size_t)i * Lc + l] = src ? (l < Lr ? src[l] : ext) : 0u;
-        if (src)
-          for (int l = Lc; l < Lr; ++l)
-            if (src[l] != ext || ((src[Lc - 1] >> 31) != (ext >> 31))) e = BIRES_EBUFSIZE;
-      }
-      out->degree = deg;
+    const int need = needed_limbs(r);
+    if (!out->c || out->limbs < 1) return BIRES_EINVAL;
+    if (out->degree < std::max(deg, 0) || out->limbs < need) {
+      out->degree = std::max(deg, out->degree);
+      out->limbs = std::max(need, out->limbs);
+      return BIRES_EBUFSIZE;
     }
+    // re-encode at the caller's limb count (sign-extend or truncate the
+    // sign-extension words, which need_limbs checked)
+    const int Lr = r->out_limbs, Lc = out->limbs;
+    for (int i = 0; i <= out->degree; ++i) {
+      const uint32_t* src = i <= deg ? &r->out[(size_t)i * Lr] : nullptr;
+      const uint32_t ext = src && (src[Lr - 1] >> 31) ? 0xFFFFFFFFu : 0u;
+      for (int l = 0; l < Lc; ++l) out->c[(size_t)i * Lc + l] = src ? (l < Lr ? src[l] : ext) : 0u;
+    }
+    out->degree = deg;
   }
+  s->table.erase(it);
+  lk.unlock();
   if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
   delete r;
   return e;

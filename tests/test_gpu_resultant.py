@@ -254,9 +254,11 @@ def test_autotune_keeps_results():
     assert b.results() == out
 
 
-def test_large_batch_lane_garner_path():
-    # >= 16384 output coefficients in one batch selects the lane-per-coefficient
-    # Garner + limb kernel; single calls take the wave-per-coefficient kernels
+def test_large_batch_mixed_shapes():
+    # 50 jobs of two shapes (>= 16384 output coefficients, at most 48 primes):
+    # the staged schedule reconstructs them with the explicit CRT on the
+    # matrix cores, like single calls; the lane-per-coefficient Garner kernel
+    # is reached through the fused schedule (tests/test_gpu_fullsize.py)
     jobs = [("res",) + synth.pair_deg20(i) + ("y",) for i in range(40)]
     jobs += [("res",) + synth.pair_deg6(i % 4) + ("y",) for i in range(10)]
     say("large batch", len(jobs))

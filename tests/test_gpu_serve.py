@@ -89,3 +89,31 @@ def test_unknown_ticket():
             srv._caps = {12345: (0, 1)}
             srv.wait(12345)
         assert ei.value.code == -7
+
+
+def test_wait_with_small_buffer_keeps_the_ticket():
+    # a too-small output buffer reports the needed sizes and keeps the result;
+    # waiting again with a buffer of those sizes returns it
+    import ctypes
+
+    import numpy as np
+    F, G = synth.pair_deg6(2)
+    R = resultant_y(F, G)
+    say("small buffer")
+    with br.Server(hbm_budget_bytes=1 << 28, max_slots=4) as srv:
+        t = srv.submit("res", F, G)
+        srv._caps.pop(t)
+        small = np.zeros((3, 1), dtype=np.uint32)
+        od = br.Upoly(2, 1, small.ctypes.data)
+        lat = ctypes.c_double()
+        e = br.lib().bires_server_wait(srv.h, t, ctypes.byref(od), -1.0, ctypes.byref(lat))
+        assert e == -2
+        assert od.degree == len(R) - 1
+        need = br.limbs_needed(R)
+        assert od.limbs == need
+        buf = np.zeros((od.degree + 1, od.limbs), dtype=np.uint32)
+        od2 = br.Upoly(od.degree, od.limbs, buf.ctypes.data)
+        assert br.lib().bires_server_wait(srv.h, t, ctypes.byref(od2), -1.0, ctypes.byref(lat)) == 0
+        assert br.limbs_to_ints(buf[: od2.degree + 1]) == R
+        # the ticket is retired once the result was delivered
+        assert br.lib().bires_server_wait(srv.h, t, ctypes.byref(od2), -1.0, ctypes.byref(lat)) == -7
