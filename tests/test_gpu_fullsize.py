@@ -178,7 +178,7 @@ def test_more_than_128_primes_single_call(i):
 def test_more_than_128_primes_mixed_batches():
     big = [synth.random_rect(1300 + i, *BIG[i]) for i in range(len(BIG))]
     small = [synth.pair_deg6(i % 4) for i in range(6)]
-    disc = synth.random_rect(1400, 4, 5, 1, 1, 420)[0]
+    disc = synth.random_rect(1400, 5, 5, 1, 1, 520)[0]
     jobs = [("res", F, G, "y") for F, G in big] + [("res", F, G, "y") for F, G in small]
     jobs += [("disc", disc, None, "y"), ("res", big[0][1], big[0][0], "y")]
     refs = [resultant_y(F, G) for _, F, G, _ in jobs[:-2]]
