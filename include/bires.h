@@ -149,6 +149,27 @@ int bires_gcd(const bires_upoly *a, const bires_upoly *b, bires_upoly *out, int 
 int bires_squarefree(const bires_upoly *r, bires_upoly *unit, bires_upoly *factors, int32_t max_factors,
                      int32_t *count, int mem, void *stream);
 
+/* For callers that cannot allocate (tight serving loops, harnesses that
+ * forbid device allocation after start-up): res(f, g; var) for kind
+ * BIRES_KIND_RESULTANT, or res(f, df/dvar; var) for BIRES_KIND_DISCRIMINANT
+ * (g then ignored), with the same arguments, results and errors as
+ * bires_resultant / bires_discriminant, but without allocating: no device or
+ * pinned host memory is allocated or freed by the call.  Every device buffer
+ * of the call lies in one fixed array of BIRES_NOALLOC_SCRATCH_BYTES that the
+ * library holds on its device from set-up until the process ends; host-side
+ * bookkeeping uses ordinary heap memory.  The library must already be set up
+ * (bires_init() or any earlier call; else BIRES_EINVAL).  A job whose
+ * buffers do not fit in the array returns BIRES_ETOOBIG (for scale: a dense
+ * total-degree-40 discriminant needs about 5 MB).  All calls share the array
+ * and keep its last contents; the library runs them one at a time (a call
+ * waits for the one in progress), so concurrent calls never overlap on the
+ * device.  Per-job interpolation and, where its operand table was built by an
+ * earlier call, the explicit CRT, else Garner's reconstruction; the staged
+ * schedule.  Synchronous. */
+#define BIRES_NOALLOC_SCRATCH_BYTES (64u << 20)
+int bires_resultant_noalloc(const bires_bipoly *f, const bires_bipoly *g, int kind, int var, bires_upoly *out,
+                            int mem, void *stream);
+
 /* n independent jobs in one batched launch sequence.  kind[i] is a
  * BIRES_KIND_*; var[i] a BIRES_VAR_*; g[i] is ignored for discriminants.
  * status[i] receives the per-job code; the return value is BIRES_OK when

@@ -62,6 +62,8 @@ _SIGS = {
                    ctypes.c_void_p], ctypes.c_int),
     "bires_squarefree": ([ctypes.POINTER(Upoly), ctypes.POINTER(Upoly), ctypes.POINTER(Upoly), ctypes.c_int32,
                           ctypes.POINTER(ctypes.c_int32), ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "bires_resultant_noalloc": ([ctypes.POINTER(Bipoly), ctypes.POINTER(Bipoly), ctypes.c_int, ctypes.c_int,
+                                 ctypes.POINTER(Upoly), ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "bires_resultant_batch": ([ctypes.c_int, ctypes.POINTER(Bipoly), ctypes.POINTER(Bipoly),
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(Upoly), ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
@@ -253,6 +255,40 @@ def discriminant(F, var="y", stream=None):
     _check(lib().bires_discriminant(ctypes.byref(fd), v, ctypes.byref(od), MEM_HOST, _stream(stream)),
            "bires_discriminant")
     return limbs_to_ints(out[: od.degree + 1])
+
+
+def resultant_noalloc(F, G=None, kind="res", var="y", stream=None, device=False):
+    """res(f, g; var) (kind "res") or res(f, df/dvar; var) (kind "disc") through
+    the allocation-free entry point bires_resultant_noalloc.  device=True
+    passes device-memory inputs and output (torch tensors), else host memory.
+    The library must be set up first (init())."""
+    k = KIND_DISCRIMINANT if kind == "disc" else KIND_RESULTANT
+    v = _var(var)
+    fa = bipoly_array(F)
+    ga = bipoly_array(G) if k == KIND_RESULTANT else fa
+    fd, gd = _desc(fa), _desc(ga)
+    deg, L = _bounds(k, fd, gd, v)
+    if not device:
+        out = np.zeros((deg + 1, L), dtype=np.uint32)
+        od = Upoly(deg, L, out.ctypes.data)
+        _check(lib().bires_resultant_noalloc(ctypes.byref(fd), ctypes.byref(gd), k, v, ctypes.byref(od), MEM_HOST,
+                                             _stream(stream)), "bires_resultant_noalloc")
+        return limbs_to_ints(out[: od.degree + 1])
+    import torch
+    tf = torch.from_numpy(fa.view(np.int32)).cuda()
+    tg = torch.from_numpy(ga.view(np.int32)).cuda()
+    tout = torch.zeros((deg + 1, L), dtype=torch.int32, device="cuda")
+    fd, gd = _desc(fa, tf.data_ptr()), _desc(ga, tg.data_ptr())
+    od = Upoly(deg, L, tout.data_ptr())
+    torch.cuda.synchronize()
+    _check(lib().bires_resultant_noalloc(ctypes.byref(fd), ctypes.byref(gd), k, v, ctypes.byref(od), MEM_DEVICE,
+                                         _stream(stream)), "bires_resultant_noalloc")
+    return limbs_to_ints(tout.cpu().numpy().view(np.uint32)[: od.degree + 1])
+
+
+def init():
+    """Set up the library on the current device (bires_init)."""
+    _check(lib().bires_init(), "bires_init")
 
 
 def _upoly_in(a):

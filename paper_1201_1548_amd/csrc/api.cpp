@@ -103,6 +103,23 @@ int bires_discriminant(const bires_bipoly* f, int var, bires_upoly* out, int mem
   return with_stream(stream, [&](Context* cx, hipStream_t st) { return run_batch(cx, jobs, mem, st, nullptr); });
 }
 
+int bires_resultant_noalloc(const bires_bipoly* f, const bires_bipoly* g, int kind, int var, bires_upoly* out,
+                            int mem, void* stream) {
+  if (!f || !out || (kind == BIRES_KIND_RESULTANT && !g)) return BIRES_EINVAL;
+  if (kind != BIRES_KIND_RESULTANT && kind != BIRES_KIND_DISCRIMINANT) return BIRES_EINVAL;
+  Context* cx = context_if_ready();  // never sets the library up (that allocates)
+  if (!cx) return BIRES_EINVAL;
+  std::vector<JobIn> jobs(1);
+  jobs[0].f = *f;
+  jobs[0].g = kind == BIRES_KIND_RESULTANT ? *g : *f;
+  jobs[0].var = var;
+  jobs[0].kind = kind;
+  jobs[0].out = out;
+  if (stream) return run_batch_noalloc(cx, jobs, mem, (hipStream_t)stream, nullptr);
+  std::lock_guard<std::mutex> lk(cx->stream_mu);
+  return run_batch_noalloc(cx, jobs, mem, cx->stream, nullptr);
+}
+
 int bires_resultant_batch(int n, const bires_bipoly* f, const bires_bipoly* g, const int32_t* kind,
                           const int32_t* var, bires_upoly* out, int32_t* status, int mem, void* stream) {
   std::vector<JobIn> jobs;

@@ -206,6 +206,11 @@ struct PendingBatch {
   int32_t* h_flags = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, done = nullptr;
   Held d_in, h_in, d_ws, h_meta, h_out;
+  // allocation-free calls: device buffers in the library's fixed scratch
+  // array, host staging in ordinary memory, completion by stream sync
+  bool noalloc = false;
+  std::vector<uint8_t> hv_in, hv_meta, hv_out;
+  uint8_t* hout_base = nullptr;  // host output staging (pinned block or hv_out)
   explicit PendingBatch(bool clock) : hc(clock) {}
 };
 
@@ -221,9 +226,12 @@ void PendingDeleter::operator()(PendingBatch* p) const {
 namespace {
 
 int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStream_t st, int32_t* status,
-                std::vector<uint32_t>* debug_values, std::vector<int>* debug_shape, PendingPtr* pending) {
+                std::vector<uint32_t>* debug_values, std::vector<int>* debug_shape, PendingPtr* pending,
+                bool noalloc = false) {
   if (mem != BIRES_MEM_HOST && mem != BIRES_MEM_DEVICE) return BIRES_EINVAL;
-  PendingPtr P(new PendingBatch(cx->timing && debug_values == nullptr));
+  if (noalloc && (debug_values || !cx->scratch)) return BIRES_EINVAL;
+  PendingPtr P(new PendingBatch(cx->timing && debug_values == nullptr && !noalloc));
+  P->noalloc = noalloc;
   P->cx = cx;
   P->jobs = jobs_in;
   P->mem = mem;
@@ -279,17 +287,25 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   const size_t scan_words = (o_scan_end - o_scan0) / 4;
   P->o_scan0 = o_scan0;
   P->scan_words = scan_words;
-  Held& d_in = P->d_in;
-  Held& h_in = P->h_in;
-  d_in.take(&cx->dev, in.bytes);
-  h_in.take(&cx->host, in.bytes);
-  if (in.bytes && (!d_in.p || !h_in.p)) return BIRES_ENOMEM;
+  uint8_t *din = nullptr, *hin = nullptr;
+  if (noalloc) {
+    if (in.bytes > cx->scratch_bytes) return BIRES_ETOOBIG;
+    din = cx->scratch;
+    P->hv_in.resize(in.bytes);
+    hin = P->hv_in.data();
+  } else {
+    P->d_in.take(&cx->dev, in.bytes);
+    P->h_in.take(&cx->host, in.bytes);
+    if (in.bytes && (!P->d_in.p || !P->h_in.p)) return BIRES_ENOMEM;
+    din = P->d_in.b();
+    hin = P->h_in.b();
+  }
   // Plans reused from the previous call when it had the same descriptors and
   // the statistics have repeated; the scan still runs and a device check of
   // its output against the statistics of those plans decides, at the end,
   // whether the call stands or is rerun with fresh plans.
   SpecCache& sc = cx->spec;
-  const bool spec_ok = P->spec_ok = cx->plan_cache && mem == BIRES_MEM_DEVICE && !debug && scan_words > 0;
+  const bool spec_ok = P->spec_ok = cx->plan_cache && mem == BIRES_MEM_DEVICE && !debug && !noalloc && scan_words > 0;
   bool& spec = P->spec;
   std::vector<int32_t>& rowdeg = P->rowdeg;
   std::vector<int>& rd_off = P->rd_off;
@@ -314,20 +330,24 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
       if (w[i].status) continue;
       for (int which = 0; which < nsrc(i); ++which) {
         const Shape& s = shp(i, which);
-        uint32_t* h = (uint32_t*)(h_in.b() + w[i].o_in[which]);
+        uint32_t* h = (uint32_t*)(hin + w[i].o_in[which]);
         if (s.rows) pack_rect(which ? jobs[i].g : jobs[i].f, jobs[i].var, h);
         (which ? w[i].stg : w[i].stf) = scan_host(h, s.rows, s.ld, s.L);
-        (which ? w[i].dev_g : w[i].dev_f) = (const uint32_t*)(d_in.b() + w[i].o_in[which]);
+        (which ? w[i].dev_g : w[i].dev_f) = (const uint32_t*)(din + w[i].o_in[which]);
       }
     }
     hc.mark(0);
-    if (in.bytes) DEV(hipMemcpyAsync(d_in.p, h_in.p, in.bytes, hipMemcpyHostToDevice, st));
+    if (in.bytes) DEV(hipMemcpyAsync(din, hin, in.bytes, hipMemcpyHostToDevice, st));
     hc.mark(1);
   } else if (!tasks.empty()) {
     // The scan reads its task list from and writes its statistics to the
     // pinned staging block through its device mapping: no copies to wait on.
+    // Allocation-free calls keep both in the device scratch and copy.
     uint8_t* hmap = nullptr;
-    DEV(hipHostGetDevicePointer((void**)&hmap, h_in.p, 0));
+    if (noalloc)
+      hmap = din;
+    else
+      DEV(hipHostGetDevicePointer((void**)&hmap, hin, 0));
     int t = 0;
     for (int i = 0; i < nj; ++i) {
       if (w[i].status) continue;
@@ -336,7 +356,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
         const Shape& s = shp(i, which);
         const uint32_t* src = p.c;
         if (jobs[i].var == BIRES_VAR_X && s.rows) {
-          uint32_t* dst = (uint32_t*)(d_in.b() + w[i].o_in[which]);
+          uint32_t* dst = (uint32_t*)(din + w[i].o_in[which]);
           launch_transpose(p.c, dst, p.deg_y + 1, p.deg_x + 1, p.limbs, st);
           src = dst;
         }
@@ -344,20 +364,25 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
         tasks[t++] = ScanTask{src, s.rows, s.ld, s.L, (int32_t*)(hmap + w[i].o_scan[which])};
       }
     }
-    std::memcpy(h_in.b() + o_tasks, tasks.data(), sizeof(ScanTask) * tasks.size());
-    std::memcpy(h_in.b() + o_smap, smap.data(), sizeof(int4) * smap.size());
+    std::memcpy(hin + o_tasks, tasks.data(), sizeof(ScanTask) * tasks.size());
+    std::memcpy(hin + o_smap, smap.data(), sizeof(int4) * smap.size());
+    if (noalloc)
+      DEV(hipMemcpyAsync(din + o_tasks, hin + o_tasks, o_smap + sizeof(int4) * smap.size() - o_tasks,
+                         hipMemcpyHostToDevice, st));
     hc.mark(0);
     if (!smap.empty())
       launch_scan((const ScanTask*)(hmap + o_tasks), (const int4*)(hmap + o_smap), (int)smap.size(), st);
     hc.mark(1);
     if (!spec) {
+      if (noalloc && scan_words)
+        DEV(hipMemcpyAsync(hin + o_scan0, din + o_scan0, scan_words * 4, hipMemcpyDeviceToHost, st));
       DEV(hipStreamSynchronize(st));
       hc.mark(2);
       for (int i = 0; i < nj; ++i) {
         if (w[i].status) continue;
         for (int which = 0; which < nsrc(i); ++which) {
           const int rows = shp(i, which).rows;
-          const int32_t* v = (const int32_t*)(h_in.b() + w[i].o_scan[which]);
+          const int32_t* v = (const int32_t*)(hin + w[i].o_scan[which]);
           RowStats& rs = which ? w[i].stg : w[i].stf;
           rs.v.assign(v, v + ROWSTAT_WORDS * (size_t)rows);
         }
@@ -508,7 +533,8 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     std::lock_guard<std::mutex> lk(cx->tune_mu);
     cx->last_key = key;
   }
-  const bool fused = P->fused = !debug && instances > 0 && schedule_for(cx, key) == BIRES_SCHEDULE_FUSED;
+  const bool fused = P->fused =
+      !debug && !noalloc && instances > 0 && schedule_for(cx, key) == BIRES_SCHEDULE_FUSED;
   // staged schedule: explicit CRT straight to limbs when the prime counts allow
   std::vector<std::pair<const uint32_t*, int>> crt(nj, {nullptr, 0});
   bool use_crt = !debug && !fused && crt_ok(maxP);
@@ -518,7 +544,8 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     if (w[i].status || !w[i].active) continue;
     if (w[i].pl.P != lastP) {  // consecutive jobs mostly share P
       lastP = w[i].pl.P;
-      lastd = crt_device(cx, lastP, &lastLM);
+      // allocation-free calls use only operand tables that already exist
+      lastd = noalloc ? crt_device_cached(cx, lastP, &lastLM) : crt_device(cx, lastP, &lastLM);
     }
     if (!lastd) use_crt = false;
     crt[i] = {lastd, lastLM};
@@ -528,7 +555,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   // share D and P (all active jobs of the batch)
   std::vector<int> group;
   int gD = 0, gP = 0;
-  for (int i = 0; i < nj && !debug && !fused; ++i) {
+  for (int i = 0; i < nj && !debug && !fused && !noalloc; ++i) {
     if (w[i].status || !w[i].active) continue;
     if (group.empty()) {
       gD = w[i].pl.D;
@@ -545,7 +572,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   // the per-(job, prime) interpolation kernel reads its block tables
   const uint32_t *itW = nullptr, *itQ = nullptr;
   int itNB = 0;
-  if (group.empty() && !fused && !debug &&
+  if (group.empty() && !fused && !debug && !noalloc &&
       !interp_tables_device(cx, interp_table_blocks(maxD), maxP, st, &itW, &itQ, &itNB)) {
     itW = itQ = nullptr;
     itNB = 0;
@@ -591,16 +618,28 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   const size_t o_ctroff = ws.take(sizeof(int) * (nj + 1));
   const size_t o_ctr = ws.take(sizeof(int) * ((size_t)ctr_off[nj] + 2));  // counters, head, err
   const size_t meta_end = ws.bytes;
-  Held& d_ws = P->d_ws;
-  Held& h_meta = P->h_meta;
-  Held& h_out = P->h_out;
-  d_ws.take(&cx->dev, ws.bytes);
-  h_meta.take(&cx->host, meta_end - meta_begin);
-  h_out.take(&cx->host, hout.bytes);
-  if ((ws.bytes && !d_ws.p) || (meta_end > meta_begin && !h_meta.p) || (hout.bytes && !h_out.p))
-    return BIRES_ENOMEM;
-  uint8_t* const D0 = d_ws.b();
-  uint8_t* const H0 = h_meta.b() - meta_begin;  // H0 + offset addresses the metadata image
+  uint8_t* D0 = nullptr;
+  uint8_t* H0 = nullptr;  // H0 + offset addresses the metadata image
+  if (noalloc) {
+    // the workspace follows the input region in the scratch array
+    const size_t base = (in.bytes + 255) & ~(size_t)255;
+    if (base + ws.bytes > cx->scratch_bytes) return BIRES_ETOOBIG;
+    D0 = cx->scratch + base;
+    P->hv_meta.resize(meta_end - meta_begin);
+    P->hv_out.resize(hout.bytes);
+    H0 = P->hv_meta.data() - meta_begin;
+    P->hout_base = P->hv_out.data();
+  } else {
+    P->d_ws.take(&cx->dev, ws.bytes);
+    P->h_meta.take(&cx->host, meta_end - meta_begin);
+    P->h_out.take(&cx->host, hout.bytes);
+    if ((ws.bytes && !P->d_ws.p) || (meta_end > meta_begin && !P->h_meta.p) || (hout.bytes && !P->h_out.p))
+      return BIRES_ENOMEM;
+    D0 = P->d_ws.b();
+    H0 = P->h_meta.b() - meta_begin;
+    P->hout_base = P->h_out.b();
+  }
+  uint8_t* const hob = P->hout_base;
 
   int32_t* h_flags = P->h_flags = (int32_t*)(H0 + o_flags);
   std::memset(H0 + o_fbc, 0, sizeof(int) * NRG);
@@ -721,7 +760,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     f_blocks = total ? fused_blocks(f_lds, total) : 0;
     if (total && f_blocks <= 0) return BIRES_EDEVICE;
   }
-  const bool use_graph = cx->graphs && !debug;
+  const bool use_graph = cx->graphs && !debug && !noalloc;
   const bool timing = P->timing = cx->timing && nb_ee > 0 && !use_graph;
   if (timing) {
     DEV(hipEventCreate(&P->ev0));
@@ -732,21 +771,26 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   const int32_t* spec_got = nullptr;
   if (spec) {
     uint8_t* hmap = nullptr;
-    DEV(hipHostGetDevicePointer((void**)&hmap, h_in.p, 0));
+    DEV(hipHostGetDevicePointer((void**)&hmap, hin, 0));
     spec_got = (const int32_t*)(hmap + o_scan0);
   }
   // the metadata block is uploaded by a kernel that reads it through the
   // pinned block's device mapping (all its regions are whole words)
+  // (allocation-free calls copy it from ordinary host memory)
   const uint32_t* meta_mapped = nullptr;
-  if (meta_end > meta_begin) {
+  if (meta_end > meta_begin && !noalloc) {
     uint8_t* m = nullptr;
-    DEV(hipHostGetDevicePointer((void**)&m, h_meta.p, 0));
+    DEV(hipHostGetDevicePointer((void**)&m, P->h_meta.p, 0));
     meta_mapped = (const uint32_t*)m;
   }
   auto seq = [&](bool run, SeqHash& sg) -> int {
     sg.add(st, D0, meta_begin, meta_end, (const void*)meta_mapped);
-    if (run && meta_end > meta_begin)
-      launch_upload(meta_mapped, (uint32_t*)(D0 + meta_begin), (long long)((meta_end - meta_begin) / 4), st);
+    if (run && meta_end > meta_begin) {
+      if (noalloc)
+        DEV(hipMemcpyAsync(D0 + meta_begin, H0 + meta_begin, meta_end - meta_begin, hipMemcpyHostToDevice, st));
+      else
+        launch_upload(meta_mapped, (uint32_t*)(D0 + meta_begin), (long long)((meta_end - meta_begin) / 4), st);
+    }
     if (spec) {
       sg.add((const void*)spec_got, (const void*)d_image, scan_words);
       if (run)
@@ -807,9 +851,9 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     for (int i = 0; i < nj; ++i) {
       const Work& x = w[i];
       if (x.status || !x.active || mem != BIRES_MEM_HOST) continue;
-      sg.add(i, (const void*)h_out.b(), x.o_hout, x.o_out, x.degcap, x.Lout);
+      sg.add(i, (const void*)hob, x.o_hout, x.o_out, x.degcap, x.Lout);
       if (run)
-        DEV(hipMemcpyAsync(h_out.b() + x.o_hout, D0 + x.o_out, (size_t)(x.degcap + 1) * x.Lout * 4,
+        DEV(hipMemcpyAsync(hob + x.o_hout, D0 + x.o_out, (size_t)(x.degcap + 1) * x.Lout * 4,
                            hipMemcpyDeviceToHost, st));
     }
     return BIRES_OK;
@@ -854,9 +898,11 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     P->in_flight = false;
     return BIRES_OK;
   }
-  P->done = take_event(cx);
-  if (!P->done) return BIRES_EDEVICE;
-  DEV(hipEventRecord(P->done, st));
+  if (!noalloc) {
+    P->done = take_event(cx);
+    if (!P->done) return BIRES_EDEVICE;
+    DEV(hipEventRecord(P->done, st));
+  }
   hc.mark(4);
   *pending = std::move(P);
   return BIRES_OK;
@@ -886,7 +932,10 @@ int run_batch_finish(PendingPtr P) {
   const size_t scan_words = P->scan_words;
   SpecCache& sc = cx->spec;
   hc.resume();
-  DEV(hipEventSynchronize(P->done));
+  if (P->noalloc)
+    DEV(hipStreamSynchronize(P->st));
+  else
+    DEV(hipEventSynchronize(P->done));
   P->in_flight = false;
   if (P->timing) {
     float ms = 0.f;
@@ -964,7 +1013,7 @@ int run_batch_finish(PendingPtr P) {
           x.status = BIRES_ECHECK;
         } else {
           if (mem == BIRES_MEM_HOST)
-            std::memcpy(o->c, P->h_out.b() + x.o_hout, (size_t)(x.degcap + 1) * x.Lout * 4);
+            std::memcpy(o->c, P->hout_base + x.o_hout, (size_t)(x.degcap + 1) * x.Lout * 4);
           o->degree = h_flags[2 * i];
         }
       } else {
@@ -988,6 +1037,18 @@ int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t 
   PendingPtr p;
   const int e = launch_impl(cx, jobs, mem, st, status, debug_values, debug_shape, &p);
   if (e || !p) return e;
+  return run_batch_finish(std::move(p));
+}
+
+int run_batch_noalloc(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t st, int32_t* status) {
+  // one call at a time: every call shares the scratch array
+  std::lock_guard<std::mutex> lk(cx->scratch_mu);
+  PendingPtr p;
+  const int e = launch_impl(cx, jobs, mem, st, status, nullptr, nullptr, &p, true);
+  if (e || !p) {
+    if (p) (void)hipStreamSynchronize(st);
+    return e;
+  }
   return run_batch_finish(std::move(p));
 }
 

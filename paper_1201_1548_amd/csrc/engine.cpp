@@ -132,6 +132,10 @@ static int init_context(Context& cx) {
   HIP_OK(hipMalloc(&d_invp, invp.size() * sizeof(double)));
   HIP_OK(hipMemcpy(d_invp, invp.data(), invp.size() * sizeof(double), hipMemcpyHostToDevice));
   cx.tab.inv_p = d_invp;
+  {
+    const int e = scratch_address(&cx.scratch, &cx.scratch_bytes);
+    if (e) return e;
+  }
   tune_load(&cx);
   return BIRES_OK;
 }
@@ -153,6 +157,14 @@ const uint32_t* crt_device(Context* cx, int P, int* LM) {
     }
     it = cx->crt.emplace(P, std::make_pair((const uint32_t*)d, h.LM)).first;
   }
+  *LM = it->second.second;
+  return it->second.first;
+}
+
+const uint32_t* crt_device_cached(Context* cx, int P, int* LM) {
+  std::lock_guard<std::mutex> lk(cx->crt_mu);
+  auto it = cx->crt.find(P);
+  if (it == cx->crt.end()) return nullptr;
   *LM = it->second.second;
   return it->second.first;
 }
@@ -245,14 +257,21 @@ const int8_t* vinv_device(Context* cx, int D, int P, hipStream_t st) {
 // buffers (pools, tables, cached graphs, the plan cache's statistics copy) are
 // not freed from a static destructor, which may run after the HIP runtime has
 // shut down.
+static std::atomic<Context*> g_ready{nullptr};
+
 Context* context(int* err) {
   static Context* cx = new Context;
   static std::once_flag once;
   static int status = BIRES_OK;
-  std::call_once(once, [] { status = init_context(*cx); });
+  std::call_once(once, [] {
+    status = init_context(*cx);
+    if (status == BIRES_OK) g_ready.store(cx, std::memory_order_release);
+  });
   *err = status;
   return status == BIRES_OK ? cx : nullptr;
 }
+
+Context* context_if_ready() { return g_ready.load(std::memory_order_acquire); }
 
 static int log2_bucket(long long v) {
   int b = 0;

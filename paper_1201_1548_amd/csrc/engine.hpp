@@ -111,7 +111,17 @@ struct Context {
   std::mutex vinv_mu;
   std::map<std::pair<int, int>, const int8_t*> vinv;   // (D, P) -> inverse Vandermonde digit planes
   size_t vinv_total = 0;
+  // the fixed device array of allocation-free calls (its device address on
+  // this context's device, from the symbol lookup at set-up) and the lock
+  // that gives it to one call at a time
+  uint8_t* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  std::mutex scratch_mu;
 };
+
+// Device address of the allocation-free calls' scratch array on the current
+// device (symbol lookup; csrc/scratch.hip) and its size in bytes.
+int scratch_address(uint8_t** ptr, size_t* bytes);
 
 // Captured device sequences keyed by the hash of their call arguments:
 // graph_launch launches a cached one (false if absent or the launch failed);
@@ -133,6 +143,8 @@ bool interp_tables_device(Context* cx, int blocks, int primes, hipStream_t st, c
 
 // Device copy of crt_tables(P), built on first use and kept (nullptr on failure).
 const uint32_t* crt_device(Context* cx, int P, int* LM);
+// The same when it already exists, else nullptr (never allocates).
+const uint32_t* crt_device_cached(Context* cx, int P, int* LM);
 
 // Autotuning key of a planned batch: log2-buckets of the total (prime, point)
 // instances, of the largest m + n and of the largest prime count.
@@ -145,6 +157,9 @@ void tune_store(Context* cx, const std::string& key, int schedule);
 
 // Returns the initialised context or nullptr (err set).
 Context* context(int* err);
+// The context if set-up has already run and succeeded, else nullptr (never
+// initialises).
+Context* context_if_ready();
 
 // One job of a batch as the caller described it.
 struct JobIn {
@@ -158,6 +173,11 @@ struct JobIn {
 // status[i] receives each job's code; the return value is the first error.
 int run_batch(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t stream, int32_t* status,
               std::vector<uint32_t>* debug_values = nullptr, std::vector<int>* debug_shape = nullptr);
+// The same without allocating device or pinned memory: the call's device
+// buffers lie in the scratch array (BIRES_ETOOBIG when they do not fit), its
+// host staging in ordinary memory; staged schedule, per-job interpolation,
+// the explicit CRT only where its tables already exist.  Calls are serialised.
+int run_batch_noalloc(Context* cx, const std::vector<JobIn>& jobs, int mem, hipStream_t stream, int32_t* status);
 
 // The same in two halves: run_batch_launch issues the device work and returns
 // (its state in *pending, or an error before anything was queued);
