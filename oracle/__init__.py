@@ -17,6 +17,11 @@ Computation of Planar Algebraic Curves"):
                      modular gcd of Section 5.1 ("Computing gcds in Z[x]")
                      reconstructs; plus gcd over F_p for certificates.
 * ``closed_forms``-- inputs whose resultant is known in closed form.
+* ``squarefree``  -- Yun's square-free decomposition in Z[x].
+* ``subresultants``-- principal subresultant coefficients (determinant
+                     definition of Section 3.2.2), the chain S_i and the
+                     bounds N^- and N^+ of the same section, and the
+                     resultant Q = res(f_x, f_y; y).
 
 Precision: all arithmetic is exact (Python's unbounded integers and
 ``fractions.Fraction``). Pins that tie this oracle to the mathematics rather
