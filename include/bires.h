@@ -9,6 +9,8 @@
  *     is the same with x and y exchanged;
  *   - res(f, f_y; y), the resultant the curve analysis projects with
  *     (Section 3.1, Project);
+ *   - Q = res(f_x, f_y; y), the resultant behind the fiber bound n_alpha^+
+ *     (Section 3.2.2, "Computation of n_alpha^+", Teissier's lemma);
  *   - gcd(a, b) in Z[x] (Section 5.1, "Computing gcds in Z[x]").
  * All results are exact integers.  They are computed by the multi-modular
  * scheme of Section 5.1 ("Computing resultants in Z[x,y]", steps (a)-(e)):
@@ -76,6 +78,7 @@ extern "C" {
 
 #define BIRES_KIND_RESULTANT 0     /* res(f, g; var) */
 #define BIRES_KIND_DISCRIMINANT 1  /* res(f, df/dvar; var); g ignored */
+#define BIRES_KIND_POLAR 2         /* res(df/dother, df/dvar; var); g ignored */
 
 /* Compiled limits. */
 #define BIRES_MAX_PRIMES 2048      /* primes per job (each above 2^30): results below ~2^62000 */
@@ -122,6 +125,58 @@ int bires_discriminant_bounds(const bires_bipoly *f, int var, int32_t *max_degre
  * deg_var f >= 1 (else BIRES_EINVAL). */
 int bires_discriminant(const bires_bipoly *f, int var, bires_upoly *out, int mem, void *stream);
 
+/* Output sizes for res(df/dother, df/dvar; var) (other: the variable that is
+ * not eliminated). */
+int bires_polar_bounds(const bires_bipoly *f, int var, int32_t *max_degree, int32_t *max_limbs);
+
+/* Q = res(f_x, f_y; y) for var = BIRES_VAR_Y (res(f_y, f_x; x) for
+ * BIRES_VAR_X): the resultant whose root multiplicities give the fiber bound
+ * n_alpha^+ = deg_y f - mult(R, alpha) + mult(Q, alpha) (Section 3.2.2,
+ * "Computation of n_alpha^+").  The paper takes Q = res(f_x*, f_y*; y) with
+ * f_x* = f_x / h, f_y* = f_y / h, h = gcd(f_x, f_y) (the remark after
+ * Teissier's lemma); this call computes the case h = 1, which holds for a
+ * curve in generic position, and does not remove a common factor.  The
+ * formal degrees are the degrees in var of the two derivatives as bivariate
+ * polynomials.  Needs deg_var f >= 1 (else BIRES_EINVAL); f_x = 0 gives the
+ * zero polynomial. */
+int bires_polar_resultant(const bires_bipoly *f, int var, bires_upoly *out, int mem, void *stream);
+
+/* Principal subresultant coefficients modulo one prime (Section 3.2.2,
+ * "(Exact) Computation of N" and "Computation of N^-"): for the Sylvester
+ * operands of `kind` (f and g; f and df/dvar; df/dother and df/dvar) with
+ * formal degrees m, n in var, sr_i(x) mod p for i = 0 .. count-1, where
+ * count = min(m, n) + 1, less one when m = n; sr_i is the coefficient of
+ * var^i of the i-th subresultant, the determinant of the Sylvester-like
+ * matrix with n - i rows of the first operand and m - i of the second; sr_0
+ * is the resultant.  The formal degrees are kept where p divides a leading
+ * coefficient (sr_i mod p is the reduction of the integer sr_i).  Output:
+ * out[i * points + c] = coefficient of x^c (other variable) of sr_i mod p, in
+ * [0, p), for c < points = the resultant's degree bound + 1 (which bounds
+ * every sr_i).  p must be one of the library's primes (bires_primes), else
+ * BIRES_EINVAL.  Inputs and out are host memory.  *count and *points are
+ * written first; BIRES_EBUFSIZE when capacity < count * points (no device
+ * work then).  A zero operand gives BIRES_EINVAL. */
+int bires_psc(const bires_bipoly *f, const bires_bipoly *g, int kind, int var, uint32_t p, uint32_t *out,
+              int64_t capacity, int32_t *count, int32_t *points, void *stream);
+
+/* The modular generic-position test of Section 3.2.2 for a curve f with
+ * no vertical asymptote (lc_var f constant), with R = res(f, df/dvar; var),
+ * its square-free part R* (e.g. the product of bires_squarefree's factors)
+ * and deg R, over the one prime p (a library prime, else BIRES_EINVAL):
+ *   N^- = sum_{i >= 1} (n - i) deg R_i^(p)                  (eq. lower-bound),
+ *   N^+ = deg R* n - deg R + deg gcd(R^inf mod p, Q mod p)   (eq. up-bound),
+ * n = deg_var f, R_i^(p) = S_{i-1} / S_i with S_0 = R* mod p and S_i =
+ * gcd(S_{i-1}, sr_i(f, df/dvar) mod p), Q = res(df/dother, df/dvar; var) (the
+ * case gcd(f_x, f_y) = 1 of the remark after Teissier's lemma), gcd(R^inf, Q)
+ * the common factors of R* and Q with their multiplicity in Q.  N^- <= N <=
+ * N^+ (N the number of distinct points in the x-critical fibers) when p is
+ * not unlucky, and N^- = N^+ certifies n_alpha = n_alpha^+ in every fiber.
+ * *flags: bit 0 p divides lc_var f; bit 1 p divides lc(R*); bit 2 Q = 0 mod
+ * p; with any bit set the bounds are not certified.  f and rstar are host
+ * memory; deg_var f >= 1 (else BIRES_EINVAL). */
+int bires_fiber_bounds(const bires_bipoly *f, int var, const bires_upoly *rstar, int32_t deg_r, uint32_t p,
+                       int64_t *n_minus, int64_t *n_plus, int32_t *flags, void *stream);
+
 /* Output sizes for gcd(a, b): degree <= min(deg a, deg b); coefficient bits from
  * the Landau-Mignotte bound 2^d * ||a||_2 of a divisor of degree d. */
 int bires_gcd_bounds(const bires_upoly *a, const bires_upoly *b, int32_t *max_degree, int32_t *max_limbs);
@@ -151,9 +206,10 @@ int bires_squarefree(const bires_upoly *r, bires_upoly *unit, bires_upoly *facto
 
 /* For callers that cannot allocate (tight serving loops, harnesses that
  * forbid device allocation after start-up): res(f, g; var) for kind
- * BIRES_KIND_RESULTANT, or res(f, df/dvar; var) for BIRES_KIND_DISCRIMINANT
- * (g then ignored), with the same arguments, results and errors as
- * bires_resultant / bires_discriminant, but without allocating: no device or
+ * BIRES_KIND_RESULTANT, res(f, df/dvar; var) for BIRES_KIND_DISCRIMINANT or
+ * res(df/dother, df/dvar; var) for BIRES_KIND_POLAR (g then ignored), with
+ * the same arguments, results and errors as bires_resultant /
+ * bires_discriminant / bires_polar_resultant, but without allocating: no device or
  * pinned host memory is allocated or freed by the call.  Every device buffer
  * of the call lies in one fixed array of BIRES_NOALLOC_SCRATCH_BYTES that the
  * library holds on its device from set-up until the process ends; host-side
@@ -171,7 +227,8 @@ int bires_resultant_noalloc(const bires_bipoly *f, const bires_bipoly *g, int ki
                             int mem, void *stream);
 
 /* n independent jobs in one batched launch sequence.  kind[i] is a
- * BIRES_KIND_*; var[i] a BIRES_VAR_*; g[i] is ignored for discriminants.
+ * BIRES_KIND_*; var[i] a BIRES_VAR_*; g[i] is ignored for the kinds that
+ * derive both operands from f (discriminant, polar).
  * status[i] receives the per-job code; the return value is BIRES_OK when
  * every job succeeded, else the first failing job's code.  Results equal those
  * of the single-job calls bit for bit. */

@@ -20,7 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 VAR_X, VAR_Y = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
-KIND_RESULTANT, KIND_DISCRIMINANT = 0, 1
+KIND_RESULTANT, KIND_DISCRIMINANT, KIND_POLAR = 0, 1, 2
+_KINDS = {"res": KIND_RESULTANT, "disc": KIND_DISCRIMINANT, "polar": KIND_POLAR}
 
 ERRORS = {
     -1: "EINVAL", -2: "EBUFSIZE", -3: "ENOMEM", -4: "ETOOBIG",
@@ -56,6 +57,16 @@ _SIGS = {
                                    ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "bires_discriminant": ([ctypes.POINTER(Bipoly), ctypes.c_int, ctypes.POINTER(Upoly), ctypes.c_int,
                             ctypes.c_void_p], ctypes.c_int),
+    "bires_polar_bounds": ([ctypes.POINTER(Bipoly), ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
+                            ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "bires_polar_resultant": ([ctypes.POINTER(Bipoly), ctypes.c_int, ctypes.POINTER(Upoly), ctypes.c_int,
+                               ctypes.c_void_p], ctypes.c_int),
+    "bires_psc": ([ctypes.POINTER(Bipoly), ctypes.POINTER(Bipoly), ctypes.c_int, ctypes.c_int, ctypes.c_uint32,
+                   ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                   ctypes.c_void_p], ctypes.c_int),
+    "bires_fiber_bounds": ([ctypes.POINTER(Bipoly), ctypes.c_int, ctypes.POINTER(Upoly), ctypes.c_int32,
+                            ctypes.c_uint32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                            ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p], ctypes.c_int),
     "bires_gcd_bounds": ([ctypes.POINTER(Upoly), ctypes.POINTER(Upoly), ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "bires_gcd": ([ctypes.POINTER(Upoly), ctypes.POINTER(Upoly), ctypes.POINTER(Upoly), ctypes.c_int,
@@ -211,10 +222,22 @@ def _bounds(kind, fd, gd, var):
     if kind == KIND_RESULTANT:
         _check(lib().bires_resultant_bounds(ctypes.byref(fd), ctypes.byref(gd), var, ctypes.byref(deg),
                                             ctypes.byref(L)), "bires_resultant_bounds")
-    else:
+    elif kind == KIND_DISCRIMINANT:
         _check(lib().bires_discriminant_bounds(ctypes.byref(fd), var, ctypes.byref(deg), ctypes.byref(L)),
                "bires_discriminant_bounds")
+    else:
+        _check(lib().bires_polar_bounds(ctypes.byref(fd), var, ctypes.byref(deg), ctypes.byref(L)),
+               "bires_polar_bounds")
     return deg.value, L.value
+
+
+def _kind(kind):
+    """Job kind code of 'res', 'disc' (res(f, df/dvar)) or 'polar' (res(df/dother, df/dvar))."""
+    if kind in _KINDS.values():
+        return kind
+    if kind not in _KINDS:
+        raise ValueError("kind must be 'res', 'disc' or 'polar'")
+    return _KINDS[kind]
 
 
 def _var(var):
@@ -257,12 +280,28 @@ def discriminant(F, var="y", stream=None):
     return limbs_to_ints(out[: od.degree + 1])
 
 
+def polar_resultant(F, var="y", stream=None):
+    """res(df/dother, df/dvar; var) -- for var 'y' the Q = res(f_x, f_y; y) of the
+    fiber bound n_alpha^+ (generic case gcd(f_x, f_y) = 1) -- as a list of
+    Python ints (host-memory call)."""
+    v = _var(var)
+    fa = bipoly_array(F)
+    fd = _desc(fa)
+    deg, L = _bounds(KIND_POLAR, fd, fd, v)
+    out = np.zeros((deg + 1, L), dtype=np.uint32)
+    od = Upoly(deg, L, out.ctypes.data)
+    _check(lib().bires_polar_resultant(ctypes.byref(fd), v, ctypes.byref(od), MEM_HOST, _stream(stream)),
+           "bires_polar_resultant")
+    return limbs_to_ints(out[: od.degree + 1])
+
+
 def resultant_noalloc(F, G=None, kind="res", var="y", stream=None, device=False):
-    """res(f, g; var) (kind "res") or res(f, df/dvar; var) (kind "disc") through
+    """res(f, g; var) (kind "res"), res(f, df/dvar; var) (kind "disc") or
+    res(df/dother, df/dvar; var) (kind "polar") through
     the allocation-free entry point bires_resultant_noalloc.  device=True
     passes device-memory inputs and output (torch tensors), else host memory.
     The library must be set up first (init())."""
-    k = KIND_DISCRIMINANT if kind == "disc" else KIND_RESULTANT
+    k = _kind(kind)
     v = _var(var)
     fa = bipoly_array(F)
     ga = bipoly_array(G) if k == KIND_RESULTANT else fa
@@ -284,6 +323,51 @@ def resultant_noalloc(F, G=None, kind="res", var="y", stream=None, device=False)
     _check(lib().bires_resultant_noalloc(ctypes.byref(fd), ctypes.byref(gd), k, v, ctypes.byref(od), MEM_DEVICE,
                                          _stream(stream)), "bires_resultant_noalloc")
     return limbs_to_ints(tout.cpu().numpy().view(np.uint32)[: od.degree + 1])
+
+
+def psc(F, G=None, kind="res", var="y", prime=None, stream=None):
+    """Principal subresultant coefficients modulo one library prime
+    (bires_psc): returns (p, [sr_0 mod p, sr_1 mod p, ...]), each a trimmed list
+    of ints in [0, p) in ascending powers of the other variable.  prime: a
+    library prime (default: the first, primes(1)[0])."""
+    k = _kind(kind)
+    p = primes(1)[0] if prime is None else int(prime)
+    fa = bipoly_array(F)
+    ga = bipoly_array(G) if k == KIND_RESULTANT else fa
+    fd, gd = _desc(fa), _desc(ga)
+    count = ctypes.c_int32()
+    pts = ctypes.c_int32()
+    code = lib().bires_psc(ctypes.byref(fd), ctypes.byref(gd), k, _var(var), p, None, 0, ctypes.byref(count),
+                           ctypes.byref(pts), _stream(stream))
+    if code != E_BUFSIZE and code != 0:
+        _check(code, "bires_psc")
+    n = count.value * pts.value
+    out = np.zeros(max(n, 1), dtype=np.uint32)
+    if n:
+        _check(lib().bires_psc(ctypes.byref(fd), ctypes.byref(gd), k, _var(var), p, out.ctypes.data, n,
+                               ctypes.byref(count), ctypes.byref(pts), _stream(stream)), "bires_psc")
+    rows = []
+    for i in range(count.value):
+        r = [int(v) for v in out[i * pts.value:(i + 1) * pts.value]]
+        while r and r[-1] == 0:
+            r.pop()
+        rows.append(r)
+    return p, rows
+
+
+def fiber_bounds(F, rstar, deg_r, var="y", prime=None, stream=None):
+    """(N^-, N^+, flags) of the modular generic-position test (bires_fiber_bounds)
+    for the curve F, the square-free part rstar of R = res(f, f_y; y) and deg R."""
+    p = primes(1)[0] if prime is None else int(prime)
+    fa = bipoly_array(F)
+    fd = _desc(fa)
+    ra, rd = _upoly_in(rstar)
+    nm = ctypes.c_int64()
+    npl = ctypes.c_int64()
+    fl = ctypes.c_int32()
+    _check(lib().bires_fiber_bounds(ctypes.byref(fd), _var(var), ctypes.byref(rd), int(deg_r), p, ctypes.byref(nm),
+                                    ctypes.byref(npl), ctypes.byref(fl), _stream(stream)), "bires_fiber_bounds")
+    return nm.value, npl.value, fl.value
 
 
 def init():
@@ -352,7 +436,8 @@ def squarefree(r, stream=None):
 
 
 def resultant_batch(jobs, stream=None):
-    """jobs: list of (kind, F, G, var) with kind 'res' or 'disc' (G ignored for 'disc').
+    """jobs: list of (kind, F, G, var) with kind 'res', 'disc' or 'polar' (G ignored
+    unless 'res').
     Returns (results, statuses); one batched launch sequence for all jobs."""
     n = len(jobs)
     keep = []
@@ -363,7 +448,7 @@ def resultant_batch(jobs, stream=None):
     outs = (Upoly * n)()
     bufs = []
     for i, (kind, F, G, var) in enumerate(jobs):
-        k = KIND_DISCRIMINANT if kind == "disc" else KIND_RESULTANT
+        k = _kind(kind)
         fa = bipoly_array(F)
         ga = bipoly_array(G) if k == KIND_RESULTANT else fa
         keep += [fa, ga]
@@ -388,7 +473,7 @@ def resultant_batch(jobs, stream=None):
 
 def plan(F, G=None, kind="res", var="y"):
     """(points D, primes P, log2 of the coefficient bound) of a job; host-only."""
-    k = KIND_DISCRIMINANT if kind == "disc" else KIND_RESULTANT
+    k = _kind(kind)
     fa = bipoly_array(F)
     ga = bipoly_array(G) if G is not None else fa
     fd, gd = _desc(fa), _desc(ga)
@@ -402,7 +487,7 @@ def plan(F, G=None, kind="res", var="y"):
 
 def bounds(F, G=None, kind="res", var="y"):
     """(max degree, max limbs) from the extents of the inputs; host-only."""
-    k = KIND_DISCRIMINANT if kind == "disc" else KIND_RESULTANT
+    k = _kind(kind)
     fa = bipoly_array(F)
     ga = bipoly_array(G) if G is not None else fa
     return _bounds(k, _desc(fa), _desc(ga), _var(var))
@@ -416,7 +501,7 @@ def primes(n):
 
 def debug_values(F, G=None, kind="res", var="y"):
     """Stage view: (primes, values[P][D]) of the univariate resultants at a = 0..D-1."""
-    k = KIND_DISCRIMINANT if kind == "disc" else KIND_RESULTANT
+    k = _kind(kind)
     D, P, _ = plan(F, G, kind, var)
     fa = bipoly_array(F)
     ga = bipoly_array(G) if G is not None else fa
@@ -534,7 +619,7 @@ class DeviceBatch:
         self.out_tensors = []
         self.caps = []
         for i, (kind, F, G, var) in enumerate(jobs):
-            k = KIND_DISCRIMINANT if kind == "disc" else KIND_RESULTANT
+            k = _kind(kind)
             fdev = DeviceBipoly(F, device=device)
             gdev = DeviceBipoly(G, device=device) if k == KIND_RESULTANT else fdev
             self.inputs.append((fdev, gdev))
@@ -599,16 +684,20 @@ class DeviceBatch:
         return {0: "staged", 1: "fused"}[chosen.value]
 
     def run_each(self, stream=None):
-        """The plain path: one single-job call per job (bires_resultant / bires_discriminant)."""
+        """The plain path: one single-job call per job (bires_resultant / bires_discriminant /
+        bires_polar_resultant)."""
         s = _torch_stream(stream)
         self._reset_outs()
         for i in range(self.n):
             if self.kinds[i] == KIND_RESULTANT:
                 code = lib().bires_resultant(ctypes.byref(self.fds[i]), ctypes.byref(self.gds[i]), self.vars[i],
                                              ctypes.byref(self.outs[i]), MEM_DEVICE, s)
-            else:
+            elif self.kinds[i] == KIND_DISCRIMINANT:
                 code = lib().bires_discriminant(ctypes.byref(self.fds[i]), self.vars[i], ctypes.byref(self.outs[i]),
                                                 MEM_DEVICE, s)
+            else:
+                code = lib().bires_polar_resultant(ctypes.byref(self.fds[i]), self.vars[i],
+                                                   ctypes.byref(self.outs[i]), MEM_DEVICE, s)
             _check(code, "single-job call")
 
     def results(self):
@@ -642,7 +731,7 @@ class Server:
         self.h = h
 
     def submit(self, kind, F, G=None, var="y"):
-        k = KIND_DISCRIMINANT if kind == "disc" else KIND_RESULTANT
+        k = _kind(kind)
         fa = bipoly_array(F)
         ga = bipoly_array(G) if k == KIND_RESULTANT else fa
         t = ctypes.c_uint64()

@@ -80,6 +80,16 @@ int bires_discriminant_bounds(const bires_bipoly* f, int var, int32_t* max_degre
   return bounds_job(jb, max_degree, max_limbs);
 }
 
+int bires_polar_bounds(const bires_bipoly* f, int var, int32_t* max_degree, int32_t* max_limbs) {
+  if (!f) return BIRES_EINVAL;
+  JobIn jb;
+  jb.f = *f;
+  jb.g = *f;
+  jb.var = var;
+  jb.kind = BIRES_KIND_POLAR;
+  return bounds_job(jb, max_degree, max_limbs);
+}
+
 int bires_resultant(const bires_bipoly* f, const bires_bipoly* g, int var, bires_upoly* out, int mem,
                     void* stream) {
   if (!f || !g || !out) return BIRES_EINVAL;
@@ -103,10 +113,22 @@ int bires_discriminant(const bires_bipoly* f, int var, bires_upoly* out, int mem
   return with_stream(stream, [&](Context* cx, hipStream_t st) { return run_batch(cx, jobs, mem, st, nullptr); });
 }
 
+int bires_polar_resultant(const bires_bipoly* f, int var, bires_upoly* out, int mem, void* stream) {
+  if (!f || !out) return BIRES_EINVAL;
+  std::vector<JobIn> jobs(1);
+  jobs[0].f = *f;
+  jobs[0].g = *f;
+  jobs[0].var = var;
+  jobs[0].kind = BIRES_KIND_POLAR;
+  jobs[0].out = out;
+  return with_stream(stream, [&](Context* cx, hipStream_t st) { return run_batch(cx, jobs, mem, st, nullptr); });
+}
+
 int bires_resultant_noalloc(const bires_bipoly* f, const bires_bipoly* g, int kind, int var, bires_upoly* out,
                             int mem, void* stream) {
   if (!f || !out || (kind == BIRES_KIND_RESULTANT && !g)) return BIRES_EINVAL;
-  if (kind != BIRES_KIND_RESULTANT && kind != BIRES_KIND_DISCRIMINANT) return BIRES_EINVAL;
+  if (kind != BIRES_KIND_RESULTANT && kind != BIRES_KIND_DISCRIMINANT && kind != BIRES_KIND_POLAR)
+    return BIRES_EINVAL;
   Context* cx = context_if_ready();  // never sets the library up (that allocates)
   if (!cx) return BIRES_EINVAL;
   std::vector<JobIn> jobs(1);
@@ -146,6 +168,27 @@ int bires_batch_wait(uint64_t ticket) {
   Context* cx = context(&err);
   if (!cx) return err;
   return async_wait(cx, ticket);
+}
+
+int bires_psc(const bires_bipoly* f, const bires_bipoly* g, int kind, int var, uint32_t p, uint32_t* out,
+              int64_t capacity, int32_t* count, int32_t* points, void* stream) {
+  if (!f || (kind == BIRES_KIND_RESULTANT && !g) || (capacity > 0 && !out)) return BIRES_EINVAL;
+  JobIn jb;
+  jb.f = *f;
+  jb.g = kind == BIRES_KIND_RESULTANT ? *g : *f;
+  jb.kind = kind;
+  jb.var = var;
+  return with_stream(stream, [&](Context* cx, hipStream_t st) {
+    return run_psc(cx, jb, p, out, capacity, count, points, st);
+  });
+}
+
+int bires_fiber_bounds(const bires_bipoly* f, int var, const bires_upoly* rstar, int32_t deg_r, uint32_t p,
+                       int64_t* n_minus, int64_t* n_plus, int32_t* flags, void* stream) {
+  if (!f || !rstar) return BIRES_EINVAL;
+  return with_stream(stream, [&](Context* cx, hipStream_t st) {
+    return run_fiber_bounds(cx, *f, var, *rstar, deg_r, p, n_minus, n_plus, flags, st);
+  });
 }
 
 int bires_gcd_bounds(const bires_upoly* a, const bires_upoly* b, int32_t* max_degree, int32_t* max_limbs) {

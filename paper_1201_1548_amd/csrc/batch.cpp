@@ -49,7 +49,8 @@ struct Layout {
 
 struct Work {
   Shape sf, sg;
-  bool disc = false;
+  int kind = BIRES_KIND_RESULTANT;
+  bool derived = false;  // both operands formed from f (discriminant, polar)
   RowStats stf, stg;
   Plan pl;
   int status = BIRES_OK;
@@ -81,6 +82,19 @@ struct Held {
 
 }  // namespace
 
+// Operand statistics of the kinds formed from f alone: g = df/dy for the
+// discriminant; f <- df/dx and g = df/dy for the polar resultant.  Both need
+// deg_y f >= 1.  On entry f holds the statistics of the input.
+static int derive_operand_stats(int kind, RowStats& f, RowStats& g) {
+  int top = -1;
+  for (int j = 0; j < f.rows(); ++j)
+    if (f.cnt(j)) top = j;
+  if (top < 1) return BIRES_EINVAL;
+  g = derive_stats(f);
+  if (kind == BIRES_KIND_POLAR) f = derive_stats_x(f);
+  return BIRES_OK;
+}
+
 static SpecKey key_of(const JobIn& jb) {
   SpecKey k;
   std::memset(&k, 0, sizeof k);
@@ -99,7 +113,8 @@ static bool same_key(const SpecKey& a, const JobIn& jb) {
 }
 
 static int validate(const JobIn& jb, bool need_out) {
-  if (jb.kind != BIRES_KIND_RESULTANT && jb.kind != BIRES_KIND_DISCRIMINANT) return BIRES_EINVAL;
+  if (jb.kind != BIRES_KIND_RESULTANT && jb.kind != BIRES_KIND_DISCRIMINANT && jb.kind != BIRES_KIND_POLAR)
+    return BIRES_EINVAL;
   if (jb.var != BIRES_VAR_X && jb.var != BIRES_VAR_Y) return BIRES_EINVAL;
   int e = check_bipoly(&jb.f, 0);
   if (e) return e;
@@ -247,11 +262,12 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     const JobIn& jb = jobs[i];
     w[i].status = validate(jb, !debug);
     if (w[i].status) continue;
-    w[i].disc = jb.kind == BIRES_KIND_DISCRIMINANT;
+    w[i].kind = jb.kind;
+    w[i].derived = jb.kind != BIRES_KIND_RESULTANT;
     w[i].sf = shape_of(jb.f, jb.var);
-    if (!w[i].disc) w[i].sg = shape_of(jb.g, jb.var);
+    if (!w[i].derived) w[i].sg = shape_of(jb.g, jb.var);
   }
-  auto nsrc = [&](int i) { return w[i].disc ? 1 : 2; };
+  auto nsrc = [&](int i) { return w[i].derived ? 1 : 2; };
   auto shp = [&](int i, int which) -> const Shape& { return which ? w[i].sg : w[i].sf; };
 
   // ---------------- inputs on the device, row statistics
@@ -410,21 +426,12 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   for (int i = 0; i < nj && !spec; ++i) {
     Work& x = w[i];
     if (x.status) continue;
-    if (x.disc) {
-      int top = -1;
-      for (int j = 0; j < x.stf.rows(); ++j)
-        if (x.stf.cnt(j)) top = j;
-      if (top < 1) {
-        x.status = BIRES_EINVAL;
-        continue;
-      }
-      x.stg = derive_stats(x.stf);
-    }
+    if (x.derived && (x.status = derive_operand_stats(x.kind, x.stf, x.stg))) continue;
     if ((x.status = make_plan(x.stf, x.stg, x.pl))) continue;
     if (x.pl.kind_special == 0 &&
         (x.pl.D > MAX_POINTS || interp_lds_words(x.pl.D) * 4 > cx->lds_per_block ||
          eval_elim_lds_bytes(x.pl.m + x.pl.n + 2, (x.pl.m + 1) * pad4(x.sf.ld) +
-                                                      (x.pl.n + 1) * pad4(x.disc ? x.sf.ld : x.sg.ld)) >
+                                                      (x.pl.n + 1) * pad4(x.derived ? x.sf.ld : x.sg.ld)) >
              cx->lds_per_block)) {
       x.status = BIRES_ETOOBIG;
       continue;
@@ -443,7 +450,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     }
     x.active = x.pl.kind_special == 0;
     if (x.active) {
-      x.ldg = x.disc ? x.sf.ld : x.sg.ld;
+      x.ldg = x.derived ? x.sf.ld : x.sg.ld;
       x.Tf = (x.pl.m + 1) * pad4(x.sf.ld);
       x.Tg = (x.pl.n + 1) * pad4(x.ldg);
       x.Lacc = std::min(x.Lout, x.pl.P + 1);
@@ -654,14 +661,14 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     const Plan& p = x.pl;
     JobDev& J = h_jobs[i];
     J.limbs_f = x.dev_f;
-    J.limbs_g = x.disc ? nullptr : x.dev_g;
+    J.limbs_g = x.derived ? nullptr : x.dev_g;
     J.Lf = x.sf.L;
-    J.Lg = x.disc ? x.sf.L : x.sg.L;
+    J.Lg = x.derived ? x.sf.L : x.sg.L;
     J.ldf = x.sf.ld;
     J.ldg = x.ldg;
     J.m = p.m;
     J.n = p.n;
-    J.disc = x.disc ? 1 : 0;
+    J.kind = x.kind;
     J.P = p.P;
     J.D = p.D;
     J.lpf = pad4(x.sf.ld);
@@ -1056,26 +1063,33 @@ int run_batch_noalloc(Context* cx, const std::vector<JobIn>& jobs, int mem, hipS
 
 namespace bires {
 
-int plan_host_job(const JobIn& jb, Plan& pl) {
+int host_job(const JobIn& jb, HostJob& h) {
   int e = validate(jb, false);
   if (e) return e;
   const Shape sf = shape_of(jb.f, jb.var);
-  std::vector<uint32_t> buf((size_t)sf.rows * sf.ld * sf.L);
-  if (sf.rows) pack_rect(jb.f, jb.var, buf.data());
-  RowStats stf = scan_host(buf.data(), sf.rows, sf.ld, sf.L), stg;
-  if (jb.kind == BIRES_KIND_DISCRIMINANT) {
-    int top = -1;
-    for (int j = 0; j < sf.rows; ++j)
-      if (stf.cnt(j)) top = j;
-    if (top < 1) return BIRES_EINVAL;
-    stg = derive_stats(stf);
+  h.rows_f = sf.rows, h.ld_f = sf.ld, h.L_f = sf.L;
+  h.f.assign((size_t)sf.rows * sf.ld * sf.L, 0u);
+  if (sf.rows) pack_rect(jb.f, jb.var, h.f.data());
+  h.stf = scan_host(h.f.data(), sf.rows, sf.ld, sf.L);
+  h.g.clear();
+  if (jb.kind != BIRES_KIND_RESULTANT) {
+    h.rows_g = 0, h.ld_g = sf.ld, h.L_g = sf.L;
+    if ((e = derive_operand_stats(jb.kind, h.stf, h.stg))) return e;
   } else {
     const Shape sg = shape_of(jb.g, jb.var);
-    std::vector<uint32_t> bg((size_t)sg.rows * sg.ld * sg.L);
-    if (sg.rows) pack_rect(jb.g, jb.var, bg.data());
-    stg = scan_host(bg.data(), sg.rows, sg.ld, sg.L);
+    h.rows_g = sg.rows, h.ld_g = sg.ld, h.L_g = sg.L;
+    h.g.assign((size_t)sg.rows * sg.ld * sg.L, 0u);
+    if (sg.rows) pack_rect(jb.g, jb.var, h.g.data());
+    h.stg = scan_host(h.g.data(), sg.rows, sg.ld, sg.L);
   }
-  return make_plan(stf, stg, pl);
+  return make_plan(h.stf, h.stg, h.pl);
+}
+
+int plan_host_job(const JobIn& jb, Plan& pl) {
+  HostJob h;
+  const int e = host_job(jb, h);
+  pl = h.pl;
+  return e;
 }
 
 int bounds_job(const JobIn& jb, int32_t* max_degree, int32_t* max_limbs) {
@@ -1083,9 +1097,8 @@ int bounds_job(const JobIn& jb, int32_t* max_degree, int32_t* max_limbs) {
   if (e) return e;
   const Shape sf = shape_of(jb.f, jb.var);
   RowStats stf = worst_stats(sf.rows, sf.ld, sf.L), stg;
-  if (jb.kind == BIRES_KIND_DISCRIMINANT) {
-    if (sf.rows < 2) return BIRES_EINVAL;
-    stg = derive_stats(stf);
+  if (jb.kind != BIRES_KIND_RESULTANT) {
+    if ((e = derive_operand_stats(jb.kind, stf, stg))) return e;
   } else {
     const Shape sg = shape_of(jb.g, jb.var);
     stg = worst_stats(sg.rows, sg.ld, sg.L);

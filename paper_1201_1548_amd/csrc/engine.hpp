@@ -195,11 +195,31 @@ int run_batch_finish(PendingPtr pending);
 // run_batch_finish then holds cx->stream_mu.
 void set_pending_stream_lock(PendingBatch* pending);
 
+// One host-memory job as the kernels read it: the limb rectangles packed with
+// rows = powers of the eliminated variable (g empty for the kinds derived
+// from f), the row statistics of the two Sylvester operands and the plan.
+struct HostJob {
+  std::vector<uint32_t> f, g;
+  int rows_f = 0, ld_f = 0, L_f = 1, rows_g = 0, ld_g = 0, L_g = 1;
+  RowStats stf, stg;
+  Plan pl;
+};
+int host_job(const JobIn& job, HostJob& h);
+
 // Plan of one host-memory job, and output sizes from the extents only (host-only).
 int bounds_job(const JobIn& job, int32_t* max_degree, int32_t* max_limbs);
 int plan_host_job(const JobIn& job, Plan& pl);
 // Output capacity (from the extents) and the device bytes one job holds while it runs.
 int job_footprint(const JobIn& job, int32_t* cap_degree, int32_t* cap_limbs, size_t* bytes);
+
+// Principal subresultant coefficients of a host-memory job modulo the table
+// prime p (psc.cpp): out[i * D + c] for i < *count, c < *points.
+int psc_count(int m, int n);
+int run_psc(Context* cx, const JobIn& job, uint32_t p, uint32_t* out, int64_t capacity, int32_t* count,
+            int32_t* points, hipStream_t st);
+// N^- and N^+ of Section 3.2.2 for a host-memory curve f, R* and deg R.
+int run_fiber_bounds(Context* cx, const bires_bipoly& f, int var, const bires_upoly& rstar, int32_t deg_r,
+                     uint32_t p, int64_t* n_minus, int64_t* n_plus, int32_t* flags, hipStream_t st);
 
 // Validates the descriptor of a bivariate input.
 int check_bipoly(const bires_bipoly* p, int allow_null_c);

@@ -8,14 +8,16 @@ namespace bires {
 
 // One res(f, g; y) job after planning.  All pointers are device memory.
 // f and g are dense rectangles of limbs (rows = powers of y); for a
-// discriminant the g residues are formed from f (g_{j,i} = (j+1) f_{j+1,i}).
+// discriminant the g residues are formed from f (g_{j,i} = (j+1) f_{j+1,i}),
+// for a polar resultant both operands are (f-side: (i+1) f_{j,i+1}, the
+// x-derivative; g-side: the y-derivative).
 struct JobDev {
   const uint32_t* limbs_f;  // [(m+1) * ldf * Lf]
-  const uint32_t* limbs_g;  // [(n+1) * ldg * Lg]; unused when disc
+  const uint32_t* limbs_g;  // [(n+1) * ldg * Lg]; unused unless kind == 0
   int32_t Lf, Lg;           // limbs per input coefficient
   int32_t ldf, ldg;         // row stride (coefficients) of the rectangles
   int32_t m, n;             // degrees in y (top non-zero row of f, g)
-  int32_t disc;             // 1: g = df/dy
+  int32_t kind;             // 0: g given; 1: g = df/dy; 2: f <- df/dx, g = df/dy
   int32_t P, D;             // primes, evaluation points (= degree bound + 1)
   int32_t lpf, lpg;         // row stride of the residue rows (ldf, ldg rounded up to 4)
   int32_t Tf, Tg;           // residues per prime: (m+1)*lpf, (n+1)*lpg; padding is zero
@@ -65,6 +67,17 @@ struct FusedPlan {
   int* err;              // bit 1: a dependency wait timed out
   int32_t stage_ld;      // limb-assembly staging row (0: direct writes)
   int32_t mrc_lane;      // 1: lane-per-coefficient Garner
+};
+
+// The degree chain of the N^- / N^+ test over one prime (k_fiber_chain).
+struct ChainDev {
+  const uint32_t* rstar;  // [dr + 1] R* mod p (Montgomery)
+  int32_t dr;             // its extent (leading coefficient may vanish mod p)
+  const uint32_t* srs;    // [K][D] sr_i mod p (plain), rows 1..K-1 used
+  int32_t K, D;
+  const uint32_t* qpol;   // [Dq] Q mod p (plain)
+  int32_t Dq;
+  int32_t* out;           // [K + 2]: deg S_0 .. deg S_{K-1} (0 past the end), deg gcd(R^inf, Q), Q mod p = 0
 };
 
 // Tables shared by every job: the prime list and the mixed-radix constants.

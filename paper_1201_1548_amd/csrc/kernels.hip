@@ -167,11 +167,20 @@ __device__ void dev_reduce(const JobDev& J, int lb, int k0, int k1, TablesDev ta
   }
   const uint32_t* src;
   int L;
-  uint32_t mult = 0;  // 0: none; else the derivative factor j+1
-  if (!isg) {
+  uint32_t mult = 0;  // 0: none; else the derivative factor (j+1 or i+1)
+  if (!isg && J.kind == 2) {
+    // x-derivative: coefficient (j, i) is (i+1) f_{j,i+1}; the last column is zero
+    if (i + 1 >= ld) {
+      for (int k = k0; k < k1; ++k) dst[(size_t)k * T] = 0u;
+      return;
+    }
+    src = J.limbs_f + ((size_t)j * J.ldf + i + 1) * J.Lf;
+    L = J.Lf;
+    mult = (uint32_t)(i + 1);
+  } else if (!isg) {
     src = J.limbs_f + ((size_t)j * J.ldf + i) * J.Lf;
     L = J.Lf;
-  } else if (J.disc) {
+  } else if (J.kind != 0) {
     src = J.limbs_f + ((size_t)(j + 1) * J.ldf + i) * J.Lf;  // coefficient (j+1, i) of f
     L = J.Lf;
     mult = (uint32_t)(j + 1);
@@ -495,27 +504,21 @@ __device__ __forceinline__ uint32_t eval_row(C* c, int d, const uint32_t (&pw)[N
 // scalar cache, which is valid when the residues were written by an earlier
 // launch (the staged schedule); the persistent fused launch, which writes
 // them itself, uses ordinary loads.
+// f(a, y) and g(a, y) modulo p_k (Montgomery form) at the point a = pt into
+// the lane arrays A[j W], B[j W] (ascending powers of y).
 template <int W, bool SC>
-__device__ __forceinline__ void dev_eval_elim(const JobDev& J, int lb, TablesDev tab, uint32_t* lds) {
+__device__ __forceinline__ void eval_pair(const JobDev& J, int k, int pt, const ModP& q, uint32_t* A, uint32_t* B) {
   typedef typename std::conditional<SC, cu32, const uint32_t>::type RW;
   typedef typename std::conditional<SC, cu4, const u32x4>::type RW4;
   typedef typename std::conditional<SC, ci32, const int32_t>::type RI;
-  const int nbpp = (J.D + W - 1) / W;
-  const int k = lb / nbpp;
-  const int a0 = (lb - k * nbpp) * W;
   const int m = J.m, n = J.n;
-  const int Tf = J.Tf, Tg = J.Tg, lpf = J.lpf, lpg = J.lpg;
-  RW* Rf = (RW*)(J.res_f + (size_t)k * Tf);
-  RW* Rg = (RW*)(J.res_g + (size_t)k * Tg);
+  const int lpf = J.lpf, lpg = J.lpg;
+  RW* Rf = (RW*)(J.res_f + (size_t)k * J.Tf);
+  RW* Rg = (RW*)(J.res_g + (size_t)k * J.Tg);
   RI* RDf = (RI*)J.rowdeg_f;
   RI* RDg = (RI*)J.rowdeg_g;
-  uint32_t* A = lds + threadIdx.x;
-  uint32_t* B = A + (m + 1) * W;
-  const int pt = a0 + (int)threadIdx.x;
-  if (pt >= J.D) return;
-  const ModP q = tab.primes[k];
   const uint32_t aM = to_mont((uint32_t)pt, q);
-  const int dmax = max(J.ldf, J.disc ? J.ldf : J.ldg) - 1;
+  const int dmax = max(J.ldf, J.kind ? J.ldf : J.ldg) - 1;
   uint32_t pw[EV_PW];
   pw[0] = q.one;
 #pragma unroll
@@ -525,6 +528,20 @@ __device__ __forceinline__ void dev_eval_elim(const JobDev& J, int lb, TablesDev
     A[j * W] = eval_row<RW, RW4>(Rf + j * lpf, __builtin_amdgcn_readfirstlane(RDf[j]), pw, apw, q);
   for (int j = 0; j <= n; ++j)
     B[j * W] = eval_row<RW, RW4>(Rg + j * lpg, __builtin_amdgcn_readfirstlane(RDg[j]), pw, apw, q);
+}
+
+template <int W, bool SC>
+__device__ __forceinline__ void dev_eval_elim(const JobDev& J, int lb, TablesDev tab, uint32_t* lds) {
+  const int nbpp = (J.D + W - 1) / W;
+  const int k = lb / nbpp;
+  const int a0 = (lb - k * nbpp) * W;
+  const int m = J.m, n = J.n;
+  uint32_t* A = lds + threadIdx.x;
+  uint32_t* B = A + (m + 1) * W;
+  const int pt = a0 + (int)threadIdx.x;
+  if (pt >= J.D) return;
+  const ModP q = tab.primes[k];
+  eval_pair<W, SC>(J, k, pt, q, A, B);
   const uint32_t r = uni_resultant<W>(A, B, m, n, q);
   J.vals[(size_t)k * J.D + pt] = from_mont(r, q);
 }
@@ -736,7 +753,7 @@ __device__ __forceinline__ bool dev_eval_elim_rg(const JobDev& J, int lb, Tables
   if (pt >= J.D) return true;
   const ModP q = tab.primes[k];
   const uint32_t aM = to_mont((uint32_t)pt, q);
-  const int dmax = max(J.ldf, J.disc ? J.ldf : J.ldg) - 1;
+  const int dmax = max(J.ldf, J.kind ? J.ldf : J.ldg) - 1;
   uint32_t pw[RG_PW];
   pw[0] = q.one;
 #pragma unroll
@@ -838,6 +855,147 @@ __global__ __launch_bounds__(64) void k_eval_elim_fb(const JobDev* jobs, const i
     dev_eval_elim<64, true>(jobs[job], b - starts[job], tab, lds);
   }
 }
+
+// ---------------------------------------------------------------------------
+// Principal subresultant coefficients modulo one prime (Section 3.2.2,
+// "(Exact) Computation of N" and "Computation of N^-"): sr_i(a) for every
+// index i of the formal degrees (m, n) and every point a, one lane per point.
+// sr_i is the determinant of the Sylvester-like matrix with n - i rows of f
+// and m - i rows of g restricted to the columns of y^(m+n-i-1) .. y^i.  Row
+// operations on that matrix give the recurrence the lanes run (A, B of formal
+// degrees a, b):
+//   sres_i(A, B) = (-1)^((a-i)(b-i)) sres_i(B, A)            (row blocks exchanged);
+//   a > b:  sres_b(A, B) = lc(B)^(a-b)                        (triangular matrix);
+//   formal lc(A) = 0, i < b: sres_i(A, B) = (-1)^(b-i) lc(B) sres_i(A of degree a-1, B);
+//   formal lc(B) = 0, i < b: sres_i(A, B) = lc(A) sres_i(A, B of degree b-1)
+//                             (expansion along the first column);
+//   a >= b, R = A mod B of degree c: sres_i(A, B) = 0 for c < i < b and
+//   sres_i(A, B) = (-1)^((a-i)(b-i)) lc(B)^(a-c) sres_i(B, R) for i <= c
+//   (A's rows minus multiples of B's rows are R's rows; the first a - c
+//   B-rows then form a triangular block with lc(B) on its diagonal).
+// The eliminations of eliminate() leave scaled remainders s R, whose scalar
+// s (a product of powers of leading coefficients) is tracked, so every sr_i(a)
+// is num / den with den a product of such scalars; each lane writes its
+// (num, den) pairs and inverts its denominators together (one inverse and
+// three products per index, Montgomery's simultaneous inversion).  The sign
+// of index i is (-1)^(E0 + i E1): (a-i)(b-i) = ab + i (a+b+1) mod 2.
+
+struct PscOut {
+  uint32_t* num;  // [K][D] numerators (Montgomery), then the values sr_i(a) (plain)
+  uint32_t* den;  // [K][D] denominators (Montgomery)
+  int32_t K;      // indices 0..K-1
+};
+
+template <int W>
+__device__ void psc_lane(uint32_t* A, uint32_t* B, int m, int n, int pt, int D, const ModP& q, PscOut o) {
+  uint32_t Nn = q.one, Nd = q.one;
+  int E0 = 0, E1 = 0;
+  auto emit = [&](int i, uint32_t vn, uint32_t vd) {
+    if (i >= o.K) return;  // indices above K are not asked for
+    uint32_t x = mmul(Nn, vn, q);
+    if ((E0 ^ (i & E1)) & 1) x = mneg(x, q.p);
+    o.num[(size_t)i * D + pt] = x;
+    o.den[(size_t)i * D + pt] = mmul(Nd, vd, q);
+  };
+  int a = m, b = n;
+  if (a > b)
+    emit(b, mpow(B[b * W], (uint32_t)(a - b), q), q.one);
+  else if (a < b)
+    emit(a, mpow(A[a * W], (uint32_t)(b - a), q), q.one);
+  if (a < b) {
+    uint32_t* T = A; A = B; B = T;
+    const int t = a; a = b; b = t;
+    E0 ^= (a * b) & 1;
+    E1 ^= (a + b + 1) & 1;
+  }
+  // formal degrees (only the first pair can have vanishing leading coefficients)
+  while (b >= 1) {
+    const bool za = A[a * W] == 0u, zb = B[b * W] == 0u;
+    if (!za && !zb) break;
+    if (za && zb) {  // the first column is zero
+      for (int i = 0; i < b; ++i) emit(i, 0u, q.one);
+      b = 0;
+      break;
+    }
+    if (zb) {
+      Nn = mmul(Nn, A[a * W], q);
+      --b;
+      emit(b, mpow(B[b * W], (uint32_t)(a - b), q), q.one);
+      continue;
+    }
+    E0 ^= b & 1;
+    E1 ^= 1;
+    Nn = mmul(Nn, B[b * W], q);
+    --a;
+    if (a < b) {
+      uint32_t* T = A; A = B; B = T;
+      const int t = a; a = b; b = t;
+      E0 ^= (a * b) & 1;
+      E1 ^= (a + b + 1) & 1;
+      emit(b, mpow(B[b * W], (uint32_t)(a - b), q), q.one);
+    }
+  }
+  // actual degrees from here: A = sA A*, B = sB B* with A*, B* the exact pair
+  uint32_t sA = q.one, sB = q.one;
+  while (b >= 1) {
+    const uint32_t lb = B[b * W];
+    eliminate<W>(A, B, a, b, lb, q);
+    int c = b - 1;
+    while (c >= 0 && A[c * W] == 0u) --c;
+    for (int i = c + 1; i < b; ++i) emit(i, 0u, q.one);
+    if (c < 0) break;
+    // A now holds lb^(a-b+1) sA (A* mod B*): the remainder's scalar
+    const uint32_t sR = mmul(mpow(lb, (uint32_t)(a - b + 1), q), sA, q);
+    E0 ^= (a * b) & 1;
+    E1 ^= (a + b + 1) & 1;
+    Nn = mmul(Nn, mpow(lb, (uint32_t)(a - c), q), q);
+    Nd = mmul(Nd, mpow(sB, (uint32_t)(a - c), q), q);
+    emit(c, mpow(A[c * W], (uint32_t)(b - c), q), mpow(sR, (uint32_t)(b - c), q));
+    uint32_t* T = A; A = B; B = T;
+    a = b;
+    b = c;
+    sA = sB;
+    sB = sR;
+  }
+  // simultaneous inversion of the K denominators: num_i <- num_i d_0 .. d_{i-1},
+  // then with inv = 1 / (d_0 .. d_i) from the top, num_i inv = num_i / d_i
+  uint32_t pre = q.one;
+  for (int i = 0; i < o.K; ++i) {
+    const size_t x = (size_t)i * D + pt;
+    o.num[x] = mmul(o.num[x], pre, q);
+    pre = mmul(pre, o.den[x], q);
+  }
+  uint32_t inv = minv(pre, q);
+  for (int i = o.K - 1; i >= 0; --i) {
+    const size_t x = (size_t)i * D + pt;
+    const uint32_t v = mmul(o.num[x], inv, q);
+    inv = mmul(inv, o.den[x], q);
+    o.num[x] = from_mont(v, q);
+  }
+}
+
+// One block of W lanes = W consecutive points; prime index 0 of tab (the
+// caller passes the table shifted to its prime).  LDS: (m + n + 2) W words.
+template <int W>
+__global__ __launch_bounds__(W) void k_psc(JobDev J, TablesDev tab, PscOut o) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const int pt = blockIdx.x * W + (int)threadIdx.x;
+  if (pt >= J.D) return;
+  uint32_t* A = lds + threadIdx.x;
+  uint32_t* B = A + (J.m + 1) * W;
+  const ModP q = tab.primes[0];
+  eval_pair<W, true>(J, 0, pt, q, A, B);
+  psc_lane<W>(A, B, J.m, J.n, pt, J.D, q, o);
+}
+
+void launch_psc(const JobDev& J, TablesDev tab, uint32_t* num, uint32_t* den, int K, hipStream_t s) {
+  const PscOut o{num, den, K};
+  const size_t lds = (size_t)(J.m + J.n + 2) * 64 * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_psc<64>, dim3((J.D + 63) / 64), dim3(64), lds, s, J, tab, o);
+}
+
+size_t psc_lds_bytes(int m, int n) { return (size_t)(m + n + 2) * 64 * sizeof(uint32_t); }
+
 
 // ---------------------------------------------------------------------------
 // (d) interpolation per prime on the nodes a = 0, 1, ..., D-1.
@@ -1706,29 +1864,14 @@ void launch_fused(const FusedPlan& F, size_t lds_bytes, int blocks, TablesDev ta
 // Outputs are scaled for the integer reconstruction: beta g, (lc a / beta) a/g,
 // (lc b / beta) b/g, whose images multiply to lc(a) a and lc(b) b.
 
-__global__ __launch_bounds__(256) void k_gcd_p(GcdDev G, TablesDev tab) {
-  extern __shared__ __align__(16) uint32_t lds[];
-  const int k = blockIdx.x;
-  const ModP q = tab.primes[k];
-  const int da = G.da, db = G.db;
-  const int mx = da > db ? da : db;
-  const int mn = da < db ? da : db;
-  uint32_t* A0 = lds;
-  uint32_t* B0 = A0 + da + 1;
-  uint32_t* X = B0 + db + 1;
-  uint32_t* Y = X + mx + 1;
-  uint32_t* Gm = Y + mx + 1;
+// Euclid's algorithm over F_p on X (degree a) and Y (degree b) in LDS, run by
+// the whole block, without inverses: each elimination X <- lc(Y) X - lc(X)
+// y^s Y changes X only by a unit factor, so the last non-zero remainder is an
+// associate of the gcd.  Leading coefficients must be non-zero.  Returns the
+// gcd's degree d, with an associate of the gcd in Y[0..d] (the pointers are
+// swapped as the roles alternate; both arrays need max(a, b) + 1 words).
+__device__ int block_gcd_fp(uint32_t*& X, uint32_t*& Y, int a, int b, const ModP& q) {
   const int tid = threadIdx.x;
-  const uint32_t* ra = G.res_a + (size_t)k * (da + 1);
-  const uint32_t* rb = G.res_b + (size_t)k * (db + 1);
-  for (int i = tid; i <= da; i += blockDim.x) A0[i] = X[i] = ra[i];
-  for (int i = tid; i <= db; i += blockDim.x) B0[i] = Y[i] = rb[i];
-  __syncthreads();
-  if (A0[da] == 0u || B0[db] == 0u) {
-    if (tid == 0) G.gdeg[k] = -2;
-    return;
-  }
-  int a = da, b = db;
   if (a < b) {
     uint32_t* T = X; X = Y; Y = T;
     int t = a; a = b; b = t;
@@ -1771,6 +1914,32 @@ __global__ __launch_bounds__(256) void k_gcd_p(GcdDev G, TablesDev tab) {
     a = b;
     b = c;
   }
+  return d;
+}
+
+__global__ __launch_bounds__(256) void k_gcd_p(GcdDev G, TablesDev tab) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const int k = blockIdx.x;
+  const ModP q = tab.primes[k];
+  const int da = G.da, db = G.db;
+  const int mx = da > db ? da : db;
+  const int mn = da < db ? da : db;
+  uint32_t* A0 = lds;
+  uint32_t* B0 = A0 + da + 1;
+  uint32_t* X = B0 + db + 1;
+  uint32_t* Y = X + mx + 1;
+  uint32_t* Gm = Y + mx + 1;
+  const int tid = threadIdx.x;
+  const uint32_t* ra = G.res_a + (size_t)k * (da + 1);
+  const uint32_t* rb = G.res_b + (size_t)k * (db + 1);
+  for (int i = tid; i <= da; i += blockDim.x) A0[i] = X[i] = ra[i];
+  for (int i = tid; i <= db; i += blockDim.x) B0[i] = Y[i] = rb[i];
+  __syncthreads();
+  if (A0[da] == 0u || B0[db] == 0u) {
+    if (tid == 0) G.gdeg[k] = -2;
+    return;
+  }
+  const int d = block_gcd_fp(X, Y, da, db, q);
   // monic gcd (Montgomery) in Gm; b == 0 means gcd 1
   const uint32_t inv = d ? minv(Y[d], q) : q.one;
   for (int i = tid; i <= d; i += blockDim.x) Gm[i] = d ? mmul(Y[i], inv, q) : q.one;
@@ -1802,6 +1971,111 @@ __global__ __launch_bounds__(256) void k_gcd_p(GcdDev G, TablesDev tab) {
   }
   __syncthreads();
   if (tid == 0) G.gdeg[k] = bad_any ? -3 : d;
+}
+
+// ---------------------------------------------------------------------------
+// The degree chain of the N^- / N^+ test (Section 3.2.2) over F_p, one block:
+//   S_0 = R* mod p, S_i = gcd(S_{i-1}, sr_i) (i >= 1, until S_i is constant),
+//   and deg gcd(R^inf, Q) = the degrees of the gcds removed from Q by
+//   H <- H / gcd(H, R*) until that gcd is constant.
+// Inputs in Montgomery form or plain as stated; every gcd is block_gcd_fp.
+
+// Degree of v[0..n) (-1 for zero), computed by the block.
+__device__ int block_degree(const uint32_t* v, int n, int* red) {
+  int top = -1;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    if (v[i] != 0u) top = i;
+  __syncthreads();
+  if (threadIdx.x == 0) *red = -1;
+  __syncthreads();
+  if (top >= 0) atomicMax(red, top);
+  __syncthreads();
+  const int d = *red;
+  __syncthreads();
+  return d;
+}
+
+__global__ __launch_bounds__(256) void k_fiber_chain(ChainDev C, TablesDev tab) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ int red;
+  const ModP q = tab.primes[0];
+  const int tid = threadIdx.x;
+  const int mx = max(max(C.dr + 1, C.D), C.Dq);
+  uint32_t* S = lds;            // current S_i, then R* for the common part
+  uint32_t* X = S + mx;
+  uint32_t* Y = X + mx;
+  uint32_t* H = Y + mx;         // Q / (removed gcds)
+  for (int i = tid; i < mx; i += blockDim.x) S[i] = i <= C.dr ? C.rstar[i] : 0u;
+  int ds = block_degree(S, C.dr + 1, &red);
+  const int d0 = ds;
+  if (tid == 0) C.out[0] = ds;
+  int i = 1;
+  for (; i < C.K && ds >= 1; ++i) {
+    const uint32_t* sr = C.srs + (size_t)i * C.D;
+    for (int t = tid; t < C.D; t += blockDim.x) Y[t] = to_mont(sr[t], q);
+    const int db = block_degree(Y, C.D, &red);
+    if (db >= 0) {  // gcd(S, 0) = S
+      for (int t = tid; t <= ds; t += blockDim.x) X[t] = S[t];
+      __syncthreads();
+      uint32_t* Xp = X;
+      uint32_t* Yp = Y;
+      const int d = block_gcd_fp(Xp, Yp, ds, db, q);
+      __syncthreads();
+      for (int t = tid; t <= d; t += blockDim.x) S[t] = Yp[t];
+      ds = d;
+      __syncthreads();
+    }
+    if (tid == 0) C.out[i] = ds;
+  }
+  for (; i < C.K; ++i)
+    if (tid == 0) C.out[i] = 0;
+  // the common part of R and Q with Q's multiplicities
+  for (int t = tid; t < mx; t += blockDim.x) {
+    S[t] = t <= C.dr ? C.rstar[t] : 0u;
+    H[t] = t < C.Dq ? to_mont(C.qpol[t], q) : 0u;
+  }
+  int dh = block_degree(H, C.Dq, &red);
+  int total = 0;
+  while (dh >= 1 && d0 >= 1) {
+    for (int t = tid; t <= dh; t += blockDim.x) X[t] = H[t];
+    for (int t = tid; t <= d0; t += blockDim.x) Y[t] = S[t];
+    __syncthreads();
+    uint32_t* Xp = X;
+    uint32_t* Yp = Y;
+    const int d = block_gcd_fp(Xp, Yp, dh, d0, q);
+    __syncthreads();
+    if (d == 0) break;
+    total += d;
+    // H <- H / G (G = Yp[0..d], made monic), wave 0 by synthetic division
+    const uint32_t inv = minv(Yp[d], q);
+    for (int t = tid; t <= d; t += blockDim.x) Yp[t] = mmul(Yp[t], inv, q);
+    __syncthreads();
+    if (tid < 64) {
+      for (int kq = dh - d; kq >= 0; --kq) {
+        const uint32_t qc = H[kq + d];
+        for (int t = tid; t < d; t += 64) H[kq + t] = msub(H[kq + t], mmul(qc, Yp[t], q), q.p);
+        if (tid == 0) Xp[kq] = qc;  // the quotient (Xp is free again)
+      }
+    }
+    __syncthreads();
+    dh -= d;
+    for (int t = tid; t < mx; t += blockDim.x) H[t] = t <= dh ? Xp[t] : 0u;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    C.out[C.K] = total;
+    C.out[C.K + 1] = dh < 0 ? 1 : 0;
+  }
+}
+
+size_t fiber_chain_lds_bytes(int dr, int D, int Dq) {
+  int mx = dr + 1 > D ? dr + 1 : D;
+  if (Dq > mx) mx = Dq;
+  return (size_t)4 * mx * sizeof(uint32_t);
+}
+
+void launch_fiber_chain(const ChainDev& C, TablesDev tab, hipStream_t s) {
+  hipLaunchKernelGGL(k_fiber_chain, dim3(1), dim3(256), fiber_chain_lds_bytes(C.dr, C.D, C.Dq), s, C, tab);
 }
 
 size_t gcd_lds_bytes(int da, int db) {

@@ -89,6 +89,15 @@ void launch_limbs_sum(const JobDev* jobs, const int* starts, int nj, int nblocks
 // once for this LDS size, capped at the task count (0 on a runtime error).
 int fused_blocks(size_t lds_bytes, int tasks);
 void launch_fused(const FusedPlan& F, size_t lds_bytes, int blocks, TablesDev tab, hipStream_t s);
+// Principal subresultant coefficients modulo prime index 0 of tab (the caller
+// shifts the table to its prime): one lane per point a < J.D, J.m and J.n the
+// formal degrees; writes sr_i(a) (plain) to num[i * D + a] for i < K, with
+// den ([K][D]) as workspace.
+size_t psc_lds_bytes(int m, int n);
+void launch_psc(const JobDev& J, TablesDev tab, uint32_t* num, uint32_t* den, int K, hipStream_t s);
+// The N^- / N^+ degree chain over prime index 0 of tab, one block.
+size_t fiber_chain_lds_bytes(int dr, int D, int Dq);
+void launch_fiber_chain(const ChainDev& C, TablesDev tab, hipStream_t s);
 size_t gcd_lds_bytes(int da, int db);
 void launch_gcd_p(const GcdDev& g, TablesDev tab, hipStream_t s);
 void launch_gather_rows(const uint32_t* src, int ld, const int* idx, int rows, int n, uint32_t* dst, hipStream_t s);

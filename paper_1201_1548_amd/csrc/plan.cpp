@@ -88,6 +88,19 @@ RowStats derive_stats(const RowStats& f) {
   return g;
 }
 
+RowStats derive_stats_x(const RowStats& f) {
+  RowStats g;
+  g.resize(f.rows());
+  for (int j = 0; j < f.rows(); ++j) {
+    const int d = f.deg(j);
+    if (d < 1) continue;  // constant or zero row: its derivative is zero
+    // i c_i with i <= d: |i c_i| < 2^(bits + ld) and the 1-norm grows by at most d
+    const int ld = 32 - __builtin_clz((uint32_t)d);
+    g.set(j, d - 1, f.bits(j) + ld, f.cnt(j), f.norm(j) + log2_fx_up((double)d));
+  }
+  return g;
+}
+
 RowStats worst_stats(int rows, int ld, int L) {
   RowStats s;
   s.resize(rows);

@@ -45,6 +45,8 @@ struct Plan {
 RowStats scan_host(const uint32_t* limbs, int rows, int ld, int L);
 // Statistics of the y-derivative computed from those of f (row j <- (j+1) row j+1).
 RowStats derive_stats(const RowStats& f);
+// Statistics of the x-derivative (row j <- d/dx row j; rows are powers of y).
+RowStats derive_stats_x(const RowStats& f);
 // Statistics that every input of the given extents satisfies (for *_bounds).
 RowStats worst_stats(int rows, int ld, int L);
 

@@ -1,10 +1,11 @@
 """Write the stored node-value digests under tests/golden/nodes_*.json from the oracle alone.
 
 Usage:  python tests/golden/make_node_digests.py [group ...] [--procs N]
-        groups: deg20 curve40 arrangement serving capacity (default: all)
+        groups: deg20 curve40 arrangement serving capacity polar (default: all)
 
 Full-size parity without a full-size Bareiss run.  For a case (f, g) with
-R = res(f, g; y):
+R = res(f, g; y) (the operands are (f, f_y) for kind disc and (f_x, f_y) for
+kind polar):
   * D - 1 = oracle.bounds.degree_bound(f, g) bounds deg R, so the D values
     R(0), ..., R(D-1) determine R (Section 2: R is a polynomial in x; the
     specialisation R(a) = det S(f(a, y), g(a, y)) keeps the formal degrees);
@@ -39,6 +40,7 @@ sys.path.insert(0, ROOT)
 
 from oracle.bounds import coeff_bound, degree_bound  # noqa: E402
 from oracle.resultant import bi_diff_y, bi_tdeg, bi_trim, resultant_at_mod  # noqa: E402
+from oracle.subresultants import bi_diff_x  # noqa: E402
 from paper_1201_1548_amd import synth  # noqa: E402
 from tests.golden.make_golden import input_digest  # noqa: E402
 
@@ -46,14 +48,15 @@ PRIME_BITS = 255
 MARGIN_BITS = 8
 DEG20_PAIRS = [1, 2, 37, 64, 100, 128, 200, 255]
 CAPACITY_MN = [(23, 9), (9, 23), (24, 4), (31, 31), (31, 2), (32, 6), (5, 0), (0, 7), (1, 1)]
-GROUPS = ("deg20", "curve40", "arrangement", "serving", "capacity")
+GROUPS = ("deg20", "curve40", "arrangement", "serving", "capacity", "polar")
 
 
 # ----------------------------------------------------------------------------
 # case specifications -> inputs (shared with the tests)
 
 def build_inputs(spec):
-    """(kind, F, G) for a case spec; G is f_y for a discriminant."""
+    """(kind, F, G) for a case spec; G is f_y for a discriminant and a polar
+    resultant (whose first Sylvester operand is f_x: see ``operands``)."""
     gen = spec["gen"]
     args = spec.get("args", [])
     kw = spec.get("kw", {})
@@ -61,6 +64,8 @@ def build_inputs(spec):
         curves, pairs = _arrangement()
         i, j = pairs[args[0]]
         F, G = curves[i], curves[j]
+    elif gen == "arrangement_curve":
+        F, G = _arrangement()[0][args[0]], None
     elif gen == "poisson_request":
         req = _poisson()[args[0]]
         F, G = req["f"], req["g"]
@@ -68,9 +73,14 @@ def build_inputs(spec):
         out = getattr(synth, gen)(*args, **kw)
         F, G = out if isinstance(out, tuple) else (out, None)
     kind = spec["kind"]
-    if kind == "disc":
+    if kind in ("disc", "polar"):
         return kind, F, bi_diff_y(F)
     return kind, F, G
+
+
+def operands(kind, F, G):
+    """The two Sylvester operands of a case from ``build_inputs``'s output."""
+    return (bi_diff_x(F), G) if kind == "polar" else (F, G)
 
 
 _CACHE = {}
@@ -139,6 +149,18 @@ def cases_for(group):
         return _arrangement_cases()
     if group == "serving":
         return _serving_cases()
+    if group == "polar":
+        curves, _ = _arrangement()
+        big = max(range(len(curves)), key=lambda i: (bi_tdeg(curves[i]), _bits(curves[i])))
+        return [
+            {"name": "polar_curve_deg40_dense", "gen": "curve_deg40", "args": [0], "kind": "polar"},
+            {"name": "polar_curve_deg40_g2_hk2", "gen": "singular_curve_deg40", "args": [0],
+             "kw": {"square_k": True, "dk": 10}, "kind": "polar"},
+            {"name": "polar_arrangement_curve_%d" % big, "gen": "arrangement_curve", "args": [big], "kind": "polar",
+             "note": "total degree %d, %d-bit coefficients" % (bi_tdeg(curves[big]), _bits(curves[big]))},
+            {"name": "polar_curve_deg12", "gen": "curve_deg40", "args": [5], "kw": {"tdeg": 12, "bits": 16},
+             "kind": "polar"},
+        ]
     raise ValueError(group)
 
 
@@ -197,8 +219,8 @@ def _serving_cases():
 # the oracle runs
 
 def _task(spec, q, a0, a1):
-    _, F, G = build_inputs(spec)
-    return [resultant_at_mod(F, G, a, q) for a in range(a0, a1)]
+    A, B = operands(*build_inputs(spec))
+    return [resultant_at_mod(A, B, a, q) for a in range(a0, a1)]
 
 
 def run_group(group, procs):
@@ -207,8 +229,8 @@ def run_group(group, procs):
     tasks = []
     for spec in cases:
         kind, F, G = build_inputs(spec)
-        D = degree_bound(F, G) + 1
-        B = coeff_bound(F, G)
+        D = degree_bound(*operands(kind, F, G)) + 1
+        B = coeff_bound(*operands(kind, F, G))
         ps = primes_for(B)
         plans.append((spec, F, G, D, B, ps))
         chunk = max(1, D // 8)
@@ -245,7 +267,8 @@ def run_group(group, procs):
         })
         out.append(rec)
     doc = {
-        "about": "Digests of R(a) mod q for a = 0..D-1 (R = res(f, g; y), or res(f, f_y; y) for kind disc), "
+        "about": "Digests of R(a) mod q for a = 0..D-1 (R = res(f, g; y), res(f, f_y; y) for kind disc, "
+                 "res(f_x, f_y; y) for kind polar), "
                  "written by tests/golden/make_node_digests.py with oracle.resultant.resultant_at_mod, "
                  "oracle.bounds.degree_bound and oracle.bounds.coeff_bound only.",
         "group": group,

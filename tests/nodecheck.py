@@ -17,7 +17,7 @@ import math
 
 from oracle.bounds import coeff_bound, degree_bound
 from tests.golden.make_golden import input_digest
-from tests.golden.make_node_digests import build_inputs, load_group, node_digest
+from tests.golden.make_node_digests import build_inputs, load_group, node_digest, operands
 
 
 def values_mod(R, q, D):
@@ -44,7 +44,7 @@ def names(group):
 
 
 def inputs(rec):
-    """(kind, f, g) as the library takes them (g = None for a discriminant) and
+    """(kind, f, g) as the library takes them (g = None unless kind is res) and
     the oracle's second Sylvester operand (g, or f_y)."""
     kind, F, G2 = build_inputs(rec)
     return kind, F, (G2 if kind == "res" else None), G2
@@ -53,13 +53,14 @@ def inputs(rec):
 def check(R, rec):
     kind, F, G, G2 = inputs(rec)
     assert input_digest(F, G) == rec["inputs_sha256"], "inputs changed since the digests were written"
-    D = degree_bound(F, G2) + 1
+    A, B = operands(kind, F, G2)
+    D = degree_bound(A, B) + 1
     assert D == rec["D"], (D, rec["D"])
     assert len(R) <= D, "degree %d above the bound %d" % (len(R) - 1, D - 1)
     primes = [int(q) for q in rec["primes"]]
     Q = math.prod(primes)
     height = max((abs(c) for c in R), default=0)
-    assert 2 * max(coeff_bound(F, G2), height) < Q, "primes do not fix the result"
+    assert 2 * max(coeff_bound(A, B), height) < Q, "primes do not fix the result"
     bad = []
     for k, (q, dg) in enumerate(zip(primes, rec["digests"])):
         vals = values_mod(R, q, D)

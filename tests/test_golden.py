@@ -50,7 +50,7 @@ import sympy  # noqa: E402
 from oracle.bounds import coeff_bound, degree_bound  # noqa: E402
 from oracle.resultant import resultant_at_mod  # noqa: E402
 from tests import nodecheck  # noqa: E402
-from tests.golden.make_node_digests import GROUPS, load_group, node_digest, primes_for  # noqa: E402
+from tests.golden.make_node_digests import GROUPS, load_group, node_digest, operands, primes_for  # noqa: E402
 
 
 @pytest.mark.parametrize("group", GROUPS)
@@ -60,14 +60,15 @@ def test_node_digest_files_are_the_oracles(group):
     for rec in doc["cases"]:
         kind, F, G, G2 = nodecheck.inputs(rec)
         assert input_digest(F, G) == rec["inputs_sha256"], rec["name"]
-        assert degree_bound(F, G2) + 1 == rec["D"]
+        A, B = operands(kind, F, G2)
+        assert degree_bound(A, B) + 1 == rec["D"]
         primes = [int(q) for q in rec["primes"]]
         assert len(set(primes)) == len(primes) == len(rec["digests"])
         assert all(sympy.isprime(q) for q in primes)
-        assert math.prod(primes) > 2 * coeff_bound(F, G2)
+        assert math.prod(primes) > 2 * coeff_bound(A, B)
         # one stored value recomputed by the oracle here
         a, v = rec["samples_prime0"][0]
-        assert resultant_at_mod(F, G2, a, primes[0]) == int(v), rec["name"]
+        assert resultant_at_mod(A, B, a, primes[0]) == int(v), rec["name"]
 
 
 def _digest_record(F, G, R_true):

@@ -562,3 +562,147 @@ def test_newton_block_tables_expand_the_newton_form():
             P = [(prod[j] + (T[b][j] if j < KB else 0)) % p for j in range(len(prod))]
         P = (P + [0] * D)[:D]
         assert P == ref, D
+
+
+# ---------------------------------------------------------------------------
+# principal subresultant coefficients per point (k_psc's psc_lane)
+
+def psc_lane_model(A, B, m, n, K, p):
+    """The kernel's recurrence for sr_0..sr_{K-1} of (A, B) with formal degrees
+    (m, n), Montgomery inputs; returns plain values.  Same steps as psc_lane:
+    closed-form top index, row-block exchange, formal drops, then Euclid with
+    the scaled remainders' scalars tracked and one simultaneous inversion."""
+    A, B = list(A), list(B)
+    one = mont(1, p)
+    num, den = [None] * K, [None] * K
+    st = {"Nn": one, "Nd": one, "E0": 0, "E1": 0}
+
+    def emit(i, vn, vd):
+        if i >= K:
+            return
+        x = mmul(st["Nn"], vn, p)
+        if (st["E0"] ^ (i & st["E1"])) & 1:
+            x = mneg(x, p)
+        assert num[i] is None, "index emitted twice"
+        num[i], den[i] = x, mmul(st["Nd"], vd, p)
+
+    def swap_sign(a, b):
+        st["E0"] ^= (a * b) & 1
+        st["E1"] ^= (a + b + 1) & 1
+
+    a, b = m, n
+    if a > b:
+        emit(b, mpow(B[b], a - b, p), one)
+    elif a < b:
+        emit(a, mpow(A[a], b - a, p), one)
+    if a < b:
+        A, B, a, b = B, A, b, a
+        swap_sign(a, b)
+    while b >= 1:
+        za, zb = A[a] == 0, B[b] == 0
+        if not za and not zb:
+            break
+        if za and zb:
+            for i in range(b):
+                emit(i, 0, one)
+            b = 0
+            break
+        if zb:
+            st["Nn"] = mmul(st["Nn"], A[a], p)
+            b -= 1
+            emit(b, mpow(B[b], a - b, p), one)
+            continue
+        st["E0"] ^= b & 1
+        st["E1"] ^= 1
+        st["Nn"] = mmul(st["Nn"], B[b], p)
+        a -= 1
+        if a < b:
+            A, B, a, b = B, A, b, a
+            swap_sign(a, b)
+            emit(b, mpow(B[b], a - b, p), one)
+    sA = sB = one
+    while b >= 1:
+        lb = B[b]
+        eliminate(A, B, a, b, lb, p, True)
+        c = b - 1
+        while c >= 0 and A[c] == 0:
+            c -= 1
+        for i in range(c + 1, b):
+            emit(i, 0, one)
+        if c < 0:
+            break
+        sR = mmul(mpow(lb, a - b + 1, p), sA, p)
+        swap_sign(a, b)
+        st["Nn"] = mmul(st["Nn"], mpow(lb, a - c, p), p)
+        st["Nd"] = mmul(st["Nd"], mpow(sB, a - c, p), p)
+        emit(c, mpow(A[c], b - c, p), mpow(sR, b - c, p))
+        A, B, a, b, sA, sB = B, A, b, c, sB, sR
+    assert all(v is not None for v in num), "index never emitted"
+    pre = one
+    for i in range(K):
+        num[i] = mmul(num[i], pre, p)
+        pre = mmul(pre, den[i], p)
+    inv = minv(pre, p)
+    out = [0] * K
+    for i in reversed(range(K)):
+        v = mmul(num[i], inv, p)
+        inv = mmul(inv, den[i], p)
+        out[i] = redc(v, p)
+    return out
+
+
+def _psc_det(fc, gc, p):
+    from oracle.subresultants import psc_indices, psc_matrix
+    m, n = len(fc) - 1, len(gc) - 1
+    return [det_mod(psc_matrix(fc, gc, i), p) if m + n - 2 * i > 0 else 1 % p for i in psc_indices(m, n)]
+
+
+def _psc_cases(rng, p):
+    for _ in range(40):
+        m, n = rng.randint(0, 7), rng.randint(0, 7)
+        if m == n == 0:
+            continue
+        fc = [rng.randrange(p) for _ in range(m + 1)]
+        gc = [rng.randrange(p) for _ in range(n + 1)]
+        yield fc, gc
+    # vanishing formal leading coefficients (one, several, both)
+    yield [3, 1, 4, 0], [2, 7, 1]
+    yield [3, 1, 0, 0], [2, 7, 1, 5]
+    yield [3, 1, 4, 1], [2, 7, 0, 0]
+    yield [3, 1, 4, 0], [2, 7, 1, 0]
+    yield [5, 0, 0, 0, 0], [1, 2, 0]
+    # common factors (defective sequences): (y - 2)^2 (y + 1) and (y - 2)^2
+    yield [4, 0, -3 % p, 1], [4, -4 % p, 1]
+    yield [(-8) % p, 12, -6 % p, 1], [4, -4 % p, 1]
+    # a remainder that skips degrees: y^5 + 1 and y^2
+    yield [1, 0, 0, 0, 0, 1], [0, 0, 1]
+
+
+@pytest.mark.parametrize("p", [1431655751, 1073741827])
+def test_psc_recurrence_matches_determinants(p):
+    from oracle.subresultants import psc_indices
+    rng = random.Random(p)
+    for fc, gc in _psc_cases(rng, p):
+        m, n = len(fc) - 1, len(gc) - 1
+        K = len(psc_indices(m, n))
+        got = psc_lane_model([mont(v, p) for v in fc], [mont(v, p) for v in gc], m, n, K, p)
+        assert got == _psc_det(fc, gc, p), (fc, gc)
+
+
+def test_psc_model_catches_a_planted_mistake():
+    """Dropping the remainder's scalar (sR = 1) gives wrong values below the
+    top two indices; the determinant comparison sees it."""
+    p = 1431655751
+    rng = random.Random(3)
+    fc = [rng.randrange(p) for _ in range(6)]
+    gc = [rng.randrange(p) for _ in range(5)]
+    got = psc_lane_model([mont(v, p) for v in fc], [mont(v, p) for v in gc], 5, 4, 5, p)
+    assert got == _psc_det(fc, gc, p)
+    global mpow
+    real = mpow
+    try:
+        mpow = lambda x, e, q: real(x, e, q) if e != 2 else real(x, 1, q)  # noqa: E731
+        bad = psc_lane_model([mont(v, p) for v in fc], [mont(v, p) for v in gc], 5, 4, 5, p)
+    finally:
+        mpow = real
+    assert bad != _psc_det(fc, gc, p)
