@@ -308,12 +308,17 @@ int bires_debug_values(const bires_bipoly *f, const bires_bipoly *g, int kind, i
  *     elimination per size bucket, interpolation, mixed radix, limbs);
  *   BIRES_SCHEDULE_FUSED: every stage of every job in one persistent launch
  *     whose blocks take tasks from a device queue in dependency order;
+ *   BIRES_SCHEDULE_SCHUR: staged, with the evaluation + elimination of the
+ *     jobs with 1 <= min(m, n) and m + n <= 128 by the Schur algorithm on the
+ *     displacement generators of the Sylvester matrix (Section 5.1, eq.
+ *     displ-sylvester), one wavefront per (prime, point) instance;
  *   BIRES_SCHEDULE_AUTO (default): the autotuner's choice for the batch's size
  *     key if it has one, else staged.
  * Results are identical under every schedule.  Process-wide setting. */
 #define BIRES_SCHEDULE_STAGED 0
 #define BIRES_SCHEDULE_FUSED 1
 #define BIRES_SCHEDULE_AUTO 2
+#define BIRES_SCHEDULE_SCHUR 3
 int bires_set_schedule(int schedule);
 
 /* Evaluation + elimination kernel of the staged schedule.
@@ -321,10 +326,18 @@ int bires_set_schedule(int schedule);
  *     (m, n: degrees in the eliminated variable) keep f's coefficient array in
  *     registers; blocks that meet a vanishing leading coefficient or a
  *     degree drop are recomputed by the general kernel; other jobs use it;
- *   BIRES_EVAL_LDS: every job uses the general kernel (both arrays in LDS).
+ *   BIRES_EVAL_LDS: every job uses the general kernel (both arrays in LDS);
+ *   BIRES_EVAL_SCHUR: jobs with 1 <= min(m, n) and m + n <= 128 use the
+ *     Schur kernel of BIRES_SCHEDULE_SCHUR (instances whose pivot vanishes mod
+ *     p fall back to Euclid), the others as under BIRES_EVAL_AUTO.
  * Results are identical.  Process-wide setting. */
 #define BIRES_EVAL_AUTO 0
 #define BIRES_EVAL_LDS 1
+#define BIRES_EVAL_SCHUR 2
+/* (prime, point) instances that batched calls have run on the Schur kernel
+ * since set-up, and how many of them met a vanishing pivot and were
+ * recomputed by Euclid's algorithm. */
+int bires_schur_stats(int64_t *instances, int64_t *fallbacks);
 int bires_set_eval_kernel(int kernel);
 
 /* Plan reuse for batched calls with device-memory inputs (default on): when
@@ -354,7 +367,7 @@ int bires_set_graphs(int enable);
 int bires_graph_stats(int64_t *captures, int64_t *replays);
 
 /* Autotuner: runs the batch (arguments as bires_resultant_batch) under every
- * schedule, keeps the fastest (best of `reps` timed runs after one warm-up) for
+ * schedule (staged, fused, Schur), keeps the fastest (best of `reps` timed runs after one warm-up) for
  * the batch's size key (total (prime, point) instances, largest degree sum in
  * the eliminated variable, largest prime count, each log2-bucketed), and
  * returns it in *chosen.  BIRES_SCHEDULE_AUTO then uses the table; when the

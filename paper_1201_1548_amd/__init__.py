@@ -104,6 +104,7 @@ _SIGS = {
     "bires_set_plan_cache": ([ctypes.c_int], ctypes.c_int),
     "bires_issue_rates": ([ctypes.POINTER(ctypes.c_double), ctypes.c_int], ctypes.c_int),
     "bires_plan_cache_stats": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "bires_schur_stats": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "bires_graph_stats": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "bires_autotune": ([ctypes.c_int, ctypes.POINTER(Bipoly), ctypes.POINTER(Bipoly),
                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Upoly),
@@ -514,19 +515,29 @@ def debug_values(F, G=None, kind="res", var="y"):
     return primes(Pp.value), vals.reshape(Pp.value, Dp.value)
 
 
-SCHEDULE_STAGED, SCHEDULE_FUSED, SCHEDULE_AUTO = 0, 1, 2
+SCHEDULE_STAGED, SCHEDULE_FUSED, SCHEDULE_AUTO, SCHEDULE_SCHUR = 0, 1, 2, 3
 
 
 def set_schedule(schedule):
-    """Launch schedule of batched calls: 'staged', 'fused' or 'auto'."""
-    code = {"staged": 0, "fused": 1, "auto": 2}[schedule] if isinstance(schedule, str) else schedule
+    """Launch schedule of batched calls: 'staged', 'fused', 'schur' (staged with
+    the Schur elimination, a wavefront per instance) or 'auto'."""
+    code = {"staged": 0, "fused": 1, "auto": 2, "schur": 3}[schedule] if isinstance(schedule, str) else schedule
     _check(lib().bires_set_schedule(code), "bires_set_schedule")
 
 
 def set_eval_kernel(kernel):
     """Evaluation + elimination kernel of the staged schedule: 'auto' (f's
-    array in registers where the degrees allow) or 'lds'."""
-    _check(lib().bires_set_eval_kernel({"auto": 0, "lds": 1}[kernel]), "bires_set_eval_kernel")
+    array in registers where the degrees allow), 'lds' or 'schur' (the Schur
+    algorithm on the displacement generators, a wavefront per instance)."""
+    _check(lib().bires_set_eval_kernel({"auto": 0, "lds": 1, "schur": 2}[kernel]), "bires_set_eval_kernel")
+
+
+def schur_stats():
+    """(instances run on the Schur kernel, of them recomputed by Euclid) since set-up."""
+    a = ctypes.c_int64()
+    b = ctypes.c_int64()
+    _check(lib().bires_schur_stats(ctypes.byref(a), ctypes.byref(b)), "bires_schur_stats")
+    return a.value, b.value
 
 
 ISSUE_RATE_INSTRUCTIONS = ("v_add_u32", "v_min_u32", "v_mul_lo_u32", "v_mad_u64_u32", "v_fma_f64")
@@ -681,7 +692,7 @@ class DeviceBatch:
         _check(lib().bires_autotune(self.n, self.fds, self.gds, self.kinds, self.vars, self.outs, self.status,
                                     MEM_DEVICE, _torch_stream(stream), reps, ctypes.byref(chosen)),
                "bires_autotune")
-        return {0: "staged", 1: "fused"}[chosen.value]
+        return {0: "staged", 1: "fused", 3: "schur"}[chosen.value]
 
     def run_each(self, stream=None):
         """The plain path: one single-job call per job (bires_resultant / bires_discriminant /

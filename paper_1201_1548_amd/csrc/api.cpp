@@ -282,11 +282,11 @@ int bires_set_graphs(int enable) {
 }
 
 int bires_set_eval_kernel(int kernel) {
-  if (kernel != BIRES_EVAL_AUTO && kernel != BIRES_EVAL_LDS) return BIRES_EINVAL;
+  if (kernel != BIRES_EVAL_AUTO && kernel != BIRES_EVAL_LDS && kernel != BIRES_EVAL_SCHUR) return BIRES_EINVAL;
   int err = BIRES_OK;
   Context* cx = context(&err);
   if (!cx) return err;
-  cx->eval_rg = kernel == BIRES_EVAL_AUTO;
+  cx->eval_mode = kernel;
   return BIRES_OK;
 }
 
@@ -347,6 +347,15 @@ int bires_plan_cache_stats(int64_t* hits, int64_t* misses) {
   return BIRES_OK;
 }
 
+int bires_schur_stats(int64_t* instances, int64_t* fallbacks) {
+  int err = BIRES_OK;
+  Context* cx = context(&err);
+  if (!cx) return err;
+  if (instances) *instances = cx->schur_instances;
+  if (fallbacks) *fallbacks = cx->schur_fallbacks;
+  return BIRES_OK;
+}
+
 int bires_graph_stats(int64_t* captures, int64_t* replays) {
   int err = BIRES_OK;
   Context* cx = context(&err);
@@ -358,7 +367,7 @@ int bires_graph_stats(int64_t* captures, int64_t* replays) {
 }
 
 int bires_set_schedule(int schedule) {
-  if (schedule < BIRES_SCHEDULE_STAGED || schedule > BIRES_SCHEDULE_AUTO) return BIRES_EINVAL;
+  if (schedule < BIRES_SCHEDULE_STAGED || schedule > BIRES_SCHEDULE_SCHUR) return BIRES_EINVAL;
   int err = BIRES_OK;
   Context* cx = context(&err);
   if (!cx) return err;
@@ -375,7 +384,7 @@ int bires_autotune(int n, const bires_bipoly* f, const bires_bipoly* g, const in
   double best = 1e300;
   int best_s = BIRES_SCHEDULE_STAGED;
   std::string key;
-  for (int sched : {BIRES_SCHEDULE_STAGED, BIRES_SCHEDULE_FUSED}) {
+  for (int sched : {BIRES_SCHEDULE_STAGED, BIRES_SCHEDULE_FUSED, BIRES_SCHEDULE_SCHUR}) {
     cx->forced_schedule = sched;
     int e = bires_resultant_batch(n, f, g, kind, var, out, status, mem, stream);  // warm-up
     double t = 1e300;

@@ -219,6 +219,7 @@ struct PendingBatch {
   std::shared_ptr<DevImage> image;  // statistics the reused plans were made from
   size_t o_scan0 = 0, scan_words = 0;
   int32_t* h_flags = nullptr;
+  long long schur_instances = 0;  // (prime, point) instances on the Schur kernel
   hipEvent_t ev0 = nullptr, ev1 = nullptr, done = nullptr;
   Held d_in, h_in, d_ws, h_meta, h_out;
   // allocation-free calls: device buffers in the library's fixed scratch
@@ -468,13 +469,35 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   // bucket, so small jobs are not held to the occupancy of the largest)
   // jobs whose f array fits in registers (eval_elim_rg_capacity 24 or 32) run
   // in two more launches
-  enum { K_RED, K_IP, K_MRC, K_SUM, K_CAR, K_CRT, K_EE0, NBUCKET = 5, K_RG0 = K_EE0 + NBUCKET, NRG = 2, NK = K_RG0 + NRG };
+  // jobs on the Schur kernel (wave per instance; 1 or 2 generator rows per
+  // lane) in two more
+  enum {
+    K_RED, K_IP, K_MRC, K_SUM, K_CAR, K_CRT, K_EE0, NBUCKET = 5, K_RG0 = K_EE0 + NBUCKET, NRG = 2,
+    K_SC0 = K_RG0 + NRG, NSC = 2, NK = K_SC0 + NSC
+  };
   const int bucket_words[NBUCKET] = {24, 40, 64, 96, 1 << 30};
   const int rg_cap[NRG] = {24, 32};
   int bw[NBUCKET] = {0}, br_[NBUCKET] = {0};
   int rdeg[NRG] = {0}, rw[NRG] = {0};
+  int sw[NSC] = {0};
   std::vector<int> starts[NK];
   for (auto& v : starts) v.assign(nj + 1, 0);
+  // the schedule: from the autotuner's table for the batch's size key
+  long long instances = 0;
+  int max_r = 0, keyP = 1;
+  for (int i = 0; i < nj; ++i)
+    if (!w[i].status && w[i].active) {
+      instances += (long long)w[i].pl.P * w[i].pl.D;
+      max_r = std::max(max_r, w[i].pl.m + w[i].pl.n);
+      keyP = std::max(keyP, w[i].pl.P);
+    }
+  const std::string key = tune_key(instances, max_r, keyP);
+  {
+    std::lock_guard<std::mutex> lk(cx->tune_mu);
+    cx->last_key = key;
+  }
+  const int sched = (debug || noalloc || instances == 0) ? BIRES_SCHEDULE_STAGED : schedule_for(cx, key);
+  const bool schur = cx->eval_mode == BIRES_EVAL_SCHUR || sched == BIRES_SCHEDULE_SCHUR;
   int maxP = 1, maxD = 1;
   for (int i = 0; i < nj; ++i) {
     Work& x = w[i];
@@ -498,8 +521,12 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     maxP = std::max(maxP, p.P);
     maxD = std::max(maxD, p.D);
     starts[K_RED][i + 1] = (x.Tf + 63) / 64 + (x.Tg + 63) / 64;
-    const int rc = cx->eval_rg ? eval_elim_rg_capacity(p.m, p.n) : 0;
-    if (rc) {
+    const int nr = schur ? schur_rows_per_lane(p.m, p.n) : 0;
+    const int rc = cx->eval_mode == BIRES_EVAL_AUTO ? eval_elim_rg_capacity(p.m, p.n) : 0;
+    if (nr) {
+      starts[K_SC0 + nr - 1][i + 1] = p.P * p.D;
+      sw[nr - 1] = std::max(sw[nr - 1], p.m + p.n + 2);
+    } else if (rc) {
       const int r = rc == rg_cap[0] ? 0 : 1;
       starts[K_RG0 + r][i + 1] = p.P * ((p.D + 63) / 64);
       rdeg[r] = std::max(rdeg[r], std::max(p.m, p.n));
@@ -528,20 +555,8 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   for (auto& v : starts)
     for (int i = 0; i < nj; ++i) v[i + 1] += v[i];
   // persistent fused launch: per-stage task starts, counter offsets, counters
-  long long instances = 0;
-  int max_r = 0;
-  for (int i = 0; i < nj; ++i)
-    if (!w[i].status && w[i].active) {
-      instances += (long long)w[i].pl.P * w[i].pl.D;
-      max_r = std::max(max_r, w[i].pl.m + w[i].pl.n);
-    }
-  const std::string key = tune_key(instances, max_r, maxP);
-  {
-    std::lock_guard<std::mutex> lk(cx->tune_mu);
-    cx->last_key = key;
-  }
-  const bool fused = P->fused =
-      !debug && !noalloc && instances > 0 && schedule_for(cx, key) == BIRES_SCHEDULE_FUSED;
+  const bool fused = P->fused = sched == BIRES_SCHEDULE_FUSED;
+  if (!fused && !debug) P->schur_instances = (long long)starts[K_SC0][nj] + starts[K_SC0 + 1][nj];
   // staged schedule: explicit CRT straight to limbs when the prime counts allow
   std::vector<std::pair<const uint32_t*, int>> crt(nj, {nullptr, 0});
   bool use_crt = !debug && !fused && crt_ok(maxP);
@@ -592,7 +607,9 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   const size_t meta_begin = ws.take(0);
   const size_t o_jobs = ws.take(sizeof(JobDev) * (size_t)nj);
   // [deg_out, err] per job, fused error, statistics mismatch of reused plans
-  const size_t o_flags = ws.take(sizeof(int32_t) * (2 * (size_t)nj + 2));
+  // per job (degree, error), then the fused error, the statistics check and
+  // the Schur kernel's fallback count
+  const size_t o_flags = ws.take(sizeof(int32_t) * (2 * (size_t)nj + 3));
   const size_t o_fbc = ws.take(sizeof(int) * NRG);                         // queue lengths, uploaded as zero
   for (int i = 0; i < nj; ++i)
     if (!w[i].status && w[i].active) w[i].o_rowdeg = ws.take((size_t)(w[i].pl.m + w[i].pl.n + 2) * 4);
@@ -654,7 +671,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   for (int i = 0; i < nj; ++i) {
     h_flags[2 * i] = -1;
     h_flags[2 * i + 1] = 0;
-    if (i == nj - 1) h_flags[2 * nj] = h_flags[2 * nj + 1] = 0;
+    if (i == nj - 1) h_flags[2 * nj] = h_flags[2 * nj + 1] = h_flags[2 * nj + 2] = 0;
     h_jobs[i] = JobDev{};
     Work& x = w[i];
     if (x.status || !x.active) continue;
@@ -823,6 +840,12 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
           launch_eval_elim_rg(rg_cap[r], d_jobs, st_of(K_RG0 + r), nj, nb_of(K_RG0 + r), rdeg[r], rw[r],
                               (int*)(D0 + o_fbc) + r, (int*)(D0 + o_fbq[r]), cx->tab, st);
       }
+      for (int r = 0; r < NSC; ++r) {
+        sg.add(nb_of(K_SC0 + r), sw[r]);
+        if (run && nb_of(K_SC0 + r))
+          launch_schur(r + 1, d_jobs, st_of(K_SC0 + r), nj, nb_of(K_SC0 + r), sw[r],
+                       (int*)(D0 + o_flags) + 2 * nj + 2, cx->tab, st);
+      }
       if (run && timing) DEV(hipEventRecord(ev1, st));
       if (!debug) {
         sg.add((const void*)itW, (const void*)itQ, itNB);
@@ -849,7 +872,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     if (debug) return BIRES_OK;
     sg.add(nj, o_flags, (const void*)h_flags);
     if (run && nj)
-      DEV(hipMemcpyAsync(h_flags, D0 + o_flags, sizeof(int32_t) * (2 * nj + 2), hipMemcpyDeviceToHost, st));
+      DEV(hipMemcpyAsync(h_flags, D0 + o_flags, sizeof(int32_t) * (2 * nj + 3), hipMemcpyDeviceToHost, st));
     if (fused) {
       sg.add(ctr_off[nj]);
       if (run)
@@ -1009,6 +1032,10 @@ int run_batch_finish(PendingPtr P) {
     }
   }
   const int fused_err = P->fused ? h_flags[2 * nj] : 0;
+  if (P->schur_instances) {
+    cx->schur_instances += P->schur_instances;
+    cx->schur_fallbacks += h_flags[2 * nj + 2];
+  }
   int first_err = BIRES_OK;
   for (int i = 0; i < nj; ++i) {
     Work& x = w[i];

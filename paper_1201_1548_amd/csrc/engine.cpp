@@ -306,7 +306,8 @@ void tune_load(Context* cx) {
   std::string key;
   int sched;
   while (in >> key >> sched)
-    if (sched == BIRES_SCHEDULE_STAGED || sched == BIRES_SCHEDULE_FUSED) cx->tuned[key] = sched;
+    if (sched == BIRES_SCHEDULE_STAGED || sched == BIRES_SCHEDULE_FUSED || sched == BIRES_SCHEDULE_SCHUR)
+      cx->tuned[key] = sched;
 }
 
 void tune_store(Context* cx, const std::string& key, int schedule) {

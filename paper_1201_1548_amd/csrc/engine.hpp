@@ -93,7 +93,8 @@ struct Context {
   int64_t host_calls = 0;
   std::mutex crt_mu;
   std::map<int, std::pair<const uint32_t*, int>> crt;  // P -> (device CrtHost buffer, LM)
-  std::atomic<bool> eval_rg{true};                       // register-array evaluation kernel where it applies
+  std::atomic<int> eval_mode{BIRES_EVAL_AUTO};           // evaluation + elimination kernel (BIRES_EVAL_*)
+  std::atomic<long long> schur_instances{0}, schur_fallbacks{0};  // Schur kernel statistics
   std::atomic<bool> graphs{false};                       // replay device sequences as captured graphs
   std::atomic<bool> plan_cache{true};                    // speculative reuse of the last call's plans
   SpecCache spec;

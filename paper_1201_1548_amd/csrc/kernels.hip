@@ -857,6 +857,123 @@ __global__ __launch_bounds__(64) void k_eval_elim_fb(const JobDev* jobs, const i
 }
 
 // ---------------------------------------------------------------------------
+// (c) by the displacement structure of the Sylvester matrix (Section 5.1,
+// "Computing resultants in Z[x,y]", eq. displ-sylvester): one wave per
+// (prime, point) instance, lanes over the generator rows.
+//
+// S is the transposed Sylvester matrix of the section's example: n columns
+// holding f_m .. f_0 shifted down by one per column, then m columns holding
+// g_n .. g_0; det S = res(f, g).  With F the down-shift of size r = m + n and
+// A = Z_n (+) Z_m the block down-shift with blocks matching S's two column
+// blocks, S - F S A^T = G B^T with G = [column 0, column n] of S and B =
+// [e_0, e_n] (only the block-leading columns survive the subtraction).
+// For any R with R - F R A^T = G B^T, F and A strictly lower triangular, the
+// first row of R is g_0 B^T and its first column G b_0^T (g_0, b_0 the first
+// rows of G, B), so the pivot is d = g_0 b_0^T; writing g_0 = (c0, c1) and
+// b_0 = (e0, e1), the Schur complement scaled by d has the generators
+//   G' = [c1 G_0 - c0 G_1, F l],   B' = [e1 B_0 - e0 B_1, A u],
+// l = G b_0^T (the first column), u = B g_0^T (the first row), restricted to
+// rows 1..: the projector I - b_0^T g_0 / d is (c1, -c0)^T (e1, -e0) / d and
+// F l u A^T / d is the other rank-one term.  Row i of F l is l_{i-1}; row i of
+// A u is u_{i-1} except at the block start i = n, where it is 0.  Without
+// divisions the generators after step k describe c_k times the k-th Schur
+// complement, c_0 = 1, c_{k+1} = c_k d_k, so det S = prod_k d_k / prod_k c_k.
+// A pivot that vanishes (a leading principal minor of S is 0 mod p, or a
+// formal leading coefficient vanishes at the point) sends the wave to
+// Euclid's algorithm on lane 0 for that instance.
+// NR rows per lane: r <= 64 NR.
+template <int NR>
+__global__ __launch_bounds__(64) void k_schur(const JobDev* jobs, const int* starts, int nj, TablesDev tab,
+                                              int* fallbacks) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int job = find_job(starts, nj, b);
+  const JobDev& J = jobs[job];
+  const int lb = b - starts[job];
+  const int k = lb / J.D, pt = lb - k * J.D;
+  const int m = J.m, n = J.n, r = m + n;
+  const int lane = threadIdx.x;
+  const ModP q = tab.primes[k];
+  const uint32_t* Rf = J.res_f + (size_t)k * J.Tf;
+  const uint32_t* Rg = J.res_g + (size_t)k * J.Tg;
+  const uint32_t aM = to_mont((uint32_t)pt, q);
+  const int dmax = max(J.ldf, J.kind ? J.ldf : J.ldg) - 1;
+  uint32_t pw[EV_PW];
+  pw[0] = q.one;
+#pragma unroll
+  for (int i = 1; i < EV_PW; ++i) pw[i] = i <= dmax ? mmul(pw[i - 1], aM, q) : 0u;
+  const uint32_t apw = dmax >= EV_PW ? mmul(pw[EV_PW - 1], aM, q) : 0u;
+  // generator rows i = lane + 64 h: G = (f_{m-i}(a), g_{n-i}(a)), B = ([i = 0], [i = n]);
+  // f(a, y) and g(a, y) also go to LDS (ascending) for the Euclid fallback
+  uint32_t* Af = lds;
+  uint32_t* Bg = lds + m + 1;
+  uint32_t g0[NR], g1[NR], b0[NR], b1[NR];
+#pragma unroll
+  for (int h = 0; h < NR; ++h) {
+    const int i = lane + 64 * h;
+    uint32_t fv = 0u, gv = 0u;
+    if (i <= m) {
+      fv = eval_row<const uint32_t, const u32x4>(Rf + (m - i) * J.lpf, J.rowdeg_f[m - i], pw, apw, q);
+      Af[m - i] = fv;
+    }
+    if (i <= n) {
+      gv = eval_row<const uint32_t, const u32x4>(Rg + (n - i) * J.lpg, J.rowdeg_g[n - i], pw, apw, q);
+      Bg[n - i] = gv;
+    }
+    g0[h] = fv;
+    g1[h] = gv;
+    b0[h] = i == 0 ? q.one : 0u;
+    b1[h] = i == n ? q.one : 0u;
+  }
+  __syncthreads();  // the LDS copies are complete before a fallback reads them
+  uint32_t num = q.one, den = q.one, c = q.one;
+  bool ok = true;
+  for (int s = 0; s < r; ++s) {
+    const int hs = s >> 6, ls = s & 63;
+    uint32_t x0 = g0[0], x1 = g1[0], y0 = b0[0], y1 = b1[0];
+#pragma unroll
+    for (int h = 1; h < NR; ++h)
+      if (hs == h) x0 = g0[h], x1 = g1[h], y0 = b0[h], y1 = b1[h];
+    const uint32_t c0 = __builtin_amdgcn_readlane(x0, ls), c1 = __builtin_amdgcn_readlane(x1, ls);
+    const uint32_t e0 = __builtin_amdgcn_readlane(y0, ls), e1 = __builtin_amdgcn_readlane(y1, ls);
+    const uint32_t d = mdot2(c0, e0, c1, e1, q);
+    if (d == 0u) {
+      ok = false;
+      break;
+    }
+    num = mmul(num, d, q);
+    den = mmul(den, c, q);
+    c = mmul(c, d, q);
+    if (s == r - 1) break;
+    const uint32_t nc0 = mneg(c0, q.p), ne0 = mneg(e0, q.p);
+    uint32_t l[NR], u[NR];
+#pragma unroll
+    for (int h = 0; h < NR; ++h) {
+      l[h] = mdot2(e0, g0[h], e1, g1[h], q);
+      u[h] = mdot2(c0, b0[h], c1, b1[h], q);
+      g0[h] = mdot2(c1, g0[h], nc0, g1[h], q);
+      b0[h] = mdot2(e1, b0[h], ne0, b1[h], q);
+    }
+#pragma unroll
+    for (int h = 0; h < NR; ++h) {
+      uint32_t lp = __shfl_up(l[h], 1), up = __shfl_up(u[h], 1);
+      if (lane == 0) {
+        lp = h ? __builtin_amdgcn_readlane(l[h > 0 ? h - 1 : 0], 63) : 0u;
+        up = h ? __builtin_amdgcn_readlane(u[h > 0 ? h - 1 : 0], 63) : 0u;
+      }
+      g1[h] = lp;
+      b1[h] = lane + 64 * h == n ? 0u : up;
+    }
+  }
+  if (ok) {
+    if (lane == 0) J.vals[(size_t)k * J.D + pt] = from_mont(mmul(num, minv(den, q), q), q);
+  } else if (lane == 0) {
+    J.vals[(size_t)k * J.D + pt] = from_mont(uni_resultant<1>(Af, Bg, m, n, q), q);
+    atomicAdd(fallbacks, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Principal subresultant coefficients modulo one prime (Section 3.2.2,
 // "(Exact) Computation of N" and "Computation of N^-"): sr_i(a) for every
 // index i of the formal degrees (m, n) and every point a, one lane per point.
@@ -2222,6 +2339,20 @@ void launch_eval_elim_rg(int C, const JobDev* jobs, const int* starts, int nj, i
     hipLaunchKernelGGL(k_eval_elim_rg32, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, tab, fb_count, fb_queue);
   hipLaunchKernelGGL(k_eval_elim_fb, dim3(std::min(nblocks, 256)), dim3(64), eval_elim_lds_bytes(max_words, 0), s,
                      jobs, starts, nj, tab, fb_count, fb_queue);
+}
+
+int schur_rows_per_lane(int m, int n) {
+  if (m < 1 || n < 1) return 0;
+  return m + n <= 64 ? 1 : m + n <= 128 ? 2 : 0;
+}
+
+void launch_schur(int NR, const JobDev* jobs, const int* starts, int nj, int nblocks, int max_words, int* fallbacks,
+                  TablesDev tab, hipStream_t s) {
+  const size_t lds = (size_t)max_words * sizeof(uint32_t);
+  if (NR == 1)
+    hipLaunchKernelGGL(k_schur<1>, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, tab, fallbacks);
+  else
+    hipLaunchKernelGGL(k_schur<2>, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, tab, fallbacks);
 }
 
 void launch_interp(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_points, TablesDev tab,

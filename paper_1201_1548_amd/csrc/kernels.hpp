@@ -50,6 +50,14 @@ void launch_eval_elim(const JobDev* jobs, const int* starts, int nj, int nblocks
 int eval_elim_rg_capacity(int m, int n);
 void launch_eval_elim_rg(int C, const JobDev* jobs, const int* starts, int nj, int nblocks, int max_deg,
                          int max_words, int* fb_count, int* fb_queue, TablesDev tab, hipStream_t s);
+// Evaluation + elimination by the Schur algorithm on the displacement
+// generators, one wave (block of 64) per (prime, point) instance: P * D blocks
+// per job; rows per lane NR = schur_rows_per_lane(m, n) (0: the job cannot
+// use it: min(m, n) = 0 or m + n > 128); max_words: max over jobs of m + n + 2.
+int schur_rows_per_lane(int m, int n);
+// fallbacks: one device int counting the instances recomputed by Euclid.
+void launch_schur(int NR, const JobDev* jobs, const int* starts, int nj, int nblocks, int max_words, int* fallbacks,
+                  TablesDev tab, hipStream_t s);
 // Interpolation of one (job, prime) per block.  W, Q: the block tables of
 // launch_interp_tables for tab_blocks blocks (null: computed in the kernel).
 void launch_interp(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_points, TablesDev tab,
