@@ -23,13 +23,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "bivariate resultants/sec (deg-20, 32-bit) batched vs plain; INT32 VALU % peak; p99"
 
-# INT32 lane-op cost of the modular primitives in their minimal gfx950 form:
-# Montgomery product = v_mad_u64_u32, v_mul_lo_u32, v_mad_u64_u32, v_sub, v_min;
-# two-product dot (one reduction) = one more v_mad_u64_u32; add/sub mod p = 2.
-OPS_MULMOD, OPS_DOT2, OPS_ADDMOD = 5, 6, 2
-# 256 CUs x 128 32-bit lanes per clock (the vector width behind the
-# 157.3 TFLOP/s fp32 figure: 2 flops x 128 x 256 x 2.4 GHz) x 2.4 GHz.
-INT32_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+# Full-rate 32-bit VALU peak: 64 lanes per clock per CU (a wave64 instruction
+# issues in 4 cycles on a 16-lane SIMD, 4 SIMDs per CU; the library's issue
+# probe measures 4.6 cycles for v_mul_lo_u32 and v_mad_u64_u32, so the
+# multiplies run at this rate; only adds reach twice it), 256 CUs, 2.4 GHz.
+LANES_PER_CU_CLOCK = 64
+
+
+def int_peak_tops(dev):
+    return dev["cus"] * LANES_PER_CU_CLOCK * dev["clock_khz"] * 1e3 / 1e12
 
 
 TRAFFIC_SOURCES = ("kernels.hip", "kernels.hpp", "job.hpp", "modp.hpp")
@@ -45,56 +47,40 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def stored_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` on `workload`, from the committed
-    rocprofv3 counter summary profiles/traffic_<kernel>_<workload>.md, or None
-    when that summary is missing or was taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.md" % (kernel, workload))
+def stored_counters(kind, kernel, workload, field):
+    """A figure of the committed rocprofv3 counter summary
+    profiles/<kind>_<kernel>_<workload>.md (a line 'field: value'), or None when
+    the summary is missing or was taken on other kernel sources (its
+    source_sha256 line differs from the current device sources)."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_%s.md" % (kind, kernel, workload))
     if not os.path.exists(path):
         return None
     fields = {}
     with open(path) as f:
         for line in f:
-            if ":" in line and line.startswith(("source_sha256", "hbm_bytes_per_launch")):
+            if ":" in line and line.startswith(("source_sha256", field)):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip().strip("`")
-    if fields.get("source_sha256") != kernel_source_digest() or "hbm_bytes_per_launch" not in fields:
+    if fields.get("source_sha256") != kernel_source_digest() or field not in fields:
         return None
-    return int(fields["hbm_bytes_per_launch"])
+    return float(fields[field])
 
 
-def _pow_cost(e):
-    return (e.bit_length() + bin(e).count("1")) if e > 0 else 0
+def stored_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` (profiles/traffic_*.md)."""
+    v = stored_counters("traffic", kernel, workload, "hbm_bytes_per_launch")
+    return None if v is None else int(v)
 
 
-def instance_ops(rowdeg_f, rowdeg_g):
-    """Algorithmic INT32 lane-ops of one (prime, point) instance of the
-    evaluation + univariate resultant kernel, for the generic case (no
-    leading coefficient vanishes).  Counts the modular operations the method
-    performs, not loop control or addressing."""
-    mul = dot = add = 0
-    for d in list(rowdeg_f) + list(rowdeg_g):     # Horner: multiply by a, add the coefficient
-        mul += d + 1
-        add += d + 1
-    a, b = len(rowdeg_f) - 1, len(rowdeg_g) - 1
-    if a < b:
-        a, b = b, a
-    while True:
-        if b == 0:
-            mul += _pow_cost(a) + 1
-            break
-        a0, kk = a, 0
-        while a >= b:
-            s = a - b
-            mul += s
-            dot += a - s
-            a -= 1
-            kk += 1
-        e = a0 - a - kk * b
-        mul += _pow_cost(abs(e)) + 1
-        a, b = b, a
-    mul += _pow_cost(2**31 - 3) + 2                 # one Fermat inverse, final product, output conversion
-    return mul * OPS_MULMOD + dot * OPS_DOT2 + add * OPS_ADDMOD
+def model_mulmods(rowdeg_f, rowdeg_g):
+    """Modular products of one (prime, point) instance in the method's own
+    terms: one product per coefficient for the evaluation of f(a, y) and
+    g(a, y), and two per Sylvester-entry elimination for the 2 m n entries of a
+    normal remainder sequence (a reference count, not the kernel's
+    instructions)."""
+    T = sum(d + 1 for d in rowdeg_f if d >= 0) + sum(d + 1 for d in rowdeg_g if d >= 0)
+    m, n = len(rowdeg_f) - 1, len(rowdeg_g) - 1
+    return T + 2 * m * n
 
 
 def cpu_baseline(pairs, D, budget_s=15.0):
@@ -339,6 +325,37 @@ def bench_curve40(args):
         for _ in range(args.steps):
             u, fs = br.squarefree(R)
         tq = (time.perf_counter() - t0) / args.steps
+        # the same discriminant through the Schur schedule (wavefront per
+        # instance), bit-exact against the staged result
+        br.set_schedule("schur")
+        try:
+            Rs_ = br.discriminant(F)
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                Rs_ = br.discriminant(F)
+            tds = (time.perf_counter() - t0) / args.steps
+        finally:
+            br.set_schedule("auto")
+        # Q = res(f_x, f_y; y), the psc's of (f, f_y) modulo one prime, and the
+        # N^- / N^+ test with R* = prod a_i
+        Q = br.polar_resultant(F)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            Q = br.polar_resultant(F)
+        tQ = (time.perf_counter() - t0) / args.steps
+        p0, rows = br.psc(F, kind="disc")
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            p0, rows = br.psc(F, kind="disc")
+        tP = (time.perf_counter() - t0) / args.steps
+        Rstar = [1]
+        for a in fs:
+            Rstar = _zx_mul(Rstar, a)
+        nb = br.fiber_bounds(F, Rstar, len(R) - 1)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            nb = br.fiber_bounds(F, Rstar, len(R) - 1)
+        tN = (time.perf_counter() - t0) / args.steps
         # R = u * prod a_i^i, checked exactly
         prod = [u]
         for i, a in enumerate(fs):
@@ -346,9 +363,15 @@ def bench_curve40(args):
                 prod = _zx_mul(prod, a)
         out[name] = {"disc_ms": round(td * 1e3, 2), "deg_R": len(R) - 1, "gcd_ms": round(tg * 1e3, 2),
                      "deg_gcd": len(h) - 1, "squarefree_ms": round(tq * 1e3, 2),
-                     "squarefree_degrees": [len(a) - 1 for a in fs], "squarefree_exact": prod == R}
+                     "squarefree_degrees": [len(a) - 1 for a in fs], "squarefree_exact": prod == R,
+                     "disc_schur_ms": round(tds * 1e3, 2), "disc_schur_exact": Rs_ == R,
+                     "polar_Q_ms": round(tQ * 1e3, 2), "deg_Q": len(Q) - 1,
+                     "psc_mod_p_ms": round(tP * 1e3, 2), "psc_count": len(rows), "psc_prime": p0,
+                     "fiber_bounds_ms": round(tN * 1e3, 2), "n_minus": nb[0], "n_plus": nb[1],
+                     "fiber_flags": nb[2]}
     return {
-        "metric": "curve-analysis resultant res(f, f_y; y), gcd(R, R') and square-free decomposition wall time (degree-40 curves)",
+        "metric": "curve-analysis resultant res(f, f_y; y), gcd(R, R'), square-free decomposition, Q = res(f_x, f_y; y), "
+                  "psc's mod p and the N^-/N^+ test: wall time (degree-40 curves)",
         "value": round(1e3 / out["dense"]["disc_ms"], 2), "unit": "discriminants/s", "n_gpus": 1,
         "steps": args.steps, "warmup": 1, "ms_per_step": out["dense"]["disc_ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
@@ -404,7 +427,7 @@ def main():
                     help="evaluation + elimination kernel of the staged schedule")
     ap.add_argument("--workload", default="deg20", choices=["deg20", "curve40", "arrangement", "serving", "copy", "rates"])
     ap.add_argument("--schedule", default="auto", choices=["auto", "staged", "fused"])
-    ap.add_argument("--requests", type=int, default=300)
+    ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--qps", type=float, default=0.0)
     ap.add_argument("--budget-gib", type=int, default=32)
     ap.add_argument("--slots", type=int, default=64)
@@ -516,6 +539,24 @@ def main():
         graph = {"value": round(n * args.steps / dtg, 2), "ms_per_step": round(dtg / args.steps * 1e3, 3),
                  "bit_exact": graph_exact, "captures": caps, "replays": reps}
 
+    # the batch under each schedule the autotuner chooses from (a few steps
+    # each, checked bit-exact): why the tuned choice is the one it is
+    schedules = {}
+    for name in ("staged", "fused", "schur"):
+        br.set_schedule(name)
+        try:
+            batch.run()
+            torch.cuda.synchronize()
+            ok = batch.results() == res_batch
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                batch.run()
+            torch.cuda.synchronize()
+            schedules[name] = {"ms_per_step": round((time.perf_counter() - t0) / reps * 1e3, 3), "bit_exact": ok}
+        finally:
+            br.set_schedule(args.schedule)
+
     # plain path: one call per pair, same pairs, same buffers
     exact_plain = None
     if not args.no_plain:
@@ -531,23 +572,33 @@ def main():
         dtp = time.perf_counter() - t0
         plain_value = n * args.plain_steps / dtp
 
-    # roofline of the dominant kernel (evaluation + univariate resultants)
-    rowdeg = [20 - j for j in range(21)]
-    ops_per_instance = instance_ops(rowdeg, rowdeg)
-    ops_launch = ops_per_instance * P * D * n
+    # roofline of the dominant kernel (evaluation + univariate resultants):
+    # integer lane-ops per (prime, point) instance from the committed SQ
+    # counters (integer VALU instructions per wave; one lane per instance),
+    # times the instances of one launch, over the live launch time
+    workload = "deg20_batch%d" % n
+    instances = P * D * n
     avg_ms = kms / max(launches, 1)
-    achieved = ops_launch / (avg_ms / 1e3) / 1e12
+    peak = int_peak_tops(dev)
+    per_inst = stored_counters("valu", "k_eval_elim_rg24", workload, "int_lane_ops_per_instance")
+    achieved = None if per_inst is None else per_inst * instances / (avg_ms / 1e3) / 1e12
+    rowdeg = [20 - j for j in range(21)]
+    mulmods = model_mulmods(rowdeg, rowdeg)
     roofline = {
         "bound": "alu",
-        "achieved": round(achieved, 3),
-        "peak": round(INT32_PEAK_TOPS, 1),
-        "unit": "T int32-op/s",
-        "frac": round(achieved / INT32_PEAK_TOPS, 4),
-        "traffic": stored_traffic("k_eval_elim_rg24", "deg20_batch%d" % n),
+        "achieved": None if achieved is None else round(achieved, 3),
+        "peak": round(peak, 2),
+        "unit": "T int32-lane-op/s",
+        "frac": None if achieved is None else round(achieved / peak, 4),
+        "traffic": stored_traffic("k_eval_elim_rg24", workload),
         "traffic_unit": "bytes per launch",
         "kernel": "k_eval_elim_rg24 (+ k_eval_elim_fb)",
         "kernel_ms": round(avg_ms, 4),
-        "ops_per_launch": ops_launch,
+        "instances_per_launch": instances,
+        "int_lane_ops_per_instance": per_inst,
+        "counters": "profiles/valu_k_eval_elim_rg24_%s.md" % workload,
+        "model_mulmods_per_instance": mulmods,
+        "model_mulmod_rate_T_per_s": round(mulmods * instances / (avg_ms / 1e3) / 1e12, 3),
     }
 
     out = {
@@ -580,6 +631,7 @@ def main():
         "pipelined": pipe,
         "host_us_per_step": {k: round(v / max(host_calls, 1), 1) for k, v in host_us.items()},
         "graph_replay": graph,
+        "schedules": schedules,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

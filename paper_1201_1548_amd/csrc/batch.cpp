@@ -749,7 +749,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   }
   const JobDev* d_jobs = (const JobDev*)(D0 + o_jobs);
   int nb_ee = 0;
-  for (int bk = 0; bk < NBUCKET + NRG; ++bk) nb_ee += nb_of(K_EE0 + bk);
+  for (int bk = 0; bk < NBUCKET + NRG + NSC; ++bk) nb_ee += nb_of(K_EE0 + bk);
   int* d_ctr = (int*)(D0 + o_ctr);
 
   // The device sequence of the call: metadata upload, kernels, result copies.

@@ -34,3 +34,23 @@ def test_golden_reader_matches_the_loader():
     here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
     for name in ("deg6_res_0.txt", "deg20_res_0.txt"):
         assert bench.read_golden(os.path.join(here, name)) == load(name)[1]
+
+
+def test_model_mulmods_and_peak():
+    rowdeg = [20 - j for j in range(21)]
+    # 231 + 231 evaluation products, 2 * 20 * 20 elimination products
+    assert bench.model_mulmods(rowdeg, rowdeg) == 462 + 800
+    assert abs(bench.int_peak_tops({"cus": 256, "clock_khz": 2400000}) - 39.3216) < 1e-9
+
+
+def test_stored_counters_reads_only_current_sources(tmp_path, monkeypatch):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    digest = bench.kernel_source_digest()
+    (prof / "valu_kx_wl.md").write_text("x\nsource_sha256: %s\nint_lane_ops_per_instance: 3557.5\n" % digest)
+    (prof / "valu_ky_wl.md").write_text("source_sha256: %s\nint_lane_ops_per_instance: 1\n" % ("0" * 64))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: digest)
+    assert bench.stored_counters("valu", "kx", "wl", "int_lane_ops_per_instance") == 3557.5
+    assert bench.stored_counters("valu", "ky", "wl", "int_lane_ops_per_instance") is None
+    assert bench.stored_counters("valu", "kz", "wl", "int_lane_ops_per_instance") is None
