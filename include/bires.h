@@ -396,12 +396,13 @@ int bires_kernel_time(double *ms, int64_t *launches);
 #define BIRES_HOST_PHASES 6
 int bires_host_time(double *us, int64_t *calls);
 
-/* Issue cost of single VALU instructions on the current device, for the
- * roofline: cycles[k] = SIMD clock cycles per wave64 instruction for k = 0..4
- * = v_add_u32, v_min_u32, v_mul_lo_u32, v_mad_u64_u32, v_fma_f64, each timed
- * over 16 independent chains per lane in 16 blocks of 256 threads per CU
- * (best of three launches, HIP events, peak engine clock).  n: entries of
- * cycles (at most 5 are written, the rest are zeroed). */
+/* Issue cost of single instructions on the current device, for the
+ * roofline: cycles[k] = SIMD clock cycles per wave64 instruction for k = 0..5
+ * = v_add_u32, v_min_u32, v_mul_lo_u32, v_mad_u64_u32, v_fma_f64 (each timed
+ * over 16 independent chains per lane) and the int8 matrix-core product
+ * v_mfma_i32_32x32x32_i8 (four independent accumulators), in 16 blocks of 256
+ * threads per CU (best of three launches, HIP events, peak engine clock).
+ * n: entries of cycles (at most 6 are written, the rest are zeroed). */
 int bires_issue_rates(double *cycles, int n);
 
 /* Properties of the current device as the HIP runtime reports them: compute

@@ -540,11 +540,12 @@ def schur_stats():
     return a.value, b.value
 
 
-ISSUE_RATE_INSTRUCTIONS = ("v_add_u32", "v_min_u32", "v_mul_lo_u32", "v_mad_u64_u32", "v_fma_f64")
+ISSUE_RATE_INSTRUCTIONS = ("v_add_u32", "v_min_u32", "v_mul_lo_u32", "v_mad_u64_u32", "v_fma_f64",
+                           "v_mfma_i32_32x32x32_i8")
 
 
 def issue_rates():
-    """SIMD cycles per wave64 instruction of single VALU instructions (dict)."""
+    """SIMD cycles per wave64 instruction of single VALU and matrix-core instructions (dict)."""
     c = (ctypes.c_double * len(ISSUE_RATE_INSTRUCTIONS))()
     _check(lib().bires_issue_rates(c, len(c)), "bires_issue_rates")
     return dict(zip(ISSUE_RATE_INSTRUCTIONS, list(c)))

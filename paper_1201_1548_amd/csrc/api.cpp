@@ -306,7 +306,7 @@ int bires_issue_rates(double* cycles, int n) {
   const double simds = 4.0 * prop.multiProcessorCount, hz = prop.clockRate * 1e3;
   const double waves = (double)blocks * 256 / 64, instr = waves * iters * 16;
   std::lock_guard<std::mutex> lk(cx->stream_mu);
-  for (int k = 0; k < n && k < 5 && rc == BIRES_OK; ++k) {
+  for (int k = 0; k < n && k < 6 && rc == BIRES_OK; ++k) {
     float best = 1e30f;
     for (int rep = 0; rep < 3 && rc == BIRES_OK; ++rep) {
       float ms = 0.f;
@@ -319,7 +319,7 @@ int bires_issue_rates(double* cycles, int n) {
     }
     cycles[k] = simds * hz * best * 1e-3 / instr;  // SIMD-cycles per wave instruction
   }
-  for (int k = 5; k < n; ++k) cycles[k] = 0.0;
+  for (int k = 6; k < n; ++k) cycles[k] = 0.0;
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(out);

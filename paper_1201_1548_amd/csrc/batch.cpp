@@ -542,13 +542,19 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     starts[K_MRC][i + 1] = p.D;  // adjusted below once the largest prime count is known
     starts[K_SUM][i + 1] = (p.D * x.Lacc + 255) / 256;
     starts[K_CAR][i + 1] = debug ? 0 : (x.degcap + 1 + 63) / 64;
-    starts[K_CRT][i + 1] = debug ? 0 : (x.degcap + 1 + 31) / 32;
+    // coefficients below D (the blocks also write the zero ones above them);
+    // adjusted below like K_MRC
+    starts[K_CRT][i + 1] = debug ? 0 : std::min(p.D, x.degcap + 1);
   }
   long long totalD = 0;
   for (int i = 0; i < nj; ++i) totalD += starts[K_MRC][i + 1];
   const bool mrc_lane = mrc_lane_ok(maxP, totalD);
   if (mrc_lane)
     for (int i = 0; i < nj; ++i) starts[K_MRC][i + 1] = (starts[K_MRC][i + 1] + 63) / 64;
+  {
+    const int rows = crt_rows_per_block(maxP);
+    for (int i = 0; i < nj; ++i) starts[K_CRT][i + 1] = (starts[K_CRT][i + 1] + rows - 1) / rows;
+  }
   int maxLcap = 1;
   for (int i = 0; i < nj; ++i)
     if (!w[i].status && w[i].active) maxLcap = std::max(maxLcap, w[i].Lout);
@@ -572,7 +578,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     if (!lastd) use_crt = false;
     crt[i] = {lastd, lastLM};
   }
-  if (use_crt && crt_lds_bytes(maxLcap) > cx->lds_per_block) use_crt = false;
+  if (use_crt && crt_lds_bytes(maxLcap, maxP) > cx->lds_per_block) use_crt = false;
   // staged schedule: interpolation on the matrix cores when at least 32 jobs
   // share D and P (all active jobs of the batch)
   std::vector<int> group;

@@ -30,7 +30,17 @@ namespace bires {
 
 // Block -> job: starts[0..nj] are the first block of each job (starts[nj] =
 // grid size); returns the largest j with starts[j] <= b (uniform, scalar).
-__device__ __forceinline__ int find_job(const int* __restrict__ starts, int nj, int b) {
+// The job j of block b: starts[j] <= b < starts[j + 1] (nj + 1 prefix
+// entries; jobs without blocks repeat an entry).  With the launch's block
+// count `total`, the guess b nj / total is the answer whenever the jobs have
+// equal block counts, and two independent loads confirm it; otherwise (or
+// with total = 0) a binary search, whose dependent loads cost a round trip
+// to L2 each.
+__device__ __forceinline__ int find_job(const int* __restrict__ starts, int nj, int b, int total = 0) {
+  if (total > 0) {
+    const int g = min((int)(((unsigned long long)b * (unsigned)nj) / (unsigned)total), nj - 1);
+    if (starts[g] <= b && b < starts[g + 1]) return g;
+  }
   int lo = 0, hi = nj;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
@@ -222,7 +232,7 @@ __device__ void dev_reduce(const JobDev& J, int lb, int k0, int k1, TablesDev ta
 }
 
 __global__ void k_reduce(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
-  const int job = find_job(starts, nj, blockIdx.x);
+  const int job = find_job(starts, nj, blockIdx.x, gridDim.x);
   dev_reduce(jobs[job], blockIdx.x - starts[job], blockIdx.y * KT, blockIdx.y * KT + KT, tab);
 }
 
@@ -560,7 +570,7 @@ template <int W>
 __global__ __launch_bounds__(W) void k_eval_elim(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
   extern __shared__ __align__(16) uint32_t lds[];
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int job = find_job(starts, nj, b);
+  const int job = find_job(starts, nj, b, gridDim.x);
   dev_eval_elim<W, true>(jobs[job], b - starts[job], tab, lds);
 }
 
@@ -819,7 +829,7 @@ template <int C>
 __device__ __forceinline__ void eval_elim_rg_block(const JobDev* jobs, const int* starts, int nj, TablesDev tab,
                                                    int* fb_count, int* fb_queue, uint32_t* lds) {
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int job = find_job(starts, nj, b);
+  const int job = find_job(starts, nj, b, gridDim.x);
   const bool ok = dev_eval_elim_rg<C>(jobs[job], b - starts[job], tab, lds);
   if (__ballot(!ok) != 0ull && threadIdx.x == 0) fb_queue[atomicAdd(fb_count, 1)] = b;
 }
@@ -887,7 +897,7 @@ __global__ __launch_bounds__(64) void k_schur(const JobDev* jobs, const int* sta
                                               int* fallbacks) {
   extern __shared__ __align__(16) uint32_t lds[];
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int job = find_job(starts, nj, b);
+  const int job = find_job(starts, nj, b, gridDim.x);
   const JobDev& J = jobs[job];
   const int lb = b - starts[job];
   const int k = lb / J.D, pt = lb - k * J.D;
@@ -1281,7 +1291,7 @@ __device__ void dev_interp(const JobDev& J, int k, TablesDev tab, uint32_t* lds,
 __global__ __launch_bounds__(256) void k_interp(const JobDev* jobs, const int* starts, int nj, TablesDev tab,
                                                 InterpTab it) {
   extern __shared__ __align__(16) uint32_t lds[];
-  const int job = find_job(starts, nj, blockIdx.x);
+  const int job = find_job(starts, nj, blockIdx.x, gridDim.x);
   dev_interp(jobs[job], blockIdx.x - starts[job], tab, lds, it);
 }
 
@@ -1419,77 +1429,135 @@ __global__ __launch_bounds__(256) void k_yplanes(const uint32_t* const* gva, int
   }
 }
 
-// One wave per 32 x 32 tile of C for one prime: (Dp/32) (Np/32) P blocks.
+// A block of four waves computes a 64 x 64 block of C for one prime, wave w
+// the 32 x 32 tile (row tile 2 br + w%2, column tile 2 bc + w/2); grid
+// ceil(nit/2) ceil(nnt/2) P blocks in XCD order, so that the blocks of one
+// prime, which share its operand planes, run on one XCD and share its L2.
 // Accumulator register r of lane l holds row 8 (r/4) + 4 (l/32) + r%4 and
 // column l%32 of the tile; operand lanes hold row (A) or column (Y) l%32 and
-// contraction indices 16 (l/32) + 0..15 of the 32-wide step.  The operands of
-// step a0 + 32 are loaded before the products of step a0 are issued.  The
-// reduced tile is transposed through LDS so that each job's 32 coefficients
-// are written as one contiguous segment.
-struct ImOps {
-  im_v4i a0, a1, a2, a3, y0, y1, y2, y3;
-};
+// contraction indices 16 (l/32) + 0..15 of the 32-wide step.
+//
+// The operand blocks of a step (1 KiB per tile and digit plane, 16 in all:
+// the two row tiles' A planes and the two column tiles' Y planes) go from
+// global memory straight into LDS (global_load_lds_dwordx4, no registers),
+// each wave fetching four, into a ring of IM_STAGES stages.  A step waits for
+// its own stage only (vmcnt leaves the younger stage in flight), then a
+// barrier makes every wave's part visible and frees the oldest stage for the
+// loads of step s + IM_STAGES - 1.  Each wave reads its tile's eight operand
+// blocks from LDS: the block's two row tiles share the A planes and its two
+// column tiles the Y planes, so a step fetches half the bytes of four
+// independent tiles.  Tiles past the matrix (odd nit or nnt) clamp their
+// loads to the last tile and write nothing.
+constexpr int IM_STAGES = 3;
+constexpr int IM_STAGE_BYTES = 16 * 1024;
 
-__device__ __forceinline__ ImOps im_load(const int8_t* A, const int8_t* Y, size_t pa, size_t py, int a0) {
-  ImOps o;
-  o.a0 = *(const im_v4i*)(A + a0);
-  o.a1 = *(const im_v4i*)(A + pa + a0);
-  o.a2 = *(const im_v4i*)(A + 2 * pa + a0);
-  o.a3 = *(const im_v4i*)(A + 3 * pa + a0);
-  o.y0 = *(const im_v4i*)(Y + a0);
-  o.y1 = *(const im_v4i*)(Y + py + a0);
-  o.y2 = *(const im_v4i*)(Y + 2 * py + a0);
-  o.y3 = *(const im_v4i*)(Y + 3 * py + a0);
-  return o;
+__device__ __forceinline__ void im_fetch(const int8_t* src, int8_t* dst) {
+  __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
+                                   (void __attribute__((address_space(3)))*)dst, 16, 0, 0);
 }
 
-__global__ __launch_bounds__(64) void k_interp_mfma(uint32_t* const* gco, int N, int Np, int D, int Dp,
-                                                    const int8_t* Ap, const int8_t* Yp, TablesDev tab) {
-  __shared__ uint32_t tile[32][33];
-  __shared__ uint32_t* colp[32];
-  const int l = threadIdx.x, r32 = l & 31, g = l >> 5;
-  // one-dimensional grid in XCD order: the tiles of one prime, which share
-  // its operand planes, run on one XCD and share its L2
-  const int nit = Dp >> 5, nnt = Np >> 5;
+// vmcnt(n) with the other counters left alone (gfx9 s_waitcnt encoding:
+// vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8), then the block
+// barrier.  The compiler inserts no wait of its own for LDS written by
+// global_load_lds, and s_barrier alone does not order memory accesses for
+// it: the empty asm statements with a memory clobber keep the LDS reads of
+// the step below the wait and the barrier.
+#define IM_WAIT_VM_BARRIER(n)                                                        \
+  do {                                                                               \
+    asm volatile("" ::: "memory");                                                   \
+    __builtin_amdgcn_s_waitcnt((((n) & 15) | (((n) >> 4) << 14)) | 0x0F70);          \
+    __builtin_amdgcn_s_barrier();                                                    \
+    asm volatile("" ::: "memory");                                                   \
+  } while (0)
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_interp_mfma(
+    uint32_t* const* gco, int N, int Np, int D, int Dp, const int8_t* Ap, const int8_t* Yp, TablesDev tab) {
+  extern __shared__ __align__(16) int8_t im_lds[];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, r32 = l & 31, g = l >> 5;
+  const int nit = Dp >> 5, nnt = Np >> 5, nbr = (nit + 1) >> 1, nbc = (nnt + 1) >> 1;
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int k = lb / (nit * nnt), rem = lb - k * nit * nnt;
-  const int it = rem % nit, nt = rem / nit;
-  const int i0 = it * 32, n0 = nt * 32;
+  const int k = lb / (nbr * nbc), rem = lb - k * nbr * nbc;
+  const int br = rem % nbr, bc = rem / nbr;
+  const int it = 2 * br + (w & 1), nt = 2 * bc + (w >> 1);
+  const bool live = it < nit && nt < nnt;
   const size_t pa = (size_t)Dp * Dp, py = (size_t)Np * Dp;
-  // operand-order blocks: 1 KiB per (row tile, step); a lane reads bytes 16 l..16 l + 15
-  const int8_t* A = Ap + (size_t)k * 4 * pa + (size_t)it * Dp * 32 + 16 * l;
-  const int8_t* Y = Yp + (size_t)k * 4 * py + (size_t)nt * Dp * 32 + 16 * l;
-  // each column's output row (null past the group), loaded now so that the
-  // latency overlaps the products; every job of the group has P primes
-  uint32_t* const cp = gco[min(n0 + r32, N - 1)];
-  im_v16i G0 = {0}, G1 = {0}, G2 = {0}, G3 = {0}, G4 = {0}, G5 = {0}, G6 = {0};
-  ImOps cur = im_load(A, Y, pa, py, 0);
-  for (int a0 = 0; a0 < Dp; a0 += 32) {
-    const ImOps o = cur;
-    if (a0 + 32 < Dp) cur = im_load(A, Y, pa, py, (a0 + 32) * 32);
-    G0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a0, o.y0, G0, 0, 0, 0);
-    G1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a0, o.y1, G1, 0, 0, 0);
-    G1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a1, o.y0, G1, 0, 0, 0);
-    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a0, o.y2, G2, 0, 0, 0);
-    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a1, o.y1, G2, 0, 0, 0);
-    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a2, o.y0, G2, 0, 0, 0);
-    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a0, o.y3, G3, 0, 0, 0);
-    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a1, o.y2, G3, 0, 0, 0);
-    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a2, o.y1, G3, 0, 0, 0);
-    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a3, o.y0, G3, 0, 0, 0);
-    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a1, o.y3, G4, 0, 0, 0);
-    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a2, o.y2, G4, 0, 0, 0);
-    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a3, o.y1, G4, 0, 0, 0);
-    G5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a2, o.y3, G5, 0, 0, 0);
-    G5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a3, o.y2, G5, 0, 0, 0);
-    G6 = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a3, o.y3, G6, 0, 0, 0);
+  // this wave's four fetches per step: waves 0, 1 the A planes of row tiles
+  // 2 br, 2 br + 1, waves 2, 3 the Y planes of column tiles 2 bc, 2 bc + 1
+  // (operand-order blocks: 1 KiB per (tile, step), lane l holds bytes 16 l..)
+  const int8_t* src;
+  size_t pstride;
+  if (w < 2) {
+    src = Ap + (size_t)k * 4 * pa + (size_t)min(2 * br + w, nit - 1) * Dp * 32 + 16 * l;
+    pstride = pa;
+  } else {
+    src = Yp + (size_t)k * 4 * py + (size_t)min(2 * bc + w - 2, nnt - 1) * Dp * 32 + 16 * l;
+    pstride = py;
   }
+  // stage layout: [row tile 0: 4 planes][row tile 1][column tile 0][column tile 1], 1 KiB each
+  int8_t* const dst0 = im_lds + w * 4096;
+  const int ra = (w & 1) * 4096 + 16 * l, ry = 8192 + (w >> 1) * 4096 + 16 * l;
+  const int nsteps = Dp >> 5;
+  const int n0 = nt * 32, i0 = it * 32;
+  // each column's output row (null past the group or the matrix), loaded
+  // before the products so that its latency is hidden; every job of the
+  // group has P primes
+  uint32_t* const cpp = l < 32 && live && n0 + l < N ? gco[n0 + l] : nullptr;
+#pragma unroll
+  for (int st = 0; st < IM_STAGES - 1; ++st) {
+    if (st < nsteps) {
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) im_fetch(src + pl * pstride + st * 1024, dst0 + st * IM_STAGE_BYTES + pl * 1024);
+    }
+  }
+  im_v16i G0 = {0}, G1 = {0}, G2 = {0}, G3 = {0}, G4 = {0}, G5 = {0}, G6 = {0};
+  for (int s = 0; s < nsteps; ++s) {
+    // this wave's fetches of step s (and the column pointer load before
+    // them) are done once at most those of step s + 1 remain
+    if (s + 1 < nsteps)
+      IM_WAIT_VM_BARRIER(4);
+    else
+      IM_WAIT_VM_BARRIER(0);
+    const int8_t* sb = im_lds + (s % IM_STAGES) * IM_STAGE_BYTES;
+    const im_v4i a0 = *(const im_v4i*)(sb + ra), a1 = *(const im_v4i*)(sb + ra + 1024),
+                 a2 = *(const im_v4i*)(sb + ra + 2048), a3 = *(const im_v4i*)(sb + ra + 3072);
+    const im_v4i y0 = *(const im_v4i*)(sb + ry), y1 = *(const im_v4i*)(sb + ry + 1024),
+                 y2 = *(const im_v4i*)(sb + ry + 2048), y3 = *(const im_v4i*)(sb + ry + 3072);
+    // the stage read at step s - 1 is free: every wave passed this barrier
+    // after its reads of it completed
+    const int sn = s + IM_STAGES - 1;
+    if (sn < nsteps) {
+      int8_t* d = dst0 + (sn % IM_STAGES) * IM_STAGE_BYTES;
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) im_fetch(src + pl * pstride + (size_t)sn * 1024, d + pl * 1024);
+    }
+    G0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, y0, G0, 0, 0, 0);
+    G1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, y1, G1, 0, 0, 0);
+    G1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, y0, G1, 0, 0, 0);
+    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, y2, G2, 0, 0, 0);
+    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, y1, G2, 0, 0, 0);
+    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, y0, G2, 0, 0, 0);
+    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, y3, G3, 0, 0, 0);
+    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, y2, G3, 0, 0, 0);
+    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, y1, G3, 0, 0, 0);
+    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, y0, G3, 0, 0, 0);
+    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, y3, G4, 0, 0, 0);
+    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, y2, G4, 0, 0, 0);
+    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, y1, G4, 0, 0, 0);
+    G5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, y3, G5, 0, 0, 0);
+    G5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, y2, G5, 0, 0, 0);
+    G6 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, y3, G6, 0, 0, 0);
+  }
+  // every wave's last reads are done before the ring is reused for the transposes
+  __syncthreads();
+  uint32_t(*tile)[33] = (uint32_t(*)[33])(im_lds + w * (32 * 33 * 4));
+  uint32_t** colp = (uint32_t**)(im_lds + 4 * (32 * 33 * 4)) + 32 * w;
+  if (l < 32) colp[l] = cpp ? cpp + (size_t)k * D : nullptr;
   const ModP q = tab.primes[k];
-  uint32_t w[7];  // Montgomery forms of 256^u
-  w[0] = q.one;
+  uint32_t wu[7];  // Montgomery forms of 256^u
+  wu[0] = q.one;
   const uint32_t m256 = to_mont(256u, q);
 #pragma unroll
-  for (int u = 1; u < 7; ++u) w[u] = mmul(w[u - 1], m256, q);
+  for (int u = 1; u < 7; ++u) wu[u] = mmul(wu[u - 1], m256, q);
   // |G_u| <= 4 Dp 2^14 <= 2^28 and w_u < p < 2^31, so sum_u G_u w_u lies
   // within 7 * 2^58.5 < 2^62 < p 2^32; adding p 2^32 (a multiple of p) makes
   // it non-negative and below 2 p 2^32, where one Montgomery reduction
@@ -1497,13 +1565,12 @@ __global__ __launch_bounds__(64) void k_interp_mfma(uint32_t* const* gco, int N,
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int32_t gv[7] = {G0[r], G1[r], G2[r], G3[r], G4[r], G5[r], G6[r]};
-    int64_t t = (int64_t)q.p << 32;
+    int64_t acc = (int64_t)q.p << 32;
 #pragma unroll
-    for (int u = 0; u < 7; ++u) t += (int64_t)gv[u] * (int64_t)(int32_t)w[u];
-    const uint32_t v = redc((uint64_t)t, q.p, q.pinv);
+    for (int u = 0; u < 7; ++u) acc += (int64_t)gv[u] * (int64_t)(int32_t)wu[u];
+    const uint32_t v = redc((uint64_t)acc, q.p, q.pinv);
     tile[r32][8 * (r >> 2) + 4 * g + (r & 3)] = umin32(v, v - q.p);  // [column][row]
   }
-  if (l < 32) colp[l] = n0 + l < N ? cp + (size_t)k * D : nullptr;
   __syncthreads();
   // lanes 0-31 write column n0 + 2c, lanes 32-63 column n0 + 2c + 1: 32 rows each
   const int i = i0 + r32;
@@ -1512,6 +1579,13 @@ __global__ __launch_bounds__(64) void k_interp_mfma(uint32_t* const* gco, int N,
     uint32_t* dst = colp[col];
     if (dst && i < D) dst[i] = tile[col][r32];
   }
+}
+
+static size_t interp_mfma_lds_bytes() {
+  // the stage ring, reused after the products for four transposes and column pointers
+  const size_t ring = (size_t)IM_STAGES * IM_STAGE_BYTES;
+  const size_t epi = 4 * (32 * 33 * 4) + 4 * 32 * sizeof(uint32_t*);
+  return ring > epi ? ring : epi;
 }
 
 // Inverse factorials per prime: invfact[k][n] = Montgomery form of 1/n!.
@@ -1581,7 +1655,7 @@ __device__ void dev_mrc_lane(const JobDev& J, int lb, TablesDev tab, uint32_t* l
 
 __global__ __launch_bounds__(64) void k_mrc_lane(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
   extern __shared__ __align__(16) uint32_t lds[];
-  const int job = find_job(starts, nj, blockIdx.x);
+  const int job = find_job(starts, nj, blockIdx.x, gridDim.x);
   dev_mrc_lane(jobs[job], blockIdx.x - starts[job], tab, lds);
 }
 
@@ -1621,7 +1695,7 @@ __device__ void dev_mrc_wave(const JobDev& J, int c, TablesDev tab, uint32_t* ld
 
 __global__ __launch_bounds__(64) void k_mrc(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
   extern __shared__ __align__(16) uint32_t lds[];
-  const int job = find_job(starts, nj, blockIdx.x);
+  const int job = find_job(starts, nj, blockIdx.x, gridDim.x);
   dev_mrc_wave(jobs[job], blockIdx.x - starts[job], tab, lds);
 }
 
@@ -1651,7 +1725,7 @@ __device__ void dev_limbs_sum(const JobDev& J, int lb, TablesDev tab) {
 }
 
 __global__ void k_limbs_sum(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
-  const int job = find_job(starts, nj, blockIdx.x);
+  const int job = find_job(starts, nj, blockIdx.x, gridDim.x);
   dev_limbs_sum(jobs[job], blockIdx.x - starts[job], tab);
 }
 
@@ -1716,7 +1790,7 @@ __device__ void dev_limbs_carry(const JobDev& J, int lb, int stage_ld, uint32_t*
 
 __global__ __launch_bounds__(64) void k_limbs_carry(const JobDev* jobs, const int* starts, int nj, int stage_ld) {
   extern __shared__ __align__(16) uint32_t lds[];
-  const int job = find_job(starts, nj, blockIdx.x);
+  const int job = find_job(starts, nj, blockIdx.x, gridDim.x);
   dev_limbs_carry(jobs[job], blockIdx.x - starts[job], stage_ld, lds);
 }
 
@@ -1734,103 +1808,156 @@ __global__ __launch_bounds__(64) void k_limbs_carry(const JobDev* jobs, const in
 // S_c = sum_{k,s} d_ks e_k(c - s).  For one coefficient per row that is a
 // product [rows x 4P] x [4P x byte columns] whose right operand depends only on
 // P (crt_tables builds it in operand order); |S_c| < 2^23 for P <= 128.
-// One wave per 32 coefficients of one job: the lanes form the digit words of
-// their rows' y_k straight into the left operand (lane x + 32 g: row x,
-// primes 8 ks + 4 g + 0..3 of step ks, four digits each), then for each tile
-// of 32 byte columns, low to high, v_mfma_i32_32x32x32_i8 over the steps, the
-// tile through LDS, and lanes 0..31 fold its 32 columns into eight 32-bit
-// limbs of X - t M with a signed carry kept in a register.  The limbs are
-// staged in LDS rows of sld words and written as one contiguous range.
+// One wave per 32 NT coefficients of one job, in NT row tiles of 32 (NT = 2
+// up to 48 primes, 1 above, for registers): the lanes form the digit words
+// of their rows' y_k straight into the left operands (lane x + 32 g: row x
+// of each tile, primes 8 ks + 4 g + 0..3 of step ks, four digits each), then
+// for each tile of 32 byte columns, low to high, v_mfma_i32_32x32x32_i8 over
+// the steps for every row tile with one right operand, the tiles through
+// LDS, and lane l < 32 NT folds row l's 32 columns into eight 32-bit limbs of
+// X - t M with a signed carry kept in a register (at NT = 2 every lane has a
+// row of the serial carry chain).  The limbs are staged in LDS rows of sld
+// words and written as one contiguous range.
 constexpr int CRT_MAXP = 128;
 
 // Every lane runs the same instructions: indices past the job's primes or
 // degree bound are clamped for the loads and their values masked to zero, and
 // all KSMAX steps run (the left operand is zero past the job's KS steps), so
 // the loads of a phase are issued together instead of behind per-lane branches.
+//
+// A job has ceil(min(D, degcap + 1) / rows) blocks.  The coefficients above
+// the last block up to the output capacity (the degree bound of the
+// extents, which can be twice D) are zero; each block of the job writes an
+// equal share of them while its residue loads are in flight.
+//
+// Up to 64 primes the right operand blocks of column tile ct + 2 are loaded
+// while tile ct is folded (two register sets, the loop unrolled by two),
+// which hides the L2 latency behind two tiles of work; above, those of tile
+// ct + 1.
 template <int KSMAX>
-__global__ __launch_bounds__(64) void k_crt_mfma(const JobDev* jobs, const int* starts, int nj, int sld,
+__device__ __forceinline__ void crt_load_b(im_v4i (&B)[KSMAX], const __attribute__((address_space(1))) uint32_t* Bt,
+                                           int ct, int NCT, int KS) {
+  const __attribute__((address_space(1))) uint32_t* Bn = Bt + (size_t)min(ct, NCT - 1) * KS * 256;
+#pragma unroll
+  for (int ks = 0; ks < KSMAX; ++ks)
+    B[ks] = *(const __attribute__((address_space(1))) im_v4i*)(Bn + (size_t)min(ks, KS - 1) * 256);
+}
+
+template <int KSMAX, int NT>
+__global__ __launch_bounds__(64) void k_crt_mfma(const JobDev* jobs, const int* starts, int nj, int sld, int cps,
                                                  TablesDev tab) {
+  constexpr int ROWS = 32 * NT;
   extern __shared__ __align__(16) uint32_t lds[];
-  const int job = find_job(starts, nj, blockIdx.x);
+  const int l = threadIdx.x, x = l & 31, g = l >> 5;
+  const int job = find_job(starts, nj, blockIdx.x, gridDim.x);
   const JobDev& J = jobs[job];
   const int P = J.P, D = J.D, Lc = J.Lcap, LM = J.crt_LM;
   const int KS = (P + 7) >> 3, NCT = (4 * LM + 4 + 31) >> 5;
-  const int l = threadIdx.x, x = l & 31, g = l >> 5;
-  const int c0 = (blockIdx.x - starts[job]) * 32, c = c0 + x;
-  if (c0 >= D) {
-    // beyond the degree bound: zero coefficients up to the output capacity
-    const int nr = min(32, J.degcap + 1 - c0);
-    uint32_t* dst = J.out + (size_t)c0 * Lc;
-    for (int i = l; i < nr * Lc; i += 64) dst[i] = 0u;
-    return;
-  }
-  int32_t* T = (int32_t*)lds;   // [32][33]: one accumulator tile, [row][column]
-  uint32_t* O = lds + 32 * 33;  // [32][sld]: limbs of the rows, then the prime constants
+  const int bj = blockIdx.x - starts[job], c0 = bj * ROWS;
+  int32_t* T = (int32_t*)lds;     // [ROWS][33]: the accumulator tiles, [row][column]
+  uint32_t* O = lds + ROWS * 33;  // [ROWS][sld]: limbs of the rows, then the prime constants
   const uint32_t* wv = J.crt;
   const uint32_t* Mw = J.crt + P + (size_t)P * LM;
   const __attribute__((address_space(1))) uint32_t* Bt =
       gmem(J.crt) + (((size_t)P + (size_t)P * LM + LM + 3) & ~(size_t)3) + 4 * l;
-  const bool row = c < D;
-  const __attribute__((address_space(1))) uint32_t* col = gmem(J.coefs) + min(c, D - 1);
-  // this lane's residues (primes 8 ks + 4 g + j), all issued before the barrier
-  uint32_t xr[KSMAX * 4];
+  bool rv[NT];
+  // this lane's residues (primes 8 ks + 4 g + j) of its row in each tile, all
+  // issued before the barrier
+  uint32_t xr[NT][KSMAX * 4];
 #pragma unroll
-  for (int u = 0; u < KSMAX * 4; ++u) xr[u] = col[(size_t)min(8 * (u >> 2) + 4 * g + (u & 3), P - 1) * D];
-  // per-prime constants staged in LDS: p, -p^{-1} mod 2^32, w_k, 1 / p_k;
-  // then the words of M, zero from LM up to the last byte column's limb
-  uint32_t* Cp = O + 32 * sld;
-  double* Ci = (double*)(Cp + 3 * CRT_MAXP);
-  uint32_t* Ms = Cp + 5 * CRT_MAXP;
+  for (int h = 0; h < NT; ++h) {
+    rv[h] = c0 + 32 * h + x < D;
+    const __attribute__((address_space(1))) uint32_t* col = gmem(J.coefs) + min(c0 + 32 * h + x, D - 1);
+#pragma unroll
+    for (int u = 0; u < KSMAX * 4; ++u) xr[h][u] = col[(size_t)min(8 * (u >> 2) + 4 * g + (u & 3), P - 1) * D];
+  }
+  // the first column tiles' operand blocks (two sets up to 64 primes, one
+  // above, for registers), also issued before the barrier
+  constexpr bool B2 = KSMAX <= 8;
+  im_v4i Ba[KSMAX], Bb[B2 ? KSMAX : 1];
+  crt_load_b<KSMAX>(Ba, Bt, 0, NCT, KS);
+  if constexpr (B2) crt_load_b<KSMAX>(Bb, Bt, 1, NCT, KS);
+  {
+    // this block's share of the zero coefficients above the job's last block
+    const int nbj = (min(D, J.degcap + 1) + ROWS - 1) / ROWS, cz = nbj * ROWS;
+    if (cz <= J.degcap) {
+      const long long nw = (long long)(J.degcap + 1 - cz) * Lc, share = (nw + nbj - 1) / nbj;
+      const long long w0 = bj * share, w1 = min(nw, w0 + share);
+      uint32_t* dst = J.out + (size_t)cz * Lc;
+      for (long long i = w0 + l; i < w1; i += 64) dst[i] = 0u;
+    }
+  }
+  // per-prime constants staged in LDS at stride cps (the batch's largest
+  // prime count, rounded up to even): p, -p^{-1} mod 2^32, w_k, 1 / p_k; then
+  // the words of M, zero from LM up to the last byte column's limb
+  uint32_t* Cp = O + ROWS * sld;
+  double* Ci = (double*)(Cp + 3 * cps);
+  uint32_t* Ms = Cp + 5 * cps;
   for (int k = l; k < P; k += 64) {
     const ModP q = tab.primes[k];
     Cp[k] = q.p;
-    Cp[CRT_MAXP + k] = q.pinv;
-    Cp[2 * CRT_MAXP + k] = wv[k];
+    Cp[cps + k] = q.pinv;
+    Cp[2 * cps + k] = wv[k];
     Ci[k] = tab.inv_p[k];
   }
   for (int w = l; w < 8 * NCT; w += 64) Ms[w] = w < LM ? Mw[w] : 0u;
   __syncthreads();
-  im_v4i A[KSMAX];
-  double f = 0.0;
+  im_v4i A[NT][KSMAX];
+  double f[NT];
+#pragma unroll
+  for (int h = 0; h < NT; ++h) f[h] = 0.0;
 #pragma unroll
   for (int ks = 0; ks < KSMAX; ++ks) {
-    uint32_t d[4];
+    uint32_t d[NT][4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int u = 4 * ks + j, kl = 8 * ks + 4 * g + j, k = min(kl, P - 1);
-      const uint32_t p = Cp[k], pinv = Cp[CRT_MAXP + k];
-      const bool live = row && kl < P;
-      const uint32_t y = redc((uint64_t)xr[u] * Cp[2 * CRT_MAXP + k], p, pinv);
-      const int32_t ys = y > (p >> 1) ? (int32_t)(y - p) : (int32_t)y;
-      f = fma((double)(live ? ys : 0), Ci[k], f);
-      d[j] = digits4(y, p) & (0u - (uint32_t)live);
+      const uint32_t p = Cp[k], pinv = Cp[cps + k], wk = Cp[2 * cps + k];
+      const double ip = Ci[k];
+#pragma unroll
+      for (int h = 0; h < NT; ++h) {
+        const bool live = rv[h] && kl < P;
+        const uint32_t y = redc((uint64_t)xr[h][u] * wk, p, pinv);
+        const int32_t ys = y > (p >> 1) ? (int32_t)(y - p) : (int32_t)y;
+        f[h] = fma((double)(live ? ys : 0), ip, f[h]);
+        d[h][j] = digits4(y, p) & (0u - (uint32_t)live);
+      }
     }
-    A[ks] = (im_v4i){(int)d[0], (int)d[1], (int)d[2], (int)d[3]};
+#pragma unroll
+    for (int h = 0; h < NT; ++h) A[h][ks] = (im_v4i){(int)d[h][0], (int)d[h][1], (int)d[h][2], (int)d[h][3]};
   }
-  f += __shfl_xor(f, 32);
-  const int64_t tq = (int64_t)floor(f + 0.5);
+  // from here on lane l < ROWS owns row c0 + l (row x of tile g)
+  int64_t tq = 0;
+  bool row = false;
+#pragma unroll
+  for (int h = 0; h < NT; ++h) {
+    const double fs = f[h] + __shfl_xor(f[h], 32);
+    if (g == h) {
+      tq = (int64_t)floor(fs + 0.5);
+      row = rv[h];
+    }
+  }
+  const bool owner = l < ROWS;
   int64_t carry = 0;
   uint32_t last = 0;
   bool bad = false, nz = false;
-  im_v4i B[KSMAX];
+  // one column tile: products, the tiles through LDS, the carry chain
+  auto tile = [&](int ct, const im_v4i(&B)[KSMAX]) {
+    im_v16i acc[NT];
 #pragma unroll
-  for (int ks = 0; ks < KSMAX; ++ks)
-    B[ks] = *(const __attribute__((address_space(1))) im_v4i*)(Bt + (size_t)min(ks, KS - 1) * 256);
-  for (int ct = 0; ct < NCT; ++ct) {
-    im_v16i acc = {0};
-#pragma unroll
-    for (int ks = 0; ks < KSMAX; ++ks) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[ks], B[ks], acc, 0, 0, 0);
-    // the next tile's operand blocks and this tile's words of M
-    const __attribute__((address_space(1))) uint32_t* Bn = Bt + (size_t)min(ct + 1, NCT - 1) * KS * 256;
+    for (int h = 0; h < NT; ++h) acc[h] = (im_v16i){0};
 #pragma unroll
     for (int ks = 0; ks < KSMAX; ++ks)
-      B[ks] = *(const __attribute__((address_space(1))) im_v4i*)(Bn + (size_t)min(ks, KS - 1) * 256);
-    // accumulator register r of lane l: row 8 (r / 4) + 4 g + r % 4, column x
 #pragma unroll
-    for (int r = 0; r < 16; ++r) T[(8 * (r >> 2) + 4 * g + (r & 3)) * 33 + x] = acc[r];
+      for (int h = 0; h < NT; ++h) acc[h] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[h][ks], B[ks], acc[h], 0, 0, 0);
+    // accumulator register r of lane l: row 8 (r / 4) + 4 g + r % 4 of its tile, column x
+#pragma unroll
+    for (int h = 0; h < NT; ++h)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) T[(32 * h + 8 * (r >> 2) + 4 * g + (r & 3)) * 33 + x] = acc[h][r];
     __syncthreads();
-    if (g == 0) {
-      const int32_t* t = T + x * 33;
+    if (owner) {
+      const int32_t* t = T + l * 33;
 #pragma unroll
       for (int w = 0; w < 8; ++w) {
         const int L = 8 * ct + w;
@@ -1841,7 +1968,7 @@ __global__ __launch_bounds__(64) void k_crt_mfma(const JobDev* jobs, const int* 
         const uint32_t limb = (uint32_t)v;
         carry = v >> 32;
         if (L < Lc) {
-          O[x * sld + L] = limb;
+          O[l * sld + L] = limb;
           nz |= limb != 0u;
           last = limb;
         } else if (limb != ((int32_t)last < 0 ? 0xFFFFFFFFu : 0u)) {
@@ -1850,24 +1977,39 @@ __global__ __launch_bounds__(64) void k_crt_mfma(const JobDev* jobs, const int* 
       }
     }
     __syncthreads();
+  };
+  if constexpr (B2) {
+    for (int ct = 0; ct < NCT; ct += 2) {
+      tile(ct, Ba);
+      crt_load_b<KSMAX>(Ba, Bt, ct + 2, NCT, KS);
+      if (ct + 1 < NCT) {
+        tile(ct + 1, Bb);
+        crt_load_b<KSMAX>(Bb, Bt, ct + 3, NCT, KS);
+      }
+    }
+  } else {
+    for (int ct = 0; ct < NCT; ++ct) {
+      tile(ct, Ba);
+      crt_load_b<KSMAX>(Ba, Bt, ct + 1, NCT, KS);
+    }
   }
-  if (g == 0) {
+  if (owner) {
     // limbs above the last byte column: the carry's extension
     for (int L = 8 * NCT; L < Lc; ++L) {
       const uint32_t limb = (uint32_t)carry;
       carry >>= 32;
-      O[x * sld + L] = limb;
+      O[l * sld + L] = limb;
       nz |= limb != 0u;
       last = limb;
     }
     if (row && (bad || carry != ((int32_t)last < 0 ? -1 : 0))) atomicOr(J.err, 1);
   }
-  // one atomic per wave: the highest non-zero coefficient of the 32
-  const uint64_t any = __ballot(g == 0 && row && nz);
+  // one atomic per wave: the highest non-zero coefficient of the block
+  const uint64_t any = __ballot(owner && row && nz);
   if (any && l == 0) atomicMax(J.deg_out, c0 + 63 - __clzll((long long)any));
   __syncthreads();
   // rows c0 .. c0 + nr - 1 are one contiguous range of nr Lc words
-  const int nr = min(32, J.degcap + 1 - c0);
+  const int nr = min(ROWS, J.degcap + 1 - c0);
   uint32_t* dst = J.out + (size_t)c0 * Lc;
   const int dq = 64 / Lc, dr = 64 - dq * Lc;
   int r = l / Lc, L = l - r * Lc;
@@ -2222,10 +2364,30 @@ void launch_gather_rows(const uint32_t* src, int ld, const int* idx, int rows, i
 
 // Issue-rate probe for the roofline: every lane runs 16 independent chains
 // of one VALU instruction (inline assembly, so the compiler can neither fold
-// nor reorder them); the host divides the SIMD-cycles of the launch by the
-// wave instructions issued.  Writes one word per thread.
+// nor reorder them), or for K = 5 sixteen int8 matrix-core products
+// v_mfma_i32_32x32x32_i8 per round over four independent accumulators; the
+// host divides the SIMD-cycles of the launch by the wave instructions
+// issued.  Writes one word per thread.
 template <int K>
 __global__ __launch_bounds__(256) void k_issue_rate(uint32_t* out, uint32_t s, int iters) {
+  if constexpr (K == 5) {
+    const im_v4i x = {(int)(threadIdx.x * 0x01010101u), (int)s, 3, -5}, y = {7, (int)threadIdx.x, -1, 9};
+    im_v16i c0 = {0}, c1 = {0}, c2 = {0}, c3 = {0};
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        c0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(x, y, c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(y, x, c1, 0, 0, 0);
+        c2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(x, x, c2, 0, 0, 0);
+        c3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(y, y, c3, 0, 0, 0);
+      }
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) r += (uint32_t)(c0[e] ^ c1[e] ^ c2[e] ^ c3[e]);
+    out[blockIdx.x * 256 + threadIdx.x] = r;
+    return;
+  }
   uint32_t a[16];
   uint64_t w[16];
   double f[16];
@@ -2262,7 +2424,8 @@ void launch_issue_rate(int kind, uint32_t* out, int blocks, int iters, hipStream
     case 1: hipLaunchKernelGGL(k_issue_rate<1>, dim3(blocks), dim3(256), 0, s, out, 7u, iters); break;
     case 2: hipLaunchKernelGGL(k_issue_rate<2>, dim3(blocks), dim3(256), 0, s, out, 7u, iters); break;
     case 3: hipLaunchKernelGGL(k_issue_rate<3>, dim3(blocks), dim3(256), 0, s, out, 7u, iters); break;
-    default: hipLaunchKernelGGL(k_issue_rate<4>, dim3(blocks), dim3(256), 0, s, out, 7u, iters); break;
+    case 4: hipLaunchKernelGGL(k_issue_rate<4>, dim3(blocks), dim3(256), 0, s, out, 7u, iters); break;
+    default: hipLaunchKernelGGL(k_issue_rate<5>, dim3(blocks), dim3(256), 0, s, out, 7u, iters); break;
   }
 }
 
@@ -2387,7 +2550,9 @@ void launch_interp_mfma(const uint32_t* const* gva, uint32_t* const* gco, int N,
   const int Dp = (D + 31) & ~31, Np = (N + 31) & ~31;
   const int chunks = Np * (Dp / 16);
   hipLaunchKernelGGL(k_yplanes, dim3((chunks + 255) / 256, P), dim3(256), 0, s, gva, N, Np, D, Dp, tab, Yp);
-  hipLaunchKernelGGL(k_interp_mfma, dim3((Dp / 32) * (Np / 32) * P), dim3(64), 0, s, gco, N, Np, D, Dp, Ap, Yp, tab);
+  const int nbr = (Dp / 32 + 1) / 2, nbc = (Np / 32 + 1) / 2;
+  hipLaunchKernelGGL(k_interp_mfma, dim3(nbr * nbc * P), dim3(256), interp_mfma_lds_bytes(), s, gco, N, Np, D, Dp,
+                     Ap, Yp, tab);
 }
 
 bool mrc_lane_ok(int max_primes, long long total_coefficients) {
@@ -2411,34 +2576,45 @@ bool crt_ok(int max_primes) { return max_primes <= CRT_MAXP; }
 
 int crt_row_stride(int max_lcap) { return max_lcap | 1; }
 
-// words of M for the largest prime count, rounded up to whole column tiles
-static int crt_max_words() { return 8 * ((4 * (CRT_MAXP + 1) + 4 + 31) / 32); }
+// Stride of the per-prime constants (even, so that the doubles stay aligned)
+// and the words of M for a prime count (M < 2^(32 P) has at most P words),
+// rounded up to whole column tiles, both sized by the batch's largest prime
+// count rather than CRT_MAXP, which keeps the blocks small.
+static int crt_const_stride(int max_primes) { return (max_primes + 1) & ~1; }
+static int crt_max_words(int max_primes) { return 8 * ((4 * (max_primes + 1) + 4 + 31) / 32); }
 
-size_t crt_lds_bytes(int max_lcap) {
-  // accumulator tile, limb rows (an even word count), prime constants
-  const size_t rows = (size_t)32 * crt_row_stride(max_lcap);
-  return (size_t)(32 * 33 + rows + 5 * CRT_MAXP + crt_max_words()) * sizeof(uint32_t);
+// Coefficients per block: two row tiles while the left operands of both fit
+// in registers (up to 48 primes), one above.
+int crt_rows_per_block(int max_primes) { return max_primes <= 48 ? 64 : 32; }
+
+size_t crt_lds_bytes(int max_lcap, int max_primes) {
+  // accumulator tiles, limb rows (an even word count), prime constants
+  const int R = crt_rows_per_block(max_primes);
+  const size_t rows = (size_t)R * crt_row_stride(max_lcap);
+  return (size_t)(R * 33 + rows + 5 * crt_const_stride(max_primes) + crt_max_words(max_primes)) * sizeof(uint32_t);
 }
 
 void launch_crt(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, int max_lcap,
                 TablesDev tab, hipStream_t s) {
   const int sld = crt_row_stride(max_lcap);
-  const size_t lds = crt_lds_bytes(max_lcap);
+  const int cps = crt_const_stride(max_primes);
+  const size_t lds = crt_lds_bytes(max_lcap, max_primes);
   const int ks = (max_primes + 7) / 8;
-#define BIRES_CRT_LAUNCH(K) \
-  hipLaunchKernelGGL(k_crt_mfma<K>, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, sld, tab)
+#define BIRES_CRT_LAUNCH(K, NT) \
+  hipLaunchKernelGGL((k_crt_mfma<K, NT>), dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, sld, cps, tab)
+  // two row tiles exactly when crt_rows_per_block(max_primes) is 64 (ks <= 6)
   if (ks <= 2)
-    BIRES_CRT_LAUNCH(2);
+    BIRES_CRT_LAUNCH(2, 2);
   else if (ks <= 4)
-    BIRES_CRT_LAUNCH(4);
+    BIRES_CRT_LAUNCH(4, 2);
   else if (ks <= 6)
-    BIRES_CRT_LAUNCH(6);
+    BIRES_CRT_LAUNCH(6, 2);
   else if (ks <= 8)
-    BIRES_CRT_LAUNCH(8);
+    BIRES_CRT_LAUNCH(8, 1);
   else if (ks <= 12)
-    BIRES_CRT_LAUNCH(12);
+    BIRES_CRT_LAUNCH(12, 1);
   else
-    BIRES_CRT_LAUNCH(16);
+    BIRES_CRT_LAUNCH(16, 1);
 #undef BIRES_CRT_LAUNCH
 }
 

@@ -85,11 +85,12 @@ bool mrc_lane_ok(int max_primes, long long total_coefficients);
 void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, bool lane, TablesDev tab,
                 hipStream_t s);
 // Explicit CRT straight to limbs on the matrix cores (k_crt_mfma): one wave
-// per 32 output coefficients, ceil((degcap+1)/32) blocks per job; needs
-// crt_ok(max primes), the jobs' crt tables (crt_tables layout) and
-// crt_lds_bytes(max output limbs) within the LDS per block.
+// per crt_rows_per_block(max primes) output coefficients, ceil((degcap+1)/rows) blocks
+// per job; needs crt_ok(max primes), the jobs' crt tables (crt_tables layout)
+// and crt_lds_bytes(max output limbs, max primes) within the LDS per block.
 bool crt_ok(int max_primes);
-size_t crt_lds_bytes(int max_lcap);
+size_t crt_lds_bytes(int max_lcap, int max_primes);
+int crt_rows_per_block(int max_primes);
 void launch_crt(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, int max_lcap,
                 TablesDev tab, hipStream_t s);
 void launch_limbs_sum(const JobDev* jobs, const int* starts, int nj, int nblocks, TablesDev tab, hipStream_t s);

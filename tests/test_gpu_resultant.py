@@ -291,6 +291,23 @@ def test_shared_shape_batch_matrix_core_interpolation():
         assert zx.evaluate(res[i], 11) == resultant_at(*pairs[i], 11)
 
 
+@pytest.mark.parametrize("n", [32, 33, 97])
+def test_matrix_core_interpolation_block_edges(n):
+    # the matrix-core interpolation runs four-wave blocks over 64 x 64 blocks
+    # of the coefficient matrix: 32 jobs leave a block's second column tile
+    # past the matrix, 33 and 97 jobs leave part of the last column tile past
+    # the group, and the deg-6 point count fills one row-tile pair exactly
+    # (deg-6 pairs 0 and 3 share D = 37 and P = 5, which the path needs)
+    idx = [(0, 3)[i % 2] for i in range(n)]
+    jobs = [("res",) + synth.pair_deg6(j) + ("y",) for j in idx]
+    assert len({br.plan(F, G)[:2] for _, F, G, _ in jobs}) == 1
+    say("deg6 batch", n)
+    res, st = br.resultant_batch(jobs)
+    assert st == [0] * n
+    for i, j in enumerate(idx):
+        assert res[i] == load("deg6_res_%d.txt" % j)[1], i
+
+
 def test_deg20_full_batch_in_the_bench_configuration():
     # the timed workload itself: 256 dense total-degree-20 pairs as device-memory batches
     # (plan reuse on), synchronous and with two batches in flight; pair 0
