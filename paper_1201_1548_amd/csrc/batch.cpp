@@ -620,8 +620,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   for (int i = 0; i < nj; ++i)
     if (!w[i].status && w[i].active) w[i].o_rowdeg = ws.take((size_t)(w[i].pl.m + w[i].pl.n + 2) * 4);
   const size_t o_maps = ws.take(sizeof(int) * (size_t)NK * (nj + 1));
-  // the group's vals and coefs pointers
-  const size_t o_gva = ws.take(sizeof(uint32_t*) * group.size());
+  // the group's coefs pointers
   const size_t o_gco = ws.take(sizeof(uint32_t*) * group.size());
   enum { F_STAGES = 6 };
   std::vector<int> fst[F_STAGES];
@@ -726,11 +725,15 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   for (int kk = 0; kk < NK; ++kk) std::memcpy(hm + (size_t)kk * (nj + 1), starts[kk].data(), sizeof(int) * (nj + 1));
   auto st_of = [&](int kk) { return dm + (size_t)kk * (nj + 1); };
   if (!group.empty()) {
-    const uint32_t** gva = (const uint32_t**)(H0 + o_gva);
     uint32_t** gco = (uint32_t**)(H0 + o_gco);
     for (size_t n = 0; n < group.size(); ++n) {
-      gva[n] = (const uint32_t*)(D0 + w[group[n]].o_vals);
       gco[n] = (uint32_t*)(D0 + w[group[n]].o_coefs);
+      // the evaluation writes this job's values into column n of the digit planes
+      JobDev& J = h_jobs[group[n]];
+      J.yp = (int8_t*)(D0 + o_yp);
+      J.ycol = (int)n;
+      J.ynp = gNp;
+      J.ydp = gDp;
     }
   }
   if (fused) {
@@ -855,12 +858,12 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
       if (run && timing) DEV(hipEventRecord(ev1, st));
       if (!debug) {
         sg.add((const void*)itW, (const void*)itQ, itNB);
-        sg.add((int)group.size(), gD, gP, (const void*)vinv, o_yp, o_gva, o_gco, nb_of(K_IP), maxD, use_crt, nb_of(K_CAR),
+        sg.add((int)group.size(), gD, gP, (const void*)vinv, o_yp, o_gco, nb_of(K_IP), maxD, use_crt, nb_of(K_CAR),
                nb_of(K_CRT), maxLcap, nb_of(K_MRC), mrc_lane, nb_of(K_SUM));
         if (run) {
           if (!group.empty())
-            launch_interp_mfma((const uint32_t* const*)(D0 + o_gva), (uint32_t* const*)(D0 + o_gco), (int)group.size(),
-                               gD, gP, vinv, (int8_t*)(D0 + o_yp), cx->tab, st);
+            launch_interp_mfma((uint32_t* const*)(D0 + o_gco), (int)group.size(), gD, gP, vinv,
+                               (const int8_t*)(D0 + o_yp), cx->tab, st);
           else if (nb_of(K_IP))
             launch_interp(d_jobs, st_of(K_IP), nj, nb_of(K_IP), maxD, cx->tab, itW, itQ, itNB, st);
           if (use_crt) {

@@ -38,6 +38,11 @@ struct JobDev {
   int32_t crt_LM;           // limbs of M = prod_{k<P} p_k
   int32_t* deg_out;         // highest non-zero coefficient index (init -1)
   int32_t* err;             // set non-zero on a failed internal check
+  // jobs of the matrix-core interpolation group: the values go straight into
+  // the group's digit planes (column ycol of ynp, ydp points per plane) instead
+  // of vals; null otherwise
+  int8_t* yp;
+  int32_t ycol, ynp, ydp;
 };
 
 // One modular gcd over P primes (see k_gcd_p).

@@ -10,14 +10,15 @@
 //                 _rg32 keep f's coefficient array in registers
 //   k_interp      (d) interpolation per prime, nodes a = 0..D-1
 //   k_interp_mfma (d) interpolation of a batch sharing the nodes, int8 matrix
-//                 cores (digit planes by k_yplanes, V^{-1} by k_vinv)
+//                 cores (value digit planes written by the evaluation
+//                 kernels, V^{-1} by k_vinv)
 //   k_invfact     table of 1/n! mod p (set-up)
 //   k_crt_mfma    (e) explicit CRT straight to limbs, int8 matrix cores
 //   k_mrc         (e) mixed-radix (Garner) digits per coefficient
 //   k_limbs_sum / k_limbs_carry   (e) digits -> two's-complement limbs
 //
 // Every kernel is batch-native: an array of per-job first-block indices maps
-// each block to its job (binary search), so a single job is a batch of one.
+// each block to its job (find_job), so a single job is a batch of one.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -450,6 +451,48 @@ __device__ __forceinline__ uint32_t fold96(const Acc96& S, const ModP& q) {
   return madd(redc(t, q.p, q.pinv), reduce32((uint32_t)(S.lo >> 32), q.p), q.p);
 }
 
+// Byte offset of element (row, idx) of a digit plane of the matrix-core
+// interpolation with Kp = padded contraction length, in operand order: 1 KiB
+// blocks per (32-row tile, 32-wide step), lane l of an operand holding row
+// l % 32 and contraction indices 16 (l / 32) + 0..15.
+__device__ __forceinline__ size_t im_off(int row, int idx, int Kp) {
+  const int rt = row >> 5, r = row & 31, ks = idx >> 5, g = (idx >> 4) & 1, b = idx & 15;
+  return ((((size_t)rt * (Kp >> 5) + ks) * 64) + r + 32 * g) * 16 + b;
+}
+
+// The four balanced base-256 digits of the symmetric representative v of
+// x mod p, packed little-endian into one word.  Adding 128 at each of the
+// three low digit positions makes those digits d_s + 128 in [0, 255] (plain
+// base 256), with the top digit (|d_3| <= 64) left in the top byte; flipping
+// bit 7 of the three low bytes subtracts the 128 again in int8 terms.
+__device__ __forceinline__ uint32_t digits4(uint32_t x, uint32_t p) {
+  const uint32_t v = x > (p >> 1) ? x - p : x;
+  return (v + 0x808080u) ^ 0x808080u;
+}
+
+// The value v = R(a) mod p_k (plain residue) of point a of job J: into vals,
+// or for a job of the matrix-core interpolation group straight into the
+// group's four digit planes of prime k (column ycol), which the
+// interpolation reads as its right operand.  Those planes are not cleared:
+// columns past the group only reach output columns that are not written,
+// and points in [D, Dp) meet zero entries of the inverse Vandermonde planes.
+// (A call, not inlined: the register allocation of the evaluation kernels'
+// loops stays that of a single store.)
+__device__ __noinline__ void put_planes(int8_t* yp, int ycol, int ynp, int ydp, int k, int a, uint32_t v, uint32_t p) {
+  const size_t plane = (size_t)ynp * ydp;
+  int8_t* base = yp + (size_t)k * 4 * plane + im_off(ycol, a, ydp);
+  const uint32_t d = digits4(v, p);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) base[s * plane] = (int8_t)(d >> (8 * s));
+}
+
+__device__ __forceinline__ void put_value(const JobDev& J, int k, int a, uint32_t v, uint32_t p) {
+  if (J.yp)
+    put_planes(J.yp, J.ycol, J.ynp, J.ydp, k, a, v, p);
+  else
+    J.vals[(size_t)k * J.D + a] = v;
+}
+
 // Read-only data with wave-uniform addresses, read through the scalar cache.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(4))) const uint32_t cu32;
@@ -553,7 +596,7 @@ __device__ __forceinline__ void dev_eval_elim(const JobDev& J, int lb, TablesDev
   const ModP q = tab.primes[k];
   eval_pair<W, SC>(J, k, pt, q, A, B);
   const uint32_t r = uni_resultant<W>(A, B, m, n, q);
-  J.vals[(size_t)k * J.D + pt] = from_mont(r, q);
+  put_value(J, k, pt, from_mont(r, q), q.p);
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin in blockIdx order, and
@@ -821,7 +864,7 @@ __device__ __forceinline__ bool dev_eval_elim_rg(const JobDev& J, int lb, Tables
   num = mmul(num, last, q);
   uint32_t r = den == q.one ? num : mmul(num, minv(den, q), q);
   if (neg) r = mneg(r, q.p);
-  J.vals[(size_t)k * J.D + pt] = from_mont(r, q);
+  put_value(J, k, pt, from_mont(r, q), q.p);
   return true;
 }
 
@@ -976,9 +1019,9 @@ __global__ __launch_bounds__(64) void k_schur(const JobDev* jobs, const int* sta
     }
   }
   if (ok) {
-    if (lane == 0) J.vals[(size_t)k * J.D + pt] = from_mont(mmul(num, minv(den, q), q), q);
+    if (lane == 0) put_value(J, k, pt, from_mont(mmul(num, minv(den, q), q), q), q.p);
   } else if (lane == 0) {
-    J.vals[(size_t)k * J.D + pt] = from_mont(uni_resultant<1>(Af, Bg, m, n, q), q);
+    put_value(J, k, pt, from_mont(uni_resultant<1>(Af, Bg, m, n, q), q), q.p);
     atomicAdd(fallbacks, 1);
   }
 }
@@ -1335,26 +1378,9 @@ size_t interp_lds_words(int D) { return (size_t)3 * D + (size_t)((D + KB - 1) / 
 typedef int im_v4i __attribute__((ext_vector_type(4)));
 typedef int im_v16i __attribute__((ext_vector_type(16)));
 
-// The four balanced base-256 digits of the symmetric representative v of
-// x mod p, packed little-endian into one word.  Adding 128 at each of the
-// three low digit positions makes those digits d_s + 128 in [0, 255] (plain
-// base 256), with the top digit (|d_3| <= 64) left in the top byte; flipping
-// bit 7 of the three low bytes subtracts the 128 again in int8 terms.
-__device__ __forceinline__ uint32_t digits4(uint32_t x, uint32_t p) {
-  const uint32_t v = x > (p >> 1) ? x - p : x;
-  return (v + 0x808080u) ^ 0x808080u;
-}
-
 __device__ __forceinline__ void put_digits(int8_t* base, size_t plane, size_t off, uint32_t d) {
 #pragma unroll
   for (int s = 0; s < 4; ++s) base[s * plane + off] = (int8_t)(d >> (8 * s));
-}
-
-// Byte offset of element (row, idx) of a plane with Kp = padded contraction
-// length, in the operand-order layout described above.
-__device__ __forceinline__ size_t im_off(int row, int idx, int Kp) {
-  const int rt = row >> 5, r = row & 31, ks = idx >> 5, g = (idx >> 4) & 1, b = idx & 15;
-  return ((((size_t)rt * (Kp >> 5) + ks) * 64) + r + 32 * g) * 16 + b;
 }
 
 // V^{-1} mod p_k for k = blockIdx.x: Ap[k][s][i][a] (s: digit, i: coefficient,
@@ -1396,36 +1422,6 @@ __global__ __launch_bounds__(256) void k_vinv(int D, int Dp, TablesDev tab, int8
       if (j) qj = madd(cur[j], mmul(aM, qj, q), q.p);  // q_{j-1} = n_j + a q_j
     }
     for (int i = D; i < Dp; ++i) put_digits(base, plane, im_off(i, a, Dp), 0u);
-  }
-}
-
-// Digit planes of the values of the group's jobs (gva[n] = their vals), zero
-// for n >= N or a >= D.  One thread per 16 consecutive nodes of one job: 16
-// values in (clamped loads, no branches), one aligned 16-byte chunk out per
-// plane.  Grid (ceil(Np Dp / 16 / 256), P).
-__global__ __launch_bounds__(256) void k_yplanes(const uint32_t* const* gva, int N, int Np, int D, int Dp,
-                                                 TablesDev tab, int8_t* Yp) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x, k = blockIdx.y;
-  const int per = Dp >> 4;
-  if (idx >= Np * per) return;
-  const int n = idx / per, a0 = (idx - n * per) * 16;
-  const uint32_t p = tab.primes[k].p;
-  const size_t plane = (size_t)Np * Dp;
-  int8_t* base = Yp + (size_t)k * 4 * plane + im_off(n, a0, Dp);
-  const __attribute__((address_space(1))) uint32_t* v = gmem(gva[min(n, N - 1)]) + (size_t)k * D;
-  uint32_t d[16];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) d[u] = v[min(a0 + u, D - 1)];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) d[u] = digits4(d[u], p) & (n < N && a0 + u < D ? ~0u : 0u);
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    uint32_t w[4];
-#pragma unroll
-    for (int q4 = 0; q4 < 4; ++q4)
-      w[q4] = ((d[4 * q4] >> (8 * s)) & 255u) | (((d[4 * q4 + 1] >> (8 * s)) & 255u) << 8) |
-              (((d[4 * q4 + 2] >> (8 * s)) & 255u) << 16) | (((d[4 * q4 + 3] >> (8 * s)) & 255u) << 24);
-    *(uint4*)(base + s * plane) = make_uint4(w[0], w[1], w[2], w[3]);
   }
 }
 
@@ -1502,6 +1498,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   // before the products so that its latency is hidden; every job of the
   // group has P primes
   uint32_t* const cpp = l < 32 && live && n0 + l < N ? gco[n0 + l] : nullptr;
+  const ModP q = tab.primes[k];  // likewise
 #pragma unroll
   for (int st = 0; st < IM_STAGES - 1; ++st) {
     if (st < nsteps) {
@@ -1511,8 +1508,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   }
   im_v16i G0 = {0}, G1 = {0}, G2 = {0}, G3 = {0}, G4 = {0}, G5 = {0}, G6 = {0};
   for (int s = 0; s < nsteps; ++s) {
-    // this wave's fetches of step s (and the column pointer load before
-    // them) are done once at most those of step s + 1 remain
+    // this wave's fetches of step s (and the loads before them) are done
+    // once at most those of step s + 1 remain
     if (s + 1 < nsteps)
       IM_WAIT_VM_BARRIER(4);
     else
@@ -1552,7 +1549,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   uint32_t(*tile)[33] = (uint32_t(*)[33])(im_lds + w * (32 * 33 * 4));
   uint32_t** colp = (uint32_t**)(im_lds + 4 * (32 * 33 * 4)) + 32 * w;
   if (l < 32) colp[l] = cpp ? cpp + (size_t)k * D : nullptr;
-  const ModP q = tab.primes[k];
   uint32_t wu[7];  // Montgomery forms of 256^u
   wu[0] = q.one;
   const uint32_t m256 = to_mont(256u, q);
@@ -2545,11 +2541,9 @@ void launch_vinv(int D, int Dp, int P, TablesDev tab, int8_t* Ap, hipStream_t s)
   hipLaunchKernelGGL(k_vinv, dim3(P), dim3(256), (size_t)2 * (D + 1) * sizeof(uint32_t), s, D, Dp, tab, Ap);
 }
 
-void launch_interp_mfma(const uint32_t* const* gva, uint32_t* const* gco, int N, int D, int P, const int8_t* Ap,
-                        int8_t* Yp, TablesDev tab, hipStream_t s) {
+void launch_interp_mfma(uint32_t* const* gco, int N, int D, int P, const int8_t* Ap, const int8_t* Yp, TablesDev tab,
+                        hipStream_t s) {
   const int Dp = (D + 31) & ~31, Np = (N + 31) & ~31;
-  const int chunks = Np * (Dp / 16);
-  hipLaunchKernelGGL(k_yplanes, dim3((chunks + 255) / 256, P), dim3(256), 0, s, gva, N, Np, D, Dp, tab, Yp);
   const int nbr = (Dp / 32 + 1) / 2, nbc = (Np / 32 + 1) / 2;
   hipLaunchKernelGGL(k_interp_mfma, dim3(nbr * nbc * P), dim3(256), interp_mfma_lds_bytes(), s, gco, N, Np, D, Dp,
                      Ap, Yp, tab);

@@ -76,8 +76,8 @@ size_t interp_lds_words(int D);
 // jobs' coefs.
 size_t vinv_bytes(int Dp, int P);
 void launch_vinv(int D, int Dp, int P, TablesDev tab, int8_t* Ap, hipStream_t s);
-void launch_interp_mfma(const uint32_t* const* gva, uint32_t* const* gco, int N, int D, int P, const int8_t* Ap,
-                        int8_t* Yp, TablesDev tab, hipStream_t s);
+void launch_interp_mfma(uint32_t* const* gco, int N, int D, int P, const int8_t* Ap, const int8_t* Yp, TablesDev tab,
+                        hipStream_t s);
 void launch_invfact(const ModP* primes, int K, uint32_t* invfact, int dmax, hipStream_t s);
 // mrc blocks per job: ceil(D/64) with lane = true (one lane per coefficient,
 // allowed when mrc_lane_ok), else D (one wave per coefficient).

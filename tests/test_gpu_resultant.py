@@ -308,6 +308,25 @@ def test_matrix_core_interpolation_block_edges(n):
         assert res[i] == load("deg6_res_%d.txt" % j)[1], i
 
 
+@pytest.mark.parametrize("kernel", ["auto", "lds", "schur"])
+def test_matrix_core_interpolation_from_every_evaluation_kernel(kernel):
+    # in a batch of >= 32 jobs sharing D and P the evaluation kernels write the
+    # values straight into the interpolation's digit planes: the register
+    # kernel, the LDS kernel and the Schur kernel each against the oracle
+    pairs = [synth.pair_deg20(i) for i in range(34)]
+    say("deg20 batch, evaluation kernel", kernel)
+    br.set_eval_kernel(kernel)
+    try:
+        res, st = br.resultant_batch([("res", F, G, "y") for F, G in pairs])
+    finally:
+        br.set_eval_kernel("auto")
+    assert st == [0] * len(pairs)
+    assert res[0] == load("deg20_res_0.txt")[1]
+    for i in (1, 20, 33):
+        for x in (2, -9):
+            assert zx.evaluate(res[i], x) == resultant_at(*pairs[i], x), (i, x)
+
+
 def test_deg20_full_batch_in_the_bench_configuration():
     # the timed workload itself: 256 dense total-degree-20 pairs as device-memory batches
     # (plan reuse on), synchronous and with two batches in flight; pair 0
