@@ -279,8 +279,8 @@ template <int W>
 __device__ __forceinline__ void eliminate(uint32_t* __restrict__ A, const uint32_t* __restrict__ B, int a, int b,
                                           uint32_t lb, const ModP& q) {
   if (a == b + 1) {
-    const uint32_t n1 = mneg(A[a * W], q.p);
-    const uint32_t n2 = mneg(mdot2(lb, A[(a - 1) * W], n1, B[(b - 1) * W], q), q.p);
+    const uint32_t n1 = mneg_factor(A[a * W], q.p);
+    const uint32_t n2 = mneg_factor(mdot2(lb, A[(a - 1) * W], n1, B[(b - 1) * W], q), q.p);
     const uint32_t l2 = mmul(lb, lb, q), l1 = mmul(lb, n1, q);
     uint32_t bp = B[0];
     A[0] = mdot2(l2, A[0], n2, bp, q);
@@ -302,7 +302,7 @@ __device__ __forceinline__ void eliminate(uint32_t* __restrict__ A, const uint32
     return;
   }
   for (; a >= b; --a) {
-    const uint32_t nla = mneg(A[a * W], q.p);
+    const uint32_t nla = mneg_factor(A[a * W], q.p);
     const int s = a - b;
     for (int t = 0; t < s; ++t) A[t * W] = mmul(lb, A[t * W], q);
     int t = s;
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(W) void k_eval_elim(const JobDev* jobs, const int* 
 template <int C, bool AREG>
 __device__ __forceinline__ void rg_elim(uint32_t (&X)[C], uint32_t* __restrict__ L, int bs, int ap, uint32_t lb,
                                         const ModP& q) {
-  const uint32_t nla = mneg(RG_A(0), q.p);
+  const uint32_t nla = mneg_factor(RG_A(0), q.p);
 #pragma unroll
   for (int j0 = 0; j0 < C - 1; j0 += 4) {
     if (j0 + 4 < C && j0 + 4 <= bs) {
@@ -689,8 +689,8 @@ __device__ __forceinline__ void rg_elim(uint32_t (&X)[C], uint32_t* __restrict__
 template <int C, bool AREG>
 __device__ __forceinline__ void rg_fused(uint32_t (&X)[C], uint32_t* __restrict__ L, int bs, uint32_t lb,
                                          const ModP& q) {
-  const uint32_t n1 = mneg(RG_A(0), q.p);
-  const uint32_t n2 = mneg(mdot2(lb, RG_A(1), n1, RG_B(1), q), q.p);
+  const uint32_t n1 = mneg_factor(RG_A(0), q.p);
+  const uint32_t n2 = mneg_factor(mdot2(lb, RG_A(1), n1, RG_B(1), q), q.p);
   const uint32_t l2 = mmul(lb, lb, q), l1 = mmul(lb, n1, q);
 #pragma unroll
   for (int k0 = 0; k0 < C - 2; k0 += 4) {
@@ -745,8 +745,8 @@ __device__ __forceinline__ RgStep rg_fstep(uint32_t (&X)[C], uint32_t* __restric
   // keep the scheduler from hoisting later steps' loads (register pressure)
   __builtin_amdgcn_sched_barrier(0);
   const uint32_t lb = RG_B(0);
-  const uint32_t n1 = mneg(RG_A(0), q.p);
-  const uint32_t n2 = mneg(mdot2(lb, RG_A(1), n1, RG_B(1), q), q.p);
+  const uint32_t n1 = mneg_factor(RG_A(0), q.p);
+  const uint32_t n2 = mneg_factor(mdot2(lb, RG_A(1), n1, RG_B(1), q), q.p);
   const uint32_t l2 = mmul(lb, lb, q), l1 = mmul(lb, n1, q);
 #pragma unroll
   for (int k = 0; k < B - 1; ++k) RG_SET_A(k, mdot3(l2, RG_A(k + 2), l1, RG_B(k + 2), n2, RG_B(k + 1), q));
@@ -998,7 +998,7 @@ __global__ __launch_bounds__(64) void k_schur(const JobDev* jobs, const int* sta
     den = mmul(den, c, q);
     c = mmul(c, d, q);
     if (s == r - 1) break;
-    const uint32_t nc0 = mneg(c0, q.p), ne0 = mneg(e0, q.p);
+    const uint32_t nc0 = mneg_factor(c0, q.p), ne0 = mneg_factor(e0, q.p);
     uint32_t l[NR], u[NR];
 #pragma unroll
     for (int h = 0; h < NR; ++h) {
