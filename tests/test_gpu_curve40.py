@@ -6,10 +6,13 @@ on sampled outputs the oracle computes one by one: R(a) mod q for a 61-bit
 prime q (determinant of the specialised Sylvester matrix over F_q, keeping the
 formal degrees).  The gcd is checked by its defining properties: it divides R
 and R' exactly, its cofactors are coprime (their gcd modulo a prime that does
-not divide their leading coefficients is 1), its leading coefficient is
-positive.  A smaller curve of the same construction is compared with the
-oracle in full."""
+not divide their leading coefficients is 1), its content is the gcd of the
+contents of R and R', and its leading coefficient is positive.  A smaller
+curve of the same construction is compared with the oracle in full.  (The
+curve discriminants also have full-size parity through the oracle's node
+digests in tests/test_gpu_fullsize.py.)"""
 
+import math
 import random
 
 import pytest
@@ -35,10 +38,16 @@ def check_R_samples(F, R, points):
 
 
 def check_gcd(R, h):
+    # h is the normalised gcd of R and R' exactly when it divides both, the
+    # cofactors are coprime, its content is gcd(cont R, cont R') (the content
+    # of a gcd is the gcd of the contents) and its leading coefficient is
+    # positive; coprimality of the cofactors is checked modulo a large prime
+    # that keeps their degrees (a common factor over Z stays common mod p)
     dR = zx.derivative(R)
     qa = zx.exact_div(R, h)
     qb = zx.exact_div(dR, h)
     assert h[-1] > 0
+    assert zx.content(h) == math.gcd(zx.content(R), zx.content(dR))
     p = 2305843009213693951  # 2^61 - 1
     assert qa[-1] % p and qb[-1] % p
     assert gcd_mod_p(qa, qb, p) == [1]
