@@ -16,8 +16,9 @@ struct ScanTask {
 };
 
 void launch_scan(const ScanTask* tasks, const int4* bmap, int nblocks, hipStream_t s);
-// Issue-rate probe: kind 0..4 = v_add_u32, v_min_u32, v_mul_lo_u32,
-// v_mad_u64_u32, v_fma_f64; 16 chains per lane, `iters` rounds; out holds
+// Issue-rate probe: kind 0..5 = v_add_u32, v_min_u32, v_mul_lo_u32,
+// v_mad_u64_u32, v_fma_f64 (16 chains per lane), v_mfma_i32_32x32x32_i8
+// (16 products per round over 4 accumulators); `iters` rounds; out holds
 // blocks * 256 words.
 void launch_issue_rate(int kind, uint32_t* out, int blocks, int iters, hipStream_t s);
 // Sets *flag (not cleared here) when got[0..n) and want[0..n) differ.
@@ -69,11 +70,11 @@ int interp_table_blocks(int max_points);
 size_t interp_table_words(int blocks, int primes, size_t* q_offset);
 void launch_interp_tables(int blocks, int primes, TablesDev tab, uint32_t* W, uint32_t* Q, hipStream_t s);
 size_t interp_lds_words(int D);
-// Interpolation of N jobs sharing D and P (gva[n] and gco[n] the vals and
-// coefs of job n of the group) as int8 matrix-core products with V^{-1}: Ap =
-// vinv_bytes(Dp, P) bytes built by launch_vinv (Dp = D rounded up to 32);
-// Yp = 4 Np Dp P bytes of workspace (Np = N rounded up to 32).  Writes the
-// jobs' coefs.
+// Interpolation of N jobs sharing D and P (gco[n] the coefs of job n of the
+// group) as int8 matrix-core products with V^{-1}: Ap = vinv_bytes(Dp, P)
+// bytes built by launch_vinv (Dp = D rounded up to 32); Yp = 4 Np Dp P bytes
+// (Np = N rounded up to 32) holding the jobs' values as digit planes, which
+// the evaluation kernels write (JobDev::yp).  Writes the jobs' coefs.
 size_t vinv_bytes(int Dp, int P);
 void launch_vinv(int D, int Dp, int P, TablesDev tab, int8_t* Ap, hipStream_t s);
 void launch_interp_mfma(uint32_t* const* gco, int N, int D, int P, const int8_t* Ap, const int8_t* Yp, TablesDev tab,
@@ -85,9 +86,11 @@ bool mrc_lane_ok(int max_primes, long long total_coefficients);
 void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, bool lane, TablesDev tab,
                 hipStream_t s);
 // Explicit CRT straight to limbs on the matrix cores (k_crt_mfma): one wave
-// per crt_rows_per_block(max primes) output coefficients, ceil((degcap+1)/rows) blocks
-// per job; needs crt_ok(max primes), the jobs' crt tables (crt_tables layout)
-// and crt_lds_bytes(max output limbs, max primes) within the LDS per block.
+// per rows = crt_rows_per_block(max primes) output coefficients,
+// ceil(min(D, degcap + 1) / rows) blocks per job, which also write the job's
+// zero coefficients above them up to degcap; needs crt_ok(max primes), the
+// jobs' crt tables (crt_tables layout) and crt_lds_bytes(max output limbs,
+// max primes) within the LDS per block.
 bool crt_ok(int max_primes);
 size_t crt_lds_bytes(int max_lcap, int max_primes);
 int crt_rows_per_block(int max_primes);
