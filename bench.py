@@ -296,6 +296,62 @@ def _zx_mul(a, b):
     return out
 
 
+def bench_autotune(args):
+    """The schedule space per workload shape: every schedule (staged, fused,
+    Schur) timed on the same device batch, checked bit-exact against the staged
+    results, and the autotuner's choice (bires_autotune, one timing per
+    schedule) next to the fastest measured one."""
+    import torch
+    import paper_1201_1548_amd as br
+    from paper_1201_1548_amd import synth
+
+    torch.cuda.set_device(0)
+    shapes = {}
+    shapes["deg20_batch256"] = [("res",) + synth.pair_deg20(s) + ("y",) for s in range(256)]
+    shapes["curve40_disc3"] = [("disc", synth.curve_deg40(0), None, "y"),
+                               ("disc", synth.singular_curve_deg40(0), None, "y"),
+                               ("disc", synth.singular_curve_deg40(0, square_k=True, dk=10), None, "y")]
+    curves, pairs = synth.arrangement_batch(0)
+    shapes["arrangement_3800"] = [("res", curves[i], curves[j], "y") for i, j in pairs]
+    reqs = synth.poisson_requests(0, n=64, qps=1.0)
+    shapes["serving_batch64"] = [(r["kind"], r["f"], r["g"], "y") for r in reqs]
+    cases = {}
+    agree = 0
+    for name, jobs in shapes.items():
+        batch = br.DeviceBatch(jobs)
+        br.set_schedule("staged")
+        batch.run()
+        torch.cuda.synchronize()
+        ref = batch.results()
+        times = {}
+        for sched in ("staged", "fused", "schur"):
+            br.set_schedule(sched)
+            batch.run()
+            torch.cuda.synchronize()
+            ok = batch.results() == ref
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                batch.run()
+            torch.cuda.synchronize()
+            times[sched] = {"ms_per_step": round((time.perf_counter() - t0) / reps * 1e3, 3), "bit_exact": ok}
+        br.set_schedule("auto")
+        chosen = batch.autotune(reps=1)
+        fastest = min(times, key=lambda k: times[k]["ms_per_step"])
+        agree += chosen == fastest
+        cases[name] = {"jobs": len(jobs), "schedules": times, "autotuner": chosen, "fastest": fastest}
+    br.set_schedule(args.schedule)
+    return {
+        "metric": "schedule space per workload shape: step time of each schedule and the autotuner's choice",
+        "value": agree, "unit": "shapes where the autotuner chose the fastest schedule", "n_gpus": 1,
+        "steps": 3, "warmup": 1, "ms_per_step": cases["deg20_batch256"]["schedules"][cases["deg20_batch256"]["autotuner"]]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "the deg-20 bench batch, the three degree-40 discriminants, the 3800 arrangement "
+                               "pairs and a batch of the first 64 serving requests"},
+        "cases": cases,
+    }
+
+
 def bench_curve40(args):
     """Curve analysis: res(f, f_y; y) of a dense total-degree-40 curve (16-bit
     coefficients), gcd(R, R') and the square-free decomposition of R; per-call
@@ -425,7 +481,8 @@ def main():
                     help="skip the leg with two batches in flight (the headline is then the synchronous leg)")
     ap.add_argument("--eval-kernel", default="auto", choices=["auto", "lds"],
                     help="evaluation + elimination kernel of the staged schedule")
-    ap.add_argument("--workload", default="deg20", choices=["deg20", "curve40", "arrangement", "serving", "copy", "rates"])
+    ap.add_argument("--workload", default="deg20",
+                    choices=["deg20", "curve40", "arrangement", "serving", "autotune", "copy", "rates"])
     ap.add_argument("--schedule", default="auto", choices=["auto", "staged", "fused"])
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--qps", type=float, default=0.0)
@@ -438,7 +495,7 @@ def main():
         sys.exit(2)
     if args.workload != "deg20":
         fn = {"curve40": bench_curve40, "arrangement": bench_arrangement, "serving": bench_serving,
-              "copy": bench_copy, "rates": bench_rates}[args.workload]
+              "autotune": bench_autotune, "copy": bench_copy, "rates": bench_rates}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
 
