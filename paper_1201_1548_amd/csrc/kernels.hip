@@ -1207,42 +1207,72 @@ struct InterpTab {
   int nb = 0;
 };
 
+// LDS layout (words): region R (2 D + 144) holding first a (D + 8, zeros past
+// D) and b (4 zeros, then D values, then 8 zeros), later the two padded
+// Horner buffers (D + 72 each, coefficient idx at 36 + idx, zeros outside the
+// current degree); then the Newton coefficients (D); then T_b, Q_b per block.
+// Each thread produces four consecutive outputs of a contraction and keeps a
+// sliding window of four operands in registers, so a multiply-add costs a
+// quarter of an LDS read instead of two.
 __device__ void dev_interp(const JobDev& J, int k, TablesDev tab, uint32_t* lds, InterpTab it = InterpTab{}) {
   const int D = J.D;
   const ModP q = tab.primes[k];
   const uint32_t r3 = mmul(q.r2, q.r2, q);  // (R^2)_M = R^3 mod p
   const int nb = (D + KB - 1) / KB;
-  uint32_t* A = lds;            // a_i, later P (ping)
-  uint32_t* Bv = lds + D;       // b_j, later P (pong)
-  uint32_t* C = lds + 2 * D;    // Newton coefficients
-  uint32_t* TQ = lds + 3 * D;   // per block: T_b (KB words) then Q_b (KB+1 words)
+  uint32_t* A = lds;                 // a_i = v_i / i!, i < D + 8 (zero past D)
+  uint32_t* Bz = lds + D + 8;        // b_j = (-1)^j / j! at Bz[4 + j], zero outside [0, D)
+  uint32_t* C = lds + 2 * D + 144;   // Newton coefficients
+  uint32_t* TQ = C + D;              // per block: T_b (KB words) then Q_b (KB+1 words)
   const uint32_t* invf = tab.invfact + (size_t)k * tab.dmax;
   const uint32_t* v = J.vals + (size_t)k * D;
-  for (int i = threadIdx.x; i < D; i += blockDim.x) {
-    const uint32_t f = invf[i];  // Montgomery form of 1/i!
-    A[i] = mmul(v[i], f, q);
-    const uint32_t bj = from_mont(f, q);
-    Bv[i] = (i & 1) ? mneg(bj, q.p) : bj;
+  for (int i = threadIdx.x; i < D + 8; i += blockDim.x) {
+    uint32_t av = 0u, bv = 0u;
+    if (i < D) {
+      const uint32_t f = invf[i];  // Montgomery form of 1/i!
+      av = mmul(v[i], f, q);
+      const uint32_t bj = from_mont(f, q);
+      bv = (i & 1) ? mneg(bj, q.p) : bj;
+    }
+    A[i] = av;
+    Bz[4 + i] = bv;
+    if (i < 4) Bz[i] = 0u;
   }
   __syncthreads();
-  for (int kk = threadIdx.x; kk < D; kk += blockDim.x) {
-    Acc96 acc;
-    int i = 0;
-    for (; i + 4 <= kk + 1; i += 4) {
-      uint64_t s = (uint64_t)A[i] * Bv[kk - i];
-      s += (uint64_t)A[i + 1] * Bv[kk - i - 1];
-      s += (uint64_t)A[i + 2] * Bv[kk - i - 2];
-      s += (uint64_t)A[i + 3] * Bv[kk - i - 3];
-      acc.add(s);
+  // c_kk = sum_{i <= kk} a_i b_{kk-i} for kk = kk0 .. kk0 + 3: the window
+  // holds b_{kk0+u-i}; terms with kk0 + u < i read the zeros below b_0
+  for (int kk0 = 4 * threadIdx.x; kk0 < D; kk0 += 4 * blockDim.x) {
+    const uint32_t* bb = Bz + 4 + kk0;
+    uint64_t w0 = bb[0], w1 = bb[1], w2 = bb[2], w3 = bb[3];
+    Acc96 c0, c1, c2, c3;
+    for (int i = 0; i < kk0 + 4; i += 4) {
+      // four products per partial sum: 4 p^2 < 2^64
+      uint64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const uint64_t a = A[i + g];
+        s0 += a * w0;
+        s1 += a * w1;
+        s2 += a * w2;
+        s3 += a * w3;
+        w3 = w2;
+        w2 = w1;
+        w1 = w0;
+        w0 = bb[-(i + g) - 1];
+      }
+      c0.add(s0);
+      c1.add(s1);
+      c2.add(s2);
+      c3.add(s3);
     }
-    uint64_t s = 0;
-    for (; i <= kk; ++i) s += (uint64_t)A[i] * Bv[kk - i];
-    acc.add(s);
-    C[kk] = reduce96(acc, q, r3);
+    C[kk0] = reduce96(c0, q, r3);
+    if (kk0 + 1 < D) C[kk0 + 1] = reduce96(c1, q, r3);
+    if (kk0 + 2 < D) C[kk0 + 2] = reduce96(c2, q, r3);
+    if (kk0 + 3 < D) C[kk0 + 3] = reduce96(c3, q, r3);
   }
   __syncthreads();
   // T_b and Q_b: from the tables when the caller has them, else one wave per
-  // block (lanes hold coefficients 0..KB)
+  // block (lanes hold coefficients 0..KB); meanwhile the Horner buffers are cleared
+  for (int i = threadIdx.x; i < 2 * D + 144; i += blockDim.x) lds[i] = 0u;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
@@ -1297,9 +1327,11 @@ __device__ void dev_interp(const JobDev& J, int k, TablesDev tab, uint32_t* lds,
     if (lane <= KB) TQ[b * (2 * KB + 1) + KB + lane] = Q;
   }
   __syncthreads();
-  // Horner over blocks: P <- P Q_b + T_b
-  uint32_t* P0 = A;
-  uint32_t* P1 = Bv;
+  // Horner over blocks: P <- P Q_b + T_b.  The buffers are zero outside the
+  // coefficients written so far (degrees only grow), so the windows need no
+  // bounds: indices run from -36 to the degree + 35.
+  uint32_t* P0 = lds + 36;
+  uint32_t* P1 = lds + (D + 72) + 36;
   int degP = min(KB, D - (nb - 1) * KB) - 1;
   for (int j = threadIdx.x; j <= degP; j += blockDim.x) P0[j] = TQ[(nb - 1) * (2 * KB + 1) + j];
   __syncthreads();
@@ -1307,21 +1339,49 @@ __device__ void dev_interp(const JobDev& J, int k, TablesDev tab, uint32_t* lds,
     const uint32_t* T = TQ + b * (2 * KB + 1);
     const uint32_t* Qb = T + KB;
     const int degN = degP + KB;
-    for (int j = threadIdx.x; j <= degN; j += blockDim.x) {
-      const int t0 = max(0, j - degP), t1 = min(KB, j);
-      Acc96 acc;
-      int t = t0;
-      for (; t + 4 <= t1 + 1; t += 4) {
-        uint64_t s = (uint64_t)P0[j - t] * Qb[t];
-        s += (uint64_t)P0[j - t - 1] * Qb[t + 1];
-        s += (uint64_t)P0[j - t - 2] * Qb[t + 2];
-        s += (uint64_t)P0[j - t - 3] * Qb[t + 3];
-        acc.add(s);
+    uint32_t qv[KB + 1];
+#pragma unroll
+    for (int t = 0; t <= KB; ++t) qv[t] = Qb[t];
+    for (int j0 = 4 * threadIdx.x; j0 <= degN; j0 += 4 * blockDim.x) {
+      // outputs j0 + u = sum_t q_t P[j0 + u - t] (+ T[j0 + u] below KB);
+      // the window holds P[j0 + u - t]
+      const uint32_t* pp = P0 + j0;
+      uint64_t w0 = pp[0], w1 = pp[1], w2 = pp[2], w3 = pp[3];
+      Acc96 c0, c1, c2, c3;
+      // eight products per partial sum: 8 p^2 < 2^64 (p < 2^32 / 3)
+#pragma unroll
+      for (int t0 = 0; t0 <= KB; t0 += 8) {
+        uint64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+          const int t = t0 + g;
+          if (t <= KB) {
+            const uint64_t qt = qv[t];
+            s0 += qt * w0;
+            s1 += qt * w1;
+            s2 += qt * w2;
+            s3 += qt * w3;
+            w3 = w2;
+            w2 = w1;
+            w1 = w0;
+            w0 = pp[-t - 1];
+          }
+        }
+        c0.add(s0);
+        c1.add(s1);
+        c2.add(s2);
+        c3.add(s3);
       }
-      uint64_t s = j < KB ? (uint64_t)T[j] : 0u;
-      for (; t <= t1; ++t) s += (uint64_t)P0[j - t] * Qb[t];
-      acc.add(s);
-      P1[j] = reduce96(acc, q, r3);
+      if (j0 < KB) {
+        c0.add(T[j0]);
+        c1.add(T[j0 + 1]);
+        c2.add(T[j0 + 2]);
+        c3.add(T[j0 + 3]);
+      }
+      P1[j0] = reduce96(c0, q, r3);
+      if (j0 + 1 <= degN) P1[j0 + 1] = reduce96(c1, q, r3);
+      if (j0 + 2 <= degN) P1[j0 + 2] = reduce96(c2, q, r3);
+      if (j0 + 3 <= degN) P1[j0 + 3] = reduce96(c3, q, r3);
     }
     __syncthreads();
     uint32_t* tmp = P0; P0 = P1; P1 = tmp;
@@ -1356,7 +1416,7 @@ __global__ __launch_bounds__(64) void k_interp_tables(int nb, TablesDev tab, uin
   if (lane <= KB) Q[((size_t)k * nb + b) * (KB + 1) + lane] = from_mont(N, q);
 }
 
-size_t interp_lds_words(int D) { return (size_t)3 * D + (size_t)((D + KB - 1) / KB) * (2 * KB + 1); }
+size_t interp_lds_words(int D) { return (size_t)3 * D + 144 + (size_t)((D + KB - 1) / KB) * (2 * KB + 1); }
 
 // (d) interpolation of a batch whose jobs share D and P, on the int8 matrix
 // cores.  With nodes 0..D-1 the coefficients are C = V^{-1} Y (one column of
