@@ -467,16 +467,16 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   // per-kernel first block of each job (prefix sums of the per-job block counts)
   // eval_elim runs one launch per size bucket (LDS per block sized for the
   // bucket, so small jobs are not held to the occupancy of the largest)
-  // jobs whose f array fits in registers (eval_elim_rg_capacity 24 or 32) run
-  // in two more launches
+  // jobs whose f array fits in registers (eval_elim_rg_capacity 24, 32 or 64)
+  // run in three more launches
   // jobs on the Schur kernel (wave per instance; 1 or 2 generator rows per
   // lane) in two more
   enum {
-    K_RED, K_IP, K_MRC, K_SUM, K_CAR, K_CRT, K_EE0, NBUCKET = 5, K_RG0 = K_EE0 + NBUCKET, NRG = 2,
+    K_RED, K_IP, K_MRC, K_SUM, K_CAR, K_CRT, K_EE0, NBUCKET = 5, K_RG0 = K_EE0 + NBUCKET, NRG = 3,
     K_SC0 = K_RG0 + NRG, NSC = 2, NK = K_SC0 + NSC
   };
   const int bucket_words[NBUCKET] = {24, 40, 64, 96, 1 << 30};
-  const int rg_cap[NRG] = {24, 32};
+  const int rg_cap[NRG] = {24, 32, 64};
   int bw[NBUCKET] = {0}, br_[NBUCKET] = {0};
   int rdeg[NRG] = {0}, rw[NRG] = {0};
   int sw[NSC] = {0};
@@ -527,7 +527,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
       starts[K_SC0 + nr - 1][i + 1] = p.P * p.D;
       sw[nr - 1] = std::max(sw[nr - 1], p.m + p.n + 2);
     } else if (rc) {
-      const int r = rc == rg_cap[0] ? 0 : 1;
+      const int r = rc == rg_cap[0] ? 0 : rc == rg_cap[1] ? 1 : 2;
       starts[K_RG0 + r][i + 1] = p.P * ((p.D + 63) / 64);
       rdeg[r] = std::max(rdeg[r], std::max(p.m, p.n));
       rw[r] = std::max(rw[r], p.m + p.n + 2);

@@ -850,6 +850,22 @@ __device__ __forceinline__ bool dev_eval_elim_rg(const JobDev& J, int lb, Tables
     as = bs;
     bs -= 1;
   }
+  if constexpr (C > 32) {
+    // steps above the unrolled chain's reach (B > 30): the fused step with
+    // wave-uniform guards (a normal step: d = 0 and a b even, so only pfx
+    // and den change)
+    while (bs > 30) {
+      bool short_rem;
+      const uint32_t lb = areg ? rg_step<C, true>(X, L, as, bs, &short_rem, q)
+                               : rg_step<C, false>(X, L, as, bs, &short_rem, q);
+      if (short_rem) return false;
+      pfx = mmul(pfx, mmul(lb, lb, q), q);
+      den = mmul(den, pfx, q);
+      areg = !areg;
+      as = bs;
+      bs -= 1;
+    }
+  }
   uint32_t last;
   if (bs == 0) {
     // the constant remainder is in the array that does not hold A
@@ -895,6 +911,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RG32_WAVES, 
     const JobDev* jobs, const int* starts, int nj, TablesDev tab, int* fb_count, int* fb_queue) {
   extern __shared__ __align__(16) uint32_t lds[];
   eval_elim_rg_block<32>(jobs, starts, nj, tab, fb_count, fb_queue, lds);
+}
+
+// C = 64 (jobs with 32 <= max(m, n) < 64): the steps above degree 30 run the
+// guarded fused step in a loop, the rest the unrolled chain.  Its LDS (65
+// words per lane) allows 9 blocks per CU, against 4 for the LDS kernel at
+// m = n = 63.
+#ifndef RG64_WAVES
+#define RG64_WAVES 2
+#endif
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RG64_WAVES, 8))) void k_eval_elim_rg64(
+    const JobDev* jobs, const int* starts, int nj, TablesDev tab, int* fb_count, int* fb_queue) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  eval_elim_rg_block<64>(jobs, starts, nj, tab, fb_count, fb_queue, lds);
 }
 
 // The queued blocks of k_eval_elim_rg, recomputed with the general kernel.
@@ -2546,7 +2575,7 @@ void launch_eval_elim(const JobDev* jobs, const int* starts, int nj, int nblocks
 int eval_elim_rg_capacity(int m, int n) {
   if (m < 1 || n < 1) return 0;
   const int d = std::max(m, n);
-  return d < 24 ? 24 : d < 32 ? 32 : 0;
+  return d < 24 ? 24 : d < 32 ? 32 : d < 64 ? 64 : 0;
 }
 
 void launch_eval_elim_rg(int C, const JobDev* jobs, const int* starts, int nj, int nblocks, int max_deg,
@@ -2554,8 +2583,10 @@ void launch_eval_elim_rg(int C, const JobDev* jobs, const int* starts, int nj, i
   const size_t lds = (size_t)(max_deg + 1) * 64 * sizeof(uint32_t);
   if (C == 24)
     hipLaunchKernelGGL(k_eval_elim_rg24, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, tab, fb_count, fb_queue);
-  else
+  else if (C == 32)
     hipLaunchKernelGGL(k_eval_elim_rg32, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, tab, fb_count, fb_queue);
+  else
+    hipLaunchKernelGGL(k_eval_elim_rg64, dim3(nblocks), dim3(64), lds, s, jobs, starts, nj, tab, fb_count, fb_queue);
   hipLaunchKernelGGL(k_eval_elim_fb, dim3(std::min(nblocks, 256)), dim3(64), eval_elim_lds_bytes(max_words, 0), s,
                      jobs, starts, nj, tab, fb_count, fb_queue);
 }

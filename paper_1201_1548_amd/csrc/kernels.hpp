@@ -41,9 +41,9 @@ size_t eval_elim_lds_bytes(int words, int res);
 void launch_eval_elim(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_words, int max_res,
                       TablesDev tab, hipStream_t s);
 // Evaluation + elimination with f's coefficient array in registers: the
-// register capacity C (24 or 32) for a job of degrees m, n in the eliminated
-// variable, or 0 when the job needs the LDS kernel (min(m, n) = 0 or
-// max(m, n) >= 32).  launch_eval_elim_rg runs the blocks of jobs with that
+// register capacity C (24, 32 or 64) for a job of degrees m, n in the
+// eliminated variable, or 0 when the job needs the LDS kernel (min(m, n) = 0
+// or max(m, n) >= 64).  launch_eval_elim_rg runs the blocks of jobs with that
 // capacity (max_deg = max over jobs of max(m, n), max_words of m + n + 2),
 // then recomputes with launch_eval_elim's kernel the blocks that leave the
 // uniform normal case.  fb_count: one device int, zero before the launch;
