@@ -142,11 +142,8 @@ struct SeqHash {
                   "hash scalars and pointers only");
     bytes(&v, sizeof v);
   }
-  void one(const FusedPlan& F) {
-    one(F.jobs), one(F.nj), one(F.head), one(F.ctr), one(F.ctr_off), one(F.err), one(F.stage_ld), one(F.mrc_lane);
-    for (int k = 0; k < 6; ++k) one(F.st[k]);
-    for (int k = 0; k < 7; ++k) one(F.base[k]);
-  }
+  // a plain struct of pointers and counts, value-initialised (zero padding)
+  void one(const FusedPlan& F) { bytes(&F, sizeof F); }
   template <class... A>
   void add(const A&... a) {
     (one(a), ...);
@@ -560,12 +557,11 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     if (!w[i].status && w[i].active) maxLcap = std::max(maxLcap, w[i].Lout);
   for (auto& v : starts)
     for (int i = 0; i < nj; ++i) v[i + 1] += v[i];
-  // persistent fused launch: per-stage task starts, counter offsets, counters
   const bool fused = P->fused = sched == BIRES_SCHEDULE_FUSED;
   if (!fused && !debug) P->schur_instances = (long long)starts[K_SC0][nj] + starts[K_SC0 + 1][nj];
-  // staged schedule: explicit CRT straight to limbs when the prime counts allow
+  // explicit CRT straight to limbs when the prime counts allow
   std::vector<std::pair<const uint32_t*, int>> crt(nj, {nullptr, 0});
-  bool use_crt = !debug && !fused && crt_ok(maxP);
+  bool use_crt = !debug && crt_ok(maxP);
   int lastP = -1, lastLM = 0;
   const uint32_t* lastd = nullptr;
   for (int i = 0; i < nj && use_crt; ++i) {
@@ -578,12 +574,14 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     if (!lastd) use_crt = false;
     crt[i] = {lastd, lastLM};
   }
-  if (use_crt && crt_lds_bytes(maxLcap, maxP) > cx->lds_per_block) use_crt = false;
-  // staged schedule: interpolation on the matrix cores when at least 32 jobs
-  // share D and P (all active jobs of the batch)
+  // (the fused launch's CRT blocks have 32 rows)
+  if (use_crt && (fused ? crt_lds_bytes_rows(maxLcap, maxP, 32) : crt_lds_bytes(maxLcap, maxP)) > cx->lds_per_block)
+    use_crt = false;
+  // interpolation on the matrix cores when at least 32 jobs share D and P
+  // (all active jobs of the batch)
   std::vector<int> group;
   int gD = 0, gP = 0;
-  for (int i = 0; i < nj && !debug && !fused && !noalloc; ++i) {
+  for (int i = 0; i < nj && !debug && !noalloc; ++i) {
     if (w[i].status || !w[i].active) continue;
     if (group.empty()) {
       gD = w[i].pl.D;
@@ -600,13 +598,46 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   // the per-(job, prime) interpolation kernel reads its block tables
   const uint32_t *itW = nullptr, *itQ = nullptr;
   int itNB = 0;
-  if (group.empty() && !fused && !debug && !noalloc &&
+  if (group.empty() && !debug && !noalloc &&
       !interp_tables_device(cx, interp_table_blocks(maxD), maxP, st, &itW, &itQ, &itNB)) {
     itW = itQ = nullptr;
     itNB = 0;
   }
   const int gDp = (gD + 31) & ~31, gNp = ((int)group.size() + 31) & ~31;
   const size_t o_yp = group.empty() ? 0 : ws.take((size_t)4 * gNp * gDp * gP);
+  // persistent fused launch: the evaluation's block lists (register Euclid at
+  // the batch's capacity fC, LDS kernel), the CRT's blocks of 32 rows
+  int fC = 0, fKS = 6, f_rgdeg = 0, f_rgw = 0, f_eew = 0;
+  std::vector<int> fst_rg, fst_ee, fst_crt;
+  if (fused) {
+    fst_rg.assign(nj + 1, 0);
+    fst_ee.assign(nj + 1, 0);
+    fst_crt.assign(nj + 1, 0);
+    auto cap = [&](const Plan& p) {
+      return cx->eval_mode == BIRES_EVAL_AUTO ? fused_capacity(eval_elim_rg_capacity(p.m, p.n)) : 0;
+    };
+    for (int i = 0; i < nj; ++i)
+      if (!w[i].status && w[i].active) fC = std::max(fC, cap(w[i].pl));
+    for (int i = 0; i < nj; ++i) {
+      const Work& x = w[i];
+      if (x.status || !x.active) continue;
+      const Plan& p = x.pl;
+      const int nb = p.P * ((p.D + 63) / 64);
+      if (cap(p)) {
+        fst_rg[i + 1] = nb;
+        f_rgdeg = std::max(f_rgdeg, std::max(p.m, p.n));
+        f_rgw = std::max(f_rgw, p.m + p.n + 2);
+      } else {
+        fst_ee[i + 1] = nb;
+        f_eew = std::max(f_eew, p.m + p.n + 2);
+      }
+      fst_crt[i + 1] = (std::min(p.D, x.degcap + 1) + 31) / 32;
+    }
+    for (std::vector<int>* v : {&fst_rg, &fst_ee, &fst_crt})
+      for (int i = 0; i < nj; ++i) (*v)[i + 1] += (*v)[i];
+    fKS = fused_crt_steps(maxP);
+  }
+  const size_t o_ffbq = ws.take(sizeof(int) * (fused ? (size_t)fst_rg[nj] : 0));
   size_t o_fbq[NRG];  // queues of blocks recomputed by the LDS kernel
   for (int r = 0; r < NRG; ++r) o_fbq[r] = ws.take(sizeof(int) * (size_t)starts[K_RG0 + r][nj]);
   // metadata uploaded with one copy: descriptors, flags, row degrees, block maps
@@ -622,30 +653,11 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   const size_t o_maps = ws.take(sizeof(int) * (size_t)NK * (nj + 1));
   // the group's coefs pointers
   const size_t o_gco = ws.take(sizeof(uint32_t*) * group.size());
-  enum { F_STAGES = 6 };
-  std::vector<int> fst[F_STAGES];
-  std::vector<int> ctr_off(nj + 1, 0);
-  if (fused) {
-    for (auto& v : fst) v.assign(nj + 1, 0);
-    for (int i = 0; i < nj; ++i) {
-      const Work& x = w[i];
-      if (x.status || !x.active) continue;
-      const Plan& p = x.pl;
-      fst[0][i + 1] = (x.Tf + 63) / 64 + (x.Tg + 63) / 64;
-      fst[1][i + 1] = p.P * ((p.D + 63) / 64);
-      fst[2][i + 1] = p.P;
-      fst[3][i + 1] = mrc_lane ? (p.D + 63) / 64 : p.D;
-      fst[4][i + 1] = (p.D * x.Lacc + 63) / 64;
-      fst[5][i + 1] = (x.degcap + 1 + 63) / 64;
-      ctr_off[i + 1] = 4 + p.P;
-    }
-    for (auto& v : fst)
-      for (int i = 0; i < nj; ++i) v[i + 1] += v[i];
-    for (int i = 0; i < nj; ++i) ctr_off[i + 1] += ctr_off[i];
-  }
-  const size_t o_fst = ws.take(sizeof(int) * F_STAGES * (nj + 1));
-  const size_t o_ctroff = ws.take(sizeof(int) * (nj + 1));
-  const size_t o_ctr = ws.take(sizeof(int) * ((size_t)ctr_off[nj] + 2));  // counters, head, err
+  // the fused launch's block maps (register Euclid, LDS kernel, CRT) and its
+  // claim and completion counters (uploaded as zero)
+  enum { F_CTR = 6 * FUSED_STAGE_INTS };
+  const size_t o_fst = ws.take(sizeof(int) * (fused ? 3 * (size_t)(nj + 1) : 0));
+  const size_t o_fctr = ws.take(sizeof(int) * (fused ? F_CTR : 0));
   const size_t meta_end = ws.bytes;
   uint8_t* D0 = nullptr;
   uint8_t* H0 = nullptr;  // H0 + offset addresses the metadata image
@@ -737,10 +749,10 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     }
   }
   if (fused) {
-    for (int k = 0; k < F_STAGES; ++k)
-      std::memcpy(H0 + o_fst + sizeof(int) * k * (nj + 1), fst[k].data(), sizeof(int) * (nj + 1));
-    std::memcpy(H0 + o_ctroff, ctr_off.data(), sizeof(int) * (nj + 1));
-    std::memset(H0 + o_ctr, 0, sizeof(int) * ((size_t)ctr_off[nj] + 2));
+    std::memcpy(H0 + o_fst, fst_rg.data(), sizeof(int) * (nj + 1));
+    std::memcpy(H0 + o_fst + sizeof(int) * (nj + 1), fst_ee.data(), sizeof(int) * (nj + 1));
+    std::memcpy(H0 + o_fst + sizeof(int) * 2 * (nj + 1), fst_crt.data(), sizeof(int) * (nj + 1));
+    std::memset(H0 + o_fctr, 0, sizeof(int) * F_CTR);
   }
   auto nb_of = [&](int kk) { return starts[kk][nj]; };
   hc.mark(3);
@@ -759,7 +771,6 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   const JobDev* d_jobs = (const JobDev*)(D0 + o_jobs);
   int nb_ee = 0;
   for (int bk = 0; bk < NBUCKET + NRG + NSC; ++bk) nb_ee += nb_of(K_EE0 + bk);
-  int* d_ctr = (int*)(D0 + o_ctr);
 
   // The device sequence of the call: metadata upload, kernels, result copies.
   // seq(run, sig) hashes every argument of every call into sig and, with
@@ -769,29 +780,93 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
   size_t f_lds = 0;
   int f_blocks = 0;
   if (fused) {
+    const int* fm = (const int*)(D0 + o_fst);
     F.jobs = d_jobs;
     F.nj = nj;
-    int total = 0;
-    for (int k = 0; k < F_STAGES; ++k) {
-      F.st[k] = (const int*)(D0 + o_fst + sizeof(int) * k * (nj + 1));
-      F.base[k] = total;
-      total += fst[k][nj];
+    F.st_rg = fm;
+    F.st_ee = fm + (nj + 1);
+    F.n_rg = fst_rg[nj];
+    F.n_ee = fst_ee[nj];
+    F.fb_count = (int*)(D0 + o_fbc);
+    F.fb_queue = (int*)(D0 + o_ffbq);
+    size_t block_lds;
+    int demand;  // blocks that the largest stage can use
+    if (!group.empty()) {
+      F.im = 1;
+      F.n_im = (gDp / 32) * (gNp / 16) * gP;  // wave tiles of 32 coefficients x 16 jobs
+      F.gco = (uint32_t* const*)(D0 + o_gco);
+      F.gN = (int)group.size();
+      F.gNp = gNp;
+      F.gD = gD;
+      F.gDp = gDp;
+      F.Ap = vinv;
+      F.Yp = (const int8_t*)(D0 + o_yp);
+      block_lds = 0;
+      demand = (F.n_im + 3) / 4;
+    } else {
+      F.st_ip = st_of(K_IP);
+      F.n_ip = nb_of(K_IP);
+      F.itW = itW;
+      F.itQ = itQ;
+      F.itNB = itNB;
+      block_lds = interp_lds_words(maxD) * 4;
+      demand = F.n_ip;
     }
-    F.base[F_STAGES] = total;
-    F.ctr = d_ctr;
-    F.ctr_off = (const int*)(D0 + o_ctroff);
-    F.head = d_ctr + ctr_off[nj];
-    F.err = d_ctr + ctr_off[nj] + 1;
-    F.stage_ld = maxLcap <= 128 ? maxLcap + 1 : 0;
-    F.mrc_lane = mrc_lane ? 1 : 0;
-    f_lds = interp_lds_words(maxD) * 4;
-    for (int i = 0; i < nj; ++i)
-      if (!w[i].status && w[i].active)
-        f_lds = std::max(f_lds, eval_elim_lds_bytes(w[i].pl.m + w[i].pl.n + 2, w[i].Tf + w[i].Tg));
-    f_lds = std::max(f_lds, (size_t)(F.mrc_lane ? maxP * 64 : 2 * maxP) * 4);
-    f_lds = std::max(f_lds, (size_t)64 * F.stage_ld * 4);
-    f_blocks = total ? fused_blocks(f_lds, total) : 0;
-    if (total && f_blocks <= 0) return BIRES_EDEVICE;
+    // LDS words of a wave's slice per wave stage (multiples of 4)
+    int lw[4] = {std::max(f_rgdeg + 1, f_eew) * 64, f_rgw * 64, 0, 0};
+    if (use_crt) {
+      F.crt = 1;
+      F.st_crt = fm + 2 * (nj + 1);
+      F.n_crt = fst_crt[nj];
+      F.sld = crt_row_stride(maxLcap);
+      F.cps = crt_const_stride(maxP);
+      lw[2] = (int)(crt_lds_bytes_rows(maxLcap, maxP, 32) / 4);
+    } else {
+      F.st_mrc = st_of(K_MRC);
+      F.n_mrc = nb_of(K_MRC);
+      F.mrc_lane = mrc_lane ? 1 : 0;
+      F.st_sum = st_of(K_SUM);
+      F.n_sum = nb_of(K_SUM);
+      F.st_car = st_of(K_CAR);
+      F.n_car = nb_of(K_CAR);
+      F.stage_ld = maxLcap <= 128 ? maxLcap + 1 : 0;
+      lw[2] = mrc_lane ? maxP * 64 : 2 * maxP;
+      lw[3] = 64 * F.stage_ld;
+      demand = std::max(demand, F.n_sum);
+    }
+    // the LDS per block that the register budget's occupancy leaves (blocks
+    // per CU without LDS); each wave stage as many waves of a block as their
+    // slices fit in it, at least one
+    const int occ = fused_blocks_per_cu(fC, fKS, 0);
+    if (occ <= 0) return BIRES_EDEVICE;
+    const size_t target = (cx->lds_per_cu / occ) & ~(size_t)15;
+    const int wave_tasks[4] = {F.n_rg + F.n_ee, F.n_rg, F.crt ? F.n_crt : F.n_mrc, F.n_car};
+    f_lds = block_lds;
+    for (int k = 0; k < 4; ++k) {
+      F.lw[k] = (lw[k] + 3) & ~3;
+      const size_t b = (size_t)F.lw[k] * 4;
+      F.wv[k] = b ? (int)std::max<size_t>(1, std::min<size_t>(4, target / b)) : 4;
+      f_lds = std::max(f_lds, F.wv[k] * b);
+      demand = std::max(demand, (wave_tasks[k] + F.wv[k] - 1) / F.wv[k]);
+    }
+    if (f_lds > cx->lds_per_block) return BIRES_ETOOBIG;
+    F.ctr = (int*)(D0 + o_fctr);
+    F.err = (int*)(D0 + o_flags) + 2 * nj;
+    const int per_cu = fused_blocks_per_cu(fC, fKS, f_lds);
+    if (per_cu <= 0) return BIRES_EDEVICE;
+    // as many blocks as the device holds at once (blocks that start late find
+    // the tasks taken)
+    f_blocks = std::min(per_cu * cx->compute_units, std::max(1, demand));
+    // tasks per claim: about eight claims per wave (or block) and stage
+    auto per_claim = [&](long long tasks, long long takers) {
+      return (int)std::max<long long>(1, std::min<long long>(32, tasks / (8 * takers)));
+    };
+    F.kc[0] = per_claim(F.n_rg + F.n_ee, (long long)f_blocks * F.wv[0]);
+    F.kc[1] = 1;
+    F.kc[2] = F.im ? per_claim(F.n_im, 4LL * f_blocks) : per_claim(F.n_ip, f_blocks);
+    F.kc[3] = per_claim(F.crt ? F.n_crt : F.n_mrc, (long long)f_blocks * F.wv[2]);
+    F.kc[4] = per_claim(F.n_sum, f_blocks);
+    F.kc[5] = per_claim(F.n_car, (long long)f_blocks * F.wv[3]);
   }
   const bool use_graph = cx->graphs && !debug && !noalloc;
   const bool timing = P->timing = cx->timing && nb_ee > 0 && !use_graph;
@@ -830,9 +905,13 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
         launch_stats_check(spec_got, d_image, (long long)scan_words, (int*)(D0 + o_flags) + 2 * nj + 1, st);
     }
     if (fused) {
-      sg.add(F, f_lds, f_blocks);
+      // the reduction in a launch of its own: the evaluation reads its
+      // residues through the scalar cache
+      sg.add(nb_of(K_RED), maxP);
+      if (run && nb_of(K_RED)) launch_reduce(d_jobs, st_of(K_RED), nj, nb_of(K_RED), maxP, cx->tab, st);
+      sg.add(F, fC, fKS, f_lds, f_blocks);
       if (run && timing) DEV(hipEventRecord(ev0, st));
-      if (run && F.base[F_STAGES]) launch_fused(F, f_lds, f_blocks, cx->tab, st);
+      if (run) launch_fused(fC, fKS, F, f_lds, f_blocks, cx->tab, st);
       if (run && timing) DEV(hipEventRecord(ev1, st));
     } else {
       sg.add(nb_of(K_RED), maxP);
@@ -882,11 +961,6 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     sg.add(nj, o_flags, (const void*)h_flags);
     if (run && nj)
       DEV(hipMemcpyAsync(h_flags, D0 + o_flags, sizeof(int32_t) * (2 * nj + 3), hipMemcpyDeviceToHost, st));
-    if (fused) {
-      sg.add(ctr_off[nj]);
-      if (run)
-        DEV(hipMemcpyAsync(h_flags + 2 * nj, d_ctr + ctr_off[nj] + 1, sizeof(int), hipMemcpyDeviceToHost, st));
-    }
     for (int i = 0; i < nj; ++i) {
       const Work& x = w[i];
       if (x.status || !x.active || mem != BIRES_MEM_HOST) continue;

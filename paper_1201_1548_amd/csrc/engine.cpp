@@ -99,6 +99,8 @@ static int init_context(Context& cx) {
   if (std::string(prop.gcnArchName).find("gfx950") == std::string::npos) return BIRES_EDEVICE;
   cx.device = dev;
   cx.lds_per_block = prop.sharedMemPerBlock;
+  cx.lds_per_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : prop.sharedMemPerBlock;
+  cx.compute_units = prop.multiProcessorCount;
   HIP_OK(hipStreamCreateWithFlags(&cx.stream, hipStreamNonBlocking));
   const HostTables& t = host_tables();
   ModP* primes = nullptr;

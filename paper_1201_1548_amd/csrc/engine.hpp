@@ -79,6 +79,8 @@ struct Context {
   Pool dev{false};
   Pool host{true};
   size_t lds_per_block = 65536;
+  size_t lds_per_cu = 65536;
+  int compute_units = 1;
   bool timing = false;
   int schedule = BIRES_SCHEDULE_AUTO;    // BIRES_SCHEDULE_*
   int forced_schedule = -1;              // set by the autotuner while it measures

@@ -57,21 +57,59 @@ struct GcdDev {
   int32_t* gdeg;          // [P] degree of the gcd mod p_k; -2: p_k divides lc(a) lc(b); -3: failed check
 };
 
-// The persistent fused launch: one queue of tasks, stage-major (reduce,
-// eval+elim, interp, mrc, limbs_sum, limbs_carry), jobs in order within a
-// stage.  Per job, ctr holds 4 + P counters at ctr_off[job]: reduce tasks
-// done, eval tasks done per prime (P), interp done, mrc done, limbs_sum done.
+// The persistent fused launch (k_fused): every stage after the reduction (a
+// launch of its own before it) for the whole batch in one launch of blocks of
+// four waves, one stage after the other; the tasks of a stage are claimed in
+// chunks from counters and a stage ends when all its tasks are done.  Wave
+// tasks run on one wave and an LDS slice of its own: evaluation +
+// elimination, the recomputation of the register-Euclid blocks that left the
+// uniform case, the explicit CRT or the Garner digits, the limb carries.
+// Block tasks run on the whole block: interpolation and the limb sums.
+// Per-job first task of each stage as in the staged kernels.
+constexpr int FUSED_STAGE_INTS = 512;  // counters of one stage of the fused launch
+
 struct FusedPlan {
   const JobDev* jobs;
   int32_t nj;
-  const int* st[6];      // per-stage first task of each job (nj + 1 entries each)
-  int32_t base[7];       // first queue index of each stage; base[6] = number of tasks
-  int* head;             // next task to take
-  int* ctr;              // completion counters
-  const int* ctr_off;    // [nj]
-  int* err;              // bit 1: a dependency wait timed out
-  int32_t stage_ld;      // limb-assembly staging row (0: direct writes)
-  int32_t mrc_lane;      // 1: lane-per-coefficient Garner
+  // evaluation + elimination: register Euclid (st_rg, n_rg blocks of 64
+  // points), then the LDS kernel (st_ee, n_ee)
+  const int* st_rg;
+  const int* st_ee;
+  int32_t n_rg, n_ee;
+  int* fb_count;  // register-Euclid blocks queued for the LDS kernel (zero before the launch)
+  int* fb_queue;  // [n_rg]
+  // interpolation: on the matrix cores for a group sharing D and P (im = 1:
+  // n_im blocks of 64 x 64), else per (job, prime) (st_ip, n_ip)
+  int32_t im, n_im;
+  uint32_t* const* gco;
+  int32_t gN, gNp, gD, gDp;
+  const int8_t* Ap;
+  const int8_t* Yp;
+  const int* st_ip;
+  int32_t n_ip;
+  const uint32_t* itW;  // Newton-to-monomial block tables (null: computed in place)
+  const uint32_t* itQ;
+  int32_t itNB;
+  // reconstruction: explicit CRT (crt = 1: blocks of 32 rows) or Garner
+  // digits, limb sums and limb carries
+  int32_t crt;
+  const int* st_crt;
+  int32_t n_crt, sld, cps;
+  const int* st_mrc;
+  int32_t n_mrc, mrc_lane;
+  const int* st_sum;
+  int32_t n_sum;
+  const int* st_car;
+  int32_t n_car, stage_ld;
+  // per wave stage (0 evaluation, 1 recomputation, 2 CRT or digits, 3
+  // carries): the waves of a block that take its tasks, the words of a
+  // wave's LDS slice
+  int32_t wv[4], lw[4];
+  // tasks per claim of stages 0 evaluation, 1 (one), 2 interpolation, 3 CRT
+  // or digits, 4 limb sums, 5 carries
+  int32_t kc[6];
+  int* ctr;  // [6][FUSED_STAGE_INTS]: per stage claim heads and finished-task counts (zero before the launch)
+  int* err;  // bit 1: a wait timed out
 };
 
 // The degree chain of the N^- / N^+ test over one prime (k_fiber_chain).

@@ -59,6 +59,26 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const
   return (const __attribute__((address_space(1))) T*)p;
 }
 
+// Lane of the calling thread in its wave.  The device functions that one wave
+// runs index with it, so that a block of several waves (the persistent
+// launch) can give each wave a task of its own.
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+// Synchronisation of the threads that run a device function together: the
+// whole block, or (WAVE) one wave of it.  A wave's LDS accesses complete in
+// order, so the wave needs no barrier; the fences keep the compiler from
+// moving memory accesses across the point.
+template <bool WAVE>
+__device__ __forceinline__ void group_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // planning statistics: for each row j of a rectangle, the x-degree, the
 // largest bit length of |c|, the number of non-zero coefficients and an upper
@@ -589,9 +609,9 @@ __device__ __forceinline__ void dev_eval_elim(const JobDev& J, int lb, TablesDev
   const int k = lb / nbpp;
   const int a0 = (lb - k * nbpp) * W;
   const int m = J.m, n = J.n;
-  uint32_t* A = lds + threadIdx.x;
+  uint32_t* A = lds + lane_id();
   uint32_t* B = A + (m + 1) * W;
-  const int pt = a0 + (int)threadIdx.x;
+  const int pt = a0 + lane_id();
   if (pt >= J.D) return;
   const ModP q = tab.primes[k];
   eval_pair<W, SC>(J, k, pt, q, A, B);
@@ -801,8 +821,8 @@ __device__ __forceinline__ bool dev_eval_elim_rg(const JobDev& J, int lb, Tables
   cu32* Rg = (cu32*)(J.res_g + (size_t)k * J.Tg);
   ci32* RDf = (ci32*)J.rowdeg_f;
   ci32* RDg = (ci32*)J.rowdeg_g;
-  uint32_t* L = lds + threadIdx.x;
-  const int pt = a0 + (int)threadIdx.x;
+  uint32_t* L = lds + lane_id();
+  const int pt = a0 + lane_id();
   if (pt >= J.D) return true;
   const ModP q = tab.primes[k];
   const uint32_t aM = to_mont((uint32_t)pt, q);
@@ -1555,12 +1575,100 @@ __device__ __forceinline__ void im_fetch(const int8_t* src, int8_t* dst) {
     asm volatile("" ::: "memory");                                                   \
   } while (0)
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_interp_mfma(
-    uint32_t* const* gco, int N, int Np, int D, int Dp, const int8_t* Ap, const int8_t* Yp, TablesDev tab) {
-  extern __shared__ __align__(16) int8_t im_lds[];
+// The products of weight classes u in [U0, U1) over every contraction step,
+// through a ring of STAGES stages (2 or 3).
+template <int U0, int U1, int STAGES>
+__device__ __forceinline__ void im_pass(const int8_t* src, size_t pstride, const int8_t* im_lds, int8_t* dst0, int ra,
+                                        int ry, int nsteps, im_v16i (&G)[U1 - U0]) {
+#pragma unroll
+  for (int st = 0; st < STAGES - 1; ++st) {
+    if (st < nsteps) {
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) im_fetch(src + pl * pstride + st * 1024, dst0 + st * IM_STAGE_BYTES + pl * 1024);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U1 - U0; ++u) G[u] = (im_v16i){0};
+  // the fetches of step s + STAGES - 1 into the stage that step s - 1 read:
+  // every wave passed this step's barrier after its reads of it completed
+  auto issue_fetch = [&](int s) {
+    const int sn = s + STAGES - 1;
+    if (sn < nsteps) {
+      int8_t* d = dst0 + (sn % STAGES) * IM_STAGE_BYTES;
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) im_fetch(src + pl * pstride + (size_t)sn * 1024, d + pl * 1024);
+    }
+  };
+  for (int s = 0; s < nsteps; ++s) {
+    // this wave's fetches of step s (and the loads before them) are done
+    // once at most those of the younger steps in flight remain
+    if constexpr (STAGES == 3) {
+      if (s + 1 < nsteps)
+        IM_WAIT_VM_BARRIER(4);
+      else
+        IM_WAIT_VM_BARRIER(0);
+    } else {
+      static_assert(STAGES == 2, "ring of two or three stages");
+      IM_WAIT_VM_BARRIER(0);
+    }
+    const int8_t* sb = im_lds + (s % STAGES) * IM_STAGE_BYTES;
+    // the Y digits this pass uses (t >= U0 - 3)
+    constexpr int T0 = U0 > 3 ? U0 - 3 : 0;
+    im_v4i yv[4];
+#pragma unroll
+    for (int i = T0; i < 4; ++i) yv[i] = *(const im_v4i*)(sb + ry + 1024 * i);
+    if constexpr (U1 - U0 == 7) {
+      im_v4i av[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = *(const im_v4i*)(sb + ra + 1024 * i);
+      issue_fetch(s);
+      // class by class, digit sd of A against digit u - sd of Y
+#pragma unroll
+      for (int u = U0; u < U1; ++u)
+#pragma unroll
+        for (int sd = (u > 3 ? u - 3 : 0); sd <= (u < 3 ? u : 3); ++sd)
+          G[u - U0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[sd], yv[u - sd], G[u - U0], 0, 0, 0);
+    } else {
+      issue_fetch(s);
+      // digit by digit of A (one A operand live at a time), against the Y
+      // digits that give a class of this pass
+#pragma unroll
+      for (int sd = 0; sd < 4; ++sd) {
+        if (sd + 3 < U0 || sd >= U1) continue;
+        const im_v4i a = *(const im_v4i*)(sb + ra + 1024 * sd);
+#pragma unroll
+        for (int td = 0; td < 4; ++td)
+          if (sd + td >= U0 && sd + td < U1)
+            G[sd + td - U0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, yv[td], G[sd + td - U0], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// sum_{u in [U0, U1)} G_u 256^u R^{-1} mod p for accumulator register r, in
+// [0, p): |G_u| <= 4 Dp 2^14 <= 2^28 and w_u < p < 2^31, so the sum lies
+// within 7 * 2^58.5 < 2^62 < p 2^32; adding p 2^32 (a multiple of p) makes it
+// non-negative and below 2 p 2^32, where redc leaves a value below 2p, hence
+// one more conditional subtraction.
+template <int U0, int U1>
+__device__ __forceinline__ uint32_t im_fold(const im_v16i (&G)[U1 - U0], int r, const uint32_t (&wu)[7],
+                                            const ModP& q) {
+  int64_t acc = (int64_t)q.p << 32;
+#pragma unroll
+  for (int u = U0; u < U1; ++u) acc += (int64_t)G[u - U0][r] * (int64_t)(int32_t)wu[u];
+  const uint32_t v = redc((uint64_t)acc, q.p, q.pinv);
+  return umin32(v, v - q.p);
+}
+
+// One 64 x 64 block of C (logical block lb) on the four waves of a block.
+// SPLIT: the seven classes in two passes over the steps (classes 0-3, then
+// 4-6), which holds 64 accumulator registers instead of 112 at the price of
+// fetching the operands twice.
+template <int STAGES, bool SPLIT>
+__device__ __forceinline__ void dev_interp_mfma(uint32_t* const* gco, int N, int Np, int D, int Dp, const int8_t* Ap,
+                                                const int8_t* Yp, TablesDev tab, int lb, int8_t* im_lds) {
   const int t = threadIdx.x, w = t >> 6, l = t & 63, r32 = l & 31, g = l >> 5;
   const int nit = Dp >> 5, nnt = Np >> 5, nbr = (nit + 1) >> 1, nbc = (nnt + 1) >> 1;
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int k = lb / (nbr * nbc), rem = lb - k * nbr * nbc;
   const int br = rem % nbr, bc = rem / nbr;
   const int it = 2 * br + (w & 1), nt = 2 * bc + (w >> 1);
@@ -1588,74 +1696,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   // group has P primes
   uint32_t* const cpp = l < 32 && live && n0 + l < N ? gco[n0 + l] : nullptr;
   const ModP q = tab.primes[k];  // likewise
+  uint32_t v[16];  // the tile's values: accumulator register r's entry
+  if constexpr (!SPLIT) {
+    im_v16i G[7];
+    im_pass<0, 7, STAGES>(src, pstride, im_lds, dst0, ra, ry, nsteps, G);
+    uint32_t wu[7];  // Montgomery forms of 256^u
+    wu[0] = q.one;
+    const uint32_t m256 = to_mont(256u, q);
 #pragma unroll
-  for (int st = 0; st < IM_STAGES - 1; ++st) {
-    if (st < nsteps) {
+    for (int u = 1; u < 7; ++u) wu[u] = mmul(wu[u - 1], m256, q);
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl) im_fetch(src + pl * pstride + st * 1024, dst0 + st * IM_STAGE_BYTES + pl * 1024);
+    for (int r = 0; r < 16; ++r) v[r] = im_fold<0, 7>(G, r, wu, q);
+  } else {
+    uint32_t wu[7];
+    {
+      im_v16i G[4];
+      im_pass<0, 4, STAGES>(src, pstride, im_lds, dst0, ra, ry, nsteps, G);
+      wu[0] = q.one;
+      const uint32_t m256 = to_mont(256u, q);
+#pragma unroll
+      for (int u = 1; u < 7; ++u) wu[u] = mmul(wu[u - 1], m256, q);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = im_fold<0, 4>(G, r, wu, q);
     }
-  }
-  im_v16i G0 = {0}, G1 = {0}, G2 = {0}, G3 = {0}, G4 = {0}, G5 = {0}, G6 = {0};
-  for (int s = 0; s < nsteps; ++s) {
-    // this wave's fetches of step s (and the loads before them) are done
-    // once at most those of step s + 1 remain
-    if (s + 1 < nsteps)
-      IM_WAIT_VM_BARRIER(4);
-    else
-      IM_WAIT_VM_BARRIER(0);
-    const int8_t* sb = im_lds + (s % IM_STAGES) * IM_STAGE_BYTES;
-    const im_v4i a0 = *(const im_v4i*)(sb + ra), a1 = *(const im_v4i*)(sb + ra + 1024),
-                 a2 = *(const im_v4i*)(sb + ra + 2048), a3 = *(const im_v4i*)(sb + ra + 3072);
-    const im_v4i y0 = *(const im_v4i*)(sb + ry), y1 = *(const im_v4i*)(sb + ry + 1024),
-                 y2 = *(const im_v4i*)(sb + ry + 2048), y3 = *(const im_v4i*)(sb + ry + 3072);
-    // the stage read at step s - 1 is free: every wave passed this barrier
-    // after its reads of it completed
-    const int sn = s + IM_STAGES - 1;
-    if (sn < nsteps) {
-      int8_t* d = dst0 + (sn % IM_STAGES) * IM_STAGE_BYTES;
+    // every wave's reads of the ring are done before the second pass refills it
+    __syncthreads();
+    im_v16i G[3];
+    im_pass<4, 7, STAGES>(src, pstride, im_lds, dst0, ra, ry, nsteps, G);
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl) im_fetch(src + pl * pstride + (size_t)sn * 1024, d + pl * 1024);
+    for (int r = 0; r < 16; ++r) {
+      const uint32_t sum = v[r] + im_fold<4, 7>(G, r, wu, q);  // < 2p < 2^32
+      v[r] = umin32(sum, sum - q.p);
     }
-    G0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, y0, G0, 0, 0, 0);
-    G1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, y1, G1, 0, 0, 0);
-    G1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, y0, G1, 0, 0, 0);
-    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, y2, G2, 0, 0, 0);
-    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, y1, G2, 0, 0, 0);
-    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, y0, G2, 0, 0, 0);
-    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, y3, G3, 0, 0, 0);
-    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, y2, G3, 0, 0, 0);
-    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, y1, G3, 0, 0, 0);
-    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, y0, G3, 0, 0, 0);
-    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, y3, G4, 0, 0, 0);
-    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, y2, G4, 0, 0, 0);
-    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, y1, G4, 0, 0, 0);
-    G5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, y3, G5, 0, 0, 0);
-    G5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, y2, G5, 0, 0, 0);
-    G6 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, y3, G6, 0, 0, 0);
   }
   // every wave's last reads are done before the ring is reused for the transposes
   __syncthreads();
   uint32_t(*tile)[33] = (uint32_t(*)[33])(im_lds + w * (32 * 33 * 4));
   uint32_t** colp = (uint32_t**)(im_lds + 4 * (32 * 33 * 4)) + 32 * w;
   if (l < 32) colp[l] = cpp ? cpp + (size_t)k * D : nullptr;
-  uint32_t wu[7];  // Montgomery forms of 256^u
-  wu[0] = q.one;
-  const uint32_t m256 = to_mont(256u, q);
 #pragma unroll
-  for (int u = 1; u < 7; ++u) wu[u] = mmul(wu[u - 1], m256, q);
-  // |G_u| <= 4 Dp 2^14 <= 2^28 and w_u < p < 2^31, so sum_u G_u w_u lies
-  // within 7 * 2^58.5 < 2^62 < p 2^32; adding p 2^32 (a multiple of p) makes
-  // it non-negative and below 2 p 2^32, where one Montgomery reduction
-  // leaves a value below 3p, hence one more conditional subtraction
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int32_t gv[7] = {G0[r], G1[r], G2[r], G3[r], G4[r], G5[r], G6[r]};
-    int64_t acc = (int64_t)q.p << 32;
-#pragma unroll
-    for (int u = 0; u < 7; ++u) acc += (int64_t)gv[u] * (int64_t)(int32_t)wu[u];
-    const uint32_t v = redc((uint64_t)acc, q.p, q.pinv);
-    tile[r32][8 * (r >> 2) + 4 * g + (r & 3)] = umin32(v, v - q.p);  // [column][row]
-  }
+  for (int r = 0; r < 16; ++r) tile[r32][8 * (r >> 2) + 4 * g + (r & 3)] = v[r];  // [column][row]
   __syncthreads();
   // lanes 0-31 write column n0 + 2c, lanes 32-63 column n0 + 2c + 1: 32 rows each
   const int i = i0 + r32;
@@ -1666,9 +1746,102 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   }
 }
 
-static size_t interp_mfma_lds_bytes() {
+// The same product on one wave per 32 x 16 tile of C (32 coefficients, 16
+// jobs of the group, one prime), on v_mfma_i32_16x16x32_i8, as the persistent
+// launch runs it: all seven weight classes of both 16-row halves stay in 56
+// accumulator registers, the operands come straight from global memory (the
+// 8 bytes a lane needs are contiguous in the 1 KiB operand-order blocks), and
+// no LDS or barrier is involved.  Operand lane l: row (A) or column (Y) l % 16,
+// indices 8 (l / 16) + 0..7 of the 32-wide step; accumulator register j of
+// lane l: row 4 (l / 16) + j, column l % 16.  Task t: prime t / (nit ntc),
+// then row tile fastest.
+__device__ __forceinline__ void dev_interp_wave(uint32_t* const* gco, int N, int Np, int D, int Dp, const int8_t* Ap,
+                                                const int8_t* Yp, TablesDev tab, int t) {
+  const int l = lane_id(), c16 = l & 15, qd = l >> 4;
+  const int nit = Dp >> 5, ntc = Np >> 4;
+  const int k = t / (nit * ntc), rem = t - k * (nit * ntc);
+  const int it = rem % nit, tc = rem / nit;
+  const size_t pa = (size_t)Dp * Dp, py = (size_t)Np * Dp;
+  // this lane's 8 bytes of a block: lane c16 + 32 (qd / 2) of the block's
+  // layout, bytes 8 (qd % 2) ..; the second 16-row half of A 16 lanes on
+  const int off = (c16 + 32 * (qd >> 1)) * 16 + 8 * (qd & 1);
+  const __attribute__((address_space(1))) int8_t* pa0 = gmem(Ap) + (size_t)k * 4 * pa + (size_t)it * Dp * 32 + off;
+  const __attribute__((address_space(1))) int8_t* py0 =
+      gmem(Yp) + (size_t)k * 4 * py + (size_t)(tc >> 1) * Dp * 32 + (tc & 1) * 256 + off;
+  const int n0 = tc * 16, i0 = it * 32;
+  uint32_t* const cp = n0 + c16 < N ? gco[n0 + c16] : nullptr;
+  const ModP q = tab.primes[k];
+  typedef long long i8x8;
+  im_v4i G[2][7];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int u = 0; u < 7; ++u) G[h][u] = (im_v4i){0, 0, 0, 0};
+  // the steps in a rotated order (the sum is the same), so that the waves of
+  // one prime, which share operand blocks, do not all read the same block at
+  // once; the next step's operands load while this step's products run
+  const int nsteps = Dp >> 5;
+  int s = (it + tc) % nsteps;
+  i8x8 a[2][4], y[4];
+  auto load = [&](i8x8(&av)[2][4], i8x8(&yv)[4], int st) {
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) {
+      const size_t sa = pl * pa + (size_t)st * 1024, sy = pl * py + (size_t)st * 1024;
+      av[0][pl] = *(const __attribute__((address_space(1))) i8x8*)(pa0 + sa);
+      av[1][pl] = *(const __attribute__((address_space(1))) i8x8*)(pa0 + sa + 256);
+      yv[pl] = *(const __attribute__((address_space(1))) i8x8*)(py0 + sy);
+    }
+  };
+  load(a, y, s);
+  for (int n = 0; n < nsteps; ++n) {
+    i8x8 an[2][4], yn[4];
+    s = s + 1 == nsteps ? 0 : s + 1;
+    if (n + 1 < nsteps) load(an, yn, s);
+    // digit sd of A against digit td of Y into class sd + td
+#pragma unroll
+    for (int sd = 0; sd < 4; ++sd)
+#pragma unroll
+      for (int td = 0; td < 4; ++td)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          G[h][sd + td] = __builtin_amdgcn_mfma_i32_16x16x32_i8(a[h][sd], y[td], G[h][sd + td], 0, 0, 0);
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) {
+      a[0][pl] = an[0][pl];
+      a[1][pl] = an[1][pl];
+      y[pl] = yn[pl];
+    }
+  }
+  uint32_t wu[7];  // Montgomery forms of 256^u
+  wu[0] = q.one;
+  const uint32_t m256 = to_mont(256u, q);
+#pragma unroll
+  for (int u = 1; u < 7; ++u) wu[u] = mmul(wu[u - 1], m256, q);
+  if (!cp) return;
+  uint32_t* dst = cp + (size_t)k * D;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = i0 + 16 * h + 4 * qd + j;
+      // as in im_fold: the class sums lie within 7 * 2^58.5 < 2^62 < p 2^32
+      int64_t acc = (int64_t)q.p << 32;
+#pragma unroll
+      for (int u = 0; u < 7; ++u) acc += (int64_t)G[h][u][j] * (int64_t)(int32_t)wu[u];
+      const uint32_t v = redc((uint64_t)acc, q.p, q.pinv);
+      if (i < D) dst[i] = umin32(v, v - q.p);
+    }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_interp_mfma(
+    uint32_t* const* gco, int N, int Np, int D, int Dp, const int8_t* Ap, const int8_t* Yp, TablesDev tab) {
+  extern __shared__ __align__(16) int8_t im_lds[];
+  dev_interp_mfma<IM_STAGES, false>(gco, N, Np, D, Dp, Ap, Yp, tab, xcd_block(blockIdx.x, gridDim.x), im_lds);
+}
+
+static size_t interp_mfma_lds_bytes(int stages = IM_STAGES) {
   // the stage ring, reused after the products for four transposes and column pointers
-  const size_t ring = (size_t)IM_STAGES * IM_STAGE_BYTES;
+  const size_t ring = (size_t)stages * IM_STAGE_BYTES;
   const size_t epi = 4 * (32 * 33 * 4) + 4 * 32 * sizeof(uint32_t*);
   return ring > epi ? ring : epi;
 }
@@ -1721,10 +1894,10 @@ __device__ __forceinline__ int lift_negative(const uint32_t* v, int stride, int 
 constexpr int MRC_LANE_MAXP = 128;
 
 __device__ void dev_mrc_lane(const JobDev& J, int lb, TablesDev tab, uint32_t* lds) {
-  const int c = lb * 64 + threadIdx.x;
+  const int c = lb * 64 + lane_id();
   const int P = J.P, D = J.D;
   if (c >= D) return;
-  uint32_t* v = lds + threadIdx.x;  // v[k * 64]
+  uint32_t* v = lds + lane_id();  // v[k * 64]
   for (int k = 0; k < P; ++k) {
     const ModP qk = tab.primes[k];
     const uint32_t* pmk = tab.pm + (size_t)k * tab.K;
@@ -1747,9 +1920,10 @@ __global__ __launch_bounds__(64) void k_mrc_lane(const JobDev* jobs, const int* 
 // One wave per coefficient, lanes over primes k = lane + 64 t: lane k keeps
 // acc_k = sum_{j<k} v_j prod_{i<j} p_i mod p_k; at step j the owner lane of j
 // finishes v_j and broadcasts it.
+template <bool WAVE>
 __device__ void dev_mrc_wave(const JobDev& J, int c, TablesDev tab, uint32_t* lds) {
   const int P = J.P, D = J.D;
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   uint32_t* x = lds;        // residues, then digits
   uint32_t* acc = lds + P;  // running prefix values
   for (int kk = lane; kk < P; kk += 64) {
@@ -1774,14 +1948,14 @@ __device__ void dev_mrc_wave(const JobDev& J, int c, TablesDev tab, uint32_t* ld
       }
     }
   }
-  __syncthreads();
+  group_sync<WAVE>();
   if (lane == 0) J.negflag[c] = lift_negative(x, 1, P, tab.primes);
 }
 
 __global__ __launch_bounds__(64) void k_mrc(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
   extern __shared__ __align__(16) uint32_t lds[];
   const int job = find_job(starts, nj, blockIdx.x, gridDim.x);
-  dev_mrc_wave(jobs[job], blockIdx.x - starts[job], tab, lds);
+  dev_mrc_wave<false>(jobs[job], blockIdx.x - starts[job], tab, lds);
 }
 
 // (e) limb assembly, pass 1: one thread per (limb l, coefficient c) forms the
@@ -1822,15 +1996,17 @@ __global__ void k_limbs_sum(const JobDev* jobs, const int* starts, int nj, Table
 constexpr int CARRY_STAGE_MAXL = 128;
 
 // stage_ld > 0: LDS rows of stage_ld words (>= Lcap + 1 of every job); 0: direct writes.
+template <bool WAVE>
 __device__ void dev_limbs_carry(const JobDev& J, int lb, int stage_ld, uint32_t* lds) {
   const int c0 = lb * 64;
-  const int c = c0 + threadIdx.x;
+  const int lane = lane_id();
+  const int c = c0 + lane;
   const int Lc = J.Lcap, D = J.D;
   const bool staged = stage_ld > 0;
   const int ld = stage_ld;
   bool nz = false;
   if (c <= J.degcap) {
-    uint32_t* o = staged ? lds + threadIdx.x * ld : J.out + (size_t)c * Lc;
+    uint32_t* o = staged ? lds + lane * ld : J.out + (size_t)c * Lc;
     if (c >= D) {
       for (int l = 0; l < Lc; ++l) o[l] = 0u;
     } else {
@@ -1860,13 +2036,13 @@ __device__ void dev_limbs_carry(const JobDev& J, int lb, int stage_ld, uint32_t*
   {
     // one atomic per wave: the highest non-zero coefficient of the 64
     const uint64_t any = __ballot(nz);
-    if (any && threadIdx.x == 0) atomicMax(J.deg_out, c0 + 63 - __clzll((long long)any));
+    if (any && lane == 0) atomicMax(J.deg_out, c0 + 63 - __clzll((long long)any));
   }
   if (staged) {
-    __syncthreads();
+    group_sync<WAVE>();
     const int nc = min(64, J.degcap + 1 - c0);
     uint32_t* dst = J.out + (size_t)c0 * Lc;
-    for (int i = threadIdx.x; i < nc * Lc; i += 64) {
+    for (int i = lane; i < nc * Lc; i += 64) {
       const int r = i / Lc;
       dst[i] = lds[r * ld + (i - r * Lc)];
     }
@@ -1876,7 +2052,7 @@ __device__ void dev_limbs_carry(const JobDev& J, int lb, int stage_ld, uint32_t*
 __global__ __launch_bounds__(64) void k_limbs_carry(const JobDev* jobs, const int* starts, int nj, int stage_ld) {
   extern __shared__ __align__(16) uint32_t lds[];
   const int job = find_job(starts, nj, blockIdx.x, gridDim.x);
-  dev_limbs_carry(jobs[job], blockIdx.x - starts[job], stage_ld, lds);
+  dev_limbs_carry<false>(jobs[job], blockIdx.x - starts[job], stage_ld, lds);
 }
 
 // (e) explicit CRT on the int8 matrix cores.  With M = prod_{k<P} p_k,
@@ -1928,17 +2104,18 @@ __device__ __forceinline__ void crt_load_b(im_v4i (&B)[KSMAX], const __attribute
     B[ks] = *(const __attribute__((address_space(1))) im_v4i*)(Bn + (size_t)min(ks, KS - 1) * 256);
 }
 
-template <int KSMAX, int NT>
-__global__ __launch_bounds__(64) void k_crt_mfma(const JobDev* jobs, const int* starts, int nj, int sld, int cps,
-                                                 TablesDev tab) {
+// One block of rows (b of the launch's nb) on one wave; WAVE: a wave of a
+// larger block, with its own LDS.
+template <int KSMAX, int NT, bool WAVE>
+__device__ __forceinline__ void dev_crt(const JobDev* jobs, const int* starts, int nj, int sld, int cps, TablesDev tab,
+                                        int b, int nb, uint32_t* lds) {
   constexpr int ROWS = 32 * NT;
-  extern __shared__ __align__(16) uint32_t lds[];
-  const int l = threadIdx.x, x = l & 31, g = l >> 5;
-  const int job = find_job(starts, nj, blockIdx.x, gridDim.x);
+  const int l = lane_id(), x = l & 31, g = l >> 5;
+  const int job = find_job(starts, nj, b, nb);
   const JobDev& J = jobs[job];
   const int P = J.P, D = J.D, Lc = J.Lcap, LM = J.crt_LM;
   const int KS = (P + 7) >> 3, NCT = (4 * LM + 4 + 31) >> 5;
-  const int bj = blockIdx.x - starts[job], c0 = bj * ROWS;
+  const int bj = b - starts[job], c0 = bj * ROWS;
   int32_t* T = (int32_t*)lds;     // [ROWS][33]: the accumulator tiles, [row][column]
   uint32_t* O = lds + ROWS * 33;  // [ROWS][sld]: limbs of the rows, then the prime constants
   const uint32_t* wv = J.crt;
@@ -1958,7 +2135,7 @@ __global__ __launch_bounds__(64) void k_crt_mfma(const JobDev* jobs, const int* 
   }
   // the first column tiles' operand blocks (two sets up to 64 primes, one
   // above, for registers), also issued before the barrier
-  constexpr bool B2 = KSMAX <= 8;
+  constexpr bool B2 = KSMAX <= 8 && !WAVE;  // one set in the persistent launch, for registers
   im_v4i Ba[KSMAX], Bb[B2 ? KSMAX : 1];
   crt_load_b<KSMAX>(Ba, Bt, 0, NCT, KS);
   if constexpr (B2) crt_load_b<KSMAX>(Bb, Bt, 1, NCT, KS);
@@ -1986,7 +2163,7 @@ __global__ __launch_bounds__(64) void k_crt_mfma(const JobDev* jobs, const int* 
     Ci[k] = tab.inv_p[k];
   }
   for (int w = l; w < 8 * NCT; w += 64) Ms[w] = w < LM ? Mw[w] : 0u;
-  __syncthreads();
+  group_sync<WAVE>();
   im_v4i A[NT][KSMAX];
   double f[NT];
 #pragma unroll
@@ -2040,7 +2217,7 @@ __global__ __launch_bounds__(64) void k_crt_mfma(const JobDev* jobs, const int* 
     for (int h = 0; h < NT; ++h)
 #pragma unroll
       for (int r = 0; r < 16; ++r) T[(32 * h + 8 * (r >> 2) + 4 * g + (r & 3)) * 33 + x] = acc[h][r];
-    __syncthreads();
+    group_sync<WAVE>();
     if (owner) {
       const int32_t* t = T + l * 33;
 #pragma unroll
@@ -2061,7 +2238,7 @@ __global__ __launch_bounds__(64) void k_crt_mfma(const JobDev* jobs, const int* 
         }
       }
     }
-    __syncthreads();
+    group_sync<WAVE>();
   };
   if constexpr (B2) {
     for (int ct = 0; ct < NCT; ct += 2) {
@@ -2092,7 +2269,7 @@ __global__ __launch_bounds__(64) void k_crt_mfma(const JobDev* jobs, const int* 
   // one atomic per wave: the highest non-zero coefficient of the block
   const uint64_t any = __ballot(owner && row && nz);
   if (any && l == 0) atomicMax(J.deg_out, c0 + 63 - __clzll((long long)any));
-  __syncthreads();
+  group_sync<WAVE>();
   // rows c0 .. c0 + nr - 1 are one contiguous range of nr Lc words
   const int nr = min(ROWS, J.degcap + 1 - c0);
   uint32_t* dst = J.out + (size_t)c0 * Lc;
@@ -2109,93 +2286,280 @@ __global__ __launch_bounds__(64) void k_crt_mfma(const JobDev* jobs, const int* 
   }
 }
 
-// ---------------------------------------------------------------------------
-// (a9) every stage of every job in one persistent launch.  Single-wave blocks
-// take queue positions with an atomic counter; a task first waits (lane 0,
-// bounded spin with sleeps) until the counter of the stage it depends on
-// reaches its target, then runs the same device function as the staged
-// kernel, then publishes its completion with an agent-scope release.  All
-// dependencies point to earlier queue positions, which were taken by running
-// blocks that wait only on still earlier ones, so the queue drains; a wait that
-// exceeds its bound sets err and the block moves on, so every wave exits.
-
-enum { FS_RED = 0, FS_EE, FS_IP, FS_MRC, FS_SUM, FS_CAR };
-
-__global__ __launch_bounds__(64) void k_fused(FusedPlan F, TablesDev tab) {
+template <int KSMAX, int NT>
+__global__ __launch_bounds__(64) void k_crt_mfma(const JobDev* jobs, const int* starts, int nj, int sld, int cps,
+                                                 TablesDev tab) {
   extern __shared__ __align__(16) uint32_t lds[];
-  __shared__ int s_task;
-  for (;;) {
-    if (threadIdx.x == 0) s_task = atomicAdd(F.head, 1);
-    __syncthreads();
-    const int t = s_task;
-    __syncthreads();
-    if (t >= F.base[6]) return;
-    int stage = 0;
-    while (t >= F.base[stage + 1]) ++stage;
-    const int local = t - F.base[stage];
-    const int job = find_job(F.st[stage], F.nj, local);
-    const int lb = local - F.st[stage][job];
-    const JobDev& J = F.jobs[job];
-    int* c = F.ctr + F.ctr_off[job];
-    const int P = J.P;
-    const int nbpp = (J.D + 63) / 64;
-    int* dep = nullptr;
-    int target = 0;
-    if (stage == FS_EE) {
-      dep = c;
-      target = F.st[FS_RED][job + 1] - F.st[FS_RED][job];
-    } else if (stage == FS_IP) {
-      dep = c + 1 + lb;
-      target = nbpp;
-    } else if (stage == FS_MRC) {
-      dep = c + 1 + P;
-      target = P;
-    } else if (stage == FS_SUM) {
-      dep = c + 2 + P;
-      target = F.st[FS_MRC][job + 1] - F.st[FS_MRC][job];
-    } else if (stage == FS_CAR) {
-      dep = c + 3 + P;
-      target = F.st[FS_SUM][job + 1] - F.st[FS_SUM][job];
+  dev_crt<KSMAX, NT, false>(jobs, starts, nj, sld, cps, tab, blockIdx.x, gridDim.x, lds);
+}
+
+// ---------------------------------------------------------------------------
+// (a9) every stage after the reduction in one persistent launch of blocks of
+// four waves, one stage after the other.  The tasks of a stage are claimed in
+// chunks from counters: the blocks of XCD x (dispatch is round-robin over the
+// eight XCDs in blockIdx order) claim from the x-th eighth of the stage's
+// task range first, where the tasks of one (job, prime) share their residues
+// and those of one prime its matrix planes in that XCD's L2, then from the
+// other eighths.  A stage ends when its count of finished tasks reaches its
+// total.  Only running blocks claim tasks and no task waits on anything, so
+// the stages drain whichever blocks the device holds at once; a block that
+// starts late finds the ranges taken.  Each task runs the staged kernel's
+// device function on the same data; the residues come from the reduction's
+// earlier launch, which keeps the scalar cache valid for the evaluation.  A
+// wait that exceeds its time bound sets err and lets the block go on, so
+// every wave exits.
+
+#ifndef FUSED_WAIT_TICKS
+#define FUSED_WAIT_TICKS 500000000ull  // 5 s of the 100 MHz wall clock
+#endif
+
+// A stage's counters (FUSED_STAGE_INTS ints): eight claim heads, then eight
+// per-XCD counts of finished tasks, each in a 128-byte line of its own (the
+// atomics on one line are serialised).
+constexpr int FUSED_LINE = 32;
+static_assert(FUSED_STAGE_INTS == 16 * FUSED_LINE, "counters of a stage");
+
+// Claims the next chunk of at most K of a stage's T tasks for the calling
+// wave (lane 0 claims for it): returns the first task and sets end, or -1
+// once every range is taken.  Head x counts the tasks taken from range x,
+// [T x / 8, T (x + 1) / 8); r walks the ranges starting from the wave's XCD.
+// Another XCD's range is first read with a plain load, so that the waves
+// that finish their own do not queue atomics on a range already taken.
+__device__ __forceinline__ int fused_claim(int* ctr, int T, int K, int xcd, int& r, int& end) {
+  while (r < 8) {
+    const int x = (xcd + r) & 7;
+    const int lo = (int)(((long long)T * x) >> 3), hi = (int)(((long long)T * (x + 1)) >> 3);
+    int c = hi - lo;
+    if (lane_id() == 0) {
+      int* h = ctr + FUSED_LINE * x;
+      if (r == 0 || __hip_atomic_load(h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < hi - lo)
+        c = __hip_atomic_fetch_add(h, K, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (dep && threadIdx.x == 0) {
-      int spins = 0;
-      while (__hip_atomic_load(dep, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        __builtin_amdgcn_s_sleep(8);
-        if (++spins > (1 << 24)) {
-          atomicOr(F.err, 2);
-          break;
+    c = __builtin_amdgcn_readfirstlane(c);
+    if (c < hi - lo) {
+      end = min(hi, lo + c + K);
+      return lo + c;
+    }
+    ++r;
+  }
+  return -1;
+}
+
+// The same for the whole block (thread 0 claims; s_claim passes it on).
+__device__ __forceinline__ int fused_claim_block(int* heads, int T, int K, int xcd, int& r, int& end,
+                                                 int* s_claim) {
+  __syncthreads();  // the previous claim has been read
+  if (threadIdx.x == 0) {
+    int e = 0;
+    s_claim[0] = fused_claim(heads, T, K, xcd, r, e);
+    s_claim[1] = e;
+  }
+  __syncthreads();
+  end = s_claim[1];
+  return s_claim[0];
+}
+
+// The end of a stage.  cnt: the calling wave's finished tasks (uniform in
+// the wave, 0 outside the stage).  The block's count goes to its XCD's
+// counter in one release by thread 0, after every wave's memory accesses
+// have completed (an agent-scope release writes the XCD's L2 back, so one
+// per block instead of one per wave); then that thread waits, with plain
+// atomic loads (an acquire in the loop would invalidate the caches at every
+// poll, under the feet of the blocks still working), until the eight
+// counters add up to the stage's T tasks, and acquires once; the block
+// barrier passes that on to the other waves.
+__device__ __forceinline__ void fused_stage_end(const FusedPlan& F, int* ctr, int cnt, int T, int xcd, int* s_cnt) {
+  if (lane_id() == 0 && cnt) atomicAdd(s_cnt, cnt);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int n = *s_cnt;
+    *s_cnt = 0;
+    if (n) __hip_atomic_fetch_add(ctr + FUSED_LINE * (8 + xcd), n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+      int done = 0;
+#pragma unroll
+      for (int x = 0; x < 8; ++x)
+        done += __hip_atomic_load(ctr + FUSED_LINE * (8 + x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (done >= T) break;
+      __builtin_amdgcn_s_sleep(8);
+      if (wall_clock64() - t0 > FUSED_WAIT_TICKS) {
+        atomicOr(F.err, 2);
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// C: register capacity of the evaluation's register Euclid (0: none);
+// KSMAX: contraction steps of the CRT's left operand (P <= 8 KSMAX).  The
+// register budget holds four waves per SIMD up to 48 primes.
+template <int C, int KSMAX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KSMAX <= 8 ? 4 : 2, 8))) void k_fused(
+    FusedPlan F, TablesDev tab) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ int s_claim[2], s_cnt;
+  // the wave's index is uniform across it (the compiler does not know that
+  // threadIdx.x >> 6 is), so every task index below is a scalar
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = lane_id();
+  const int xcd = blockIdx.x & 7;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  // (b)+(c) evaluation and elimination: wave tasks
+  {
+    int* c = F.ctr;
+    const int T = F.n_rg + F.n_ee;
+    int cnt = 0;
+    if (w < F.wv[0]) {
+      uint32_t* sl = lds + w * F.lw[0];
+      int r = 0, e = 0;
+      for (int t0 = fused_claim(c, T, F.kc[0], xcd, r, e); t0 >= 0; t0 = fused_claim(c, T, F.kc[0], xcd, r, e)) {
+        for (int t = t0; t < e; ++t, ++cnt) {
+          if (t < F.n_rg) {
+            if constexpr (C > 0) {
+              const int job = find_job(F.st_rg, F.nj, t, F.n_rg);
+              const bool ok = dev_eval_elim_rg<C>(F.jobs[job], t - F.st_rg[job], tab, sl);
+              if (__ballot(!ok) != 0ull && lane == 0) F.fb_queue[atomicAdd(F.fb_count, 1)] = t;
+            }
+          } else {
+            const int u = t - F.n_rg;
+            const int job = find_job(F.st_ee, F.nj, u, F.n_ee);
+            dev_eval_elim<64, true>(F.jobs[job], u - F.st_ee[job], tab, sl);
+          }
         }
       }
     }
-    __syncthreads();
-    if (stage == FS_RED) dev_reduce(J, lb, 0, P, tab);
-    else if (stage == FS_EE) dev_eval_elim<64, false>(J, lb, tab, lds);
-    else if (stage == FS_IP) dev_interp(J, lb, tab, lds);
-    else if (stage == FS_MRC) {
-      if (F.mrc_lane) dev_mrc_lane(J, lb, tab, lds);
-      else dev_mrc_wave(J, lb, tab, lds);
-    } else if (stage == FS_SUM) dev_limbs_sum(J, lb, tab);
-    else dev_limbs_carry(J, lb, F.stage_ld, lds);
-    __syncthreads();
-    if (threadIdx.x == 0 && stage != FS_CAR) {
-      int* done = stage == FS_RED ? c : stage == FS_EE ? c + 1 + lb / nbpp : c + 1 + P + (stage - FS_IP);
-      __threadfence();
-      __hip_atomic_fetch_add(done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    fused_stage_end(F, c, cnt, T, xcd, &s_cnt);
+  }
+  if constexpr (C > 0) {
+    // the queued blocks, recomputed by the LDS kernel's function
+    int* c = F.ctr + 1 * FUSED_STAGE_INTS;
+    const int T = __hip_atomic_load(F.fb_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int cnt = 0;
+    if (T > 0 && w < F.wv[1]) {
+      uint32_t* sl = lds + w * F.lw[1];
+      int r = 0, e = 0;
+      for (int t0 = fused_claim(c, T, 1, xcd, r, e); t0 >= 0; t0 = fused_claim(c, T, 1, xcd, r, e)) {
+        for (int i = t0; i < e; ++i, ++cnt) {
+          const int b = __hip_atomic_load(F.fb_queue + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const int job = find_job(F.st_rg, F.nj, b, F.n_rg);
+          dev_eval_elim<64, true>(F.jobs[job], b - F.st_rg[job], tab, sl);
+        }
+      }
+    }
+    // (no queued block: every block reads the same count, no wait)
+    if (T > 0) fused_stage_end(F, c, cnt, T, xcd, &s_cnt);
+  }
+  // (d) interpolation: wave tasks on the matrix cores for a group, else
+  // block tasks per (job, prime)
+  {
+    int* c = F.ctr + 2 * FUSED_STAGE_INTS;
+    int r = 0, e = 0, cnt = 0;
+    if (F.im) {
+      for (int t0 = fused_claim(c, F.n_im, F.kc[2], xcd, r, e); t0 >= 0;
+           t0 = fused_claim(c, F.n_im, F.kc[2], xcd, r, e))
+        for (int t = t0; t < e; ++t, ++cnt) dev_interp_wave(F.gco, F.gN, F.gNp, F.gD, F.gDp, F.Ap, F.Yp, tab, t);
+      fused_stage_end(F, c, cnt, F.n_im, xcd, &s_cnt);
+    } else {
+      InterpTab it;
+      it.W = F.itW;
+      it.Q = F.itQ;
+      it.nb = F.itNB;
+      for (int t0 = fused_claim_block(c, F.n_ip, F.kc[2], xcd, r, e, s_claim); t0 >= 0;
+           t0 = fused_claim_block(c, F.n_ip, F.kc[2], xcd, r, e, s_claim)) {
+        for (int b = t0; b < e; ++b, ++cnt) {
+          const int job = find_job(F.st_ip, F.nj, b, F.n_ip);
+          dev_interp(F.jobs[job], b - F.st_ip[job], tab, lds, it);
+          __syncthreads();  // the next task refills the LDS read above
+        }
+      }
+      // the block's count once (wave 0 holds it)
+      fused_stage_end(F, c, w == 0 ? cnt : 0, F.n_ip, xcd, &s_cnt);
+    }
+  }
+  // (e) reconstruction
+  if (F.crt) {
+    int* c = F.ctr + 3 * FUSED_STAGE_INTS;
+    if (w < F.wv[2]) {
+      uint32_t* sl = lds + w * F.lw[2];
+      int r = 0, e = 0;
+      for (int t0 = fused_claim(c, F.n_crt, F.kc[3], xcd, r, e); t0 >= 0;
+           t0 = fused_claim(c, F.n_crt, F.kc[3], xcd, r, e))
+        for (int t = t0; t < e; ++t)
+          dev_crt<KSMAX, 1, true>(F.jobs, F.st_crt, F.nj, F.sld, F.cps, tab, t, F.n_crt, sl);
+    }
+    // the launch's end orders the results: no count, no wait
+  } else {
+    {
+      int* c = F.ctr + 3 * FUSED_STAGE_INTS;
+      int cnt = 0;
+      if (w < F.wv[2]) {
+        uint32_t* sl = lds + w * F.lw[2];
+        int r = 0, e = 0;
+        for (int t0 = fused_claim(c, F.n_mrc, F.kc[3], xcd, r, e); t0 >= 0;
+             t0 = fused_claim(c, F.n_mrc, F.kc[3], xcd, r, e)) {
+          for (int t = t0; t < e; ++t, ++cnt) {
+            const int job = find_job(F.st_mrc, F.nj, t, F.n_mrc);
+            if (F.mrc_lane)
+              dev_mrc_lane(F.jobs[job], t - F.st_mrc[job], tab, sl);
+            else
+              dev_mrc_wave<true>(F.jobs[job], t - F.st_mrc[job], tab, sl);
+          }
+        }
+      }
+      fused_stage_end(F, c, cnt, F.n_mrc, xcd, &s_cnt);
+    }
+    {
+      int* c = F.ctr + 4 * FUSED_STAGE_INTS;
+      int r = 0, e = 0, cnt = 0;
+      for (int t0 = fused_claim_block(c, F.n_sum, F.kc[4], xcd, r, e, s_claim); t0 >= 0;
+           t0 = fused_claim_block(c, F.n_sum, F.kc[4], xcd, r, e, s_claim)) {
+        for (int b = t0; b < e; ++b, ++cnt) {
+          const int job = find_job(F.st_sum, F.nj, b, F.n_sum);
+          dev_limbs_sum(F.jobs[job], b - F.st_sum[job], tab);
+        }
+      }
+      fused_stage_end(F, c, w == 0 ? cnt : 0, F.n_sum, xcd, &s_cnt);
+    }
+    {
+      int* c = F.ctr + 5 * FUSED_STAGE_INTS;
+      if (w < F.wv[3]) {
+        uint32_t* sl = lds + w * F.lw[3];
+        int r = 0, e = 0;
+        for (int t0 = fused_claim(c, F.n_car, F.kc[5], xcd, r, e); t0 >= 0;
+             t0 = fused_claim(c, F.n_car, F.kc[5], xcd, r, e)) {
+          for (int t = t0; t < e; ++t) {
+            const int job = find_job(F.st_car, F.nj, t, F.n_car);
+            dev_limbs_carry<true>(F.jobs[job], t - F.st_car[job], F.stage_ld, sl);
+          }
+        }
+      }
     }
   }
 }
 
-int fused_blocks(size_t lds_bytes, int tasks) {
-  int dev = 0, per_cu = 0;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused, 64, lds_bytes) != hipSuccess) return 0;
-  const long long n = (long long)per_cu * prop.multiProcessorCount;
-  return (int)(n < tasks ? n : tasks);
+#define BIRES_FUSED_KERNEL(C, KS)                                                             \
+  ((C) == 24 ? ((KS) == 6 ? (const void*)k_fused<24, 6> : (const void*)k_fused<24, 16>)     \
+   : (C) == 32 ? ((KS) == 6 ? (const void*)k_fused<32, 6> : (const void*)k_fused<32, 16>)   \
+               : ((KS) == 6 ? (const void*)k_fused<0, 6> : (const void*)k_fused<0, 16>))
+
+int fused_capacity(int c) { return c == 24 || c == 32 ? c : 0; }
+int fused_crt_steps(int max_primes) { return max_primes <= 48 ? 6 : 16; }
+
+int fused_blocks_per_cu(int C, int KS, size_t lds_bytes) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, BIRES_FUSED_KERNEL(C, KS), 256, lds_bytes) != hipSuccess)
+    return 0;
+  return per_cu;
 }
 
-void launch_fused(const FusedPlan& F, size_t lds_bytes, int blocks, TablesDev tab, hipStream_t s) {
-  hipLaunchKernelGGL(k_fused, dim3(blocks), dim3(64), lds_bytes, s, F, tab);
+void launch_fused(int C, int KS, const FusedPlan& F, size_t lds_bytes, int blocks, TablesDev tab, hipStream_t s) {
+  void* args[] = {(void*)&F, (void*)&tab};
+  (void)hipLaunchKernel(BIRES_FUSED_KERNEL(C, KS), dim3(blocks), dim3(256), args, lds_bytes, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -2665,18 +3029,21 @@ int crt_row_stride(int max_lcap) { return max_lcap | 1; }
 // and the words of M for a prime count (M < 2^(32 P) has at most P words),
 // rounded up to whole column tiles, both sized by the batch's largest prime
 // count rather than CRT_MAXP, which keeps the blocks small.
-static int crt_const_stride(int max_primes) { return (max_primes + 1) & ~1; }
+int crt_const_stride(int max_primes) { return (max_primes + 1) & ~1; }
 static int crt_max_words(int max_primes) { return 8 * ((4 * (max_primes + 1) + 4 + 31) / 32); }
 
 // Coefficients per block: two row tiles while the left operands of both fit
 // in registers (up to 48 primes), one above.
 int crt_rows_per_block(int max_primes) { return max_primes <= 48 ? 64 : 32; }
 
-size_t crt_lds_bytes(int max_lcap, int max_primes) {
+size_t crt_lds_bytes_rows(int max_lcap, int max_primes, int R) {
   // accumulator tiles, limb rows (an even word count), prime constants
-  const int R = crt_rows_per_block(max_primes);
   const size_t rows = (size_t)R * crt_row_stride(max_lcap);
   return (size_t)(R * 33 + rows + 5 * crt_const_stride(max_primes) + crt_max_words(max_primes)) * sizeof(uint32_t);
+}
+
+size_t crt_lds_bytes(int max_lcap, int max_primes) {
+  return crt_lds_bytes_rows(max_lcap, max_primes, crt_rows_per_block(max_primes));
 }
 
 void launch_crt(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, int max_lcap,

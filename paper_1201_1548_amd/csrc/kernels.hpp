@@ -93,14 +93,24 @@ void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int 
 // max primes) within the LDS per block.
 bool crt_ok(int max_primes);
 size_t crt_lds_bytes(int max_lcap, int max_primes);
+size_t crt_lds_bytes_rows(int max_lcap, int max_primes, int rows);
+// the CRT's LDS strides: limb rows (sld) and prime constants (cps)
+int crt_row_stride(int max_lcap);
+int crt_const_stride(int max_primes);
 int crt_rows_per_block(int max_primes);
 void launch_crt(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, int max_lcap,
                 TablesDev tab, hipStream_t s);
 void launch_limbs_sum(const JobDev* jobs, const int* starts, int nj, int nblocks, TablesDev tab, hipStream_t s);
-// Persistent fused launch (see FusedPlan): blocks that fit on the device at
-// once for this LDS size, capped at the task count (0 on a runtime error).
-int fused_blocks(size_t lds_bytes, int tasks);
-void launch_fused(const FusedPlan& F, size_t lds_bytes, int blocks, TablesDev tab, hipStream_t s);
+// Persistent fused launch (see FusedPlan), blocks of 256 threads: C the
+// register Euclid's capacity (fused_capacity: 24, 32, or 0 for the LDS
+// kernel only), KS = fused_crt_steps(max primes); blocks of one CU at once
+// for this LDS size (0 on a runtime error).  The matrix-core interpolation
+// runs on tiles of 32 coefficients x 16 jobs per wave without LDS, the CRT
+// takes crt_lds_bytes_rows(.., 32) per wave.
+int fused_capacity(int rg_capacity);
+int fused_crt_steps(int max_primes);
+int fused_blocks_per_cu(int C, int KS, size_t lds_bytes);
+void launch_fused(int C, int KS, const FusedPlan& F, size_t lds_bytes, int blocks, TablesDev tab, hipStream_t s);
 // Principal subresultant coefficients modulo prime index 0 of tab (the caller
 // shifts the table to its prime): one lane per point a < J.D, J.m and J.n the
 // formal degrees; writes sr_i(a) (plain) to num[i * D + a] for i < K, with

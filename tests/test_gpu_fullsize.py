@@ -8,6 +8,7 @@ tests/golden/make_node_digests.py.  Covered:
 
 * 8 of the 256 dense total-degree-20 pairs of the benchmark batch (device
   memory, plan reuse, the staged schedule), besides pair 0's stored full value;
+  the persistent fused schedule's results of the whole batch equal them;
 * the degree-40 curve-analysis resultants res(f, f_y; y) (D = 1561): the dense
   curve, g^2 + h k and g^2 + h k^2, with gcd(R, R') checked by its defining
   properties including its content;
@@ -18,7 +19,8 @@ tests/golden/make_node_digests.py.  Covered:
   reconstruction) through the server, in a mix with other requests, and as
   single calls;
 * the evaluation kernels' capacity boundaries (register array 24/32, LDS
-  kernel, a zero y-degree), batched with each kernel and single.
+  kernel, a zero y-degree), batched with each kernel, under the fused
+  schedule and single.
 The P > 128 route is also checked against the oracle's full Bareiss value on
 low-y-degree pairs with 360..700-bit coefficients, alone and in mixed batches.
 """
@@ -59,6 +61,15 @@ def test_deg20_bench_batch_pairs_full():
         rec = nodecheck.case("deg20", name)
         say("  ", name)
         nodecheck.check(res[rec["args"][0]], rec)
+    say("  the same batch under the persistent fused schedule")
+    try:
+        br.set_schedule("fused")
+        b.run()
+        fused = b.results()
+    finally:
+        br.set_schedule("staged")
+    assert list(b.status) == [0] * 256
+    assert fused == res
 
 
 def check_gcd(R, h):
@@ -152,11 +163,14 @@ def test_capacity_boundaries_full(mn):
         lds, st_l = br.resultant_batch(jobs)
         br.set_eval_kernel("auto")
         reg, st_r = br.resultant_batch(jobs)
+        br.set_schedule("fused")
+        fus, st_f = br.resultant_batch(jobs)
     finally:
         br.set_eval_kernel("auto")
-    assert st_l == st_r == [0, 0, 0]
+        br.set_schedule("staged")
+    assert st_l == st_r == st_f == [0, 0, 0]
     nodecheck.check(reg[0], rec)
-    assert lds == reg and reg[1] == reg[0] == br.resultant(F, G)
+    assert lds == reg == fus and reg[1] == reg[0] == br.resultant(F, G)
 
 
 # ---------------------------------------------------------------------------
@@ -194,14 +208,21 @@ def test_more_than_128_primes_mixed_batches():
     assert st2 == [0] * len(jobs + filler)
     assert res2[:len(jobs)] == refs
     assert res2[len(jobs)] == load("deg20_res_0.txt")[1]
+    # the persistent fused schedule takes the same Garner route
+    try:
+        br.set_schedule("fused")
+        res3, st3 = br.resultant_batch(jobs + filler)
+    finally:
+        br.set_schedule("staged")
+    assert st3 == st2 and res3 == res2
     b = br.DeviceBatch(jobs)
     b.run()
     assert b.results() == refs
 
 
-def test_lane_garner_kernel_in_large_fused_batch():
-    # the fused schedule reconstructs by Garner's digits; with >= 16384 output
-    # coefficients and at most 128 primes it takes one lane per coefficient
+def test_large_fused_batch_of_mixed_shapes():
+    # the persistent fused schedule on two shapes (no matrix-core group: the
+    # interpolation per (job, prime)), reconstructed by the explicit CRT
     jobs = [("res",) + synth.pair_deg20(s) + ("y",) for s in range(42)]
     jobs += [("res",) + synth.pair_deg6(i) + ("y",) for i in range(4)]
     say("fused batch of", len(jobs))

@@ -257,8 +257,7 @@ def test_autotune_keeps_results():
 def test_large_batch_mixed_shapes():
     # 50 jobs of two shapes (>= 16384 output coefficients, at most 48 primes):
     # the staged schedule reconstructs them with the explicit CRT on the
-    # matrix cores, like single calls; the lane-per-coefficient Garner kernel
-    # is reached through the fused schedule (tests/test_gpu_fullsize.py)
+    # matrix cores, like single calls
     jobs = [("res",) + synth.pair_deg20(i) + ("y",) for i in range(40)]
     jobs += [("res",) + synth.pair_deg6(i % 4) + ("y",) for i in range(10)]
     say("large batch", len(jobs))
