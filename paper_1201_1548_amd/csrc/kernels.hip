@@ -2105,7 +2105,7 @@ __device__ __forceinline__ void crt_load_b(im_v4i (&B)[KSMAX], const __attribute
 }
 
 // One block of rows (b of the launch's nb) on one wave; WAVE: a wave of a
-// larger block, with its own LDS.
+// larger block (the persistent launch), with its own LDS slice.
 template <int KSMAX, int NT, bool WAVE>
 __device__ __forceinline__ void dev_crt(const JobDev* jobs, const int* starts, int nj, int sld, int cps, TablesDev tab,
                                         int b, int nb, uint32_t* lds) {
@@ -2286,11 +2286,189 @@ __device__ __forceinline__ void dev_crt(const JobDev* jobs, const int* starts, i
   }
 }
 
+// The staged kernel keeps its own copy of the body above: called through the
+// device function, the compiler schedules the operand loads differently and
+// takes 255 VGPRs for 48 primes (one wave per SIMD, 30 -> 44 us at config 2)
+// instead of 150.
 template <int KSMAX, int NT>
 __global__ __launch_bounds__(64) void k_crt_mfma(const JobDev* jobs, const int* starts, int nj, int sld, int cps,
                                                  TablesDev tab) {
+  constexpr int ROWS = 32 * NT;
   extern __shared__ __align__(16) uint32_t lds[];
-  dev_crt<KSMAX, NT, false>(jobs, starts, nj, sld, cps, tab, blockIdx.x, gridDim.x, lds);
+  const int l = threadIdx.x, x = l & 31, g = l >> 5;
+  const int job = find_job(starts, nj, blockIdx.x, gridDim.x);
+  const JobDev& J = jobs[job];
+  const int P = J.P, D = J.D, Lc = J.Lcap, LM = J.crt_LM;
+  const int KS = (P + 7) >> 3, NCT = (4 * LM + 4 + 31) >> 5;
+  const int bj = blockIdx.x - starts[job], c0 = bj * ROWS;
+  int32_t* T = (int32_t*)lds;     // [ROWS][33]: the accumulator tiles, [row][column]
+  uint32_t* O = lds + ROWS * 33;  // [ROWS][sld]: limbs of the rows, then the prime constants
+  const uint32_t* wv = J.crt;
+  const uint32_t* Mw = J.crt + P + (size_t)P * LM;
+  const __attribute__((address_space(1))) uint32_t* Bt =
+      gmem(J.crt) + (((size_t)P + (size_t)P * LM + LM + 3) & ~(size_t)3) + 4 * l;
+  bool rv[NT];
+  // this lane's residues (primes 8 ks + 4 g + j) of its row in each tile, all
+  // issued before the barrier
+  uint32_t xr[NT][KSMAX * 4];
+#pragma unroll
+  for (int h = 0; h < NT; ++h) {
+    rv[h] = c0 + 32 * h + x < D;
+    const __attribute__((address_space(1))) uint32_t* col = gmem(J.coefs) + min(c0 + 32 * h + x, D - 1);
+#pragma unroll
+    for (int u = 0; u < KSMAX * 4; ++u) xr[h][u] = col[(size_t)min(8 * (u >> 2) + 4 * g + (u & 3), P - 1) * D];
+  }
+  // the first column tiles' operand blocks (two sets up to 64 primes, one
+  // above, for registers), also issued before the barrier
+  constexpr bool B2 = KSMAX <= 8;
+  im_v4i Ba[KSMAX], Bb[B2 ? KSMAX : 1];
+  crt_load_b<KSMAX>(Ba, Bt, 0, NCT, KS);
+  if constexpr (B2) crt_load_b<KSMAX>(Bb, Bt, 1, NCT, KS);
+  {
+    // this block's share of the zero coefficients above the job's last block
+    const int nbj = (min(D, J.degcap + 1) + ROWS - 1) / ROWS, cz = nbj * ROWS;
+    if (cz <= J.degcap) {
+      const long long nw = (long long)(J.degcap + 1 - cz) * Lc, share = (nw + nbj - 1) / nbj;
+      const long long w0 = bj * share, w1 = min(nw, w0 + share);
+      uint32_t* dst = J.out + (size_t)cz * Lc;
+      for (long long i = w0 + l; i < w1; i += 64) dst[i] = 0u;
+    }
+  }
+  // per-prime constants staged in LDS at stride cps (the batch's largest
+  // prime count, rounded up to even): p, -p^{-1} mod 2^32, w_k, 1 / p_k; then
+  // the words of M, zero from LM up to the last byte column's limb
+  uint32_t* Cp = O + ROWS * sld;
+  double* Ci = (double*)(Cp + 3 * cps);
+  uint32_t* Ms = Cp + 5 * cps;
+  for (int k = l; k < P; k += 64) {
+    const ModP q = tab.primes[k];
+    Cp[k] = q.p;
+    Cp[cps + k] = q.pinv;
+    Cp[2 * cps + k] = wv[k];
+    Ci[k] = tab.inv_p[k];
+  }
+  for (int w = l; w < 8 * NCT; w += 64) Ms[w] = w < LM ? Mw[w] : 0u;
+  __syncthreads();
+  im_v4i A[NT][KSMAX];
+  double f[NT];
+#pragma unroll
+  for (int h = 0; h < NT; ++h) f[h] = 0.0;
+#pragma unroll
+  for (int ks = 0; ks < KSMAX; ++ks) {
+    uint32_t d[NT][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int u = 4 * ks + j, kl = 8 * ks + 4 * g + j, k = min(kl, P - 1);
+      const uint32_t p = Cp[k], pinv = Cp[cps + k], wk = Cp[2 * cps + k];
+      const double ip = Ci[k];
+#pragma unroll
+      for (int h = 0; h < NT; ++h) {
+        const bool live = rv[h] && kl < P;
+        const uint32_t y = redc((uint64_t)xr[h][u] * wk, p, pinv);
+        const int32_t ys = y > (p >> 1) ? (int32_t)(y - p) : (int32_t)y;
+        f[h] = fma((double)(live ? ys : 0), ip, f[h]);
+        d[h][j] = digits4(y, p) & (0u - (uint32_t)live);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < NT; ++h) A[h][ks] = (im_v4i){(int)d[h][0], (int)d[h][1], (int)d[h][2], (int)d[h][3]};
+  }
+  // from here on lane l < ROWS owns row c0 + l (row x of tile g)
+  int64_t tq = 0;
+  bool row = false;
+#pragma unroll
+  for (int h = 0; h < NT; ++h) {
+    const double fs = f[h] + __shfl_xor(f[h], 32);
+    if (g == h) {
+      tq = (int64_t)floor(fs + 0.5);
+      row = rv[h];
+    }
+  }
+  const bool owner = l < ROWS;
+  int64_t carry = 0;
+  uint32_t last = 0;
+  bool bad = false, nz = false;
+  // one column tile: products, the tiles through LDS, the carry chain
+  auto tile = [&](int ct, const im_v4i(&B)[KSMAX]) {
+    im_v16i acc[NT];
+#pragma unroll
+    for (int h = 0; h < NT; ++h) acc[h] = (im_v16i){0};
+#pragma unroll
+    for (int ks = 0; ks < KSMAX; ++ks)
+#pragma unroll
+      for (int h = 0; h < NT; ++h) acc[h] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[h][ks], B[ks], acc[h], 0, 0, 0);
+    // accumulator register r of lane l: row 8 (r / 4) + 4 g + r % 4 of its tile, column x
+#pragma unroll
+    for (int h = 0; h < NT; ++h)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) T[(32 * h + 8 * (r >> 2) + 4 * g + (r & 3)) * 33 + x] = acc[h][r];
+    __syncthreads();
+    if (owner) {
+      const int32_t* t = T + l * 33;
+#pragma unroll
+      for (int w = 0; w < 8; ++w) {
+        const int L = 8 * ct + w;
+        // |S_c| <= P (3 * 128 + 64) 128 < 2^23 (the top digit of y_k is at most
+        // 64 in size), so t_0 + 2^8 t_1 and t_2 + 2^8 t_3 fit in 32 bits
+        const int32_t lo = t[4 * w] + (t[4 * w + 1] << 8), hi = t[4 * w + 2] + (t[4 * w + 3] << 8);
+        const int64_t v = carry + (int64_t)lo + ((int64_t)hi << 16) - tq * (int64_t)Ms[L];
+        const uint32_t limb = (uint32_t)v;
+        carry = v >> 32;
+        if (L < Lc) {
+          O[l * sld + L] = limb;
+          nz |= limb != 0u;
+          last = limb;
+        } else if (limb != ((int32_t)last < 0 ? 0xFFFFFFFFu : 0u)) {
+          bad = true;
+        }
+      }
+    }
+    __syncthreads();
+  };
+  if constexpr (B2) {
+    for (int ct = 0; ct < NCT; ct += 2) {
+      tile(ct, Ba);
+      crt_load_b<KSMAX>(Ba, Bt, ct + 2, NCT, KS);
+      if (ct + 1 < NCT) {
+        tile(ct + 1, Bb);
+        crt_load_b<KSMAX>(Bb, Bt, ct + 3, NCT, KS);
+      }
+    }
+  } else {
+    for (int ct = 0; ct < NCT; ++ct) {
+      tile(ct, Ba);
+      crt_load_b<KSMAX>(Ba, Bt, ct + 1, NCT, KS);
+    }
+  }
+  if (owner) {
+    // limbs above the last byte column: the carry's extension
+    for (int L = 8 * NCT; L < Lc; ++L) {
+      const uint32_t limb = (uint32_t)carry;
+      carry >>= 32;
+      O[l * sld + L] = limb;
+      nz |= limb != 0u;
+      last = limb;
+    }
+    if (row && (bad || carry != ((int32_t)last < 0 ? -1 : 0))) atomicOr(J.err, 1);
+  }
+  // one atomic per wave: the highest non-zero coefficient of the block
+  const uint64_t any = __ballot(owner && row && nz);
+  if (any && l == 0) atomicMax(J.deg_out, c0 + 63 - __clzll((long long)any));
+  __syncthreads();
+  // rows c0 .. c0 + nr - 1 are one contiguous range of nr Lc words
+  const int nr = min(ROWS, J.degcap + 1 - c0);
+  uint32_t* dst = J.out + (size_t)c0 * Lc;
+  const int dq = 64 / Lc, dr = 64 - dq * Lc;
+  int r = l / Lc, L = l - r * Lc;
+  for (int i = l; i < nr * Lc; i += 64) {
+    dst[i] = O[r * sld + L];
+    r += dq;
+    L += dr;
+    if (L >= Lc) {
+      L -= Lc;
+      ++r;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
