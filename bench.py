@@ -299,8 +299,8 @@ def _zx_mul(a, b):
 def bench_autotune(args):
     """The schedule space per workload shape: every schedule (staged, fused,
     Schur) timed on the same device batch, checked bit-exact against the staged
-    results, and the autotuner's choice (bires_autotune, one timing per
-    schedule) next to the fastest measured one."""
+    results, and the autotuner's choice (bires_autotune, the best of three
+    timed rounds per schedule) next to the fastest measured one."""
     import torch
     import paper_1201_1548_amd as br
     from paper_1201_1548_amd import synth
@@ -336,7 +336,7 @@ def bench_autotune(args):
             torch.cuda.synchronize()
             times[sched] = {"ms_per_step": round((time.perf_counter() - t0) / reps * 1e3, 3), "bit_exact": ok}
         br.set_schedule("auto")
-        chosen = batch.autotune(reps=1)
+        chosen = batch.autotune(reps=3)
         fastest = min(times, key=lambda k: times[k]["ms_per_step"])
         agree += chosen == fastest
         cases[name] = {"jobs": len(jobs), "schedules": times, "autotuner": chosen, "fastest": fastest}

@@ -367,10 +367,11 @@ int bires_set_graphs(int enable);
 int bires_graph_stats(int64_t *captures, int64_t *replays);
 
 /* Autotuner: runs the batch (arguments as bires_resultant_batch) under every
- * schedule (staged, fused, Schur), keeps the fastest (best of `reps` timed runs after one warm-up) for
- * the batch's size key (total (prime, point) instances, largest degree sum in
- * the eliminated variable, largest prime count, each log2-bucketed), and
- * returns it in *chosen.  BIRES_SCHEDULE_AUTO then uses the table; when the
+ * schedule (staged, fused, Schur), keeps the fastest (the best of `reps` timed
+ * runs of each, in rounds that take the schedules in turn, after one warm-up
+ * round) for the batch's size key (total (prime, point) instances, largest
+ * degree sum in the eliminated variable, largest prime count, each
+ * log2-bucketed), and returns it in *chosen.  BIRES_SCHEDULE_AUTO then uses the table; when the
  * environment variable BIRES_AUTOTUNE_CACHE names a file, the table is loaded
  * from it at set-up and rewritten after every tuning run.  The outputs hold the
  * batch's results afterwards. */

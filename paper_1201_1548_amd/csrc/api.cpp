@@ -381,29 +381,32 @@ int bires_autotune(int n, const bires_bipoly* f, const bires_bipoly* g, const in
   int err = BIRES_OK;
   Context* cx = context(&err);
   if (!cx) return err;
-  double best = 1e300;
-  int best_s = BIRES_SCHEDULE_STAGED;
+  // each schedule once to warm up, then the timed rounds in turn (staged,
+  // fused, Schur, staged, ...), so that a drift of the device's clocks or a
+  // stray slow call does not favour one schedule; the best time of each
+  const int scheds[3] = {BIRES_SCHEDULE_STAGED, BIRES_SCHEDULE_FUSED, BIRES_SCHEDULE_SCHUR};
+  double t[3] = {1e300, 1e300, 1e300};
   std::string key;
-  for (int sched : {BIRES_SCHEDULE_STAGED, BIRES_SCHEDULE_FUSED, BIRES_SCHEDULE_SCHUR}) {
-    cx->forced_schedule = sched;
-    int e = bires_resultant_batch(n, f, g, kind, var, out, status, mem, stream);  // warm-up
-    double t = 1e300;
-    for (int r = 0; r < reps && e == BIRES_OK; ++r) {
+  for (int r = -1; r < reps; ++r) {
+    for (int i = 0; i < 3; ++i) {
+      cx->forced_schedule = scheds[i];
       const auto t0 = std::chrono::steady_clock::now();
-      e = bires_resultant_batch(n, f, g, kind, var, out, status, mem, stream);
-      t = std::min(t, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
-    }
-    cx->forced_schedule = -1;
-    if (e != BIRES_OK) return e;
-    {
+      const int e = bires_resultant_batch(n, f, g, kind, var, out, status, mem, stream);
+      const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      cx->forced_schedule = -1;
+      if (e != BIRES_OK) return e;
+      if (r >= 0) t[i] = std::min(t[i], dt);
       std::lock_guard<std::mutex> lk(cx->tune_mu);
       key = cx->last_key;
     }
-    if (t < best) {
-      best = t;
-      best_s = sched;
-    }
   }
+  int best_s = BIRES_SCHEDULE_STAGED;
+  double best = 1e300;
+  for (int i = 0; i < 3; ++i)
+    if (t[i] < best) {
+      best = t[i];
+      best_s = scheds[i];
+    }
   tune_store(cx, key, best_s);
   if (chosen) *chosen = best_s;
   return BIRES_OK;
