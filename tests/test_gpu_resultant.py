@@ -241,6 +241,37 @@ def test_fused_schedule_matches_staged(schedule):
             assert R == (resultant_y(F, G) if var == "y" else resultant_x(F, G))
 
 
+def test_fused_batches_in_flight_on_two_streams():
+    # two persistent fused launches at once on two streams: neither holds the
+    # whole device, so each launch's stages must drain with the blocks it has
+    # (tasks are claimed, a stage ends on its count of finished tasks); one
+    # batch takes the matrix-core interpolation, the other the per-(job, prime)
+    # one
+    import torch
+    jobs_a = [("res",) + synth.pair_deg20(s) + ("y",) for s in range(256)]
+    jobs_b = [("res",) + synth.pair_deg6(i % 4) + ("y",) for i in range(40)]
+    say("fused batches on two streams", len(jobs_a), len(jobs_b))
+    a, b = br.DeviceBatch(jobs_a), br.DeviceBatch(jobs_b)
+    br.set_schedule("staged")
+    a.run()
+    b.run()
+    ref_a, ref_b = a.results(), b.results()
+    assert ref_a[0] == load("deg20_res_0.txt")[1]
+    assert ref_b[:4] == [load("deg6_res_%d.txt" % i)[1] for i in range(4)]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    try:
+        br.set_schedule("fused")
+        for rep in range(3):
+            a.run_async(s1)
+            b.run_async(s2)
+            a.wait()
+            b.wait()
+            assert a.results() == ref_a, rep
+            assert b.results() == ref_b, rep
+    finally:
+        br.set_schedule("staged")
+
+
 def test_autotune_keeps_results():
     jobs = [("res",) + synth.pair_deg6(i % 4) + ("y",) for i in range(16)]
     say("autotune")
