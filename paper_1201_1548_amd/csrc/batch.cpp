@@ -793,7 +793,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     int demand;  // blocks that the largest stage can use
     if (!group.empty()) {
       F.im = 1;
-      F.n_im = (gDp / 32) * (gNp / 16) * gP;  // wave tiles of 32 coefficients x 16 jobs
+      F.n_im = ((gDp / 32 + 1) / 2) * (gNp / 32) * gP;  // blocks of 64 coefficients x 32 jobs
       F.gco = (uint32_t* const*)(D0 + o_gco);
       F.gN = (int)group.size();
       F.gNp = gNp;
@@ -801,8 +801,8 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
       F.gDp = gDp;
       F.Ap = vinv;
       F.Yp = (const int8_t*)(D0 + o_yp);
-      block_lds = 0;
-      demand = (F.n_im + 3) / 4;
+      block_lds = fused_interp_lds_bytes();
+      demand = F.n_im;
     } else {
       F.st_ip = st_of(K_IP);
       F.n_ip = nb_of(K_IP);
@@ -863,7 +863,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     };
     F.kc[0] = per_claim(F.n_rg + F.n_ee, (long long)f_blocks * F.wv[0]);
     F.kc[1] = 1;
-    F.kc[2] = F.im ? per_claim(F.n_im, 4LL * f_blocks) : per_claim(F.n_ip, f_blocks);
+    F.kc[2] = per_claim(F.im ? F.n_im : F.n_ip, f_blocks);
     F.kc[3] = per_claim(F.crt ? F.n_crt : F.n_mrc, (long long)f_blocks * F.wv[2]);
     F.kc[4] = per_claim(F.n_sum, f_blocks);
     F.kc[5] = per_claim(F.n_car, (long long)f_blocks * F.wv[3]);

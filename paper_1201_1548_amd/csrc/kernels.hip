@@ -1746,30 +1746,48 @@ __device__ __forceinline__ void dev_interp_mfma(uint32_t* const* gco, int N, int
   }
 }
 
-// The same product on one wave per 32 x 16 tile of C (32 coefficients, 16
-// jobs of the group, one prime), on v_mfma_i32_16x16x32_i8, as the persistent
-// launch runs it: all seven weight classes of both 16-row halves stay in 56
-// accumulator registers, the operands come straight from global memory (the
-// 8 bytes a lane needs are contiguous in the 1 KiB operand-order blocks), and
-// no LDS or barrier is involved.  Operand lane l: row (A) or column (Y) l % 16,
-// indices 8 (l / 16) + 0..7 of the 32-wide step; accumulator register j of
-// lane l: row 4 (l / 16) + j, column l % 16.  Task t: prime t / (nit ntc),
-// then row tile fastest.
-__device__ __forceinline__ void dev_interp_wave(uint32_t* const* gco, int N, int Np, int D, int Dp, const int8_t* Ap,
-                                                const int8_t* Yp, TablesDev tab, int t) {
-  const int l = lane_id(), c16 = l & 15, qd = l >> 4;
-  const int nit = Dp >> 5, ntc = Np >> 4;
-  const int k = t / (nit * ntc), rem = t - k * (nit * ntc);
-  const int it = rem % nit, tc = rem / nit;
+// The same product in the persistent launch, whose register budget (four
+// waves per SIMD for the evaluation) cannot hold seven 32 x 32 accumulators
+// per wave: a block of four waves computes a 64 x 32 block of C (coefficient
+// rows 64 br .., jobs 32 bc .., prime k), wave w the 32 x 16 tile of row tile
+// 2 br + w % 2 and column half w / 2 on v_mfma_i32_16x16x32_i8, with all seven
+// weight classes of both 16-row halves in 56 accumulator registers.  The
+// operand blocks of a step (A planes of the two row tiles, Y planes of the
+// column tile: 12 KiB) go through a ring of three stages in LDS (36 KiB), each
+// wave fetching three; a wave reads the 8 bytes per lane of its
+// 16 x 32 operands (row or column l % 16, indices 8 (l / 16) + 0..7 of the
+// step, contiguous in the 1 KiB operand-order blocks).  Accumulator register
+// j of lane l: row 4 (l / 16) + j, column l % 16.  Logical block lb: prime
+// lb / (nbr nbc), then row pair fastest.
+constexpr int IMB_STAGE_BYTES = 12 * 1024;
+constexpr int IMB_STAGES = 3;
+
+__device__ __forceinline__ void dev_interp_blk(uint32_t* const* gco, int N, int Np, int D, int Dp, const int8_t* Ap,
+                                               const int8_t* Yp, TablesDev tab, int lb, int8_t* im_lds) {
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, c16 = l & 15, qd = l >> 4;
+  const int nit = Dp >> 5, nct = Np >> 5, nbr = (nit + 1) >> 1;
+  const int k = lb / (nbr * nct), rem = lb - k * (nbr * nct);
+  const int br = rem % nbr, bc = rem / nbr;
+  const int it = 2 * br + (w & 1), hc = w >> 1;
   const size_t pa = (size_t)Dp * Dp, py = (size_t)Np * Dp;
-  // this lane's 8 bytes of a block: lane c16 + 32 (qd / 2) of the block's
-  // layout, bytes 8 (qd % 2) ..; the second 16-row half of A 16 lanes on
+  // this wave's three fetches per step: blocks 3 w .. 3 w + 2 of the twelve
+  // (0-7: the A planes of row tiles 2 br, 2 br + 1; 8-11: the Y planes)
+  const int8_t* src[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int f = 3 * w + i;
+    if (f < 8)
+      src[i] = Ap + (size_t)k * 4 * pa + (size_t)(f & 3) * pa + (size_t)min(2 * br + (f >> 2), nit - 1) * Dp * 32 + 16 * l;
+    else
+      src[i] = Yp + (size_t)k * 4 * py + (size_t)(f - 8) * py + (size_t)bc * Dp * 32 + 16 * l;
+  }
+  const int nsteps = Dp >> 5;
+  // this lane's operand bytes within a block; the wave's A blocks start at
+  // (w % 2) 4 KiB, its Y half 256 bytes into the Y blocks
   const int off = (c16 + 32 * (qd >> 1)) * 16 + 8 * (qd & 1);
-  const __attribute__((address_space(1))) int8_t* pa0 = gmem(Ap) + (size_t)k * 4 * pa + (size_t)it * Dp * 32 + off;
-  const __attribute__((address_space(1))) int8_t* py0 =
-      gmem(Yp) + (size_t)k * 4 * py + (size_t)(tc >> 1) * Dp * 32 + (tc & 1) * 256 + off;
-  const int n0 = tc * 16, i0 = it * 32;
-  uint32_t* const cp = n0 + c16 < N ? gco[n0 + c16] : nullptr;
+  const int ra = (w & 1) * 4096 + off, ry = 8192 + hc * 256 + off;
+  const int n0 = bc * 32 + hc * 16, i0 = it * 32;
+  uint32_t* const cp = it < nit && n0 + c16 < N ? gco[n0 + c16] : nullptr;
   const ModP q = tab.primes[k];
   typedef long long i8x8;
   im_v4i G[2][7];
@@ -1777,26 +1795,36 @@ __device__ __forceinline__ void dev_interp_wave(uint32_t* const* gco, int N, int
   for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int u = 0; u < 7; ++u) G[h][u] = (im_v4i){0, 0, 0, 0};
-  // the steps in a rotated order (the sum is the same), so that the waves of
-  // one prime, which share operand blocks, do not all read the same block at
-  // once; the next step's operands load while this step's products run
-  const int nsteps = Dp >> 5;
-  int s = (it + tc) % nsteps;
-  i8x8 a[2][4], y[4];
-  auto load = [&](i8x8(&av)[2][4], i8x8(&yv)[4], int st) {
+#pragma unroll
+  for (int st = 0; st < IMB_STAGES - 1; ++st) {
+    if (st < nsteps) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) im_fetch(src[i] + st * 1024, im_lds + st * IMB_STAGE_BYTES + (3 * w + i) * 1024);
+    }
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    // this wave's fetches of step s (and the loads before them) are done
+    // once at most those of step s + 1 remain
+    if (s + 1 < nsteps)
+      IM_WAIT_VM_BARRIER(3);
+    else
+      IM_WAIT_VM_BARRIER(0);
+    const int8_t* sb = im_lds + (s % IMB_STAGES) * IMB_STAGE_BYTES;
+    i8x8 a[2][4], y[4];
 #pragma unroll
     for (int pl = 0; pl < 4; ++pl) {
-      const size_t sa = pl * pa + (size_t)st * 1024, sy = pl * py + (size_t)st * 1024;
-      av[0][pl] = *(const __attribute__((address_space(1))) i8x8*)(pa0 + sa);
-      av[1][pl] = *(const __attribute__((address_space(1))) i8x8*)(pa0 + sa + 256);
-      yv[pl] = *(const __attribute__((address_space(1))) i8x8*)(py0 + sy);
+      a[0][pl] = *(const i8x8*)(sb + ra + pl * 1024);
+      a[1][pl] = *(const i8x8*)(sb + ra + pl * 1024 + 256);
+      y[pl] = *(const i8x8*)(sb + ry + pl * 1024);
     }
-  };
-  load(a, y, s);
-  for (int n = 0; n < nsteps; ++n) {
-    i8x8 an[2][4], yn[4];
-    s = s + 1 == nsteps ? 0 : s + 1;
-    if (n + 1 < nsteps) load(an, yn, s);
+    // the stage read at step s - 1 is free: every wave passed this barrier
+    // after its reads of it completed
+    const int sn = s + IMB_STAGES - 1;
+    if (sn < nsteps) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        im_fetch(src[i] + (size_t)sn * 1024, im_lds + (sn % IMB_STAGES) * IMB_STAGE_BYTES + (3 * w + i) * 1024);
+    }
     // digit sd of A against digit td of Y into class sd + td
 #pragma unroll
     for (int sd = 0; sd < 4; ++sd)
@@ -1805,33 +1833,30 @@ __device__ __forceinline__ void dev_interp_wave(uint32_t* const* gco, int N, int
 #pragma unroll
         for (int h = 0; h < 2; ++h)
           G[h][sd + td] = __builtin_amdgcn_mfma_i32_16x16x32_i8(a[h][sd], y[td], G[h][sd + td], 0, 0, 0);
-#pragma unroll
-    for (int pl = 0; pl < 4; ++pl) {
-      a[0][pl] = an[0][pl];
-      a[1][pl] = an[1][pl];
-      y[pl] = yn[pl];
-    }
   }
   uint32_t wu[7];  // Montgomery forms of 256^u
   wu[0] = q.one;
   const uint32_t m256 = to_mont(256u, q);
 #pragma unroll
   for (int u = 1; u < 7; ++u) wu[u] = mmul(wu[u - 1], m256, q);
-  if (!cp) return;
-  uint32_t* dst = cp + (size_t)k * D;
+  if (cp) {
+    uint32_t* dst = cp + (size_t)k * D;
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int i = i0 + 16 * h + 4 * qd + j;
-      // as in im_fold: the class sums lie within 7 * 2^58.5 < 2^62 < p 2^32
-      int64_t acc = (int64_t)q.p << 32;
+      for (int j = 0; j < 4; ++j) {
+        const int i = i0 + 16 * h + 4 * qd + j;
+        // as in im_fold: the class sums lie within 7 * 2^58.5 < 2^62 < p 2^32
+        int64_t acc = (int64_t)q.p << 32;
 #pragma unroll
-      for (int u = 0; u < 7; ++u) acc += (int64_t)G[h][u][j] * (int64_t)(int32_t)wu[u];
-      const uint32_t v = redc((uint64_t)acc, q.p, q.pinv);
-      if (i < D) dst[i] = umin32(v, v - q.p);
-    }
+        for (int u = 0; u < 7; ++u) acc += (int64_t)G[h][u][j] * (int64_t)(int32_t)wu[u];
+        const uint32_t v = redc((uint64_t)acc, q.p, q.pinv);
+        if (i < D) dst[i] = umin32(v, v - q.p);
+      }
+  }
 }
+
+size_t fused_interp_lds_bytes() { return (size_t)IMB_STAGES * IMB_STAGE_BYTES; }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_interp_mfma(
     uint32_t* const* gco, int N, int Np, int D, int Dp, const int8_t* Ap, const int8_t* Yp, TablesDev tab) {
@@ -2632,32 +2657,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KSMAX <= 8 
     // (no queued block: every block reads the same count, no wait)
     if (T > 0) fused_stage_end(F, c, cnt, T, xcd, &s_cnt);
   }
-  // (d) interpolation: wave tasks on the matrix cores for a group, else
-  // block tasks per (job, prime)
+  // (d) interpolation: block tasks, on the matrix cores for a group, else
+  // per (job, prime)
   {
     int* c = F.ctr + 2 * FUSED_STAGE_INTS;
+    const int T = F.im ? F.n_im : F.n_ip;
+    InterpTab it;
+    it.W = F.itW;
+    it.Q = F.itQ;
+    it.nb = F.itNB;
     int r = 0, e = 0, cnt = 0;
-    if (F.im) {
-      for (int t0 = fused_claim(c, F.n_im, F.kc[2], xcd, r, e); t0 >= 0;
-           t0 = fused_claim(c, F.n_im, F.kc[2], xcd, r, e))
-        for (int t = t0; t < e; ++t, ++cnt) dev_interp_wave(F.gco, F.gN, F.gNp, F.gD, F.gDp, F.Ap, F.Yp, tab, t);
-      fused_stage_end(F, c, cnt, F.n_im, xcd, &s_cnt);
-    } else {
-      InterpTab it;
-      it.W = F.itW;
-      it.Q = F.itQ;
-      it.nb = F.itNB;
-      for (int t0 = fused_claim_block(c, F.n_ip, F.kc[2], xcd, r, e, s_claim); t0 >= 0;
-           t0 = fused_claim_block(c, F.n_ip, F.kc[2], xcd, r, e, s_claim)) {
-        for (int b = t0; b < e; ++b, ++cnt) {
+    for (int t0 = fused_claim_block(c, T, F.kc[2], xcd, r, e, s_claim); t0 >= 0;
+         t0 = fused_claim_block(c, T, F.kc[2], xcd, r, e, s_claim)) {
+      for (int b = t0; b < e; ++b, ++cnt) {
+        if (F.im) {
+          dev_interp_blk(F.gco, F.gN, F.gNp, F.gD, F.gDp, F.Ap, F.Yp, tab, b, (int8_t*)lds);
+        } else {
           const int job = find_job(F.st_ip, F.nj, b, F.n_ip);
           dev_interp(F.jobs[job], b - F.st_ip[job], tab, lds, it);
-          __syncthreads();  // the next task refills the LDS read above
         }
+        __syncthreads();  // the next task refills the LDS read above
       }
-      // the block's count once (wave 0 holds it)
-      fused_stage_end(F, c, w == 0 ? cnt : 0, F.n_ip, xcd, &s_cnt);
     }
+    // the block's count once (wave 0 holds it)
+    fused_stage_end(F, c, w == 0 ? cnt : 0, T, xcd, &s_cnt);
   }
   // (e) reconstruction
   if (F.crt) {

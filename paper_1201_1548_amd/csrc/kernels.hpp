@@ -105,11 +105,12 @@ void launch_limbs_sum(const JobDev* jobs, const int* starts, int nj, int nblocks
 // register Euclid's capacity (fused_capacity: 24, 32, or 0 for the LDS
 // kernel only), KS = fused_crt_steps(max primes); blocks of one CU at once
 // for this LDS size (0 on a runtime error).  The matrix-core interpolation
-// runs on tiles of 32 coefficients x 16 jobs per wave without LDS, the CRT
-// takes crt_lds_bytes_rows(.., 32) per wave.
+// takes fused_interp_lds_bytes per block (64 x 32 blocks of C), the CRT
+// crt_lds_bytes_rows(.., 32) per wave.
 int fused_capacity(int rg_capacity);
 int fused_crt_steps(int max_primes);
 int fused_blocks_per_cu(int C, int KS, size_t lds_bytes);
+size_t fused_interp_lds_bytes();
 void launch_fused(int C, int KS, const FusedPlan& F, size_t lds_bytes, int blocks, TablesDev tab, hipStream_t s);
 // Principal subresultant coefficients modulo prime index 0 of tab (the caller
 // shifts the table to its prime): one lane per point a < J.D, J.m and J.n the
