@@ -305,9 +305,12 @@ int bires_debug_values(const bires_bipoly *f, const bires_bipoly *g, int kind, i
 
 /* Launch schedule of the batched pipeline.
  *   BIRES_SCHEDULE_STAGED: one launch per stage (reduce, evaluation +
- *     elimination per size bucket, interpolation, mixed radix, limbs);
- *   BIRES_SCHEDULE_FUSED: every stage of every job in one persistent launch
- *     whose blocks take tasks from a device queue in dependency order;
+ *     elimination per size bucket, interpolation, explicit CRT or mixed
+ *     radix and limbs);
+ *   BIRES_SCHEDULE_FUSED: the reduction, then every other stage of every job
+ *     in one persistent launch, stage after stage; its blocks claim each
+ *     stage's tasks from device counters, so no block waits on one that has
+ *     not started (the launch may share the device with other work);
  *   BIRES_SCHEDULE_SCHUR: staged, with the evaluation + elimination of the
  *     jobs with 1 <= min(m, n) and m + n <= 128 by the Schur algorithm on the
  *     displacement generators of the Sylvester matrix (Section 5.1, eq.

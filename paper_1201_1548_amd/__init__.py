@@ -528,7 +528,9 @@ def set_schedule(schedule):
 def set_eval_kernel(kernel):
     """Evaluation + elimination kernel of the staged schedule: 'auto' (f's
     array in registers where the degrees allow), 'lds' or 'schur' (the Schur
-    algorithm on the displacement generators, a wavefront per instance)."""
+    algorithm on the displacement generators, a wavefront per instance).  The
+    fused schedule follows 'auto' and 'lds', and runs the LDS kernel's
+    function in place of Schur."""
     _check(lib().bires_set_eval_kernel({"auto": 0, "lds": 1, "schur": 2}[kernel]), "bires_set_eval_kernel")
 
 
