@@ -6,8 +6,11 @@
 //   k_transpose   exchange x and y in a limb rectangle (res_x, disc_x)
 //   k_reduce      (a) coefficients modulo each prime, Montgomery form
 //   k_eval_elim   (b)+(c) evaluate at x = a and take the univariate resultant
-//                 over F_p, one lane per (prime, point); k_eval_elim_rg24 and
-//                 _rg32 keep f's coefficient array in registers
+//                 over F_p, one lane per (prime, point); k_eval_elim_rg24,
+//                 _rg32 and _rg64 keep f's coefficient array in registers
+//   k_schur       (c) the same elimination by the Schur algorithm on the
+//                 displacement generators, one wave per (prime, point)
+//   k_psc         principal subresultant coefficients mod p, one lane per point
 //   k_interp      (d) interpolation per prime, nodes a = 0..D-1
 //   k_interp_mfma (d) interpolation of a batch sharing the nodes, int8 matrix
 //                 cores (value digit planes written by the evaluation
@@ -16,6 +19,8 @@
 //   k_crt_mfma    (e) explicit CRT straight to limbs, int8 matrix cores
 //   k_mrc         (e) mixed-radix (Garner) digits per coefficient
 //   k_limbs_sum / k_limbs_carry   (e) digits -> two's-complement limbs
+//   k_fused       every stage after the reduction in one persistent launch
+//   k_gcd_p / k_fiber_chain   gcd mod p, the N^- / N^+ degree chain
 //
 // Every kernel is batch-native: an array of per-job first-block indices maps
 // each block to its job (find_job), so a single job is a batch of one.
@@ -1575,177 +1580,6 @@ __device__ __forceinline__ void im_fetch(const int8_t* src, int8_t* dst) {
     asm volatile("" ::: "memory");                                                   \
   } while (0)
 
-// The products of weight classes u in [U0, U1) over every contraction step,
-// through a ring of STAGES stages (2 or 3).
-template <int U0, int U1, int STAGES>
-__device__ __forceinline__ void im_pass(const int8_t* src, size_t pstride, const int8_t* im_lds, int8_t* dst0, int ra,
-                                        int ry, int nsteps, im_v16i (&G)[U1 - U0]) {
-#pragma unroll
-  for (int st = 0; st < STAGES - 1; ++st) {
-    if (st < nsteps) {
-#pragma unroll
-      for (int pl = 0; pl < 4; ++pl) im_fetch(src + pl * pstride + st * 1024, dst0 + st * IM_STAGE_BYTES + pl * 1024);
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < U1 - U0; ++u) G[u] = (im_v16i){0};
-  // the fetches of step s + STAGES - 1 into the stage that step s - 1 read:
-  // every wave passed this step's barrier after its reads of it completed
-  auto issue_fetch = [&](int s) {
-    const int sn = s + STAGES - 1;
-    if (sn < nsteps) {
-      int8_t* d = dst0 + (sn % STAGES) * IM_STAGE_BYTES;
-#pragma unroll
-      for (int pl = 0; pl < 4; ++pl) im_fetch(src + pl * pstride + (size_t)sn * 1024, d + pl * 1024);
-    }
-  };
-  for (int s = 0; s < nsteps; ++s) {
-    // this wave's fetches of step s (and the loads before them) are done
-    // once at most those of the younger steps in flight remain
-    if constexpr (STAGES == 3) {
-      if (s + 1 < nsteps)
-        IM_WAIT_VM_BARRIER(4);
-      else
-        IM_WAIT_VM_BARRIER(0);
-    } else {
-      static_assert(STAGES == 2, "ring of two or three stages");
-      IM_WAIT_VM_BARRIER(0);
-    }
-    const int8_t* sb = im_lds + (s % STAGES) * IM_STAGE_BYTES;
-    // the Y digits this pass uses (t >= U0 - 3)
-    constexpr int T0 = U0 > 3 ? U0 - 3 : 0;
-    im_v4i yv[4];
-#pragma unroll
-    for (int i = T0; i < 4; ++i) yv[i] = *(const im_v4i*)(sb + ry + 1024 * i);
-    if constexpr (U1 - U0 == 7) {
-      im_v4i av[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = *(const im_v4i*)(sb + ra + 1024 * i);
-      issue_fetch(s);
-      // class by class, digit sd of A against digit u - sd of Y
-#pragma unroll
-      for (int u = U0; u < U1; ++u)
-#pragma unroll
-        for (int sd = (u > 3 ? u - 3 : 0); sd <= (u < 3 ? u : 3); ++sd)
-          G[u - U0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[sd], yv[u - sd], G[u - U0], 0, 0, 0);
-    } else {
-      issue_fetch(s);
-      // digit by digit of A (one A operand live at a time), against the Y
-      // digits that give a class of this pass
-#pragma unroll
-      for (int sd = 0; sd < 4; ++sd) {
-        if (sd + 3 < U0 || sd >= U1) continue;
-        const im_v4i a = *(const im_v4i*)(sb + ra + 1024 * sd);
-#pragma unroll
-        for (int td = 0; td < 4; ++td)
-          if (sd + td >= U0 && sd + td < U1)
-            G[sd + td - U0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, yv[td], G[sd + td - U0], 0, 0, 0);
-      }
-    }
-  }
-}
-
-// sum_{u in [U0, U1)} G_u 256^u R^{-1} mod p for accumulator register r, in
-// [0, p): |G_u| <= 4 Dp 2^14 <= 2^28 and w_u < p < 2^31, so the sum lies
-// within 7 * 2^58.5 < 2^62 < p 2^32; adding p 2^32 (a multiple of p) makes it
-// non-negative and below 2 p 2^32, where redc leaves a value below 2p, hence
-// one more conditional subtraction.
-template <int U0, int U1>
-__device__ __forceinline__ uint32_t im_fold(const im_v16i (&G)[U1 - U0], int r, const uint32_t (&wu)[7],
-                                            const ModP& q) {
-  int64_t acc = (int64_t)q.p << 32;
-#pragma unroll
-  for (int u = U0; u < U1; ++u) acc += (int64_t)G[u - U0][r] * (int64_t)(int32_t)wu[u];
-  const uint32_t v = redc((uint64_t)acc, q.p, q.pinv);
-  return umin32(v, v - q.p);
-}
-
-// One 64 x 64 block of C (logical block lb) on the four waves of a block.
-// SPLIT: the seven classes in two passes over the steps (classes 0-3, then
-// 4-6), which holds 64 accumulator registers instead of 112 at the price of
-// fetching the operands twice.
-template <int STAGES, bool SPLIT>
-__device__ __forceinline__ void dev_interp_mfma(uint32_t* const* gco, int N, int Np, int D, int Dp, const int8_t* Ap,
-                                                const int8_t* Yp, TablesDev tab, int lb, int8_t* im_lds) {
-  const int t = threadIdx.x, w = t >> 6, l = t & 63, r32 = l & 31, g = l >> 5;
-  const int nit = Dp >> 5, nnt = Np >> 5, nbr = (nit + 1) >> 1, nbc = (nnt + 1) >> 1;
-  const int k = lb / (nbr * nbc), rem = lb - k * nbr * nbc;
-  const int br = rem % nbr, bc = rem / nbr;
-  const int it = 2 * br + (w & 1), nt = 2 * bc + (w >> 1);
-  const bool live = it < nit && nt < nnt;
-  const size_t pa = (size_t)Dp * Dp, py = (size_t)Np * Dp;
-  // this wave's four fetches per step: waves 0, 1 the A planes of row tiles
-  // 2 br, 2 br + 1, waves 2, 3 the Y planes of column tiles 2 bc, 2 bc + 1
-  // (operand-order blocks: 1 KiB per (tile, step), lane l holds bytes 16 l..)
-  const int8_t* src;
-  size_t pstride;
-  if (w < 2) {
-    src = Ap + (size_t)k * 4 * pa + (size_t)min(2 * br + w, nit - 1) * Dp * 32 + 16 * l;
-    pstride = pa;
-  } else {
-    src = Yp + (size_t)k * 4 * py + (size_t)min(2 * bc + w - 2, nnt - 1) * Dp * 32 + 16 * l;
-    pstride = py;
-  }
-  // stage layout: [row tile 0: 4 planes][row tile 1][column tile 0][column tile 1], 1 KiB each
-  int8_t* const dst0 = im_lds + w * 4096;
-  const int ra = (w & 1) * 4096 + 16 * l, ry = 8192 + (w >> 1) * 4096 + 16 * l;
-  const int nsteps = Dp >> 5;
-  const int n0 = nt * 32, i0 = it * 32;
-  // each column's output row (null past the group or the matrix), loaded
-  // before the products so that its latency is hidden; every job of the
-  // group has P primes
-  uint32_t* const cpp = l < 32 && live && n0 + l < N ? gco[n0 + l] : nullptr;
-  const ModP q = tab.primes[k];  // likewise
-  uint32_t v[16];  // the tile's values: accumulator register r's entry
-  if constexpr (!SPLIT) {
-    im_v16i G[7];
-    im_pass<0, 7, STAGES>(src, pstride, im_lds, dst0, ra, ry, nsteps, G);
-    uint32_t wu[7];  // Montgomery forms of 256^u
-    wu[0] = q.one;
-    const uint32_t m256 = to_mont(256u, q);
-#pragma unroll
-    for (int u = 1; u < 7; ++u) wu[u] = mmul(wu[u - 1], m256, q);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = im_fold<0, 7>(G, r, wu, q);
-  } else {
-    uint32_t wu[7];
-    {
-      im_v16i G[4];
-      im_pass<0, 4, STAGES>(src, pstride, im_lds, dst0, ra, ry, nsteps, G);
-      wu[0] = q.one;
-      const uint32_t m256 = to_mont(256u, q);
-#pragma unroll
-      for (int u = 1; u < 7; ++u) wu[u] = mmul(wu[u - 1], m256, q);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = im_fold<0, 4>(G, r, wu, q);
-    }
-    // every wave's reads of the ring are done before the second pass refills it
-    __syncthreads();
-    im_v16i G[3];
-    im_pass<4, 7, STAGES>(src, pstride, im_lds, dst0, ra, ry, nsteps, G);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const uint32_t sum = v[r] + im_fold<4, 7>(G, r, wu, q);  // < 2p < 2^32
-      v[r] = umin32(sum, sum - q.p);
-    }
-  }
-  // every wave's last reads are done before the ring is reused for the transposes
-  __syncthreads();
-  uint32_t(*tile)[33] = (uint32_t(*)[33])(im_lds + w * (32 * 33 * 4));
-  uint32_t** colp = (uint32_t**)(im_lds + 4 * (32 * 33 * 4)) + 32 * w;
-  if (l < 32) colp[l] = cpp ? cpp + (size_t)k * D : nullptr;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) tile[r32][8 * (r >> 2) + 4 * g + (r & 3)] = v[r];  // [column][row]
-  __syncthreads();
-  // lanes 0-31 write column n0 + 2c, lanes 32-63 column n0 + 2c + 1: 32 rows each
-  const int i = i0 + r32;
-  for (int c = 0; c < 16; ++c) {
-    const int col = 2 * c + g;
-    uint32_t* dst = colp[col];
-    if (dst && i < D) dst[i] = tile[col][r32];
-  }
-}
-
 // The same product in the persistent launch, whose register budget (four
 // waves per SIMD for the evaluation) cannot hold seven 32 x 32 accumulators
 // per wave: a block of four waves computes a 64 x 32 block of C (coefficient
@@ -1846,7 +1680,9 @@ __device__ __forceinline__ void dev_interp_blk(uint32_t* const* gco, int N, int 
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int i = i0 + 16 * h + 4 * qd + j;
-        // as in im_fold: the class sums lie within 7 * 2^58.5 < 2^62 < p 2^32
+        // |G_u| <= 4 Dp 2^14 <= 2^28 and w_u < p < 2^31: the class sums lie
+        // within 7 * 2^58.5 < 2^62 < p 2^32, and adding p 2^32 leaves a value
+        // in [0, 2 p 2^32), where redc gives one below 2p
         int64_t acc = (int64_t)q.p << 32;
 #pragma unroll
         for (int u = 0; u < 7; ++u) acc += (int64_t)G[h][u][j] * (int64_t)(int32_t)wu[u];
@@ -1861,12 +1697,117 @@ size_t fused_interp_lds_bytes() { return (size_t)IMB_STAGES * IMB_STAGE_BYTES; }
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_interp_mfma(
     uint32_t* const* gco, int N, int Np, int D, int Dp, const int8_t* Ap, const int8_t* Yp, TablesDev tab) {
   extern __shared__ __align__(16) int8_t im_lds[];
-  dev_interp_mfma<IM_STAGES, false>(gco, N, Np, D, Dp, Ap, Yp, tab, xcd_block(blockIdx.x, gridDim.x), im_lds);
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, r32 = l & 31, g = l >> 5;
+  const int nit = Dp >> 5, nnt = Np >> 5, nbr = (nit + 1) >> 1, nbc = (nnt + 1) >> 1;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int k = lb / (nbr * nbc), rem = lb - k * nbr * nbc;
+  const int br = rem % nbr, bc = rem / nbr;
+  const int it = 2 * br + (w & 1), nt = 2 * bc + (w >> 1);
+  const bool live = it < nit && nt < nnt;
+  const size_t pa = (size_t)Dp * Dp, py = (size_t)Np * Dp;
+  // this wave's four fetches per step: waves 0, 1 the A planes of row tiles
+  // 2 br, 2 br + 1, waves 2, 3 the Y planes of column tiles 2 bc, 2 bc + 1
+  // (operand-order blocks: 1 KiB per (tile, step), lane l holds bytes 16 l..)
+  const int8_t* src;
+  size_t pstride;
+  if (w < 2) {
+    src = Ap + (size_t)k * 4 * pa + (size_t)min(2 * br + w, nit - 1) * Dp * 32 + 16 * l;
+    pstride = pa;
+  } else {
+    src = Yp + (size_t)k * 4 * py + (size_t)min(2 * bc + w - 2, nnt - 1) * Dp * 32 + 16 * l;
+    pstride = py;
+  }
+  // stage layout: [row tile 0: 4 planes][row tile 1][column tile 0][column tile 1], 1 KiB each
+  int8_t* const dst0 = im_lds + w * 4096;
+  const int ra = (w & 1) * 4096 + 16 * l, ry = 8192 + (w >> 1) * 4096 + 16 * l;
+  const int nsteps = Dp >> 5;
+  const int n0 = nt * 32, i0 = it * 32;
+  // each column's output row (null past the group or the matrix), loaded
+  // before the products so that its latency is hidden; every job of the
+  // group has P primes
+  uint32_t* const cpp = l < 32 && live && n0 + l < N ? gco[n0 + l] : nullptr;
+  const ModP q = tab.primes[k];  // likewise
+#pragma unroll
+  for (int st = 0; st < IM_STAGES - 1; ++st) {
+    if (st < nsteps) {
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) im_fetch(src + pl * pstride + st * 1024, dst0 + st * IM_STAGE_BYTES + pl * 1024);
+    }
+  }
+  im_v16i G0 = {0}, G1 = {0}, G2 = {0}, G3 = {0}, G4 = {0}, G5 = {0}, G6 = {0};
+  for (int s = 0; s < nsteps; ++s) {
+    // this wave's fetches of step s (and the loads before them) are done
+    // once at most those of step s + 1 remain
+    if (s + 1 < nsteps)
+      IM_WAIT_VM_BARRIER(4);
+    else
+      IM_WAIT_VM_BARRIER(0);
+    const int8_t* sb = im_lds + (s % IM_STAGES) * IM_STAGE_BYTES;
+    const im_v4i a0 = *(const im_v4i*)(sb + ra), a1 = *(const im_v4i*)(sb + ra + 1024),
+                 a2 = *(const im_v4i*)(sb + ra + 2048), a3 = *(const im_v4i*)(sb + ra + 3072);
+    const im_v4i y0 = *(const im_v4i*)(sb + ry), y1 = *(const im_v4i*)(sb + ry + 1024),
+                 y2 = *(const im_v4i*)(sb + ry + 2048), y3 = *(const im_v4i*)(sb + ry + 3072);
+    // the stage read at step s - 1 is free: every wave passed this barrier
+    // after its reads of it completed
+    const int sn = s + IM_STAGES - 1;
+    if (sn < nsteps) {
+      int8_t* d = dst0 + (sn % IM_STAGES) * IM_STAGE_BYTES;
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) im_fetch(src + pl * pstride + (size_t)sn * 1024, d + pl * 1024);
+    }
+    G0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, y0, G0, 0, 0, 0);
+    G1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, y1, G1, 0, 0, 0);
+    G1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, y0, G1, 0, 0, 0);
+    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, y2, G2, 0, 0, 0);
+    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, y1, G2, 0, 0, 0);
+    G2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, y0, G2, 0, 0, 0);
+    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, y3, G3, 0, 0, 0);
+    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, y2, G3, 0, 0, 0);
+    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, y1, G3, 0, 0, 0);
+    G3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, y0, G3, 0, 0, 0);
+    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, y3, G4, 0, 0, 0);
+    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, y2, G4, 0, 0, 0);
+    G4 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, y1, G4, 0, 0, 0);
+    G5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, y3, G5, 0, 0, 0);
+    G5 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, y2, G5, 0, 0, 0);
+    G6 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, y3, G6, 0, 0, 0);
+  }
+  // every wave's last reads are done before the ring is reused for the transposes
+  __syncthreads();
+  uint32_t(*tile)[33] = (uint32_t(*)[33])(im_lds + w * (32 * 33 * 4));
+  uint32_t** colp = (uint32_t**)(im_lds + 4 * (32 * 33 * 4)) + 32 * w;
+  if (l < 32) colp[l] = cpp ? cpp + (size_t)k * D : nullptr;
+  uint32_t wu[7];  // Montgomery forms of 256^u
+  wu[0] = q.one;
+  const uint32_t m256 = to_mont(256u, q);
+#pragma unroll
+  for (int u = 1; u < 7; ++u) wu[u] = mmul(wu[u - 1], m256, q);
+  // |G_u| <= 4 Dp 2^14 <= 2^28 and w_u < p < 2^31, so sum_u G_u w_u lies
+  // within 7 * 2^58.5 < 2^62 < p 2^32; adding p 2^32 (a multiple of p) makes
+  // it non-negative and below 2 p 2^32, where one Montgomery reduction
+  // leaves a value below 3p, hence one more conditional subtraction
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int32_t gv[7] = {G0[r], G1[r], G2[r], G3[r], G4[r], G5[r], G6[r]};
+    int64_t acc = (int64_t)q.p << 32;
+#pragma unroll
+    for (int u = 0; u < 7; ++u) acc += (int64_t)gv[u] * (int64_t)(int32_t)wu[u];
+    const uint32_t v = redc((uint64_t)acc, q.p, q.pinv);
+    tile[r32][8 * (r >> 2) + 4 * g + (r & 3)] = umin32(v, v - q.p);  // [column][row]
+  }
+  __syncthreads();
+  // lanes 0-31 write column n0 + 2c, lanes 32-63 column n0 + 2c + 1: 32 rows each
+  const int i = i0 + r32;
+  for (int c = 0; c < 16; ++c) {
+    const int col = 2 * c + g;
+    uint32_t* dst = colp[col];
+    if (dst && i < D) dst[i] = tile[col][r32];
+  }
 }
 
-static size_t interp_mfma_lds_bytes(int stages = IM_STAGES) {
+static size_t interp_mfma_lds_bytes() {
   // the stage ring, reused after the products for four transposes and column pointers
-  const size_t ring = (size_t)stages * IM_STAGE_BYTES;
+  const size_t ring = (size_t)IM_STAGES * IM_STAGE_BYTES;
   const size_t epi = 4 * (32 * 33 * 4) + 4 * 32 * sizeof(uint32_t*);
   return ring > epi ? ring : epi;
 }
@@ -2129,9 +2070,9 @@ __device__ __forceinline__ void crt_load_b(im_v4i (&B)[KSMAX], const __attribute
     B[ks] = *(const __attribute__((address_space(1))) im_v4i*)(Bn + (size_t)min(ks, KS - 1) * 256);
 }
 
-// One block of rows (b of the launch's nb) on one wave; WAVE: a wave of a
-// larger block (the persistent launch), with its own LDS slice.
-template <int KSMAX, int NT, bool WAVE>
+// The same on one wave of a larger block (the persistent launch), with its
+// own LDS slice: block b of the launch's nb, one operand set for registers.
+template <int KSMAX, int NT>
 __device__ __forceinline__ void dev_crt(const JobDev* jobs, const int* starts, int nj, int sld, int cps, TablesDev tab,
                                         int b, int nb, uint32_t* lds) {
   constexpr int ROWS = 32 * NT;
@@ -2158,12 +2099,9 @@ __device__ __forceinline__ void dev_crt(const JobDev* jobs, const int* starts, i
 #pragma unroll
     for (int u = 0; u < KSMAX * 4; ++u) xr[h][u] = col[(size_t)min(8 * (u >> 2) + 4 * g + (u & 3), P - 1) * D];
   }
-  // the first column tiles' operand blocks (two sets up to 64 primes, one
-  // above, for registers), also issued before the barrier
-  constexpr bool B2 = KSMAX <= 8 && !WAVE;  // one set in the persistent launch, for registers
-  im_v4i Ba[KSMAX], Bb[B2 ? KSMAX : 1];
+  // the first column tile's operand blocks, also issued before the barrier
+  im_v4i Ba[KSMAX];
   crt_load_b<KSMAX>(Ba, Bt, 0, NCT, KS);
-  if constexpr (B2) crt_load_b<KSMAX>(Bb, Bt, 1, NCT, KS);
   {
     // this block's share of the zero coefficients above the job's last block
     const int nbj = (min(D, J.degcap + 1) + ROWS - 1) / ROWS, cz = nbj * ROWS;
@@ -2188,7 +2126,7 @@ __device__ __forceinline__ void dev_crt(const JobDev* jobs, const int* starts, i
     Ci[k] = tab.inv_p[k];
   }
   for (int w = l; w < 8 * NCT; w += 64) Ms[w] = w < LM ? Mw[w] : 0u;
-  group_sync<WAVE>();
+  group_sync<true>();
   im_v4i A[NT][KSMAX];
   double f[NT];
 #pragma unroll
@@ -2242,7 +2180,7 @@ __device__ __forceinline__ void dev_crt(const JobDev* jobs, const int* starts, i
     for (int h = 0; h < NT; ++h)
 #pragma unroll
       for (int r = 0; r < 16; ++r) T[(32 * h + 8 * (r >> 2) + 4 * g + (r & 3)) * 33 + x] = acc[h][r];
-    group_sync<WAVE>();
+    group_sync<true>();
     if (owner) {
       const int32_t* t = T + l * 33;
 #pragma unroll
@@ -2263,22 +2201,11 @@ __device__ __forceinline__ void dev_crt(const JobDev* jobs, const int* starts, i
         }
       }
     }
-    group_sync<WAVE>();
+    group_sync<true>();
   };
-  if constexpr (B2) {
-    for (int ct = 0; ct < NCT; ct += 2) {
-      tile(ct, Ba);
-      crt_load_b<KSMAX>(Ba, Bt, ct + 2, NCT, KS);
-      if (ct + 1 < NCT) {
-        tile(ct + 1, Bb);
-        crt_load_b<KSMAX>(Bb, Bt, ct + 3, NCT, KS);
-      }
-    }
-  } else {
-    for (int ct = 0; ct < NCT; ++ct) {
-      tile(ct, Ba);
-      crt_load_b<KSMAX>(Ba, Bt, ct + 1, NCT, KS);
-    }
+  for (int ct = 0; ct < NCT; ++ct) {
+    tile(ct, Ba);
+    crt_load_b<KSMAX>(Ba, Bt, ct + 1, NCT, KS);
   }
   if (owner) {
     // limbs above the last byte column: the carry's extension
@@ -2294,7 +2221,7 @@ __device__ __forceinline__ void dev_crt(const JobDev* jobs, const int* starts, i
   // one atomic per wave: the highest non-zero coefficient of the block
   const uint64_t any = __ballot(owner && row && nz);
   if (any && l == 0) atomicMax(J.deg_out, c0 + 63 - __clzll((long long)any));
-  group_sync<WAVE>();
+  group_sync<true>();
   // rows c0 .. c0 + nr - 1 are one contiguous range of nr Lc words
   const int nr = min(ROWS, J.degcap + 1 - c0);
   uint32_t* dst = J.out + (size_t)c0 * Lc;
@@ -2311,10 +2238,10 @@ __device__ __forceinline__ void dev_crt(const JobDev* jobs, const int* starts, i
   }
 }
 
-// The staged kernel keeps its own copy of the body above: called through the
-// device function, the compiler schedules the operand loads differently and
-// takes 255 VGPRs for 48 primes (one wave per SIMD, 30 -> 44 us at config 2)
-// instead of 150.
+// The staged kernel keeps its own copy of the body above (with two operand
+// sets up to 64 primes): called through the device function, the compiler
+// schedules the operand loads differently and takes 255 VGPRs for 48 primes
+// (one wave per SIMD, 30 -> 44 us at config 2) instead of 150.
 template <int KSMAX, int NT>
 __global__ __launch_bounds__(64) void k_crt_mfma(const JobDev* jobs, const int* starts, int nj, int sld, int cps,
                                                  TablesDev tab) {
@@ -2691,7 +2618,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KSMAX <= 8 
       for (int t0 = fused_claim(c, F.n_crt, F.kc[3], xcd, r, e); t0 >= 0;
            t0 = fused_claim(c, F.n_crt, F.kc[3], xcd, r, e))
         for (int t = t0; t < e; ++t)
-          dev_crt<KSMAX, 1, true>(F.jobs, F.st_crt, F.nj, F.sld, F.cps, tab, t, F.n_crt, sl);
+          dev_crt<KSMAX, 1>(F.jobs, F.st_crt, F.nj, F.sld, F.cps, tab, t, F.n_crt, sl);
     }
     // the launch's end orders the results: no count, no wait
   } else {
