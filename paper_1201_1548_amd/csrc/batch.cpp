@@ -536,18 +536,14 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
       br_[bk] = std::max(br_[bk], x.Tf + x.Tg);
     }
     starts[K_IP][i + 1] = p.P;
-    starts[K_MRC][i + 1] = p.D;  // adjusted below once the largest prime count is known
+    starts[K_MRC][i + 1] = p.D;  // Garner: one wave per coefficient
     starts[K_SUM][i + 1] = (p.D * x.Lacc + 255) / 256;
     starts[K_CAR][i + 1] = debug ? 0 : (x.degcap + 1 + 63) / 64;
     // coefficients below D (the blocks also write the zero ones above them);
-    // adjusted below like K_MRC
+    // divided below by the rows per block, which depend on the largest prime
+    // count
     starts[K_CRT][i + 1] = debug ? 0 : std::min(p.D, x.degcap + 1);
   }
-  long long totalD = 0;
-  for (int i = 0; i < nj; ++i) totalD += starts[K_MRC][i + 1];
-  const bool mrc_lane = mrc_lane_ok(maxP, totalD);
-  if (mrc_lane)
-    for (int i = 0; i < nj; ++i) starts[K_MRC][i + 1] = (starts[K_MRC][i + 1] + 63) / 64;
   {
     const int rows = crt_rows_per_block(maxP);
     for (int i = 0; i < nj; ++i) starts[K_CRT][i + 1] = (starts[K_CRT][i + 1] + rows - 1) / rows;
@@ -824,13 +820,12 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
     } else {
       F.st_mrc = st_of(K_MRC);
       F.n_mrc = nb_of(K_MRC);
-      F.mrc_lane = mrc_lane ? 1 : 0;
       F.st_sum = st_of(K_SUM);
       F.n_sum = nb_of(K_SUM);
       F.st_car = st_of(K_CAR);
       F.n_car = nb_of(K_CAR);
       F.stage_ld = maxLcap <= 128 ? maxLcap + 1 : 0;
-      lw[2] = mrc_lane ? maxP * 64 : 2 * maxP;
+      lw[2] = 2 * maxP;
       lw[3] = 64 * F.stage_ld;
       demand = std::max(demand, F.n_sum);
     }
@@ -938,7 +933,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
       if (!debug) {
         sg.add((const void*)itW, (const void*)itQ, itNB);
         sg.add((int)group.size(), gD, gP, (const void*)vinv, o_yp, o_gco, nb_of(K_IP), maxD, use_crt, nb_of(K_CAR),
-               nb_of(K_CRT), maxLcap, nb_of(K_MRC), mrc_lane, nb_of(K_SUM));
+               nb_of(K_CRT), maxLcap, nb_of(K_MRC), nb_of(K_SUM));
         if (run) {
           if (!group.empty())
             launch_interp_mfma((uint32_t* const*)(D0 + o_gco), (int)group.size(), gD, gP, vinv,
@@ -949,7 +944,7 @@ int launch_impl(Context* cx, const std::vector<JobIn>& jobs_in, int mem, hipStre
             // residues to limbs in one pass over the output capacity
             if (nb_of(K_CRT)) launch_crt(d_jobs, st_of(K_CRT), nj, nb_of(K_CRT), maxP, maxLcap, cx->tab, st);
           } else {
-            if (nb_of(K_MRC)) launch_mrc(d_jobs, st_of(K_MRC), nj, nb_of(K_MRC), maxP, mrc_lane, cx->tab, st);
+            if (nb_of(K_MRC)) launch_mrc(d_jobs, st_of(K_MRC), nj, nb_of(K_MRC), maxP, cx->tab, st);
             if (nb_of(K_SUM)) launch_limbs_sum(d_jobs, st_of(K_SUM), nj, nb_of(K_SUM), cx->tab, st);
             if (nb_of(K_CAR)) launch_limbs_carry(d_jobs, st_of(K_CAR), nj, nb_of(K_CAR), maxLcap, st);
           }

@@ -266,9 +266,6 @@ int reconstruct(Context* cx, const std::vector<int>& S, const std::vector<const 
   std::memcpy(H + o_pm, pm.data(), pm.size() * 4);
   std::memcpy(H + o_pi, pi.data(), pi.size() * 4);
   std::memcpy(H + o_idx, S.data(), (size_t)P * 4);
-  long long total_n = 0;
-  for (int j = 0; j < nj; ++j) total_n += n[j];
-  const bool lane = mrc_lane_ok(P, total_n);
   JobDev* J = (JobDev*)(H + o_jobs);
   int* st3 = (int*)(H + o_st);
   int32_t* flags = (int32_t*)(H + o_flags);
@@ -290,7 +287,7 @@ int reconstruct(Context* cx, const std::vector<int>& S, const std::vector<const 
     J[j].err = dev.as<int32_t>(o_flags) + 2 * j + 1;
     flags[2 * j] = -1;
     flags[2 * j + 1] = 0;
-    st3[j + 1] = st3[j] + (lane ? (n[j] + 63) / 64 : n[j]);  // mrc
+    st3[j + 1] = st3[j] + n[j];  // mrc
     st3[nj + 1 + j + 1] = st3[nj + 1 + j] + (n[j] * Lacc + 255) / 256;  // limbs_sum
     st3[2 * (nj + 1) + j + 1] = st3[2 * (nj + 1) + j] + (n[j] + 63) / 64;  // limbs_carry
   }
@@ -306,7 +303,7 @@ int reconstruct(Context* cx, const std::vector<int>& S, const std::vector<const 
   tab.K = P;
   const int* dst = dev.as<int>(o_st);
   const JobDev* dj = dev.as<JobDev>(o_jobs);
-  launch_mrc(dj, dst, nj, st3[nj], P, lane, tab, st);
+  launch_mrc(dj, dst, nj, st3[nj], P, tab, st);
   launch_limbs_sum(dj, dst + nj + 1, nj, st3[2 * nj + 1], tab, st);
   launch_limbs_carry(dj, dst + 2 * (nj + 1), nj, st3[3 * nj + 2], Lcap, st);
   if (hipGetLastError() != hipSuccess) return BIRES_EDEVICE;

@@ -96,7 +96,7 @@ struct FusedPlan {
   const int* st_crt;
   int32_t n_crt, sld, cps;
   const int* st_mrc;
-  int32_t n_mrc, mrc_lane;
+  int32_t n_mrc;
   const int* st_sum;
   int32_t n_sum;
   const int* st_car;

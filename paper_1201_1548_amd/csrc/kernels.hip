@@ -1854,35 +1854,6 @@ __device__ __forceinline__ int lift_negative(const uint32_t* v, int stride, int 
   return 0;
 }
 
-// One lane per coefficient (P <= MRC_LANE_MAXP): the prefix value mod p_k is
-// evaluated by Horner's rule over the earlier digits, t <- t p_j + v_j for
-// j = k-1 .. 0, with the constants p_j mod p_k (uniform, scalar loads).
-constexpr int MRC_LANE_MAXP = 128;
-
-__device__ void dev_mrc_lane(const JobDev& J, int lb, TablesDev tab, uint32_t* lds) {
-  const int c = lb * 64 + lane_id();
-  const int P = J.P, D = J.D;
-  if (c >= D) return;
-  uint32_t* v = lds + lane_id();  // v[k * 64]
-  for (int k = 0; k < P; ++k) {
-    const ModP qk = tab.primes[k];
-    const uint32_t* pmk = tab.pm + (size_t)k * tab.K;
-    uint32_t t = k ? reduce32(v[(k - 1) * 64], qk.p) : 0u;
-#pragma unroll 4
-    for (int j = k - 2; j >= 0; --j) t = madd(mmul(t, pmk[j], qk), reduce32(v[j * 64], qk.p), qk.p);
-    const uint32_t vk = mmul(msub(J.coefs[(size_t)k * D + c], t, qk.p), tab.cm[k], qk);
-    v[k * 64] = vk;
-    J.digits[(size_t)k * D + c] = vk;
-  }
-  J.negflag[c] = lift_negative(v, 64, P, tab.primes);
-}
-
-__global__ __launch_bounds__(64) void k_mrc_lane(const JobDev* jobs, const int* starts, int nj, TablesDev tab) {
-  extern __shared__ __align__(16) uint32_t lds[];
-  const int job = find_job(starts, nj, blockIdx.x, gridDim.x);
-  dev_mrc_lane(jobs[job], blockIdx.x - starts[job], tab, lds);
-}
-
 // One wave per coefficient, lanes over primes k = lane + 64 t: lane k keeps
 // acc_k = sum_{j<k} v_j prod_{i<j} p_i mod p_k; at step j the owner lane of j
 // finishes v_j and broadcasts it.
@@ -2632,10 +2603,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KSMAX <= 8 
              t0 = fused_claim(c, F.n_mrc, F.kc[3], xcd, r, e)) {
           for (int t = t0; t < e; ++t, ++cnt) {
             const int job = find_job(F.st_mrc, F.nj, t, F.n_mrc);
-            if (F.mrc_lane)
-              dev_mrc_lane(F.jobs[job], t - F.st_mrc[job], tab, sl);
-            else
-              dev_mrc_wave<true>(F.jobs[job], t - F.st_mrc[job], tab, sl);
+            dev_mrc_wave<true>(F.jobs[job], t - F.st_mrc[job], tab, sl);
           }
         }
       }
@@ -3132,21 +3100,10 @@ void launch_interp_mfma(uint32_t* const* gco, int N, int D, int P, const int8_t*
                      Ap, Yp, tab);
 }
 
-bool mrc_lane_ok(int max_primes, long long total_coefficients) {
-  // one lane per coefficient needs enough coefficients to fill the device;
-  // otherwise one wave per coefficient has the shorter critical path
-  return max_primes <= MRC_LANE_MAXP && total_coefficients >= 16384;
-}
-
-void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, bool lane, TablesDev tab,
+void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, TablesDev tab,
                 hipStream_t s) {
-  if (lane) {
-    hipLaunchKernelGGL(k_mrc_lane, dim3(nblocks), dim3(64), (size_t)max_primes * 64 * sizeof(uint32_t), s, jobs,
-                       starts, nj, tab);
-  } else {
-    hipLaunchKernelGGL(k_mrc, dim3(nblocks), dim3(64), (size_t)2 * max_primes * sizeof(uint32_t), s, jobs, starts,
-                       nj, tab);
-  }
+  hipLaunchKernelGGL(k_mrc, dim3(nblocks), dim3(64), (size_t)2 * max_primes * sizeof(uint32_t), s, jobs, starts, nj,
+                     tab);
 }
 
 bool crt_ok(int max_primes) { return max_primes <= CRT_MAXP; }

@@ -80,10 +80,8 @@ void launch_vinv(int D, int Dp, int P, TablesDev tab, int8_t* Ap, hipStream_t s)
 void launch_interp_mfma(uint32_t* const* gco, int N, int D, int P, const int8_t* Ap, const int8_t* Yp, TablesDev tab,
                         hipStream_t s);
 void launch_invfact(const ModP* primes, int K, uint32_t* invfact, int dmax, hipStream_t s);
-// mrc blocks per job: ceil(D/64) with lane = true (one lane per coefficient,
-// allowed when mrc_lane_ok), else D (one wave per coefficient).
-bool mrc_lane_ok(int max_primes, long long total_coefficients);
-void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, bool lane, TablesDev tab,
+// Garner digits: one wave per coefficient, D blocks per job.
+void launch_mrc(const JobDev* jobs, const int* starts, int nj, int nblocks, int max_primes, TablesDev tab,
                 hipStream_t s);
 // Explicit CRT straight to limbs on the matrix cores (k_crt_mfma): one wave
 // per rows = crt_rows_per_block(max primes) output coefficients,
