@@ -272,6 +272,30 @@ def test_fused_batches_in_flight_on_two_streams():
         br.set_schedule("staged")
 
 
+def test_fused_matrix_core_group_above_48_primes():
+    # 32 copies of a pair with 200-bit coefficients (D = 73, P = 80): the
+    # fused launch with the matrix-core interpolation group and the CRT for up
+    # to 128 primes, against the oracle's Bareiss value and the staged schedule
+    F, G = synth.random_rect(2100, 6, 6, 6, 6, 200)
+    D, P, _ = br.plan(F, G)
+    assert 48 < P <= 128, P
+    jobs = [("res", F, G, "y")] * 32
+    say("fused group of 32, D", D, "P", P)
+    ref = resultant_y(F, G)
+    b = br.DeviceBatch(jobs)
+    try:
+        br.set_schedule("staged")
+        b.run()
+        staged = b.results()
+        br.set_schedule("fused")
+        b.run()
+        fused = b.results()
+    finally:
+        br.set_schedule("staged")
+    assert staged == [ref] * 32
+    assert fused == staged
+
+
 def test_autotune_keeps_results():
     jobs = [("res",) + synth.pair_deg6(i % 4) + ("y",) for i in range(16)]
     say("autotune")
