@@ -2212,7 +2212,7 @@ __device__ __forceinline__ void dev_crt(const JobDev* jobs, const int* starts, i
 // The staged kernel keeps its own copy of the body above (with two operand
 // sets up to 64 primes): called through the device function, the compiler
 // schedules the operand loads differently and takes 255 VGPRs for 48 primes
-// (one wave per SIMD, 30 -> 44 us at config 2) instead of 150.
+// (one wave per SIMD, 30 -> 44 us for 256 degree-20 pairs) instead of 150.
 template <int KSMAX, int NT>
 __global__ __launch_bounds__(64) void k_crt_mfma(const JobDev* jobs, const int* starts, int nj, int sld, int cps,
                                                  TablesDev tab) {
